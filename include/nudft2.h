@@ -1,0 +1,155 @@
+/*
+ * nudft2 -- direct solver for the 2D type-II inverse NUDFT on AMD MI355X.
+ *
+ * The problem (Section 1 of Li & Liu, "A superfast direct solver for the 2D
+ * type-II inverse NUDFT based on HSS matrices"): given M >= N = nx*ny sample
+ * points (x_j, y_j) and values f_j, find coefficients c minimising
+ * ||A c - f||_2 with
+ *
+ *     A(j, (kx, ky)) = exp(-2 pi i (kx x_j + ky y_j)).
+ *
+ * Frequencies are centred: kx in [-nx/2, nx/2), ky in [-ny/2, ny/2).  A
+ * coefficient array is C-order (nx, ny): c[i][j] <-> (kx, ky) =
+ * (i - nx/2, j - ny/2); its vectorised column index is ky' + kx' ny with the
+ * 0-based kx' = i, ky' = j (the paper's lexicographic ordering).
+ *
+ * Method (Algorithm 4.1): the transformed matrix G = A F^{-1} (F the 2D DFT)
+ * is the face-splitting product G^x . G^y of two 1D transformed NUDFT
+ * matrices (Section 3.1).  The library compresses G^x and G^y into HSS form
+ * (tolerance eps/10), assembles the HSS form of their face-splitting product
+ * (Theorem 3.3), recompresses it (Section 2.3, tolerance eps), factors it by
+ * URV (Section 2.4), and solves with one URV sweep plus a 2D inverse DFT.
+ * Optionally the solution is refined in FP64 against the exact operator A
+ * (r = f - A c; c += F^{-1} H^+ r) until ||dc||/||c|| <= ir_tol.
+ *
+ * Complex data are interleaved (re, im) double pairs, the storage of
+ * torch.complex128 / numpy complex128.  Unless stated otherwise pointers to
+ * right-hand sides and solutions are DEVICE pointers owned by the caller.
+ * Every entry point returns a status code; nothing aborts or throws across
+ * this boundary.  Work is enqueued on opts.stream (a hipStream_t; NULL means
+ * the default stream) and is asynchronous except where a call must read a
+ * result back (factor reads ranks per level, refinement reads one norm per
+ * iteration, get_info).  A plan is not re-entrant: calls on one plan must not
+ * overlap.
+ */
+#ifndef NUDFT2_H
+#define NUDFT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NUDFT2_OK = 0,
+  NUDFT2_E_INVAL = 1,     /* invalid argument (checked before any device work) */
+  NUDFT2_E_STATE = 2,     /* call out of order (e.g. solve before factor)      */
+  NUDFT2_E_DEVICE = 3,    /* no usable GPU / HIP runtime error                 */
+  NUDFT2_E_NOMEM = 4,     /* device allocation failed or opts.mem_cap exceeded  */
+  NUDFT2_E_SINGULAR = 5,  /* a triangular pivot of the URV factors vanished     */
+  NUDFT2_E_NOCONV = 6,    /* refinement hit ir_maxit before ir_tol             */
+  NUDFT2_E_INTERNAL = 7
+} nudft2_status;
+
+typedef struct nudft2_plan_s* nudft2_plan_t;
+
+/* Options.  Fill with nudft2_default_opts() and override fields. */
+typedef struct {
+  int32_t precision;  /* 0: FP64 HSS factors; 1: FP32 factors, FP64 refinement */
+  double eps;         /* HSS tolerance of the recompression (1D stage: eps/10) */
+  int32_t leaf;       /* columns per dimension of a leaf (paper: 16)           */
+  double ir_tol;      /* refinement stop: ||dc||_2 / ||c||_2 <= ir_tol          */
+  int32_t ir_maxit;   /* refinement iterations; 0 = plain direct solve          */
+  int32_t refine;     /* 0: iterative refinement; 1: CG on the normal equations */
+  void* stream;       /* hipStream_t; NULL = default stream                     */
+  size_t mem_cap;     /* device bytes the plan may hold; 0 = no cap             */
+} nudft2_opts;
+
+/* Per-solve report (host memory, may be NULL). */
+typedef struct {
+  int32_t iterations;     /* refinement iterations taken                     */
+  double rel_update;      /* last ||dc|| / ||c||                              */
+  double rel_residual;    /* last ||f - A c|| / ||f|| (first right-hand side)  */
+} nudft2_solve_info;
+
+/* Plan-wide report (host memory). */
+typedef struct {
+  int32_t nprob;          /* problems in the plan                             */
+  int32_t levels;         /* depth L of the (deepest) quadtree                */
+  int32_t max_rank_u[16]; /* per level 0..L: largest row rank after recompression */
+  int32_t max_rank_v[16]; /* per level 0..L: largest column rank                */
+  int64_t factor_bytes;   /* device bytes held by the factors                 */
+  double factor_flops;    /* flops counted over the factorization's operations */
+  double t_plan_ms, t_compress_ms, t_facesplit_ms, t_recompress_ms, t_urv_ms;
+} nudft2_info;
+
+void nudft2_default_opts(nudft2_opts* opts);
+
+/* Plan for one problem.  points: HOST pointer to M interleaved (x_j, y_j)
+ * doubles, any finite values (wrapped into [0,1)); copied, caller keeps
+ * ownership.  Requires nx, ny even and >= 2, M >= nx*ny (Section 1), all
+ * points finite, opts valid (eps in (0,1), leaf >= 2).  Bins the points into
+ * the quadtree and uploads them; does not factor.  *out is set only on
+ * success.  Errors: E_INVAL, E_DEVICE, E_NOMEM. */
+nudft2_status nudft2_plan(nudft2_plan_t* out, const double* points, int64_t M,
+                          int32_t nx, int32_t ny, const nudft2_opts* opts);
+
+/* Plan for nprob independent problems solved together (one launch per tree
+ * level for all problems).  points: HOST, concatenated; problem p owns
+ * points[2*m_off[p] .. 2*m_off[p+1]).  m_off, nx, ny: HOST arrays (nprob+1,
+ * nprob, nprob).  Right-hand sides and solutions of a batch plan are
+ * concatenated in problem order: f of problem p at f + 2*m_off[p] (per
+ * right-hand side stride 2*m_off[nprob] doubles), c of problem p at an offset
+ * of sum_{q<p} nx[q]*ny[q] complex entries. */
+nudft2_status nudft2_plan_batch(nudft2_plan_t* out, int32_t nprob,
+                                const double* points, const int64_t* m_off,
+                                const int32_t* nx, const int32_t* ny,
+                                const nudft2_opts* opts);
+
+/* Build the HSS approximation of G (1D compression, face-splitting assembly,
+ * recompression) and its URV factorization.  Idempotent.  Synchronises with
+ * the stream (ranks are read back per level).  Errors: E_NOMEM, E_SINGULAR,
+ * E_DEVICE. */
+nudft2_status nudft2_factor(nudft2_plan_t plan);
+
+/* Least-squares solve for nrhs right-hand sides.  f: DEVICE, nrhs x M
+ * complex128 (row-major, right-hand side r at f + 2*M*r), in the caller's
+ * point order.  c: DEVICE, nrhs x nx x ny complex128 output.  With
+ * opts.ir_maxit == 0 returns the direct solution c = F^{-1} H^+ f; otherwise
+ * refines in FP64 (E_NOCONV leaves the last iterate in c).  Errors: E_INVAL
+ * (null pointer, nrhs <= 0), E_STATE (not factored), E_NOCONV, E_DEVICE. */
+nudft2_status nudft2_solve(nudft2_plan_t plan, const double* f, double* c,
+                           int32_t nrhs, nudft2_solve_info* info);
+
+/* Adjoint of the least-squares solution operator: w = (A^+)^* g for g of
+ * shape nrhs x nx x ny, w of shape nrhs x M (DEVICE).  Used for gradients
+ * with respect to f.  Requires the factorization (used as preconditioner of
+ * CG on the normal equations).  Errors as nudft2_solve. */
+nudft2_status nudft2_solve_adj(nudft2_plan_t plan, const double* g, double* w,
+                               int32_t nrhs, nudft2_solve_info* info);
+
+/* f = A c exactly in FP64 (Section 1 sum).  c: DEVICE nrhs x nx x ny, f:
+ * DEVICE nrhs x M.  Does not need the factorization.  Errors: E_INVAL. */
+nudft2_status nudft2_apply(nudft2_plan_t plan, const double* c, double* f,
+                           int32_t nrhs);
+
+/* c = A^* f exactly in FP64.  f: DEVICE nrhs x M, c: DEVICE nrhs x nx x ny. */
+nudft2_status nudft2_apply_adj(nudft2_plan_t plan, const double* f, double* c,
+                               int32_t nrhs);
+
+/* Fill *info (HOST).  Synchronises with the plan's stream. */
+nudft2_status nudft2_get_info(nudft2_plan_t plan, nudft2_info* info);
+
+/* Release every device buffer of the plan.  NULL is accepted. */
+nudft2_status nudft2_destroy(nudft2_plan_t plan);
+
+/* Static description of a status code. */
+const char* nudft2_strerror(nudft2_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUDFT2_H */

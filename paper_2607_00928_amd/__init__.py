@@ -1,0 +1,205 @@
+"""MI355X-native direct solver for the 2D type-II inverse NUDFT.
+
+Python binding of libnudft2 (include/nudft2.h).  The binding only marshals
+arguments: every step of the factorization, the solve and the transforms
+runs in the library's HIP kernels.  PyTorch supplies device memory and the
+stream.
+
+    plan = Plan(points, nx, ny, precision="fp32", eps=1e-4)
+    plan.factor()
+    c = plan.solve(f)          # f: complex128 CUDA tensor (M,) or (nrhs, M)
+    f2 = plan.apply(c)         # exact FP64 A c
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import NudftError, check, lib
+
+__all__ = ["Plan", "BatchPlan", "NudftError", "lsq_solve"]
+
+_PREC = {"fp64": 0, "fp32": 1, 0: 0, 1: 1}
+
+
+def _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap):
+    o = _lib.default_opts()
+    o.precision = _PREC[precision]
+    o.eps = float(eps)
+    o.leaf = int(leaf)
+    o.ir_tol = float(ir_tol)
+    o.ir_maxit = int(ir_maxit)
+    o.refine = int(refine)
+    o.stream = C.c_void_p(stream) if stream else None
+    o.mem_cap = int(mem_cap)
+    return o
+
+
+def _host_points(points) -> np.ndarray:
+    if isinstance(points, torch.Tensor):
+        points = points.detach().cpu().numpy()
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    if pts.ndim != 2 or pts.shape[1] != 2:
+        raise ValueError("points must have shape (M, 2)")
+    return pts
+
+
+def _current_stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class _PlanBase:
+    _handle = None
+
+    def _check_dev(self, t: torch.Tensor, name: str):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+            raise TypeError(f"{name} must be a complex128 CUDA tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def factor(self):
+        check(lib.nudft2_factor(self._handle), "nudft2_factor")
+        return self
+
+    def info(self) -> dict:
+        inf = _lib.Info()
+        check(lib.nudft2_get_info(self._handle, C.byref(inf)), "nudft2_get_info")
+        L = inf.levels
+        return dict(nprob=inf.nprob, levels=L,
+                    max_rank_u=list(inf.max_rank_u)[:L + 1],
+                    max_rank_v=list(inf.max_rank_v)[:L + 1],
+                    factor_bytes=inf.factor_bytes, factor_flops=inf.factor_flops,
+                    t_plan_ms=inf.t_plan_ms, t_compress_ms=inf.t_compress_ms,
+                    t_facesplit_ms=inf.t_facesplit_ms,
+                    t_recompress_ms=inf.t_recompress_ms, t_urv_ms=inf.t_urv_ms)
+
+    def _rhs(self, f: torch.Tensor):
+        self._check_dev(f, "f")
+        if f.dim() == 1:
+            if f.numel() != self.M:
+                raise ValueError("f has the wrong length")
+            return 1, (self.N_shape)
+        if f.dim() != 2 or f.shape[1] != self.M:
+            raise ValueError("f must be (M,) or (nrhs, M)")
+        return f.shape[0], (f.shape[0],) + self.N_shape
+
+    def solve(self, f: torch.Tensor, out: torch.Tensor | None = None,
+              return_info: bool = False):
+        nrhs, shape = self._rhs(f)
+        c = out if out is not None else torch.empty(shape, dtype=torch.complex128,
+                                                    device=f.device)
+        self._check_dev(c, "out")
+        si = _lib.SolveInfo()
+        st = lib.nudft2_solve(self._handle, C.c_void_p(f.data_ptr()),
+                              C.c_void_p(c.data_ptr()), nrhs, C.byref(si))
+        check(st, "nudft2_solve")
+        if return_info:
+            return c, dict(iterations=si.iterations, rel_update=si.rel_update,
+                           rel_residual=si.rel_residual)
+        return c
+
+    def solve_adj(self, g: torch.Tensor, return_info: bool = False):
+        self._check_dev(g, "g")
+        nrhs = 1 if g.dim() == len(self.N_shape) else g.shape[0]
+        shape = (self.M,) if nrhs == 1 and g.dim() == len(self.N_shape) else (nrhs, self.M)
+        w = torch.empty(shape, dtype=torch.complex128, device=g.device)
+        si = _lib.SolveInfo()
+        st = lib.nudft2_solve_adj(self._handle, C.c_void_p(g.data_ptr()),
+                                  C.c_void_p(w.data_ptr()), nrhs, C.byref(si))
+        check(st, "nudft2_solve_adj")
+        if return_info:
+            return w, dict(iterations=si.iterations, rel_update=si.rel_update,
+                           rel_residual=si.rel_residual)
+        return w
+
+    def apply(self, c: torch.Tensor) -> torch.Tensor:
+        self._check_dev(c, "c")
+        nrhs = 1 if c.dim() == len(self.N_shape) else c.shape[0]
+        shape = (self.M,) if c.dim() == len(self.N_shape) else (nrhs, self.M)
+        f = torch.empty(shape, dtype=torch.complex128, device=c.device)
+        check(lib.nudft2_apply(self._handle, C.c_void_p(c.data_ptr()),
+                               C.c_void_p(f.data_ptr()), nrhs), "nudft2_apply")
+        return f
+
+    def apply_adj(self, f: torch.Tensor) -> torch.Tensor:
+        nrhs, shape = self._rhs(f)
+        c = torch.empty(shape, dtype=torch.complex128, device=f.device)
+        check(lib.nudft2_apply_adj(self._handle, C.c_void_p(f.data_ptr()),
+                                   C.c_void_p(c.data_ptr()), nrhs), "nudft2_apply_adj")
+        return c
+
+    def close(self):
+        if self._handle is not None:
+            lib.nudft2_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan(_PlanBase):
+    """One problem: points (M, 2) host array, nx x ny centred frequencies."""
+
+    def __init__(self, points, nx: int, ny: int, *, precision="fp32", eps=1e-4,
+                 leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0, stream=None,
+                 mem_cap=0, device=None):
+        pts = _host_points(points)
+        self.M = pts.shape[0]
+        self.nx, self.ny = int(nx), int(ny)
+        self.N_shape = (self.nx, self.ny)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if stream is None:
+            stream = _current_stream(dev)
+        o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap)
+        h = C.c_void_p()
+        with torch.cuda.device(dev):
+            st = lib.nudft2_plan(C.byref(h), _lib.dptr(pts), self.M, self.nx, self.ny,
+                                 C.byref(o))
+        check(st, "nudft2_plan")
+        self._handle = h
+        self.points = pts
+
+
+class BatchPlan(_PlanBase):
+    """Many independent problems; right-hand sides and solutions are flat
+    concatenations (see nudft2_plan_batch)."""
+
+    def __init__(self, points_list, nx_list, ny_list, *, precision="fp32",
+                 eps=1e-4, leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0,
+                 stream=None, mem_cap=0, device=None):
+        pts = [_host_points(p) for p in points_list]
+        m_off = np.zeros(len(pts) + 1, dtype=np.int64)
+        m_off[1:] = np.cumsum([p.shape[0] for p in pts])
+        allp = np.ascontiguousarray(np.concatenate(pts, axis=0))
+        nx = np.ascontiguousarray(nx_list, dtype=np.int32)
+        ny = np.ascontiguousarray(ny_list, dtype=np.int32)
+        self.M = int(m_off[-1])
+        self.m_off = m_off
+        self.n_off = np.concatenate([[0], np.cumsum(nx.astype(np.int64) * ny)])
+        self.N_shape = (int(self.n_off[-1]),)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if stream is None:
+            stream = _current_stream(dev)
+        o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap)
+        h = C.c_void_p()
+        with torch.cuda.device(dev):
+            st = lib.nudft2_plan_batch(
+                C.byref(h), len(pts), _lib.dptr(allp),
+                m_off.ctypes.data_as(C.POINTER(C.c_int64)),
+                nx.ctypes.data_as(C.POINTER(C.c_int32)),
+                ny.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(o))
+        check(st, "nudft2_plan_batch")
+        self._handle = h
+        self.nx_list, self.ny_list = nx, ny
+
+
+def lsq_solve(*args, **kwargs):
+    """Differentiable least-squares solve (see .autograd)."""
+    from .autograd import lsq_solve as _f
+    return _f(*args, **kwargs)

@@ -1,0 +1,72 @@
+// Plan: problems, trees, point orderings and the factors of the solver.
+#pragma once
+
+#include <memory>
+
+#include "common.h"
+
+namespace nd {
+
+struct HSSFactors;   // defined in hss.h
+
+// Host description of one problem's trees.
+//  * 1D trees (x and y), both of depth L: node (l, a) owns the columns
+//    [colx[l][a], colx[l][a+1]) and the rows of the x-sorted point order
+//    [rowx[l][a], rowx[l][a+1]) (global indices).
+//  * 2D quadtree of depth L, nodes of a level in Morton order z (children of
+//    z are 4z + 2p + q): node z owns the rows [row2[l][z], row2[l][z+1]) of
+//    the 2D-sorted point order (global) and the columns
+//    [col2[l][z], col2[l][z+1]) of the quadtree column order (per problem).
+struct Problem {
+  int nx = 0, ny = 0, L = 0;
+  int64_t m0 = 0, M = 0;   // points of this problem: [m0, m0 + M)
+  int64_t c0 = 0;          // coefficient offset (complex entries)
+  std::vector<std::vector<int>> colx, coly;
+  std::vector<std::vector<int64_t>> rowx, rowy;
+  std::vector<std::vector<int64_t>> row2;
+  std::vector<std::vector<int>> col2;
+  int64_t N() const { return (int64_t)nx * ny; }
+};
+
+// Device descriptor for the apply kernels.
+struct ApplyProb {
+  int64_t m0, M, c0;
+  int nx, ny;
+};
+
+struct Plan {
+  nudft2_opts opts{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Arena arena;
+  std::vector<Problem> probs;
+  int64_t Mtot = 0, Ntot = 0;
+  int Lmax = 0;
+
+  // device arrays (global over problems)
+  double* pts_user = nullptr;      // Mtot x 2, caller's order
+  double* pts_2d = nullptr;        // Mtot x 2, 2D-sorted
+  int64_t* perm2d = nullptr;       // 2D-sorted index -> caller index
+  double* xs = nullptr;            // x of the x-sorted order (Mtot)
+  double* ys = nullptr;            // y of the y-sorted order (Mtot)
+  int64_t* posx = nullptr;         // 2D-sorted index -> x-sorted index
+  int64_t* posy = nullptr;         // 2D-sorted index -> y-sorted index
+  int64_t* colperm = nullptr;      // quadtree column index (global) -> natural index (global)
+  ApplyProb* d_aprob = nullptr;
+  int* d_tile_off = nullptr;       // apply row-tile prefix (nprob + 1)
+  int apply_tiles = 0;
+
+  bool factored = false;
+  std::unique_ptr<HSSFactors> hss;
+  nudft2_info info{};
+
+  ~Plan();
+};
+
+Plan* make_plan(int nprob, const double* points, const int64_t* m_off,
+                const int32_t* nx, const int32_t* ny, const nudft2_opts* opts);
+
+void apply_fwd(Plan* P, const double2* c, double2* f, int nrhs, hipStream_t s);
+void apply_adj(Plan* P, const double2* f, double2* c, int nrhs, hipStream_t s);
+
+}  // namespace nd

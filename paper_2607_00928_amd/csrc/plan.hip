@@ -1,0 +1,327 @@
+// Plan construction: validation, point binning (quadtree and 1D trees) and
+// upload.  Binning is host code (the points arrive in host memory).
+//
+// Trees (Definitions 2.1 and 3.2): both 1D trees bisect [0, 1) dyadically to
+// a common depth L = ceil(log2(max(nx, ny) / leaf)); node (l, a) of the x tree
+// owns the points with floor(x 2^l) = a and the columns l' with
+// floor(l' 2^l / nx) = a (half-open intervals).  The 2D tree is their
+// face-splitting product: node (l, a, b) owns the points in the box and the
+// columns K^x_a x K^y_b.  Points are sorted by the Morton code of their leaf
+// box so that every quadtree node owns a contiguous range of rows, and the
+// columns of every node are contiguous in the "quadtree column order"
+// (children concatenated in (p, q) order, each leaf kx-major).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "hss.h"
+#include "plan.h"
+
+namespace nd {
+
+void* Arena::alloc(size_t n) {
+  if (n == 0) n = 1;
+  n = (n + 255) & ~size_t(255);
+  if (cap && bytes + n > cap)
+    throw Error(NUDFT2_E_NOMEM, "plan memory cap exceeded");
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(NUDFT2_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  blocks.push_back({p, n});
+  bytes += n;
+  peak = std::max(peak, bytes);
+  return p;
+}
+
+void Arena::release(void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < blocks.size(); ++i)
+    if (blocks[i].first == p) {
+      (void)hipFree(p);
+      bytes -= blocks[i].second;
+      blocks[i] = blocks.back();
+      blocks.pop_back();
+      return;
+    }
+}
+
+void Arena::release_all() {
+  for (auto& b : blocks) (void)hipFree(b.first);
+  blocks.clear();
+  bytes = 0;
+}
+
+Plan::~Plan() {
+  hss.reset();
+  arena.release_all();
+}
+
+static inline uint32_t interleave(uint32_t a, uint32_t b, int L) {
+  uint32_t z = 0;
+  for (int i = 0; i < L; ++i) z |= (((a >> i) & 1u) << (2 * i + 1)) | (((b >> i) & 1u) << (2 * i));
+  return z;
+}
+
+static inline void deinterleave(uint32_t z, int L, uint32_t& a, uint32_t& b) {
+  a = b = 0;
+  for (int i = 0; i < L; ++i) {
+    a |= ((z >> (2 * i + 1)) & 1u) << i;
+    b |= ((z >> (2 * i)) & 1u) << i;
+  }
+}
+
+int tree_depth(int nx, int ny, int leaf) {
+  int L = 0;
+  while ((int64_t)std::max(nx, ny) > (int64_t)leaf << L) ++L;
+  return L;
+}
+
+static inline double wrap01(double v) {
+  double w = v - std::floor(v);
+  if (w >= 1.0) w -= 1.0;
+  return w;
+}
+
+static inline int bin_of(double v, int level) {
+  int b = (int)std::floor(v * (double)(1 << level));
+  return std::min(std::max(b, 0), (1 << level) - 1);
+}
+
+// Host part of the plan: fills the trees and the orderings (host arrays).
+struct HostOrder {
+  std::vector<double> pts_user, pts_2d, xs, ys;
+  std::vector<int64_t> perm2d, posx, posy, colperm;
+};
+
+static void bin_problem(Problem& q, const double* pts, int leaf, HostOrder& H) {
+  const int L = q.L;
+  const int64_t M = q.M, m0 = q.m0;
+  const int nleaf1 = 1 << L;
+  const int nleaf2 = 1 << (2 * L);
+  std::vector<int> bx(M), by(M);
+  std::vector<uint32_t> z(M);
+  for (int64_t j = 0; j < M; ++j) {
+    double x = wrap01(pts[2 * (m0 + j)]), y = wrap01(pts[2 * (m0 + j) + 1]);
+    H.pts_user[2 * (m0 + j)] = x;
+    H.pts_user[2 * (m0 + j) + 1] = y;
+    bx[j] = bin_of(x, L);
+    by[j] = bin_of(y, L);
+    z[j] = interleave(bx[j], by[j], L);
+  }
+  // columns of the 1D trees
+  q.colx.assign(L + 1, {});
+  q.coly.assign(L + 1, {});
+  for (int l = 0; l <= L; ++l) {
+    int na = 1 << l;
+    q.colx[l].resize(na + 1);
+    q.coly[l].resize(na + 1);
+    for (int a = 0; a <= na; ++a) {
+      q.colx[l][a] = (int)(((int64_t)a * q.nx + na - 1) / na);
+      q.coly[l][a] = (int)(((int64_t)a * q.ny + na - 1) / na);
+    }
+  }
+  // 2D order: stable counting sort by leaf Morton code
+  std::vector<int64_t> cnt2(nleaf2 + 1, 0);
+  for (int64_t j = 0; j < M; ++j) cnt2[z[j] + 1]++;
+  for (int i = 0; i < nleaf2; ++i) cnt2[i + 1] += cnt2[i];
+  std::vector<int64_t> ord2(M);
+  {
+    std::vector<int64_t> pos(cnt2.begin(), cnt2.end() - 1);
+    for (int64_t j = 0; j < M; ++j) ord2[pos[z[j]]++] = j;
+  }
+  q.row2.assign(L + 1, {});
+  for (int l = 0; l <= L; ++l) {
+    int nn = 1 << (2 * l);
+    q.row2[l].resize(nn + 1);
+    int sh = 2 * (L - l);
+    for (int zz = 0; zz <= nn; ++zz) q.row2[l][zz] = m0 + cnt2[(int64_t)zz << sh];
+  }
+  // 1D orders
+  auto sort1d = [&](const std::vector<int>& b, std::vector<int64_t>& ord,
+                    std::vector<std::vector<int64_t>>& rows) {
+    std::vector<int64_t> cnt(nleaf1 + 1, 0);
+    for (int64_t j = 0; j < M; ++j) cnt[b[j] + 1]++;
+    for (int i = 0; i < nleaf1; ++i) cnt[i + 1] += cnt[i];
+    ord.resize(M);
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t j = 0; j < M; ++j) ord[pos[b[j]]++] = j;
+    rows.assign(L + 1, {});
+    for (int l = 0; l <= L; ++l) {
+      int na = 1 << l;
+      rows[l].resize(na + 1);
+      for (int a = 0; a <= na; ++a) rows[l][a] = m0 + cnt[(int64_t)a << (L - l)];
+    }
+  };
+  std::vector<int64_t> ordx, ordy;
+  sort1d(bx, ordx, q.rowx);
+  sort1d(by, ordy, q.rowy);
+  std::vector<int64_t> invx(M), invy(M);
+  for (int64_t i = 0; i < M; ++i) {
+    invx[ordx[i]] = i;
+    invy[ordy[i]] = i;
+  }
+  for (int64_t i = 0; i < M; ++i) {
+    int64_t j = ord2[i];
+    H.perm2d[m0 + i] = m0 + j;
+    H.pts_2d[2 * (m0 + i)] = H.pts_user[2 * (m0 + j)];
+    H.pts_2d[2 * (m0 + i) + 1] = H.pts_user[2 * (m0 + j) + 1];
+    H.posx[m0 + i] = m0 + invx[j];
+    H.posy[m0 + i] = m0 + invy[j];
+    H.xs[m0 + i] = H.pts_user[2 * (m0 + ordx[i])];
+    H.ys[m0 + i] = H.pts_user[2 * (m0 + ordy[i]) + 1];
+  }
+  // quadtree column order
+  q.col2.assign(L + 1, {});
+  for (int l = 0; l <= L; ++l) {
+    int nn = 1 << (2 * l);
+    q.col2[l].resize(nn + 1);
+    q.col2[l][0] = 0;
+    for (int zz = 0; zz < nn; ++zz) {
+      uint32_t a, b;
+      deinterleave(zz, l, a, b);
+      int d = (q.colx[l][a + 1] - q.colx[l][a]) * (q.coly[l][b + 1] - q.coly[l][b]);
+      q.col2[l][zz + 1] = q.col2[l][zz] + d;
+    }
+  }
+  for (int zz = 0; zz < nleaf2; ++zz) {
+    uint32_t a, b;
+    deinterleave(zz, L, a, b);
+    int x0 = q.colx[L][a], x1 = q.colx[L][a + 1];
+    int y0 = q.coly[L][b], y1 = q.coly[L][b + 1];
+    int64_t o = q.c0 + q.col2[L][zz];
+    for (int i = x0; i < x1; ++i)
+      for (int j = y0; j < y1; ++j) H.colperm[o++] = q.c0 + (int64_t)i * q.ny + j;
+  }
+}
+
+static void validate(int nprob, const double* points, const int64_t* m_off,
+                     const int32_t* nx, const int32_t* ny, const nudft2_opts* o) {
+  ND_CHECK(nprob >= 1, NUDFT2_E_INVAL, "nprob must be >= 1");
+  ND_CHECK(points && m_off && nx && ny, NUDFT2_E_INVAL, "null pointer argument");
+  ND_CHECK(m_off[0] == 0, NUDFT2_E_INVAL, "m_off[0] must be 0");
+  ND_CHECK(o != nullptr, NUDFT2_E_INVAL, "null options");
+  ND_CHECK(o->precision == 0 || o->precision == 1, NUDFT2_E_INVAL, "precision must be 0 or 1");
+  ND_CHECK(o->eps > 0.0 && o->eps < 1.0, NUDFT2_E_INVAL, "eps must lie in (0, 1)");
+  ND_CHECK(o->leaf >= 2 && o->leaf <= 64, NUDFT2_E_INVAL, "leaf must lie in [2, 64]");
+  ND_CHECK(o->ir_maxit >= 0, NUDFT2_E_INVAL, "ir_maxit must be >= 0");
+  ND_CHECK(o->ir_tol >= 0.0, NUDFT2_E_INVAL, "ir_tol must be >= 0");
+  ND_CHECK(o->refine == 0 || o->refine == 1, NUDFT2_E_INVAL, "refine must be 0 or 1");
+  for (int p = 0; p < nprob; ++p) {
+    ND_CHECK(nx[p] >= 2 && ny[p] >= 2 && nx[p] % 2 == 0 && ny[p] % 2 == 0,
+             NUDFT2_E_INVAL, "nx, ny must be even and >= 2");
+    ND_CHECK(nx[p] <= 4096 && ny[p] <= 4096, NUDFT2_E_INVAL, "nx, ny must be <= 4096");
+    int64_t M = m_off[p + 1] - m_off[p];
+    ND_CHECK(M >= (int64_t)nx[p] * ny[p], NUDFT2_E_INVAL, "need M >= nx*ny points");
+    int L = tree_depth(nx[p], ny[p], o->leaf);
+    ND_CHECK(L <= 10, NUDFT2_E_INVAL, "tree too deep (nx/leaf > 1024)");
+  }
+  int64_t Mt = m_off[nprob];
+  for (int64_t j = 0; j < 2 * Mt; ++j)
+    ND_CHECK(std::isfinite(points[j]), NUDFT2_E_INVAL, "non-finite point coordinate");
+}
+
+Plan* make_plan(int nprob, const double* points, const int64_t* m_off,
+                const int32_t* nx, const int32_t* ny, const nudft2_opts* opts) {
+  validate(nprob, points, m_off, nx, ny, opts);
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    throw Error(NUDFT2_E_DEVICE, "no HIP device available");
+  }
+  std::unique_ptr<Plan> P(new Plan());
+  P->opts = *opts;
+  P->stream = (hipStream_t)opts->stream;
+  P->arena.cap = opts->mem_cap;
+  ND_HIP(hipGetDevice(&P->device));
+  P->Mtot = m_off[nprob];
+  P->probs.resize(nprob);
+  int64_t c0 = 0;
+  for (int p = 0; p < nprob; ++p) {
+    Problem& q = P->probs[p];
+    q.nx = nx[p];
+    q.ny = ny[p];
+    q.m0 = m_off[p];
+    q.M = m_off[p + 1] - m_off[p];
+    q.c0 = c0;
+    q.L = tree_depth(q.nx, q.ny, opts->leaf);
+    c0 += q.N();
+    P->Lmax = std::max(P->Lmax, q.L);
+  }
+  P->Ntot = c0;
+  HostOrder H;
+  H.pts_user.resize(2 * P->Mtot);
+  H.pts_2d.resize(2 * P->Mtot);
+  H.xs.resize(P->Mtot);
+  H.ys.resize(P->Mtot);
+  H.perm2d.resize(P->Mtot);
+  H.posx.resize(P->Mtot);
+  H.posy.resize(P->Mtot);
+  H.colperm.resize(P->Ntot);
+  for (auto& q : P->probs) bin_problem(q, points, opts->leaf, H);
+
+  Arena& A = P->arena;
+  P->pts_user = (double*)A.alloc(sizeof(double) * 2 * P->Mtot);
+  P->pts_2d = (double*)A.alloc(sizeof(double) * 2 * P->Mtot);
+  P->perm2d = (int64_t*)A.alloc(sizeof(int64_t) * P->Mtot);
+  P->xs = (double*)A.alloc(sizeof(double) * P->Mtot);
+  P->ys = (double*)A.alloc(sizeof(double) * P->Mtot);
+  P->posx = (int64_t*)A.alloc(sizeof(int64_t) * P->Mtot);
+  P->posy = (int64_t*)A.alloc(sizeof(int64_t) * P->Mtot);
+  P->colperm = (int64_t*)A.alloc(sizeof(int64_t) * P->Ntot);
+  hipStream_t s = P->stream;
+  ND_HIP(hipMemcpyAsync(P->pts_user, H.pts_user.data(), sizeof(double) * 2 * P->Mtot, hipMemcpyHostToDevice, s));
+  ND_HIP(hipMemcpyAsync(P->pts_2d, H.pts_2d.data(), sizeof(double) * 2 * P->Mtot, hipMemcpyHostToDevice, s));
+  ND_HIP(hipMemcpyAsync(P->perm2d, H.perm2d.data(), sizeof(int64_t) * P->Mtot, hipMemcpyHostToDevice, s));
+  ND_HIP(hipMemcpyAsync(P->xs, H.xs.data(), sizeof(double) * P->Mtot, hipMemcpyHostToDevice, s));
+  ND_HIP(hipMemcpyAsync(P->ys, H.ys.data(), sizeof(double) * P->Mtot, hipMemcpyHostToDevice, s));
+  ND_HIP(hipMemcpyAsync(P->posx, H.posx.data(), sizeof(int64_t) * P->Mtot, hipMemcpyHostToDevice, s));
+  ND_HIP(hipMemcpyAsync(P->posy, H.posy.data(), sizeof(int64_t) * P->Mtot, hipMemcpyHostToDevice, s));
+  ND_HIP(hipMemcpyAsync(P->colperm, H.colperm.data(), sizeof(int64_t) * P->Ntot, hipMemcpyHostToDevice, s));
+
+  std::vector<ApplyProb> ap(nprob);
+  std::vector<int> toff(nprob + 1, 0);
+  for (int p = 0; p < nprob; ++p) {
+    const Problem& q = P->probs[p];
+    ap[p] = ApplyProb{q.m0, q.M, q.c0, q.nx, q.ny};
+    toff[p + 1] = toff[p] + ceil_div(q.M, 64);
+  }
+  P->apply_tiles = toff[nprob];
+  P->d_aprob = (ApplyProb*)A.alloc(sizeof(ApplyProb) * nprob);
+  P->d_tile_off = (int*)A.alloc(sizeof(int) * (nprob + 1));
+  ND_HIP(hipMemcpyAsync(P->d_aprob, ap.data(), sizeof(ApplyProb) * nprob, hipMemcpyHostToDevice, s));
+  ND_HIP(hipMemcpyAsync(P->d_tile_off, toff.data(), sizeof(int) * (nprob + 1), hipMemcpyHostToDevice, s));
+  ND_HIP(hipStreamSynchronize(s));
+  P->info.nprob = nprob;
+  P->info.levels = P->Lmax;
+  return P.release();
+}
+
+// Host-only binning used by the test hooks: returns the 2D order (caller
+// indices), leaf row offsets (4^L + 1) and the quadtree column permutation.
+void host_binning(const double* points, int64_t M, int nx, int ny, int leaf,
+                  int64_t* perm2d, int64_t* leaf_rows, int64_t* colperm) {
+  Problem q;
+  q.nx = nx;
+  q.ny = ny;
+  q.M = M;
+  q.L = tree_depth(nx, ny, leaf);
+  HostOrder H;
+  H.pts_user.resize(2 * M);
+  H.pts_2d.resize(2 * M);
+  H.xs.resize(M);
+  H.ys.resize(M);
+  H.perm2d.resize(M);
+  H.posx.resize(M);
+  H.posy.resize(M);
+  H.colperm.resize(q.N());
+  bin_problem(q, points, leaf, H);
+  std::copy(H.perm2d.begin(), H.perm2d.end(), perm2d);
+  std::copy(q.row2[q.L].begin(), q.row2[q.L].end(), leaf_rows);
+  std::copy(H.colperm.begin(), H.colperm.end(), colperm);
+}
+
+}  // namespace nd

@@ -1,0 +1,114 @@
+"""C-ABI checks that need no GPU: exported symbols, argument validation and
+status codes, host binning against the oracle's trees."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+from paper_2607_00928_amd import _lib  # noqa: E402
+from paper_2607_00928_amd._lib import lib  # noqa: E402
+from nudft_inputs import make_problem  # noqa: E402
+from oracle import hss as ohss  # noqa: E402
+
+HAS_GPU = torch.cuda.is_available()
+
+
+def declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(inc, fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(nudft2_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_symbols()
+    assert "nudft2_solve" in names and "nudft2_plan" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _plan(points, M, nx, ny, opts=None):
+    o = opts or _lib.default_opts()
+    h = C.c_void_p()
+    p = None if points is None else _lib.dptr(points)
+    return lib.nudft2_plan(C.byref(h), p, M, nx, ny, C.byref(o)), h
+
+
+def test_invalid_arguments_rejected_before_device_work():
+    pr = make_problem(8, 8, 16, 16, 0.3, 3)
+    pts = np.ascontiguousarray(pr.points)
+    assert _plan(None, pr.M, 8, 8)[0] == 1
+    assert _plan(pts, 63, 8, 8)[0] == 1            # M < N
+    assert _plan(pts, pr.M, 7, 8)[0] == 1          # odd
+    assert _plan(pts, pr.M, 0, 8)[0] == 1
+    bad = pts.copy()
+    bad[5, 1] = np.nan
+    assert _plan(bad, pr.M, 8, 8)[0] == 1
+    bad[5, 1] = np.inf
+    assert _plan(bad, pr.M, 8, 8)[0] == 1
+    o = _lib.default_opts()
+    o.eps = 0.0
+    assert _plan(pts, pr.M, 8, 8, o)[0] == 1
+    o = _lib.default_opts()
+    o.precision = 3
+    assert _plan(pts, pr.M, 8, 8, o)[0] == 1
+    assert lib.nudft2_last_error() != b""
+
+
+def test_null_plan_calls():
+    assert lib.nudft2_factor(None) == 1
+    assert lib.nudft2_solve(None, None, None, 1, None) == 1
+    assert lib.nudft2_apply(None, None, None, 1) == 1
+    assert lib.nudft2_destroy(None) == 0
+    assert lib.nudft2_strerror(2) == b"call out of order"
+
+
+@pytest.mark.skipif(HAS_GPU, reason="checks the no-device status on a CPU-only host")
+def test_valid_arguments_without_device():
+    pr = make_problem(8, 8, 16, 16, 0.3, 3)
+    st, _ = _plan(np.ascontiguousarray(pr.points), pr.M, 8, 8)
+    assert st == 3
+
+
+@pytest.mark.parametrize("nx,ny,leaf", [(16, 16, 4), (24, 8, 4), (12, 20, 4)])
+def test_binning_matches_oracle_tree(nx, ny, leaf):
+    pr = make_problem(nx, ny, 2 * nx, 2 * ny, 0.45, 5)
+    pts = np.ascontiguousarray(pr.points)
+    M = pr.M
+    L = ohss.depth_for(nx, ny, leaf)
+    perm = np.zeros(M, np.int64)
+    rows = np.zeros(4 ** L + 1, np.int64)
+    colperm = np.zeros(nx * ny, np.int64)
+    depth = C.c_int32()
+    st = lib.nudft2_test_binning(
+        _lib.dptr(pts), M, nx, ny, leaf,
+        perm.ctypes.data_as(C.POINTER(C.c_int64)),
+        rows.ctypes.data_as(C.POINTER(C.c_int64)),
+        colperm.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(depth))
+    assert st == 0
+    assert depth.value == L
+    t = ohss.tree_2d(pr.points, nx, ny, L)
+    # leaves in Morton order: z -> (a, b) with child index 2p + q per level
+    for z in range(4 ** L):
+        a = b = 0
+        for i in range(L):
+            a |= ((z >> (2 * i + 1)) & 1) << i
+            b |= ((z >> (2 * i)) & 1) << i
+        nd = t.nodes[(L, a, b)]
+        got_rows = np.sort(perm[rows[z]:rows[z + 1]])
+        assert np.array_equal(got_rows, nd.rows)
+        # leaf columns in quadtree order equal the node's kx-major columns
+        c0 = sum(t.nodes[(L, *ab)].cols.size for ab in [
+            (sum(((zz >> (2 * i + 1)) & 1) << i for i in range(L)),
+             sum(((zz >> (2 * i)) & 1) << i for i in range(L))) for zz in range(z)])
+        assert np.array_equal(colperm[c0:c0 + nd.cols.size], nd.cols)
+    assert np.array_equal(np.sort(colperm), np.arange(nx * ny))
