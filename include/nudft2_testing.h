@@ -29,9 +29,14 @@ nudft2_status nudft2_test_binning(const double* points, int64_t M, int32_t nx,
 
 /* One 16x16x4 FP64 matrix-core step on the device with A[i][k] = a[i*4+k],
  * B[k][j] = b[k*16+j] (HOST inputs); writes D = A B (16 x 16, row-major) to
- * the HOST array d.  Checks the operand/accumulator lane layout the kernels
- * assume. */
+ * the HOST array d, writing accumulator register v of lane l to row l/16+4v,
+ * column l%16 (the interleaved row layout of the FP64 instruction). */
 nudft2_status nudft2_test_mfma_layout(const double* a, const double* b, double* d);
+
+/* Same for the FP32 16x16x4 step.  The probe writes the accumulator register
+ * v of lane l to row 4(l/16)+v, column l%16 of d, so d equals A B exactly when
+ * the instruction uses that (blocked) row layout. */
+nudft2_status nudft2_test_mfma_layout32(const float* a, const float* b, float* d);
 
 #ifdef __cplusplus
 }

@@ -73,6 +73,7 @@ def _load():
     DP = C.POINTER(C.c_double)
     I64P = C.POINTER(C.c_int64)
     I32P = C.POINTER(C.c_int32)
+    FP = C.POINTER(C.c_float)
     sig = {
         "nudft2_default_opts": (None, [C.POINTER(Opts)]),
         "nudft2_plan": (C.c_int, [C.POINTER(P), DP, C.c_int64, C.c_int32, C.c_int32,
@@ -91,6 +92,7 @@ def _load():
         "nudft2_test_binning": (C.c_int, [DP, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                           I64P, I64P, I64P, I32P]),
         "nudft2_test_mfma_layout": (C.c_int, [DP, DP, DP]),
+        "nudft2_test_mfma_layout32": (C.c_int, [FP, FP, FP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

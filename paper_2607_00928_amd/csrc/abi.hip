@@ -40,7 +40,35 @@ __global__ void mfma_probe_kernel(const double* a, const double* b, double* d) {
   double bv = b[(lane / 16) * 16 + lane % 16];
   dbl4 acc = dbl4{0, 0, 0, 0};
   acc = mfma16(av, bv, acc);
+  for (int v = 0; v < 4; ++v) d[((lane / 16) + 4 * v) * 16 + lane % 16] = acc[v];
+}
+__global__ void mfma_probe32_kernel(const float* a, const float* b, float* d) {
+  int lane = threadIdx.x;
+  float av = a[(lane % 16) * 4 + lane / 16];
+  float bv = b[(lane / 16) * 16 + lane % 16];
+  flt4 acc = flt4{0, 0, 0, 0};
+  acc = mfma16(av, bv, acc);
   for (int v = 0; v < 4; ++v) d[(4 * (lane / 16) + v) * 16 + lane % 16] = acc[v];
+}
+template <typename T, typename K>
+void run_probe(K kern, const T* a, const T* b, T* d) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    throw Error(NUDFT2_E_DEVICE, "no HIP device available");
+  }
+  T *da, *db, *dd;
+  ND_HIP(hipMalloc(&da, 64 * sizeof(T)));
+  ND_HIP(hipMalloc(&db, 64 * sizeof(T)));
+  ND_HIP(hipMalloc(&dd, 256 * sizeof(T)));
+  ND_HIP(hipMemcpy(da, a, 64 * sizeof(T), hipMemcpyHostToDevice));
+  ND_HIP(hipMemcpy(db, b, 64 * sizeof(T), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(kern, dim3(1), dim3(64), 0, nullptr, da, db, dd);
+  ND_HIP(hipGetLastError());
+  ND_HIP(hipMemcpy(d, dd, 256 * sizeof(T), hipMemcpyDeviceToHost));
+  (void)hipFree(da);
+  (void)hipFree(db);
+  (void)hipFree(dd);
 }
 }  // namespace
 
@@ -184,23 +212,14 @@ nudft2_status nudft2_test_binning(const double* points, int64_t M, int32_t nx, i
 nudft2_status nudft2_test_mfma_layout(const double* a, const double* b, double* d) {
   return guard([&] {
     ND_CHECK(a && b && d, NUDFT2_E_INVAL, "null pointer");
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
-      (void)hipGetLastError();
-      throw Error(NUDFT2_E_DEVICE, "no HIP device available");
-    }
-    double *da, *db, *dd;
-    ND_HIP(hipMalloc(&da, 64 * sizeof(double)));
-    ND_HIP(hipMalloc(&db, 64 * sizeof(double)));
-    ND_HIP(hipMalloc(&dd, 256 * sizeof(double)));
-    ND_HIP(hipMemcpy(da, a, 64 * sizeof(double), hipMemcpyHostToDevice));
-    ND_HIP(hipMemcpy(db, b, 64 * sizeof(double), hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, nullptr, da, db, dd);
-    ND_HIP(hipGetLastError());
-    ND_HIP(hipMemcpy(d, dd, 256 * sizeof(double), hipMemcpyDeviceToHost));
-    (void)hipFree(da);
-    (void)hipFree(db);
-    (void)hipFree(dd);
+    run_probe<double>(mfma_probe_kernel, a, b, d);
+  });
+}
+
+nudft2_status nudft2_test_mfma_layout32(const float* a, const float* b, float* d) {
+  return guard([&] {
+    ND_CHECK(a && b && d, NUDFT2_E_INVAL, "null pointer");
+    run_probe<float>(mfma_probe32_kernel, a, b, d);
   });
 }
 

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void apply_fwd_kernel(
       bool ok = (kx0 + kxl) < nx;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int r = wave * 16 + 4 * kq + v;
+        int r = wave * 16 + mrow<double>(lane, v);
         double2 ax = cmul(basex[r][tt], E1x[r][lane & 15]);
         double tr = accr[tt][v], ti = acci[tt][v];
         if (ok) {
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void apply_fwd_kernel(
   if ((lane & 15) == 0) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      int64_t r = row0 + wave * 16 + 4 * kq + v;
+      int64_t r = row0 + wave * 16 + mrow<double>(lane, v);
       if (r < pr.M) fp[r] = mk<double>(facc[v], faci[v]);
     }
   }
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void apply_adj_kernel(
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int v = 0; v < 4; ++v) {
-        int kx = kx0 + wm + a * 16 + 4 * (lane >> 4) + v;
+        int kx = kx0 + wm + a * 16 + mrow<double>(lane, v);
         int ky = ky0 + wn + b * 16 + (lane & 15);
         if (kx < nx && ky < ny) {
           double* dst = reinterpret_cast<double*>(cp + (int64_t)kx * ny + ky);

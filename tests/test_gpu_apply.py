@@ -26,6 +26,12 @@ def test_mfma_layout():
     st = _lib.lib.nudft2_test_mfma_layout(_lib.dptr(a), _lib.dptr(b), _lib.dptr(d))
     assert st == 0
     assert np.array_equal(d, a @ b)
+    a32, b32 = a.astype(np.float32), b.astype(np.float32)
+    d32 = np.zeros((16, 16), np.float32)
+    fp = lambda x: x.ctypes.data_as(__import__("ctypes").POINTER(__import__("ctypes").c_float))
+    st = _lib.lib.nudft2_test_mfma_layout32(fp(a32), fp(b32), fp(d32))
+    assert st == 0
+    assert np.array_equal(d32, a32 @ b32)
 
 
 @pytest.mark.parametrize("nx,ny,mx,my,delta,seed", [
@@ -69,8 +75,9 @@ def test_apply_full_size_sampled():
     c = plan.apply_adj(torch.from_numpy(g).to(dev())).cpu().numpy()
     kx = rng.integers(0, 512, 16)
     ky = rng.integers(0, 512, 16)
-    ex = onu.nudft_1d(pr.points[:, 0], 512)[:, kx]
-    ey = onu.nudft_1d(pr.points[:, 1], 512)[:, ky]
+    k = onu.centred_freqs(512)
+    ex = onu.expi_turns(onu.phase_turns(k[kx], pr.points[:, 0]))
+    ey = onu.expi_turns(onu.phase_turns(k[ky], pr.points[:, 1]))
     ref = (ex * ey).conj().T @ g
     got = c[kx, ky]
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
