@@ -38,6 +38,41 @@ nudft2_status nudft2_test_mfma_layout(const double* a, const double* b, double* 
  * the instruction uses that (blocked) row layout. */
 nudft2_status nudft2_test_mfma_layout32(const float* a, const float* b, float* d);
 
+/* Batched dense building blocks on DEVICE data (complex128 when prec == 0,
+ * complex64 when prec == 1; column-major with leading dimensions).  Per
+ * problem sizes, leading dimensions and device addresses are HOST arrays;
+ * all work runs on the default stream and is finished on return.
+ *
+ * gemm:  C_i = alpha op(A_i) op(B_i) + beta C_i; op 0 = none, 1 = conj
+ *        transpose; mnk = (m, n, k) per problem, ld = (lda, ldb, ldc),
+ *        ptrs = (A, B, C).
+ * geqrf: Householder QR; mn = (m, n), ld = (lda, ldr), ptrs = (A, R, Tb) with
+ *        Tb holding ceil(min(m,n)/32) blocks of 32x32.  A returns the
+ *        explicit unit lower-trapezoidal reflectors V, R the triangular
+ *        factor, Tb the compact-WY factors (Q = prod_j (I - V_j T_j V_j^H)).
+ * ormqr: C <- Q C (trans = 0) or Q^H C (trans = 1) with dims = (m, k, nc),
+ *        ld = (ldv, ldc), ptrs = (V, Tb, C).
+ * pchol: diagonally pivoted Cholesky of Hermitian PSD K_i (w_i x w_i,
+ *        complex128, leading dimension w_i, overwritten) into L_i (w_i x
+ *        rmax_i), stopping when the remaining Schur-complement trace is at
+ *        most tol2 * trace(K_i).  rank_out (HOST, nb) and piv_out (HOST,
+ *        sum rmax_i) receive the ranks and pivot rows.
+ * trsv:  R_i X_i = B_i in place, R upper triangular; dims = (k, nrhs),
+ *        ld = (ldr, ldb), ptrs = (R, B). */
+nudft2_status nudft2_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t nb,
+                               const int32_t* mnk, const int32_t* ld, const int64_t* ptrs,
+                               double alpha_re, double alpha_im, double beta);
+nudft2_status nudft2_test_geqrf(int32_t prec, int32_t nb, const int32_t* mn,
+                                const int32_t* ld, const int64_t* ptrs);
+nudft2_status nudft2_test_ormqr(int32_t prec, int32_t trans, int32_t nb,
+                                const int32_t* dims, const int32_t* ld,
+                                const int64_t* ptrs);
+nudft2_status nudft2_test_pchol(int32_t nb, const int32_t* w, const int32_t* rmax,
+                                const int64_t* ptrs, double tol2, int32_t* rank_out,
+                                int32_t* piv_out);
+nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims,
+                               const int32_t* ld, const int64_t* ptrs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,12 @@ def _load():
                                           I64P, I64P, I64P, I32P]),
         "nudft2_test_mfma_layout": (C.c_int, [DP, DP, DP]),
         "nudft2_test_mfma_layout32": (C.c_int, [FP, FP, FP]),
+        "nudft2_test_gemm": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, I32P, I32P,
+                                       I64P, C.c_double, C.c_double, C.c_double]),
+        "nudft2_test_geqrf": (C.c_int, [C.c_int32, C.c_int32, I32P, I32P, I64P]),
+        "nudft2_test_ormqr": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, I32P, I32P, I64P]),
+        "nudft2_test_pchol": (C.c_int, [C.c_int32, I32P, I32P, I64P, C.c_double, I32P, I32P]),
+        "nudft2_test_trsv": (C.c_int, [C.c_int32, C.c_int32, I32P, I32P, I64P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -4,6 +4,7 @@
 #include "../../include/nudft2_testing.h"
 #include "device_util.h"
 #include "hss.h"
+#include "la.h"
 #include "plan.h"
 #include "solver.h"
 
@@ -71,6 +72,73 @@ void run_probe(K kern, const T* a, const T* b, T* d) {
   (void)hipFree(dd);
 }
 }  // namespace
+
+static void need_device() {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    throw Error(NUDFT2_E_DEVICE, "no HIP device available");
+  }
+}
+
+template <typename T>
+static void test_gemm(int opA, int opB, int nb, const int32_t* mnk, const int32_t* ld,
+                      const int64_t* ptrs, double ar, double ai, double beta) {
+  std::vector<GemmDesc<T>> d(nb);
+  for (int i = 0; i < nb; ++i)
+    d[i] = GemmDesc<T>{mnk[3 * i], mnk[3 * i + 1], mnk[3 * i + 2], ld[3 * i], ld[3 * i + 1],
+                       ld[3 * i + 2], (const cplx<T>*)ptrs[3 * i],
+                       (const cplx<T>*)ptrs[3 * i + 1], (cplx<T>*)ptrs[3 * i + 2], (T)ar,
+                       (T)ai, (T)beta};
+  DescPool pool;
+  pool.init(1 << 20, nullptr);
+  gemm_batched<T>(pool, d, (Op)opA, (Op)opB);
+  pool.sync_reset();
+}
+
+template <typename T>
+static void test_geqrf(int nb, const int32_t* mn, const int32_t* ld, const int64_t* ptrs) {
+  std::vector<QRDesc<T>> d(nb);
+  for (int i = 0; i < nb; ++i)
+    d[i] = QRDesc<T>{mn[2 * i], mn[2 * i + 1], ld[2 * i], ld[2 * i + 1], (cplx<T>*)ptrs[3 * i],
+                     (cplx<T>*)ptrs[3 * i + 1], (cplx<T>*)ptrs[3 * i + 2]};
+  DescPool pool;
+  pool.init(16 << 20, nullptr);
+  void* ws;
+  ND_HIP(hipMalloc(&ws, qr_workspace<T>(d)));
+  geqrf_batched<T>(pool, d, ws);
+  pool.sync_reset();
+  ND_HIP(hipFree(ws));
+}
+
+template <typename T>
+static void test_ormqr(int trans, int nb, const int32_t* dims, const int32_t* ld,
+                       const int64_t* ptrs) {
+  std::vector<OrmDesc<T>> d(nb);
+  for (int i = 0; i < nb; ++i)
+    d[i] = OrmDesc<T>{dims[3 * i], dims[3 * i + 1], dims[3 * i + 2], ld[2 * i], ld[2 * i + 1],
+                      (const cplx<T>*)ptrs[3 * i], (const cplx<T>*)ptrs[3 * i + 1],
+                      (cplx<T>*)ptrs[3 * i + 2]};
+  DescPool pool;
+  pool.init(16 << 20, nullptr);
+  void* ws;
+  ND_HIP(hipMalloc(&ws, orm_workspace<T>(d)));
+  ormqr_batched<T>(pool, d, trans != 0, ws);
+  pool.sync_reset();
+  ND_HIP(hipFree(ws));
+}
+
+template <typename T>
+static void test_trsv(int nb, const int32_t* dims, const int32_t* ld, const int64_t* ptrs) {
+  std::vector<TrsDesc<T>> d(nb);
+  for (int i = 0; i < nb; ++i)
+    d[i] = TrsDesc<T>{dims[2 * i], dims[2 * i + 1], ld[2 * i], ld[2 * i + 1],
+                      (const cplx<T>*)ptrs[2 * i], (cplx<T>*)ptrs[2 * i + 1]};
+  DescPool pool;
+  pool.init(1 << 20, nullptr);
+  trsv_upper_batched<T>(pool, d);
+  pool.sync_reset();
+}
 
 }  // namespace nd
 
@@ -220,6 +288,82 @@ nudft2_status nudft2_test_mfma_layout32(const float* a, const float* b, float* d
   return guard([&] {
     ND_CHECK(a && b && d, NUDFT2_E_INVAL, "null pointer");
     run_probe<float>(mfma_probe32_kernel, a, b, d);
+  });
+}
+
+nudft2_status nudft2_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t nb,
+                               const int32_t* mnk, const int32_t* ld, const int64_t* ptrs,
+                               double ar, double ai, double beta) {
+  return guard([&] {
+    ND_CHECK(mnk && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
+    need_device();
+    if (prec == 0) test_gemm<double>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta);
+    else test_gemm<float>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta);
+  });
+}
+
+nudft2_status nudft2_test_geqrf(int32_t prec, int32_t nb, const int32_t* mn, const int32_t* ld,
+                                const int64_t* ptrs) {
+  return guard([&] {
+    ND_CHECK(mn && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
+    need_device();
+    if (prec == 0) test_geqrf<double>(nb, mn, ld, ptrs);
+    else test_geqrf<float>(nb, mn, ld, ptrs);
+  });
+}
+
+nudft2_status nudft2_test_ormqr(int32_t prec, int32_t trans, int32_t nb, const int32_t* dims,
+                                const int32_t* ld, const int64_t* ptrs) {
+  return guard([&] {
+    ND_CHECK(dims && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
+    need_device();
+    if (prec == 0) test_ormqr<double>(trans, nb, dims, ld, ptrs);
+    else test_ormqr<float>(trans, nb, dims, ld, ptrs);
+  });
+}
+
+nudft2_status nudft2_test_pchol(int32_t nb, const int32_t* w, const int32_t* rmax,
+                                const int64_t* ptrs, double tol2, int32_t* rank_out,
+                                int32_t* piv_out) {
+  return guard([&] {
+    ND_CHECK(w && rmax && ptrs && rank_out && piv_out && nb > 0, NUDFT2_E_INVAL, "bad arguments");
+    need_device();
+    std::vector<PcholDesc> d(nb);
+    std::vector<void*> allocs;
+    int* ranks;
+    ND_HIP(hipMalloc((void**)&ranks, sizeof(int) * nb));
+    int tot = 0;
+    for (int i = 0; i < nb; ++i) tot += rmax[i];
+    int* piv;
+    ND_HIP(hipMalloc((void**)&piv, sizeof(int) * std::max(tot, 1)));
+    int off = 0;
+    for (int i = 0; i < nb; ++i) {
+      double* dw;
+      ND_HIP(hipMalloc((void**)&dw, sizeof(double) * std::max(w[i], 1)));
+      allocs.push_back(dw);
+      d[i] = PcholDesc{w[i], w[i], w[i], rmax[i], (double2*)ptrs[2 * i], (double2*)ptrs[2 * i + 1],
+                       dw, piv + off, ranks + i, tol2};
+      off += rmax[i];
+    }
+    DescPool pool;
+    pool.init(16 << 20, nullptr);
+    pchol_batched(pool, d);
+    pool.sync_reset();
+    ND_HIP(hipMemcpy(rank_out, ranks, sizeof(int) * nb, hipMemcpyDeviceToHost));
+    if (tot > 0) ND_HIP(hipMemcpy(piv_out, piv, sizeof(int) * tot, hipMemcpyDeviceToHost));
+    for (void* p : allocs) (void)hipFree(p);
+    (void)hipFree(ranks);
+    (void)hipFree(piv);
+  });
+}
+
+nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims, const int32_t* ld,
+                               const int64_t* ptrs) {
+  return guard([&] {
+    ND_CHECK(dims && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
+    need_device();
+    if (prec == 0) test_trsv<double>(nb, dims, ld, ptrs);
+    else test_trsv<float>(nb, dims, ld, ptrs);
   });
 }
 

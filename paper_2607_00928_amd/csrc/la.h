@@ -1,0 +1,128 @@
+// Batched dense complex linear algebra on the matrix cores (gfx950).
+//
+// All matrices are column-major with a leading dimension; complex numbers are
+// interleaved (float2 / double2).  A "batch" is a list of independent
+// problems of arbitrary (ragged) sizes executed by one launch.
+#pragma once
+
+#include "common.h"
+
+namespace nd {
+
+enum Op { OpN = 0, OpC = 1 };   // none / conjugate transpose
+
+// Descriptor staging: descriptors are written to pinned host memory and
+// copied to the device on the stream.  The pool is a bump allocator that is
+// recycled only by an explicit sync_reset() (stream synchronisation first),
+// so a descriptor is never overwritten while a kernel may still read it.
+struct DescPool {
+  char* host = nullptr;
+  char* dev = nullptr;
+  size_t cap = 0, used = 0;
+  hipStream_t stream = nullptr;
+  void init(size_t bytes, hipStream_t s);
+  void destroy();
+  // copies n bytes to the device, returns the device address
+  void* push(const void* src, size_t n);
+  void sync_reset();
+  ~DescPool() { destroy(); }
+};
+
+template <typename T>
+struct GemmDesc {
+  int m, n, k;
+  int lda, ldb, ldc;
+  const cplx<T>* A;
+  const cplx<T>* B;
+  cplx<T>* C;
+  T ar, ai;     // alpha
+  T beta;       // real beta
+};
+
+template <typename T>
+void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB);
+
+// Householder QR of a batch: A (m x n, lda) is overwritten by the explicit
+// reflector matrix V (m x kmin, unit lower trapezoidal, zeros above the
+// diagonal); R (kmin x n, ldr) receives the triangular factor; Tb receives the
+// compact-WY factors, one QR_NB x QR_NB block per panel (Q = H_1 ... H_k,
+// each panel Q_j = I - V_j T_j V_j^H).  ws: workspace (see qr_workspace).
+constexpr int QR_NB = 32;
+template <typename T>
+struct QRDesc {
+  int m, n;
+  int lda, ldr;
+  cplx<T>* A;
+  cplx<T>* R;
+  cplx<T>* Tb;   // ceil(kmin / QR_NB) blocks of QR_NB*QR_NB
+};
+inline int qr_kmin(int m, int n) { return m < n ? m : n; }
+inline int qr_nblocks(int m, int n) { return (qr_kmin(m, n) + QR_NB - 1) / QR_NB; }
+template <typename T>
+size_t qr_workspace(const std::vector<QRDesc<T>>& d);   // bytes
+template <typename T>
+void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& d, void* ws);
+
+// Apply Q (trans = false) or Q^H (trans = true) of a QR from geqrf_batched to
+// C (m x nc, ldc) from the left, in place.  Only the first `kuse` reflectors
+// of each problem are used when kuse >= 0 (all when kuse < 0).
+template <typename T>
+struct OrmDesc {
+  int m, k, nc;         // rows, reflectors, columns of C
+  int ldv, ldc;
+  const cplx<T>* V;
+  const cplx<T>* Tb;
+  cplx<T>* C;
+};
+template <typename T>
+size_t orm_workspace(const std::vector<OrmDesc<T>>& d);
+template <typename T>
+void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans, void* ws);
+
+// Diagonally pivoted Cholesky of Hermitian PSD matrices K (w x w, FP64,
+// overwritten by the Schur complement) with a trace stopping rule: stop at the
+// first k with sum of the remaining diagonal <= tol2 * trace(K).  Outputs the
+// factor L (w x rmax, ldl; columns in pivot order) and the rank (device int).
+struct PcholDesc {
+  int w, ldk, ldl, rmax;
+  double2* K;
+  double2* L;
+  double* d;       // workspace, w doubles
+  int* piv;        // rmax ints
+  int* rank;       // output
+  double tol2;
+};
+void pchol_batched(DescPool& pool, const std::vector<PcholDesc>& d);
+
+// Batched upper-triangular solve R X = B in place (R: k x k, ldr; B: k x nrhs,
+// ldb).
+template <typename T>
+struct TrsDesc {
+  int k, nrhs, ldr, ldb;
+  const cplx<T>* R;
+  cplx<T>* B;
+};
+template <typename T>
+void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d);
+
+// Elementwise helpers (batched over descriptors).
+template <typename TD, typename TS>
+struct CopyDesc {
+  int m, n, lds, ldd;
+  const cplx<TS>* S;
+  cplx<TD>* D;
+  int conj_trans;   // 1: D = S^H (D is n x m)
+};
+template <typename TD, typename TS>
+void copy_batched(DescPool& pool, const std::vector<CopyDesc<TD, TS>>& d);
+
+template <typename T>
+struct FillDesc {
+  int m, n, ld;
+  cplx<T>* D;
+  int identity;     // 1: identity (ones on the diagonal), 0: zeros
+};
+template <typename T>
+void fill_batched(DescPool& pool, const std::vector<FillDesc<T>>& d);
+
+}  // namespace nd

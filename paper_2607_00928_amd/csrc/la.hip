@@ -1,0 +1,701 @@
+// Batched complex GEMM / Householder QR / pivoted Cholesky / triangular solve
+// for gfx950.  GEMM-shaped work runs on the 16x16x4 matrix cores (FP64 or
+// FP32 with FP32 accumulation): a complex product is four real MFMAs,
+// Cr += Ar Br - Ai Bi and Ci += Ar Bi + Ai Br.
+#include <algorithm>
+#include <cstring>
+
+#include "device_util.h"
+#include "la.h"
+
+namespace nd {
+
+// ------------------------------------------------------------ descriptor pool
+void DescPool::init(size_t bytes, hipStream_t s) {
+  destroy();
+  cap = bytes;
+  stream = s;
+  ND_HIP(hipHostMalloc((void**)&host, cap, hipHostMallocDefault));
+  ND_HIP(hipMalloc((void**)&dev, cap));
+  used = 0;
+}
+
+void DescPool::destroy() {
+  if (host) (void)hipHostFree(host);
+  if (dev) (void)hipFree(dev);
+  host = dev = nullptr;
+  cap = used = 0;
+}
+
+void DescPool::sync_reset() {
+  ND_HIP(hipStreamSynchronize(stream));
+  used = 0;
+}
+
+void* DescPool::push(const void* src, size_t n) {
+  size_t need = (n + 255) & ~size_t(255);
+  ND_CHECK(used + need <= cap, NUDFT2_E_INTERNAL, "descriptor pool exhausted");
+  std::memcpy(host + used, src, n);
+  ND_HIP(hipMemcpyAsync(dev + used, host + used, n, hipMemcpyHostToDevice, stream));
+  void* d = dev + used;
+  used += need;
+  return d;
+}
+
+namespace {
+
+// ------------------------------------------------------------------- GEMM
+constexpr int GT = 64;    // output tile
+constexpr int GK = 16;    // k per stage
+
+template <typename T, int OPA, int OPB>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs) {
+  using C2 = cplx<T>;
+  using A4 = typename acc4<T>::type;
+  __shared__ T Asr[GK][GT + 4], Asi[GK][GT + 4];
+  __shared__ T Bsr[GK][GT + 4], Bsi[GK][GT + 4];
+  const GemmDesc<T> d = descs[blockIdx.y];
+  const int tm = (d.m + GT - 1) / GT, tn = (d.n + GT - 1) / GT;
+  if ((int)blockIdx.x >= tm * tn) return;
+  const int i0 = (blockIdx.x % tm) * GT, j0 = (blockIdx.x / tm) * GT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  A4 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) { accr[a][b] = A4{0, 0, 0, 0}; acci[a][b] = A4{0, 0, 0, 0}; }
+
+  for (int l0 = 0; l0 < d.k; l0 += GK) {
+    __syncthreads();
+    // A tile: rows i0..i0+63 of op(A), k l0..l0+15
+    if (OPA == OpN) {
+      int i = tid & 63, lq = tid >> 6;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int l = lq + 4 * u;
+        C2 v = mk<T>(0, 0);
+        if (i0 + i < d.m && l0 + l < d.k) v = d.A[(int64_t)(i0 + i) + (int64_t)(l0 + l) * d.lda];
+        Asr[l][i] = v.x;
+        Asi[l][i] = v.y;
+      }
+    } else {
+      int l = tid & 15, iq = tid >> 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int i = iq + 16 * u;
+        C2 v = mk<T>(0, 0);
+        if (i0 + i < d.m && l0 + l < d.k) v = d.A[(int64_t)(l0 + l) + (int64_t)(i0 + i) * d.lda];
+        Asr[l][i] = v.x;
+        Asi[l][i] = -v.y;
+      }
+    }
+    if (OPB == OpN) {
+      int l = tid & 15, jq = tid >> 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int j = jq + 16 * u;
+        C2 v = mk<T>(0, 0);
+        if (j0 + j < d.n && l0 + l < d.k) v = d.B[(int64_t)(l0 + l) + (int64_t)(j0 + j) * d.ldb];
+        Bsr[l][j] = v.x;
+        Bsi[l][j] = v.y;
+      }
+    } else {
+      int j = tid & 63, lq = tid >> 6;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int l = lq + 4 * u;
+        C2 v = mk<T>(0, 0);
+        if (j0 + j < d.n && l0 + l < d.k) v = d.B[(int64_t)(j0 + j) + (int64_t)(l0 + l) * d.ldb];
+        Bsr[l][j] = v.x;
+        Bsi[l][j] = -v.y;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int l = kk * 4 + (lane >> 4);
+      T ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        ar[a] = Asr[l][wr + a * 16 + (lane & 15)];
+        ai[a] = Asi[l][wr + a * 16 + (lane & 15)];
+        br[a] = Bsr[l][wc + a * 16 + (lane & 15)];
+        bi[a] = Bsi[l][wc + a * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          accr[a][b] = mfma16(ar[a], br[b], accr[a][b]);
+          accr[a][b] = mfma16(-ai[a], bi[b], accr[a][b]);
+          acci[a][b] = mfma16(ar[a], bi[b], acci[a][b]);
+          acci[a][b] = mfma16(ai[a], br[b], acci[a][b]);
+        }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int i = i0 + wr + a * 16 + mrow<T>(lane, v);
+        int j = j0 + wc + b * 16 + (lane & 15);
+        if (i < d.m && j < d.n) {
+          T cr = accr[a][b][v], ci = acci[a][b][v];
+          C2 out = mk<T>(d.ar * cr - d.ai * ci, d.ar * ci + d.ai * cr);
+          C2* p = d.C + (int64_t)i + (int64_t)j * d.ldc;
+          if (d.beta != T(0)) {
+            C2 o = *p;
+            out.x += d.beta * o.x;
+            out.y += d.beta * o.y;
+          }
+          *p = out;
+        }
+      }
+}
+
+// -------------------------------------------------------------- QR panel
+// One workgroup factors columns [j0, j0 + jb) of one problem: Householder
+// vectors (LAPACK larfg convention: H = I - tau v v^H, v_0 = 1, H^H x = beta
+// e_1 with real beta), the panel's compact-WY factor T (Q_panel = I - V T V^H)
+// and the explicit V / R split described in la.h.
+template <typename T>
+__global__ __launch_bounds__(256) void qr_panel_kernel(const QRDesc<T>* __restrict__ descs,
+                                                       const int* __restrict__ active, int j0) {
+  using C2 = cplx<T>;
+  __shared__ C2 red[4][QR_NB + 1];
+  __shared__ T redr[4];
+  __shared__ C2 wv[QR_NB];
+  __shared__ C2 Ts[QR_NB][QR_NB + 1];
+  __shared__ C2 tau_s, scal_s;
+  __shared__ T beta_s;
+  const QRDesc<T> d = descs[active[blockIdx.x]];
+  const int kmin = min(d.m, d.n);
+  const int jb = min(QR_NB, kmin - j0);
+  const int mr = d.m - j0;
+  C2* Ap = d.A + j0 + (int64_t)j0 * d.lda;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  for (int e = tid; e < QR_NB * QR_NB; e += 256) Ts[e % QR_NB][e / QR_NB] = mk<T>(0, 0);
+
+  for (int jj = 0; jj < jb; ++jj) {
+    // pass 1: sigma^2 = sum_{i > jj} |a_i|^2
+    T s = 0;
+    for (int i = jj + 1 + tid; i < mr; i += 256) {
+      C2 v = Ap[i + (int64_t)jj * d.lda];
+      s += v.x * v.x + v.y * v.y;
+    }
+    s = warp_sum(s);
+    if (lane == 0) redr[wave] = s;
+    __syncthreads();
+    if (tid == 0) {
+      T sig = redr[0] + redr[1] + redr[2] + redr[3];
+      C2 alpha = Ap[jj + (int64_t)jj * d.lda];
+      C2 tau, scal;
+      T beta;
+      if (sig == T(0) && alpha.y == T(0)) {
+        tau = mk<T>(0, 0);
+        scal = mk<T>(0, 0);
+        beta = alpha.x;
+      } else {
+        T nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig);
+        beta = alpha.x >= T(0) ? -nrm : nrm;
+        tau = mk<T>((beta - alpha.x) / beta, -alpha.y / beta);
+        // scal = 1 / (alpha - beta)
+        T dr = alpha.x - beta, di = alpha.y;
+        T den = dr * dr + di * di;
+        scal = mk<T>(dr / den, -di / den);
+      }
+      tau_s = tau;
+      scal_s = scal;
+      beta_s = beta;
+      Ts[jj][jj] = tau;
+    }
+    __syncthreads();
+    const C2 tau = tau_s, scal = scal_s;
+    // scale the vector below the diagonal
+    for (int i = jj + 1 + tid; i < mr; i += 256) {
+      C2* p = Ap + i + (int64_t)jj * d.lda;
+      *p = cmul(*p, scal);
+    }
+    if (tid == 0) Ap[jj + (int64_t)jj * d.lda] = mk<T>(beta_s, 0);
+    __syncthreads();
+    // pass 2: u_c = sum_{i >= jj} conj(v_i) A(i, c) for all c != jj
+    C2 acc[QR_NB];
+#pragma unroll
+    for (int c = 0; c < QR_NB; ++c) acc[c] = mk<T>(0, 0);
+    for (int i = jj + tid; i < mr; i += 256) {
+      C2 vi = (i == jj) ? mk<T>(1, 0) : Ap[i + (int64_t)jj * d.lda];
+#pragma unroll
+      for (int c = 0; c < QR_NB; ++c) {
+        if (c < jb && c != jj) {
+          C2 a = Ap[i + (int64_t)c * d.lda];
+          acc[c] = cadd(acc[c], cmulc(vi, a));
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < QR_NB; ++c) {
+      acc[c].x = warp_sum(acc[c].x);
+      acc[c].y = warp_sum(acc[c].y);
+      if (lane == 0) red[wave][c] = acc[c];
+    }
+    __syncthreads();
+    if (tid < QR_NB) {
+      C2 t = red[0][tid];
+      t = cadd(t, red[1][tid]);
+      t = cadd(t, red[2][tid]);
+      t = cadd(t, red[3][tid]);
+      wv[tid] = t;
+    }
+    __syncthreads();
+    // T column: T(0:jj, jj) = -tau T(0:jj, 0:jj) z, z_i = conj(u_i)
+    if (tid == 0) {
+      for (int r = 0; r < jj; ++r) {
+        C2 sum = mk<T>(0, 0);
+        for (int q = r; q < jj; ++q) sum = cadd(sum, cmul(Ts[r][q], cconj(wv[q])));
+        C2 t = cmul(tau, sum);
+        Ts[r][jj] = mk<T>(-t.x, -t.y);
+      }
+    }
+    // pass 3: A(i, c) -= conj(tau) v_i u_c for c > jj
+    const C2 ctau = cconj(tau);
+    for (int i = jj + tid; i < mr; i += 256) {
+      C2 vi = (i == jj) ? mk<T>(1, 0) : Ap[i + (int64_t)jj * d.lda];
+      C2 f = cmul(ctau, vi);
+      for (int c = jj + 1; c < jb; ++c) {
+        C2* p = Ap + i + (int64_t)c * d.lda;
+        *p = csub(*p, cmul(f, wv[c]));
+      }
+    }
+    __syncthreads();
+  }
+  // write T, the R block of the panel, the R rows above the panel, and make V explicit
+  const int blk = j0 / QR_NB;
+  C2* Tb = d.Tb + (int64_t)blk * QR_NB * QR_NB;
+  for (int e = tid; e < QR_NB * QR_NB; e += 256) {
+    int r = e % QR_NB, c = e / QR_NB;
+    Tb[r + c * QR_NB] = (r < jb && c < jb) ? Ts[r][c] : mk<T>(0, 0);
+  }
+  for (int c = 0; c < jb; ++c) {
+    int gc = j0 + c;
+    for (int r = tid; r < j0 + jb; r += 256) {
+      C2* pa = d.A + r + (int64_t)gc * d.lda;
+      C2* pr = d.R + r + (int64_t)gc * d.ldr;
+      if (r < j0) {
+        *pr = *pa;
+        *pa = mk<T>(0, 0);
+      } else {
+        int rr = r - j0;
+        if (rr <= c) {
+          *pr = *pa;
+          *pa = (rr == c) ? mk<T>(1, 0) : mk<T>(0, 0);
+        } else {
+          *pr = mk<T>(0, 0);
+        }
+      }
+    }
+  }
+}
+
+// copy of the trailing columns of wide problems (n > m) into R at the end
+template <typename T>
+__global__ void qr_wide_tail_kernel(const QRDesc<T>* __restrict__ descs) {
+  const QRDesc<T> d = descs[blockIdx.y];
+  if (d.n <= d.m) return;
+  int64_t cnt = (int64_t)d.m * (d.n - d.m);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
+    int r = (int)(e % d.m), c = d.m + (int)(e / d.m);
+    d.R[r + (int64_t)c * d.ldr] = d.A[r + (int64_t)c * d.lda];
+  }
+}
+
+// ------------------------------------------------------------ pivoted Cholesky
+constexpr int PC_NB = 32;
+
+__global__ void pchol_init_kernel(const PcholDesc* __restrict__ descs, double* trace_out) {
+  const PcholDesc d = descs[blockIdx.x];
+  __shared__ double red[4];
+  double s = 0;
+  for (int i = threadIdx.x; i < d.w; i += 256) {
+    double v = d.K[i + (int64_t)i * d.ldk].x;
+    d.d[i] = v;
+    s += v;
+  }
+  s = warp_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    trace_out[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    *d.rank = 0;
+  }
+}
+
+// One panel of up to PC_NB pivots.  state[b]: 1 = still running.
+__global__ __launch_bounds__(256) void pchol_panel_kernel(const PcholDesc* __restrict__ descs,
+                                                          const double* __restrict__ trace,
+                                                          int* __restrict__ state, int k0) {
+  const int b = blockIdx.x;
+  if (!state[b]) return;
+  const PcholDesc d = descs[b];
+  __shared__ double rv[4];
+  __shared__ int ri[4];
+  __shared__ double rs[4];
+  __shared__ int piv_s;
+  __shared__ double dp_s;
+  __shared__ int stop_s;
+  __shared__ double2 lp[PC_NB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double tol = d.tol2 * trace[b];
+  int k = k0;
+  for (int kk = 0; kk < PC_NB; ++kk, ++k) {
+    // remaining trace and argmax of the Schur diagonal
+    double best = -1.0, sum = 0.0;
+    int bi = -1;
+    for (int i = tid; i < d.w; i += 256) {
+      double v = d.d[i];
+      if (v > -1e300) {          // pivoted rows hold -inf
+        sum += v > 0 ? v : 0;
+        if (v > best) { best = v; bi = i; }
+      }
+    }
+    sum = warp_sum(sum);
+    for (int o = 32; o > 0; o >>= 1) {
+      double ob = __shfl_xor(best, o, 64);
+      int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi >= 0 && (bi < 0 || oi < bi))) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { rv[wave] = best; ri[wave] = bi; rs[wave] = sum; }
+    __syncthreads();
+    if (tid == 0) {
+      double bb = rv[0];
+      int ii = ri[0];
+      double ss = rs[0];
+      for (int w = 1; w < 4; ++w) {
+        ss += rs[w];
+        if (rv[w] > bb || (rv[w] == bb && ri[w] >= 0 && (ii < 0 || ri[w] < ii))) { bb = rv[w]; ii = ri[w]; }
+      }
+      int stop = (k >= d.rmax || k >= d.w || ss <= tol || ii < 0 || bb <= 0.0) ? 1 : 0;
+      stop_s = stop;
+      piv_s = ii;
+      dp_s = bb;
+      if (stop) {
+        *d.rank = k;
+        state[b] = 0;
+      } else {
+        d.piv[k] = ii;
+      }
+    }
+    __syncthreads();
+    if (stop_s) return;
+    const int p = piv_s;
+    const double sdp = sqrt(dp_s);
+    // conj of the pivot row of the panel's previous columns
+    if (tid < kk) {
+      double2 v = d.L[p + (int64_t)(k0 + tid) * d.ldl];
+      lp[tid] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < d.w; i += 256) {
+      double2 v = d.K[i + (int64_t)p * d.ldk];
+      for (int q = 0; q < kk; ++q) v = csub(v, cmulc(lp[q], d.L[i + (int64_t)(k0 + q) * d.ldl]));
+      // L(i,k) = (K(i,p) - sum L(i,q) conj(L(p,q))) / sqrt(d_p)
+      double dd = d.d[i];
+      if (dd <= -1e300) v = mk<double>(0.0, 0.0);
+      v.x /= sdp;
+      v.y /= sdp;
+      if (i == p) v = mk<double>(sdp, 0.0);
+      d.L[i + (int64_t)k * d.ldl] = v;
+      if (i == p) d.d[i] = -1.0 / 0.0;
+      else if (dd > -1e300) d.d[i] = dd - (v.x * v.x + v.y * v.y);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void pchol_finish_kernel(const PcholDesc* __restrict__ descs, const int* state, int kend) {
+  const PcholDesc d = descs[blockIdx.x];
+  if (threadIdx.x == 0 && state[blockIdx.x]) *d.rank = min(kend, min(d.rmax, d.w));
+}
+
+// Schur update of the unpivoted part: K -= L_p L_p^H with the panel's columns.
+// Done with the GEMM kernel (opB = C) by the host.
+
+// ------------------------------------------------------------ triangular solve
+template <typename T>
+__global__ __launch_bounds__(256) void trsv_upper_kernel(const TrsDesc<T>* __restrict__ descs) {
+  using C2 = cplx<T>;
+  const TrsDesc<T> d = descs[blockIdx.x];
+  const int rhs = blockIdx.y;
+  if (rhs >= d.nrhs) return;
+  C2* b = d.B + (int64_t)rhs * d.ldb;
+  __shared__ C2 xs;
+  for (int i = d.k - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) {
+      C2 r = d.R[i + (int64_t)i * d.ldr];
+      C2 v = b[i];
+      T den = r.x * r.x + r.y * r.y;
+      C2 x = mk<T>((v.x * r.x + v.y * r.y) / den, (v.y * r.x - v.x * r.y) / den);
+      b[i] = x;
+      xs = x;
+    }
+    __syncthreads();
+    C2 x = xs;
+    for (int r = threadIdx.x; r < i; r += 256) b[r] = csub(b[r], cmul(d.R[r + (int64_t)i * d.ldr], x));
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ copy / fill
+template <typename TD, typename TS>
+__global__ void copy_kernel(const CopyDesc<TD, TS>* __restrict__ descs) {
+  const CopyDesc<TD, TS> d = descs[blockIdx.y];
+  int64_t cnt = (int64_t)d.m * d.n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
+    int i = (int)(e % d.m), j = (int)(e / d.m);
+    cplx<TS> v = d.S[i + (int64_t)j * d.lds];
+    cplx<TD> o = mk<TD>((TD)v.x, (TD)v.y);
+    if (d.conj_trans) {
+      o.y = -o.y;
+      d.D[j + (int64_t)i * d.ldd] = o;
+    } else {
+      d.D[i + (int64_t)j * d.ldd] = o;
+    }
+  }
+}
+
+template <typename T>
+__global__ void fill_kernel(const FillDesc<T>* __restrict__ descs) {
+  const FillDesc<T> d = descs[blockIdx.y];
+  int64_t cnt = (int64_t)d.m * d.n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
+    int i = (int)(e % d.m), j = (int)(e / d.m);
+    d.D[i + (int64_t)j * d.ld] = mk<T>((d.identity && i == j) ? T(1) : T(0), T(0));
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host API
+template <typename T>
+void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB) {
+  if (d.empty()) return;
+  size_t chunk = 32768;
+  for (size_t s = 0; s < d.size(); s += chunk) {
+    size_t n = std::min(chunk, d.size() - s);
+    int maxt = 0;
+    std::vector<GemmDesc<T>> sub(d.begin() + s, d.begin() + s + n);
+    for (auto& g : sub) {
+      if (g.m <= 0 || g.n <= 0) { g.m = 0; g.n = 0; continue; }
+      if (g.k <= 0) {   // C = beta C: run with k = 0 (zero accumulators)
+        g.k = 0;
+      }
+      maxt = std::max(maxt, ceil_div(g.m, GT) * ceil_div(g.n, GT));
+    }
+    if (maxt == 0) continue;
+    auto* dd = (GemmDesc<T>*)pool.push(sub.data(), sizeof(GemmDesc<T>) * n);
+    dim3 grid(maxt, (unsigned)n);
+    if (opA == OpN && opB == OpN)
+      hipLaunchKernelGGL((gemm_kernel<T, OpN, OpN>), grid, dim3(256), 0, pool.stream, dd);
+    else if (opA == OpC && opB == OpN)
+      hipLaunchKernelGGL((gemm_kernel<T, OpC, OpN>), grid, dim3(256), 0, pool.stream, dd);
+    else if (opA == OpN && opB == OpC)
+      hipLaunchKernelGGL((gemm_kernel<T, OpN, OpC>), grid, dim3(256), 0, pool.stream, dd);
+    else
+      hipLaunchKernelGGL((gemm_kernel<T, OpC, OpC>), grid, dim3(256), 0, pool.stream, dd);
+    ND_HIP(hipGetLastError());
+  }
+}
+
+template <typename T>
+size_t qr_workspace(const std::vector<QRDesc<T>>& d) {
+  size_t s = 0;
+  for (auto& q : d) s += (size_t)QR_NB * std::max(q.n, 1) * 2;
+  return s * sizeof(cplx<T>) + 256;
+}
+
+template <typename T>
+void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& d, void* ws) {
+  if (d.empty()) return;
+  const int nb = (int)d.size();
+  auto* dd = (QRDesc<T>*)pool.push(d.data(), sizeof(QRDesc<T>) * nb);
+  int kmax = 0;
+  for (auto& q : d) kmax = std::max(kmax, qr_kmin(q.m, q.n));
+  // workspace layout per problem: W (QR_NB x n) and W2 (QR_NB x n)
+  std::vector<cplx<T>*> W(nb), W2(nb);
+  {
+    cplx<T>* p = (cplx<T>*)ws;
+    for (int i = 0; i < nb; ++i) {
+      W[i] = p;
+      p += (size_t)QR_NB * std::max(d[i].n, 1);
+      W2[i] = p;
+      p += (size_t)QR_NB * std::max(d[i].n, 1);
+    }
+  }
+  std::vector<int> act;
+  std::vector<GemmDesc<T>> g1, g2, g3;
+  for (int j0 = 0; j0 < kmax; j0 += QR_NB) {
+    act.clear();
+    g1.clear(); g2.clear(); g3.clear();
+    for (int i = 0; i < nb; ++i) {
+      const QRDesc<T>& q = d[i];
+      int kmin = qr_kmin(q.m, q.n);
+      if (kmin <= j0) continue;
+      act.push_back(i);
+      int jb = std::min(QR_NB, kmin - j0);
+      int nt = q.n - j0 - jb;
+      if (nt <= 0) continue;
+      int mr = q.m - j0;
+      cplx<T>* V = q.A + j0 + (int64_t)j0 * q.lda;
+      cplx<T>* At = q.A + j0 + (int64_t)(j0 + jb) * q.lda;
+      cplx<T>* Tb = q.Tb + (int64_t)(j0 / QR_NB) * QR_NB * QR_NB;
+      g1.push_back({jb, nt, mr, q.lda, q.lda, QR_NB, V, At, W[i], T(1), T(0), T(0)});
+      g2.push_back({jb, nt, jb, QR_NB, QR_NB, QR_NB, Tb, W[i], W2[i], T(1), T(0), T(0)});
+      g3.push_back({mr, nt, jb, q.lda, QR_NB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
+    }
+    int* dact = (int*)pool.push(act.data(), sizeof(int) * act.size());
+    hipLaunchKernelGGL((qr_panel_kernel<T>), dim3((unsigned)act.size()), dim3(256), 0,
+                       pool.stream, dd, dact, j0);
+    ND_HIP(hipGetLastError());
+    gemm_batched<T>(pool, g1, OpC, OpN);
+    gemm_batched<T>(pool, g2, OpC, OpN);
+    gemm_batched<T>(pool, g3, OpN, OpN);
+  }
+  hipLaunchKernelGGL((qr_wide_tail_kernel<T>), dim3(64, nb), dim3(256), 0, pool.stream, dd);
+  ND_HIP(hipGetLastError());
+}
+
+template <typename T>
+size_t orm_workspace(const std::vector<OrmDesc<T>>& d) {
+  size_t s = 0;
+  for (auto& q : d) s += (size_t)QR_NB * std::max(q.nc, 1) * 2;
+  return s * sizeof(cplx<T>) + 256;
+}
+
+template <typename T>
+void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans, void* ws) {
+  if (d.empty()) return;
+  const int nb = (int)d.size();
+  std::vector<cplx<T>*> W(nb), W2(nb);
+  {
+    cplx<T>* p = (cplx<T>*)ws;
+    for (int i = 0; i < nb; ++i) {
+      W[i] = p;
+      p += (size_t)QR_NB * std::max(d[i].nc, 1);
+      W2[i] = p;
+      p += (size_t)QR_NB * std::max(d[i].nc, 1);
+    }
+  }
+  int nbl = 0;
+  for (auto& q : d) nbl = std::max(nbl, (q.k + QR_NB - 1) / QR_NB);
+  std::vector<GemmDesc<T>> g1, g2, g3;
+  for (int s = 0; s < nbl; ++s) {
+    g1.clear(); g2.clear(); g3.clear();
+    for (int i = 0; i < nb; ++i) {
+      const OrmDesc<T>& q = d[i];
+      int nblk = (q.k + QR_NB - 1) / QR_NB;
+      if (s >= nblk || q.nc <= 0) continue;
+      int blk = trans ? s : nblk - 1 - s;
+      int j0 = blk * QR_NB;
+      int jb = std::min(QR_NB, q.k - j0);
+      int mr = q.m - j0;
+      const cplx<T>* V = q.V + j0 + (int64_t)j0 * q.ldv;
+      const cplx<T>* Tb = q.Tb + (int64_t)blk * QR_NB * QR_NB;
+      cplx<T>* Cp = q.C + j0;
+      g1.push_back({jb, q.nc, mr, q.ldv, q.ldc, QR_NB, V, Cp, W[i], T(1), T(0), T(0)});
+      g2.push_back({jb, q.nc, jb, QR_NB, QR_NB, QR_NB, Tb, W[i], W2[i], T(1), T(0), T(0)});
+      g3.push_back({mr, q.nc, jb, q.ldv, QR_NB, q.ldc, V, W2[i], Cp, T(-1), T(0), T(1)});
+    }
+    gemm_batched<T>(pool, g1, OpC, OpN);
+    gemm_batched<T>(pool, g2, trans ? OpC : OpN, OpN);
+    gemm_batched<T>(pool, g3, OpN, OpN);
+  }
+}
+
+void pchol_batched(DescPool& pool, const std::vector<PcholDesc>& d) {
+  if (d.empty()) return;
+  const int nb = (int)d.size();
+  auto* dd = (PcholDesc*)pool.push(d.data(), sizeof(PcholDesc) * nb);
+  std::vector<int> ones(nb, 1);
+  std::vector<double> zeros(nb, 0.0);
+  double* trace = (double*)pool.push(zeros.data(), sizeof(double) * nb);
+  int* state = (int*)pool.push(ones.data(), sizeof(int) * nb);
+  hipLaunchKernelGGL(pchol_init_kernel, dim3(nb), dim3(256), 0, pool.stream, dd, trace);
+  int rmax = 0;
+  for (auto& q : d) rmax = std::max(rmax, std::min(q.rmax, q.w));
+  std::vector<GemmDesc<double>> g;
+  std::vector<int> hstate(nb);
+  for (int k0 = 0; k0 < rmax; k0 += PC_NB) {
+    hipLaunchKernelGGL(pchol_panel_kernel, dim3(nb), dim3(256), 0, pool.stream, dd, trace,
+                       state, k0);
+    ND_HIP(hipGetLastError());
+    // Schur update with this panel's columns for the problems still running
+    ND_HIP(hipMemcpyAsync(hstate.data(), state, sizeof(int) * nb, hipMemcpyDeviceToHost,
+                          pool.stream));
+    ND_HIP(hipStreamSynchronize(pool.stream));
+    g.clear();
+    bool any = false;
+    for (int i = 0; i < nb; ++i) {
+      if (!hstate[i]) continue;
+      any = true;
+      const PcholDesc& q = d[i];
+      int kb = std::min(PC_NB, std::min(q.rmax, q.w) - k0);
+      if (kb <= 0) continue;
+      const double2* Lp = q.L + (int64_t)k0 * q.ldl;
+      g.push_back({q.w, q.w, kb, q.ldl, q.ldl, q.ldk, Lp, Lp, q.K, -1.0, 0.0, 1.0});
+    }
+    if (!any) break;
+    gemm_batched<double>(pool, g, OpN, OpC);
+  }
+  int kend = rmax;
+  hipLaunchKernelGGL(pchol_finish_kernel, dim3(nb), dim3(64), 0, pool.stream, dd, state, kend);
+  ND_HIP(hipGetLastError());
+}
+
+template <typename T>
+void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
+  if (d.empty()) return;
+  int maxr = 0;
+  for (auto& q : d) maxr = std::max(maxr, q.nrhs);
+  auto* dd = (TrsDesc<T>*)pool.push(d.data(), sizeof(TrsDesc<T>) * d.size());
+  hipLaunchKernelGGL((trsv_upper_kernel<T>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
+                     pool.stream, dd);
+  ND_HIP(hipGetLastError());
+}
+
+template <typename TD, typename TS>
+void copy_batched(DescPool& pool, const std::vector<CopyDesc<TD, TS>>& d) {
+  if (d.empty()) return;
+  auto* dd = (CopyDesc<TD, TS>*)pool.push(d.data(), sizeof(CopyDesc<TD, TS>) * d.size());
+  hipLaunchKernelGGL((copy_kernel<TD, TS>), dim3(64, (unsigned)d.size()), dim3(256), 0,
+                     pool.stream, dd);
+  ND_HIP(hipGetLastError());
+}
+
+template <typename T>
+void fill_batched(DescPool& pool, const std::vector<FillDesc<T>>& d) {
+  if (d.empty()) return;
+  auto* dd = (FillDesc<T>*)pool.push(d.data(), sizeof(FillDesc<T>) * d.size());
+  hipLaunchKernelGGL((fill_kernel<T>), dim3(64, (unsigned)d.size()), dim3(256), 0,
+                     pool.stream, dd);
+  ND_HIP(hipGetLastError());
+}
+
+#define INST(T)                                                                          \
+  template void gemm_batched<T>(DescPool&, const std::vector<GemmDesc<T>>&, Op, Op);     \
+  template size_t qr_workspace<T>(const std::vector<QRDesc<T>>&);                        \
+  template void geqrf_batched<T>(DescPool&, const std::vector<QRDesc<T>>&, void*);       \
+  template size_t orm_workspace<T>(const std::vector<OrmDesc<T>>&);                      \
+  template void ormqr_batched<T>(DescPool&, const std::vector<OrmDesc<T>>&, bool, void*); \
+  template void trsv_upper_batched<T>(DescPool&, const std::vector<TrsDesc<T>>&);        \
+  template void fill_batched<T>(DescPool&, const std::vector<FillDesc<T>>&);
+INST(float)
+INST(double)
+template void copy_batched<float, double>(DescPool&, const std::vector<CopyDesc<float, double>>&);
+template void copy_batched<double, float>(DescPool&, const std::vector<CopyDesc<double, float>>&);
+template void copy_batched<double, double>(DescPool&, const std::vector<CopyDesc<double, double>>&);
+template void copy_batched<float, float>(DescPool&, const std::vector<CopyDesc<float, float>>&);
+
+}  // namespace nd

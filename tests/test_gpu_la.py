@@ -1,0 +1,218 @@
+"""GPU checks of the batched dense building blocks (GEMM, Householder QR,
+Q application, pivoted Cholesky, triangular solve) against NumPy/LAPACK."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+nd = pytest.importorskip("paper_2607_00928_amd")
+from paper_2607_00928_amd import _lib  # noqa: E402
+
+lib = _lib.lib
+DEV = torch.device("cuda", 0)
+CT = {0: (np.complex128, torch.complex128), 1: (np.complex64, torch.complex64)}
+TOL = {0: 1e-12, 1: 2e-5}
+
+
+def crandn(rng, *shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2)
+
+
+def to_dev(Mat, prec, cols=None):
+    """column-major device copy (ld = rows)"""
+    npt, tt = CT[prec]
+    return torch.from_numpy(np.ascontiguousarray(Mat.T.astype(npt))).to(DEV)
+
+
+def from_dev(t, m, n):
+    return t.cpu().numpy().reshape(n, m).T
+
+
+def i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def i64(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_batched_ragged(prec, opa, opb):
+    rng = np.random.default_rng(10 * prec + 2 * opa + opb)
+    shapes = [(1, 1, 1), (70, 33, 19), (64, 64, 64), (130, 5, 200), (3, 150, 17), (65, 129, 0)]
+    mats, keep = [], []
+    mnk, ld, ptr = [], [], []
+    alpha = 0.7 - 0.3j
+    for (m, n, k) in shapes:
+        A = crandn(rng, *((m, k) if opa == 0 else (k, m)))
+        B = crandn(rng, *((k, n) if opb == 0 else (n, k)))
+        Cm = crandn(rng, m, n)
+        ta, tb, tc = to_dev(A, prec), to_dev(B, prec), to_dev(Cm, prec)
+        keep += [ta, tb, tc]
+        mats.append((A, B, Cm, tc))
+        mnk += [m, n, k]
+        ld += [max(A.shape[0], 1), max(B.shape[0], 1), max(m, 1)]
+        ptr += [ta.data_ptr(), tb.data_ptr(), tc.data_ptr()]
+    a1, p1 = i32(mnk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_gemm(prec, opa, opb, len(shapes), p1, p2, p3, alpha.real, alpha.imag, 1.0)
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+        oA = A if opa == 0 else A.conj().T
+        oB = B if opb == 0 else B.conj().T
+        ref = alpha * (oA @ oB) + Cm
+        got = from_dev(tc, m, n)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(got - ref).max() < TOL[prec] * scale * max(1, k) ** 0.5 * 10, (m, n, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_geqrf_ormqr(prec):
+    rng = np.random.default_rng(3 + prec)
+    shapes = [(100, 37), (37, 100), (64, 64), (5, 3), (1030, 546), (33, 1), (300, 97)]
+    keep = []
+    mn, ld, ptr, data = [], [], [], []
+    for (m, n) in shapes:
+        A = crandn(rng, m, n)
+        k = min(m, n)
+        nbk = (k + 31) // 32
+        tA = to_dev(A, prec)
+        tR = torch.zeros((n, k), dtype=CT[prec][1], device=DEV)       # k x n col-major
+        tT = torch.zeros((nbk, 32, 32), dtype=CT[prec][1], device=DEV)
+        keep += [tA, tR, tT]
+        data.append((A, tA, tR, tT))
+        mn += [m, n]
+        ld += [m, k]
+        ptr += [tA.data_ptr(), tR.data_ptr(), tT.data_ptr()]
+    a1, p1 = i32(mn)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_geqrf(prec, len(shapes), p1, p2, p3)
+    assert st == 0, lib.nudft2_last_error()
+    # form Q (m x m) by applying Q to the identity, check Q R = A, Q unitary
+    dims, ld2, ptr2, Qs = [], [], [], []
+    for (m, n), (A, tA, tR, tT) in zip(shapes, data):
+        tQ = to_dev(np.eye(m), prec)
+        keep.append(tQ)
+        Qs.append(tQ)
+        dims += [m, min(m, n), m]
+        ld2 += [m, m]
+        ptr2 += [tA.data_ptr(), tT.data_ptr(), tQ.data_ptr()]
+    b1, q1 = i32(dims)
+    b2, q2 = i32(ld2)
+    b3, q3 = i64(ptr2)
+    st = lib.nudft2_test_ormqr(prec, 0, len(shapes), q1, q2, q3)
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n), (A, tA, tR, tT), tQ in zip(shapes, data, Qs):
+        k = min(m, n)
+        Q = from_dev(tQ, m, m)
+        R = from_dev(tR, k, n)
+        assert np.abs(np.tril(R, -1)).max() == 0
+        err = np.abs(Q[:, :k] @ R - A).max() / np.abs(A).max()
+        orth = np.abs(Q.conj().T @ Q - np.eye(m)).max()
+        print(f"qr {m}x{n} prec{prec}: recon {err:.1e} orth {orth:.1e}")
+        assert err < 50 * TOL[prec] * np.sqrt(m)
+        assert orth < 50 * TOL[prec] * np.sqrt(m)
+        # |R| diagonal equals LAPACK's up to phases
+        Rl = np.linalg.qr(A.astype(np.complex128), mode="r")
+        assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(Rl)), rtol=1e-3 if prec else 1e-9)
+    # Q^H (Q C) = C via the trans path
+    dims3, ld3, ptr3, Cs = [], [], [], []
+    for (m, n), (A, tA, tR, tT) in zip(shapes, data):
+        Cm = crandn(rng, m, 7)
+        tC = to_dev(Cm, prec)
+        keep.append(tC)
+        Cs.append((Cm, tC))
+        dims3 += [m, min(m, n), 7]
+        ld3 += [m, m]
+        ptr3 += [tA.data_ptr(), tT.data_ptr(), tC.data_ptr()]
+    c1, r1 = i32(dims3)
+    c2, r2 = i32(ld3)
+    c3, r3 = i64(ptr3)
+    assert lib.nudft2_test_ormqr(prec, 0, len(shapes), r1, r2, r3) == 0
+    assert lib.nudft2_test_ormqr(prec, 1, len(shapes), r1, r2, r3) == 0
+    for (m, n), (Cm, tC) in zip(shapes, Cs):
+        got = from_dev(tC, m, 7)
+        assert np.abs(got - Cm).max() < 100 * TOL[prec] * np.sqrt(m)
+
+
+def test_pchol_trace_rule():
+    rng = np.random.default_rng(7)
+    sizes = [(40, 40), (300, 120), (473, 473), (17, 5)]
+    keep, data = [], []
+    w, rmax, ptr = [], [], []
+    tol2 = 1e-8
+    for (n, rm) in sizes:
+        # Hermitian PSD with geometrically decaying spectrum
+        Qm, _ = np.linalg.qr(crandn(rng, n, n))
+        lam = 10.0 ** (-12 * np.arange(n) / n)
+        K = (Qm * lam) @ Qm.conj().T
+        K = (K + K.conj().T) / 2
+        tK = to_dev(K, 0)
+        tL = torch.zeros((rm, n), dtype=torch.complex128, device=DEV)
+        keep += [tK, tL]
+        data.append((K, tK, tL, n, rm))
+        w.append(n)
+        rmax.append(rm)
+        ptr += [tK.data_ptr(), tL.data_ptr()]
+    a1, p1 = i32(w)
+    a2, p2 = i32(rmax)
+    a3, p3 = i64(ptr)
+    ranks = np.zeros(len(sizes), np.int32)
+    piv = np.zeros(sum(rmax), np.int32)
+    st = lib.nudft2_test_pchol(len(sizes), p1, p2, p3, tol2,
+                               ranks.ctypes.data_as(C.POINTER(C.c_int32)),
+                               piv.ctypes.data_as(C.POINTER(C.c_int32)))
+    assert st == 0, lib.nudft2_last_error()
+    off = 0
+    for (K, tK, tL, n, rm), r in zip(data, ranks):
+        L = from_dev(tL, n, rm)[:, :r]
+        p = piv[off:off + r]
+        off += rm
+        S = K - L @ L.conj().T
+        tr = np.trace(K).real
+        print(f"pchol n={n}: rank {r}, residual trace {np.trace(S).real / tr:.2e}")
+        assert len(set(p.tolist())) == r
+        if r < rm:
+            assert np.trace(S).real <= tol2 * tr * (1 + 1e-6) + 1e-13 * tr
+            assert np.trace(S).real >= -1e-10 * tr
+        # L restricted to the pivot rows is lower triangular in pivot order
+        Lp = L[p, :]
+        assert np.abs(np.triu(Lp, 1)).max() < 1e-12 * np.abs(Lp).max()
+        # the rank is not far from the trace-optimal rank of the spectrum
+        lam = np.sort(np.linalg.eigvalsh(K))[::-1]
+        tail = np.concatenate([np.cumsum(lam[::-1])[::-1], [0.0]])
+        ropt = int(np.nonzero(tail <= tol2 * tr)[0][0])
+        if r < rm:
+            assert r <= 2 * ropt + 8
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_trsv(prec):
+    rng = np.random.default_rng(11)
+    sizes = [(1, 1), (50, 3), (300, 2), (7, 1)]
+    keep, data, dims, ld, ptr = [], [], [], [], []
+    for (k, nr) in sizes:
+        R = np.triu(crandn(rng, k, k)) + 4 * np.eye(k)
+        B = crandn(rng, k, nr)
+        tR, tB = to_dev(R, prec), to_dev(B, prec)
+        keep += [tR, tB]
+        data.append((R, B, tB, k, nr))
+        dims += [k, nr]
+        ld += [k, k]
+        ptr += [tR.data_ptr(), tB.data_ptr()]
+    a1, p1 = i32(dims)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    assert lib.nudft2_test_trsv(prec, len(sizes), p1, p2, p3) == 0
+    for R, B, tB, k, nr in data:
+        X = from_dev(tB, k, nr)
+        ref = np.linalg.solve(R, B)
+        assert np.abs(X - ref).max() < 100 * TOL[prec] * max(1, np.abs(ref).max())
