@@ -73,6 +73,14 @@ nudft2_status nudft2_test_pchol(int32_t nb, const int32_t* w, const int32_t* rma
 nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims,
                                const int32_t* ld, const int64_t* ptrs);
 
+/* 1D HSS compression of G^x (dim 0) or G^y (dim 1) of a single-problem plan
+ * at tolerance tol (no factorization needed), then y = H x with x: DEVICE n
+ * complex128 in natural column order (0-based frequency l), y: DEVICE M
+ * complex128 in the caller's point order.  ranks (HOST, 2*(L+1) ints, may be
+ * NULL) receives the largest row / column rank per level. */
+nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double tol,
+                                       const double* x, double* y, int32_t* ranks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -367,4 +367,33 @@ nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims, co
   });
 }
 
+nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double tol,
+                                       const double* x, double* y, int32_t* ranks) {
+  return guard([&] {
+    ND_CHECK(plan && x && y && (dim == 0 || dim == 1), NUDFT2_E_INVAL, "bad arguments");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    ND_CHECK(P->probs.size() == 1, NUDFT2_E_INVAL, "single-problem plans only");
+    Ctx cx;
+    cx.P = P;
+    cx.s = P->stream;
+    cx.pool.init(64 << 20, cx.s);
+    std::vector<Tree1> t;
+    build_1d(cx, dim, tol, t);
+    if (ranks) {
+      int L = t[0].L;
+      for (int l = 0; l <= L; ++l) {
+        int ru = 0, rv = 0;
+        for (auto& nd : t[0].lv[l]) {
+          ru = std::max(ru, nd.rU);
+          rv = std::max(rv, nd.rV);
+        }
+        ranks[2 * l] = ru;
+        ranks[2 * l + 1] = rv;
+      }
+    }
+    matvec_1d(cx, dim, t, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+    free_1d(P, t);
+  });
+}
+
 }  // extern "C"

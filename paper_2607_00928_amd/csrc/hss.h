@@ -1,16 +1,143 @@
-// HSS / URV factor storage of a plan.
+// HSS data of a plan: 1D trees (FP64), the 2D face-split HSS matrix and its
+// URV factors (working precision T = float or double).
 #pragma once
 
+#include "la.h"
 #include "plan.h"
 
 namespace nd {
 
+template <typename T>
+struct Mat {
+  cplx<T>* p = nullptr;
+  int r = 0, c = 0, ld = 0;
+  cplx<T>* at(int64_t i, int64_t j) const { return p + i + j * (int64_t)ld; }
+  Mat sub(int i, int j, int rr, int cc) const {
+    Mat m;
+    m.p = at(i, j);
+    m.r = rr;
+    m.c = cc;
+    m.ld = ld;
+    return m;
+  }
+};
+
+// Execution context: stream, descriptor pool and temporaries.
+struct Ctx {
+  Plan* P = nullptr;
+  hipStream_t s = nullptr;
+  DescPool pool;
+  std::vector<void*> tmp;
+  void* tmp_alloc(size_t bytes) {
+    void* p = P->arena.alloc(bytes);
+    tmp.push_back(p);
+    return p;
+  }
+  void release_tmp() {
+    ND_HIP(hipStreamSynchronize(s));
+    for (void* p : tmp) P->arena.release(p);
+    tmp.clear();
+  }
+  ~Ctx() {
+    (void)hipStreamSynchronize(s);
+    for (void* p : tmp) P->arena.release(p);
+  }
+};
+
+// Allocate one chunk for a list of matrices (each with ld = max(rows, 1)).
+template <typename T>
+void* carve(Arena& A, std::vector<Mat<T>*>& ms, std::vector<void*>* track = nullptr) {
+  size_t tot = 0;
+  for (Mat<T>* m : ms) {
+    if (m->ld < m->r) m->ld = m->r;
+    if (m->ld < 1) m->ld = 1;
+    tot += ((size_t)m->ld * std::max(m->c, 1) + 31) & ~size_t(31);
+  }
+  if (tot == 0) return nullptr;
+  cplx<T>* base = (cplx<T>*)A.alloc(tot * sizeof(cplx<T>));
+  if (track) track->push_back(base);
+  size_t off = 0;
+  for (Mat<T>* m : ms) {
+    m->p = base + off;
+    off += ((size_t)m->ld * std::max(m->c, 1) + 31) & ~size_t(31);
+  }
+  return base;
+}
+
+// ------------------------------------------------------------------ 1D trees
+struct Node1 {
+  int64_t row0 = 0, m = 0;   // rows in the axis-sorted order (global)
+  int col0 = 0, d = 0;       // columns [col0, col0 + d)
+  int rU = 0, rV = 0;
+  Mat<double> U;             // leaf: m x rU
+  Mat<double> Vf;            // d x rV (explicit nested basis)
+  Mat<double> R, W;          // level >= 2: to the parent
+  Mat<double> B;             // level >= 1: B_{a, sib(a)}  (rU x rV_sib)
+  Mat<double> BV;            // level >= 1: B_{a, sib(a)} Vf_sib^H  (rU x d_sib)
+};
+
+struct Tree1 {
+  int n = 0, L = 0;
+  int64_t M = 0, m0 = 0;
+  std::vector<std::vector<Node1>> lv;
+  std::vector<void*> mem;    // chunks owned by this tree
+};
+
+// ------------------------------------------------------------------ 2D HSS
+template <typename T>
+struct Node2 {
+  int l = 0, z = 0, a = 0, b = 0;
+  int64_t row0 = 0, m = 0;   // rows in the 2D-sorted order (global)
+  int col0 = 0, n = 0;       // quadtree column range within the problem
+  int dx = 0, dy = 0;
+  int wU = 0, wV = 0;        // current widths of the row / column bases
+  Mat<T> U, V;               // leaves
+  Mat<T> R, W;               // l >= 2
+  Mat<T> B[3];               // l >= 1: with the siblings in child order
+  Mat<T> F, G;               // stage-1 factors
+  Mat<double> TU, TV;        // stage-2 weights (r x r)
+  // URV
+  int mm = 0, nn = 0;        // rows / unknowns of the (merged) node
+  int mchk = 0, k = 0;
+  bool sizered = false;
+  Mat<T> UD;                 // [U D] -> reflectors of Omega (mm x (wU + nn))
+  Mat<T> Tom;                // T blocks of Omega
+  Mat<T> Vq, Tq;             // reflectors / T of QR(V) (nn x wV)
+  Mat<T> Pr, Tp;             // reflectors / T of QR(D~(:, 0:k))
+  Mat<T> D11, D12, U1;       // k x k, k x wV, k x wU
+  Mat<T> D22, U2, V2;        // (mchk-k) x wV, (mchk-k) x wU, wV x wV (or nn x wV)
+};
+
+template <typename T>
+struct Prob2 {
+  int L = 0;
+  std::vector<std::vector<Node2<T>>> lv;   // lv[l][z]
+  // root
+  Mat<T> rootA, rootR, rootT;
+  int root_m = 0, root_n = 0;
+  Mat<double> Fx, Fy;        // inverse DFT matrices (nx x nx, ny x ny), FP64
+};
+
 struct HSSFactors {
+  int precision = 0;
   virtual ~HSSFactors() = default;
+};
+using HSSBase = HSSFactors;
+
+template <typename T>
+struct HSS2 : HSSBase {
+  std::vector<Prob2<T>> probs;
+  std::vector<void*> mem;
 };
 
 int tree_depth(int nx, int ny, int leaf);
 void host_binning(const double* points, int64_t M, int nx, int ny, int leaf,
                   int64_t* perm2d, int64_t* leaf_rows, int64_t* colperm);
+
+// 1D compression of G^x (dim 0) or G^y (dim 1) for every problem.
+void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out);
+void free_1d(Plan* P, std::vector<Tree1>& t);
+// y = H x for a 1D HSS (test hook): x (n, natural columns), y (M, caller order).
+void matvec_1d(Ctx& cx, int dim, const std::vector<Tree1>& t, const double2* x, double2* y);
 
 }  // namespace nd
