@@ -81,6 +81,16 @@ nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims,
 nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double tol,
                                        const double* x, double* y, int32_t* ranks);
 
+/* Build the recompressed HSS approximation of G (1D stage at eps/10,
+ * face-splitting assembly, recompression at eps) of a single-problem plan in
+ * the plan's precision, then y = H x (x: DEVICE N complex128 in natural
+ * column order l^y + l^x ny, 0-based; y: DEVICE M complex128, caller's point
+ * order).  stages: 0 = face-splitting generators only, 1 = after the exact
+ * orthogonalisation stage, 2 = fully recompressed.  The ranks per level are
+ * left in the plan's info. */
+nudft2_status nudft2_test_hss_matvec(nudft2_plan_t plan, const double* x, double* y,
+                                     int32_t stages);
+
 #ifdef __cplusplus
 }
 #endif

@@ -396,4 +396,36 @@ nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double t
   });
 }
 
+nudft2_status nudft2_test_hss_matvec(nudft2_plan_t plan, const double* x, double* y,
+                                     int32_t stages) {
+  return guard([&] {
+    ND_CHECK(plan && x && y, NUDFT2_E_INVAL, "bad arguments");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    ND_CHECK(P->probs.size() == 1, NUDFT2_E_INVAL, "single-problem plans only");
+    Ctx cx;
+    cx.P = P;
+    cx.s = P->stream;
+    cx.pool.init(256 << 20, cx.s);
+    std::vector<Tree1> tx, ty;
+    build_1d(cx, 0, P->opts.eps / 10, tx);
+    build_1d(cx, 1, P->opts.eps / 10, ty);
+    auto run = [&](auto& H) {
+      build_2d(cx, tx, ty, P->opts.eps, H, stages);
+      free_1d(P, tx);
+      free_1d(P, ty);
+      matvec_2d(cx, H, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+      ND_HIP(hipStreamSynchronize(cx.s));
+      for (void* m : H.mem) P->arena.release(m);
+      H.mem.clear();
+    };
+    if (P->opts.precision == 0) {
+      HSS2<double> H;
+      run(H);
+    } else {
+      HSS2<float> H;
+      run(H);
+    }
+  });
+}
+
 }  // extern "C"

@@ -130,6 +130,22 @@ struct HSS2 : HSSBase {
   std::vector<void*> mem;
 };
 
+// Orthonormal basis Q (m x min(m,c)) of the columns of each A (destroyed);
+// optionally the triangular factors into Rout (caller-allocated, k x c).
+template <typename T>
+void orth(Ctx& cx, std::vector<Mat<T>>& A, std::vector<Mat<T>>& Q,
+          std::vector<Mat<T>>* Rout = nullptr);
+
+struct PcholOut {
+  Mat<double> L;
+  int* piv = nullptr;
+  int rank = 0;
+};
+// Diagonally pivoted Cholesky with the trace rule on FP64 Grams (destroyed);
+// ranks are returned on the host (synchronises).
+void pchol_run(Ctx& cx, std::vector<Mat<double>>& K, std::vector<int>& rmax, double tol2,
+               std::vector<PcholOut>& out);
+
 int tree_depth(int nx, int ny, int leaf);
 void host_binning(const double* points, int64_t M, int nx, int ny, int leaf,
                   int64_t* perm2d, int64_t* leaf_rows, int64_t* colperm);
@@ -139,5 +155,14 @@ void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out);
 void free_1d(Plan* P, std::vector<Tree1>& t);
 // y = H x for a 1D HSS (test hook): x (n, natural columns), y (M, caller order).
 void matvec_1d(Ctx& cx, int dim, const std::vector<Tree1>& t, const double2* x, double2* y);
+
+// Face-splitting assembly (Theorem 3.3) + recompression (Section 2.3).
+template <typename T>
+void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& ty, double eps,
+              HSS2<T>& H, int stages = 2);
+// y = H x for problem 0 of a recompressed HSS (test hook); x natural column
+// order, y caller's point order (FP64 in and out).
+template <typename T>
+void matvec_2d(Ctx& cx, HSS2<T>& H, const double2* x, double2* y);
 
 }  // namespace nd

@@ -30,82 +30,6 @@ namespace {
 
 constexpr int RMAX1D = 128;
 
-// Orthonormal basis of the columns of A (destroyed): Q (m x k), k = min(m, c).
-void orth64(Ctx& cx, std::vector<Mat<double>>& A, std::vector<Mat<double>>& Q) {
-  if (A.empty()) return;
-  std::vector<QRDesc<double>> qd;
-  std::vector<Mat<double>> Rb(A.size()), Tb(A.size());
-  std::vector<Mat<double>*> ms;
-  for (size_t i = 0; i < A.size(); ++i) {
-    int k = std::min(A[i].r, A[i].c);
-    Rb[i].r = std::max(k, 1);
-    Rb[i].c = std::max(A[i].c, 1);
-    Tb[i].r = QR_NB * QR_NB;
-    Tb[i].c = std::max(qr_nblocks(A[i].r, A[i].c), 1);
-    ms.push_back(&Rb[i]);
-    ms.push_back(&Tb[i]);
-  }
-  carve(cx.P->arena, ms, &cx.tmp);
-  for (size_t i = 0; i < A.size(); ++i)
-    qd.push_back({A[i].r, A[i].c, A[i].ld, Rb[i].ld, A[i].p, Rb[i].p, Tb[i].p});
-  void* ws = cx.tmp_alloc(qr_workspace<double>(qd));
-  geqrf_batched<double>(cx.pool, qd, ws);
-  std::vector<FillDesc<double>> fd;
-  std::vector<OrmDesc<double>> od;
-  for (size_t i = 0; i < A.size(); ++i) {
-    int k = std::min(A[i].r, A[i].c);
-    fd.push_back({Q[i].r, Q[i].c, Q[i].ld, Q[i].p, 1});
-    od.push_back({A[i].r, k, Q[i].c, A[i].ld, Q[i].ld, A[i].p, Tb[i].p, Q[i].p});
-  }
-  fill_batched<double>(cx.pool, fd);
-  void* ws2 = cx.tmp_alloc(orm_workspace<double>(od));
-  ormqr_batched<double>(cx.pool, od, false, ws2);
-}
-
-struct PcholOut {
-  Mat<double> L;
-  int* piv = nullptr;
-  int rank = 0;
-};
-
-// Pivoted Cholesky of a batch of FP64 Grams (w x w, ld w); returns ranks on
-// the host.  K is destroyed.
-void pchol_run(Ctx& cx, std::vector<Mat<double>>& K, std::vector<int>& rmax, double tol2,
-               std::vector<PcholOut>& out) {
-  size_t nb = K.size();
-  out.assign(nb, PcholOut());
-  if (nb == 0) return;
-  std::vector<Mat<double>*> ms;
-  for (size_t i = 0; i < nb; ++i) {
-    out[i].L.r = K[i].r;
-    out[i].L.c = std::max(rmax[i], 1);
-    ms.push_back(&out[i].L);
-  }
-  carve(cx.P->arena, ms, &cx.tmp);
-  int tot = 0, totw = 0;
-  for (size_t i = 0; i < nb; ++i) {
-    tot += std::max(rmax[i], 1);
-    totw += std::max(K[i].r, 1);
-  }
-  int* piv = (int*)cx.tmp_alloc(sizeof(int) * tot);
-  int* rank = (int*)cx.tmp_alloc(sizeof(int) * nb);
-  double* dw = (double*)cx.tmp_alloc(sizeof(double) * totw);
-  std::vector<PcholDesc> pd;
-  int po = 0, wo = 0;
-  for (size_t i = 0; i < nb; ++i) {
-    out[i].piv = piv + po;
-    pd.push_back({K[i].r, K[i].ld, out[i].L.ld, rmax[i], (double2*)K[i].p, (double2*)out[i].L.p,
-                  dw + wo, piv + po, rank + i, tol2});
-    po += std::max(rmax[i], 1);
-    wo += std::max(K[i].r, 1);
-  }
-  pchol_batched(cx.pool, pd);
-  std::vector<int> h(nb);
-  ND_HIP(hipMemcpyAsync(h.data(), rank, sizeof(int) * nb, hipMemcpyDeviceToHost, cx.s));
-  ND_HIP(hipStreamSynchronize(cx.s));
-  for (size_t i = 0; i < nb; ++i) out[i].rank = h[i];
-}
-
 }  // namespace
 
 void free_1d(Plan* P, std::vector<Tree1>& t) {
@@ -392,7 +316,7 @@ void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out) {
           c2.W = Ys[i].sub(c1.rV, 0, c2.rV, nd.rV);
         }
       }
-      orth64(cx, Ain, Qout);
+      orth<double>(cx, Ain, Qout);
       if (!leaf) {
         // V_f(t) = [V_f(c1) W_c1; V_f(c2) W_c2]
         std::vector<GemmDesc<double>> gv;

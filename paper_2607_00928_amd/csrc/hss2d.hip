@@ -1,0 +1,903 @@
+// Face-splitting HSS assembly (Theorem 3.3) and recompression (Section 2.3).
+//
+// Assembly: from the two 1D HSS matrices of G^x and G^y, every quadtree node
+// xi = (alpha, beta) gets the generators of H = H^x . H^y on the product tree:
+// explicit leaf bases U_xi, V_xi, and Kronecker-structured transfer (R, W) and
+// sibling interaction (B) matrices for all four children of a node (the
+// paper writes the first child out; the other three follow by selecting the
+// child's own / sibling column groups, see gen.hip).
+//
+// Recompression, stage 1 (bottom-up, exact): thin QR of the leaf bases,
+// B <- F B G^H between siblings, thin QR of the stacked [F_c R_c] and
+// [G_c W_c] at every non-root node.  Stage 2 (top-down, truncation at eps):
+// for every node alpha the row block C^U = [B_{alpha,beta} | R_alpha S_parent]
+// and column block C^V = [B_{beta,alpha}^H | W_alpha S_parent] are compressed.
+// Where the paper takes a truncated SVD, the rank decision here is a
+// diagonally pivoted Cholesky factorization K ~ L L^H of the FP64 Gram
+// K = C C^H with the trace rule (relative Frobenius error eps); the new basis
+// is P = orth(L) and the weight passed to the children is the triangular
+// factor T of L = P T (T T^H = P^H K P up to the discarded part, the role of
+// S^2 in the paper).  The updates B <- P^H B Q, R <- P^H R, W <- Q^H W,
+// U <- U P, V <- V Q and R_child <- R_child P, W_child <- W_child Q follow the
+// paper.
+#include <algorithm>
+#include <map>
+#include <tuple>
+
+#include "gen.h"
+#include "hss.h"
+
+namespace nd {
+
+namespace {
+
+template <typename T>
+struct Builder {
+  Ctx& cx;
+  HSS2<T>& H;
+  Plan* P;
+  std::map<std::tuple<int, int, int>, void*> chunk;   // (problem, level, kind)
+  enum { K_U, K_V, K_R, K_W, K_B, K_F, K_G, K_TU, K_TV };
+
+  Builder(Ctx& c, HSS2<T>& h) : cx(c), H(h), P(c.P) {}
+
+  void own(int p, int l, int kind, void* ptr, std::vector<void*>& old) {
+    auto key = std::make_tuple(p, l, kind);
+    auto it = chunk.find(key);
+    if (it != chunk.end() && it->second) old.push_back(it->second);
+    chunk[key] = ptr;
+  }
+  void release(std::vector<void*>& old) {
+    ND_HIP(hipStreamSynchronize(cx.s));
+    for (void* p : old) P->arena.release(p);
+    old.clear();
+  }
+  Node2<T>& node(int p, int l, int z) { return H.probs[p].lv[l][z]; }
+
+  // nodes of every problem at level l (absolute level)
+  template <typename F>
+  void each_level(int l, F&& f) {
+    for (int p = 0; p < (int)H.probs.size(); ++p) {
+      if (l > H.probs[p].L) continue;
+      for (int z = 0; z < (1 << (2 * l)); ++z) f(p, z);
+    }
+  }
+  static int sib_child(int c, int s) { return s < c ? s : s + 1; }
+  static int sib_slot(int c, int other) { return other < c ? other : other - 1; }
+};
+
+}  // namespace
+
+template <typename T>
+void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& ty, double eps,
+              HSS2<T>& H, int stages) {
+  Plan* P = cx.P;
+  Builder<T> bd(cx, H);
+  const int np = (int)P->probs.size();
+  H.probs.assign(np, Prob2<T>());
+  int Lmax = 0;
+  for (int p = 0; p < np; ++p) {
+    const Problem& q = P->probs[p];
+    Prob2<T>& pb = H.probs[p];
+    pb.L = q.L;
+    Lmax = std::max(Lmax, q.L);
+    pb.lv.assign(q.L + 1, {});
+    for (int l = 0; l <= q.L; ++l) {
+      int nn = 1 << (2 * l);
+      pb.lv[l].resize(nn);
+      for (int z = 0; z < nn; ++z) {
+        Node2<T>& nd = pb.lv[l][z];
+        uint32_t a, b;
+        deinterleave(z, l, a, b);
+        nd.l = l;
+        nd.z = z;
+        nd.a = a;
+        nd.b = b;
+        nd.row0 = q.row2[l][z];
+        nd.m = q.row2[l][z + 1] - q.row2[l][z];
+        nd.col0 = q.col2[l][z];
+        nd.n = q.col2[l][z + 1] - q.col2[l][z];
+        nd.dx = q.colx[l][a + 1] - q.colx[l][a];
+        nd.dy = q.coly[l][b + 1] - q.coly[l][b];
+        if (l >= 1) {
+          const Node1& ax = tx[p].lv[l][a];
+          const Node1& by = ty[p].lv[l][b];
+          nd.wU = nd.dx * by.rU + ax.rU * nd.dy + ax.rU * by.rU;
+          nd.wV = nd.dx * by.rV + ax.rV * nd.dy + ax.rV * by.rV;
+        }
+      }
+    }
+  }
+  if (Lmax == 0) return;
+  std::vector<void*> old;
+
+  // ------------------------------------------------ face-split assembly
+  {
+    // leaves
+    std::vector<LeafDesc<T>> ud;
+    std::vector<LeafVDesc<T>> vd;
+    for (int p = 0; p < np; ++p) {
+      Prob2<T>& pb = H.probs[p];
+      if (pb.L == 0) continue;
+      std::vector<Mat<T>*> mu, mv;
+      for (auto& nd : pb.lv[pb.L]) {
+        nd.U.r = (int)nd.m;
+        nd.U.c = nd.wU;
+        nd.V.r = nd.dx * nd.dy;
+        nd.V.c = nd.wV;
+        mu.push_back(&nd.U);
+        mv.push_back(&nd.V);
+      }
+      bd.own(p, pb.L, Builder<T>::K_U, carve(P->arena, mu), old);
+      bd.own(p, pb.L, Builder<T>::K_V, carve(P->arena, mv), old);
+      const Problem& q = P->probs[p];
+      for (auto& nd : pb.lv[pb.L]) {
+        const Node1& ax = tx[p].lv[pb.L][nd.a];
+        const Node1& by = ty[p].lv[pb.L][nd.b];
+        LeafDesc<T> d{};
+        d.row0 = nd.row0;
+        d.m = (int)nd.m;
+        d.nx = q.nx;
+        d.ny = q.ny;
+        d.colx0 = ax.col0;
+        d.dx = nd.dx;
+        d.coly0 = by.col0;
+        d.dy = nd.dy;
+        d.Ux = ax.U.p;
+        d.ldux = ax.U.ld;
+        d.rowx0 = ax.row0;
+        d.rx = ax.rU;
+        d.Uy = by.U.p;
+        d.lduy = by.U.ld;
+        d.rowy0 = by.row0;
+        d.ry = by.rU;
+        d.out = nd.U.p;
+        d.ld = nd.U.ld;
+        d.coff = 0;
+        if (nd.m > 0 && nd.wU > 0) ud.push_back(d);
+        LeafVDesc<T> v{nd.dx, nd.dy, ax.Vf.p, ax.Vf.ld, ax.rV, by.Vf.p, by.Vf.ld, by.rV, nd.V.p,
+                       nd.V.ld};
+        if (nd.wV > 0) vd.push_back(v);
+      }
+    }
+    gen_leafU<T>(cx.pool, ud, P->pts_2d, P->posx, P->posy);
+    gen_leafV<T>(cx.pool, vd);
+    // transfer and interaction matrices
+    std::vector<AsmDesc<T>> ad;
+    for (int p = 0; p < np; ++p) {
+      Prob2<T>& pb = H.probs[p];
+      const Problem& q = P->probs[p];
+      for (int l = 1; l <= pb.L; ++l) {
+        std::vector<Mat<T>*> mr, mw, mb;
+        for (auto& nd : pb.lv[l]) {
+          if (l >= 2) {
+            const Node2<T>& par = pb.lv[l - 1][nd.z >> 2];
+            nd.R.r = nd.wU;
+            nd.R.c = par.wU;
+            nd.W.r = nd.wV;
+            nd.W.c = par.wV;
+            mr.push_back(&nd.R);
+            mw.push_back(&nd.W);
+          }
+          int c = nd.z & 3;
+          for (int s = 0; s < 3; ++s) {
+            const Node2<T>& sb = pb.lv[l][(nd.z & ~3) | Builder<T>::sib_child(c, s)];
+            nd.B[s].r = nd.wU;
+            nd.B[s].c = sb.wV;
+            mb.push_back(&nd.B[s]);
+          }
+        }
+        if (l >= 2) {
+          bd.own(p, l, Builder<T>::K_R, carve(P->arena, mr), old);
+          bd.own(p, l, Builder<T>::K_W, carve(P->arena, mw), old);
+        }
+        bd.own(p, l, Builder<T>::K_B, carve(P->arena, mb), old);
+        for (auto& nd : pb.lv[l]) {
+          const Node1& ax = tx[p].lv[l][nd.a];
+          const Node1& by = ty[p].lv[l][nd.b];
+          if (l >= 2) {
+            const Node2<T>& par = pb.lv[l - 1][nd.z >> 2];
+            const Node1& tx_ = tx[p].lv[l - 1][nd.a >> 1];
+            const Node1& sy_ = ty[p].lv[l - 1][nd.b >> 1];
+            const Node1& axs = tx[p].lv[l][nd.a ^ 1];
+            const Node1& bys = ty[p].lv[l][nd.b ^ 1];
+            AsmDesc<T> r{};
+            r.kind = 0;
+            r.rows = nd.wU;
+            r.cols = par.wU;
+            r.ld = nd.R.ld;
+            r.out = nd.R.p;
+            r.dx = nd.dx; r.dy = nd.dy; r.rx = ax.rU; r.ry = by.rU;
+            r.cdx = par.dx; r.cdy = par.dy; r.crx = tx_.rU; r.cry = sy_.rU;
+            r.own_x = ax.col0 - tx_.col0;
+            r.own_y = by.col0 - sy_.col0;
+            r.sib_x = axs.col0 - tx_.col0;
+            r.sib_y = bys.col0 - sy_.col0;
+            r.dsx = axs.d;
+            r.dsy = bys.d;
+            r.X = ax.R.p; r.ldX = ax.R.ld;
+            r.Y = by.R.p; r.ldY = by.R.ld;
+            r.BX = ax.BV.p; r.ldBX = ax.BV.ld;
+            r.BY = by.BV.p; r.ldBY = by.BV.ld;
+            ad.push_back(r);
+            AsmDesc<T> w = r;
+            w.kind = 1;
+            w.rows = nd.wV;
+            w.cols = par.wV;
+            w.ld = nd.W.ld;
+            w.out = nd.W.p;
+            w.rx = ax.rV; w.ry = by.rV; w.crx = tx_.rV; w.cry = sy_.rV;
+            w.X = ax.W.p; w.ldX = ax.W.ld;
+            w.Y = by.W.p; w.ldY = by.W.ld;
+            ad.push_back(w);
+          }
+          int c = nd.z & 3;
+          for (int s = 0; s < 3; ++s) {
+            const Node2<T>& sb = pb.lv[l][(nd.z & ~3) | Builder<T>::sib_child(c, s)];
+            const Node1& axs = tx[p].lv[l][sb.a];
+            const Node1& bys = ty[p].lv[l][sb.b];
+            AsmDesc<T> b{};
+            b.kind = 2;
+            b.rows = nd.wU;
+            b.cols = sb.wV;
+            b.ld = nd.B[s].ld;
+            b.out = nd.B[s].p;
+            b.dx = nd.dx; b.dy = nd.dy; b.rx = ax.rU; b.ry = by.rU;
+            b.cdx = sb.dx; b.cdy = sb.dy; b.crx = axs.rV; b.cry = bys.rV;
+            if (sb.a == nd.a) {
+              b.bcase = 0;
+              b.Y = by.B.p; b.ldY = by.B.ld;
+            } else if (sb.b == nd.b) {
+              b.bcase = 1;
+              b.X = ax.B.p; b.ldX = ax.B.ld;
+            } else {
+              b.bcase = 2;
+              b.X = ax.B.p; b.ldX = ax.B.ld;
+              b.Y = by.B.p; b.ldY = by.B.ld;
+            }
+            ad.push_back(b);
+          }
+        }
+        (void)q;
+      }
+    }
+    gen_asm<T>(cx.pool, ad);
+    ND_HIP(hipStreamSynchronize(cx.s));
+    cx.pool.sync_reset();
+  }
+
+  // ------------------------------------------------ stage 1 (bottom-up)
+  if (stages >= 1) {
+    // leaves: U = U~ F, V = V~ G
+    std::vector<Mat<T>> A, Q, R;
+    std::vector<std::tuple<int, int, int>> who;   // (p, z, 0=U / 1=V)
+    for (int p = 0; p < np; ++p) {
+      Prob2<T>& pb = H.probs[p];
+      if (pb.L == 0) continue;
+      std::vector<Mat<T>*> mq, mf;
+      std::vector<Mat<T>> nu(pb.lv[pb.L].size()), nv(pb.lv[pb.L].size());
+      for (auto& nd : pb.lv[pb.L]) {
+        int ku = std::min((int)nd.m, nd.wU), kv = std::min(nd.dx * nd.dy, nd.wV);
+        nu[nd.z].r = (int)nd.m;
+        nu[nd.z].c = ku;
+        nv[nd.z].r = nd.dx * nd.dy;
+        nv[nd.z].c = kv;
+        nd.F.r = ku;
+        nd.F.c = nd.wU;
+        nd.G.r = kv;
+        nd.G.c = nd.wV;
+        mq.push_back(&nu[nd.z]);
+        mq.push_back(&nv[nd.z]);
+        mf.push_back(&nd.F);
+        mf.push_back(&nd.G);
+      }
+      void* cq = carve(P->arena, mq);
+      bd.own(p, pb.L, Builder<T>::K_F, carve(P->arena, mf), old);
+      for (auto& nd : pb.lv[pb.L]) {
+        if (nd.m > 0 && nd.wU > 0) {
+          A.push_back(nd.U);
+          Q.push_back(nu[nd.z]);
+          R.push_back(nd.F);
+        }
+        if (nd.wV > 0) {
+          A.push_back(nd.V);
+          Q.push_back(nv[nd.z]);
+          R.push_back(nd.G);
+        }
+      }
+      orth<T>(cx, A, Q, &R);
+      A.clear(); Q.clear(); R.clear();
+      ND_HIP(hipStreamSynchronize(cx.s));
+      cx.release_tmp();
+      cx.pool.sync_reset();
+      for (auto& nd : pb.lv[pb.L]) {
+        nd.U = nu[nd.z];
+        nd.V = nv[nd.z];
+      }
+      bd.own(p, pb.L, Builder<T>::K_U, cq, old);
+      bd.own(p, pb.L, Builder<T>::K_V, nullptr, old);
+      bd.release(old);
+    }
+    // non-leaf nodes, from the leaves' parents to the root
+    for (int h = 1; h <= Lmax; ++h) {
+      for (int p = 0; p < np; ++p) {
+        Prob2<T>& pb = H.probs[p];
+        int l = pb.L - h;
+        if (l < 0) continue;
+        int lc = l + 1;
+        // B~_{ci,cj} = F_ci B_{ci,cj} G_cj^H for the children (level lc)
+        std::vector<Mat<T>*> mb, mx;
+        std::vector<Mat<T>> X(pb.lv[lc].size() * 3), NB(pb.lv[lc].size() * 3);
+        for (auto& nd : pb.lv[lc]) {
+          int c = nd.z & 3;
+          for (int s = 0; s < 3; ++s) {
+            const Node2<T>& sb = pb.lv[lc][(nd.z & ~3) | Builder<T>::sib_child(c, s)];
+            X[nd.z * 3 + s].r = nd.B[s].r;
+            X[nd.z * 3 + s].c = sb.G.r;
+            NB[nd.z * 3 + s].r = nd.F.r;
+            NB[nd.z * 3 + s].c = sb.G.r;
+            mx.push_back(&X[nd.z * 3 + s]);
+            mb.push_back(&NB[nd.z * 3 + s]);
+          }
+        }
+        carve(P->arena, mx, &cx.tmp);
+        void* cb = carve(P->arena, mb);
+        std::vector<GemmDesc<T>> g1, g2;
+        for (auto& nd : pb.lv[lc]) {
+          int c = nd.z & 3;
+          for (int s = 0; s < 3; ++s) {
+            const Node2<T>& sb = pb.lv[lc][(nd.z & ~3) | Builder<T>::sib_child(c, s)];
+            Mat<T>& x = X[nd.z * 3 + s];
+            Mat<T>& nb = NB[nd.z * 3 + s];
+            g1.push_back({x.r, x.c, sb.G.c, nd.B[s].ld, sb.G.ld, x.ld, nd.B[s].p, sb.G.p, x.p,
+                          T(1), T(0), T(0)});
+            g2.push_back({nb.r, nb.c, nd.F.c, nd.F.ld, x.ld, nb.ld, nd.F.p, x.p, nb.p, T(1), T(0),
+                          T(0)});
+          }
+        }
+        gemm_batched<T>(cx.pool, g1, OpN, OpC);
+        gemm_batched<T>(cx.pool, g2, OpN, OpN);
+        std::vector<Mat<T>> SR, SW, QR_, QW_, FR, FW;
+        std::vector<Mat<T>*> ms, mnew, mf;
+        std::vector<Mat<T>> sr(pb.lv[l].size()), sw(pb.lv[l].size()), qr(pb.lv[l].size()),
+            qw(pb.lv[l].size());
+        if (l >= 1) {
+          // stacked [F_c R_c] and [G_c W_c] of every node at level l
+          for (auto& nd : pb.lv[l]) {
+            int rows_u = 0, rows_v = 0;
+            for (int c = 0; c < 4; ++c) {
+              rows_u += pb.lv[lc][4 * nd.z + c].F.r;
+              rows_v += pb.lv[lc][4 * nd.z + c].G.r;
+            }
+            sr[nd.z].r = rows_u;
+            sr[nd.z].c = nd.wU;
+            sw[nd.z].r = rows_v;
+            sw[nd.z].c = nd.wV;
+            ms.push_back(&sr[nd.z]);
+            ms.push_back(&sw[nd.z]);
+            int ku = std::min(rows_u, nd.wU), kv = std::min(rows_v, nd.wV);
+            qr[nd.z].r = rows_u;
+            qr[nd.z].c = ku;
+            qw[nd.z].r = rows_v;
+            qw[nd.z].c = kv;
+            mnew.push_back(&qr[nd.z]);
+            mnew.push_back(&qw[nd.z]);
+            nd.F.r = ku;
+            nd.F.c = nd.wU;
+            nd.G.r = kv;
+            nd.G.c = nd.wV;
+            mf.push_back(&nd.F);
+            mf.push_back(&nd.G);
+          }
+          carve(P->arena, ms, &cx.tmp);
+          std::vector<GemmDesc<T>> gs;
+          for (auto& nd : pb.lv[l]) {
+            int ou = 0, ov = 0;
+            for (int c = 0; c < 4; ++c) {
+              Node2<T>& ch = pb.lv[lc][4 * nd.z + c];
+              gs.push_back({ch.F.r, nd.wU, ch.F.c, ch.F.ld, ch.R.ld, sr[nd.z].ld, ch.F.p, ch.R.p,
+                            sr[nd.z].at(ou, 0), T(1), T(0), T(0)});
+              gs.push_back({ch.G.r, nd.wV, ch.G.c, ch.G.ld, ch.W.ld, sw[nd.z].ld, ch.G.p, ch.W.p,
+                            sw[nd.z].at(ov, 0), T(1), T(0), T(0)});
+              ou += ch.F.r;
+              ov += ch.G.r;
+            }
+          }
+          gemm_batched<T>(cx.pool, gs, OpN, OpN);
+          void* cq = carve(P->arena, mnew);
+          void* cf = carve(P->arena, mf);
+          std::vector<Mat<T>> A, Q, R;
+          for (auto& nd : pb.lv[l]) {
+            if (sr[nd.z].r > 0 && nd.wU > 0) {
+              A.push_back(sr[nd.z]);
+              Q.push_back(qr[nd.z]);
+              R.push_back(nd.F);
+            }
+            if (sw[nd.z].r > 0 && nd.wV > 0) {
+              A.push_back(sw[nd.z]);
+              Q.push_back(qw[nd.z]);
+              R.push_back(nd.G);
+            }
+          }
+          orth<T>(cx, A, Q, &R);
+          bd.own(p, l, Builder<T>::K_F, cf, old);
+          bd.own(p, lc, Builder<T>::K_R, cq, old);
+          bd.own(p, lc, Builder<T>::K_W, nullptr, old);
+        }
+        // children: new B, widths, transfer views
+        for (auto& nd : pb.lv[lc]) {
+          for (int s = 0; s < 3; ++s) nd.B[s] = NB[nd.z * 3 + s];
+        }
+        if (l >= 1) {
+          for (auto& nd : pb.lv[l]) {
+            int ou = 0, ov = 0;
+            for (int c = 0; c < 4; ++c) {
+              Node2<T>& ch = pb.lv[lc][4 * nd.z + c];
+              ch.R = qr[nd.z].sub(ou, 0, ch.F.r, qr[nd.z].c);
+              ch.W = qw[nd.z].sub(ov, 0, ch.G.r, qw[nd.z].c);
+              ou += ch.F.r;
+              ov += ch.G.r;
+            }
+          }
+        }
+        for (auto& nd : pb.lv[lc]) {
+          nd.wU = nd.F.r;
+          nd.wV = nd.G.r;
+        }
+        bd.own(p, lc, Builder<T>::K_B, cb, old);
+        bd.own(p, lc, Builder<T>::K_F, nullptr, old);   // children's F/G no longer needed
+        cx.release_tmp();
+        cx.pool.sync_reset();
+        bd.release(old);
+      }
+    }
+    for (int p = 0; p < np; ++p) {
+      Prob2<T>& pb = H.probs[p];
+      if (pb.L >= 1) {
+        for (auto& nd : pb.lv[0]) {
+          nd.wU = nd.F.r;
+          nd.wV = nd.G.r;
+        }
+      }
+    }
+  }
+
+  // ------------------------------------------------ stage 2 (top-down)
+  if (stages >= 2) {
+    const double tol2 = eps * eps;
+    for (int l = 1; l <= Lmax; ++l) {
+      struct Ref { int p, z; };
+      std::vector<Ref> nodes;
+      bd.each_level(l, [&](int p, int z) { nodes.push_back({p, z}); });
+      if (nodes.empty()) continue;
+      // FP64 copies of the blocks that enter the Grams
+      auto to64 = [&](const Mat<T>& m) -> Mat<double> {
+        Mat<double> o;
+        o.r = m.r;
+        o.c = m.c;
+        if (std::is_same<T, double>::value) {
+          o.p = (double2*)m.p;
+          o.ld = m.ld;
+          return o;
+        }
+        o.ld = std::max(m.r, 1);
+        o.p = (double2*)cx.tmp_alloc(sizeof(double2) * (size_t)o.ld * std::max(m.c, 1));
+        std::vector<CopyDesc<double, T>> cd{{m.r, m.c, m.ld, o.ld, m.p, o.p, 0}};
+        if (m.r > 0 && m.c > 0) copy_batched<double, T>(cx.pool, cd);
+        return o;
+      };
+      std::vector<Mat<double>> KU(nodes.size()), KV(nodes.size()), XU(nodes.size()),
+          XV(nodes.size());
+      std::vector<Mat<double>*> mk;
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        Node2<T>& nd = bd.node(nodes[i].p, l, nodes[i].z);
+        KU[i].r = KU[i].c = nd.wU;
+        KV[i].r = KV[i].c = nd.wV;
+        mk.push_back(&KU[i]);
+        mk.push_back(&KV[i]);
+        if (l >= 2) {
+          const Node2<T>& par = bd.node(nodes[i].p, l - 1, nodes[i].z >> 2);
+          XU[i].r = nd.wU;
+          XU[i].c = par.TU.c;
+          XV[i].r = nd.wV;
+          XV[i].c = par.TV.c;
+          mk.push_back(&XU[i]);
+          mk.push_back(&XV[i]);
+        }
+      }
+      carve(P->arena, mk, &cx.tmp);
+      // K^U = sum_s B_{a,s} B_{a,s}^H + X X^H,  K^V = sum_s B_{s,a}^H B_{s,a} + Y Y^H
+      // with X = R_a T^U_parent, Y = W_a T^V_parent (levels >= 2)
+      // one launch per accumulation slot: a batched launch must not hold two
+      // descriptors that update the same output matrix
+      std::vector<GemmDesc<double>> gx, gnc[4], gcn[4];
+      std::vector<FillDesc<double>> fz;
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        int p = nodes[i].p, z = nodes[i].z;
+        Node2<T>& nd = bd.node(p, l, z);
+        int c = z & 3;
+        if (nd.wU > 0) fz.push_back({nd.wU, nd.wU, KU[i].ld, (double2*)KU[i].p, 0});
+        if (nd.wV > 0) fz.push_back({nd.wV, nd.wV, KV[i].ld, (double2*)KV[i].p, 0});
+        for (int s = 0; s < 3; ++s) {
+          int zs = (z & ~3) | Builder<T>::sib_child(c, s);
+          Node2<T>& sb = bd.node(p, l, zs);
+          Mat<double> b = to64(nd.B[s]);
+          if (nd.wU > 0 && b.c > 0)
+            gnc[s].push_back({nd.wU, nd.wU, b.c, b.ld, b.ld, KU[i].ld, b.p, b.p, KU[i].p, 1.0, 0.0,
+                              1.0});
+          int slot = Builder<T>::sib_slot(zs & 3, c);
+          Mat<double> bs = to64(sb.B[slot]);
+          if (nd.wV > 0 && bs.r > 0)
+            gcn[s].push_back({nd.wV, nd.wV, bs.r, bs.ld, bs.ld, KV[i].ld, bs.p, bs.p, KV[i].p, 1.0,
+                              0.0, 1.0});
+        }
+        if (l >= 2) {
+          const Node2<T>& par = bd.node(p, l - 1, z >> 2);
+          Mat<double> r = to64(nd.R), w = to64(nd.W);
+          if (nd.wU > 0 && par.TU.c > 0) {
+            gx.push_back({nd.wU, par.TU.c, r.c, r.ld, par.TU.ld, XU[i].ld, r.p, par.TU.p, XU[i].p,
+                          1.0, 0.0, 0.0});
+            gnc[3].push_back({nd.wU, nd.wU, XU[i].c, XU[i].ld, XU[i].ld, KU[i].ld, XU[i].p,
+                              XU[i].p, KU[i].p, 1.0, 0.0, 1.0});
+          }
+          if (nd.wV > 0 && par.TV.c > 0) {
+            gx.push_back({nd.wV, par.TV.c, w.c, w.ld, par.TV.ld, XV[i].ld, w.p, par.TV.p, XV[i].p,
+                          1.0, 0.0, 0.0});
+            gnc[3].push_back({nd.wV, nd.wV, XV[i].c, XV[i].ld, XV[i].ld, KV[i].ld, XV[i].p,
+                              XV[i].p, KV[i].p, 1.0, 0.0, 1.0});
+          }
+        }
+      }
+      fill_batched<double>(cx.pool, fz);
+      gemm_batched<double>(cx.pool, gx, OpN, OpN);
+      for (int s = 0; s < 4; ++s) {
+        gemm_batched<double>(cx.pool, gnc[s], OpN, OpC);
+        gemm_batched<double>(cx.pool, gcn[s], OpC, OpN);
+      }
+      // rank decisions
+      std::vector<Mat<double>> Ks;
+      std::vector<int> rmax;
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        Ks.push_back(KU[i]);
+        rmax.push_back(KU[i].r);
+        Ks.push_back(KV[i]);
+        rmax.push_back(KV[i].r);
+      }
+      std::vector<PcholOut> po;
+      pchol_run(cx, Ks, rmax, tol2, po);
+      // P = orth(L), T = triangular factor (FP64)
+      std::vector<Mat<double>> A, Q, R;
+      std::vector<Mat<double>> Pm(nodes.size() * 2);
+      std::vector<Mat<double>*> mp, mt;
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        Node2<T>& nd = bd.node(nodes[i].p, l, nodes[i].z);
+        for (int s = 0; s < 2; ++s) {
+          int r = po[2 * i + s].rank;
+          Pm[2 * i + s].r = s == 0 ? nd.wU : nd.wV;
+          Pm[2 * i + s].c = r;
+          mp.push_back(&Pm[2 * i + s]);
+          Mat<double>& Tm = s == 0 ? nd.TU : nd.TV;
+          Tm.r = r;
+          Tm.c = r;
+          mt.push_back(&Tm);
+        }
+      }
+      carve(P->arena, mp, &cx.tmp);
+      // the T matrices persist until the children are processed: one chunk per level
+      bd.own(-1, l, Builder<T>::K_TU, carve(P->arena, mt), old);
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        Node2<T>& nd = bd.node(nodes[i].p, l, nodes[i].z);
+        for (int s = 0; s < 2; ++s) {
+          if (po[2 * i + s].rank == 0) continue;
+          Mat<double> a = po[2 * i + s].L;
+          a.c = po[2 * i + s].rank;
+          A.push_back(a);
+          Q.push_back(Pm[2 * i + s]);
+          R.push_back(s == 0 ? nd.TU : nd.TV);
+        }
+      }
+      orth<double>(cx, A, Q, &R);
+      // working-precision copies of P and Q
+      std::vector<Mat<T>> Pw(nodes.size() * 2);
+      std::vector<Mat<T>*> mpw;
+      for (size_t i = 0; i < Pm.size(); ++i) {
+        Pw[i].r = Pm[i].r;
+        Pw[i].c = Pm[i].c;
+        mpw.push_back(&Pw[i]);
+      }
+      carve(P->arena, mpw, &cx.tmp);
+      {
+        std::vector<CopyDesc<T, double>> cd;
+        for (size_t i = 0; i < Pm.size(); ++i)
+          if (Pm[i].r > 0 && Pm[i].c > 0)
+            cd.push_back({Pm[i].r, Pm[i].c, Pm[i].ld, Pw[i].ld, Pm[i].p, Pw[i].p, 0});
+        copy_batched<T, double>(cx.pool, cd);
+      }
+      // ---- updates
+      // B^_{alpha,s} = P_alpha^H B Q_s
+      std::map<int, std::vector<Mat<T>*>> mnb;   // per problem
+      std::vector<Mat<T>> NB(nodes.size() * 3), XB(nodes.size() * 3);
+      std::vector<Mat<T>*> mxb;
+      std::map<std::pair<int, int>, int> idx;
+      for (size_t i = 0; i < nodes.size(); ++i) idx[{nodes[i].p, nodes[i].z}] = (int)i;
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        int p = nodes[i].p, z = nodes[i].z;
+        Node2<T>& nd = bd.node(p, l, z);
+        int c = z & 3;
+        for (int s = 0; s < 3; ++s) {
+          int zs = (z & ~3) | Builder<T>::sib_child(c, s);
+          int j = idx[{p, zs}];
+          XB[3 * i + s].r = nd.B[s].r;
+          XB[3 * i + s].c = Pw[2 * j + 1].c;
+          NB[3 * i + s].r = Pw[2 * i].c;
+          NB[3 * i + s].c = Pw[2 * j + 1].c;
+          mxb.push_back(&XB[3 * i + s]);
+          mnb[p].push_back(&NB[3 * i + s]);
+        }
+      }
+      carve(P->arena, mxb, &cx.tmp);
+      for (auto& kv : mnb) bd.own(kv.first, l, Builder<T>::K_B, carve(P->arena, kv.second), old);
+      std::vector<GemmDesc<T>> gb1, gb2;
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        int p = nodes[i].p, z = nodes[i].z;
+        Node2<T>& nd = bd.node(p, l, z);
+        int c = z & 3;
+        for (int s = 0; s < 3; ++s) {
+          int zs = (z & ~3) | Builder<T>::sib_child(c, s);
+          int j = idx[{p, zs}];
+          Mat<T>& x = XB[3 * i + s];
+          Mat<T>& nb = NB[3 * i + s];
+          const Mat<T>& q = Pw[2 * j + 1];
+          const Mat<T>& pp = Pw[2 * i];
+          gb1.push_back({x.r, x.c, nd.B[s].c, nd.B[s].ld, q.ld, x.ld, nd.B[s].p, q.p, x.p, T(1),
+                         T(0), T(0)});
+          gb2.push_back({nb.r, nb.c, pp.r, pp.ld, x.ld, nb.ld, pp.p, x.p, nb.p, T(1), T(0), T(0)});
+        }
+      }
+      gemm_batched<T>(cx.pool, gb1, OpN, OpN);
+      gemm_batched<T>(cx.pool, gb2, OpC, OpN);
+      // R^ = P^H R, W^ = Q^H W (l >= 2); leaf bases; children's transfers
+      std::map<int, std::vector<Mat<T>*>> mrw, mleaf, mchild;
+      std::vector<Mat<T>> NR(nodes.size()), NW(nodes.size()), NU(nodes.size()), NV(nodes.size());
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        int p = nodes[i].p;
+        Node2<T>& nd = bd.node(p, l, nodes[i].z);
+        if (l >= 2) {
+          NR[i].r = Pw[2 * i].c;
+          NR[i].c = nd.R.c;
+          NW[i].r = Pw[2 * i + 1].c;
+          NW[i].c = nd.W.c;
+          mrw[p].push_back(&NR[i]);
+          mrw[p].push_back(&NW[i]);
+        }
+        if (l == H.probs[p].L) {
+          NU[i].r = nd.U.r;
+          NU[i].c = Pw[2 * i].c;
+          NV[i].r = nd.V.r;
+          NV[i].c = Pw[2 * i + 1].c;
+          mleaf[p].push_back(&NU[i]);
+          mleaf[p].push_back(&NV[i]);
+        }
+      }
+      for (auto& kv : mrw) bd.own(kv.first, l, Builder<T>::K_R, carve(P->arena, kv.second), old);
+      for (auto& kv : mleaf) bd.own(kv.first, l, Builder<T>::K_U, carve(P->arena, kv.second), old);
+      std::vector<GemmDesc<T>> gr, gl;
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        int p = nodes[i].p;
+        Node2<T>& nd = bd.node(p, l, nodes[i].z);
+        const Mat<T>& pp = Pw[2 * i];
+        const Mat<T>& qq = Pw[2 * i + 1];
+        if (l >= 2) {
+          gr.push_back({NR[i].r, NR[i].c, pp.r, pp.ld, nd.R.ld, NR[i].ld, pp.p, nd.R.p, NR[i].p,
+                        T(1), T(0), T(0)});
+          gr.push_back({NW[i].r, NW[i].c, qq.r, qq.ld, nd.W.ld, NW[i].ld, qq.p, nd.W.p, NW[i].p,
+                        T(1), T(0), T(0)});
+        }
+        if (l == H.probs[p].L) {
+          gl.push_back({NU[i].r, NU[i].c, pp.r, nd.U.ld, pp.ld, NU[i].ld, nd.U.p, pp.p, NU[i].p,
+                        T(1), T(0), T(0)});
+          gl.push_back({NV[i].r, NV[i].c, qq.r, nd.V.ld, qq.ld, NV[i].ld, nd.V.p, qq.p, NV[i].p,
+                        T(1), T(0), T(0)});
+        }
+      }
+      gemm_batched<T>(cx.pool, gr, OpC, OpN);
+      gemm_batched<T>(cx.pool, gl, OpN, OpN);
+      // children of non-leaf nodes: R_chi <- R_chi P_alpha, W_chi <- W_chi Q_alpha
+      std::vector<Mat<T>> CR, CW;
+      std::vector<std::pair<int, int>> cref;   // (problem, child z)
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        int p = nodes[i].p;
+        if (l >= H.probs[p].L) continue;
+        for (int c = 0; c < 4; ++c) cref.push_back({p, 4 * nodes[i].z + c});
+      }
+      CR.resize(cref.size());
+      CW.resize(cref.size());
+      for (size_t k = 0; k < cref.size(); ++k) {
+        Node2<T>& ch = bd.node(cref[k].first, l + 1, cref[k].second);
+        int i = idx[{cref[k].first, cref[k].second >> 2}];
+        CR[k].r = ch.R.r;
+        CR[k].c = Pw[2 * i].c;
+        CW[k].r = ch.W.r;
+        CW[k].c = Pw[2 * i + 1].c;
+        mchild[cref[k].first].push_back(&CR[k]);
+        mchild[cref[k].first].push_back(&CW[k]);
+      }
+      for (auto& kv : mchild)
+        bd.own(kv.first, l + 1, Builder<T>::K_R, carve(P->arena, kv.second), old);
+      std::vector<GemmDesc<T>> gc;
+      for (size_t k = 0; k < cref.size(); ++k) {
+        Node2<T>& ch = bd.node(cref[k].first, l + 1, cref[k].second);
+        int i = idx[{cref[k].first, cref[k].second >> 2}];
+        const Mat<T>& pp = Pw[2 * i];
+        const Mat<T>& qq = Pw[2 * i + 1];
+        gc.push_back({CR[k].r, CR[k].c, pp.r, ch.R.ld, pp.ld, CR[k].ld, ch.R.p, pp.p, CR[k].p, T(1),
+                      T(0), T(0)});
+        gc.push_back({CW[k].r, CW[k].c, qq.r, ch.W.ld, qq.ld, CW[k].ld, ch.W.p, qq.p, CW[k].p, T(1),
+                      T(0), T(0)});
+      }
+      gemm_batched<T>(cx.pool, gc, OpN, OpN);
+      ND_HIP(hipStreamSynchronize(cx.s));
+      // install
+      for (size_t i = 0; i < nodes.size(); ++i) {
+        int p = nodes[i].p;
+        Node2<T>& nd = bd.node(p, l, nodes[i].z);
+        for (int s = 0; s < 3; ++s) nd.B[s] = NB[3 * i + s];
+        if (l >= 2) {
+          nd.R = NR[i];
+          nd.W = NW[i];
+        }
+        if (l == H.probs[p].L) {
+          nd.U = NU[i];
+          nd.V = NV[i];
+        }
+        nd.wU = Pw[2 * i].c;
+        nd.wV = Pw[2 * i + 1].c;
+      }
+      for (size_t k = 0; k < cref.size(); ++k) {
+        Node2<T>& ch = bd.node(cref[k].first, l + 1, cref[k].second);
+        ch.R = CR[k];
+        ch.W = CW[k];
+      }
+      // the parent's T matrices are no longer needed
+      if (l >= 2) bd.own(-1, l - 1, Builder<T>::K_TU, nullptr, old);
+      cx.release_tmp();
+      cx.pool.sync_reset();
+      bd.release(old);
+    }
+  }
+  // hand the remaining chunks to the HSS object
+  for (auto& kv : bd.chunk)
+    if (kv.second) H.mem.push_back(kv.second);
+  // record ranks
+  for (int l = 0; l <= Lmax && l < 16; ++l) {
+    int ru = 0, rv = 0;
+    for (auto& pb : H.probs)
+      if (l <= pb.L && l >= 1)
+        for (auto& nd : pb.lv[l]) {
+          ru = std::max(ru, nd.wU);
+          rv = std::max(rv, nd.wV);
+        }
+    P->info.max_rank_u[l] = ru;
+    P->info.max_rank_v[l] = rv;
+  }
+}
+
+template <typename T>
+void matvec_2d(Ctx& cx, HSS2<T>& H, const double2* x, double2* y) {
+  // y = H x for the recompressed HSS of problem 0 (test hook); x natural
+  // column order, y caller's point order, FP64 in and out.
+  Plan* P = cx.P;
+  const Problem& q = P->probs[0];
+  Prob2<T>& pb = H.probs[0];
+  const int L = pb.L;
+  ND_CHECK(L >= 1, NUDFT2_E_INVAL, "single-node tree");
+  // x to quadtree order in working precision (host permutation, tiny sizes)
+  std::vector<int64_t> cp(q.N());
+  ND_HIP(hipMemcpy(cp.data(), P->colperm + q.c0, sizeof(int64_t) * q.N(), hipMemcpyDeviceToHost));
+  std::vector<double2> hx(q.N());
+  ND_HIP(hipMemcpy(hx.data(), x, sizeof(double2) * q.N(), hipMemcpyDeviceToHost));
+  std::vector<cplx<T>> hxq(q.N());
+  for (int64_t i = 0; i < q.N(); ++i) hxq[i] = mk<T>((T)hx[cp[i] - q.c0].x, (T)hx[cp[i] - q.c0].y);
+  cplx<T>* xq = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * q.N());
+  ND_HIP(hipMemcpy(xq, hxq.data(), sizeof(cplx<T>) * q.N(), hipMemcpyHostToDevice));
+  std::vector<std::vector<cplx<T>*>> xh(L + 1), yh(L + 1);
+  for (int l = 1; l <= L; ++l)
+    for (auto& nd : pb.lv[l]) {
+      xh[l].push_back((cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * std::max(nd.wV, 1)));
+      yh[l].push_back((cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * std::max(nd.wU, 1)));
+    }
+  std::vector<GemmDesc<T>> g;
+  for (auto& nd : pb.lv[L])
+    if (nd.wV > 0)
+      g.push_back({nd.wV, 1, nd.V.r, nd.V.ld, std::max(nd.n, 1), nd.wV, nd.V.p, xq + nd.col0,
+                   xh[L][nd.z], T(1), T(0), T(0)});
+  gemm_batched<T>(cx.pool, g, OpC, OpN);
+  for (int l = L - 1; l >= 1; --l) {
+    for (int c = 0; c < 4; ++c) {
+      std::vector<GemmDesc<T>> gc;
+      for (auto& nd : pb.lv[l]) {
+        const Node2<T>& ch = pb.lv[l + 1][4 * nd.z + c];
+        if (nd.wV == 0) continue;
+        gc.push_back({nd.wV, 1, ch.wV, ch.W.ld, std::max(ch.wV, 1), nd.wV, ch.W.p,
+                      xh[l + 1][ch.z], xh[l][nd.z], T(1), T(0), c == 0 ? T(0) : T(1)});
+      }
+      gemm_batched<T>(cx.pool, gc, OpC, OpN);
+    }
+  }
+  for (int l = 1; l <= L; ++l) {
+    for (int s = 0; s < 3; ++s) {
+      std::vector<GemmDesc<T>> gs;
+      for (auto& nd : pb.lv[l]) {
+        int zs = (nd.z & ~3) | (s < (nd.z & 3) ? s : s + 1);
+        const Node2<T>& sb = pb.lv[l][zs];
+        if (nd.wU == 0) continue;
+        gs.push_back({nd.wU, 1, sb.wV, nd.B[s].ld, std::max(sb.wV, 1), nd.wU, nd.B[s].p,
+                      xh[l][zs], yh[l][nd.z], T(1), T(0), s == 0 ? T(0) : T(1)});
+      }
+      gemm_batched<T>(cx.pool, gs, OpN, OpN);
+    }
+    if (l >= 2) {
+      std::vector<GemmDesc<T>> gr;
+      for (auto& nd : pb.lv[l]) {
+        const Node2<T>& par = pb.lv[l - 1][nd.z >> 2];
+        if (nd.wU == 0 || par.wU == 0) continue;
+        gr.push_back({nd.wU, 1, par.wU, nd.R.ld, par.wU, nd.wU, nd.R.p, yh[l - 1][par.z],
+                      yh[l][nd.z], T(1), T(0), T(1)});
+      }
+      gemm_batched<T>(cx.pool, gr, OpN, OpN);
+    }
+  }
+  // leaves: y = D x + U yh, in the 2D-sorted order
+  cplx<T>* y2 = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * q.M);
+  std::vector<Mat<T>> Ds(pb.lv[L].size());
+  std::vector<Mat<T>*> md;
+  for (auto& nd : pb.lv[L]) {
+    Ds[nd.z].r = (int)nd.m;
+    Ds[nd.z].c = nd.n;
+    md.push_back(&Ds[nd.z]);
+  }
+  carve(P->arena, md, &cx.tmp);
+  std::vector<LeafDesc<T>> ld;
+  std::vector<GemmDesc<T>> gu, gd;
+  for (auto& nd : pb.lv[L]) {
+    LeafDesc<T> d{};
+    d.row0 = nd.row0;
+    d.m = (int)nd.m;
+    d.nx = q.nx;
+    d.ny = q.ny;
+    d.colx0 = q.colx[L][nd.a];
+    d.dx = nd.dx;
+    d.coly0 = q.coly[L][nd.b];
+    d.dy = nd.dy;
+    d.out = Ds[nd.z].p;
+    d.ld = Ds[nd.z].ld;
+    if (nd.m > 0) ld.push_back(d);
+    if (nd.m == 0) continue;
+    gu.push_back({(int)nd.m, 1, nd.wU, nd.U.ld, std::max(nd.wU, 1), (int)q.M, nd.U.p, yh[L][nd.z],
+                  y2 + (nd.row0 - q.m0), T(1), T(0), T(0)});
+    gd.push_back({(int)nd.m, 1, nd.n, Ds[nd.z].ld, std::max(nd.n, 1), (int)q.M, Ds[nd.z].p,
+                  xq + nd.col0, y2 + (nd.row0 - q.m0), T(1), T(0), T(1)});
+  }
+  gen_leafD<T>(cx.pool, ld, P->pts_2d);
+  gemm_batched<T>(cx.pool, gu, OpN, OpN);
+  gemm_batched<T>(cx.pool, gd, OpN, OpN);
+  std::vector<cplx<T>> hy(q.M);
+  std::vector<int64_t> perm(q.M);
+  ND_HIP(hipMemcpyAsync(hy.data(), y2, sizeof(cplx<T>) * q.M, hipMemcpyDeviceToHost, cx.s));
+  ND_HIP(hipMemcpyAsync(perm.data(), P->perm2d + q.m0, sizeof(int64_t) * q.M, hipMemcpyDeviceToHost, cx.s));
+  ND_HIP(hipStreamSynchronize(cx.s));
+  std::vector<double2> out(q.M);
+  for (int64_t s = 0; s < q.M; ++s) out[perm[s] - q.m0] = mk<double>(hy[s].x, hy[s].y);
+  ND_HIP(hipMemcpy(y, out.data(), sizeof(double2) * q.M, hipMemcpyHostToDevice));
+  cx.release_tmp();
+  cx.pool.sync_reset();
+}
+
+template void build_2d<float>(Ctx&, const std::vector<Tree1>&, const std::vector<Tree1>&, double,
+                              HSS2<float>&, int);
+template void build_2d<double>(Ctx&, const std::vector<Tree1>&, const std::vector<Tree1>&, double,
+                               HSS2<double>&, int);
+template void matvec_2d<float>(Ctx&, HSS2<float>&, const double2*, double2*);
+template void matvec_2d<double>(Ctx&, HSS2<double>&, const double2*, double2*);
+
+}  // namespace nd

@@ -39,6 +39,8 @@ struct GemmDesc {
   T beta;       // real beta
 };
 
+// One launch for the whole list.  Two descriptors of one list must not write
+// the same output matrix (their tiles run concurrently).
 template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB);
 

@@ -9,6 +9,21 @@ namespace nd {
 
 struct HSSFactors;   // defined in hss.h
 
+// Morton code of a quadtree node (x bit above y bit at every level), so that
+// the children of node z are 4z + 2p + q.
+inline uint32_t interleave(uint32_t a, uint32_t b, int L) {
+  uint32_t z = 0;
+  for (int i = 0; i < L; ++i) z |= (((a >> i) & 1u) << (2 * i + 1)) | (((b >> i) & 1u) << (2 * i));
+  return z;
+}
+inline void deinterleave(uint32_t z, int L, uint32_t& a, uint32_t& b) {
+  a = b = 0;
+  for (int i = 0; i < L; ++i) {
+    a |= ((z >> (2 * i + 1)) & 1u) << i;
+    b |= ((z >> (2 * i)) & 1u) << i;
+  }
+}
+
 // Host description of one problem's trees.
 //  * 1D trees (x and y), both of depth L: node (l, a) owns the columns
 //    [colx[l][a], colx[l][a+1]) and the rows of the x-sorted point order

@@ -59,20 +59,6 @@ Plan::~Plan() {
   arena.release_all();
 }
 
-static inline uint32_t interleave(uint32_t a, uint32_t b, int L) {
-  uint32_t z = 0;
-  for (int i = 0; i < L; ++i) z |= (((a >> i) & 1u) << (2 * i + 1)) | (((b >> i) & 1u) << (2 * i));
-  return z;
-}
-
-static inline void deinterleave(uint32_t z, int L, uint32_t& a, uint32_t& b) {
-  a = b = 0;
-  for (int i = 0; i < L; ++i) {
-    a |= ((z >> (2 * i + 1)) & 1u) << i;
-    b |= ((z >> (2 * i)) & 1u) << i;
-  }
-}
-
 int tree_depth(int nx, int ny, int leaf) {
   int L = 0;
   while ((int64_t)std::max(nx, ny) > (int64_t)leaf << L) ++L;
