@@ -22,12 +22,15 @@ struct Mat {
   }
 };
 
-// Execution context: stream, descriptor pool and temporaries.
+// Execution context: stream, descriptor pool and temporaries.  Temporaries
+// are released in scopes: release_tmp() frees what was allocated since the
+// innermost TmpScope began.
 struct Ctx {
   Plan* P = nullptr;
   hipStream_t s = nullptr;
   DescPool pool;
   std::vector<void*> tmp;
+  size_t base = 0;
   void* tmp_alloc(size_t bytes) {
     void* p = P->arena.alloc(bytes);
     tmp.push_back(p);
@@ -35,12 +38,24 @@ struct Ctx {
   }
   void release_tmp() {
     ND_HIP(hipStreamSynchronize(s));
-    for (void* p : tmp) P->arena.release(p);
-    tmp.clear();
+    for (size_t i = base; i < tmp.size(); ++i) P->arena.release(tmp[i]);
+    tmp.resize(base);
   }
   ~Ctx() {
     (void)hipStreamSynchronize(s);
     for (void* p : tmp) P->arena.release(p);
+  }
+};
+
+struct TmpScope {
+  Ctx& c;
+  size_t saved;
+  explicit TmpScope(Ctx& cx) : c(cx), saved(cx.base) { c.base = c.tmp.size(); }
+  ~TmpScope() {
+    (void)hipStreamSynchronize(c.s);
+    for (size_t i = c.base; i < c.tmp.size(); ++i) c.P->arena.release(c.tmp[i]);
+    c.tmp.resize(c.base);
+    c.base = saved;
   }
 };
 
@@ -96,23 +111,29 @@ struct Node2 {
   Mat<T> B[3];               // l >= 1: with the siblings in child order
   Mat<T> F, G;               // stage-1 factors
   Mat<double> TU, TV;        // stage-2 weights (r x r)
-  // URV
-  int mm = 0, nn = 0;        // rows / unknowns of the (merged) node
-  int mchk = 0, k = 0;
+  // URV factorization (Section 2.4): the node is a leaf of the (reduced) HSS
+  // matrix with mm rows, nn unknowns, row basis U (mm x wU), column basis V
+  // (nn x wV) and diagonal block D (mm x nn).
+  int mm = 0, nn = 0;
+  int mchk = 0;              // rows after the size reduction
+  int k = 0;                 // unknowns eliminated at this node
+  int nu = 0, pr = 0;        // unknowns / rows passed to the parent
   bool sizered = false;
-  Mat<T> UD;                 // [U D] -> reflectors of Omega (mm x (wU + nn))
-  Mat<T> Tom;                // T blocks of Omega
-  Mat<T> Vq, Tq;             // reflectors / T of QR(V) (nn x wV)
-  Mat<T> Pr, Tp;             // reflectors / T of QR(D~(:, 0:k))
-  Mat<T> D11, D12, U1;       // k x k, k x wV, k x wU
-  Mat<T> D22, U2, V2;        // (mchk-k) x wV, (mchk-k) x wU, wV x wV (or nn x wV)
+  Mat<T> UD;                 // [U D]; after the size reduction: reflectors of Omega
+  Mat<T> Tom;                // compact-WY blocks of Omega
+  Mat<T> Vm;                 // V (nn x wV); after QR: its reflectors (Q0)
+  Mat<T> Tq;                 // compact-WY blocks of Q0
+  Mat<T> V2;                 // V^_2 (nu x wV)
+  Mat<T> Wm;                 // [D~(:,0:k) | U^ | D~(:,k:)] -> [P refl. | U1,U2 | D12,D22]
+  Mat<T> Tp;                 // compact-WY blocks of P
+  Mat<T> D11;                // k x k upper triangular
 };
 
 template <typename T>
 struct Prob2 {
   int L = 0;
   std::vector<std::vector<Node2<T>>> lv;   // lv[l][z]
-  // root
+  // root least-squares factor: QR of the merged root block (rm x rn)
   Mat<T> rootA, rootR, rootT;
   int root_m = 0, root_n = 0;
   Mat<double> Fx, Fy;        // inverse DFT matrices (nx x nx, ny x ny), FP64
@@ -164,5 +185,14 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
 // order, y caller's point order (FP64 in and out).
 template <typename T>
 void matvec_2d(Ctx& cx, HSS2<T>& H, const double2* x, double2* y);
+
+// URV factorization of the recompressed HSS (bottom-up, root QR).
+template <typename T>
+void urv_factor(Ctx& cx, HSS2<T>& H);
+// Least-squares solve with the URV factors: f (ldf x nrhs, rows in the
+// 2D-sorted point order, working precision) -> c (ldc x nrhs, quadtree column
+// order, working precision).  f is overwritten.
+template <typename T>
+void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t ldc, int nrhs);
 
 }  // namespace nd

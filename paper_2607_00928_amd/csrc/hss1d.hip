@@ -39,6 +39,7 @@ void free_1d(Plan* P, std::vector<Tree1>& t) {
 }
 
 void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out) {
+  TmpScope scope_(cx);
   Plan* P = cx.P;
   const int np = (int)P->probs.size();
   out.assign(np, Tree1());
@@ -459,6 +460,7 @@ void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out) {
 }
 
 void matvec_1d(Ctx& cx, int dim, const std::vector<Tree1>& trees, const double2* x, double2* y) {
+  TmpScope scope_(cx);
   Plan* P = cx.P;
   const Tree1& t = trees[0];
   const Problem& q = P->probs[0];

@@ -71,6 +71,7 @@ struct Builder {
 template <typename T>
 void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& ty, double eps,
               HSS2<T>& H, int stages) {
+  TmpScope scope_(cx);
   Plan* P = cx.P;
   Builder<T> bd(cx, H);
   const int np = (int)P->probs.size();
@@ -784,6 +785,7 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
 
 template <typename T>
 void matvec_2d(Ctx& cx, HSS2<T>& H, const double2* x, double2* y) {
+  TmpScope scope_(cx);
   // y = H x for the recompressed HSS of problem 0 (test hook); x natural
   // column order, y caller's point order, FP64 in and out.
   Plan* P = cx.P;
