@@ -48,8 +48,11 @@ namespace {
 constexpr int GT = 64;    // output tile
 constexpr int GK = 16;    // k per stage
 
+// splits > 1: blockIdx.z takes the k range [z kc, (z+1) kc) and the result is
+// added atomically (C must already hold beta C).
 template <typename T, int OPA, int OPB>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs) {
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs,
+                                                   int splits) {
   using C2 = cplx<T>;
   using A4 = typename acc4<T>::type;
   __shared__ T Asr[GK][GT + 4], Asi[GK][GT + 4];
@@ -57,6 +60,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
   const GemmDesc<T> d = descs[blockIdx.y];
   const int tm = (d.m + GT - 1) / GT, tn = (d.n + GT - 1) / GT;
   if ((int)blockIdx.x >= tm * tn) return;
+  int kc = (((d.k + splits - 1) / splits) + GK - 1) / GK * GK;
+  const int kbeg = (int)blockIdx.z * kc;
+  const int kend = min(d.k, kbeg + kc);
+  if (kbeg >= kend && splits > 1) return;
   const int i0 = (blockIdx.x % tm) * GT, j0 = (blockIdx.x / tm) * GT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -66,7 +73,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
 #pragma unroll
     for (int b = 0; b < 2; ++b) { accr[a][b] = A4{0, 0, 0, 0}; acci[a][b] = A4{0, 0, 0, 0}; }
 
-  for (int l0 = 0; l0 < d.k; l0 += GK) {
+  for (int l0 = kbeg; l0 < kend; l0 += GK) {
     __syncthreads();
     // A tile: rows i0..i0+63 of op(A), k l0..l0+15
     if (OPA == OpN) {
@@ -75,7 +82,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
       for (int u = 0; u < 4; ++u) {
         int l = lq + 4 * u;
         C2 v = mk<T>(0, 0);
-        if (i0 + i < d.m && l0 + l < d.k) v = d.A[(int64_t)(i0 + i) + (int64_t)(l0 + l) * d.lda];
+        if (i0 + i < d.m && l0 + l < kend) v = d.A[(int64_t)(i0 + i) + (int64_t)(l0 + l) * d.lda];
         Asr[l][i] = v.x;
         Asi[l][i] = v.y;
       }
@@ -85,7 +92,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
       for (int u = 0; u < 4; ++u) {
         int i = iq + 16 * u;
         C2 v = mk<T>(0, 0);
-        if (i0 + i < d.m && l0 + l < d.k) v = d.A[(int64_t)(l0 + l) + (int64_t)(i0 + i) * d.lda];
+        if (i0 + i < d.m && l0 + l < kend) v = d.A[(int64_t)(l0 + l) + (int64_t)(i0 + i) * d.lda];
         Asr[l][i] = v.x;
         Asi[l][i] = -v.y;
       }
@@ -96,7 +103,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
       for (int u = 0; u < 4; ++u) {
         int j = jq + 16 * u;
         C2 v = mk<T>(0, 0);
-        if (j0 + j < d.n && l0 + l < d.k) v = d.B[(int64_t)(l0 + l) + (int64_t)(j0 + j) * d.ldb];
+        if (j0 + j < d.n && l0 + l < kend) v = d.B[(int64_t)(l0 + l) + (int64_t)(j0 + j) * d.ldb];
         Bsr[l][j] = v.x;
         Bsi[l][j] = v.y;
       }
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
       for (int u = 0; u < 4; ++u) {
         int l = lq + 4 * u;
         C2 v = mk<T>(0, 0);
-        if (j0 + j < d.n && l0 + l < d.k) v = d.B[(int64_t)(j0 + j) + (int64_t)(l0 + l) * d.ldb];
+        if (j0 + j < d.n && l0 + l < kend) v = d.B[(int64_t)(j0 + j) + (int64_t)(l0 + l) * d.ldb];
         Bsr[l][j] = v.x;
         Bsi[l][j] = -v.y;
       }
@@ -146,6 +153,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
           T cr = accr[a][b][v], ci = acci[a][b][v];
           C2 out = mk<T>(d.ar * cr - d.ai * ci, d.ar * ci + d.ai * cr);
           C2* p = d.C + (int64_t)i + (int64_t)j * d.ldc;
+          if (splits > 1) {
+            atomicAdd(&p->x, out.x);
+            atomicAdd(&p->y, out.y);
+            continue;
+          }
           if (d.beta != T(0)) {
             C2 o = *p;
             out.x += d.beta * o.x;
@@ -154,6 +166,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
           *p = out;
         }
       }
+}
+
+// C <- beta C for split-k launches (beta 0 writes zeros)
+template <typename T>
+__global__ void gemm_prescale_kernel(const GemmDesc<T>* __restrict__ descs) {
+  const GemmDesc<T> d = descs[blockIdx.y];
+  if (d.beta == T(1)) return;
+  int64_t cnt = (int64_t)d.m * d.n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
+    int i = (int)(e % d.m), j = (int)(e / d.m);
+    cplx<T>* p = d.C + (int64_t)i + (int64_t)j * d.ldc;
+    if (d.beta == T(0)) *p = mk<T>(0, 0);
+    else { cplx<T> v = *p; *p = mk<T>(v.x * d.beta, v.y * d.beta); }
+  }
 }
 
 // -------------------------------------------------------------- QR panel
@@ -295,6 +321,224 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const QRDesc<T>* __restri
         } else {
           *pr = mk<T>(0, 0);
         }
+      }
+    }
+  }
+}
+
+// Cooperative panel factorization: a group of gsize workgroups factors one
+// problem's panel; every thread keeps RPT rows of the panel in registers.
+// Per column one group barrier: the partial sums (sigma^2 and the raw dots
+// conj(x)^T A(:, c) over the rows below the diagonal) are added atomically
+// into a rotating scratch buffer, after which every workgroup derives the
+// reflector (tau, beta, 1/(alpha - beta)) and the update coefficients
+// u_c = A(jj, c) + conj(scal) s_c by itself.  Groups loop over problems.
+// Requires all workgroups to be resident (cooperative launch).
+__device__ inline void group_barrier(unsigned* cnt, unsigned target, int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(cnt, 1u);
+    unsigned it = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++it > (1u << 26)) {
+        atomicExch(err, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+constexpr int QS = QR_NB + 1;          // sums per column: QR_NB dots + sigma
+constexpr int QSCR = 3 * QS + 3 * QR_NB;   // rotating sums + rotating row copies
+
+template <typename T, int RPT>
+__global__ __launch_bounds__(256) void qr_panel_coop_kernel(
+    const QRDesc<T>* __restrict__ descs, const int* __restrict__ active, int nact, int j0,
+    int gsize, cplx<T>* __restrict__ scratch, unsigned* __restrict__ bar, int* __restrict__ err) {
+  using C2 = cplx<T>;
+  __shared__ T redr[4][QS], redi[4][QS];
+  __shared__ C2 tot[QS];
+  __shared__ C2 rowv[QR_NB];
+  __shared__ C2 Ts[QR_NB][QR_NB + 1];
+  __shared__ C2 tau_s, scal_s;
+  __shared__ T beta_s;
+  __shared__ C2 zs[QR_NB];
+  const int ngroups = gridDim.x / gsize;
+  const int g = blockIdx.x / gsize, w = blockIdx.x % gsize;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  C2* sums = scratch + (size_t)g * QSCR;
+  C2* rows = sums + 3 * QS;
+  unsigned* cnt = bar + g;
+  unsigned epoch = 0;
+  int step = 0;
+  for (int pi = g; pi < nact; pi += ngroups) {
+    const QRDesc<T> d = descs[active[pi]];
+    const int kmin = min(d.m, d.n);
+    const int jb = min(QR_NB, kmin - j0);
+    const int mr = d.m - j0;
+    C2* Ap = d.A + j0 + (int64_t)j0 * d.lda;
+    C2 a[RPT][QR_NB];
+    int rid[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      rid[q] = w * 256 * RPT + q * 256 + tid;
+#pragma unroll
+      for (int c = 0; c < QR_NB; ++c)
+        a[q][c] = (rid[q] < mr && c < jb) ? Ap[rid[q] + (int64_t)c * d.lda] : mk<T>(0, 0);
+    }
+    if (w == 0)
+      for (int e = tid; e < QR_NB * QR_NB; e += 256) Ts[e % QR_NB][e / QR_NB] = mk<T>(0, 0);
+    for (int jj = 0; jj < jb; ++jj, ++step) {
+      C2* buf = sums + (step % 3) * QS;
+      C2* rbuf = rows + (step % 3) * QR_NB;
+      // ---- pivot column values of own rows (static register indexing)
+      C2 xq[RPT];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        xq[q] = mk<T>(0, 0);
+#pragma unroll
+        for (int c = 0; c < QR_NB; ++c)
+          if (c == jj) xq[q] = a[q][c];
+      }
+      // ---- partial sums over own rows below the diagonal; publish row jj
+#pragma unroll
+      for (int c = 0; c <= QR_NB; ++c) {
+        T vr = 0, vi = 0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          if (rid[q] > jj && rid[q] < mr) {
+            C2 x = xq[q];
+            if (c == QR_NB) {
+              vr += x.x * x.x + x.y * x.y;
+            } else if (c != jj && c < jb) {
+              C2 y = a[q][c];
+              vr += x.x * y.x + x.y * y.y;   // conj(x) y
+              vi += x.x * y.y - x.y * y.x;
+            }
+          }
+        }
+        vr = warp_sum(vr);
+        vi = warp_sum(vi);
+        if (lane == 0) {
+          redr[wave][c] = vr;
+          redi[wave][c] = vi;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RPT; ++q)
+        if (rid[q] == jj) {
+#pragma unroll
+          for (int c = 0; c < QR_NB; ++c) rbuf[c] = a[q][c];
+        }
+      __syncthreads();
+      if (tid < QS) {
+        T vr = redr[0][tid] + redr[1][tid] + redr[2][tid] + redr[3][tid];
+        T vi = redi[0][tid] + redi[1][tid] + redi[2][tid] + redi[3][tid];
+        if (vr != T(0)) atomicAdd(&buf[tid].x, vr);
+        if (vi != T(0)) atomicAdd(&buf[tid].y, vi);
+      }
+      if (w == 0 && tid < QS) sums[((step + 1) % 3) * QS + tid] = mk<T>(0, 0);
+      group_barrier(cnt, (++epoch) * (unsigned)gsize, err);
+      if (tid < QS) tot[tid] = buf[tid];
+      if (tid < QR_NB) rowv[tid] = rbuf[tid];
+      __syncthreads();
+      if (tid == 0) {
+        T sig = tot[QR_NB].x;
+        C2 alpha = rowv[jj];
+        C2 tau, scal;
+        T beta;
+        if (sig == T(0) && alpha.y == T(0)) {
+          tau = mk<T>(0, 0);
+          scal = mk<T>(0, 0);
+          beta = alpha.x;
+        } else {
+          T nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig);
+          beta = alpha.x >= T(0) ? -nrm : nrm;
+          tau = mk<T>((beta - alpha.x) / beta, -alpha.y / beta);
+          T dr = alpha.x - beta, di = alpha.y;
+          T den = dr * dr + di * di;
+          scal = mk<T>(dr / den, -di / den);
+        }
+        tau_s = tau;
+        scal_s = scal;
+        beta_s = beta;
+        if (w == 0) {
+          // T(0:jj, jj) = -tau T(0:jj, 0:jj) z,  z_q = v_q^H v_jj
+          //             = scal conj(s_q) + conj(A(jj, q))
+          Ts[jj][jj] = tau;
+          for (int q2 = 0; q2 < jj; ++q2) {
+            C2 sq = tot[q2];
+            zs[q2] = cadd(cmul(scal, cconj(sq)), cconj(rowv[q2]));
+          }
+          for (int r = 0; r < jj; ++r) {
+            C2 sum = mk<T>(0, 0);
+            for (int q2 = r; q2 < jj; ++q2) sum = cadd(sum, cmul(Ts[r][q2], zs[q2]));
+            C2 t = cmul(tau, sum);
+            Ts[r][jj] = mk<T>(-t.x, -t.y);
+          }
+        }
+      }
+      __syncthreads();
+      const C2 tau = tau_s, scal = scal_s, ctau = cconj(tau_s);
+      const C2 cscal = cconj(scal);
+      // ---- update own rows
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        if (rid[q] < jj || rid[q] >= mr) continue;
+        const bool diag = rid[q] == jj;
+        const C2 v = diag ? mk<T>(1, 0) : cmul(xq[q], scal);
+        const C2 f = cmul(ctau, v);
+        const C2 newjj = diag ? mk<T>(beta_s, 0) : v;
+#pragma unroll
+        for (int c = 0; c < QR_NB; ++c) {
+          if (c == jj) {
+            a[q][c] = newjj;
+          } else if (c > jj && c < jb) {
+            C2 u = cadd(rowv[c], cmul(cscal, tot[c]));
+            a[q][c] = csub(a[q][c], cmul(f, u));
+          }
+        }
+      }
+    }
+    // ---- write back: R block rows, explicit V, T
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (rid[q] >= mr) continue;
+#pragma unroll
+      for (int c = 0; c < QR_NB; ++c) {
+        if (c >= jb) continue;
+        C2* pa = Ap + rid[q] + (int64_t)c * d.lda;
+        if (rid[q] < jb) {
+          C2* pr = d.R + (j0 + rid[q]) + (int64_t)(j0 + c) * d.ldr;
+          if (rid[q] <= c) {
+            *pr = a[q][c];
+            *pa = (rid[q] == c) ? mk<T>(1, 0) : mk<T>(0, 0);
+          } else {
+            *pr = mk<T>(0, 0);
+            *pa = a[q][c];
+          }
+        } else {
+          *pa = a[q][c];
+        }
+      }
+    }
+    if (w == 0) {
+      for (int c = 0; c < jb; ++c)
+        for (int r = tid; r < j0; r += 256) {
+          C2* pa = d.A + r + (int64_t)(j0 + c) * d.lda;
+          d.R[r + (int64_t)(j0 + c) * d.ldr] = *pa;
+          *pa = mk<T>(0, 0);
+        }
+      __syncthreads();
+      const int blk = j0 / QR_NB;
+      C2* Tb = d.Tb + (int64_t)blk * QR_NB * QR_NB;
+      for (int e = tid; e < QR_NB * QR_NB; e += 256) {
+        int r = e % QR_NB, c = e / QR_NB;
+        Tb[r + c * QR_NB] = (r < jb && c < jb) ? Ts[r][c] : mk<T>(0, 0);
       }
     }
   }
@@ -483,30 +727,72 @@ template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB) {
   if (d.empty()) return;
   size_t chunk = 32768;
-  for (size_t s = 0; s < d.size(); s += chunk) {
-    size_t n = std::min(chunk, d.size() - s);
-    int maxt = 0;
-    std::vector<GemmDesc<T>> sub(d.begin() + s, d.begin() + s + n);
+  for (size_t s0 = 0; s0 < d.size(); s0 += chunk) {
+    size_t n = std::min(chunk, d.size() - s0);
+    int maxt = 0, maxk = 0;
+    std::vector<GemmDesc<T>> sub(d.begin() + s0, d.begin() + s0 + n);
     for (auto& g : sub) {
       if (g.m <= 0 || g.n <= 0) { g.m = 0; g.n = 0; continue; }
-      if (g.k <= 0) {   // C = beta C: run with k = 0 (zero accumulators)
-        g.k = 0;
-      }
+      if (g.k < 0) g.k = 0;
       maxt = std::max(maxt, ceil_div(g.m, GT) * ceil_div(g.n, GT));
+      maxk = std::max(maxk, g.k);
     }
     if (maxt == 0) continue;
+    // split the k loop when the output tiles cannot fill the chip
+    int64_t wgs = (int64_t)maxt * (int64_t)n;
+    int splits = 1;
+    if (wgs < 1024 && maxk >= 512) {
+      splits = (int)std::min<int64_t>((maxk + 255) / 256, (2048 + wgs - 1) / wgs);
+      splits = std::max(1, std::min(splits, 64));
+    }
     auto* dd = (GemmDesc<T>*)pool.push(sub.data(), sizeof(GemmDesc<T>) * n);
-    dim3 grid(maxt, (unsigned)n);
+    if (splits > 1) {
+      int64_t mx = 0;
+      for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
+      hipLaunchKernelGGL((gemm_prescale_kernel<T>),
+                         dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
+                              (unsigned)n),
+                         dim3(256), 0, pool.stream, dd);
+    }
+    dim3 grid(maxt, (unsigned)n, splits);
     if (opA == OpN && opB == OpN)
-      hipLaunchKernelGGL((gemm_kernel<T, OpN, OpN>), grid, dim3(256), 0, pool.stream, dd);
+      hipLaunchKernelGGL((gemm_kernel<T, OpN, OpN>), grid, dim3(256), 0, pool.stream, dd, splits);
     else if (opA == OpC && opB == OpN)
-      hipLaunchKernelGGL((gemm_kernel<T, OpC, OpN>), grid, dim3(256), 0, pool.stream, dd);
+      hipLaunchKernelGGL((gemm_kernel<T, OpC, OpN>), grid, dim3(256), 0, pool.stream, dd, splits);
     else if (opA == OpN && opB == OpC)
-      hipLaunchKernelGGL((gemm_kernel<T, OpN, OpC>), grid, dim3(256), 0, pool.stream, dd);
+      hipLaunchKernelGGL((gemm_kernel<T, OpN, OpC>), grid, dim3(256), 0, pool.stream, dd, splits);
     else
-      hipLaunchKernelGGL((gemm_kernel<T, OpC, OpC>), grid, dim3(256), 0, pool.stream, dd);
+      hipLaunchKernelGGL((gemm_kernel<T, OpC, OpC>), grid, dim3(256), 0, pool.stream, dd, splits);
     ND_HIP(hipGetLastError());
   }
+}
+
+// Launch the cooperative panel kernel: groups of gsize workgroups, as many
+// groups as fit on the device at once (they loop over the active problems).
+template <typename T>
+void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const int* dact, int nact, int j0,
+                     int maxmr) {
+  constexpr int RPT = sizeof(T) == 4 ? 2 : 1;
+  const void* kern = (const void*)qr_panel_coop_kernel<T, RPT>;
+  static int max_res[2] = {0, 0};
+  int& mres = max_res[sizeof(T) == 4 ? 0 : 1];
+  if (mres == 0) {
+    int dev = 0, cus = 0, per = 0;
+    ND_HIP(hipGetDevice(&dev));
+    ND_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    ND_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 256, 0));
+    mres = std::max(1, cus * std::max(per, 1));
+  }
+  int gsize = std::max(1, (maxmr + 256 * RPT - 1) / (256 * RPT));
+  ND_CHECK(gsize <= mres, NUDFT2_E_INTERNAL, "QR panel taller than the device can hold");
+  int ngroups = std::max(1, std::min(nact, mres / gsize));
+  std::vector<char> zeros((size_t)ngroups * (QSCR * sizeof(cplx<T>) + sizeof(unsigned)) + 64, 0);
+  cplx<T>* scr = (cplx<T>*)pool.push(zeros.data(), (size_t)ngroups * QSCR * sizeof(cplx<T>));
+  unsigned* bar = (unsigned*)pool.push(zeros.data(), (size_t)ngroups * sizeof(unsigned));
+  int* err = (int*)pool.push(zeros.data(), sizeof(int));
+  void* args[] = {(void*)&dd, (void*)&dact, (void*)&nact, (void*)&j0, (void*)&gsize,
+                  (void*)&scr, (void*)&bar, (void*)&err};
+  ND_HIP(hipLaunchCooperativeKernel(kern, dim3(ngroups * gsize), dim3(256), args, 0, pool.stream));
 }
 
 template <typename T>
@@ -556,9 +842,9 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& d, void* ws) {
       g3.push_back({mr, nt, jb, q.lda, QR_NB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
     }
     int* dact = (int*)pool.push(act.data(), sizeof(int) * act.size());
-    hipLaunchKernelGGL((qr_panel_kernel<T>), dim3((unsigned)act.size()), dim3(256), 0,
-                       pool.stream, dd, dact, j0);
-    ND_HIP(hipGetLastError());
+    int maxmr = 0;
+    for (int i : act) maxmr = std::max(maxmr, d[i].m - j0);
+    qr_panel_launch<T>(pool, dd, dact, (int)act.size(), j0, maxmr);
     gemm_batched<T>(pool, g1, OpC, OpN);
     gemm_batched<T>(pool, g2, OpC, OpN);
     gemm_batched<T>(pool, g3, OpN, OpN);
@@ -655,7 +941,7 @@ void pchol_batched(DescPool& pool, const std::vector<PcholDesc>& d) {
 }
 
 template <typename T>
-void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
+static void trsv_small(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
   if (d.empty()) return;
   int maxr = 0;
   for (auto& q : d) maxr = std::max(maxr, q.nrhs);
@@ -663,6 +949,41 @@ void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
   hipLaunchKernelGGL((trsv_upper_kernel<T>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
                      pool.stream, dd);
   ND_HIP(hipGetLastError());
+}
+
+// Upper-triangular solves.  Small systems: one workgroup each.  Large ones:
+// blocked back substitution, 128 x 128 diagonal blocks solved by one
+// workgroup, the rows above updated by a matrix-core GEMM.
+template <typename T>
+void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
+  constexpr int BS = 128;
+  std::vector<TrsDesc<T>> small, big;
+  for (auto& q : d) {
+    if (q.k <= 0 || q.nrhs <= 0) continue;
+    (q.k <= 2 * BS ? small : big).push_back(q);
+  }
+  trsv_small<T>(pool, small);
+  if (big.empty()) return;
+  int maxblk = 0;
+  for (auto& q : big) maxblk = std::max(maxblk, (q.k + BS - 1) / BS);
+  std::vector<TrsDesc<T>> dg;
+  std::vector<GemmDesc<T>> gu;
+  for (int s = 0; s < maxblk; ++s) {
+    dg.clear();
+    gu.clear();
+    for (auto& q : big) {
+      int nblk = (q.k + BS - 1) / BS;
+      if (s >= nblk) continue;
+      int b = nblk - 1 - s;
+      int i0 = b * BS, bs = std::min(BS, q.k - i0);
+      dg.push_back({bs, q.nrhs, q.ldr, q.ldb, q.R + i0 + (int64_t)i0 * q.ldr, q.B + i0});
+      if (i0 > 0)
+        gu.push_back({i0, q.nrhs, bs, q.ldr, q.ldb, q.ldb, q.R + (int64_t)i0 * q.ldr, q.B + i0,
+                      q.B, T(-1), T(0), T(1)});
+    }
+    trsv_small<T>(pool, dg);
+    gemm_batched<T>(pool, gu, OpN, OpN);
+  }
 }
 
 template <typename TD, typename TS>
