@@ -83,6 +83,14 @@ typedef struct {
   int64_t factor_bytes;   /* device bytes held by the factors                 */
   double factor_flops;    /* flops counted over the factorization's operations */
   double t_plan_ms, t_compress_ms, t_facesplit_ms, t_recompress_ms, t_urv_ms;
+  /* kernel timing while profiling is on (nudft2_set_profiling), per class:
+   * 0 = exact FP64 apply, 1 = FP32 matrix-core GEMM, 2 = FP64 matrix-core
+   * GEMM, 3 = Householder panel.  Milliseconds from HIP events recorded on
+   * the plan's stream around each launch; algorithmic flops (8 per complex
+   * multiply-add of the launch's problems); launch counts. */
+  double kernel_ms[4];
+  double kernel_flops[4];
+  int64_t kernel_launches[4];
 } nudft2_info;
 
 void nudft2_default_opts(nudft2_opts* opts);
@@ -141,6 +149,10 @@ nudft2_status nudft2_apply_adj(nudft2_plan_t plan, const double* f, double* c,
 
 /* Fill *info (HOST).  Synchronises with the plan's stream. */
 nudft2_status nudft2_get_info(nudft2_plan_t plan, nudft2_info* info);
+
+/* Turn per-kernel-class event timing on (1) or off (0); resets the totals.
+ * Synchronises with the plan's stream. */
+nudft2_status nudft2_set_profiling(nudft2_plan_t plan, int32_t on);
 
 /* Release every device buffer of the plan.  NULL is accepted. */
 nudft2_status nudft2_destroy(nudft2_plan_t plan);

@@ -74,7 +74,12 @@ class _PlanBase:
                     factor_bytes=inf.factor_bytes, factor_flops=inf.factor_flops,
                     t_plan_ms=inf.t_plan_ms, t_compress_ms=inf.t_compress_ms,
                     t_facesplit_ms=inf.t_facesplit_ms,
-                    t_recompress_ms=inf.t_recompress_ms, t_urv_ms=inf.t_urv_ms)
+                    t_recompress_ms=inf.t_recompress_ms, t_urv_ms=inf.t_urv_ms,
+                    kernel_ms=list(inf.kernel_ms), kernel_flops=list(inf.kernel_flops),
+                    kernel_launches=list(inf.kernel_launches))
+
+    def set_profiling(self, on: bool = True):
+        check(lib.nudft2_set_profiling(self._handle, 1 if on else 0), "nudft2_set_profiling")
 
     def _rhs(self, f: torch.Tensor):
         self._check_dev(f, "f")

@@ -52,6 +52,9 @@ class Info(C.Structure):
         ("t_facesplit_ms", C.c_double),
         ("t_recompress_ms", C.c_double),
         ("t_urv_ms", C.c_double),
+        ("kernel_ms", C.c_double * 4),
+        ("kernel_flops", C.c_double * 4),
+        ("kernel_launches", C.c_int64 * 4),
     ]
 
 
@@ -87,6 +90,7 @@ def _load():
         "nudft2_apply_adj": (C.c_int, [P, P, P, C.c_int32]),
         "nudft2_get_info": (C.c_int, [P, C.POINTER(Info)]),
         "nudft2_destroy": (C.c_int, [P]),
+        "nudft2_set_profiling": (C.c_int, [P, C.c_int32]),
         "nudft2_strerror": (C.c_char_p, [C.c_int]),
         "nudft2_last_error": (C.c_char_p, []),
         "nudft2_test_binning": (C.c_int, [DP, C.c_int64, C.c_int32, C.c_int32, C.c_int32,

@@ -11,6 +11,15 @@
 namespace nd {
 
 static thread_local std::string g_last_error;
+thread_local Profiler* g_prof = nullptr;
+
+// Routes kernel timing of the calling thread to the plan's profiler while an
+// entry point runs.
+struct PlanProf {
+  Profiler* saved;
+  explicit PlanProf(Plan* P) : saved(g_prof) { g_prof = P->profiling ? &P->prof : nullptr; }
+  ~PlanProf() { g_prof = saved; }
+};
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 template <typename F>
@@ -199,6 +208,7 @@ nudft2_status nudft2_factor(nudft2_plan_t plan) {
   return guard([&] {
     ND_CHECK(plan != nullptr, NUDFT2_E_INVAL, "null plan");
     Plan* P = reinterpret_cast<Plan*>(plan);
+    PlanProf pp(P);
     factor(P);
   });
 }
@@ -210,6 +220,7 @@ nudft2_status nudft2_solve(nudft2_plan_t plan, const double* f, double* c, int32
     ND_CHECK(nrhs > 0, NUDFT2_E_INVAL, "nrhs must be positive");
     Plan* P = reinterpret_cast<Plan*>(plan);
     ND_CHECK(P->factored, NUDFT2_E_STATE, "solve before factor");
+    PlanProf pp(P);
     solve(P, reinterpret_cast<const double2*>(f), reinterpret_cast<double2*>(c), nrhs, info,
           false);
   });
@@ -232,6 +243,7 @@ nudft2_status nudft2_apply(nudft2_plan_t plan, const double* c, double* f, int32
     ND_CHECK(plan != nullptr && f != nullptr && c != nullptr, NUDFT2_E_INVAL, "null pointer");
     ND_CHECK(nrhs > 0, NUDFT2_E_INVAL, "nrhs must be positive");
     Plan* P = reinterpret_cast<Plan*>(plan);
+    PlanProf pp(P);
     apply_fwd(P, reinterpret_cast<const double2*>(c), reinterpret_cast<double2*>(f), nrhs,
               P->stream);
   });
@@ -252,8 +264,24 @@ nudft2_status nudft2_get_info(nudft2_plan_t plan, nudft2_info* info) {
     ND_CHECK(plan != nullptr && info != nullptr, NUDFT2_E_INVAL, "null pointer");
     Plan* P = reinterpret_cast<Plan*>(plan);
     ND_HIP(hipStreamSynchronize(P->stream));
+    P->prof.collect();
     *info = P->info;
     info->factor_bytes = (int64_t)P->arena.bytes;
+    for (int i = 0; i < KC_COUNT; ++i) {
+      info->kernel_ms[i] = P->prof.ms[i];
+      info->kernel_flops[i] = P->prof.flops[i];
+      info->kernel_launches[i] = P->prof.launches[i];
+    }
+  });
+}
+
+nudft2_status nudft2_set_profiling(nudft2_plan_t plan, int32_t on) {
+  return guard([&] {
+    ND_CHECK(plan != nullptr, NUDFT2_E_INVAL, "null plan");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    ND_HIP(hipStreamSynchronize(P->stream));
+    P->prof.reset();
+    P->profiling = on != 0;
   });
 }
 

@@ -12,6 +12,7 @@
 // split over chunks of points with FP64 atomics into C.
 #include "device_util.h"
 #include "plan.h"
+#include "prof.h"
 
 namespace nd {
 
@@ -246,6 +247,9 @@ __global__ void zero_kernel(double2* p, int64_t n) {
 
 void apply_fwd(Plan* P, const double2* c, double2* f, int nrhs, hipStream_t s) {
   dim3 grid(P->apply_tiles, nrhs);
+  double fl = 0;
+  for (auto& q : P->probs) fl += 8.0 * (double)q.M * (double)q.N() * nrhs;
+  ProfScope ps(s, KC_APPLY, fl);
   hipLaunchKernelGGL(apply_fwd_kernel, grid, dim3(256), 0, s, P->pts_user, c, f,
                      P->d_aprob, (int)P->probs.size(), P->d_tile_off, P->Mtot,
                      P->Ntot);

@@ -7,6 +7,7 @@
 
 #include "device_util.h"
 #include "la.h"
+#include "prof.h"
 
 namespace nd {
 
@@ -337,17 +338,16 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const QRDesc<T>* __restri
 __device__ inline void group_barrier(unsigned* cnt, unsigned target, int* err) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    atomicAdd(cnt, 1u);
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned it = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (++it > (1u << 26)) {
         atomicExch(err, 1);
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
@@ -466,23 +466,21 @@ __global__ __launch_bounds__(256) void qr_panel_coop_kernel(
         tau_s = tau;
         scal_s = scal;
         beta_s = beta;
-        if (w == 0) {
-          // T(0:jj, jj) = -tau T(0:jj, 0:jj) z,  z_q = v_q^H v_jj
-          //             = scal conj(s_q) + conj(A(jj, q))
-          Ts[jj][jj] = tau;
-          for (int q2 = 0; q2 < jj; ++q2) {
-            C2 sq = tot[q2];
-            zs[q2] = cadd(cmul(scal, cconj(sq)), cconj(rowv[q2]));
-          }
-          for (int r = 0; r < jj; ++r) {
-            C2 sum = mk<T>(0, 0);
-            for (int q2 = r; q2 < jj; ++q2) sum = cadd(sum, cmul(Ts[r][q2], zs[q2]));
-            C2 t = cmul(tau, sum);
-            Ts[r][jj] = mk<T>(-t.x, -t.y);
-          }
-        }
       }
       __syncthreads();
+      if (w == 0) {
+        // T(0:jj, jj) = -tau T(0:jj, 0:jj) z,  z_q = v_q^H v_jj
+        //             = scal conj(s_q) + conj(A(jj, q))
+        if (tid < jj) zs[tid] = cadd(cmul(scal_s, cconj(tot[tid])), cconj(rowv[tid]));
+        if (tid == 0) Ts[jj][jj] = tau_s;
+        __syncthreads();
+        if (tid < jj) {
+          C2 sum = mk<T>(0, 0);
+          for (int q2 = tid; q2 < jj; ++q2) sum = cadd(sum, cmul(Ts[tid][q2], zs[q2]));
+          C2 t = cmul(tau_s, sum);
+          Ts[tid][jj] = mk<T>(-t.x, -t.y);
+        }
+      }
       const C2 tau = tau_s, scal = scal_s, ctau = cconj(tau_s);
       const C2 cscal = cconj(scal);
       // ---- update own rows
@@ -755,6 +753,9 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
                          dim3(256), 0, pool.stream, dd);
     }
     dim3 grid(maxt, (unsigned)n, splits);
+    double fl = 0;
+    for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
+    ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl);
     if (opA == OpN && opB == OpN)
       hipLaunchKernelGGL((gemm_kernel<T, OpN, OpN>), grid, dim3(256), 0, pool.stream, dd, splits);
     else if (opA == OpC && opB == OpN)
@@ -792,6 +793,7 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const int* dact, int n
   int* err = (int*)pool.push(zeros.data(), sizeof(int));
   void* args[] = {(void*)&dd, (void*)&dact, (void*)&nact, (void*)&j0, (void*)&gsize,
                   (void*)&scr, (void*)&bar, (void*)&err};
+  ProfScope ps(pool.stream, KC_QRPANEL, 0.0);
   ND_HIP(hipLaunchCooperativeKernel(kern, dim3(ngroups * gsize), dim3(256), args, 0, pool.stream));
 }
 

@@ -4,6 +4,7 @@
 #include <memory>
 
 #include "common.h"
+#include "prof.h"
 
 namespace nd {
 
@@ -73,6 +74,8 @@ struct Plan {
 
   bool factored = false;
   std::unique_ptr<HSSFactors> hss;
+  bool profiling = false;
+  Profiler prof;
   nudft2_info info{};
 
   ~Plan();

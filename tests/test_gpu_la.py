@@ -76,7 +76,8 @@ def test_gemm_batched_ragged(prec, opa, opb):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_geqrf_ormqr(prec):
     rng = np.random.default_rng(3 + prec)
-    shapes = [(100, 37), (37, 100), (64, 64), (5, 3), (1030, 546), (33, 1), (300, 97)]
+    shapes = [(100, 37), (37, 100), (64, 64), (5, 3), (1030, 546), (33, 1), (300, 97),
+              (3000, 70), (257, 300)]
     keep = []
     mn, ld, ptr, data = [], [], [], []
     for (m, n) in shapes:
@@ -197,7 +198,7 @@ def test_pchol_trace_rule():
 @pytest.mark.parametrize("prec", [0, 1])
 def test_trsv(prec):
     rng = np.random.default_rng(11)
-    sizes = [(1, 1), (50, 3), (300, 2), (7, 1)]
+    sizes = [(1, 1), (50, 3), (300, 2), (7, 1), (700, 2)]
     keep, data, dims, ld, ptr = [], [], [], [], []
     for (k, nr) in sizes:
         R = np.triu(crandn(rng, k, k)) + 4 * np.eye(k)
