@@ -73,23 +73,25 @@ nudft2_status nudft2_test_pchol(int32_t nb, const int32_t* w, const int32_t* rma
 nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims,
                                const int32_t* ld, const int64_t* ptrs);
 
-/* 1D HSS compression of G^x (dim 0) or G^y (dim 1) of a single-problem plan
- * at tolerance tol (no factorization needed), then y = H x with x: DEVICE n
- * complex128 in natural column order (0-based frequency l), y: DEVICE M
- * complex128 in the caller's point order.  ranks (HOST, 2*(L+1) ints, may be
+/* 1D HSS compression of G^x (dim 0) or G^y (dim 1) of every problem of the
+ * plan at tolerance tol (no factorization needed), then y = H x for problem
+ * `prob` with x: DEVICE n complex128 in natural column order (0-based
+ * frequency l), y: DEVICE M_prob complex128, the problem's points in the
+ * caller's order.  ranks (HOST, 2*(L+1) ints, may be
  * NULL) receives the largest row / column rank per level. */
 nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double tol,
-                                       const double* x, double* y, int32_t* ranks);
+                                       const double* x, double* y, int32_t* ranks,
+                                       int32_t prob);
 
 /* Build the recompressed HSS approximation of G (1D stage at eps/10,
- * face-splitting assembly, recompression at eps) of a single-problem plan in
- * the plan's precision, then y = H x (x: DEVICE N complex128 in natural
- * column order l^y + l^x ny, 0-based; y: DEVICE M complex128, caller's point
- * order).  stages: 0 = face-splitting generators only, 1 = after the exact
+ * face-splitting assembly, recompression at eps) of every problem of the plan
+ * in the plan's precision, then y = H x for problem `prob` (x: DEVICE N_prob
+ * complex128 in natural column order l^y + l^x ny, 0-based; y: DEVICE M_prob
+ * complex128, the problem's points in the caller's order).  stages: 0 = face-splitting generators only, 1 = after the exact
  * orthogonalisation stage, 2 = fully recompressed.  The ranks per level are
  * left in the plan's info. */
 nudft2_status nudft2_test_hss_matvec(nudft2_plan_t plan, const double* x, double* y,
-                                     int32_t stages);
+                                     int32_t stages, int32_t prob);
 
 #ifdef __cplusplus
 }

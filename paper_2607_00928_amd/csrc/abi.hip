@@ -396,11 +396,12 @@ nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims, co
 }
 
 nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double tol,
-                                       const double* x, double* y, int32_t* ranks) {
+                                       const double* x, double* y, int32_t* ranks,
+                                       int32_t prob) {
   return guard([&] {
     ND_CHECK(plan && x && y && (dim == 0 || dim == 1), NUDFT2_E_INVAL, "bad arguments");
     Plan* P = reinterpret_cast<Plan*>(plan);
-    ND_CHECK(P->probs.size() == 1, NUDFT2_E_INVAL, "single-problem plans only");
+    ND_CHECK(prob >= 0 && prob < (int)P->probs.size(), NUDFT2_E_INVAL, "problem index out of range");
     Ctx cx;
     cx.P = P;
     cx.s = P->stream;
@@ -408,10 +409,10 @@ nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double t
     std::vector<Tree1> t;
     build_1d(cx, dim, tol, t);
     if (ranks) {
-      int L = t[0].L;
+      int L = t[prob].L;
       for (int l = 0; l <= L; ++l) {
         int ru = 0, rv = 0;
-        for (auto& nd : t[0].lv[l]) {
+        for (auto& nd : t[prob].lv[l]) {
           ru = std::max(ru, nd.rU);
           rv = std::max(rv, nd.rV);
         }
@@ -419,17 +420,17 @@ nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double t
         ranks[2 * l + 1] = rv;
       }
     }
-    matvec_1d(cx, dim, t, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+    matvec_1d(cx, dim, t, prob, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
     free_1d(P, t);
   });
 }
 
 nudft2_status nudft2_test_hss_matvec(nudft2_plan_t plan, const double* x, double* y,
-                                     int32_t stages) {
+                                     int32_t stages, int32_t prob) {
   return guard([&] {
     ND_CHECK(plan && x && y, NUDFT2_E_INVAL, "bad arguments");
     Plan* P = reinterpret_cast<Plan*>(plan);
-    ND_CHECK(P->probs.size() == 1, NUDFT2_E_INVAL, "single-problem plans only");
+    ND_CHECK(prob >= 0 && prob < (int)P->probs.size(), NUDFT2_E_INVAL, "problem index out of range");
     Ctx cx;
     cx.P = P;
     cx.s = P->stream;
@@ -441,7 +442,7 @@ nudft2_status nudft2_test_hss_matvec(nudft2_plan_t plan, const double* x, double
       build_2d(cx, tx, ty, P->opts.eps, H, stages);
       free_1d(P, tx);
       free_1d(P, ty);
-      matvec_2d(cx, H, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+      matvec_2d(cx, H, prob, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
       ND_HIP(hipStreamSynchronize(cx.s));
       for (void* m : H.mem) P->arena.release(m);
       H.mem.clear();

@@ -5,6 +5,9 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
+#include <set>
+#include <unordered_map>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -58,15 +61,33 @@ __host__ __device__ inline C cconj(C a) { a.y = -a.y; return a; }
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // ----------------------------------------------------------------- memory
-// Every device buffer of a plan is registered here so that destroy (and
-// error paths) can release it; mem_cap is enforced on the running total.
+// Device memory of a plan: a sub-allocator over large slabs obtained from
+// hipMalloc once and returned only by release_all (plan destruction).
+// Released blocks go to a free list (best fit, coalescing within a slab), so
+// the many short-lived temporaries of a factorization never reach hipMalloc /
+// hipFree.  mem_cap bounds the bytes reserved in slabs.
+//
+// Debug switches (environment): NUDFT2_POISON=1 fills new blocks with NaN;
+// NUDFT2_GUARD=1 appends a patterned tail to every block that check() and
+// release() verify; NUDFT2_QUARANTINE=1 never reuses released blocks
+// (they are filled with NaN, and check() reports later writes into them).
 struct Arena {
-  std::vector<std::pair<void*, size_t>> blocks;
-  size_t bytes = 0, peak = 0, cap = 0;
+  std::vector<std::pair<void*, size_t>> slabs;
+  std::set<uintptr_t> slab_start;
+  std::map<uintptr_t, size_t> free_by_addr;
+  std::multimap<size_t, uintptr_t> free_by_size;
+  std::unordered_map<uintptr_t, std::pair<size_t, size_t>> live;   // block -> (size, span)
+  size_t bytes = 0, peak = 0, cap = 0, reserved = 0;
   void* alloc(size_t n);
   void release(void* p);
   void release_all();
+  size_t block_size(const void* p) const;
+  void check(const char* where);
   ~Arena() { release_all(); }
+
+ private:
+  void add_free(uintptr_t a, size_t n);
+  void take_free(std::map<uintptr_t, size_t>::iterator it);
 };
 
 }  // namespace nd

@@ -11,6 +11,7 @@
 //   and interaction (B) generators of non-leaf nodes.
 #include "device_util.h"
 #include "gen.h"
+#include "hazard.h"
 
 namespace nd {
 
@@ -253,6 +254,13 @@ void gen_G1(hipStream_t s, const double* xs, int64_t M, int n, double2* G, int64
 template <typename T>
 void gen_leafD(DescPool& pool, const std::vector<LeafDesc<T>>& d, const double* pts2d) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    for (size_t i = 0; i < d.size(); ++i)
+      v.push_back(region(d[i].out + (int64_t)d[i].coff * d[i].ld, sizeof(cplx<T>), d[i].m,
+                         d[i].dx * d[i].dy, d[i].ld, true, (int)i));
+    check_hazards("gen_leafD", v);
+  }
   int64_t mx = 0;
   for (auto& q : d) mx = std::max<int64_t>(mx, (int64_t)q.m * q.dx * q.dy);
   auto* dd = (LeafDesc<T>*)pool.push(d.data(), sizeof(LeafDesc<T>) * d.size());
@@ -265,6 +273,15 @@ template <typename T>
 void gen_leafU(DescPool& pool, const std::vector<LeafDesc<T>>& d, const double* pts2d,
                const int64_t* posx, const int64_t* posy) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    for (size_t i = 0; i < d.size(); ++i) {
+      const LeafDesc<T>& q = d[i];
+      v.push_back(region(q.out, sizeof(cplx<T>), q.m, q.dx * q.ry + q.rx * q.dy + q.rx * q.ry,
+                         q.ld, true, (int)i));
+    }
+    check_hazards("gen_leafU", v);
+  }
   int64_t mx = 0;
   for (auto& q : d)
     mx = std::max<int64_t>(mx, (int64_t)q.m * (q.dx * q.ry + q.rx * q.dy + q.rx * q.ry));
@@ -277,6 +294,15 @@ void gen_leafU(DescPool& pool, const std::vector<LeafDesc<T>>& d, const double* 
 template <typename T>
 void gen_leafV(DescPool& pool, const std::vector<LeafVDesc<T>>& d) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    for (size_t i = 0; i < d.size(); ++i) {
+      const LeafVDesc<T>& q = d[i];
+      v.push_back(region(q.out, sizeof(cplx<T>), q.dx * q.dy,
+                         q.dx * q.ry + q.rx * q.dy + q.rx * q.ry, q.ld, true, (int)i));
+    }
+    check_hazards("gen_leafV", v);
+  }
   int64_t mx = 0;
   for (auto& q : d)
     mx = std::max<int64_t>(mx, (int64_t)q.dx * q.dy * (q.dx * q.ry + q.rx * q.dy + q.rx * q.ry));
@@ -289,6 +315,12 @@ void gen_leafV(DescPool& pool, const std::vector<LeafVDesc<T>>& d) {
 template <typename T>
 void gen_asm(DescPool& pool, const std::vector<AsmDesc<T>>& d) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    for (size_t i = 0; i < d.size(); ++i)
+      v.push_back(region(d[i].out, sizeof(cplx<T>), d[i].rows, d[i].cols, d[i].ld, true, (int)i));
+    check_hazards("gen_asm", v);
+  }
   int64_t mx = 0;
   for (auto& q : d) mx = std::max<int64_t>(mx, (int64_t)q.rows * q.cols);
   if (mx == 0) return;
@@ -300,6 +332,12 @@ void gen_asm(DescPool& pool, const std::vector<AsmDesc<T>>& d) {
 
 void zero_rc(DescPool& pool, const std::vector<ZeroRCDesc>& d, bool rows_too) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    for (size_t i = 0; i < d.size(); ++i)
+      v.push_back(region(d[i].K, 16, d[i].n, d[i].n, d[i].ld, true, (int)i));
+    check_hazards("zero_rc", v);
+  }
   int64_t mx = 0;
   for (auto& q : d) mx = std::max<int64_t>(mx, (int64_t)q.n * q.w);
   if (mx == 0) return;
@@ -315,6 +353,12 @@ void zero_rc(DescPool& pool, const std::vector<ZeroRCDesc>& d, bool rows_too) {
 
 void gather_cols(DescPool& pool, const std::vector<GatherDesc>& d) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    for (size_t i = 0; i < d.size(); ++i)
+      v.push_back(region(d[i].out, 16, d[i].m, d[i].r, d[i].ldo, true, (int)i));
+    check_hazards("gather_cols", v);
+  }
   int64_t mx = 0;
   for (auto& q : d) mx = std::max<int64_t>(mx, (int64_t)q.m * q.r);
   if (mx == 0) return;

@@ -175,16 +175,17 @@ void host_binning(const double* points, int64_t M, int nx, int ny, int leaf,
 void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out);
 void free_1d(Plan* P, std::vector<Tree1>& t);
 // y = H x for a 1D HSS (test hook): x (n, natural columns), y (M, caller order).
-void matvec_1d(Ctx& cx, int dim, const std::vector<Tree1>& t, const double2* x, double2* y);
+void matvec_1d(Ctx& cx, int dim, const std::vector<Tree1>& t, int prob, const double2* x,
+               double2* y);
 
 // Face-splitting assembly (Theorem 3.3) + recompression (Section 2.3).
 template <typename T>
 void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& ty, double eps,
               HSS2<T>& H, int stages = 2);
-// y = H x for problem 0 of a recompressed HSS (test hook); x natural column
-// order, y caller's point order (FP64 in and out).
+// y = H x for problem `prob` of a recompressed HSS (test hook); x natural
+// column order, y caller's point order (FP64 in and out, problem-local).
 template <typename T>
-void matvec_2d(Ctx& cx, HSS2<T>& H, const double2* x, double2* y);
+void matvec_2d(Ctx& cx, HSS2<T>& H, int prob, const double2* x, double2* y);
 
 // URV factorization of the recompressed HSS (bottom-up, root QR).
 template <typename T>

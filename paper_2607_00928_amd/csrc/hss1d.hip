@@ -459,11 +459,12 @@ void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out) {
   cx.release_tmp();
 }
 
-void matvec_1d(Ctx& cx, int dim, const std::vector<Tree1>& trees, const double2* x, double2* y) {
+void matvec_1d(Ctx& cx, int dim, const std::vector<Tree1>& trees, int prob, const double2* x,
+               double2* y) {
   TmpScope scope_(cx);
   Plan* P = cx.P;
-  const Tree1& t = trees[0];
-  const Problem& q = P->probs[0];
+  const Tree1& t = trees[prob];
+  const Problem& q = P->probs[prob];
   ND_CHECK(t.L >= 1, NUDFT2_E_INVAL, "1D tree has a single node");
   // x-hat per node at every level: xh(l, a) = Vf^H x(K_a)
   std::vector<std::vector<double2*>> xh(t.L + 1), yh(t.L + 1);

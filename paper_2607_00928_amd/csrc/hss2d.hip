@@ -21,6 +21,9 @@
 // U <- U P, V <- V Q and R_child <- R_child P, W_child <- W_child Q follow the
 // paper.
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <tuple>
 
@@ -62,6 +65,7 @@ struct Builder {
       for (int z = 0; z < (1 << (2 * l)); ++z) f(p, z);
     }
   }
+
   static int sib_child(int c, int s) { return s < c ? s : s + 1; }
   static int sib_slot(int c, int other) { return other < c ? other : other - 1; }
 };
@@ -265,6 +269,7 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
     gen_asm<T>(cx.pool, ad);
     ND_HIP(hipStreamSynchronize(cx.s));
     cx.pool.sync_reset();
+    P->arena.check("face-split assembly");
   }
 
   // ------------------------------------------------ stage 1 (bottom-up)
@@ -318,6 +323,7 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
       bd.own(p, pb.L, Builder<T>::K_U, cq, old);
       bd.own(p, pb.L, Builder<T>::K_V, nullptr, old);
       bd.release(old);
+      P->arena.check("stage 1, leaves");
     }
     // non-leaf nodes, from the leaves' parents to the root
     for (int h = 1; h <= Lmax; ++h) {
@@ -450,6 +456,7 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
         cx.release_tmp();
         cx.pool.sync_reset();
         bd.release(old);
+        P->arena.check("stage 1, non-leaf level");
       }
     }
     for (int p = 0; p < np; ++p) {
@@ -764,6 +771,7 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
       cx.release_tmp();
       cx.pool.sync_reset();
       bd.release(old);
+      P->arena.check("stage 2 level");
     }
   }
   // hand the remaining chunks to the HSS object
@@ -784,13 +792,13 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
 }
 
 template <typename T>
-void matvec_2d(Ctx& cx, HSS2<T>& H, const double2* x, double2* y) {
+void matvec_2d(Ctx& cx, HSS2<T>& H, int prob, const double2* x, double2* y) {
   TmpScope scope_(cx);
-  // y = H x for the recompressed HSS of problem 0 (test hook); x natural
+  // y = H x for the recompressed HSS of one problem (test hook); x natural
   // column order, y caller's point order, FP64 in and out.
   Plan* P = cx.P;
-  const Problem& q = P->probs[0];
-  Prob2<T>& pb = H.probs[0];
+  const Problem& q = P->probs[prob];
+  Prob2<T>& pb = H.probs[prob];
   const int L = pb.L;
   ND_CHECK(L >= 1, NUDFT2_E_INVAL, "single-node tree");
   // x to quadtree order in working precision (host permutation, tiny sizes)
@@ -899,7 +907,7 @@ template void build_2d<float>(Ctx&, const std::vector<Tree1>&, const std::vector
                               HSS2<float>&, int);
 template void build_2d<double>(Ctx&, const std::vector<Tree1>&, const std::vector<Tree1>&, double,
                                HSS2<double>&, int);
-template void matvec_2d<float>(Ctx&, HSS2<float>&, const double2*, double2*);
-template void matvec_2d<double>(Ctx&, HSS2<double>&, const double2*, double2*);
+template void matvec_2d<float>(Ctx&, HSS2<float>&, int, const double2*, double2*);
+template void matvec_2d<double>(Ctx&, HSS2<double>&, int, const double2*, double2*);
 
 }  // namespace nd

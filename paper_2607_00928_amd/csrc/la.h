@@ -18,10 +18,12 @@ enum Op { OpN = 0, OpC = 1 };   // none / conjugate transpose
 struct DescPool {
   char* host = nullptr;
   char* dev = nullptr;
+  int* flag = nullptr;   // device error flag (set by a cooperative panel whose barrier timed out)
   size_t cap = 0, used = 0;
   hipStream_t stream = nullptr;
   void init(size_t bytes, hipStream_t s);
   void destroy();
+  void check_flag();   // synchronises; E_INTERNAL if the flag is set
   // copies n bytes to the device, returns the device address
   void* push(const void* src, size_t n);
   void sync_reset();

@@ -3,10 +3,13 @@
 // FP32 with FP32 accumulation): a complex product is four real MFMAs,
 // Cr += Ar Br - Ai Bi and Ci += Ar Bi + Ai Br.
 #include <algorithm>
+#include <cstdlib>
+#include <cstdio>
 #include <cstring>
 
 #include "device_util.h"
 #include "la.h"
+#include "hazard.h"
 #include "prof.h"
 
 namespace nd {
@@ -17,14 +20,24 @@ void DescPool::init(size_t bytes, hipStream_t s) {
   cap = bytes;
   stream = s;
   ND_HIP(hipHostMalloc((void**)&host, cap, hipHostMallocDefault));
-  ND_HIP(hipMalloc((void**)&dev, cap));
+  ND_HIP(hipMalloc((void**)&dev, cap + 256));
+  flag = (int*)(dev + cap);
+  ND_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
   used = 0;
+}
+
+void DescPool::check_flag() {
+  int h = 0;
+  ND_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+  ND_HIP(hipStreamSynchronize(stream));
+  ND_CHECK(h == 0, NUDFT2_E_INTERNAL, "a cooperative QR panel timed out in its group barrier");
 }
 
 void DescPool::destroy() {
   if (host) (void)hipHostFree(host);
   if (dev) (void)hipFree(dev);
   host = dev = nullptr;
+  flag = nullptr;
   cap = used = 0;
 }
 
@@ -184,149 +197,11 @@ __global__ void gemm_prescale_kernel(const GemmDesc<T>* __restrict__ descs) {
 }
 
 // -------------------------------------------------------------- QR panel
-// One workgroup factors columns [j0, j0 + jb) of one problem: Householder
-// vectors (LAPACK larfg convention: H = I - tau v v^H, v_0 = 1, H^H x = beta
-// e_1 with real beta), the panel's compact-WY factor T (Q_panel = I - V T V^H)
-// and the explicit V / R split described in la.h.
-template <typename T>
-__global__ __launch_bounds__(256) void qr_panel_kernel(const QRDesc<T>* __restrict__ descs,
-                                                       const int* __restrict__ active, int j0) {
-  using C2 = cplx<T>;
-  __shared__ C2 red[4][QR_NB + 1];
-  __shared__ T redr[4];
-  __shared__ C2 wv[QR_NB];
-  __shared__ C2 Ts[QR_NB][QR_NB + 1];
-  __shared__ C2 tau_s, scal_s;
-  __shared__ T beta_s;
-  const QRDesc<T> d = descs[active[blockIdx.x]];
-  const int kmin = min(d.m, d.n);
-  const int jb = min(QR_NB, kmin - j0);
-  const int mr = d.m - j0;
-  C2* Ap = d.A + j0 + (int64_t)j0 * d.lda;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-  for (int e = tid; e < QR_NB * QR_NB; e += 256) Ts[e % QR_NB][e / QR_NB] = mk<T>(0, 0);
-
-  for (int jj = 0; jj < jb; ++jj) {
-    // pass 1: sigma^2 = sum_{i > jj} |a_i|^2
-    T s = 0;
-    for (int i = jj + 1 + tid; i < mr; i += 256) {
-      C2 v = Ap[i + (int64_t)jj * d.lda];
-      s += v.x * v.x + v.y * v.y;
-    }
-    s = warp_sum(s);
-    if (lane == 0) redr[wave] = s;
-    __syncthreads();
-    if (tid == 0) {
-      T sig = redr[0] + redr[1] + redr[2] + redr[3];
-      C2 alpha = Ap[jj + (int64_t)jj * d.lda];
-      C2 tau, scal;
-      T beta;
-      if (sig == T(0) && alpha.y == T(0)) {
-        tau = mk<T>(0, 0);
-        scal = mk<T>(0, 0);
-        beta = alpha.x;
-      } else {
-        T nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig);
-        beta = alpha.x >= T(0) ? -nrm : nrm;
-        tau = mk<T>((beta - alpha.x) / beta, -alpha.y / beta);
-        // scal = 1 / (alpha - beta)
-        T dr = alpha.x - beta, di = alpha.y;
-        T den = dr * dr + di * di;
-        scal = mk<T>(dr / den, -di / den);
-      }
-      tau_s = tau;
-      scal_s = scal;
-      beta_s = beta;
-      Ts[jj][jj] = tau;
-    }
-    __syncthreads();
-    const C2 tau = tau_s, scal = scal_s;
-    // scale the vector below the diagonal
-    for (int i = jj + 1 + tid; i < mr; i += 256) {
-      C2* p = Ap + i + (int64_t)jj * d.lda;
-      *p = cmul(*p, scal);
-    }
-    if (tid == 0) Ap[jj + (int64_t)jj * d.lda] = mk<T>(beta_s, 0);
-    __syncthreads();
-    // pass 2: u_c = sum_{i >= jj} conj(v_i) A(i, c) for all c != jj
-    C2 acc[QR_NB];
-#pragma unroll
-    for (int c = 0; c < QR_NB; ++c) acc[c] = mk<T>(0, 0);
-    for (int i = jj + tid; i < mr; i += 256) {
-      C2 vi = (i == jj) ? mk<T>(1, 0) : Ap[i + (int64_t)jj * d.lda];
-#pragma unroll
-      for (int c = 0; c < QR_NB; ++c) {
-        if (c < jb && c != jj) {
-          C2 a = Ap[i + (int64_t)c * d.lda];
-          acc[c] = cadd(acc[c], cmulc(vi, a));
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < QR_NB; ++c) {
-      acc[c].x = warp_sum(acc[c].x);
-      acc[c].y = warp_sum(acc[c].y);
-      if (lane == 0) red[wave][c] = acc[c];
-    }
-    __syncthreads();
-    if (tid < QR_NB) {
-      C2 t = red[0][tid];
-      t = cadd(t, red[1][tid]);
-      t = cadd(t, red[2][tid]);
-      t = cadd(t, red[3][tid]);
-      wv[tid] = t;
-    }
-    __syncthreads();
-    // T column: T(0:jj, jj) = -tau T(0:jj, 0:jj) z, z_i = conj(u_i)
-    if (tid == 0) {
-      for (int r = 0; r < jj; ++r) {
-        C2 sum = mk<T>(0, 0);
-        for (int q = r; q < jj; ++q) sum = cadd(sum, cmul(Ts[r][q], cconj(wv[q])));
-        C2 t = cmul(tau, sum);
-        Ts[r][jj] = mk<T>(-t.x, -t.y);
-      }
-    }
-    // pass 3: A(i, c) -= conj(tau) v_i u_c for c > jj
-    const C2 ctau = cconj(tau);
-    for (int i = jj + tid; i < mr; i += 256) {
-      C2 vi = (i == jj) ? mk<T>(1, 0) : Ap[i + (int64_t)jj * d.lda];
-      C2 f = cmul(ctau, vi);
-      for (int c = jj + 1; c < jb; ++c) {
-        C2* p = Ap + i + (int64_t)c * d.lda;
-        *p = csub(*p, cmul(f, wv[c]));
-      }
-    }
-    __syncthreads();
-  }
-  // write T, the R block of the panel, the R rows above the panel, and make V explicit
-  const int blk = j0 / QR_NB;
-  C2* Tb = d.Tb + (int64_t)blk * QR_NB * QR_NB;
-  for (int e = tid; e < QR_NB * QR_NB; e += 256) {
-    int r = e % QR_NB, c = e / QR_NB;
-    Tb[r + c * QR_NB] = (r < jb && c < jb) ? Ts[r][c] : mk<T>(0, 0);
-  }
-  for (int c = 0; c < jb; ++c) {
-    int gc = j0 + c;
-    for (int r = tid; r < j0 + jb; r += 256) {
-      C2* pa = d.A + r + (int64_t)gc * d.lda;
-      C2* pr = d.R + r + (int64_t)gc * d.ldr;
-      if (r < j0) {
-        *pr = *pa;
-        *pa = mk<T>(0, 0);
-      } else {
-        int rr = r - j0;
-        if (rr <= c) {
-          *pr = *pa;
-          *pa = (rr == c) ? mk<T>(1, 0) : mk<T>(0, 0);
-        } else {
-          *pr = mk<T>(0, 0);
-        }
-      }
-    }
-  }
-}
-
+// Householder vectors follow the LAPACK larfg convention (H = I - tau v v^H,
+// v_0 = 1, H^H x = beta e_1 with real beta); each panel also produces its
+// compact-WY factor T (Q_panel = I - V T V^H) and the explicit V / R split
+// described in la.h.
+//
 // Cooperative panel factorization: a group of gsize workgroups factors one
 // problem's panel; every thread keeps RPT rows of the panel in registers.
 // Per column one group barrier: the partial sums (sigma^2 and the raw dots
@@ -525,12 +400,17 @@ __global__ __launch_bounds__(256) void qr_panel_coop_kernel(
       }
     }
     if (w == 0) {
-      for (int c = 0; c < jb; ++c)
+      // rows above the panel move from A to R; R below the panel's diagonal
+      // block is zero (nothing else writes it)
+      for (int c = 0; c < jb; ++c) {
         for (int r = tid; r < j0; r += 256) {
           C2* pa = d.A + r + (int64_t)(j0 + c) * d.lda;
           d.R[r + (int64_t)(j0 + c) * d.ldr] = *pa;
           *pa = mk<T>(0, 0);
         }
+        for (int r = j0 + jb + tid; r < kmin; r += 256)
+          d.R[r + (int64_t)(j0 + c) * d.ldr] = mk<T>(0, 0);
+      }
       __syncthreads();
       const int blk = j0 / QR_NB;
       C2* Tb = d.Tb + (int64_t)blk * QR_NB * QR_NB;
@@ -724,6 +604,21 @@ __global__ void fill_kernel(const FillDesc<T>* __restrict__ descs) {
 template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    const int64_t es = sizeof(cplx<T>);
+    for (size_t i = 0; i < d.size(); ++i) {
+      const GemmDesc<T>& g = d[i];
+      if (g.m <= 0 || g.n <= 0) continue;
+      v.push_back(region(g.C, es, g.m, g.n, g.ldc, true, (int)i));
+      if (g.k <= 0) continue;
+      if (opA == OpN) v.push_back(region(g.A, es, g.m, g.k, g.lda, false, (int)i));
+      else v.push_back(region(g.A, es, g.k, g.m, g.lda, false, (int)i));
+      if (opB == OpN) v.push_back(region(g.B, es, g.k, g.n, g.ldb, false, (int)i));
+      else v.push_back(region(g.B, es, g.n, g.k, g.ldb, false, (int)i));
+    }
+    check_hazards(sizeof(T) == 4 ? "gemm<float>" : "gemm<double>", v);
+  }
   size_t chunk = 32768;
   for (size_t s0 = 0; s0 < d.size(); s0 += chunk) {
     size_t n = std::min(chunk, d.size() - s0);
@@ -790,11 +685,13 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const int* dact, int n
   std::vector<char> zeros((size_t)ngroups * (QSCR * sizeof(cplx<T>) + sizeof(unsigned)) + 64, 0);
   cplx<T>* scr = (cplx<T>*)pool.push(zeros.data(), (size_t)ngroups * QSCR * sizeof(cplx<T>));
   unsigned* bar = (unsigned*)pool.push(zeros.data(), (size_t)ngroups * sizeof(unsigned));
-  int* err = (int*)pool.push(zeros.data(), sizeof(int));
+  int* err = pool.flag;
   void* args[] = {(void*)&dd, (void*)&dact, (void*)&nact, (void*)&j0, (void*)&gsize,
                   (void*)&scr, (void*)&bar, (void*)&err};
-  ProfScope ps(pool.stream, KC_QRPANEL, 0.0);
-  ND_HIP(hipLaunchCooperativeKernel(kern, dim3(ngroups * gsize), dim3(256), args, 0, pool.stream));
+  {
+    ProfScope ps(pool.stream, KC_QRPANEL, 0.0);
+    ND_HIP(hipLaunchCooperativeKernel(kern, dim3(ngroups * gsize), dim3(256), args, 0, pool.stream));
+  }
 }
 
 template <typename T>
@@ -807,6 +704,19 @@ size_t qr_workspace(const std::vector<QRDesc<T>>& d) {
 template <typename T>
 void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& d, void* ws) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    const int64_t es = sizeof(cplx<T>);
+    for (size_t i = 0; i < d.size(); ++i) {
+      const QRDesc<T>& q = d[i];
+      int kmin = qr_kmin(q.m, q.n);
+      v.push_back(region(q.A, es, q.m, q.n, q.lda, true, (int)i));
+      v.push_back(region(q.R, es, kmin, q.n, q.ldr, true, (int)i));
+      v.push_back(region(q.Tb, es, QR_NB * QR_NB, qr_nblocks(q.m, q.n), QR_NB * QR_NB, true,
+                         (int)i));
+    }
+    check_hazards("geqrf", v);
+  }
   const int nb = (int)d.size();
   auto* dd = (QRDesc<T>*)pool.push(d.data(), sizeof(QRDesc<T>) * nb);
   int kmax = 0;
@@ -865,6 +775,19 @@ size_t orm_workspace(const std::vector<OrmDesc<T>>& d) {
 template <typename T>
 void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans, void* ws) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    const int64_t es = sizeof(cplx<T>);
+    for (size_t i = 0; i < d.size(); ++i) {
+      const OrmDesc<T>& q = d[i];
+      if (q.nc <= 0 || q.k <= 0) continue;
+      v.push_back(region(q.C, es, q.m, q.nc, q.ldc, true, (int)i));
+      v.push_back(region(q.V, es, q.m, q.k, q.ldv, false, (int)i));
+      int nbk = (q.k + QR_NB - 1) / QR_NB;
+      v.push_back(region(q.Tb, es, QR_NB * QR_NB, nbk, QR_NB * QR_NB, false, (int)i));
+    }
+    check_hazards("ormqr", v);
+  }
   const int nb = (int)d.size();
   std::vector<cplx<T>*> W(nb), W2(nb);
   {
@@ -904,6 +827,18 @@ void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans,
 
 void pchol_batched(DescPool& pool, const std::vector<PcholDesc>& d) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    for (size_t i = 0; i < d.size(); ++i) {
+      const PcholDesc& q = d[i];
+      v.push_back(region(q.K, 16, q.w, q.w, q.ldk, true, (int)i));
+      v.push_back(region(q.L, 16, q.w, q.rmax, q.ldl, true, (int)i));
+      v.push_back(region(q.d, 8, q.w, 1, q.w, true, (int)i));
+      v.push_back(region(q.piv, 4, q.rmax, 1, q.rmax, true, (int)i));
+      v.push_back(region(q.rank, 4, 1, 1, 1, true, (int)i));
+    }
+    check_hazards("pchol", v);
+  }
   const int nb = (int)d.size();
   auto* dd = (PcholDesc*)pool.push(d.data(), sizeof(PcholDesc) * nb);
   std::vector<int> ones(nb, 1);
@@ -959,6 +894,17 @@ static void trsv_small(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
 template <typename T>
 void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
   constexpr int BS = 128;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    const int64_t es = sizeof(cplx<T>);
+    for (size_t i = 0; i < d.size(); ++i) {
+      const TrsDesc<T>& q = d[i];
+      if (q.k <= 0 || q.nrhs <= 0) continue;
+      v.push_back(region(q.B, es, q.k, q.nrhs, q.ldb, true, (int)i));
+      v.push_back(region(q.R, es, q.k, q.k, q.ldr, false, (int)i));
+    }
+    check_hazards("trsv", v);
+  }
   std::vector<TrsDesc<T>> small, big;
   for (auto& q : d) {
     if (q.k <= 0 || q.nrhs <= 0) continue;
@@ -991,6 +937,17 @@ void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
 template <typename TD, typename TS>
 void copy_batched(DescPool& pool, const std::vector<CopyDesc<TD, TS>>& d) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    for (size_t i = 0; i < d.size(); ++i) {
+      const CopyDesc<TD, TS>& q = d[i];
+      if (q.m <= 0 || q.n <= 0) continue;
+      v.push_back(region(q.S, sizeof(cplx<TS>), q.m, q.n, q.lds, false, (int)i));
+      if (q.conj_trans) v.push_back(region(q.D, sizeof(cplx<TD>), q.n, q.m, q.ldd, true, (int)i));
+      else v.push_back(region(q.D, sizeof(cplx<TD>), q.m, q.n, q.ldd, true, (int)i));
+    }
+    check_hazards("copy", v);
+  }
   auto* dd = (CopyDesc<TD, TS>*)pool.push(d.data(), sizeof(CopyDesc<TD, TS>) * d.size());
   hipLaunchKernelGGL((copy_kernel<TD, TS>), dim3(64, (unsigned)d.size()), dim3(256), 0,
                      pool.stream, dd);
@@ -1000,6 +957,12 @@ void copy_batched(DescPool& pool, const std::vector<CopyDesc<TD, TS>>& d) {
 template <typename T>
 void fill_batched(DescPool& pool, const std::vector<FillDesc<T>>& d) {
   if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    for (size_t i = 0; i < d.size(); ++i)
+      v.push_back(region(d[i].D, sizeof(cplx<T>), d[i].m, d[i].n, d[i].ld, true, (int)i));
+    check_hazards("fill", v);
+  }
   auto* dd = (FillDesc<T>*)pool.push(d.data(), sizeof(FillDesc<T>) * d.size());
   hipLaunchKernelGGL((fill_kernel<T>), dim3(64, (unsigned)d.size()), dim3(256), 0,
                      pool.stream, dd);

@@ -10,6 +10,8 @@
 // box so that every quadtree node owns a contiguous range of rows, and the
 // columns of every node are contiguous in the "quadtree column order"
 // (children concatenated in (p, q) order, each leaf kx-major).
+#include <cstdio>
+#include <cstdlib>
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -19,39 +21,165 @@
 
 namespace nd {
 
+namespace {
+constexpr size_t GUARD = 4096;
+constexpr unsigned char GUARD_BYTE = 0xA5;
+constexpr size_t SLAB = size_t(1) << 30;
+bool env_on(const char* name) {
+  const char* e = std::getenv(name);
+  return e && e[0] == '1';
+}
+bool guard_on() {
+  static const bool on = env_on("NUDFT2_GUARD");
+  return on;
+}
+bool poison_on() {
+  static const bool on = env_on("NUDFT2_POISON");
+  return on;
+}
+bool quarantine_on() {
+  static const bool on = env_on("NUDFT2_QUARANTINE");
+  return on;
+}
+// first overwritten guard byte after n bytes of the block, or -1
+int64_t guard_bad(const void* p, size_t n) {
+  std::vector<unsigned char> h(GUARD);
+  ND_HIP(hipDeviceSynchronize());
+  ND_HIP(hipMemcpy(h.data(), (const char*)p + n, GUARD, hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < GUARD; ++i)
+    if (h[i] != GUARD_BYTE) return (int64_t)i;
+  return -1;
+}
+std::vector<std::pair<void*, size_t>> g_quarantine;
+}  // namespace
+
+void Arena::take_free(std::map<uintptr_t, size_t>::iterator it) {
+  auto range = free_by_size.equal_range(it->second);
+  for (auto j = range.first; j != range.second; ++j)
+    if (j->second == it->first) {
+      free_by_size.erase(j);
+      break;
+    }
+  free_by_addr.erase(it);
+}
+
+void Arena::add_free(uintptr_t a, size_t n) {
+  // coalesce with the neighbours inside the same slab
+  auto next = free_by_addr.find(a + n);
+  if (next != free_by_addr.end() && !slab_start.count(a + n)) {
+    n += next->second;
+    take_free(next);
+  }
+  auto it = free_by_addr.lower_bound(a);
+  if (it != free_by_addr.begin() && !slab_start.count(a)) {
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == a) {
+      a = prev->first;
+      n += prev->second;
+      take_free(prev);
+    }
+  }
+  free_by_addr[a] = n;
+  free_by_size.insert({n, a});
+}
+
 void* Arena::alloc(size_t n) {
   if (n == 0) n = 1;
   n = (n + 255) & ~size_t(255);
-  if (cap && bytes + n > cap)
-    throw Error(NUDFT2_E_NOMEM, "plan memory cap exceeded");
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, n);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error(NUDFT2_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  const size_t span = n + (guard_on() ? GUARD : 0);
+  auto fit = free_by_size.lower_bound(span);
+  uintptr_t a = 0;
+  if (fit != free_by_size.end()) {
+    a = fit->second;
+    size_t have = fit->first;
+    take_free(free_by_addr.find(a));
+    if (have > span) add_free(a + span, have - span);
+  } else {
+    size_t want = std::max(span, SLAB);
+    if (cap && reserved + want > cap) want = span;
+    if (cap && reserved + want > cap)
+      throw Error(NUDFT2_E_NOMEM, "plan memory cap exceeded");
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess && want > span) {
+      (void)hipGetLastError();
+      want = span;
+      e = hipMalloc(&p, want);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(NUDFT2_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    slabs.push_back({p, want});
+    slab_start.insert((uintptr_t)p);
+    reserved += want;
+    a = (uintptr_t)p;
+    if (want > span) add_free(a + span, want - span);
   }
-  blocks.push_back({p, n});
+  void* p = (void*)a;
+  if (poison_on()) ND_HIP(hipMemset(p, 0xFF, n));   // debug: NaN everywhere until written
+  if (guard_on()) ND_HIP(hipMemset((char*)p + n, GUARD_BYTE, GUARD));
+  live[a] = {n, span};
   bytes += n;
   peak = std::max(peak, bytes);
   return p;
 }
 
+size_t Arena::block_size(const void* p) const {
+  auto it = live.find((uintptr_t)p);
+  return it == live.end() ? 0 : it->second.first;
+}
+
 void Arena::release(void* p) {
   if (!p) return;
-  for (size_t i = 0; i < blocks.size(); ++i)
-    if (blocks[i].first == p) {
-      (void)hipFree(p);
-      bytes -= blocks[i].second;
-      blocks[i] = blocks.back();
-      blocks.pop_back();
-      return;
+  auto it = live.find((uintptr_t)p);
+  if (it == live.end()) return;
+  const size_t n = it->second.first, span = it->second.second;
+  if (guard_on() && guard_bad(p, n) >= 0)
+    std::fprintf(stderr, "nudft2: write past the end of a released block of %zu bytes\n", n);
+  live.erase(it);
+  bytes -= n;
+  if (quarantine_on()) {
+    ND_HIP(hipDeviceSynchronize());
+    ND_HIP(hipMemset(p, 0xFF, n));
+    g_quarantine.push_back({p, n});
+    return;
+  }
+  add_free((uintptr_t)p, span);
+}
+
+void Arena::check(const char* where) {
+  if (quarantine_on()) {
+    ND_HIP(hipDeviceSynchronize());
+    for (auto& q : g_quarantine) {
+      std::vector<unsigned char> h(q.second);
+      ND_HIP(hipMemcpy(h.data(), q.first, q.second, hipMemcpyDeviceToHost));
+      size_t bad = 0;
+      for (unsigned char c : h) bad += c != 0xFF;
+      if (bad)
+        throw Error(NUDFT2_E_INTERNAL, "write into a released block (" + std::to_string(q.second) +
+                                           " bytes) detected at " + where);
     }
+  }
+  if (!guard_on()) return;
+  for (auto& b : live) {
+    int64_t off = guard_bad((const void*)b.first, b.second.first);
+    if (off >= 0)
+      throw Error(NUDFT2_E_INTERNAL, std::string("write past the end of a device block (") +
+                                         std::to_string(b.second.first) + " bytes, guard offset " +
+                                         std::to_string(off) + ") detected at " + where);
+  }
 }
 
 void Arena::release_all() {
-  for (auto& b : blocks) (void)hipFree(b.first);
-  blocks.clear();
+  for (auto& s : slabs) (void)hipFree(s.first);
+  slabs.clear();
+  slab_start.clear();
+  free_by_addr.clear();
+  free_by_size.clear();
+  live.clear();
   bytes = 0;
+  reserved = 0;
 }
 
 Plan::~Plan() {

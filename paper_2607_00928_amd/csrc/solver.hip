@@ -155,7 +155,7 @@ void factor_t(Plan* P) {
     hipLaunchKernelGGL(idft_matrix_kernel, dim3(grid_for((int64_t)q.ny * q.ny)), dim3(256), 0,
                        cx.s, pb.Fy.p, q.ny);
   }
-  ND_HIP(hipStreamSynchronize(cx.s));
+  cx.pool.check_flag();
   double t3 = now_ms();
   P->info.t_compress_ms = t1 - t0;
   P->info.t_recompress_ms = t2 - t1;   // face-split assembly + recompression

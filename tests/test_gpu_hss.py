@@ -34,7 +34,7 @@ def test_hss1d_matvec(nx, ny, mx, my, delta, seed, tol):
         ranks = np.zeros(2 * 8, np.int32)
         st = lib.nudft2_test_hss1d_matvec(plan._handle, dim, tol, C.c_void_p(xt.data_ptr()),
                                           C.c_void_p(yt.data_ptr()),
-                                          ranks.ctypes.data_as(C.POINTER(C.c_int32)))
+                                          ranks.ctypes.data_as(C.POINTER(C.c_int32)), 0)
         assert st == 0, lib.nudft2_last_error()
         G = onu.kernel_1d(pr.points[:, dim], n)
         ref = G @ x
@@ -60,7 +60,7 @@ def test_hss2d_matvec(nx, ny, mx, my, delta, seed, prec, eps, stages):
     xt = torch.from_numpy(x).to(DEV)
     yt = torch.empty(pr.M, dtype=torch.complex128, device=DEV)
     st = lib.nudft2_test_hss_matvec(plan._handle, C.c_void_p(xt.data_ptr()),
-                                    C.c_void_p(yt.data_ptr()), stages)
+                                    C.c_void_p(yt.data_ptr()), stages, 0)
     assert st == 0, lib.nudft2_last_error()
     G = onu.dense_G(pr.points, nx, ny)
     ref = G @ x

@@ -85,7 +85,8 @@ def test_geqrf_ormqr(prec):
         k = min(m, n)
         nbk = (k + 31) // 32
         tA = to_dev(A, prec)
-        tR = torch.zeros((n, k), dtype=CT[prec][1], device=DEV)       # k x n col-major
+        # R starts as garbage: the factorization must write all of it
+        tR = torch.full((n, k), 7.0 - 3.0j, dtype=CT[prec][1], device=DEV)   # k x n col-major
         tT = torch.zeros((nbk, 32, 32), dtype=CT[prec][1], device=DEV)
         keep += [tA, tR, tT]
         data.append((A, tA, tR, tT))
