@@ -62,7 +62,9 @@ typedef struct {
   int32_t leaf;       /* columns per dimension of a leaf (paper: 16)           */
   double ir_tol;      /* refinement stop: ||dc||_2 / ||c||_2 <= ir_tol          */
   int32_t ir_maxit;   /* refinement iterations; 0 = plain direct solve          */
-  int32_t refine;     /* 0: iterative refinement; 1: CG on the normal equations */
+  int32_t refine;     /* 0: refinement c += S(f - Ac) (exact for consistent f);
+                         1: refinement on the normal equations
+                            c += S S^* A^*(f - Ac) (exact least squares for any f) */
   void* stream;       /* hipStream_t; NULL = default stream                     */
   size_t mem_cap;     /* device bytes the plan may hold; 0 = no cap             */
 } nudft2_opts;
@@ -125,18 +127,42 @@ nudft2_status nudft2_factor(nudft2_plan_t plan);
 /* Least-squares solve for nrhs right-hand sides.  f: DEVICE, nrhs x M
  * complex128 (row-major, right-hand side r at f + 2*M*r), in the caller's
  * point order.  c: DEVICE, nrhs x nx x ny complex128 output.  With
- * opts.ir_maxit == 0 returns the direct solution c = F^{-1} H^+ f; otherwise
- * refines in FP64 (E_NOCONV leaves the last iterate in c).  Errors: E_INVAL
+ * opts.ir_maxit == 0 returns the direct solution c = S f with S = F^{-1} H^+
+ * (Algorithm 4.1); otherwise refines in FP64 against the exact A until
+ * ||dc||/||c|| <= ir_tol: opts.refine = 0 iterates c += S(f - A c), whose fixed
+ * point is the least-squares solution when f is in the range of A; refine = 1
+ * iterates c += S S^* A^*(f - A c), whose fixed point is the least-squares
+ * solution for any f (E_NOCONV leaves the last iterate in c).  Errors: E_INVAL
  * (null pointer, nrhs <= 0), E_STATE (not factored), E_NOCONV, E_DEVICE. */
 nudft2_status nudft2_solve(nudft2_plan_t plan, const double* f, double* c,
                            int32_t nrhs, nudft2_solve_info* info);
 
-/* Adjoint of the least-squares solution operator: w = (A^+)^* g for g of
- * shape nrhs x nx x ny, w of shape nrhs x M (DEVICE).  Used for gradients
- * with respect to f.  Requires the factorization (used as preconditioner of
- * CG on the normal equations).  Errors as nudft2_solve. */
+/* Adjoint of the least-squares solution operator: w = (A^+)^* g =
+ * A (A^*A)^{-1} g for g of shape nrhs x nx x ny, w of shape nrhs x M (DEVICE,
+ * caller-owned).  (A^*A)^{-1} g is obtained by refinement on the normal
+ * equations preconditioned by S S^* (S = F^{-1} H^+ the factored solution
+ * operator and S^* its adjoint sweep), stopped at ||dz||/||z|| <= ir_tol
+ * (at least one step even when ir_maxit == 0).  This is the map that gives
+ * dL/df = w for an upstream gradient g = dL/dc of the solution.  Errors:
+ * E_INVAL, E_STATE (not factored), E_NOCONV, E_DEVICE. */
 nudft2_status nudft2_solve_adj(nudft2_plan_t plan, const double* g, double* w,
                                int32_t nrhs, nudft2_solve_info* info);
+
+/* Backward pass of c = A^+ f (c the least-squares solution for f, as returned
+ * by nudft2_solve with refine = 1) for an upstream gradient g = dL/dc (real
+ * loss, dL = Re<g, dc>, the convention of PyTorch's complex autograd).  With
+ * z = (A^*A)^{-1} g, w = A z, r = f - A c, s = A(k^x o c), t = A(k^x o z):
+ *     grad_f = w,
+ *     dL/dx_j = 2 pi Im(conj(r_j) t_j - conj(w_j) s_j)   (k^y for dL/dy_j),
+ * obtained by differentiating the normal equations A^*A c = A^*f with
+ * dA(j,k)/dx_j = -2 pi i k^x A(j,k) (centred k).  f, c, g, grad_f: DEVICE
+ * complex128 (nrhs x M, nrhs x nx x ny, nrhs x nx x ny, nrhs x M).
+ * grad_points: DEVICE M x 2 doubles in the caller's point order (x, y
+ * interleaved) summed over the right-hand sides, or NULL to skip it.  Errors
+ * as nudft2_solve_adj. */
+nudft2_status nudft2_lsq_backward(nudft2_plan_t plan, const double* f, const double* c,
+                                  const double* g, double* grad_f, double* grad_points,
+                                  int32_t nrhs, nudft2_solve_info* info);
 
 /* f = A c exactly in FP64 (Section 1 sum).  c: DEVICE nrhs x nx x ny, f:
  * DEVICE nrhs x M.  Does not need the factorization.  Errors: E_INVAL. */

@@ -57,8 +57,9 @@ nudft2_status nudft2_test_mfma_layout32(const float* a, const float* b, float* d
  *        rmax_i), stopping when the remaining Schur-complement trace is at
  *        most tol2 * trace(K_i).  rank_out (HOST, nb) and piv_out (HOST,
  *        sum rmax_i) receive the ranks and pivot rows.
- * trsv:  R_i X_i = B_i in place, R upper triangular; dims = (k, nrhs),
- *        ld = (ldr, ldb), ptrs = (R, B). */
+ * trsv:  R_i X_i = B_i (conj_trans = 0) or R_i^H X_i = B_i (conj_trans = 1)
+ *        in place, R upper triangular; dims = (k, nrhs), ld = (ldr, ldb),
+ *        ptrs = (R, B). */
 nudft2_status nudft2_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t nb,
                                const int32_t* mnk, const int32_t* ld, const int64_t* ptrs,
                                double alpha_re, double alpha_im, double beta);
@@ -71,7 +72,7 @@ nudft2_status nudft2_test_pchol(int32_t nb, const int32_t* w, const int32_t* rma
                                 const int64_t* ptrs, double tol2, int32_t* rank_out,
                                 int32_t* piv_out);
 nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims,
-                               const int32_t* ld, const int64_t* ptrs);
+                               const int32_t* ld, const int64_t* ptrs, int32_t conj_trans);
 
 /* 1D HSS compression of G^x (dim 0) or G^y (dim 1) of every problem of the
  * plan at tolerance tol (no factorization needed), then y = H x for problem

@@ -120,6 +120,29 @@ class _PlanBase:
                            rel_residual=si.rel_residual)
         return w
 
+    def lsq_backward(self, f: torch.Tensor, c: torch.Tensor, g: torch.Tensor,
+                     points_grad: bool = True, return_info: bool = False):
+        """Backward pass of c = A^+ f for the upstream gradient g = dL/dc:
+        returns (dL/df, dL/dpoints or None) (see nudft2_lsq_backward)."""
+        nrhs, _ = self._rhs(f)
+        self._check_dev(c, "c")
+        self._check_dev(g, "g")
+        if c.numel() != g.numel() or c.numel() != nrhs * int(np.prod(self.N_shape)):
+            raise ValueError("c and g must match the solution shape")
+        gf = torch.empty_like(f)
+        gp = (torch.empty((self.M, 2), dtype=torch.float64, device=f.device)
+              if points_grad else None)
+        si = _lib.SolveInfo()
+        st = lib.nudft2_lsq_backward(self._handle, C.c_void_p(f.data_ptr()),
+                                     C.c_void_p(c.data_ptr()), C.c_void_p(g.data_ptr()),
+                                     C.c_void_p(gf.data_ptr()),
+                                     C.c_void_p(gp.data_ptr()) if gp is not None else None,
+                                     nrhs, C.byref(si))
+        check(st, "nudft2_lsq_backward")
+        if return_info:
+            return gf, gp, dict(iterations=si.iterations, rel_update=si.rel_update)
+        return gf, gp
+
     def apply(self, c: torch.Tensor) -> torch.Tensor:
         self._check_dev(c, "c")
         nrhs = 1 if c.dim() == len(self.N_shape) else c.shape[0]

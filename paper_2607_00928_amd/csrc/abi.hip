@@ -138,14 +138,14 @@ static void test_ormqr(int trans, int nb, const int32_t* dims, const int32_t* ld
 }
 
 template <typename T>
-static void test_trsv(int nb, const int32_t* dims, const int32_t* ld, const int64_t* ptrs) {
+static void test_trsv(int nb, const int32_t* dims, const int32_t* ld, const int64_t* ptrs, bool ct) {
   std::vector<TrsDesc<T>> d(nb);
   for (int i = 0; i < nb; ++i)
     d[i] = TrsDesc<T>{dims[2 * i], dims[2 * i + 1], ld[2 * i], ld[2 * i + 1],
                       (const cplx<T>*)ptrs[2 * i], (cplx<T>*)ptrs[2 * i + 1]};
   DescPool pool;
   pool.init(1 << 20, nullptr);
-  trsv_upper_batched<T>(pool, d);
+  trsv_upper_batched<T>(pool, d, ct);
   pool.sync_reset();
 }
 
@@ -233,8 +233,25 @@ nudft2_status nudft2_solve_adj(nudft2_plan_t plan, const double* g, double* w, i
     ND_CHECK(nrhs > 0, NUDFT2_E_INVAL, "nrhs must be positive");
     Plan* P = reinterpret_cast<Plan*>(plan);
     ND_CHECK(P->factored, NUDFT2_E_STATE, "solve before factor");
+    PlanProf pp(P);
     solve(P, reinterpret_cast<const double2*>(g), reinterpret_cast<double2*>(w), nrhs, info,
           true);
+  });
+}
+
+nudft2_status nudft2_lsq_backward(nudft2_plan_t plan, const double* f, const double* c,
+                                  const double* g, double* grad_f, double* grad_points,
+                                  int32_t nrhs, nudft2_solve_info* info) {
+  return guard([&] {
+    ND_CHECK(plan != nullptr && f != nullptr && c != nullptr && g != nullptr && grad_f != nullptr,
+             NUDFT2_E_INVAL, "null pointer");
+    ND_CHECK(nrhs > 0, NUDFT2_E_INVAL, "nrhs must be positive");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    ND_CHECK(P->factored, NUDFT2_E_STATE, "backward before factor");
+    PlanProf pp(P);
+    lsq_backward(P, reinterpret_cast<const double2*>(f), reinterpret_cast<const double2*>(c),
+                 reinterpret_cast<const double2*>(g), reinterpret_cast<double2*>(grad_f),
+                 grad_points, nrhs, info);
   });
 }
 
@@ -386,12 +403,12 @@ nudft2_status nudft2_test_pchol(int32_t nb, const int32_t* w, const int32_t* rma
 }
 
 nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims, const int32_t* ld,
-                               const int64_t* ptrs) {
+                               const int64_t* ptrs, int32_t conj_trans) {
   return guard([&] {
     ND_CHECK(dims && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
     need_device();
-    if (prec == 0) test_trsv<double>(nb, dims, ld, ptrs);
-    else test_trsv<float>(nb, dims, ld, ptrs);
+    if (prec == 0) test_trsv<double>(nb, dims, ld, ptrs, conj_trans != 0);
+    else test_trsv<float>(nb, dims, ld, ptrs, conj_trans != 0);
   });
 }
 

@@ -195,5 +195,10 @@ void urv_factor(Ctx& cx, HSS2<T>& H);
 // order, working precision).  f is overwritten.
 template <typename T>
 void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t ldc, int nrhs);
+// Adjoint of urv_solve: c (ldc x nrhs, quadtree column order, working
+// precision, overwritten) -> f (ldf x nrhs, 2D-sorted rows, working precision).
+template <typename T>
+void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int64_t ldf,
+                   int nrhs);
 
 }  // namespace nd

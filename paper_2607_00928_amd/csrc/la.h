@@ -98,8 +98,8 @@ struct PcholDesc {
 };
 void pchol_batched(DescPool& pool, const std::vector<PcholDesc>& d);
 
-// Batched upper-triangular solve R X = B in place (R: k x k, ldr; B: k x nrhs,
-// ldb).
+// Batched upper-triangular solve R X = B in place, or R^H X = B when
+// conj_trans (R: k x k, ldr; B: k x nrhs, ldb).
 template <typename T>
 struct TrsDesc {
   int k, nrhs, ldr, ldb;
@@ -107,7 +107,8 @@ struct TrsDesc {
   cplx<T>* B;
 };
 template <typename T>
-void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d);
+void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d,
+                        bool conj_trans = false);
 
 // Elementwise helpers (batched over descriptors).
 template <typename TD, typename TS>

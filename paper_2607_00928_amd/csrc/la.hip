@@ -546,7 +546,9 @@ __global__ void pchol_finish_kernel(const PcholDesc* __restrict__ descs, const i
 // Done with the GEMM kernel (opB = C) by the host.
 
 // ------------------------------------------------------------ triangular solve
-template <typename T>
+// R X = B (CT = false, back substitution) or R^H X = B (CT = true, forward
+// substitution) with R upper triangular; one workgroup per (system, column).
+template <typename T, bool CT>
 __global__ __launch_bounds__(256) void trsv_upper_kernel(const TrsDesc<T>* __restrict__ descs) {
   using C2 = cplx<T>;
   const TrsDesc<T> d = descs[blockIdx.x];
@@ -554,9 +556,11 @@ __global__ __launch_bounds__(256) void trsv_upper_kernel(const TrsDesc<T>* __res
   if (rhs >= d.nrhs) return;
   C2* b = d.B + (int64_t)rhs * d.ldb;
   __shared__ C2 xs;
-  for (int i = d.k - 1; i >= 0; --i) {
+  for (int s = 0; s < d.k; ++s) {
+    const int i = CT ? s : d.k - 1 - s;
     if (threadIdx.x == 0) {
       C2 r = d.R[i + (int64_t)i * d.ldr];
+      if (CT) r.y = -r.y;
       C2 v = b[i];
       T den = r.x * r.x + r.y * r.y;
       C2 x = mk<T>((v.x * r.x + v.y * r.y) / den, (v.y * r.x - v.x * r.y) / den);
@@ -565,7 +569,13 @@ __global__ __launch_bounds__(256) void trsv_upper_kernel(const TrsDesc<T>* __res
     }
     __syncthreads();
     C2 x = xs;
-    for (int r = threadIdx.x; r < i; r += 256) b[r] = csub(b[r], cmul(d.R[r + (int64_t)i * d.ldr], x));
+    if (CT) {
+      // rows below: b_r -= conj(R(i, r)) x
+      for (int r = i + 1 + threadIdx.x; r < d.k; r += 256)
+        b[r] = csub(b[r], cmul(cconj(d.R[i + (int64_t)r * d.ldr]), x));
+    } else {
+      for (int r = threadIdx.x; r < i; r += 256) b[r] = csub(b[r], cmul(d.R[r + (int64_t)i * d.ldr], x));
+    }
     __syncthreads();
   }
 }
@@ -878,21 +888,26 @@ void pchol_batched(DescPool& pool, const std::vector<PcholDesc>& d) {
 }
 
 template <typename T>
-static void trsv_small(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
+static void trsv_small(DescPool& pool, const std::vector<TrsDesc<T>>& d, bool ct) {
   if (d.empty()) return;
   int maxr = 0;
   for (auto& q : d) maxr = std::max(maxr, q.nrhs);
   auto* dd = (TrsDesc<T>*)pool.push(d.data(), sizeof(TrsDesc<T>) * d.size());
-  hipLaunchKernelGGL((trsv_upper_kernel<T>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
-                     pool.stream, dd);
+  if (ct)
+    hipLaunchKernelGGL((trsv_upper_kernel<T, true>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
+                       pool.stream, dd);
+  else
+    hipLaunchKernelGGL((trsv_upper_kernel<T, false>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
+                       pool.stream, dd);
   ND_HIP(hipGetLastError());
 }
 
-// Upper-triangular solves.  Small systems: one workgroup each.  Large ones:
-// blocked back substitution, 128 x 128 diagonal blocks solved by one
-// workgroup, the rows above updated by a matrix-core GEMM.
+// Upper-triangular solves R X = B, or R^H X = B when conj_trans.  Small
+// systems: one workgroup each.  Large ones: blocked substitution, 128 x 128
+// diagonal blocks solved by one workgroup, the remaining rows updated by a
+// matrix-core GEMM (rows above for R, rows below for R^H).
 template <typename T>
-void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
+void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d, bool conj_trans) {
   constexpr int BS = 128;
   if (hazards_enabled()) {
     std::vector<Region> v;
@@ -910,7 +925,7 @@ void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
     if (q.k <= 0 || q.nrhs <= 0) continue;
     (q.k <= 2 * BS ? small : big).push_back(q);
   }
-  trsv_small<T>(pool, small);
+  trsv_small<T>(pool, small, conj_trans);
   if (big.empty()) return;
   int maxblk = 0;
   for (auto& q : big) maxblk = std::max(maxblk, (q.k + BS - 1) / BS);
@@ -922,15 +937,19 @@ void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d) {
     for (auto& q : big) {
       int nblk = (q.k + BS - 1) / BS;
       if (s >= nblk) continue;
-      int b = nblk - 1 - s;
+      int b = conj_trans ? s : nblk - 1 - s;
       int i0 = b * BS, bs = std::min(BS, q.k - i0);
       dg.push_back({bs, q.nrhs, q.ldr, q.ldb, q.R + i0 + (int64_t)i0 * q.ldr, q.B + i0});
-      if (i0 > 0)
+      if (!conj_trans && i0 > 0)
         gu.push_back({i0, q.nrhs, bs, q.ldr, q.ldb, q.ldb, q.R + (int64_t)i0 * q.ldr, q.B + i0,
                       q.B, T(-1), T(0), T(1)});
+      int rest = q.k - i0 - bs;
+      if (conj_trans && rest > 0)
+        gu.push_back({rest, q.nrhs, bs, q.ldr, q.ldb, q.ldb, q.R + i0 + (int64_t)(i0 + bs) * q.ldr,
+                      q.B + i0, q.B + i0 + bs, T(-1), T(0), T(1)});
     }
-    trsv_small<T>(pool, dg);
-    gemm_batched<T>(pool, gu, OpN, OpN);
+    trsv_small<T>(pool, dg, conj_trans);
+    gemm_batched<T>(pool, gu, conj_trans ? OpC : OpN, OpN);
   }
 }
 
@@ -975,7 +994,7 @@ void fill_batched(DescPool& pool, const std::vector<FillDesc<T>>& d) {
   template void geqrf_batched<T>(DescPool&, const std::vector<QRDesc<T>>&, void*);       \
   template size_t orm_workspace<T>(const std::vector<OrmDesc<T>>&);                      \
   template void ormqr_batched<T>(DescPool&, const std::vector<OrmDesc<T>>&, bool, void*); \
-  template void trsv_upper_batched<T>(DescPool&, const std::vector<TrsDesc<T>>&);        \
+  template void trsv_upper_batched<T>(DescPool&, const std::vector<TrsDesc<T>>&, bool);  \
   template void fill_batched<T>(DescPool&, const std::vector<FillDesc<T>>&);
 INST(float)
 INST(double)

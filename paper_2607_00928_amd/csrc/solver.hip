@@ -103,11 +103,97 @@ __global__ void zero_d_kernel(double* p, int64_t n) {
 }
 
 __global__ void inv_kernel(const double* s, double* inv, double* sq, int n) {
-  int i = threadIdx.x;
-  if (i < n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double v = sqrt(s[i]);
     sq[i] = v > 0 ? v : 1.0;
     inv[i] = v > 0 ? 1.0 / v : 1.0;
+  }
+}
+
+// out[r][perm2d[s]] = phi_s fw[s + r*ldw] scale[r]  (adjoint of prep_rhs_kernel)
+template <typename T>
+__global__ void prep_adj_kernel(const PrepDesc* __restrict__ pd, const double* __restrict__ pts2d,
+                                const int64_t* __restrict__ perm2d, const cplx<T>* __restrict__ fw,
+                                int64_t ldw, const double* __restrict__ scale,
+                                double2* __restrict__ out, int64_t ldo, int nrhs) {
+  const PrepDesc d = pd[blockIdx.y];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < d.M * nrhs;
+       e += (int64_t)gridDim.x * 256) {
+    int64_t j = e % d.M;
+    int r = (int)(e / d.M);
+    int64_t s = d.m0 + j;
+    double x = pts2d[2 * s], y = pts2d[2 * s + 1];
+    double2 ph = cmul(expi_kx((double)(d.nx / 2), x), expi_kx((double)(d.ny / 2), y));
+    cplx<T> v = fw[s + r * ldw];
+    double2 o = cmul(cconj(ph), mk<double>((double)v.x, (double)v.y));
+    double sc = scale[r];
+    out[r * ldo + perm2d[s]] = mk<double>(o.x * sc, o.y * sc);
+  }
+}
+
+// cw[i + r*ldw] = in[r][colperm[i]] inv_scale[r]  (adjoint of post_sol_kernel)
+template <typename T>
+__global__ void post_adj_kernel(const double2* __restrict__ in, int64_t ldi,
+                                const int64_t* __restrict__ colperm,
+                                const double* __restrict__ inv_scale, cplx<T>* __restrict__ cw,
+                                int64_t ldw, int64_t N, int nrhs) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N * nrhs;
+       e += (int64_t)gridDim.x * 256) {
+    int64_t i = e % N;
+    int r = (int)(e / N);
+    double2 v = in[r * ldi + colperm[i]];
+    double sc = inv_scale[r];
+    cw[i + r * ldw] = mk<T>((T)(v.x * sc), (T)(v.y * sc));
+  }
+}
+
+struct KDesc {
+  int64_t c0, N;
+  int nx, ny;
+};
+
+// Y = [k^x o c; k^x o z; k^y o c; k^y o z] (each nrhs x Ntot) with the centred
+// frequencies of the coefficient index (i = kx' ny + ky')
+__global__ void kscale_kernel(const KDesc* __restrict__ kd, const double2* __restrict__ c,
+                              const double2* __restrict__ z, double2* __restrict__ Y,
+                              int64_t Ntot, int nrhs) {
+  const KDesc d = kd[blockIdx.y];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < d.N * nrhs;
+       e += (int64_t)gridDim.x * 256) {
+    int64_t i = e % d.N;
+    int r = (int)(e / d.N);
+    double kx = (double)(i / d.ny) - (double)(d.nx / 2);
+    double ky = (double)(i % d.ny) - (double)(d.ny / 2);
+    int64_t o = r * Ntot + d.c0 + i;
+    double2 cv = c[o], zv = z[o];
+    int64_t sN = (int64_t)nrhs * Ntot;
+    Y[o] = mk<double>(kx * cv.x, kx * cv.y);
+    Y[sN + o] = mk<double>(kx * zv.x, kx * zv.y);
+    Y[2 * sN + o] = mk<double>(ky * cv.x, ky * cv.y);
+    Y[3 * sN + o] = mk<double>(ky * zv.x, ky * zv.y);
+  }
+}
+
+// dL/dx_j = 2 pi sum_r Im(conj(r_j) t_j - conj(w_j) s_j) with s = A(k^x o c),
+// t = A(k^x o z), likewise y with k^y; S4 = A Y (4 nrhs x Mtot)
+__global__ void grad_points_kernel(const double2* __restrict__ r, const double2* __restrict__ w,
+                                   const double2* __restrict__ S4, double* __restrict__ grad,
+                                   int64_t Mtot, int nrhs) {
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < Mtot;
+       j += (int64_t)gridDim.x * 256) {
+    double gx = 0, gy = 0;
+    const int64_t sM = (int64_t)nrhs * Mtot;
+    for (int q = 0; q < nrhs; ++q) {
+      int64_t o = q * Mtot + j;
+      double2 rv = r[o], wv = w[o];
+      double2 sx = S4[o], tx = S4[sM + o], sy = S4[2 * sM + o], ty = S4[3 * sM + o];
+      // Im(conj(a) b) = a.x b.y - a.y b.x
+      gx += (rv.x * tx.y - rv.y * tx.x) - (wv.x * sx.y - wv.y * sx.x);
+      gy += (rv.x * ty.y - rv.y * ty.x) - (wv.x * sy.y - wv.y * sy.x);
+    }
+    grad[2 * j] = two_pi * gx;
+    grad[2 * j + 1] = two_pi * gy;
   }
 }
 
@@ -220,87 +306,262 @@ void sumsq(hipStream_t s, const double2* x, int64_t n, int64_t ldx, int nrhs, do
   ND_HIP(hipGetLastError());
 }
 
+// out = S^H v for the solution operator S of hss_inverse (v: nrhs x Ntot,
+// natural order; out: nrhs x Mtot, caller order), v normalised per right-hand
+// side by inv_scale and the result multiplied by scale.
+template <typename T>
+void hss_inverse_adj(Ctx& cx, HSS2<T>& H, const double2* v, double2* out, int nrhs,
+                     SolveWs<T>& w, const double* scale, const double* inv_scale) {
+  Plan* P = cx.P;
+  // adjoint 2D inverse DFT: X = Fy^H V Fx^H per problem and right-hand side
+  std::vector<GemmDesc<double>> g1, g2;
+  for (size_t p = 0; p < P->probs.size(); ++p) {
+    const Problem& q = P->probs[p];
+    Prob2<T>& pb = H.probs[p];
+    for (int rr = 0; rr < nrhs; ++rr) {
+      const double2* V = v + rr * P->Ntot + q.c0;
+      double2* T1 = w.tmp + rr * P->Ntot + q.c0;
+      double2* X = w.chat + rr * P->Ntot + q.c0;
+      g1.push_back({q.ny, q.nx, q.ny, pb.Fy.ld, q.ny, q.ny, pb.Fy.p, V, T1, 1.0, 0.0, 0.0});
+      g2.push_back({q.ny, q.nx, q.nx, q.ny, pb.Fx.ld, q.ny, T1, pb.Fx.p, X, 1.0, 0.0, 0.0});
+    }
+  }
+  gemm_batched<double>(cx.pool, g1, OpC, OpN);
+  gemm_batched<double>(cx.pool, g2, OpN, OpC);
+  hipLaunchKernelGGL((post_adj_kernel<T>), dim3(grid_for(P->Ntot * nrhs)), dim3(256), 0, cx.s,
+                     w.chat, P->Ntot, P->colperm, inv_scale, w.cw, P->Ntot, P->Ntot, nrhs);
+  ND_HIP(hipGetLastError());
+  urv_solve_adj<T>(cx, H, w.cw, P->Ntot, w.fw, P->Mtot, nrhs);
+  std::vector<PrepDesc> pd;
+  int64_t mmax = 0;
+  for (auto& q : P->probs) {
+    pd.push_back({q.m0, q.M, q.nx, q.ny});
+    mmax = std::max(mmax, q.M);
+  }
+  auto* dpd = (PrepDesc*)cx.pool.push(pd.data(), sizeof(PrepDesc) * pd.size());
+  hipLaunchKernelGGL((prep_adj_kernel<T>), dim3(grid_for(mmax * nrhs), (unsigned)pd.size()),
+                     dim3(256), 0, cx.s, dpd, P->pts_2d, P->perm2d, w.fw, P->Mtot, scale, out,
+                     P->Mtot, nrhs);
+  ND_HIP(hipGetLastError());
+}
+
+// Shared state of the solve drivers: workspace, the two HSS solution
+// operators S (M -> N) and S^H (N -> M), norms.
+template <typename T>
+struct SolveCtx {
+  Plan* P;
+  HSS2<T>& H;
+  Ctx cx;
+  int nrhs;
+  SolveWs<T> w;
+  double* nrm2;
+  double* scale;
+  double* inv;
+  double* red;
+  SolveCtx(Plan* p, int nr) : P(p), H(*static_cast<HSS2<T>*>(p->hss.get())), nrhs(nr) {
+    cx.P = P;
+    cx.s = P->stream;
+    cx.pool.init(64 << 20, cx.s);
+    w.fw = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * P->Mtot * nrhs);
+    w.cw = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * P->Ntot * nrhs);
+    w.chat = (double2*)cx.tmp_alloc(sizeof(double2) * P->Ntot * nrhs);
+    w.tmp = (double2*)cx.tmp_alloc(sizeof(double2) * P->Ntot * nrhs);
+    w.sums = (double*)cx.tmp_alloc(sizeof(double) * 8 * nrhs);
+    nrm2 = w.sums;
+    scale = w.sums + nrhs;
+    inv = w.sums + 2 * nrhs;
+    red = w.sums + 3 * nrhs;
+  }
+  double2* vecM() { return (double2*)cx.tmp_alloc(sizeof(double2) * P->Mtot * nrhs); }
+  double2* vecN() { return (double2*)cx.tmp_alloc(sizeof(double2) * P->Ntot * nrhs); }
+  void zero(double2* x, int64_t n) {
+    hipLaunchKernelGGL(zero_d_kernel, dim3(grid_for(2 * n * nrhs)), dim3(256), 0, cx.s,
+                       (double*)x, 2 * n * nrhs);
+  }
+  void copy(const double2* x, double2* y, int64_t n) {
+    ND_HIP(hipMemcpyAsync(y, x, sizeof(double2) * n * nrhs, hipMemcpyDeviceToDevice, cx.s));
+  }
+  void axpby(double a, const double2* x, double b, double2* y, int64_t n) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, cx.s, a, x, b, y,
+                       n * nrhs);
+  }
+  void normalise(const double2* x, int64_t n) {
+    sumsq(cx.s, x, n, n, nrhs, nrm2);
+    hipLaunchKernelGGL(inv_kernel, dim3(1), dim3(256), 0, cx.s, nrm2, inv, scale, nrhs);
+  }
+  // d = S r (r: nrhs x Mtot -> d: nrhs x Ntot)
+  void S(const double2* r, double2* d) {
+    normalise(r, P->Mtot);
+    hss_inverse<T>(cx, H, r, d, nrhs, w, scale, inv);
+  }
+  // out = S^H v (v: nrhs x Ntot -> out: nrhs x Mtot)
+  void SH(const double2* v, double2* out) {
+    normalise(v, P->Ntot);
+    hss_inverse_adj<T>(cx, H, v, out, nrhs, w, scale, inv);
+  }
+  // squared norms per right-hand side of several vectors, read back (synchronises)
+  std::vector<double> norms2(std::initializer_list<std::pair<const double2*, int64_t>> xs) {
+    std::vector<double> h(xs.size() * nrhs);
+    int i = 0;
+    for (auto& x : xs) {
+      sumsq(cx.s, x.first, x.second, x.second, nrhs, red);
+      ND_HIP(hipMemcpyAsync(h.data() + i * nrhs, red, sizeof(double) * nrhs,
+                            hipMemcpyDeviceToHost, cx.s));
+      ND_HIP(hipStreamSynchronize(cx.s));
+      ++i;
+    }
+    cx.pool.sync_reset();
+    return h;
+  }
+  // worst ||a_r|| / ||b_r|| over the right-hand sides of a two-vector norm read
+  double worst_ratio(const std::vector<double>& h, int ia, int ib) const {
+    double worst = 0;
+    for (int r = 0; r < nrhs; ++r)
+      worst = std::max(worst, std::sqrt(h[ia * nrhs + r]) /
+                                  std::max(std::sqrt(h[ib * nrhs + r]), 1e-300));
+    return worst;
+  }
+};
+
+void report(nudft2_solve_info* info, int its, double upd, double res) {
+  if (!info) return;
+  info->iterations = its;
+  info->rel_update = upd;
+  info->rel_residual = res;
+}
+
+// Least-squares solve.  refine == 0: iterative refinement c += S (f - A c)
+// (exact for consistent f); refine == 1: refinement on the normal equations,
+// c += S S^H A^H (f - A c), whose fixed point is the least-squares solution
+// for any f.  ir_maxit == 0: the direct solution S f.
 template <typename T>
 void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info* info) {
-  HSS2<T>& H = *static_cast<HSS2<T>*>(P->hss.get());
-  Ctx cx;
-  cx.P = P;
-  cx.s = P->stream;
-  cx.pool.init(64 << 20, cx.s);
-  SolveWs<T> w;
-  w.fw = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * P->Mtot * nrhs);
-  w.cw = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * P->Ntot * nrhs);
-  w.chat = (double2*)cx.tmp_alloc(sizeof(double2) * P->Ntot * nrhs);
-  w.tmp = (double2*)cx.tmp_alloc(sizeof(double2) * P->Ntot * nrhs);
-  w.sums = (double*)cx.tmp_alloc(sizeof(double) * 8 * nrhs);
-  double* nrm2 = w.sums;
-  double* scale = w.sums + nrhs;
-  double* inv = w.sums + 2 * nrhs;
-  double* tmp2 = w.sums + 3 * nrhs;
-  const int64_t MN = P->Mtot * nrhs, NN = P->Ntot * nrhs;
+  SolveCtx<T> sc(P, nrhs);
+  const int64_t M = P->Mtot, N = P->Ntot;
   const int maxit = P->opts.ir_maxit;
   if (maxit == 0) {
-    sumsq(cx.s, f, P->Mtot, P->Mtot, nrhs, nrm2);
-    hipLaunchKernelGGL(inv_kernel, dim3(1), dim3(64), 0, cx.s, nrm2, inv, scale, nrhs);
-    hss_inverse<T>(cx, H, f, c, nrhs, w, scale, inv);
-    if (info) {
-      info->iterations = 0;
-      info->rel_update = 0;
-      info->rel_residual = -1;
-    }
-    ND_HIP(hipStreamSynchronize(cx.s));
+    sc.S(f, c);
+    ND_HIP(hipStreamSynchronize(sc.cx.s));
+    report(info, 0, 0, -1);
     return;
   }
-  double2* rr = (double2*)cx.tmp_alloc(sizeof(double2) * MN);
-  double2* dd = (double2*)cx.tmp_alloc(sizeof(double2) * NN);
-  ND_HIP(hipMemcpyAsync(rr, f, sizeof(double2) * MN, hipMemcpyDeviceToDevice, cx.s));
-  hipLaunchKernelGGL(zero_d_kernel, dim3(grid_for(2 * NN)), dim3(256), 0, cx.s, (double*)c,
-                     2 * NN);
-  std::vector<double> h(4 * nrhs);
-  double fn = 0;
-  {
-    sumsq(cx.s, f, P->Mtot, P->Mtot, nrhs, nrm2);
-    ND_HIP(hipMemcpyAsync(h.data(), nrm2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, cx.s));
-    ND_HIP(hipStreamSynchronize(cx.s));
-    fn = std::sqrt(h[0]);
-  }
+  const bool ne = P->opts.refine == 1;
+  double2* rr = sc.vecM();
+  double2* dd = sc.vecN();
+  double2* rN = ne ? sc.vecN() : nullptr;
+  double2* tM = ne ? sc.vecM() : nullptr;
+  sc.copy(f, rr, M);
+  sc.zero(c, N);
+  const double fn = std::sqrt(sc.norms2({{f, M}})[0]);
   int it = 0;
   double upd = 0, res = 1;
   bool conv = false;
   for (it = 1; it <= maxit; ++it) {
-    // d = H^+ r (normalised), c += d
-    sumsq(cx.s, rr, P->Mtot, P->Mtot, nrhs, nrm2);
-    hipLaunchKernelGGL(inv_kernel, dim3(1), dim3(64), 0, cx.s, nrm2, inv, scale, nrhs);
-    hss_inverse<T>(cx, H, rr, dd, nrhs, w, scale, inv);
-    hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(NN)), dim3(256), 0, cx.s, 1.0, dd, 1.0, c, NN);
-    // r = f - A c
-    apply_fwd(P, c, rr, nrhs, cx.s);
-    hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(MN)), dim3(256), 0, cx.s, 1.0, f, -1.0, rr, MN);
-    sumsq(cx.s, dd, P->Ntot, P->Ntot, nrhs, tmp2);
-    sumsq(cx.s, c, P->Ntot, P->Ntot, nrhs, tmp2 + nrhs);
-    sumsq(cx.s, rr, P->Mtot, P->Mtot, nrhs, tmp2 + 2 * nrhs);
-    ND_HIP(hipMemcpyAsync(h.data(), tmp2, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, cx.s));
-    ND_HIP(hipStreamSynchronize(cx.s));
-    cx.pool.sync_reset();
-    double worst = 0;
-    for (int r = 0; r < nrhs; ++r) {
-      double u = std::sqrt(h[r]) / std::max(std::sqrt(h[nrhs + r]), 1e-300);
-      worst = std::max(worst, u);
+    if (ne) {
+      apply_adj(P, rr, rN, nrhs, sc.cx.s);
+      sc.SH(rN, tM);
+      sc.S(tM, dd);
+    } else {
+      sc.S(rr, dd);
     }
-    upd = worst;
+    sc.axpby(1.0, dd, 1.0, c, N);
+    apply_fwd(P, c, rr, nrhs, sc.cx.s);
+    sc.axpby(1.0, f, -1.0, rr, M);
+    std::vector<double> h = sc.norms2({{dd, N}, {c, N}, {rr, M}});
+    upd = sc.worst_ratio(h, 0, 1);
     res = std::sqrt(h[2 * nrhs]) / std::max(fn, 1e-300);
-    if (!(worst == worst)) break;   // NaN: stop
-    if (worst <= P->opts.ir_tol) {
+    if (!(upd == upd)) break;   // NaN: stop
+    if (upd <= P->opts.ir_tol) {
       conv = true;
       break;
     }
   }
-  if (info) {
-    info->iterations = std::min(it, maxit);
-    info->rel_update = upd;
-    info->rel_residual = res;
-  }
+  report(info, std::min(it, maxit), upd, res);
   if (!conv) throw Error(NUDFT2_E_NOCONV, "refinement did not reach ir_tol");
+}
+
+// z = (A^H A)^{-1} g by refinement on the normal equations preconditioned by
+// S S^H: z += S S^H (g - A^H A z).  Returns iterations and the last update.
+template <typename T>
+void normal_solve(SolveCtx<T>& sc, const double2* g, double2* z, int& its, double& upd) {
+  Plan* P = sc.P;
+  const int64_t M = P->Mtot, N = P->Ntot;
+  const int maxit = std::max(P->opts.ir_maxit, 1);
+  double2* rz = sc.vecN();
+  double2* dd = sc.vecN();
+  double2* u = sc.vecM();
+  double2* tM = sc.vecM();
+  sc.copy(g, rz, N);
+  sc.zero(z, N);
+  bool conv = false;
+  for (its = 1; its <= maxit; ++its) {
+    sc.SH(rz, tM);
+    sc.S(tM, dd);
+    sc.axpby(1.0, dd, 1.0, z, N);
+    apply_fwd(P, z, u, sc.nrhs, sc.cx.s);
+    apply_adj(P, u, rz, sc.nrhs, sc.cx.s);
+    sc.axpby(1.0, g, -1.0, rz, N);
+    std::vector<double> h = sc.norms2({{dd, N}, {z, N}});
+    upd = sc.worst_ratio(h, 0, 1);
+    if (!(upd == upd)) break;
+    if (upd <= P->opts.ir_tol) {
+      conv = true;
+      break;
+    }
+  }
+  its = std::min(its, maxit);
+  if (!conv) throw Error(NUDFT2_E_NOCONV, "refinement did not reach ir_tol");
+}
+
+// w = (A^+)^H g = A (A^H A)^{-1} g
+template <typename T>
+void solve_adj_t(Plan* P, const double2* g, double2* w, int nrhs, nudft2_solve_info* info) {
+  SolveCtx<T> sc(P, nrhs);
+  double2* z = sc.vecN();
+  int its = 0;
+  double upd = 0;
+  normal_solve<T>(sc, g, z, its, upd);
+  apply_fwd(P, z, w, nrhs, sc.cx.s);
+  ND_HIP(hipStreamSynchronize(sc.cx.s));
+  report(info, its, upd, -1);
+}
+
+// Backward pass of c = A^+ f for upstream g = dL/dc: grad_f = (A^+)^H g and,
+// when grad_pts is given, dL/d(x_j, y_j) (summed over the right-hand sides).
+template <typename T>
+void lsq_backward_t(Plan* P, const double2* f, const double2* c, const double2* g,
+                    double2* grad_f, double* grad_pts, int nrhs, nudft2_solve_info* info) {
+  SolveCtx<T> sc(P, nrhs);
+  const int64_t M = P->Mtot, N = P->Ntot;
+  double2* z = sc.vecN();
+  int its = 0;
+  double upd = 0;
+  normal_solve<T>(sc, g, z, its, upd);
+  double2* w = grad_f ? grad_f : sc.vecM();
+  apply_fwd(P, z, w, nrhs, sc.cx.s);
+  if (grad_pts) {
+    double2* r = sc.vecM();
+    apply_fwd(P, c, r, nrhs, sc.cx.s);
+    sc.axpby(1.0, f, -1.0, r, M);
+    double2* Y = (double2*)sc.cx.tmp_alloc(sizeof(double2) * 4 * N * nrhs);
+    double2* S4 = (double2*)sc.cx.tmp_alloc(sizeof(double2) * 4 * M * nrhs);
+    std::vector<KDesc> kd;
+    int64_t nmax = 0;
+    for (auto& q : P->probs) {
+      kd.push_back({q.c0, q.N(), q.nx, q.ny});
+      nmax = std::max<int64_t>(nmax, q.N());
+    }
+    auto* dkd = (KDesc*)sc.cx.pool.push(kd.data(), sizeof(KDesc) * kd.size());
+    hipLaunchKernelGGL(kscale_kernel, dim3(grid_for(nmax * nrhs), (unsigned)kd.size()), dim3(256),
+                       0, sc.cx.s, dkd, c, z, Y, N, nrhs);
+    ND_HIP(hipGetLastError());
+    apply_fwd(P, Y, S4, 4 * nrhs, sc.cx.s);
+    hipLaunchKernelGGL(grad_points_kernel, dim3(grid_for(M)), dim3(256), 0, sc.cx.s, r, w, S4,
+                       grad_pts, M, nrhs);
+    ND_HIP(hipGetLastError());
+  }
+  ND_HIP(hipStreamSynchronize(sc.cx.s));
+  report(info, its, upd, -1);
 }
 
 }  // namespace
@@ -313,9 +574,19 @@ void factor(Plan* P) {
 
 void solve(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info* info,
            bool adjoint) {
-  ND_CHECK(!adjoint, NUDFT2_E_INTERNAL, "adjoint solve not available yet");
-  if (P->hss->precision == 0) solve_t<double>(P, f, c, nrhs, info);
-  else solve_t<float>(P, f, c, nrhs, info);
+  if (P->hss->precision == 0) {
+    if (adjoint) solve_adj_t<double>(P, f, c, nrhs, info);
+    else solve_t<double>(P, f, c, nrhs, info);
+  } else {
+    if (adjoint) solve_adj_t<float>(P, f, c, nrhs, info);
+    else solve_t<float>(P, f, c, nrhs, info);
+  }
+}
+
+void lsq_backward(Plan* P, const double2* f, const double2* c, const double2* g, double2* grad_f,
+                  double* grad_pts, int nrhs, nudft2_solve_info* info) {
+  if (P->hss->precision == 0) lsq_backward_t<double>(P, f, c, g, grad_f, grad_pts, nrhs, info);
+  else lsq_backward_t<float>(P, f, c, g, grad_f, grad_pts, nrhs, info);
 }
 
 }  // namespace nd

@@ -590,9 +590,233 @@ void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t
   cx.pool.sync_reset();
 }
 
+// Adjoint of urv_solve: f = S^H c for the linear map S: f -> c of the solve
+// above.  The steps run in reverse order with their adjoints: the top-down
+// substitution backwards over the levels (Q0^H, D11^{-H}, the transposed B, R,
+// V2 and U1, D12 couplings), the root least-squares step (R^{-H}, then Q),
+// then the bottom-up sweep forwards (P, then Omega, with the rows dropped by
+// the size reduction set to zero).  c (ldc x nrhs, quadtree column order) is
+// overwritten; f (ldf x nrhs, 2D-sorted rows) receives the result.
+template <typename T>
+void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int64_t ldf,
+                   int nrhs) {
+  TmpScope scope_(cx);
+  Plan* P = cx.P;
+  const int np = (int)H.probs.size();
+  int Lmax = 0;
+  for (auto& pb : H.probs) Lmax = std::max(Lmax, pb.L);
+  std::vector<std::vector<std::vector<Mat<T>>>> Fb(np), Cb(np), Bb(np), Zb(np);
+  std::vector<Mat<T>*> mtmp;
+  for (int p = 0; p < np; ++p) {
+    Prob2<T>& pb = H.probs[p];
+    const Problem& q = P->probs[p];
+    Fb[p].resize(pb.L + 1);
+    Cb[p].resize(pb.L + 1);
+    Bb[p].resize(pb.L + 1);
+    Zb[p].resize(pb.L + 1);
+    for (int l = 0; l <= pb.L; ++l) {
+      size_t nn = (size_t)1 << (2 * l);
+      Fb[p][l].resize(nn);
+      Cb[p][l].resize(nn);
+      Bb[p][l].resize(nn);
+      Zb[p][l].resize(nn);
+    }
+    if (pb.L == 0) {
+      Mat<T> m;
+      m.p = f + q.m0;
+      m.r = (int)q.M;
+      m.c = nrhs;
+      m.ld = (int)ldf;
+      Fb[p][0][0] = m;
+      continue;
+    }
+    for (auto& nd : pb.lv[pb.L]) {
+      Mat<T> m;
+      m.p = f + nd.row0;
+      m.r = (int)nd.m;
+      m.c = nrhs;
+      m.ld = (int)ldf;
+      Fb[p][pb.L][nd.z] = m;
+      Mat<T> cm;
+      cm.p = c + q.c0 + nd.col0;
+      cm.r = nd.n;
+      cm.c = nrhs;
+      cm.ld = (int)ldc;
+      Cb[p][pb.L][nd.z] = cm;
+    }
+    for (int l = 0; l < pb.L; ++l)
+      for (int z = 0; z < (1 << (2 * l)); ++z) {
+        Mat<T>& m = Fb[p][l][z];
+        m.r = l == 0 ? pb.root_m : pb.lv[l][z].mm;
+        m.c = nrhs;
+        mtmp.push_back(&m);
+        if (l >= 1) {
+          Mat<T>& cm = Cb[p][l][z];
+          cm.r = pb.lv[l][z].nn;
+          cm.c = nrhs;
+          mtmp.push_back(&cm);
+        }
+      }
+    for (int l = 1; l <= pb.L; ++l)
+      for (int z = 0; z < (1 << (2 * l)); ++z) {
+        Mat<T>& b = Bb[p][l][z];
+        b.r = pb.lv[l][z].wU;
+        b.c = nrhs;
+        mtmp.push_back(&b);
+        Mat<T>& zz = Zb[p][l][z];
+        zz.r = pb.lv[l][z].wV;
+        zz.c = nrhs;
+        mtmp.push_back(&zz);
+      }
+  }
+  carve(P->arena, mtmp, &cx.tmp);
+  {
+    std::vector<FillDesc<T>> fz;
+    for (int p = 0; p < np; ++p)
+      for (int l = 1; l <= H.probs[p].L; ++l)
+        for (auto& b : Bb[p][l])
+          if (b.r > 0) fz.push_back({b.r, nrhs, b.ld, b.p, 0});
+    fill_batched<T>(cx.pool, fz);
+  }
+
+  // ---- adjoint of the top-down substitution
+  for (int l = Lmax; l >= 1; --l) {
+    std::vector<OrmDesc<T>> oq;
+    std::vector<CopyDesc<T, T>> cy, cpar;
+    std::vector<TrsDesc<T>> td;
+    std::vector<GemmDesc<T>> g12, gu1, gz[3], gv, gr[4];
+    for (int p = 0; p < np; ++p) {
+      Prob2<T>& pb = H.probs[p];
+      if (l > pb.L) continue;
+      for (auto& nd : pb.lv[l]) {
+        if (nd.k == 0) continue;
+        Mat<T>& cb = Cb[p][l][nd.z];
+        Mat<T>& fb = Fb[p][l][nd.z];
+        oq.push_back({nd.nn, nd.wV, nrhs, nd.Vm.ld, cb.ld, nd.Vm.p, nd.Tq.p, cb.p});
+        cy.push_back({nd.k, nrhs, cb.ld, fb.ld, cb.at(nd.nu, 0), fb.p, 0});
+        td.push_back({nd.k, nrhs, nd.D11.ld, fb.ld, nd.D11.p, fb.p});
+        Mat<T> U1 = nd.Wm.sub(0, nd.k, nd.k, nd.wU);
+        Mat<T> D12 = nd.Wm.sub(0, nd.k + nd.wU, nd.k, nd.nu);
+        if (nd.nu > 0)
+          g12.push_back({nd.nu, nrhs, nd.k, D12.ld, fb.ld, cb.ld, D12.p, fb.p, cb.p, T(-1), T(0),
+                         T(1)});
+        if (nd.wU > 0)
+          gu1.push_back({nd.wU, nrhs, nd.k, U1.ld, fb.ld, Bb[p][l][nd.z].ld, U1.p, fb.p,
+                         Bb[p][l][nd.z].p, T(-1), T(0), T(1)});
+      }
+    }
+    if (!oq.empty()) ormqr_batched<T>(cx.pool, oq, true, cx.tmp_alloc(orm_workspace<T>(oq)));
+    copy_batched<T, T>(cx.pool, cy);
+    trsv_upper_batched<T>(cx.pool, td, true);
+    gemm_batched<T>(cx.pool, g12, OpC, OpN);
+    gemm_batched<T>(cx.pool, gu1, OpC, OpN);
+    // Z-bar of a node: its siblings' b-bar through their interaction blocks
+    for (int p = 0; p < np; ++p) {
+      Prob2<T>& pb = H.probs[p];
+      if (l > pb.L) continue;
+      for (auto& nd : pb.lv[l]) {
+        if (nd.wV == 0) continue;
+        int cz = nd.z & 3;
+        for (int s = 0; s < 3; ++s) {
+          int zs = (nd.z & ~3) | (s < cz ? s : s + 1);
+          const Node2<T>& sb = pb.lv[l][zs];
+          const Mat<T>& Bs = sb.B[sib_slot<T>(zs & 3, cz)];
+          gz[s].push_back({nd.wV, nrhs, sb.wU, Bs.ld, Bb[p][l][zs].ld, Zb[p][l][nd.z].ld, Bs.p,
+                           Bb[p][l][zs].p, Zb[p][l][nd.z].p, T(1), T(0), s == 0 ? T(0) : T(1)});
+        }
+        if (nd.nu > 0)
+          gv.push_back({nd.nu, nrhs, nd.wV, nd.V2.ld, Zb[p][l][nd.z].ld, Cb[p][l][nd.z].ld,
+                        nd.V2.p, Zb[p][l][nd.z].p, Cb[p][l][nd.z].p, T(1), T(0), T(1)});
+      }
+    }
+    for (int s = 0; s < 3; ++s) gemm_batched<T>(cx.pool, gz[s], OpC, OpN);
+    gemm_batched<T>(cx.pool, gv, OpN, OpN);
+    // c2-bar into the parent's slice; b-bar into the parent's b-bar
+    for (int p = 0; p < np; ++p) {
+      Prob2<T>& pb = H.probs[p];
+      if (l > pb.L) continue;
+      for (auto& nd : pb.lv[l]) {
+        int zp = nd.z >> 2;
+        Mat<T>& par = (l == 1) ? Fb[p][0][0] : Cb[p][l - 1][zp];
+        int off = 0;
+        for (int c2 = 0; c2 < (nd.z & 3); ++c2) off += pb.lv[l][(nd.z & ~3) + c2].nu;
+        if (nd.nu > 0)
+          cpar.push_back({nd.nu, nrhs, Cb[p][l][nd.z].ld, par.ld, Cb[p][l][nd.z].p, par.at(off, 0),
+                          0});
+        if (l >= 2) {
+          const Node2<T>& pn = pb.lv[l - 1][zp];
+          if (pn.wU > 0 && nd.wU > 0)
+            gr[nd.z & 3].push_back({pn.wU, nrhs, nd.wU, nd.R.ld, Bb[p][l][nd.z].ld,
+                                    Bb[p][l - 1][zp].ld, nd.R.p, Bb[p][l][nd.z].p,
+                                    Bb[p][l - 1][zp].p, T(1), T(0), T(1)});
+        }
+      }
+    }
+    copy_batched<T, T>(cx.pool, cpar);
+    for (int s = 0; s < 4; ++s) gemm_batched<T>(cx.pool, gr[s], OpC, OpN);
+  }
+  // ---- adjoint of the root least-squares step: f_root = Q [R^{-H} c_root; 0]
+  {
+    std::vector<CopyDesc<T, T>> cd;
+    std::vector<FillDesc<T>> fz;
+    std::vector<TrsDesc<T>> td;
+    std::vector<OrmDesc<T>> od;
+    for (int p = 0; p < np; ++p) {
+      Prob2<T>& pb = H.probs[p];
+      const Problem& q = P->probs[p];
+      Mat<T>& fr = Fb[p][0][0];
+      if (pb.L == 0) cd.push_back({pb.root_n, nrhs, (int)ldc, fr.ld, c + q.c0, fr.p, 0});
+      if (pb.root_m > pb.root_n)
+        fz.push_back({pb.root_m - pb.root_n, nrhs, fr.ld, fr.at(pb.root_n, 0), 0});
+      if (pb.root_n == 0) continue;
+      td.push_back({pb.root_n, nrhs, pb.rootR.ld, fr.ld, pb.rootR.p, fr.p});
+      od.push_back({pb.root_m, pb.root_n, nrhs, pb.rootA.ld, fr.ld, pb.rootA.p, pb.rootT.p, fr.p});
+    }
+    copy_batched<T, T>(cx.pool, cd);
+    fill_batched<T>(cx.pool, fz);
+    trsv_upper_batched<T>(cx.pool, td, true);
+    if (!od.empty()) ormqr_batched<T>(cx.pool, od, false, cx.tmp_alloc(orm_workspace<T>(od)));
+  }
+  // ---- adjoint of the bottom-up sweep: unstack, P, Omega
+  for (int l = 1; l <= Lmax; ++l) {
+    std::vector<CopyDesc<T, T>> cd;
+    std::vector<FillDesc<T>> fz;
+    std::vector<OrmDesc<T>> o2, o1;
+    for (int p = 0; p < np; ++p) {
+      Prob2<T>& pb = H.probs[p];
+      if (l > pb.L) continue;
+      for (int z = 0; z < (1 << (2 * (l - 1))); ++z) {
+        Mat<T>& fp = Fb[p][l - 1][z];
+        int off = 0;
+        for (int c2 = 0; c2 < 4; ++c2) {
+          const Node2<T>& ch = pb.lv[l][4 * z + c2];
+          Mat<T>& fc = Fb[p][l][4 * z + c2];
+          if (ch.pr > 0) cd.push_back({ch.pr, nrhs, fp.ld, fc.ld, fp.at(off, 0), fc.at(ch.k, 0), 0});
+          off += ch.pr;
+        }
+      }
+      for (auto& nd : pb.lv[l]) {
+        Mat<T>& fm = Fb[p][l][nd.z];
+        if (nd.mm > nd.mchk) fz.push_back({nd.mm - nd.mchk, nrhs, fm.ld, fm.at(nd.mchk, 0), 0});
+        if (nd.k > 0) o2.push_back({nd.mchk, nd.k, nrhs, nd.Wm.ld, fm.ld, nd.Wm.p, nd.Tp.p, fm.p});
+        if (nd.sizered)
+          o1.push_back({nd.mm, nd.mchk, nrhs, nd.UD.ld, fm.ld, nd.UD.p, nd.Tom.p, fm.p});
+      }
+    }
+    copy_batched<T, T>(cx.pool, cd);
+    fill_batched<T>(cx.pool, fz);
+    if (!o2.empty()) ormqr_batched<T>(cx.pool, o2, false, cx.tmp_alloc(orm_workspace<T>(o2)));
+    if (!o1.empty()) ormqr_batched<T>(cx.pool, o1, false, cx.tmp_alloc(orm_workspace<T>(o1)));
+  }
+  cx.release_tmp();
+  cx.pool.sync_reset();
+}
+
 template void urv_factor<float>(Ctx&, HSS2<float>&);
 template void urv_factor<double>(Ctx&, HSS2<double>&);
 template void urv_solve<float>(Ctx&, HSS2<float>&, float2*, int64_t, float2*, int64_t, int);
 template void urv_solve<double>(Ctx&, HSS2<double>&, double2*, int64_t, double2*, int64_t, int);
+template void urv_solve_adj<float>(Ctx&, HSS2<float>&, float2*, int64_t, float2*, int64_t, int);
+template void urv_solve_adj<double>(Ctx&, HSS2<double>&, double2*, int64_t, double2*, int64_t, int);
 
 }  // namespace nd

@@ -197,9 +197,10 @@ def test_pchol_trace_rule():
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_trsv(prec):
-    rng = np.random.default_rng(11)
-    sizes = [(1, 1), (50, 3), (300, 2), (7, 1), (700, 2)]
+@pytest.mark.parametrize("ct", [0, 1])
+def test_trsv(prec, ct):
+    rng = np.random.default_rng(11 + ct)
+    sizes = [(1, 1), (50, 3), (300, 2), (7, 1), (700, 2), (257, 1)]
     keep, data, dims, ld, ptr = [], [], [], [], []
     for (k, nr) in sizes:
         R = np.triu(crandn(rng, k, k)) + 4 * np.eye(k)
@@ -213,8 +214,8 @@ def test_trsv(prec):
     a1, p1 = i32(dims)
     a2, p2 = i32(ld)
     a3, p3 = i64(ptr)
-    assert lib.nudft2_test_trsv(prec, len(sizes), p1, p2, p3) == 0
+    assert lib.nudft2_test_trsv(prec, len(sizes), p1, p2, p3, ct) == 0
     for R, B, tB, k, nr in data:
         X = from_dev(tB, k, nr)
-        ref = np.linalg.solve(R, B)
+        ref = np.linalg.solve(R.conj().T if ct else R, B)
         assert np.abs(X - ref).max() < 100 * TOL[prec] * max(1, np.abs(ref).max())
