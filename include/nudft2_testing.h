@@ -86,13 +86,14 @@ nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double t
 
 /* Build the recompressed HSS approximation of G (1D stage at eps/10,
  * face-splitting assembly, recompression at eps) of every problem of the plan
- * in the plan's precision, then y = H x for problem `prob` (x: DEVICE N_prob
- * complex128 in natural column order l^y + l^x ny, 0-based; y: DEVICE M_prob
- * complex128, the problem's points in the caller's order).  stages: 0 = face-splitting generators only, 1 = after the exact
+ * in the plan's precision, then Y = H X for problem `prob` (X: DEVICE nrhs x
+ * N_prob complex128, each row in natural column order l^y + l^x ny, 0-based;
+ * Y: DEVICE nrhs x M_prob complex128, the problem's points in the caller's
+ * order).  stages: 0 = face-splitting generators only, 1 = after the exact
  * orthogonalisation stage, 2 = fully recompressed.  The ranks per level are
  * left in the plan's info. */
 nudft2_status nudft2_test_hss_matvec(nudft2_plan_t plan, const double* x, double* y,
-                                     int32_t stages, int32_t prob);
+                                     int32_t stages, int32_t prob, int32_t nrhs);
 
 #ifdef __cplusplus
 }

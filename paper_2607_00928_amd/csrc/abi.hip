@@ -443,9 +443,9 @@ nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double t
 }
 
 nudft2_status nudft2_test_hss_matvec(nudft2_plan_t plan, const double* x, double* y,
-                                     int32_t stages, int32_t prob) {
+                                     int32_t stages, int32_t prob, int32_t nrhs) {
   return guard([&] {
-    ND_CHECK(plan && x && y, NUDFT2_E_INVAL, "bad arguments");
+    ND_CHECK(plan && x && y && nrhs > 0, NUDFT2_E_INVAL, "bad arguments");
     Plan* P = reinterpret_cast<Plan*>(plan);
     ND_CHECK(prob >= 0 && prob < (int)P->probs.size(), NUDFT2_E_INVAL, "problem index out of range");
     Ctx cx;
@@ -459,7 +459,8 @@ nudft2_status nudft2_test_hss_matvec(nudft2_plan_t plan, const double* x, double
       build_2d(cx, tx, ty, P->opts.eps, H, stages);
       free_1d(P, tx);
       free_1d(P, ty);
-      matvec_2d(cx, H, prob, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+      matvec_2d(cx, H, prob, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y),
+                nrhs);
       ND_HIP(hipStreamSynchronize(cx.s));
       for (void* m : H.mem) P->arena.release(m);
       H.mem.clear();

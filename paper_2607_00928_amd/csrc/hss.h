@@ -182,10 +182,10 @@ void matvec_1d(Ctx& cx, int dim, const std::vector<Tree1>& t, int prob, const do
 template <typename T>
 void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& ty, double eps,
               HSS2<T>& H, int stages = 2);
-// y = H x for problem `prob` of a recompressed HSS (test hook); x natural
-// column order, y caller's point order (FP64 in and out, problem-local).
+// Y = H X for problem `prob` of a recompressed HSS (test hook); X (nrhs x N)
+// natural column order, Y (nrhs x M) caller's point order (FP64, problem-local).
 template <typename T>
-void matvec_2d(Ctx& cx, HSS2<T>& H, int prob, const double2* x, double2* y);
+void matvec_2d(Ctx& cx, HSS2<T>& H, int prob, const double2* x, double2* y, int nrhs);
 
 // URV factorization of the recompressed HSS (bottom-up, root QR).
 template <typename T>

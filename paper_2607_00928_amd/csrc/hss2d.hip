@@ -792,34 +792,40 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
 }
 
 template <typename T>
-void matvec_2d(Ctx& cx, HSS2<T>& H, int prob, const double2* x, double2* y) {
+void matvec_2d(Ctx& cx, HSS2<T>& H, int prob, const double2* x, double2* y, int nrhs) {
   TmpScope scope_(cx);
-  // y = H x for the recompressed HSS of one problem (test hook); x natural
-  // column order, y caller's point order, FP64 in and out.
+  // Y = H X for the recompressed HSS of one problem (test hook): X (nrhs x N,
+  // natural column order), Y (nrhs x M, caller's point order), FP64.
   Plan* P = cx.P;
   const Problem& q = P->probs[prob];
   Prob2<T>& pb = H.probs[prob];
   const int L = pb.L;
   ND_CHECK(L >= 1, NUDFT2_E_INVAL, "single-node tree");
-  // x to quadtree order in working precision (host permutation, tiny sizes)
-  std::vector<int64_t> cp(q.N());
-  ND_HIP(hipMemcpy(cp.data(), P->colperm + q.c0, sizeof(int64_t) * q.N(), hipMemcpyDeviceToHost));
-  std::vector<double2> hx(q.N());
-  ND_HIP(hipMemcpy(hx.data(), x, sizeof(double2) * q.N(), hipMemcpyDeviceToHost));
-  std::vector<cplx<T>> hxq(q.N());
-  for (int64_t i = 0; i < q.N(); ++i) hxq[i] = mk<T>((T)hx[cp[i] - q.c0].x, (T)hx[cp[i] - q.c0].y);
-  cplx<T>* xq = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * q.N());
-  ND_HIP(hipMemcpy(xq, hxq.data(), sizeof(cplx<T>) * q.N(), hipMemcpyHostToDevice));
+  const int64_t N = q.N(), M = q.M;
+  // X to quadtree order in working precision (host permutation, test sizes)
+  std::vector<int64_t> cp(N);
+  ND_HIP(hipMemcpy(cp.data(), P->colperm + q.c0, sizeof(int64_t) * N, hipMemcpyDeviceToHost));
+  std::vector<double2> hx(N * nrhs);
+  ND_HIP(hipMemcpy(hx.data(), x, sizeof(double2) * N * nrhs, hipMemcpyDeviceToHost));
+  std::vector<cplx<T>> hxq(N * nrhs);
+  for (int r = 0; r < nrhs; ++r)
+    for (int64_t i = 0; i < N; ++i) {
+      double2 v = hx[r * N + cp[i] - q.c0];
+      hxq[r * N + i] = mk<T>((T)v.x, (T)v.y);
+    }
+  cplx<T>* xq = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * N * nrhs);
+  ND_HIP(hipMemcpy(xq, hxq.data(), sizeof(cplx<T>) * N * nrhs, hipMemcpyHostToDevice));
   std::vector<std::vector<cplx<T>*>> xh(L + 1), yh(L + 1);
   for (int l = 1; l <= L; ++l)
     for (auto& nd : pb.lv[l]) {
-      xh[l].push_back((cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * std::max(nd.wV, 1)));
-      yh[l].push_back((cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * std::max(nd.wU, 1)));
+      xh[l].push_back((cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * std::max(nd.wV, 1) * nrhs));
+      yh[l].push_back((cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * std::max(nd.wU, 1) * nrhs));
     }
+  auto ldv = [](int w) { return std::max(w, 1); };
   std::vector<GemmDesc<T>> g;
   for (auto& nd : pb.lv[L])
     if (nd.wV > 0)
-      g.push_back({nd.wV, 1, nd.V.r, nd.V.ld, std::max(nd.n, 1), nd.wV, nd.V.p, xq + nd.col0,
+      g.push_back({nd.wV, nrhs, nd.V.r, nd.V.ld, (int)N, nd.wV, nd.V.p, xq + nd.col0,
                    xh[L][nd.z], T(1), T(0), T(0)});
   gemm_batched<T>(cx.pool, g, OpC, OpN);
   for (int l = L - 1; l >= 1; --l) {
@@ -828,8 +834,8 @@ void matvec_2d(Ctx& cx, HSS2<T>& H, int prob, const double2* x, double2* y) {
       for (auto& nd : pb.lv[l]) {
         const Node2<T>& ch = pb.lv[l + 1][4 * nd.z + c];
         if (nd.wV == 0) continue;
-        gc.push_back({nd.wV, 1, ch.wV, ch.W.ld, std::max(ch.wV, 1), nd.wV, ch.W.p,
-                      xh[l + 1][ch.z], xh[l][nd.z], T(1), T(0), c == 0 ? T(0) : T(1)});
+        gc.push_back({nd.wV, nrhs, ch.wV, ch.W.ld, ldv(ch.wV), nd.wV, ch.W.p, xh[l + 1][ch.z],
+                      xh[l][nd.z], T(1), T(0), c == 0 ? T(0) : T(1)});
       }
       gemm_batched<T>(cx.pool, gc, OpC, OpN);
     }
@@ -841,8 +847,8 @@ void matvec_2d(Ctx& cx, HSS2<T>& H, int prob, const double2* x, double2* y) {
         int zs = (nd.z & ~3) | (s < (nd.z & 3) ? s : s + 1);
         const Node2<T>& sb = pb.lv[l][zs];
         if (nd.wU == 0) continue;
-        gs.push_back({nd.wU, 1, sb.wV, nd.B[s].ld, std::max(sb.wV, 1), nd.wU, nd.B[s].p,
-                      xh[l][zs], yh[l][nd.z], T(1), T(0), s == 0 ? T(0) : T(1)});
+        gs.push_back({nd.wU, nrhs, sb.wV, nd.B[s].ld, ldv(sb.wV), nd.wU, nd.B[s].p, xh[l][zs],
+                      yh[l][nd.z], T(1), T(0), s == 0 ? T(0) : T(1)});
       }
       gemm_batched<T>(cx.pool, gs, OpN, OpN);
     }
@@ -851,14 +857,14 @@ void matvec_2d(Ctx& cx, HSS2<T>& H, int prob, const double2* x, double2* y) {
       for (auto& nd : pb.lv[l]) {
         const Node2<T>& par = pb.lv[l - 1][nd.z >> 2];
         if (nd.wU == 0 || par.wU == 0) continue;
-        gr.push_back({nd.wU, 1, par.wU, nd.R.ld, par.wU, nd.wU, nd.R.p, yh[l - 1][par.z],
+        gr.push_back({nd.wU, nrhs, par.wU, nd.R.ld, par.wU, nd.wU, nd.R.p, yh[l - 1][par.z],
                       yh[l][nd.z], T(1), T(0), T(1)});
       }
       gemm_batched<T>(cx.pool, gr, OpN, OpN);
     }
   }
-  // leaves: y = D x + U yh, in the 2D-sorted order
-  cplx<T>* y2 = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * q.M);
+  // leaves: Y = D X + U yh, in the 2D-sorted order
+  cplx<T>* y2 = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * M * nrhs);
   std::vector<Mat<T>> Ds(pb.lv[L].size());
   std::vector<Mat<T>*> md;
   for (auto& nd : pb.lv[L]) {
@@ -881,24 +887,27 @@ void matvec_2d(Ctx& cx, HSS2<T>& H, int prob, const double2* x, double2* y) {
     d.dy = nd.dy;
     d.out = Ds[nd.z].p;
     d.ld = Ds[nd.z].ld;
-    if (nd.m > 0) ld.push_back(d);
     if (nd.m == 0) continue;
-    gu.push_back({(int)nd.m, 1, nd.wU, nd.U.ld, std::max(nd.wU, 1), (int)q.M, nd.U.p, yh[L][nd.z],
+    ld.push_back(d);
+    gu.push_back({(int)nd.m, nrhs, nd.wU, nd.U.ld, ldv(nd.wU), (int)M, nd.U.p, yh[L][nd.z],
                   y2 + (nd.row0 - q.m0), T(1), T(0), T(0)});
-    gd.push_back({(int)nd.m, 1, nd.n, Ds[nd.z].ld, std::max(nd.n, 1), (int)q.M, Ds[nd.z].p,
-                  xq + nd.col0, y2 + (nd.row0 - q.m0), T(1), T(0), T(1)});
+    gd.push_back({(int)nd.m, nrhs, nd.n, Ds[nd.z].ld, (int)N, (int)M, Ds[nd.z].p, xq + nd.col0,
+                  y2 + (nd.row0 - q.m0), T(1), T(0), T(1)});
   }
   gen_leafD<T>(cx.pool, ld, P->pts_2d);
   gemm_batched<T>(cx.pool, gu, OpN, OpN);
   gemm_batched<T>(cx.pool, gd, OpN, OpN);
-  std::vector<cplx<T>> hy(q.M);
-  std::vector<int64_t> perm(q.M);
-  ND_HIP(hipMemcpyAsync(hy.data(), y2, sizeof(cplx<T>) * q.M, hipMemcpyDeviceToHost, cx.s));
-  ND_HIP(hipMemcpyAsync(perm.data(), P->perm2d + q.m0, sizeof(int64_t) * q.M, hipMemcpyDeviceToHost, cx.s));
+  std::vector<cplx<T>> hy(M * nrhs);
+  std::vector<int64_t> perm(M);
+  ND_HIP(hipMemcpyAsync(hy.data(), y2, sizeof(cplx<T>) * M * nrhs, hipMemcpyDeviceToHost, cx.s));
+  ND_HIP(hipMemcpyAsync(perm.data(), P->perm2d + q.m0, sizeof(int64_t) * M, hipMemcpyDeviceToHost,
+                        cx.s));
   ND_HIP(hipStreamSynchronize(cx.s));
-  std::vector<double2> out(q.M);
-  for (int64_t s = 0; s < q.M; ++s) out[perm[s] - q.m0] = mk<double>(hy[s].x, hy[s].y);
-  ND_HIP(hipMemcpy(y, out.data(), sizeof(double2) * q.M, hipMemcpyHostToDevice));
+  std::vector<double2> out(M * nrhs);
+  for (int r = 0; r < nrhs; ++r)
+    for (int64_t s = 0; s < M; ++s)
+      out[r * M + perm[s] - q.m0] = mk<double>(hy[r * M + s].x, hy[r * M + s].y);
+  ND_HIP(hipMemcpy(y, out.data(), sizeof(double2) * M * nrhs, hipMemcpyHostToDevice));
   cx.release_tmp();
   cx.pool.sync_reset();
 }
@@ -907,7 +916,7 @@ template void build_2d<float>(Ctx&, const std::vector<Tree1>&, const std::vector
                               HSS2<float>&, int);
 template void build_2d<double>(Ctx&, const std::vector<Tree1>&, const std::vector<Tree1>&, double,
                                HSS2<double>&, int);
-template void matvec_2d<float>(Ctx&, HSS2<float>&, int, const double2*, double2*);
-template void matvec_2d<double>(Ctx&, HSS2<double>&, int, const double2*, double2*);
+template void matvec_2d<float>(Ctx&, HSS2<float>&, int, const double2*, double2*, int);
+template void matvec_2d<double>(Ctx&, HSS2<double>&, int, const double2*, double2*, int);
 
 }  // namespace nd

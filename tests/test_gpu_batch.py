@@ -74,7 +74,7 @@ def test_batch_hss_expansions_per_problem(order):
             xt = torch.from_numpy(x).to(DEV)
             yt = torch.empty(p.M, dtype=torch.complex128, device=DEV)
             st = lib.nudft2_test_hss_matvec(bp._handle, C.c_void_p(xt.data_ptr()),
-                                            C.c_void_p(yt.data_ptr()), stages, i)
+                                            C.c_void_p(yt.data_ptr()), stages, i, 1)
             assert st == 0, lib.nudft2_last_error()
             e = rel(yt.cpu().numpy(), G @ x)
             print(f"problem {i} ({nxs[i]}x{nys[i]}) 2D stages {stages}: {e:.2e}")

@@ -1,0 +1,105 @@
+"""Parity at the full sizes of the workloads: n = 128 (FP64 factors, 32 x 32
+sub-block checks of the HSS approximation) and n = 512 (the benchmark
+configuration), where the dense oracle is out of reach: consistent
+right-hand sides pin the solution to c_true, and the oracle's direct sums
+give sampled rows of A c and of the exact residual."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from nudft_inputs import complex_normal, config_problem
+from oracle import nudft as onu
+
+pytestmark = pytest.mark.gpu
+
+nd = pytest.importorskip("paper_2607_00928_amd")
+
+DEV = torch.device("cuda", 0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_fp64_128_subblocks_of_hss_approximation():
+    """32 x 32 blocks of the recompressed HSS matrix (FP64, eps = 1e-6)
+    against the closed-form G = A F^{-1}: a block inside one leaf box, one
+    between neighbouring boxes, one far off the diagonal."""
+    pr = config_problem("fp64_128")
+    nx = ny = 128
+    eps = 1e-6
+    plan = nd.Plan(pr.points, nx, ny, precision="fp64", eps=eps)
+    lib = nd._lib.lib
+    # rows of three regions of the unit square, columns of three frequency ranges
+    x, y = pr.points[:, 0], pr.points[:, 1]
+    regions = [
+        ((x < 1 / 16) & (y < 1 / 16), 0),                 # corner box, low frequencies
+        ((x >= 1 / 16) & (x < 1 / 8) & (y < 1 / 16), 0),  # neighbouring box, same columns
+        ((x > 0.8) & (y > 0.8), 0),                       # far box, low frequencies
+    ]
+    col_sets = [np.arange(32), np.arange(2000, 2032), np.arange(16384 - 32, 16384)]
+    rng = np.random.default_rng(8)
+    worst = 0.0
+    for (mask, _), cols in zip(regions, col_sets):
+        rows = np.sort(rng.choice(np.nonzero(mask)[0], 32, replace=False))
+        X = np.zeros((32, nx * ny), complex)
+        X[np.arange(32), cols] = 1.0
+        xt = torch.from_numpy(X).to(DEV)
+        yt = torch.empty((32, pr.M), dtype=torch.complex128, device=DEV)
+        st = lib.nudft2_test_hss_matvec(plan._handle, C.c_void_p(xt.data_ptr()),
+                                        C.c_void_p(yt.data_ptr()), 2, 0, 32)
+        assert st == 0, lib.nudft2_last_error()
+        Hb = yt.cpu().numpy()[:, rows].T               # (rows, cols)
+        Gb = onu.dense_G(pr.points[rows], nx, ny)[:, cols]
+        err = np.abs(Hb - Gb).max()
+        worst = max(worst, err)
+        print(f"block rows {rows[:3]}.. cols {cols[0]}..{cols[-1]}: max |H - G| {err:.2e}, "
+              f"max |G| {np.abs(Gb).max():.2e}")
+        # entries of G are bounded by 1; the Frobenius error is eps ||G||_F
+        assert err < 10 * eps
+    plan.close()
+
+
+def test_fp64_128_direct_solve_small_eps():
+    """FP64 factors at eps = 1e-10 without refinement: the direct solution is
+    within the approximation error of the least-squares solution, which the
+    1e-12 noise keeps within ~1e-12 of c_true."""
+    pr = config_problem("fp64_128")
+    f0 = onu.apply(pr.points, pr.c_true)
+    eta = pr.noise_dir * (pr.noise_rel * np.linalg.norm(f0) / np.linalg.norm(pr.noise_dir))
+    f = f0 + eta
+    plan = nd.Plan(pr.points, 128, 128, precision="fp64", eps=1e-10, ir_maxit=0)
+    plan.factor()
+    c = plan.solve(torch.from_numpy(f).to(DEV)).cpu().numpy()
+    e = rel(c, pr.c_true)
+    info = plan.info()
+    print(f"fp64_128 direct, eps 1e-10: {e:.2e}, ranks U {info['max_rank_u']}")
+    assert e < 1e-8
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_n512_factor_refined_solve(precision):
+    """n = 512 x 512, M = 1024^2, jitter 0.4, eps = 1e-2, refinement to 1e-12
+    (the benchmark's configuration)."""
+    pr = config_problem("n512")
+    nx = ny = 512
+    ct = torch.from_numpy(pr.c_true).to(DEV)
+    plan = nd.Plan(pr.points, nx, ny, precision=precision, eps=1e-2, ir_tol=1e-12, ir_maxit=60)
+    f = plan.apply(ct)
+    rng = np.random.default_rng(12)
+    rows = np.sort(rng.choice(pr.M, 2048, replace=False))
+    f_rows = onu.apply(pr.points[rows], pr.c_true)
+    assert rel(f.cpu().numpy()[rows], f_rows) < 1e-13
+    plan.factor()
+    c, si = plan.solve(f, return_info=True)
+    e = rel(c.cpu().numpy(), pr.c_true)
+    r_rows = onu.apply(pr.points[rows], c.cpu().numpy()) - f_rows
+    res = np.linalg.norm(r_rows) / np.linalg.norm(f_rows)
+    print(f"n512 {precision}: err vs c_true {e:.2e}, sampled residual {res:.2e}, "
+          f"{si['iterations']} iterations")
+    assert e < 1e-10
+    assert res < 1e-12
+    plan.close()

@@ -60,7 +60,7 @@ def test_hss2d_matvec(nx, ny, mx, my, delta, seed, prec, eps, stages):
     xt = torch.from_numpy(x).to(DEV)
     yt = torch.empty(pr.M, dtype=torch.complex128, device=DEV)
     st = lib.nudft2_test_hss_matvec(plan._handle, C.c_void_p(xt.data_ptr()),
-                                    C.c_void_p(yt.data_ptr()), stages, 0)
+                                    C.c_void_p(yt.data_ptr()), stages, 0, 1)
     assert st == 0, lib.nudft2_last_error()
     G = onu.dense_G(pr.points, nx, ny)
     ref = G @ x
