@@ -46,10 +46,13 @@ nudft2_status nudft2_test_mfma_layout32(const float* a, const float* b, float* d
  * gemm:  C_i = alpha op(A_i) op(B_i) + beta C_i; op 0 = none, 1 = conj
  *        transpose; mnk = (m, n, k) per problem, ld = (lda, ldb, ldc),
  *        ptrs = (A, B, C).
- * geqrf: Householder QR; mn = (m, n), ld = (lda, ldr), ptrs = (A, R, Tb) with
- *        Tb holding ceil(min(m,n)/32) blocks of 32x32.  A returns the
- *        explicit unit lower-trapezoidal reflectors V, R the triangular
- *        factor, Tb the compact-WY factors (Q = prod_j (I - V_j T_j V_j^H)).
+ * geqrf: Householder QR; mn = (m, n), ld = (lda, ldr), ptrs = (A, R, Tb).
+ *        A returns the explicit unit lower-trapezoidal reflectors V, R the
+ *        triangular factor, Tb the compact-WY factors of the column blocks
+ *        of 128 reflectors (Q = prod_b (I - V_b T_b V_b^H)): with
+ *        k = min(m, n), block b has kb = min(128, k - 128 b) columns and its
+ *        kb x kb factor T_b (leading dimension kb) starts at element
+ *        128^2 b of Tb (Tb holds 128^2 (nb - 1) + kb_last^2 elements).
  * ormqr: C <- Q C (trans = 0) or Q^H C (trans = 1) with dims = (m, k, nc),
  *        ld = (ldv, ldc), ptrs = (V, Tb, C).
  * pchol: diagonally pivoted Cholesky of Hermitian PSD K_i (w_i x w_i,

@@ -19,8 +19,8 @@ void orth(Ctx& cx, std::vector<Mat<T>>& A, std::vector<Mat<T>>& Q,
     int k = std::min(A[i].r, A[i].c);
     Rb[i].r = std::max(k, 1);
     Rb[i].c = std::max(A[i].c, 1);
-    Tb[i].r = QR_NB * QR_NB;
-    Tb[i].c = std::max(qr_nblocks(A[i].r, A[i].c), 1);
+    Tb[i].r = (int)qr_tsize(A[i].r, A[i].c);
+    Tb[i].c = 1;
     ms.push_back(&Rb[i]);
     ms.push_back(&Tb[i]);
   }

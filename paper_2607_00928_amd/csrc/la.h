@@ -49,19 +49,33 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
 // Householder QR of a batch: A (m x n, lda) is overwritten by the explicit
 // reflector matrix V (m x kmin, unit lower trapezoidal, zeros above the
 // diagonal); R (kmin x n, ldr) receives the triangular factor; Tb receives the
-// compact-WY factors, one QR_NB x QR_NB block per panel (Q = H_1 ... H_k,
-// each panel Q_j = I - V_j T_j V_j^H).  ws: workspace (see qr_workspace).
+// compact-WY factors of the column blocks of QR_OB reflectors (Q = H_1 ... H_k
+// = Q_0 Q_1 ..., Q_b = I - V_b T_b V_b^H).  Block b has kb = min(QR_OB, kmin -
+// QR_OB b) columns; its T_b (kb x kb, leading dimension kb) starts at
+// Tb + QR_OB^2 b; qr_tsize gives the element count.  The factorization runs in
+// QR_NB-column panels (one cooperative launch each) with their updates
+// confined to the block, then updates the trailing columns once per block.
+// ws: workspace (see qr_workspace).
 constexpr int QR_NB = 32;
+constexpr int QR_OB = 128;
 template <typename T>
 struct QRDesc {
   int m, n;
   int lda, ldr;
   cplx<T>* A;
   cplx<T>* R;
-  cplx<T>* Tb;   // ceil(kmin / QR_NB) blocks of QR_NB*QR_NB
+  cplx<T>* Tb;   // qr_tsize(m, n) elements
+  cplx<T>* Tw;   // internal: the panels' QR_NB x QR_NB factors of the current block
 };
 inline int qr_kmin(int m, int n) { return m < n ? m : n; }
 inline int qr_nblocks(int m, int n) { return (qr_kmin(m, n) + QR_NB - 1) / QR_NB; }
+inline int64_t qr_tsize(int m, int n) {
+  const int k = qr_kmin(m, n);
+  if (k <= 0) return 1;
+  const int nob = (k + QR_OB - 1) / QR_OB;
+  const int64_t kl = k - (int64_t)QR_OB * (nob - 1);
+  return (int64_t)QR_OB * QR_OB * (nob - 1) + kl * kl;
+}
 template <typename T>
 size_t qr_workspace(const std::vector<QRDesc<T>>& d);   // bytes
 template <typename T>

@@ -412,13 +412,62 @@ __global__ __launch_bounds__(256) void qr_panel_coop_kernel(
           d.R[r + (int64_t)(j0 + c) * d.ldr] = mk<T>(0, 0);
       }
       __syncthreads();
-      const int blk = j0 / QR_NB;
-      C2* Tb = d.Tb + (int64_t)blk * QR_NB * QR_NB;
+      const int blk = (j0 % QR_OB) / QR_NB;
+      C2* Tb = d.Tw + (int64_t)blk * QR_NB * QR_NB;
       for (int e = tid; e < QR_NB * QR_NB; e += 256) {
         int r = e % QR_NB, c = e / QR_NB;
         Tb[r + c * QR_NB] = (r < jb && c < jb) ? Ts[r][c] : mk<T>(0, 0);
       }
     }
+  }
+}
+
+// T of one block of QR_OB reflectors from its panels' factors: with
+// S = V^H V of the block's reflectors and the panels' T_j on the diagonal,
+// T(0:c0, c0:c0+jb) = -T(0:c0, 0:c0) S(0:c0, c0:c0+jb) T_j for the panels in
+// order (Q_A Q_B = I - [V_A V_B] [T_A, -T_A V_A^H V_B T_B; 0, T_B] [V_A V_B]^H).
+template <typename T>
+struct WyDesc {
+  int kb, lds;
+  const cplx<T>* Tw;   // the panels' QR_NB x QR_NB factors
+  const cplx<T>* S;    // kb x kb, lds
+  cplx<T>* Tout;       // kb x kb, leading dimension kb
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void wy_merge_kernel(const WyDesc<T>* __restrict__ descs) {
+  using C2 = cplx<T>;
+  const WyDesc<T> d = descs[blockIdx.x];
+  const int kb = d.kb, tid = threadIdx.x;
+  const int nbi = (kb + QR_NB - 1) / QR_NB;
+  C2* To = d.Tout;
+  __shared__ C2 X[QR_OB - QR_NB][QR_NB];
+  for (int e = tid; e < kb * kb; e += 256) {
+    int r = e % kb, c = e / kb;
+    int bi = r / QR_NB, bj = c / QR_NB;
+    To[r + (int64_t)c * kb] =
+        bi == bj ? d.Tw[(int64_t)bi * QR_NB * QR_NB + (r % QR_NB) + (c % QR_NB) * QR_NB]
+                 : mk<T>(0, 0);
+  }
+  __syncthreads();
+  for (int j = 1; j < nbi; ++j) {
+    const int c0 = j * QR_NB, jb = min(QR_NB, kb - c0);
+    for (int e = tid; e < c0 * jb; e += 256) {
+      int r = e % c0, c = e / c0;
+      C2 sum = mk<T>(0, 0);
+      for (int q = 0; q <= c; ++q)   // T_j upper triangular
+        sum = cadd(sum, cmul(d.S[r + (int64_t)(c0 + q) * d.lds], To[(c0 + q) + (int64_t)(c0 + c) * kb]));
+      X[r][c] = sum;
+    }
+    __syncthreads();
+    for (int e = tid; e < c0 * jb; e += 256) {
+      int r = e % c0, c = e / c0;
+      C2 sum = mk<T>(0, 0);
+      for (int q = r; q < c0; ++q)   // T(0:c0, 0:c0) upper triangular
+        sum = cadd(sum, cmul(To[r + (int64_t)q * kb], X[q][c]));
+      To[r + (int64_t)(c0 + c) * kb] = mk<T>(-sum.x, -sum.y);
+    }
+    __syncthreads();
   }
 }
 
@@ -659,8 +708,14 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     }
     dim3 grid(maxt, (unsigned)n, splits);
     double fl = 0;
-    for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
-    ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl);
+    int mm = 0, mn = 0;
+    for (auto& g : sub) {
+      fl += 8.0 * g.m * (double)g.n * g.k;
+      mm = std::max(mm, g.m);
+      mn = std::max(mn, g.n);
+    }
+    ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, mm, mn, maxk,
+                 (int)opA * 2 + (int)opB + 10 * splits);
     if (opA == OpN && opB == OpN)
       hipLaunchKernelGGL((gemm_kernel<T, OpN, OpN>), grid, dim3(256), 0, pool.stream, dd, splits);
     else if (opA == OpC && opB == OpN)
@@ -699,74 +754,125 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const int* dact, int n
   void* args[] = {(void*)&dd, (void*)&dact, (void*)&nact, (void*)&j0, (void*)&gsize,
                   (void*)&scr, (void*)&bar, (void*)&err};
   {
-    ProfScope ps(pool.stream, KC_QRPANEL, 0.0);
+    ProfScope ps(pool.stream, KC_QRPANEL, 0.0, nact, maxmr, 0, 0, gsize);
     ND_HIP(hipLaunchCooperativeKernel(kern, dim3(ngroups * gsize), dim3(256), args, 0, pool.stream));
   }
 }
 
+// per problem: W and W2 (QR_OB x n), S (QR_OB x QR_OB), the panels' factors
+// (QR_OB / QR_NB blocks of QR_NB x QR_NB)
 template <typename T>
 size_t qr_workspace(const std::vector<QRDesc<T>>& d) {
   size_t s = 0;
-  for (auto& q : d) s += (size_t)QR_NB * std::max(q.n, 1) * 2;
+  for (auto& q : d)
+    s += (size_t)QR_OB * std::max(q.n, 1) * 2 + (size_t)QR_OB * QR_OB + (size_t)QR_OB * QR_NB;
   return s * sizeof(cplx<T>) + 256;
 }
 
 template <typename T>
-void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& d, void* ws) {
-  if (d.empty()) return;
+void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& din, void* ws) {
+  if (din.empty()) return;
   if (hazards_enabled()) {
     std::vector<Region> v;
     const int64_t es = sizeof(cplx<T>);
-    for (size_t i = 0; i < d.size(); ++i) {
-      const QRDesc<T>& q = d[i];
+    for (size_t i = 0; i < din.size(); ++i) {
+      const QRDesc<T>& q = din[i];
       int kmin = qr_kmin(q.m, q.n);
       v.push_back(region(q.A, es, q.m, q.n, q.lda, true, (int)i));
       v.push_back(region(q.R, es, kmin, q.n, q.ldr, true, (int)i));
-      v.push_back(region(q.Tb, es, QR_NB * QR_NB, qr_nblocks(q.m, q.n), QR_NB * QR_NB, true,
-                         (int)i));
+      v.push_back(region(q.Tb, es, qr_tsize(q.m, q.n), 1, qr_tsize(q.m, q.n), true, (int)i));
     }
     check_hazards("geqrf", v);
   }
-  const int nb = (int)d.size();
-  auto* dd = (QRDesc<T>*)pool.push(d.data(), sizeof(QRDesc<T>) * nb);
-  int kmax = 0;
-  for (auto& q : d) kmax = std::max(kmax, qr_kmin(q.m, q.n));
-  // workspace layout per problem: W (QR_NB x n) and W2 (QR_NB x n)
-  std::vector<cplx<T>*> W(nb), W2(nb);
+  const int nb = (int)din.size();
+  std::vector<QRDesc<T>> d(din);
+  // workspace layout per problem
+  std::vector<cplx<T>*> W(nb), W2(nb), S(nb);
   {
     cplx<T>* p = (cplx<T>*)ws;
     for (int i = 0; i < nb; ++i) {
       W[i] = p;
-      p += (size_t)QR_NB * std::max(d[i].n, 1);
+      p += (size_t)QR_OB * std::max(d[i].n, 1);
       W2[i] = p;
-      p += (size_t)QR_NB * std::max(d[i].n, 1);
+      p += (size_t)QR_OB * std::max(d[i].n, 1);
+      S[i] = p;
+      p += (size_t)QR_OB * QR_OB;
+      d[i].Tw = p;
+      p += (size_t)QR_OB * QR_NB;
     }
   }
+  auto* dd = (QRDesc<T>*)pool.push(d.data(), sizeof(QRDesc<T>) * nb);
+  int kmax = 0;
+  for (auto& q : d) kmax = std::max(kmax, qr_kmin(q.m, q.n));
   std::vector<int> act;
   std::vector<GemmDesc<T>> g1, g2, g3;
-  for (int j0 = 0; j0 < kmax; j0 += QR_NB) {
-    act.clear();
+  std::vector<WyDesc<T>> wy;
+  for (int J0 = 0; J0 < kmax; J0 += QR_OB) {
+    // panels of this block, each updating the block's later columns
+    for (int j0 = J0; j0 < std::min(J0 + QR_OB, kmax); j0 += QR_NB) {
+      act.clear();
+      g1.clear(); g2.clear(); g3.clear();
+      for (int i = 0; i < nb; ++i) {
+        const QRDesc<T>& q = d[i];
+        int kmin = qr_kmin(q.m, q.n);
+        if (kmin <= j0) continue;
+        act.push_back(i);
+        int jb = std::min(QR_NB, kmin - j0);
+        int nt = std::min(q.n, J0 + QR_OB) - j0 - jb;
+        if (nt <= 0) continue;
+        int mr = q.m - j0;
+        cplx<T>* V = q.A + j0 + (int64_t)j0 * q.lda;
+        cplx<T>* At = q.A + j0 + (int64_t)(j0 + jb) * q.lda;
+        cplx<T>* Tj = q.Tw + (int64_t)((j0 % QR_OB) / QR_NB) * QR_NB * QR_NB;
+        g1.push_back({jb, nt, mr, q.lda, q.lda, QR_NB, V, At, W[i], T(1), T(0), T(0)});
+        g2.push_back({jb, nt, jb, QR_NB, QR_NB, QR_NB, Tj, W[i], W2[i], T(1), T(0), T(0)});
+        g3.push_back({mr, nt, jb, q.lda, QR_NB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
+      }
+      int* dact = (int*)pool.push(act.data(), sizeof(int) * act.size());
+      int maxmr = 0;
+      for (int i : act) maxmr = std::max(maxmr, d[i].m - j0);
+      qr_panel_launch<T>(pool, dd, dact, (int)act.size(), j0, maxmr);
+      gemm_batched<T>(pool, g1, OpC, OpN);
+      gemm_batched<T>(pool, g2, OpC, OpN);
+      gemm_batched<T>(pool, g3, OpN, OpN);
+    }
+    // block factor T_b from the panels' factors and S = V_b^H V_b
+    g1.clear();
+    wy.clear();
+    for (int i = 0; i < nb; ++i) {
+      const QRDesc<T>& q = d[i];
+      int kmin = qr_kmin(q.m, q.n);
+      if (kmin <= J0) continue;
+      int kb = std::min(QR_OB, kmin - J0);
+      cplx<T>* V = q.A + J0 + (int64_t)J0 * q.lda;
+      if (kb > QR_NB)
+        g1.push_back({kb, kb, q.m - J0, q.lda, q.lda, QR_OB, V, V, S[i], T(1), T(0), T(0)});
+      wy.push_back({kb, QR_OB, q.Tw, S[i], q.Tb + (int64_t)QR_OB * QR_OB * (J0 / QR_OB)});
+    }
+    gemm_batched<T>(pool, g1, OpC, OpN);
+    if (!wy.empty()) {
+      auto* dw = (WyDesc<T>*)pool.push(wy.data(), sizeof(WyDesc<T>) * wy.size());
+      hipLaunchKernelGGL((wy_merge_kernel<T>), dim3((unsigned)wy.size()), dim3(256), 0,
+                         pool.stream, dw);
+      ND_HIP(hipGetLastError());
+    }
+    // trailing columns beyond the block: one update with the block's reflectors
     g1.clear(); g2.clear(); g3.clear();
     for (int i = 0; i < nb; ++i) {
       const QRDesc<T>& q = d[i];
       int kmin = qr_kmin(q.m, q.n);
-      if (kmin <= j0) continue;
-      act.push_back(i);
-      int jb = std::min(QR_NB, kmin - j0);
-      int nt = q.n - j0 - jb;
+      if (kmin <= J0) continue;
+      int kb = std::min(QR_OB, kmin - J0);
+      int nt = q.n - (J0 + QR_OB);
       if (nt <= 0) continue;
-      int mr = q.m - j0;
-      cplx<T>* V = q.A + j0 + (int64_t)j0 * q.lda;
-      cplx<T>* At = q.A + j0 + (int64_t)(j0 + jb) * q.lda;
-      cplx<T>* Tb = q.Tb + (int64_t)(j0 / QR_NB) * QR_NB * QR_NB;
-      g1.push_back({jb, nt, mr, q.lda, q.lda, QR_NB, V, At, W[i], T(1), T(0), T(0)});
-      g2.push_back({jb, nt, jb, QR_NB, QR_NB, QR_NB, Tb, W[i], W2[i], T(1), T(0), T(0)});
-      g3.push_back({mr, nt, jb, q.lda, QR_NB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
+      int mr = q.m - J0;
+      cplx<T>* V = q.A + J0 + (int64_t)J0 * q.lda;
+      cplx<T>* At = q.A + J0 + (int64_t)(J0 + QR_OB) * q.lda;
+      const cplx<T>* Tb = q.Tb + (int64_t)QR_OB * QR_OB * (J0 / QR_OB);
+      g1.push_back({kb, nt, mr, q.lda, q.lda, QR_OB, V, At, W[i], T(1), T(0), T(0)});
+      g2.push_back({kb, nt, kb, kb, QR_OB, QR_OB, Tb, W[i], W2[i], T(1), T(0), T(0)});
+      g3.push_back({mr, nt, kb, q.lda, QR_OB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
     }
-    int* dact = (int*)pool.push(act.data(), sizeof(int) * act.size());
-    int maxmr = 0;
-    for (int i : act) maxmr = std::max(maxmr, d[i].m - j0);
-    qr_panel_launch<T>(pool, dd, dact, (int)act.size(), j0, maxmr);
     gemm_batched<T>(pool, g1, OpC, OpN);
     gemm_batched<T>(pool, g2, OpC, OpN);
     gemm_batched<T>(pool, g3, OpN, OpN);
@@ -778,10 +884,11 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& d, void* ws) {
 template <typename T>
 size_t orm_workspace(const std::vector<OrmDesc<T>>& d) {
   size_t s = 0;
-  for (auto& q : d) s += (size_t)QR_NB * std::max(q.nc, 1) * 2;
+  for (auto& q : d) s += (size_t)QR_OB * std::max(q.nc, 1) * 2;
   return s * sizeof(cplx<T>) + 256;
 }
 
+// C <- Q C or Q^H C block by block (QR_OB reflectors and their T_b at a time)
 template <typename T>
 void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans, void* ws) {
   if (d.empty()) return;
@@ -793,8 +900,7 @@ void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans,
       if (q.nc <= 0 || q.k <= 0) continue;
       v.push_back(region(q.C, es, q.m, q.nc, q.ldc, true, (int)i));
       v.push_back(region(q.V, es, q.m, q.k, q.ldv, false, (int)i));
-      int nbk = (q.k + QR_NB - 1) / QR_NB;
-      v.push_back(region(q.Tb, es, QR_NB * QR_NB, nbk, QR_NB * QR_NB, false, (int)i));
+      v.push_back(region(q.Tb, es, qr_tsize(q.m, q.k), 1, qr_tsize(q.m, q.k), false, (int)i));
     }
     check_hazards("ormqr", v);
   }
@@ -804,30 +910,30 @@ void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans,
     cplx<T>* p = (cplx<T>*)ws;
     for (int i = 0; i < nb; ++i) {
       W[i] = p;
-      p += (size_t)QR_NB * std::max(d[i].nc, 1);
+      p += (size_t)QR_OB * std::max(d[i].nc, 1);
       W2[i] = p;
-      p += (size_t)QR_NB * std::max(d[i].nc, 1);
+      p += (size_t)QR_OB * std::max(d[i].nc, 1);
     }
   }
   int nbl = 0;
-  for (auto& q : d) nbl = std::max(nbl, (q.k + QR_NB - 1) / QR_NB);
+  for (auto& q : d) nbl = std::max(nbl, (q.k + QR_OB - 1) / QR_OB);
   std::vector<GemmDesc<T>> g1, g2, g3;
   for (int s = 0; s < nbl; ++s) {
     g1.clear(); g2.clear(); g3.clear();
     for (int i = 0; i < nb; ++i) {
       const OrmDesc<T>& q = d[i];
-      int nblk = (q.k + QR_NB - 1) / QR_NB;
+      int nblk = (q.k + QR_OB - 1) / QR_OB;
       if (s >= nblk || q.nc <= 0) continue;
       int blk = trans ? s : nblk - 1 - s;
-      int j0 = blk * QR_NB;
-      int jb = std::min(QR_NB, q.k - j0);
+      int j0 = blk * QR_OB;
+      int kb = std::min(QR_OB, q.k - j0);
       int mr = q.m - j0;
       const cplx<T>* V = q.V + j0 + (int64_t)j0 * q.ldv;
-      const cplx<T>* Tb = q.Tb + (int64_t)blk * QR_NB * QR_NB;
+      const cplx<T>* Tb = q.Tb + (int64_t)QR_OB * QR_OB * blk;
       cplx<T>* Cp = q.C + j0;
-      g1.push_back({jb, q.nc, mr, q.ldv, q.ldc, QR_NB, V, Cp, W[i], T(1), T(0), T(0)});
-      g2.push_back({jb, q.nc, jb, QR_NB, QR_NB, QR_NB, Tb, W[i], W2[i], T(1), T(0), T(0)});
-      g3.push_back({mr, q.nc, jb, q.ldv, QR_NB, q.ldc, V, W2[i], Cp, T(-1), T(0), T(1)});
+      g1.push_back({kb, q.nc, mr, q.ldv, q.ldc, QR_OB, V, Cp, W[i], T(1), T(0), T(0)});
+      g2.push_back({kb, q.nc, kb, kb, QR_OB, QR_OB, Tb, W[i], W2[i], T(1), T(0), T(0)});
+      g3.push_back({mr, q.nc, kb, q.ldv, QR_OB, q.ldc, V, W2[i], Cp, T(-1), T(0), T(1)});
     }
     gemm_batched<T>(pool, g1, OpC, OpN);
     gemm_batched<T>(pool, g2, trans ? OpC : OpN, OpN);

@@ -4,6 +4,8 @@
 // back by nudft2_get_info.
 #pragma once
 
+#include <cstdlib>
+
 #include "common.h"
 
 namespace nd {
@@ -15,6 +17,7 @@ struct Profiler {
     hipEvent_t a, b;
     int cls;
     double flops;
+    int info[5];   // launch shape for the optional log: descriptors, max m, n, k, variant
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -37,23 +40,32 @@ struct Profiler {
     (void)cls;
     (void)fl;
   }
-  void end(hipStream_t s, int cls, double fl, hipEvent_t a) {
+  void end(hipStream_t s, int cls, double fl, hipEvent_t a, const int* info) {
     hipEvent_t b = get();
     ND_HIP(hipEventRecord(b, s));
-    recs.push_back({a, b, cls, fl});
+    Rec r{a, b, cls, fl, {0, 0, 0, 0, 0}};
+    for (int i = 0; i < 5; ++i) r.info[i] = info[i];
+    recs.push_back(r);
   }
   // fold recorded pairs into the totals (synchronises on the last event)
   void collect() {
+    // NUDFT2_PROF_LOG=<file>: one line per timed launch (class, ms, flops, shape)
+    static const char* logname = std::getenv("NUDFT2_PROF_LOG");
+    FILE* log = logname ? std::fopen(logname, "a") : nullptr;
     for (auto& r : recs) {
       ND_HIP(hipEventSynchronize(r.b));
       float t = 0;
       ND_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      if (log)
+        std::fprintf(log, "%d %.6f %.6e %d %d %d %d %d\n", r.cls, t, r.flops, r.info[0], r.info[1],
+                     r.info[2], r.info[3], r.info[4]);
       ms[r.cls] += t;
       flops[r.cls] += r.flops;
       launches[r.cls] += 1;
       pool.push_back(r.a);
       pool.push_back(r.b);
     }
+    if (log) std::fclose(log);
     recs.clear();
   }
   void reset() {
@@ -80,11 +92,14 @@ struct ProfScope {
   int cls;
   double fl;
   hipEvent_t a = nullptr;
-  ProfScope(hipStream_t st, int c, double f) : s(st), cls(c), fl(f) {
+  int info[5] = {0, 0, 0, 0, 0};
+  ProfScope(hipStream_t st, int c, double f, int nd = 0, int m = 0, int n = 0, int k = 0,
+            int var = 0)
+      : s(st), cls(c), fl(f), info{nd, m, n, k, var} {
     if (g_prof) g_prof->begin(s, cls, fl, a);
   }
   ~ProfScope() {
-    if (g_prof && a) g_prof->end(s, cls, fl, a);
+    if (g_prof && a) g_prof->end(s, cls, fl, a, info);
   }
 };
 

@@ -121,20 +121,20 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
           throw Error(NUDFT2_E_SINGULAR, "a tree node has fewer sample points than unknowns to eliminate");
         nd.pr = nd.mchk - nd.k;
         if (nd.sizered) {
-          nd.Tom.r = QR_NB * QR_NB;
-          nd.Tom.c = std::max(qr_nblocks(nd.mm, nd.wU + nd.nn), 1);
+          nd.Tom.r = (int)qr_tsize(nd.mm, nd.wU + nd.nn);
+          nd.Tom.c = 1;
           mp.push_back(&nd.Tom);
           Rr[i].r = nd.mchk;
           Rr[i].c = nd.wU + nd.nn;
           mt.push_back(&Rr[i]);
         }
         if (nd.k > 0) {
-          nd.Tq.r = QR_NB * QR_NB;
-          nd.Tq.c = std::max(qr_nblocks(nd.nn, nd.wV), 1);
+          nd.Tq.r = (int)qr_tsize(nd.nn, nd.wV);
+          nd.Tq.c = 1;
           nd.V2.r = nd.wV;
           nd.V2.c = nd.wV;
-          nd.Tp.r = QR_NB * QR_NB;
-          nd.Tp.c = std::max(qr_nblocks(nd.mchk, nd.k), 1);
+          nd.Tp.r = (int)qr_tsize(nd.mchk, nd.k);
+          nd.Tp.c = 1;
           nd.D11.r = nd.k;
           nd.D11.c = nd.k;
           mp.push_back(&nd.Tq);
@@ -362,8 +362,8 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
         throw Error(NUDFT2_E_SINGULAR, "root block has fewer rows than unknowns");
       pb.rootR.r = pb.root_n;
       pb.rootR.c = pb.root_n;
-      pb.rootT.r = QR_NB * QR_NB;
-      pb.rootT.c = std::max(qr_nblocks(pb.root_m, pb.root_n), 1);
+      pb.rootT.r = (int)qr_tsize(pb.root_m, pb.root_n);
+      pb.rootT.c = 1;
       mp.push_back(&pb.rootR);
       mp.push_back(&pb.rootT);
     }

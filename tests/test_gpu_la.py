@@ -77,17 +77,18 @@ def test_gemm_batched_ragged(prec, opa, opb):
 def test_geqrf_ormqr(prec):
     rng = np.random.default_rng(3 + prec)
     shapes = [(100, 37), (37, 100), (64, 64), (5, 3), (1030, 546), (33, 1), (300, 97),
-              (3000, 70), (257, 300)]
+              (3000, 70), (257, 300), (700, 129), (400, 256), (130, 700)]
     keep = []
     mn, ld, ptr, data = [], [], [], []
     for (m, n) in shapes:
         A = crandn(rng, m, n)
         k = min(m, n)
-        nbk = (k + 31) // 32
+        nob = (k + 127) // 128
+        tsize = 128 * 128 * (nob - 1) + (k - 128 * (nob - 1)) ** 2
         tA = to_dev(A, prec)
         # R starts as garbage: the factorization must write all of it
         tR = torch.full((n, k), 7.0 - 3.0j, dtype=CT[prec][1], device=DEV)   # k x n col-major
-        tT = torch.zeros((nbk, 32, 32), dtype=CT[prec][1], device=DEV)
+        tT = torch.full((tsize,), 5.0 + 1.0j, dtype=CT[prec][1], device=DEV)
         keep += [tA, tR, tT]
         data.append((A, tA, tR, tT))
         mn += [m, n]
@@ -203,7 +204,9 @@ def test_trsv(prec, ct):
     sizes = [(1, 1), (50, 3), (300, 2), (7, 1), (700, 2), (257, 1)]
     keep, data, dims, ld, ptr = [], [], [], [], []
     for (k, nr) in sizes:
-        R = np.triu(crandn(rng, k, k)) + 4 * np.eye(k)
+        # well-conditioned triangle (a unit-scale random triangle is
+        # exponentially ill-conditioned in k)
+        R = np.triu(crandn(rng, k, k), 1) / np.sqrt(k) + (2 + np.abs(crandn(rng, k))) * np.eye(k)
         B = crandn(rng, k, nr)
         tR, tB = to_dev(R, prec), to_dev(B, prec)
         keep += [tR, tB]
