@@ -42,10 +42,40 @@ __device__ inline double2 expi_kx(double k, double x) {
   return z;
 }
 
+// Lane moves through the DPP crossbar (no LDS traffic): the value of the
+// lane selected by CTRL in rows enabled by RMASK, 0 elsewhere.
+template <int CTRL, int RMASK>
+__device__ inline float dpp_get(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RMASK, 0xF, false));
+}
+template <int CTRL, int RMASK>
+__device__ inline double dpp_get(double v) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, RMASK, 0xF, false);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, RMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float lane_bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double lane_bcast(double v, int l) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane (all lanes must be
+// active): rotations within each row of 16 lanes (row_ror 1, 2, 4, 8) give
+// every lane its row's sum; row_bcast 15 and 31 carry the row sums into the
+// last row, whose lane 63 then holds the total.
 template <typename T>
 __device__ inline T warp_sum(T v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_get<0x121, 0xF>(v);
+  v += dpp_get<0x122, 0xF>(v);
+  v += dpp_get<0x124, 0xF>(v);
+  v += dpp_get<0x128, 0xF>(v);
+  v += dpp_get<0x142, 0xA>(v);
+  v += dpp_get<0x143, 0xC>(v);
+  return lane_bcast(v, 63);
 }
 
 }  // namespace nd

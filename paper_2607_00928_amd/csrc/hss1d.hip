@@ -128,7 +128,7 @@ void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out) {
         Node1& nd = t.lv[r.l][r.a];
         const double2* Ga = Gf[r.p] + (nd.row0 - t.m0);
         g1.push_back({t.n, t.n, (int)nd.m, (int)t.M, (int)t.M, KU[i].ld, Ga, Ga,
-                      (double2*)KU[i].p, 1.0, 0.0, 0.0});
+                      (double2*)KU[i].p, 1.0, 0.0, 0.0, 1});
         zr.push_back({t.n, nd.col0, nd.d, KU[i].ld, (double2*)KU[i].p});
       }
       gemm_batched<double>(cx.pool, g1, OpC, OpN);
@@ -154,7 +154,8 @@ void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out) {
         cd.push_back({Stmp[i].r, t.n, ldT[r.p][lc], Stmp[i].ld, Tc, (double2*)Stmp[i].p, 0});
         zr.push_back({Stmp[i].r, nd.col0, nd.d, Stmp[i].ld, (double2*)Stmp[i].p});
         g1.push_back({Stmp[i].r, Stmp[i].r, t.n, Stmp[i].ld, Stmp[i].ld, KU[i].ld,
-                      (double2*)Stmp[i].p, (double2*)Stmp[i].p, (double2*)KU[i].p, 1.0, 0.0, 0.0});
+                      (double2*)Stmp[i].p, (double2*)Stmp[i].p, (double2*)KU[i].p, 1.0, 0.0, 0.0,
+                      1});
       }
       copy_batched<double, double>(cx.pool, cd);
       zero_rc(cx.pool, zr, false);
@@ -193,8 +194,9 @@ void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out) {
       int k1 = (int)(nd.row0 - t.m0);
       int s2 = (int)(nd.row0 - t.m0 + nd.m);
       int k2 = (int)(t.M - s2);
-      g1.push_back({w, w, k1, ldp, ldp, KV[i].ld, Pc, Pc, (double2*)KV[i].p, 1.0, 0.0, 0.0});
-      g2.push_back({w, w, k2, ldp, ldp, KV[i].ld, Pc + s2, Pc + s2, (double2*)KV[i].p, 1.0, 0.0, 1.0});
+      g1.push_back({w, w, k1, ldp, ldp, KV[i].ld, Pc, Pc, (double2*)KV[i].p, 1.0, 0.0, 0.0, 1});
+      g2.push_back({w, w, k2, ldp, ldp, KV[i].ld, Pc + s2, Pc + s2, (double2*)KV[i].p, 1.0, 0.0, 1.0,
+                    1});
     }
     gemm_batched<double>(cx.pool, g1, OpC, OpN);
     gemm_batched<double>(cx.pool, g2, OpC, OpN);

@@ -532,12 +532,12 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
           Mat<double> b = to64(nd.B[s]);
           if (nd.wU > 0 && b.c > 0)
             gnc[s].push_back({nd.wU, nd.wU, b.c, b.ld, b.ld, KU[i].ld, b.p, b.p, KU[i].p, 1.0, 0.0,
-                              1.0});
+                              1.0, 1});
           int slot = Builder<T>::sib_slot(zs & 3, c);
           Mat<double> bs = to64(sb.B[slot]);
           if (nd.wV > 0 && bs.r > 0)
             gcn[s].push_back({nd.wV, nd.wV, bs.r, bs.ld, bs.ld, KV[i].ld, bs.p, bs.p, KV[i].p, 1.0,
-                              0.0, 1.0});
+                              0.0, 1.0, 1});
         }
         if (l >= 2) {
           const Node2<T>& par = bd.node(p, l - 1, z >> 2);
@@ -546,13 +546,13 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
             gx.push_back({nd.wU, par.TU.c, r.c, r.ld, par.TU.ld, XU[i].ld, r.p, par.TU.p, XU[i].p,
                           1.0, 0.0, 0.0});
             gnc[3].push_back({nd.wU, nd.wU, XU[i].c, XU[i].ld, XU[i].ld, KU[i].ld, XU[i].p,
-                              XU[i].p, KU[i].p, 1.0, 0.0, 1.0});
+                              XU[i].p, KU[i].p, 1.0, 0.0, 1.0, 1});
           }
           if (nd.wV > 0 && par.TV.c > 0) {
             gx.push_back({nd.wV, par.TV.c, w.c, w.ld, par.TV.ld, XV[i].ld, w.p, par.TV.p, XV[i].p,
                           1.0, 0.0, 0.0});
             gnc[3].push_back({nd.wV, nd.wV, XV[i].c, XV[i].ld, XV[i].ld, KV[i].ld, XV[i].p,
-                              XV[i].p, KV[i].p, 1.0, 0.0, 1.0});
+                              XV[i].p, KV[i].p, 1.0, 0.0, 1.0, 1});
           }
         }
       }

@@ -39,10 +39,13 @@ struct GemmDesc {
   cplx<T>* C;
   T ar, ai;     // alpha
   T beta;       // real beta
+  int lower;    // 1: C (square) is Hermitian, only tiles reaching its lower triangle are computed
 };
 
 // One launch for the whole list.  Two descriptors of one list must not write
-// the same output matrix (their tiles run concurrently).
+// the same output matrix (their tiles run concurrently).  A descriptor with
+// lower = 1 leaves the tiles strictly above the diagonal untouched (for
+// Hermitian products whose consumer reads the lower triangle only).
 template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB);
 
@@ -97,8 +100,9 @@ size_t orm_workspace(const std::vector<OrmDesc<T>>& d);
 template <typename T>
 void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans, void* ws);
 
-// Diagonally pivoted Cholesky of Hermitian PSD matrices K (w x w, FP64,
-// overwritten by the Schur complement) with a trace stopping rule: stop at the
+// Diagonally pivoted Cholesky of Hermitian PSD matrices K (w x w, FP64, only
+// the lower triangle is read; overwritten by the Schur complement's lower
+// triangle) with a trace stopping rule: stop at the
 // first k with sum of the remaining diagonal <= tol2 * trace(K).  Outputs the
 // factor L (w x rmax, ldl; columns in pivot order) and the rank (device int).
 struct PcholDesc {
@@ -143,5 +147,6 @@ struct FillDesc {
 };
 template <typename T>
 void fill_batched(DescPool& pool, const std::vector<FillDesc<T>>& d);
+
 
 }  // namespace nd

@@ -79,6 +79,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
   const int kend = min(d.k, kbeg + kc);
   if (kbeg >= kend && splits > 1) return;
   const int i0 = (blockIdx.x % tm) * GT, j0 = (blockIdx.x / tm) * GT;
+  if (d.lower && j0 > i0 + GT - 1) return;   // strictly above the diagonal of a Hermitian C
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   A4 accr[2][2], acci[2][2];
@@ -182,6 +183,94 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
       }
 }
 
+// Skinny products (n <= SK_N columns, B not transposed): memory-bound on A.
+// op(A) = A: one thread per row of C, the B panel staged in LDS.
+// op(A) = A^H: one wave per row of C (a dot product along a column of A).
+// blockIdx.z splits the k range; with splits > 1 the results are added
+// atomically to a pre-scaled C.
+constexpr int SK_N = 8;
+constexpr int SK_L = 64;
+
+template <typename T>
+__device__ inline void skinny_store(const GemmDesc<T>& d, int i, int j, cplx<T> v, int splits) {
+  cplx<T> out = mk<T>(d.ar * v.x - d.ai * v.y, d.ar * v.y + d.ai * v.x);
+  cplx<T>* p = d.C + (int64_t)i + (int64_t)j * d.ldc;
+  if (splits > 1) {
+    atomicAdd(&p->x, out.x);
+    atomicAdd(&p->y, out.y);
+    return;
+  }
+  if (d.beta != T(0)) {
+    cplx<T> o = *p;
+    out.x += d.beta * o.x;
+    out.y += d.beta * o.y;
+  }
+  *p = out;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_skinny_n_kernel(const GemmDesc<T>* __restrict__ descs,
+                                                            int splits) {
+  using C2 = cplx<T>;
+  const GemmDesc<T> d = descs[blockIdx.y];
+  const int i0 = blockIdx.x * 256;
+  if (i0 >= d.m || d.n <= 0) return;
+  const int kc = (d.k + splits - 1) / splits;
+  const int kb = blockIdx.z * kc, ke = min(d.k, kb + kc);
+  if (kb >= ke && splits > 1) return;
+  __shared__ C2 Bs[SK_L][SK_N];
+  const int tid = threadIdx.x, i = i0 + tid;
+  C2 acc[SK_N];
+#pragma unroll
+  for (int j = 0; j < SK_N; ++j) acc[j] = mk<T>(0, 0);
+  for (int l0 = kb; l0 < ke; l0 += SK_L) {
+    __syncthreads();
+    for (int e = tid; e < SK_L * SK_N; e += 256) {
+      int l = e % SK_L, j = e / SK_L;
+      Bs[l][j] = (l0 + l < ke && j < d.n) ? d.B[(int64_t)(l0 + l) + (int64_t)j * d.ldb] : mk<T>(0, 0);
+    }
+    __syncthreads();
+    if (i < d.m) {
+      const int lm = min(SK_L, ke - l0);
+      const C2* ap = d.A + i + (int64_t)l0 * d.lda;
+      for (int l = 0; l < lm; ++l) {
+        C2 a = ap[(int64_t)l * d.lda];
+#pragma unroll
+        for (int j = 0; j < SK_N; ++j) acc[j] = cadd(acc[j], cmul(a, Bs[l][j]));
+      }
+    }
+  }
+  if (i < d.m)
+    for (int j = 0; j < d.n; ++j) skinny_store(d, i, j, acc[j], splits);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_skinny_c_kernel(const GemmDesc<T>* __restrict__ descs,
+                                                            int splits) {
+  using C2 = cplx<T>;
+  const GemmDesc<T> d = descs[blockIdx.y];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 4 + wave;
+  if (i >= d.m || d.n <= 0) return;
+  const int kc = (d.k + splits - 1) / splits;
+  const int kb = blockIdx.z * kc, ke = min(d.k, kb + kc);
+  if (kb >= ke && splits > 1) return;
+  C2 acc[SK_N];
+#pragma unroll
+  for (int j = 0; j < SK_N; ++j) acc[j] = mk<T>(0, 0);
+  const C2* ap = d.A + (int64_t)i * d.lda;
+  for (int l = kb + lane; l < ke; l += 64) {
+    C2 a = cconj(ap[l]);
+#pragma unroll
+    for (int j = 0; j < SK_N; ++j)
+      if (j < d.n) acc[j] = cadd(acc[j], cmul(a, d.B[(int64_t)l + (int64_t)j * d.ldb]));
+  }
+  for (int j = 0; j < d.n; ++j) {
+    T re = warp_sum(acc[j].x), im = warp_sum(acc[j].y);
+    if (lane == 0) skinny_store(d, i, j, mk<T>(re, im), splits);
+  }
+}
+
 // C <- beta C for split-k launches (beta 0 writes zeros)
 template <typename T>
 __global__ void gemm_prescale_kernel(const GemmDesc<T>* __restrict__ descs) {
@@ -202,13 +291,19 @@ __global__ void gemm_prescale_kernel(const GemmDesc<T>* __restrict__ descs) {
 // compact-WY factor T (Q_panel = I - V T V^H) and the explicit V / R split
 // described in la.h.
 //
-// Cooperative panel factorization: a group of gsize workgroups factors one
-// problem's panel; every thread keeps RPT rows of the panel in registers.
-// Per column one group barrier: the partial sums (sigma^2 and the raw dots
-// conj(x)^T A(:, c) over the rows below the diagonal) are added atomically
-// into a rotating scratch buffer, after which every workgroup derives the
-// reflector (tau, beta, 1/(alpha - beta)) and the update coefficients
-// u_c = A(jj, c) + conj(scal) s_c by itself.  Groups loop over problems.
+// Panel factorization: a group of gsize workgroups factors one problem's
+// panel; workgroup w of the group holds panel rows [w 128 R, (w+1) 128 R)
+// in registers.  Wave v of a workgroup owns the column group v / 2 (QP_CG
+// consecutive columns) on the row half v % 2; lane l of it holds rows
+// half * 64 QP_R + l + 64 k (k < QP_R) of those columns, so loads and stores
+// are coalesced and the per-column sums reduce within the wave (DPP) to one
+// partial per row half.  The pivot column is published to LDS with its rows
+// at and above the diagonal zeroed (double-buffered), so the sums and the
+// update need no row masks.  With gsize > 1 the workgroups add their sums
+// atomically into a rotating scratch buffer and meet at a group barrier.
+// Every thread derives the reflector (tau, beta, 1/(alpha - beta)) and the
+// update u_c = A(jj, c) + conj(scal) s_c by itself.  Row jj (jj < QR_NB) is
+// lane jj of the first row half of workgroup 0.  Groups loop over problems.
 // Requires all workgroups to be resident (cooperative launch).
 __device__ inline void group_barrier(unsigned* cnt, unsigned target, int* err) {
   __syncthreads();
@@ -227,24 +322,46 @@ __device__ inline void group_barrier(unsigned* cnt, unsigned target, int* err) {
   __syncthreads();
 }
 
-constexpr int QS = QR_NB + 1;          // sums per column: QR_NB dots + sigma
+constexpr int QS = QR_NB + 1;          // rotating sum slots per column
 constexpr int QSCR = 3 * QS + 3 * QR_NB;   // rotating sums + rotating row copies
+constexpr int QP_NT = 1024;            // threads of a panel workgroup
+constexpr int QP_CG = 4;               // columns per thread
+// rows per lane: 4 x 4 complex FP32 or 2 x 4 complex FP64 values (32 VGPRs)
+template <typename T> struct QPanel { static constexpr int R = 2; };
+template <> struct QPanel<float> { static constexpr int R = 4; };
 
-template <typename T, int RPT>
-__global__ __launch_bounds__(256) void qr_panel_coop_kernel(
+// sum over the 64 lanes of a wave, valid in lane 63 (all lanes active)
+template <typename T>
+__device__ inline T wave_sum63(T v) {
+  v += dpp_get<0x121, 0xF>(v);
+  v += dpp_get<0x122, 0xF>(v);
+  v += dpp_get<0x124, 0xF>(v);
+  v += dpp_get<0x128, 0xF>(v);
+  v += dpp_get<0x142, 0xA>(v);
+  v += dpp_get<0x143, 0xC>(v);
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(QP_NT) void qr_panel_kernel(
     const QRDesc<T>* __restrict__ descs, const int* __restrict__ active, int nact, int j0,
     int gsize, cplx<T>* __restrict__ scratch, unsigned* __restrict__ bar, int* __restrict__ err) {
   using C2 = cplx<T>;
-  __shared__ T redr[4][QS], redi[4][QS];
-  __shared__ C2 tot[QS];
-  __shared__ C2 rowv[QR_NB];
+  constexpr int R = QPanel<T>::R;
+  constexpr int HALF = 64 * R;           // rows of one row half
+  constexpr int ROWS = 2 * HALF;         // rows of a workgroup
+  static_assert(QP_NT / 64 == 2 * (QR_NB / QP_CG), "16 waves: 8 column groups x 2 row halves");
+  __shared__ C2 X[2][ROWS];              // pivot column, double-buffered
+  __shared__ C2 sp[2][QR_NB];            // per row half column sums
+  __shared__ C2 tot[QR_NB];              // (gsize > 1) group column sums
+  __shared__ C2 rowv[QR_NB];             // row jj
   __shared__ C2 Ts[QR_NB][QR_NB + 1];
-  __shared__ C2 tau_s, scal_s;
-  __shared__ T beta_s;
-  __shared__ C2 zs[QR_NB];
   const int ngroups = gridDim.x / gsize;
   const int g = blockIdx.x / gsize, w = blockIdx.x % gsize;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int cg = wv >> 1, hf = wv & 1;
+  const int c0 = cg * QP_CG;             // first column of this thread
+  const int lr = hf * HALF + lane;       // workgroup row of k = 0
   C2* sums = scratch + (size_t)g * QSCR;
   C2* rows = sums + 3 * QS;
   unsigned* cnt = bar + g;
@@ -255,170 +372,198 @@ __global__ __launch_bounds__(256) void qr_panel_coop_kernel(
     const int kmin = min(d.m, d.n);
     const int jb = min(QR_NB, kmin - j0);
     const int mr = d.m - j0;
+    const int r0 = w * ROWS;
     C2* Ap = d.A + j0 + (int64_t)j0 * d.lda;
-    C2 a[RPT][QR_NB];
-    int rid[RPT];
+    C2 a[R][QP_CG];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      rid[q] = w * 256 * RPT + q * 256 + tid;
+    for (int k = 0; k < R; ++k) {
+      const int gi = r0 + lr + 64 * k;
 #pragma unroll
-      for (int c = 0; c < QR_NB; ++c)
-        a[q][c] = (rid[q] < mr && c < jb) ? Ap[rid[q] + (int64_t)c * d.lda] : mk<T>(0, 0);
+      for (int l = 0; l < QP_CG; ++l)
+        a[k][l] = (gi < mr && c0 + l < jb) ? Ap[gi + (int64_t)(c0 + l) * d.lda] : mk<T>(0, 0);
     }
     if (w == 0)
-      for (int e = tid; e < QR_NB * QR_NB; e += 256) Ts[e % QR_NB][e / QR_NB] = mk<T>(0, 0);
+      for (int e = tid; e < QR_NB * QR_NB; e += QP_NT) Ts[e % QR_NB][e / QR_NB] = mk<T>(0, 0);
+    if (cg == 0) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) X[0][lr + 64 * k] = r0 + lr + 64 * k > 0 ? a[k][0] : mk<T>(0, 0);
+    }
+    __syncthreads();
     for (int jj = 0; jj < jb; ++jj, ++step) {
-      C2* buf = sums + (step % 3) * QS;
-      C2* rbuf = rows + (step % 3) * QR_NB;
-      // ---- pivot column values of own rows (static register indexing)
-      C2 xq[RPT];
+      // ---- column sums conj(x)^T A(:, c) over the rows below the diagonal
+      //      (sigma^2 in the pivot's own slot), one per row half
+      C2 xv[R];
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        xq[q] = mk<T>(0, 0);
+      for (int k = 0; k < R; ++k) xv[k] = X[jj & 1][lr + 64 * k];
 #pragma unroll
-        for (int c = 0; c < QR_NB; ++c)
-          if (c == jj) xq[q] = a[q][c];
+      for (int l = 0; l < QP_CG; ++l) {
+        T sr = 0, si = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          sr += xv[k].x * a[k][l].x + xv[k].y * a[k][l].y;
+          si += xv[k].x * a[k][l].y - xv[k].y * a[k][l].x;
+        }
+        sr = wave_sum63(sr);
+        si = wave_sum63(si);
+        if (lane == 63) sp[hf][c0 + l] = mk<T>(sr, si);
       }
-      // ---- partial sums over own rows below the diagonal; publish row jj
+      const bool row_owner = r0 == 0 && hf == 0 && lane == jj;
+      if (row_owner && gsize == 1) {
 #pragma unroll
-      for (int c = 0; c <= QR_NB; ++c) {
-        T vr = 0, vi = 0;
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          if (rid[q] > jj && rid[q] < mr) {
-            C2 x = xq[q];
-            if (c == QR_NB) {
-              vr += x.x * x.x + x.y * x.y;
-            } else if (c != jj && c < jb) {
-              C2 y = a[q][c];
-              vr += x.x * y.x + x.y * y.y;   // conj(x) y
-              vi += x.x * y.y - x.y * y.x;
-            }
-          }
-        }
-        vr = warp_sum(vr);
-        vi = warp_sum(vi);
-        if (lane == 0) {
-          redr[wave][c] = vr;
-          redi[wave][c] = vi;
-        }
+        for (int l = 0; l < QP_CG; ++l) rowv[c0 + l] = a[0][l];
       }
-#pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (rid[q] == jj) {
-#pragma unroll
-          for (int c = 0; c < QR_NB; ++c) rbuf[c] = a[q][c];
-        }
       __syncthreads();
-      if (tid < QS) {
-        T vr = redr[0][tid] + redr[1][tid] + redr[2][tid] + redr[3][tid];
-        T vi = redi[0][tid] + redi[1][tid] + redi[2][tid] + redi[3][tid];
-        if (vr != T(0)) atomicAdd(&buf[tid].x, vr);
-        if (vi != T(0)) atomicAdd(&buf[tid].y, vi);
+      if (gsize > 1) {
+        C2* buf = sums + (step % 3) * QS;
+        C2* rbuf = rows + (step % 3) * QR_NB;
+        if (tid < QR_NB) {
+          const T vr = sp[0][tid].x + sp[1][tid].x, vi = sp[0][tid].y + sp[1][tid].y;
+          if (vr != T(0)) atomicAdd(&buf[tid].x, vr);
+          if (vi != T(0)) atomicAdd(&buf[tid].y, vi);
+        }
+        if (row_owner) {
+#pragma unroll
+          for (int l = 0; l < QP_CG; ++l) rbuf[c0 + l] = a[0][l];
+        }
+        if (w == 0 && tid < QS) sums[((step + 1) % 3) * QS + tid] = mk<T>(0, 0);
+        group_barrier(cnt, (++epoch) * (unsigned)gsize, err);
+        if (tid < QR_NB) {
+          tot[tid] = buf[tid];
+          rowv[tid] = rbuf[tid];
+        }
+        __syncthreads();
       }
-      if (w == 0 && tid < QS) sums[((step + 1) % 3) * QS + tid] = mk<T>(0, 0);
-      group_barrier(cnt, (++epoch) * (unsigned)gsize, err);
-      if (tid < QS) tot[tid] = buf[tid];
-      if (tid < QR_NB) rowv[tid] = rbuf[tid];
-      __syncthreads();
-      if (tid == 0) {
-        T sig = tot[QR_NB].x;
-        C2 alpha = rowv[jj];
-        C2 tau, scal;
-        T beta;
+      auto colsum = [&](int c) -> C2 {
+        return gsize == 1 ? cadd(sp[0][c], sp[1][c]) : tot[c];
+      };
+      // ---- the reflector, derived by every thread from sigma^2 and A(jj, jj)
+      C2 tau, scal;
+      T beta;
+      {
+        const T sig = colsum(jj).x;
+        const C2 alpha = rowv[jj];
         if (sig == T(0) && alpha.y == T(0)) {
           tau = mk<T>(0, 0);
           scal = mk<T>(0, 0);
           beta = alpha.x;
         } else {
-          T nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig);
+          const T nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig);
           beta = alpha.x >= T(0) ? -nrm : nrm;
           tau = mk<T>((beta - alpha.x) / beta, -alpha.y / beta);
-          T dr = alpha.x - beta, di = alpha.y;
-          T den = dr * dr + di * di;
+          const T dr = alpha.x - beta, di = alpha.y;
+          const T den = dr * dr + di * di;
           scal = mk<T>(dr / den, -di / den);
         }
-        tau_s = tau;
-        scal_s = scal;
-        beta_s = beta;
       }
-      __syncthreads();
       if (w == 0) {
-        // T(0:jj, jj) = -tau T(0:jj, 0:jj) z,  z_q = v_q^H v_jj
-        //             = scal conj(s_q) + conj(A(jj, q))
-        if (tid < jj) zs[tid] = cadd(cmul(scal_s, cconj(tot[tid])), cconj(rowv[tid]));
-        if (tid == 0) Ts[jj][jj] = tau_s;
-        __syncthreads();
-        if (tid < jj) {
-          C2 sum = mk<T>(0, 0);
-          for (int q2 = tid; q2 < jj; ++q2) sum = cadd(sum, cmul(Ts[tid][q2], zs[q2]));
-          C2 t = cmul(tau_s, sum);
-          Ts[tid][jj] = mk<T>(-t.x, -t.y);
+        // T(0:jj, jj) = -tau T(0:jj, 0:jj) z,  z_q = v_q^H v_jj = scal conj(s_q) + conj(A(jj, q)):
+        // thread (q, i) = (tid % 32, tid / 32) forms T(i, q) z_q, the 32
+        // lanes of row i sum them (row rotations, then row_bcast 15 into
+        // lanes 16..31 of each half-wave)
+        const int q = tid % QR_NB, i = tid / QR_NB;
+        C2 pr = mk<T>(0, 0);
+        if (i < jj && q >= i && q < jj) {
+          const C2 z = cadd(cmul(scal, cconj(colsum(q))), cconj(rowv[q]));
+          pr = cmul(Ts[i][q], z);
         }
+        T sr = pr.x, si = pr.y;
+        sr += dpp_get<0x121, 0xF>(sr);
+        si += dpp_get<0x121, 0xF>(si);
+        sr += dpp_get<0x122, 0xF>(sr);
+        si += dpp_get<0x122, 0xF>(si);
+        sr += dpp_get<0x124, 0xF>(sr);
+        si += dpp_get<0x124, 0xF>(si);
+        sr += dpp_get<0x128, 0xF>(sr);
+        si += dpp_get<0x128, 0xF>(si);
+        sr += dpp_get<0x142, 0xA>(sr);
+        si += dpp_get<0x142, 0xA>(si);
+        if (q == 16 && i < jj) {
+          const C2 t = cmul(tau, mk<T>(sr, si));
+          Ts[i][jj] = mk<T>(-t.x, -t.y);
+        }
+        if (tid == 0) Ts[jj][jj] = tau;
       }
-      const C2 tau = tau_s, scal = scal_s, ctau = cconj(tau_s);
-      const C2 cscal = cconj(scal);
-      // ---- update own rows
+      // ---- update (branches are uniform per wave): columns right of jj
+      //      lose conj(tau) v u_c with v = (1, scal x); column jj becomes v
+      //      below the diagonal and beta on it
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        if (rid[q] < jj || rid[q] >= mr) continue;
-        const bool diag = rid[q] == jj;
-        const C2 v = diag ? mk<T>(1, 0) : cmul(xq[q], scal);
-        const C2 f = cmul(ctau, v);
-        const C2 newjj = diag ? mk<T>(beta_s, 0) : v;
+      for (int l = 0; l < QP_CG; ++l) {
+        const int c = c0 + l;
+        if (c > jj && c < jb) {
+          const C2 u = cadd(rowv[c], cmul(cconj(scal), colsum(c)));
+          const C2 fu = cmul(cconj(tau), u);
+          const C2 sfu = cmul(scal, fu);
 #pragma unroll
-        for (int c = 0; c < QR_NB; ++c) {
-          if (c == jj) {
-            a[q][c] = newjj;
-          } else if (c > jj && c < jb) {
-            C2 u = cadd(rowv[c], cmul(cscal, tot[c]));
-            a[q][c] = csub(a[q][c], cmul(f, u));
+          for (int k = 0; k < R; ++k) a[k][l] = csub(a[k][l], cmul(xv[k], sfu));
+          if (row_owner) a[0][l] = csub(a[0][l], fu);
+        } else if (c == jj) {
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const int gi = r0 + lr + 64 * k;
+            if (gi == jj) a[k][l] = mk<T>(beta, 0);
+            else if (gi > jj) a[k][l] = cmul(a[k][l], scal);
           }
         }
       }
+      // ---- publish the next pivot column
+      if (jj + 1 < jb && cg == (jj + 1) / QP_CG) {
+        const int ln = (jj + 1) % QP_CG;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          C2 v = a[k][0];
+#pragma unroll
+          for (int l = 1; l < QP_CG; ++l)
+            if (l == ln) v = a[k][l];
+          X[(jj + 1) & 1][lr + 64 * k] = r0 + lr + 64 * k > jj + 1 ? v : mk<T>(0, 0);
+        }
+      }
+      __syncthreads();
     }
     // ---- write back: R block rows, explicit V, T
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      if (rid[q] >= mr) continue;
+    for (int k = 0; k < R; ++k) {
+      const int gi = r0 + lr + 64 * k;
 #pragma unroll
-      for (int c = 0; c < QR_NB; ++c) {
-        if (c >= jb) continue;
-        C2* pa = Ap + rid[q] + (int64_t)c * d.lda;
-        if (rid[q] < jb) {
-          C2* pr = d.R + (j0 + rid[q]) + (int64_t)(j0 + c) * d.ldr;
-          if (rid[q] <= c) {
-            *pr = a[q][c];
-            *pa = (rid[q] == c) ? mk<T>(1, 0) : mk<T>(0, 0);
+      for (int l = 0; l < QP_CG; ++l) {
+        const int c = c0 + l;
+        if (gi >= mr || c >= jb) continue;
+        C2* pa = Ap + gi + (int64_t)c * d.lda;
+        if (gi < jb) {
+          C2* pr = d.R + (j0 + gi) + (int64_t)(j0 + c) * d.ldr;
+          if (gi <= c) {
+            *pr = a[k][l];
+            *pa = gi == c ? mk<T>(1, 0) : mk<T>(0, 0);
           } else {
             *pr = mk<T>(0, 0);
-            *pa = a[q][c];
+            *pa = a[k][l];
           }
         } else {
-          *pa = a[q][c];
+          *pa = a[k][l];
         }
       }
     }
     if (w == 0) {
       // rows above the panel move from A to R; R below the panel's diagonal
       // block is zero (nothing else writes it)
-      for (int c = 0; c < jb; ++c) {
-        for (int r = tid; r < j0; r += 256) {
-          C2* pa = d.A + r + (int64_t)(j0 + c) * d.lda;
-          d.R[r + (int64_t)(j0 + c) * d.ldr] = *pa;
-          *pa = mk<T>(0, 0);
-        }
-        for (int r = j0 + jb + tid; r < kmin; r += 256)
-          d.R[r + (int64_t)(j0 + c) * d.ldr] = mk<T>(0, 0);
+      for (int e = tid; e < jb * j0; e += QP_NT) {
+        const int r = e % j0, c = e / j0;
+        C2* pa = d.A + r + (int64_t)(j0 + c) * d.lda;
+        d.R[r + (int64_t)(j0 + c) * d.ldr] = *pa;
+        *pa = mk<T>(0, 0);
       }
-      __syncthreads();
+      const int nz = kmin - j0 - jb;
+      for (int e = tid; e < jb * nz; e += QP_NT) {
+        const int r = j0 + jb + e % nz, c = e / nz;
+        d.R[r + (int64_t)(j0 + c) * d.ldr] = mk<T>(0, 0);
+      }
       const int blk = (j0 % QR_OB) / QR_NB;
       C2* Tb = d.Tw + (int64_t)blk * QR_NB * QR_NB;
-      for (int e = tid; e < QR_NB * QR_NB; e += 256) {
-        int r = e % QR_NB, c = e / QR_NB;
+      for (int e = tid; e < QR_NB * QR_NB; e += QP_NT) {
+        const int r = e % QR_NB, c = e / QR_NB;
         Tb[r + c * QR_NB] = (r < jb && c < jb) ? Ts[r][c] : mk<T>(0, 0);
       }
     }
+    __syncthreads();
   }
 }
 
@@ -570,7 +715,8 @@ __global__ __launch_bounds__(256) void pchol_panel_kernel(const PcholDesc* __res
     }
     __syncthreads();
     for (int i = tid; i < d.w; i += 256) {
-      double2 v = d.K[i + (int64_t)p * d.ldk];
+      // K is Hermitian and held in its lower triangle
+      double2 v = i >= p ? d.K[i + (int64_t)p * d.ldk] : cconj(d.K[p + (int64_t)i * d.ldk]);
       for (int q = 0; q < kk; ++q) v = csub(v, cmulc(lp[q], d.L[i + (int64_t)(k0 + q) * d.ldl]));
       // L(i,k) = (K(i,p) - sum L(i,q) conj(L(p,q))) / sqrt(d_p)
       double dd = d.d[i];
@@ -661,6 +807,40 @@ __global__ void fill_kernel(const FillDesc<T>* __restrict__ descs) {
 
 // ------------------------------------------------------------------ host API
 template <typename T>
+static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, Op opA, int maxm,
+                           int maxn, int maxk) {
+  const size_t n = sub.size();
+  const int rows_per_wg = opA == OpN ? 256 : 4;
+  const int64_t bx = (maxm + rows_per_wg - 1) / rows_per_wg;
+  int64_t wgs = bx * (int64_t)n;
+  int splits = 1;
+  const int kmin_split = opA == OpN ? 4 * SK_L : 1024;
+  if (wgs < 1024 && maxk >= 2 * kmin_split) {
+    splits = (int)std::min<int64_t>(maxk / kmin_split, (2048 + wgs - 1) / wgs);
+    splits = std::max(1, std::min(splits, 256));
+  }
+  auto* dd = (GemmDesc<T>*)pool.push(sub.data(), sizeof(GemmDesc<T>) * n);
+  if (splits > 1) {
+    int64_t mx = 0;
+    for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
+    hipLaunchKernelGGL((gemm_prescale_kernel<T>),
+                       dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
+                            (unsigned)n),
+                       dim3(256), 0, pool.stream, dd);
+  }
+  double fl = 0;
+  for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
+  ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn, maxk,
+               (int)opA * 2 + 10 * splits + 1000);
+  dim3 grid((unsigned)bx, (unsigned)n, (unsigned)splits);
+  if (opA == OpN)
+    hipLaunchKernelGGL((gemm_skinny_n_kernel<T>), grid, dim3(256), 0, pool.stream, dd, splits);
+  else
+    hipLaunchKernelGGL((gemm_skinny_c_kernel<T>), grid, dim3(256), 0, pool.stream, dd, splits);
+  ND_HIP(hipGetLastError());
+}
+
+template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB) {
   if (d.empty()) return;
   if (hazards_enabled()) {
@@ -681,15 +861,21 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
   size_t chunk = 32768;
   for (size_t s0 = 0; s0 < d.size(); s0 += chunk) {
     size_t n = std::min(chunk, d.size() - s0);
-    int maxt = 0, maxk = 0;
+    int maxt = 0, maxk = 0, maxn = 0, maxm = 0;
     std::vector<GemmDesc<T>> sub(d.begin() + s0, d.begin() + s0 + n);
     for (auto& g : sub) {
       if (g.m <= 0 || g.n <= 0) { g.m = 0; g.n = 0; continue; }
       if (g.k < 0) g.k = 0;
       maxt = std::max(maxt, ceil_div(g.m, GT) * ceil_div(g.n, GT));
       maxk = std::max(maxk, g.k);
+      maxn = std::max(maxn, g.n);
+      maxm = std::max(maxm, g.m);
     }
     if (maxt == 0) continue;
+    if (maxn <= SK_N && opB == OpN) {
+      skinny_batched<T>(pool, sub, opA, maxm, maxn, maxk);
+      continue;
+    }
     // split the k loop when the output tiles cannot fill the chip
     int64_t wgs = (int64_t)maxt * (int64_t)n;
     int splits = 1;
@@ -710,7 +896,7 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     double fl = 0;
     int mm = 0, mn = 0;
     for (auto& g : sub) {
-      fl += 8.0 * g.m * (double)g.n * g.k;
+      fl += (g.lower ? 4.0 * (double)g.m * (g.n + 1) : 8.0 * g.m * (double)g.n) * g.k;
       mm = std::max(mm, g.m);
       mn = std::max(mn, g.n);
     }
@@ -733,18 +919,18 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
 template <typename T>
 void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const int* dact, int nact, int j0,
                      int maxmr) {
-  constexpr int RPT = sizeof(T) == 4 ? 2 : 1;
-  const void* kern = (const void*)qr_panel_coop_kernel<T, RPT>;
+  const void* kern = (const void*)qr_panel_kernel<T>;
   static int max_res[2] = {0, 0};
   int& mres = max_res[sizeof(T) == 4 ? 0 : 1];
   if (mres == 0) {
     int dev = 0, cus = 0, per = 0;
     ND_HIP(hipGetDevice(&dev));
     ND_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    ND_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 256, 0));
+    ND_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, QP_NT, 0));
     mres = std::max(1, cus * std::max(per, 1));
   }
-  int gsize = std::max(1, (maxmr + 256 * RPT - 1) / (256 * RPT));
+  constexpr int rows = 128 * QPanel<T>::R;
+  int gsize = std::max(1, (maxmr + rows - 1) / rows);
   ND_CHECK(gsize <= mres, NUDFT2_E_INTERNAL, "QR panel taller than the device can hold");
   int ngroups = std::max(1, std::min(nact, mres / gsize));
   std::vector<char> zeros((size_t)ngroups * (QSCR * sizeof(cplx<T>) + sizeof(unsigned)) + 64, 0);
@@ -755,7 +941,7 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const int* dact, int n
                   (void*)&scr, (void*)&bar, (void*)&err};
   {
     ProfScope ps(pool.stream, KC_QRPANEL, 0.0, nact, maxmr, 0, 0, gsize);
-    ND_HIP(hipLaunchCooperativeKernel(kern, dim3(ngroups * gsize), dim3(256), args, 0, pool.stream));
+    ND_HIP(hipLaunchCooperativeKernel(kern, dim3(ngroups * gsize), dim3(QP_NT), args, 0, pool.stream));
   }
 }
 
@@ -983,7 +1169,7 @@ void pchol_batched(DescPool& pool, const std::vector<PcholDesc>& d) {
       int kb = std::min(PC_NB, std::min(q.rmax, q.w) - k0);
       if (kb <= 0) continue;
       const double2* Lp = q.L + (int64_t)k0 * q.ldl;
-      g.push_back({q.w, q.w, kb, q.ldl, q.ldl, q.ldk, Lp, Lp, q.K, -1.0, 0.0, 1.0});
+      g.push_back({q.w, q.w, kb, q.ldl, q.ldl, q.ldk, Lp, Lp, q.K, -1.0, 0.0, 1.0, 1});
     }
     if (!any) break;
     gemm_batched<double>(pool, g, OpN, OpC);

@@ -74,6 +74,41 @@ def test_gemm_batched_ragged(prec, opa, opb):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("opa", [0, 1])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_gemm_skinny(prec, opa, beta):
+    """Products with at most 8 columns (the memory-bound path), including
+    long k (split over workgroups) and a single row."""
+    rng = np.random.default_rng(20 + 2 * prec + opa)
+    shapes = [(1, 1, 1), (300, 1, 700), (5000, 3, 64), (17, 8, 3000), (64, 2, 40000), (1, 5, 9),
+              (257, 7, 0)]
+    mats, keep = [], []
+    mnk, ld, ptr = [], [], []
+    alpha = -0.4 + 1.1j
+    for (m, n, k) in shapes:
+        A = crandn(rng, *((m, k) if opa == 0 else (k, m)))
+        B = crandn(rng, k, n)
+        Cm = crandn(rng, m, n)
+        ta, tb, tc = to_dev(A, prec), to_dev(B, prec), to_dev(Cm, prec)
+        keep += [ta, tb, tc]
+        mats.append((A, B, Cm, tc))
+        mnk += [m, n, k]
+        ld += [max(A.shape[0], 1), max(B.shape[0], 1), max(m, 1)]
+        ptr += [ta.data_ptr(), tb.data_ptr(), tc.data_ptr()]
+    a1, p1 = i32(mnk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_gemm(prec, opa, 0, len(shapes), p1, p2, p3, alpha.real, alpha.imag, beta)
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+        oA = A if opa == 0 else A.conj().T
+        ref = alpha * (oA @ B) + beta * Cm
+        got = from_dev(tc, m, n)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(got - ref).max() < TOL[prec] * scale * max(1, k) ** 0.5 * 10, (m, n, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_geqrf_ormqr(prec):
     rng = np.random.default_rng(3 + prec)
     shapes = [(100, 37), (37, 100), (64, 64), (5, 3), (1030, 546), (33, 1), (300, 97),
