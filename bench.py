@@ -35,6 +35,7 @@ WORKLOADS = {
 
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBPS = 8000.0
 
 
 def main():
@@ -139,6 +140,22 @@ def main():
         last_plan.solve(F16)
         torch.cuda.synchronize()
         extra["solves_per_s_nrhs16"] = 16 / (time.perf_counter() - t0)
+    # direct solve (no refinement): the sweep reads every URV factor once, so
+    # its rate against the factor bytes it reads is its HBM roofline
+    last_plan.set_solve_opts(ir_maxit=0)
+    last_plan.solve(f)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        last_plan.solve(f)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    sweep_s = float(np.median(ts))
+    sb = info["sweep_bytes"]
+    sweep = {"ms": 1e3 * sweep_s, "bytes": sb, "gbps": sb / sweep_s / 1e9,
+             "frac_hbm": sb / sweep_s / (HBM_PEAK_GBPS * 1e9)}
+    last_plan.set_solve_opts(ir_maxit=60)
     # exact FP64 apply alone (its own kernel-class timing)
     last_plan.set_profiling(True)
     for _ in range(5):
@@ -191,6 +208,7 @@ def main():
         "ranks_u": info["max_rank_u"], "ranks_v": info["max_rank_v"],
         "factor_bytes": info["factor_bytes"],
         "kernels": kernels,
+        "sweep": sweep,
         "apply": {"ms": apply_ms, "tflops": apply_tf, "frac_fp64_peak": apply_tf / FP64_PEAK_TFLOPS},
         "fp64_path": fp64,
         "roofline": roof,

@@ -67,6 +67,10 @@ typedef struct {
                             c += S S^* A^*(f - Ac) (exact least squares for any f) */
   void* stream;       /* hipStream_t; NULL = default stream                     */
   size_t mem_cap;     /* device bytes the plan may hold; 0 = no cap             */
+  int32_t graph;      /* 1: each solve call captures its refinement iteration
+                         (HSS solve sweep, update, exact apply, residual, norms)
+                         once into a HIP graph and replays it; 0: eager launches.
+                         Kernel profiling (nudft2_set_profiling) runs eagerly. */
 } nudft2_opts;
 
 /* Per-solve report (host memory, may be NULL). */
@@ -84,6 +88,9 @@ typedef struct {
   int32_t max_rank_v[16]; /* per level 0..L: largest column rank                */
   int64_t factor_bytes;   /* device bytes held by the factors                 */
   double factor_flops;    /* flops counted over the factorization's operations */
+  int64_t sweep_bytes;    /* factor bytes one solve sweep reads (Algorithm 4.1's
+                             bottom-up, root and top-down steps, per pass;
+                             right-hand sides excluded): its HBM traffic   */
   double t_plan_ms, t_compress_ms, t_facesplit_ms, t_recompress_ms, t_urv_ms;
   /* kernel timing while profiling is on (nudft2_set_profiling), per class:
    * 0 = exact FP64 apply, 1 = FP32 matrix-core GEMM, 2 = FP64 matrix-core
@@ -136,6 +143,13 @@ nudft2_status nudft2_factor(nudft2_plan_t plan);
  * (null pointer, nrhs <= 0), E_STATE (not factored), E_NOCONV, E_DEVICE. */
 nudft2_status nudft2_solve(nudft2_plan_t plan, const double* f, double* c,
                            int32_t nrhs, nudft2_solve_info* info);
+
+/* Change the refinement options (ir_tol, ir_maxit, refine; meaning as in
+ * nudft2_opts) of a plan, factored or not: one factorization serves direct
+ * and refined solves.  Errors: E_INVAL (null plan, ir_tol < 0, ir_maxit < 0,
+ * refine not 0 or 1). */
+nudft2_status nudft2_set_solve_opts(nudft2_plan_t plan, double ir_tol, int32_t ir_maxit,
+                                    int32_t refine);
 
 /* Adjoint of the least-squares solution operator: w = (A^+)^* g =
  * A (A^*A)^{-1} g for g of shape nrhs x nx x ny, w of shape nrhs x M (DEVICE,

@@ -25,8 +25,9 @@ __all__ = ["Plan", "BatchPlan", "NudftError", "lsq_solve"]
 _PREC = {"fp64": 0, "fp32": 1, 0: 0, 1: 1}
 
 
-def _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap):
+def _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph=True):
     o = _lib.default_opts()
+    o.graph = 1 if graph else 0
     o.precision = _PREC[precision]
     o.eps = float(eps)
     o.leaf = int(leaf)
@@ -72,11 +73,22 @@ class _PlanBase:
                     max_rank_u=list(inf.max_rank_u)[:L + 1],
                     max_rank_v=list(inf.max_rank_v)[:L + 1],
                     factor_bytes=inf.factor_bytes, factor_flops=inf.factor_flops,
+                    sweep_bytes=inf.sweep_bytes,
                     t_plan_ms=inf.t_plan_ms, t_compress_ms=inf.t_compress_ms,
                     t_facesplit_ms=inf.t_facesplit_ms,
                     t_recompress_ms=inf.t_recompress_ms, t_urv_ms=inf.t_urv_ms,
                     kernel_ms=list(inf.kernel_ms), kernel_flops=list(inf.kernel_flops),
                     kernel_launches=list(inf.kernel_launches))
+
+    def set_solve_opts(self, ir_tol: float | None = None, ir_maxit: int | None = None,
+                       refine: int | None = None):
+        """Change the refinement options of this plan (factored or not)."""
+        tol = self.ir_tol if ir_tol is None else float(ir_tol)
+        maxit = self.ir_maxit if ir_maxit is None else int(ir_maxit)
+        ref = self.refine if refine is None else int(refine)
+        check(lib.nudft2_set_solve_opts(self._handle, tol, maxit, ref), "nudft2_set_solve_opts")
+        self.ir_tol, self.ir_maxit, self.refine = tol, maxit, ref
+        return self
 
     def set_profiling(self, on: bool = True):
         check(lib.nudft2_set_profiling(self._handle, 1 if on else 0), "nudft2_set_profiling")
@@ -176,7 +188,7 @@ class Plan(_PlanBase):
 
     def __init__(self, points, nx: int, ny: int, *, precision="fp32", eps=1e-4,
                  leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0, stream=None,
-                 mem_cap=0, device=None):
+                 mem_cap=0, device=None, graph=True):
         pts = _host_points(points)
         self.M = pts.shape[0]
         self.nx, self.ny = int(nx), int(ny)
@@ -184,7 +196,8 @@ class Plan(_PlanBase):
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         if stream is None:
             stream = _current_stream(dev)
-        o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap)
+        o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph)
+        self.ir_tol, self.ir_maxit, self.refine = float(ir_tol), int(ir_maxit), int(refine)
         h = C.c_void_p()
         with torch.cuda.device(dev):
             st = lib.nudft2_plan(C.byref(h), _lib.dptr(pts), self.M, self.nx, self.ny,
@@ -200,7 +213,7 @@ class BatchPlan(_PlanBase):
 
     def __init__(self, points_list, nx_list, ny_list, *, precision="fp32",
                  eps=1e-4, leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0,
-                 stream=None, mem_cap=0, device=None):
+                 stream=None, mem_cap=0, device=None, graph=True):
         pts = [_host_points(p) for p in points_list]
         m_off = np.zeros(len(pts) + 1, dtype=np.int64)
         m_off[1:] = np.cumsum([p.shape[0] for p in pts])
@@ -214,7 +227,8 @@ class BatchPlan(_PlanBase):
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         if stream is None:
             stream = _current_stream(dev)
-        o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap)
+        o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph)
+        self.ir_tol, self.ir_maxit, self.refine = float(ir_tol), int(ir_maxit), int(refine)
         h = C.c_void_p()
         with torch.cuda.device(dev):
             st = lib.nudft2_plan_batch(

@@ -28,6 +28,7 @@ class Opts(C.Structure):
         ("refine", C.c_int32),
         ("stream", C.c_void_p),
         ("mem_cap", C.c_size_t),
+        ("graph", C.c_int32),
     ]
 
 
@@ -47,6 +48,7 @@ class Info(C.Structure):
         ("max_rank_v", C.c_int32 * 16),
         ("factor_bytes", C.c_int64),
         ("factor_flops", C.c_double),
+        ("sweep_bytes", C.c_int64),
         ("t_plan_ms", C.c_double),
         ("t_compress_ms", C.c_double),
         ("t_facesplit_ms", C.c_double),
@@ -92,6 +94,7 @@ def _load():
         "nudft2_get_info": (C.c_int, [P, C.POINTER(Info)]),
         "nudft2_destroy": (C.c_int, [P]),
         "nudft2_set_profiling": (C.c_int, [P, C.c_int32]),
+        "nudft2_set_solve_opts": (C.c_int, [P, C.c_double, C.c_int32, C.c_int32]),
         "nudft2_strerror": (C.c_char_p, [C.c_int]),
         "nudft2_last_error": (C.c_char_p, []),
         "nudft2_test_binning": (C.c_int, [DP, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
@@ -100,6 +103,9 @@ def _load():
         "nudft2_test_mfma_layout32": (C.c_int, [FP, FP, FP]),
         "nudft2_test_gemm": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, I32P, I32P,
                                        I64P, C.c_double, C.c_double, C.c_double]),
+        "nudft2_test_gemm_cfg": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, I32P,
+                                           I32P, I64P, C.c_double, C.c_double, C.c_double,
+                                           C.c_int32, C.POINTER(C.c_float)]),
         "nudft2_test_geqrf": (C.c_int, [C.c_int32, C.c_int32, I32P, I32P, I64P]),
         "nudft2_test_ormqr": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, I32P, I32P, I64P]),
         "nudft2_test_pchol": (C.c_int, [C.c_int32, I32P, I32P, I64P, C.c_double, I32P, I32P]),

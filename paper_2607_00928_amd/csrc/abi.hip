@@ -92,7 +92,8 @@ static void need_device() {
 
 template <typename T>
 static void test_gemm(int opA, int opB, int nb, const int32_t* mnk, const int32_t* ld,
-                      const int64_t* ptrs, double ar, double ai, double beta) {
+                      const int64_t* ptrs, double ar, double ai, double beta, int splits = 0,
+                      float* ms = nullptr) {
   std::vector<GemmDesc<T>> d(nb);
   for (int i = 0; i < nb; ++i)
     d[i] = GemmDesc<T>{mnk[3 * i], mnk[3 * i + 1], mnk[3 * i + 2], ld[3 * i], ld[3 * i + 1],
@@ -100,8 +101,22 @@ static void test_gemm(int opA, int opB, int nb, const int32_t* mnk, const int32_
                        (const cplx<T>*)ptrs[3 * i + 1], (cplx<T>*)ptrs[3 * i + 2], (T)ar,
                        (T)ai, (T)beta};
   DescPool pool;
-  pool.init(1 << 20, nullptr);
-  gemm_batched<T>(pool, d, (Op)opA, (Op)opB);
+  pool.init(std::max<size_t>(1 << 20, sizeof(GemmDesc<T>) * (size_t)nb * 2 + 4096), nullptr);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms) {
+    ND_HIP(hipEventCreate(&e0));
+    ND_HIP(hipEventCreate(&e1));
+    ND_HIP(hipStreamSynchronize(nullptr));
+    ND_HIP(hipEventRecord(e0, nullptr));
+  }
+  gemm_batched<T>(pool, d, (Op)opA, (Op)opB, splits);
+  if (ms) {
+    ND_HIP(hipEventRecord(e1, nullptr));
+    ND_HIP(hipEventSynchronize(e1));
+    ND_HIP(hipEventElapsedTime(ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
   pool.sync_reset();
 }
 
@@ -166,6 +181,7 @@ void nudft2_default_opts(nudft2_opts* o) {
   o->refine = 0;
   o->stream = nullptr;
   o->mem_cap = 0;
+  o->graph = 1;
 }
 
 const char* nudft2_strerror(nudft2_status s) {
@@ -292,6 +308,19 @@ nudft2_status nudft2_get_info(nudft2_plan_t plan, nudft2_info* info) {
   });
 }
 
+nudft2_status nudft2_set_solve_opts(nudft2_plan_t plan, double ir_tol, int32_t ir_maxit,
+                                    int32_t refine) {
+  return guard([&] {
+    ND_CHECK(plan != nullptr, NUDFT2_E_INVAL, "null plan");
+    ND_CHECK(ir_tol >= 0 && ir_maxit >= 0 && (refine == 0 || refine == 1), NUDFT2_E_INVAL,
+             "bad refinement options");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    P->opts.ir_tol = ir_tol;
+    P->opts.ir_maxit = ir_maxit;
+    P->opts.refine = refine;
+  });
+}
+
 nudft2_status nudft2_set_profiling(nudft2_plan_t plan, int32_t on) {
   return guard([&] {
     ND_CHECK(plan != nullptr, NUDFT2_E_INVAL, "null plan");
@@ -344,6 +373,18 @@ nudft2_status nudft2_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t n
     need_device();
     if (prec == 0) test_gemm<double>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta);
     else test_gemm<float>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta);
+  });
+}
+
+nudft2_status nudft2_test_gemm_cfg(int32_t prec, int32_t opA, int32_t opB, int32_t nb,
+                                   const int32_t* mnk, const int32_t* ld, const int64_t* ptrs,
+                                   double ar, double ai, double beta, int32_t splits,
+                                   float* ms) {
+  return guard([&] {
+    ND_CHECK(mnk && ld && ptrs && nb > 0 && splits >= 0, NUDFT2_E_INVAL, "bad arguments");
+    need_device();
+    if (prec == 0) test_gemm<double>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta, splits, ms);
+    else test_gemm<float>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta, splits, ms);
   });
 }
 

@@ -24,19 +24,22 @@ struct Mat {
 
 // Execution context: stream, descriptor pool and temporaries.  Temporaries
 // are released in scopes: release_tmp() frees what was allocated since the
-// innermost TmpScope began.
+// innermost TmpScope began.  keep (graph capture): scopes neither wait nor
+// release; everything stays until the context is destroyed.
 struct Ctx {
   Plan* P = nullptr;
   hipStream_t s = nullptr;
   DescPool pool;
   std::vector<void*> tmp;
   size_t base = 0;
+  bool keep = false;
   void* tmp_alloc(size_t bytes) {
     void* p = P->arena.alloc(bytes);
     tmp.push_back(p);
     return p;
   }
   void release_tmp() {
+    if (keep) return;
     ND_HIP(hipStreamSynchronize(s));
     for (size_t i = base; i < tmp.size(); ++i) P->arena.release(tmp[i]);
     tmp.resize(base);
@@ -52,6 +55,10 @@ struct TmpScope {
   size_t saved;
   explicit TmpScope(Ctx& cx) : c(cx), saved(cx.base) { c.base = c.tmp.size(); }
   ~TmpScope() {
+    if (c.keep) {
+      c.base = saved;
+      return;
+    }
     (void)hipStreamSynchronize(c.s);
     for (size_t i = c.base; i < c.tmp.size(); ++i) c.P->arena.release(c.tmp[i]);
     c.tmp.resize(c.base);
@@ -195,6 +202,10 @@ void urv_factor(Ctx& cx, HSS2<T>& H);
 // order, working precision).  f is overwritten.
 template <typename T>
 void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t ldc, int nrhs);
+// Bytes of the factors one solve sweep reads per pass (the algorithmic HBM
+// traffic of urv_solve, right-hand sides excluded).
+template <typename T>
+int64_t urv_sweep_bytes(const HSS2<T>& H);
 // Adjoint of urv_solve: c (ldc x nrhs, quadtree column order, working
 // precision, overwritten) -> f (ldf x nrhs, 2D-sorted rows, working precision).
 template <typename T>

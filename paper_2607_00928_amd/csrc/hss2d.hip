@@ -478,90 +478,142 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
       std::vector<Ref> nodes;
       bd.each_level(l, [&](int p, int z) { nodes.push_back({p, z}); });
       if (nodes.empty()) continue;
-      // FP64 copies of the blocks that enter the Grams
-      auto to64 = [&](const Mat<T>& m) -> Mat<double> {
-        Mat<double> o;
-        o.r = m.r;
-        o.c = m.c;
-        if (std::is_same<T, double>::value) {
-          o.p = (double2*)m.p;
-          o.ld = m.ld;
+      // Grams K^U = sum_s B_{a,s} B_{a,s}^H + X X^H, K^V = sum_s B_{s,a}^H B_{s,a} + Y Y^H
+      // with X = R_a T^U_parent, Y = W_a T^V_parent (levels >= 2), lower
+      // triangles only.  They are formed on MFMA in FP32 when T = float and
+      // eps >= 5e-3 (the trace threshold eps^2 sits far above FP32 rounding of
+      // the Gram entries), else in FP64; the rank decisions (pivoted Cholesky
+      // and its trace test) always run on FP64 Grams.
+      std::vector<Mat<double>> KU(nodes.size()), KV(nodes.size());
+      auto form_grams = [&](auto tag) {
+        using G = decltype(tag);
+        // a block in the Gram precision: the block itself or a converted copy
+        auto conv = [&](const Mat<T>& m) -> Mat<G> {
+          Mat<G> o;
+          o.r = m.r;
+          o.c = m.c;
+          if constexpr (std::is_same<T, G>::value) {
+            o.p = m.p;
+            o.ld = m.ld;
+          } else {
+            o.ld = std::max(m.r, 1);
+            o.p = (cplx<G>*)cx.tmp_alloc(sizeof(cplx<G>) * (size_t)o.ld * std::max(m.c, 1));
+            std::vector<CopyDesc<G, T>> cd{{m.r, m.c, m.ld, o.ld, m.p, o.p, 0}};
+            if (m.r > 0 && m.c > 0) copy_batched<G, T>(cx.pool, cd);
+          }
           return o;
+        };
+        // the parents' FP64 weights T in the Gram precision (one copy per parent)
+        std::map<std::pair<int, int>, Mat<G>> tconv;
+        auto convT = [&](const Mat<double>& m, int p, int key) -> Mat<G> {
+          if constexpr (std::is_same<G, double>::value) {
+            (void)p;
+            (void)key;
+            return m;
+          } else {
+            auto it = tconv.find({p, key});
+            if (it != tconv.end()) return it->second;
+            Mat<G> o;
+            o.r = m.r;
+            o.c = m.c;
+            o.ld = std::max(m.r, 1);
+            o.p = (cplx<G>*)cx.tmp_alloc(sizeof(cplx<G>) * (size_t)o.ld * std::max(m.c, 1));
+            std::vector<CopyDesc<G, double>> cd{{m.r, m.c, m.ld, o.ld, m.p, o.p, 0}};
+            if (m.r > 0 && m.c > 0) copy_batched<G, double>(cx.pool, cd);
+            tconv[{p, key}] = o;
+            return o;
+          }
+        };
+        std::vector<Mat<G>> GU(nodes.size()), GV(nodes.size()), XU(nodes.size()),
+            XV(nodes.size());
+        std::vector<Mat<G>*> mk;
+        for (size_t i = 0; i < nodes.size(); ++i) {
+          Node2<T>& nd = bd.node(nodes[i].p, l, nodes[i].z);
+          GU[i].r = GU[i].c = nd.wU;
+          GV[i].r = GV[i].c = nd.wV;
+          mk.push_back(&GU[i]);
+          mk.push_back(&GV[i]);
+          if (l >= 2) {
+            const Node2<T>& par = bd.node(nodes[i].p, l - 1, nodes[i].z >> 2);
+            XU[i].r = nd.wU;
+            XU[i].c = par.TU.c;
+            XV[i].r = nd.wV;
+            XV[i].c = par.TV.c;
+            mk.push_back(&XU[i]);
+            mk.push_back(&XV[i]);
+          }
         }
-        o.ld = std::max(m.r, 1);
-        o.p = (double2*)cx.tmp_alloc(sizeof(double2) * (size_t)o.ld * std::max(m.c, 1));
-        std::vector<CopyDesc<double, T>> cd{{m.r, m.c, m.ld, o.ld, m.p, o.p, 0}};
-        if (m.r > 0 && m.c > 0) copy_batched<double, T>(cx.pool, cd);
-        return o;
+        carve(P->arena, mk, &cx.tmp);
+        // one launch per accumulation slot: a batched launch must not hold two
+        // descriptors that update the same output matrix
+        std::vector<GemmDesc<G>> gx, gnc[4], gcn[4];
+        std::vector<FillDesc<G>> fz;
+        for (size_t i = 0; i < nodes.size(); ++i) {
+          int p = nodes[i].p, z = nodes[i].z;
+          Node2<T>& nd = bd.node(p, l, z);
+          int c = z & 3;
+          if (nd.wU > 0) fz.push_back({nd.wU, nd.wU, GU[i].ld, GU[i].p, 0});
+          if (nd.wV > 0) fz.push_back({nd.wV, nd.wV, GV[i].ld, GV[i].p, 0});
+          for (int s = 0; s < 3; ++s) {
+            int zs = (z & ~3) | Builder<T>::sib_child(c, s);
+            Node2<T>& sb = bd.node(p, l, zs);
+            Mat<G> b = conv(nd.B[s]);
+            if (nd.wU > 0 && b.c > 0)
+              gnc[s].push_back({nd.wU, nd.wU, b.c, b.ld, b.ld, GU[i].ld, b.p, b.p, GU[i].p, G(1),
+                                G(0), G(1), 1});
+            int slot = Builder<T>::sib_slot(zs & 3, c);
+            Mat<G> bs = conv(sb.B[slot]);
+            if (nd.wV > 0 && bs.r > 0)
+              gcn[s].push_back({nd.wV, nd.wV, bs.r, bs.ld, bs.ld, GV[i].ld, bs.p, bs.p, GV[i].p,
+                                G(1), G(0), G(1), 1});
+          }
+          if (l >= 2) {
+            const Node2<T>& par = bd.node(p, l - 1, z >> 2);
+            Mat<G> r = conv(nd.R), w = conv(nd.W);
+            if (nd.wU > 0 && par.TU.c > 0) {
+              Mat<G> tu = convT(par.TU, p, 2 * (z >> 2));
+              gx.push_back({nd.wU, par.TU.c, r.c, r.ld, tu.ld, XU[i].ld, r.p, tu.p, XU[i].p, G(1),
+                            G(0), G(0)});
+              gnc[3].push_back({nd.wU, nd.wU, XU[i].c, XU[i].ld, XU[i].ld, GU[i].ld, XU[i].p,
+                                XU[i].p, GU[i].p, G(1), G(0), G(1), 1});
+            }
+            if (nd.wV > 0 && par.TV.c > 0) {
+              Mat<G> tv = convT(par.TV, p, 2 * (z >> 2) + 1);
+              gx.push_back({nd.wV, par.TV.c, w.c, w.ld, tv.ld, XV[i].ld, w.p, tv.p, XV[i].p, G(1),
+                            G(0), G(0)});
+              gnc[3].push_back({nd.wV, nd.wV, XV[i].c, XV[i].ld, XV[i].ld, GV[i].ld, XV[i].p,
+                                XV[i].p, GV[i].p, G(1), G(0), G(1), 1});
+            }
+          }
+        }
+        fill_batched<G>(cx.pool, fz);
+        gemm_batched<G>(cx.pool, gx, OpN, OpN);
+        for (int s = 0; s < 4; ++s) {
+          gemm_batched<G>(cx.pool, gnc[s], OpN, OpC);
+          gemm_batched<G>(cx.pool, gcn[s], OpC, OpN);
+        }
+        if constexpr (std::is_same<G, double>::value) {
+          KU = GU;
+          KV = GV;
+        } else {
+          std::vector<Mat<double>*> mkd;
+          for (size_t i = 0; i < nodes.size(); ++i) {
+            KU[i].r = KU[i].c = GU[i].r;
+            KV[i].r = KV[i].c = GV[i].r;
+            mkd.push_back(&KU[i]);
+            mkd.push_back(&KV[i]);
+          }
+          carve(P->arena, mkd, &cx.tmp);
+          std::vector<CopyDesc<double, G>> cd;
+          for (size_t i = 0; i < nodes.size(); ++i) {
+            if (GU[i].r > 0) cd.push_back({GU[i].r, GU[i].c, GU[i].ld, KU[i].ld, GU[i].p, KU[i].p, 0});
+            if (GV[i].r > 0) cd.push_back({GV[i].r, GV[i].c, GV[i].ld, KV[i].ld, GV[i].p, KV[i].p, 0});
+          }
+          copy_batched<double, G>(cx.pool, cd);
+        }
       };
-      std::vector<Mat<double>> KU(nodes.size()), KV(nodes.size()), XU(nodes.size()),
-          XV(nodes.size());
-      std::vector<Mat<double>*> mk;
-      for (size_t i = 0; i < nodes.size(); ++i) {
-        Node2<T>& nd = bd.node(nodes[i].p, l, nodes[i].z);
-        KU[i].r = KU[i].c = nd.wU;
-        KV[i].r = KV[i].c = nd.wV;
-        mk.push_back(&KU[i]);
-        mk.push_back(&KV[i]);
-        if (l >= 2) {
-          const Node2<T>& par = bd.node(nodes[i].p, l - 1, nodes[i].z >> 2);
-          XU[i].r = nd.wU;
-          XU[i].c = par.TU.c;
-          XV[i].r = nd.wV;
-          XV[i].c = par.TV.c;
-          mk.push_back(&XU[i]);
-          mk.push_back(&XV[i]);
-        }
-      }
-      carve(P->arena, mk, &cx.tmp);
-      // K^U = sum_s B_{a,s} B_{a,s}^H + X X^H,  K^V = sum_s B_{s,a}^H B_{s,a} + Y Y^H
-      // with X = R_a T^U_parent, Y = W_a T^V_parent (levels >= 2)
-      // one launch per accumulation slot: a batched launch must not hold two
-      // descriptors that update the same output matrix
-      std::vector<GemmDesc<double>> gx, gnc[4], gcn[4];
-      std::vector<FillDesc<double>> fz;
-      for (size_t i = 0; i < nodes.size(); ++i) {
-        int p = nodes[i].p, z = nodes[i].z;
-        Node2<T>& nd = bd.node(p, l, z);
-        int c = z & 3;
-        if (nd.wU > 0) fz.push_back({nd.wU, nd.wU, KU[i].ld, (double2*)KU[i].p, 0});
-        if (nd.wV > 0) fz.push_back({nd.wV, nd.wV, KV[i].ld, (double2*)KV[i].p, 0});
-        for (int s = 0; s < 3; ++s) {
-          int zs = (z & ~3) | Builder<T>::sib_child(c, s);
-          Node2<T>& sb = bd.node(p, l, zs);
-          Mat<double> b = to64(nd.B[s]);
-          if (nd.wU > 0 && b.c > 0)
-            gnc[s].push_back({nd.wU, nd.wU, b.c, b.ld, b.ld, KU[i].ld, b.p, b.p, KU[i].p, 1.0, 0.0,
-                              1.0, 1});
-          int slot = Builder<T>::sib_slot(zs & 3, c);
-          Mat<double> bs = to64(sb.B[slot]);
-          if (nd.wV > 0 && bs.r > 0)
-            gcn[s].push_back({nd.wV, nd.wV, bs.r, bs.ld, bs.ld, KV[i].ld, bs.p, bs.p, KV[i].p, 1.0,
-                              0.0, 1.0, 1});
-        }
-        if (l >= 2) {
-          const Node2<T>& par = bd.node(p, l - 1, z >> 2);
-          Mat<double> r = to64(nd.R), w = to64(nd.W);
-          if (nd.wU > 0 && par.TU.c > 0) {
-            gx.push_back({nd.wU, par.TU.c, r.c, r.ld, par.TU.ld, XU[i].ld, r.p, par.TU.p, XU[i].p,
-                          1.0, 0.0, 0.0});
-            gnc[3].push_back({nd.wU, nd.wU, XU[i].c, XU[i].ld, XU[i].ld, KU[i].ld, XU[i].p,
-                              XU[i].p, KU[i].p, 1.0, 0.0, 1.0, 1});
-          }
-          if (nd.wV > 0 && par.TV.c > 0) {
-            gx.push_back({nd.wV, par.TV.c, w.c, w.ld, par.TV.ld, XV[i].ld, w.p, par.TV.p, XV[i].p,
-                          1.0, 0.0, 0.0});
-            gnc[3].push_back({nd.wV, nd.wV, XV[i].c, XV[i].ld, XV[i].ld, KV[i].ld, XV[i].p,
-                              XV[i].p, KV[i].p, 1.0, 0.0, 1.0, 1});
-          }
-        }
-      }
-      fill_batched<double>(cx.pool, fz);
-      gemm_batched<double>(cx.pool, gx, OpN, OpN);
-      for (int s = 0; s < 4; ++s) {
-        gemm_batched<double>(cx.pool, gnc[s], OpN, OpC);
-        gemm_batched<double>(cx.pool, gcn[s], OpC, OpN);
-      }
+      if (std::is_same<T, float>::value && eps >= 5e-3) form_grams(float{});
+      else form_grams(double{});
       // rank decisions
       std::vector<Mat<double>> Ks;
       std::vector<int> rmax;

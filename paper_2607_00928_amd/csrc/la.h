@@ -21,11 +21,16 @@ struct DescPool {
   int* flag = nullptr;   // device error flag (set by a cooperative panel whose barrier timed out)
   size_t cap = 0, used = 0;
   hipStream_t stream = nullptr;
+  // deferred: push() only stages on the host and sync_reset() does nothing,
+  // so a stream capture records no copies and no waits; flush() then uploads
+  // everything staged (the descriptors stay valid for the graph's lifetime)
+  bool deferred = false;
   void init(size_t bytes, hipStream_t s);
   void destroy();
   void check_flag();   // synchronises; E_INTERNAL if the flag is set
   // copies n bytes to the device, returns the device address
   void* push(const void* src, size_t n);
+  void flush();
   void sync_reset();
   ~DescPool() { destroy(); }
 };
@@ -46,8 +51,13 @@ struct GemmDesc {
 // the same output matrix (their tiles run concurrently).  A descriptor with
 // lower = 1 leaves the tiles strictly above the diagonal untouched (for
 // Hermitian products whose consumer reads the lower triangle only).
+// The k loop is split over workgroups (atomic accumulation into a pre-scaled
+// C) by the count the autotuned table gives for the launch's shape class
+// (gemm_tuning.inc, written by tune_gemm.py), else by a heuristic;
+// splits_force > 0 overrides both (used by the tuner).
 template <typename T>
-void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB);
+void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB,
+                  int splits_force = 0);
 
 // Householder QR of a batch: A (m x n, lda) is overwritten by the explicit
 // reflector matrix V (m x kmin, unit lower trapezoidal, zeros above the

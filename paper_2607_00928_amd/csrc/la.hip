@@ -42,6 +42,7 @@ void DescPool::destroy() {
 }
 
 void DescPool::sync_reset() {
+  if (deferred) return;
   ND_HIP(hipStreamSynchronize(stream));
   used = 0;
 }
@@ -50,10 +51,14 @@ void* DescPool::push(const void* src, size_t n) {
   size_t need = (n + 255) & ~size_t(255);
   ND_CHECK(used + need <= cap, NUDFT2_E_INTERNAL, "descriptor pool exhausted");
   std::memcpy(host + used, src, n);
-  ND_HIP(hipMemcpyAsync(dev + used, host + used, n, hipMemcpyHostToDevice, stream));
+  if (!deferred) ND_HIP(hipMemcpyAsync(dev + used, host + used, n, hipMemcpyHostToDevice, stream));
   void* d = dev + used;
   used += need;
   return d;
+}
+
+void DescPool::flush() {
+  if (used > 0) ND_HIP(hipMemcpyAsync(dev, host, used, hipMemcpyHostToDevice, stream));
 }
 
 namespace {
@@ -82,11 +87,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
   if (d.lower && j0 > i0 + GT - 1) return;   // strictly above the diagonal of a Hermitian C
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  A4 accr[2][2], acci[2][2];
+  // Gauss (3M) products: p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi);
+  // Re = p1 - p2, Im = p3 - p1 - p2
+  A4 acc1[2][2], acc2[2][2], acc3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) { accr[a][b] = A4{0, 0, 0, 0}; acci[a][b] = A4{0, 0, 0, 0}; }
+    for (int b = 0; b < 2; ++b) {
+      acc1[a][b] = A4{0, 0, 0, 0};
+      acc2[a][b] = A4{0, 0, 0, 0};
+      acc3[a][b] = A4{0, 0, 0, 0};
+    }
 
   for (int l0 = kbeg; l0 < kend; l0 += GK) {
     __syncthreads();
@@ -145,14 +156,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
         br[a] = Bsr[l][wc + a * 16 + (lane & 15)];
         bi[a] = Bsi[l][wc + a * 16 + (lane & 15)];
       }
+      T as[2], bs[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        as[a] = ar[a] + ai[a];
+        bs[a] = br[a] + bi[a];
+      }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          accr[a][b] = mfma16(ar[a], br[b], accr[a][b]);
-          accr[a][b] = mfma16(-ai[a], bi[b], accr[a][b]);
-          acci[a][b] = mfma16(ar[a], bi[b], acci[a][b]);
-          acci[a][b] = mfma16(ai[a], br[b], acci[a][b]);
+          acc1[a][b] = mfma16(ar[a], br[b], acc1[a][b]);
+          acc2[a][b] = mfma16(ai[a], bi[b], acc2[a][b]);
+          acc3[a][b] = mfma16(as[a], bs[b], acc3[a][b]);
         }
     }
   }
@@ -165,7 +181,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
         int i = i0 + wr + a * 16 + mrow<T>(lane, v);
         int j = j0 + wc + b * 16 + (lane & 15);
         if (i < d.m && j < d.n) {
-          T cr = accr[a][b][v], ci = acci[a][b][v];
+          const T p1 = acc1[a][b][v], p2 = acc2[a][b][v];
+          const T cr = p1 - p2, ci = acc3[a][b][v] - p1 - p2;
           C2 out = mk<T>(d.ar * cr - d.ai * ci, d.ar * ci + d.ai * cr);
           C2* p = d.C + (int64_t)i + (int64_t)j * d.ldc;
           if (splits > 1) {
@@ -806,16 +823,45 @@ __global__ void fill_kernel(const FillDesc<T>* __restrict__ descs) {
 }  // namespace
 
 // ------------------------------------------------------------------ host API
+// Autotuned k splits per launch shape class: precision (0 FP64, 1 FP32),
+// op(A), op(B), ceil(log2) of the largest m, n, k and of the descriptor count.
+struct GemmTune {
+  int prec, opa, opb, lm, ln, lk, lnd, splits;
+};
+static const GemmTune kGemmTune[] = {
+    {-1, 0, 0, 0, 0, 0, 0, 0},   // sentinel
+#include "gemm_tuning.inc"
+};
+
+static int clog2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+template <typename T>
+static int tuned_splits(Op opA, Op opB, int maxm, int maxn, int maxk, int nd) {
+  const int prec = sizeof(T) == 4 ? 1 : 0;
+  const int lm = clog2(maxm), ln = clog2(maxn), lk = clog2(maxk), lnd = clog2(nd);
+  for (const GemmTune& t : kGemmTune)
+    if (t.prec == prec && t.opa == (int)opA && t.opb == (int)opB && t.lm == lm && t.ln == ln &&
+        t.lk == lk && t.lnd == lnd)
+      return t.splits;
+  return 0;
+}
+
 template <typename T>
 static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, Op opA, int maxm,
-                           int maxn, int maxk) {
+                           int maxn, int maxk, int force) {
   const size_t n = sub.size();
   const int rows_per_wg = opA == OpN ? 256 : 4;
   const int64_t bx = (maxm + rows_per_wg - 1) / rows_per_wg;
   int64_t wgs = bx * (int64_t)n;
   int splits = 1;
   const int kmin_split = opA == OpN ? 4 * SK_L : 1024;
-  if (wgs < 1024 && maxk >= 2 * kmin_split) {
+  if (force > 0) {
+    splits = std::max(1, std::min({force, std::max(1, maxk / SK_L), 4096}));
+  } else if (wgs < 1024 && maxk >= 2 * kmin_split) {
     splits = (int)std::min<int64_t>(maxk / kmin_split, (2048 + wgs - 1) / wgs);
     splits = std::max(1, std::min(splits, 256));
   }
@@ -841,7 +887,8 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
 }
 
 template <typename T>
-void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB) {
+void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB,
+                  int splits_force) {
   if (d.empty()) return;
   if (hazards_enabled()) {
     std::vector<Region> v;
@@ -872,14 +919,18 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
       maxm = std::max(maxm, g.m);
     }
     if (maxt == 0) continue;
+    const int force =
+        splits_force > 0 ? splits_force : tuned_splits<T>(opA, opB, maxm, maxn, maxk, (int)n);
     if (maxn <= SK_N && opB == OpN) {
-      skinny_batched<T>(pool, sub, opA, maxm, maxn, maxk);
+      skinny_batched<T>(pool, sub, opA, maxm, maxn, maxk, force);
       continue;
     }
     // split the k loop when the output tiles cannot fill the chip
     int64_t wgs = (int64_t)maxt * (int64_t)n;
     int splits = 1;
-    if (wgs < 1024 && maxk >= 512) {
+    if (force > 0) {
+      splits = std::max(1, std::min({force, std::max(1, ceil_div(maxk, GK)), 4096}));
+    } else if (wgs < 1024 && maxk >= 512) {
       splits = (int)std::min<int64_t>((maxk + 255) / 256, (2048 + wgs - 1) / wgs);
       splits = std::max(1, std::min(splits, 64));
     }
@@ -1281,7 +1332,7 @@ void fill_batched(DescPool& pool, const std::vector<FillDesc<T>>& d) {
 }
 
 #define INST(T)                                                                          \
-  template void gemm_batched<T>(DescPool&, const std::vector<GemmDesc<T>>&, Op, Op);     \
+  template void gemm_batched<T>(DescPool&, const std::vector<GemmDesc<T>>&, Op, Op, int);\
   template size_t qr_workspace<T>(const std::vector<QRDesc<T>>&);                        \
   template void geqrf_batched<T>(DescPool&, const std::vector<QRDesc<T>>&, void*);       \
   template size_t orm_workspace<T>(const std::vector<OrmDesc<T>>&);                      \

@@ -247,6 +247,7 @@ void factor_t(Plan* P) {
   P->info.t_recompress_ms = t2 - t1;   // face-split assembly + recompression
   P->info.t_facesplit_ms = 0;
   P->info.t_urv_ms = t3 - t2;
+  P->info.sweep_bytes = urv_sweep_bytes<T>(*H);
   P->hss.reset(H.release());
   P->factored = true;
 }
@@ -346,7 +347,9 @@ void hss_inverse_adj(Ctx& cx, HSS2<T>& H, const double2* v, double2* out, int nr
 }
 
 // Shared state of the solve drivers: workspace, the two HSS solution
-// operators S (M -> N) and S^H (N -> M), norms.
+// operators S (M -> N) and S^H (N -> M), norms, and the refinement iteration
+// as a HIP graph.  The operators take the context they launch on: the eager
+// one (cx) or the capture context (gcx).
 template <typename T>
 struct SolveCtx {
   Plan* P;
@@ -357,7 +360,14 @@ struct SolveCtx {
   double* nrm2;
   double* scale;
   double* inv;
-  double* red;
+  double* red;   // 5 nrhs slots of norms read back by the drivers
+  // graph of the iteration body: recorded on a private stream by a context of
+  // its own that keeps its descriptors and temporaries while the graph lives
+  bool use_graph;
+  Ctx gcx;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
   SolveCtx(Plan* p, int nr) : P(p), H(*static_cast<HSS2<T>*>(p->hss.get())), nrhs(nr) {
     cx.P = P;
     cx.s = P->stream;
@@ -371,6 +381,20 @@ struct SolveCtx {
     scale = w.sums + nrhs;
     inv = w.sums + 2 * nrhs;
     red = w.sums + 3 * nrhs;
+    use_graph = P->opts.graph == 1 && !P->profiling;
+  }
+  ~SolveCtx() {
+    (void)hipStreamSynchronize(cx.s);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) {
+      (void)hipStreamSynchronize(cap);
+      gcx.s = cx.s;   // the capture stream goes; gcx releases its temporaries on cx.s
+      gcx.pool.stream = cx.s;
+      (void)hipStreamDestroy(cap);
+    } else {
+      gcx.s = cx.s;
+    }
   }
   double2* vecM() { return (double2*)cx.tmp_alloc(sizeof(double2) * P->Mtot * nrhs); }
   double2* vecN() { return (double2*)cx.tmp_alloc(sizeof(double2) * P->Ntot * nrhs); }
@@ -381,37 +405,85 @@ struct SolveCtx {
   void copy(const double2* x, double2* y, int64_t n) {
     ND_HIP(hipMemcpyAsync(y, x, sizeof(double2) * n * nrhs, hipMemcpyDeviceToDevice, cx.s));
   }
-  void axpby(double a, const double2* x, double b, double2* y, int64_t n) {
-    hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, cx.s, a, x, b, y,
+  void axpby(Ctx& k, double a, const double2* x, double b, double2* y, int64_t n) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, k.s, a, x, b, y,
                        n * nrhs);
   }
-  void normalise(const double2* x, int64_t n) {
-    sumsq(cx.s, x, n, n, nrhs, nrm2);
-    hipLaunchKernelGGL(inv_kernel, dim3(1), dim3(256), 0, cx.s, nrm2, inv, scale, nrhs);
+  void axpby(double a, const double2* x, double b, double2* y, int64_t n) {
+    axpby(cx, a, x, b, y, n);
+  }
+  void normalise(Ctx& k, const double2* x, int64_t n) {
+    sumsq(k.s, x, n, n, nrhs, nrm2);
+    hipLaunchKernelGGL(inv_kernel, dim3(1), dim3(256), 0, k.s, nrm2, inv, scale, nrhs);
   }
   // d = S r (r: nrhs x Mtot -> d: nrhs x Ntot)
-  void S(const double2* r, double2* d) {
-    normalise(r, P->Mtot);
-    hss_inverse<T>(cx, H, r, d, nrhs, w, scale, inv);
+  void S(Ctx& k, const double2* r, double2* d) {
+    normalise(k, r, P->Mtot);
+    hss_inverse<T>(k, H, r, d, nrhs, w, scale, inv);
   }
+  void S(const double2* r, double2* d) { S(cx, r, d); }
   // out = S^H v (v: nrhs x Ntot -> out: nrhs x Mtot)
-  void SH(const double2* v, double2* out) {
-    normalise(v, P->Ntot);
-    hss_inverse_adj<T>(cx, H, v, out, nrhs, w, scale, inv);
+  void SH(Ctx& k, const double2* v, double2* out) {
+    normalise(k, v, P->Ntot);
+    hss_inverse_adj<T>(k, H, v, out, nrhs, w, scale, inv);
+  }
+  // squared norms per right-hand side into red + i nrhs (no wait)
+  void norm_into(Ctx& k, int i, const double2* x, int64_t n) {
+    sumsq(k.s, x, n, n, nrhs, red + i * nrhs);
+  }
+  // read back the first cnt norm slots (synchronises); the eager pool is
+  // recycled here
+  std::vector<double> read_norms(int cnt) {
+    std::vector<double> h(cnt * nrhs);
+    ND_HIP(hipMemcpyAsync(h.data(), red, sizeof(double) * cnt * nrhs, hipMemcpyDeviceToHost,
+                          cx.s));
+    ND_HIP(hipStreamSynchronize(cx.s));
+    cx.pool.sync_reset();
+    return h;
   }
   // squared norms per right-hand side of several vectors, read back (synchronises)
   std::vector<double> norms2(std::initializer_list<std::pair<const double2*, int64_t>> xs) {
-    std::vector<double> h(xs.size() * nrhs);
     int i = 0;
-    for (auto& x : xs) {
-      sumsq(cx.s, x.first, x.second, x.second, nrhs, red);
-      ND_HIP(hipMemcpyAsync(h.data() + i * nrhs, red, sizeof(double) * nrhs,
-                            hipMemcpyDeviceToHost, cx.s));
-      ND_HIP(hipStreamSynchronize(cx.s));
-      ++i;
+    for (auto& x : xs) norm_into(cx, i++, x.first, x.second);
+    return read_norms(i);
+  }
+  // Run the iteration body: eagerly, or (graph mode) captured once on the
+  // first call and replayed on cx.s.  The body must issue the same work with
+  // the same pointers on every call, and launch only on k.s through k.pool.
+  template <class F>
+  void run(F&& body) {
+    if (!use_graph) {
+      body(cx);
+      return;
     }
-    cx.pool.sync_reset();
-    return h;
+    if (!gexec) {
+      ND_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      gcx.P = P;
+      gcx.s = cap;
+      gcx.pool.init(64 << 20, cap);
+      ND_HIP(hipStreamSynchronize(cap));
+      gcx.pool.deferred = true;
+      gcx.keep = true;
+      Profiler* saved = g_prof;
+      g_prof = nullptr;
+      ND_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+      try {
+        body(gcx);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        g_prof = saved;
+        throw;
+      }
+      g_prof = saved;
+      ND_HIP(hipStreamEndCapture(cap, &graph));
+      ND_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      // descriptors reach the device before the first replay (same stream)
+      gcx.pool.stream = cx.s;
+      gcx.pool.flush();
+    }
+    ND_HIP(hipGraphLaunch(gexec, cx.s));
   }
   // worst ||a_r|| / ||b_r|| over the right-hand sides of a two-vector norm read
   double worst_ratio(const std::vector<double>& h, int ia, int ib) const {
@@ -456,18 +528,25 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
   int it = 0;
   double upd = 0, res = 1;
   bool conv = false;
-  for (it = 1; it <= maxit; ++it) {
+  // one iteration: d = S r (or S S^H A^H r), c += d, r = f - A c, norms
+  auto body = [&](Ctx& k) {
     if (ne) {
-      apply_adj(P, rr, rN, nrhs, sc.cx.s);
-      sc.SH(rN, tM);
-      sc.S(tM, dd);
+      apply_adj(P, rr, rN, nrhs, k.s);
+      sc.SH(k, rN, tM);
+      sc.S(k, tM, dd);
     } else {
-      sc.S(rr, dd);
+      sc.S(k, rr, dd);
     }
-    sc.axpby(1.0, dd, 1.0, c, N);
-    apply_fwd(P, c, rr, nrhs, sc.cx.s);
-    sc.axpby(1.0, f, -1.0, rr, M);
-    std::vector<double> h = sc.norms2({{dd, N}, {c, N}, {rr, M}});
+    sc.axpby(k, 1.0, dd, 1.0, c, N);
+    apply_fwd(P, c, rr, nrhs, k.s);
+    sc.axpby(k, 1.0, f, -1.0, rr, M);
+    sc.norm_into(k, 0, dd, N);
+    sc.norm_into(k, 1, c, N);
+    sc.norm_into(k, 2, rr, M);
+  };
+  for (it = 1; it <= maxit; ++it) {
+    sc.run(body);
+    std::vector<double> h = sc.read_norms(3);
     upd = sc.worst_ratio(h, 0, 1);
     res = std::sqrt(h[2 * nrhs]) / std::max(fn, 1e-300);
     if (!(upd == upd)) break;   // NaN: stop
@@ -494,14 +573,20 @@ void normal_solve(SolveCtx<T>& sc, const double2* g, double2* z, int& its, doubl
   sc.copy(g, rz, N);
   sc.zero(z, N);
   bool conv = false;
+  // one iteration: d = S S^H r, z += d, r = g - A^H A z, norms
+  auto body = [&](Ctx& k) {
+    sc.SH(k, rz, tM);
+    sc.S(k, tM, dd);
+    sc.axpby(k, 1.0, dd, 1.0, z, N);
+    apply_fwd(P, z, u, sc.nrhs, k.s);
+    apply_adj(P, u, rz, sc.nrhs, k.s);
+    sc.axpby(k, 1.0, g, -1.0, rz, N);
+    sc.norm_into(k, 0, dd, N);
+    sc.norm_into(k, 1, z, N);
+  };
   for (its = 1; its <= maxit; ++its) {
-    sc.SH(rz, tM);
-    sc.S(tM, dd);
-    sc.axpby(1.0, dd, 1.0, z, N);
-    apply_fwd(P, z, u, sc.nrhs, sc.cx.s);
-    apply_adj(P, u, rz, sc.nrhs, sc.cx.s);
-    sc.axpby(1.0, g, -1.0, rz, N);
-    std::vector<double> h = sc.norms2({{dd, N}, {z, N}});
+    sc.run(body);
+    std::vector<double> h = sc.read_norms(2);
     upd = sc.worst_ratio(h, 0, 1);
     if (!(upd == upd)) break;
     if (upd <= P->opts.ir_tol) {

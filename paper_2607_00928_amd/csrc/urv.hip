@@ -814,6 +814,35 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
 
 template void urv_factor<float>(Ctx&, HSS2<float>&);
 template void urv_factor<double>(Ctx&, HSS2<double>&);
+// Stored entries each step of urv_solve reads: the reflector blocks of
+// Omega, P and Q0 with their compact-WY factors, V^_2 (z = V^_2^H c2), the
+// sibling couplings B and the parent transfer R (b^), D12 and U1, the
+// triangle D11, and the root's reflectors, factor and triangle.
+template <typename T>
+int64_t urv_sweep_bytes(const HSS2<T>& H) {
+  double e = 0;
+  for (const auto& pb : H.probs) {
+    for (int l = 1; l <= pb.L; ++l)
+      for (const auto& nd : pb.lv[l]) {
+        if (nd.sizered) e += (double)nd.mm * nd.mchk + qr_tsize(nd.mm, nd.mchk);
+        if (nd.k > 0) {
+          e += (double)nd.mchk * nd.k + qr_tsize(nd.mchk, nd.k);
+          e += (double)nd.k * (nd.k + 1) / 2 + (double)nd.k * nd.nu + (double)nd.k * nd.wU;
+        }
+        e += (double)nd.nu * nd.wV;
+        if (nd.wV > 0) e += (double)nd.nn * nd.wV + qr_tsize(nd.nn, nd.wV);
+        for (int s = 0; s < 3; ++s) e += (double)nd.B[s].r * nd.B[s].c;
+        if (l >= 2) e += (double)nd.R.r * nd.R.c;
+      }
+    if (pb.root_n > 0)
+      e += (double)pb.root_m * pb.root_n + qr_tsize(pb.root_m, pb.root_n) +
+           (double)pb.root_n * (pb.root_n + 1) / 2;
+  }
+  return (int64_t)(e * sizeof(cplx<T>));
+}
+
+template int64_t urv_sweep_bytes<float>(const HSS2<float>&);
+template int64_t urv_sweep_bytes<double>(const HSS2<double>&);
 template void urv_solve<float>(Ctx&, HSS2<float>&, float2*, int64_t, float2*, int64_t, int);
 template void urv_solve<double>(Ctx&, HSS2<double>&, double2*, int64_t, double2*, int64_t, int);
 template void urv_solve_adj<float>(Ctx&, HSS2<float>&, float2*, int64_t, float2*, int64_t, int);

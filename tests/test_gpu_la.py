@@ -257,3 +257,41 @@ def test_trsv(prec, ct):
         X = from_dev(tB, k, nr)
         ref = np.linalg.solve(R.conj().T if ct else R, B)
         assert np.abs(X - ref).max() < 100 * TOL[prec] * max(1, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_large_batch(prec, opa, opb):
+    """A batch of 24 products of a few hundred rows and columns (many tiles,
+    no k splitting): ragged m, n, k (not multiples of the tile or k stage), a
+    tiny product and an empty one in the same batch, beta = 1."""
+    rng = np.random.default_rng(40 + 10 * prec + 2 * opa + opb)
+    shapes = [(600 - 7 * i, 520 + 5 * i, 200 + 13 * i) for i in range(24)]
+    shapes += [(3, 2, 5), (0, 4, 4), (130, 129, 1)]
+    mats, keep = [], []
+    mnk, ld, ptr = [], [], []
+    alpha = 0.9 + 0.2j
+    for (m, n, k) in shapes:
+        A = crandn(rng, *((m, k) if opa == 0 else (k, m)))
+        B = crandn(rng, *((k, n) if opb == 0 else (n, k)))
+        Cm = crandn(rng, m, n)
+        ta, tb, tc = to_dev(A, prec), to_dev(B, prec), to_dev(Cm, prec)
+        keep += [ta, tb, tc]
+        mats.append((A, B, Cm, tc))
+        mnk += [m, n, k]
+        ld += [max(A.shape[0], 1), max(B.shape[0], 1), max(m, 1)]
+        ptr += [ta.data_ptr(), tb.data_ptr(), tc.data_ptr()]
+    a1, p1 = i32(mnk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_gemm(prec, opa, opb, len(shapes), p1, p2, p3, alpha.real, alpha.imag, 1.0)
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+        if m == 0:
+            continue
+        oA = A if opa == 0 else A.conj().T
+        oB = B if opb == 0 else B.conj().T
+        ref = alpha * (oA @ oB) + Cm
+        got = from_dev(tc, m, n)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(got - ref).max() < TOL[prec] * scale * max(1, k) ** 0.5 * 10, (m, n, k)

@@ -79,3 +79,87 @@ def test_fp64_128_consistent_pin():
     print(f"fp64_128: err vs c_true {e:.2e}, its {si['iterations']}, info {plan.info()}")
     assert e < 1e-10
     plan.close()
+
+
+def test_set_solve_opts_direct_and_refined():
+    """One factorization serves the direct solve (ir_maxit = 0: the
+    HSS-accuracy solution) and, after switching the options back, the refined
+    one; bad options are rejected."""
+    pr = make_problem(32, 32, 64, 64, 0.25, 1)
+    f = onu.apply(pr.points, pr.c_true)
+    ft = torch.from_numpy(f).to(DEV)
+    plan = nd.Plan(pr.points, 32, 32, precision="fp32", eps=1e-2, ir_maxit=40, ir_tol=1e-13)
+    plan.factor()
+    c1 = plan.solve(ft).cpu().numpy()
+    assert rel(c1, pr.c_true) < 1e-10
+    plan.set_solve_opts(ir_maxit=0)
+    c0, si = plan.solve(ft, return_info=True)
+    e0 = rel(c0.cpu().numpy(), pr.c_true)
+    assert si["iterations"] == 0 and 1e-10 < e0 < 1e-1
+    plan.set_solve_opts(ir_maxit=40)
+    assert rel(plan.solve(ft).cpu().numpy(), pr.c_true) < 1e-10
+    assert plan.info()["sweep_bytes"] > 0
+    with pytest.raises(nd.NudftError):
+        plan.set_solve_opts(refine=2)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("refine", [0, 1])
+def test_graph_replays_match_eager(prec, refine):
+    """The refinement iteration captured into a HIP graph (replayed once per
+    iteration, with the norm readback and host decisions between replays)
+    gives the eager launches' result, on two right-hand sides and on a second
+    solve call with the same plan."""
+    pr = make_problem(48, 32, 96, 64, 0.3, 3)
+    rng = np.random.default_rng(31)
+    f = np.stack([onu.apply(pr.points, pr.c_true), complex_normal(rng, (pr.M,))])
+    ft = torch.from_numpy(f).to(DEV)
+    out = {}
+    for graph in (False, True):
+        plan = nd.Plan(pr.points, 48, 32, precision=prec, eps=1e-2, ir_maxit=60, ir_tol=1e-13,
+                       refine=refine, graph=graph)
+        plan.factor()
+        if refine == 0:
+            ft_use = ft[:1].contiguous()
+        else:
+            ft_use = ft
+        c1, s1 = plan.solve(ft_use, return_info=True)
+        c2, s2 = plan.solve(ft_use, return_info=True)
+        out[graph] = (c1.cpu().numpy(), c2.cpu().numpy(), s1["iterations"], s2["iterations"])
+        plan.close()
+    ce, ce2, ie, _ = out[False]
+    cg, cg2, ig, ig2 = out[True]
+    assert abs(ie - ig) <= 1 and ig == ig2
+    assert rel(cg, ce) < 1e-12 and rel(cg2, ce) < 1e-12
+    ref = onu.lstsq(pr.points, f[0], 48, 32)
+    assert rel(cg.reshape(-1, 48 * 32)[0], ref.reshape(-1)) < 1e-10
+
+
+def test_graph_adjoint_and_batch():
+    """Graph-captured normal-equation iterations (solve_adj) and a batch plan's
+    graph-captured solve agree with their eager counterparts."""
+    pr = make_problem(32, 32, 64, 64, 0.25, 1)
+    rng = np.random.default_rng(5)
+    g = torch.from_numpy(complex_normal(rng, (32, 32))).to(DEV)
+    w = {}
+    for graph in (False, True):
+        plan = nd.Plan(pr.points, 32, 32, precision="fp32", eps=1e-2, ir_maxit=60,
+                       ir_tol=1e-13, graph=graph)
+        plan.factor()
+        w[graph] = plan.solve_adj(g).cpu().numpy()
+        plan.close()
+    assert rel(w[True], w[False]) < 1e-12
+    probs = [make_problem(nx, ny, 2 * nx, 2 * ny, 0.3, 40 + i)
+             for i, (nx, ny) in enumerate([(32, 48), (64, 32), (16, 16)])]
+    fs = np.concatenate([onu.apply(p.points, p.c_true) for p in probs])
+    cs = {}
+    for graph in (False, True):
+        bp = nd.BatchPlan([p.points for p in probs], [32, 64, 16], [48, 32, 16],
+                          precision="fp32", eps=1e-2, ir_maxit=60, ir_tol=1e-13, graph=graph)
+        bp.factor()
+        cs[graph] = bp.solve(torch.from_numpy(fs).to(DEV)).cpu().numpy()
+        bp.close()
+    assert rel(cs[True], cs[False]) < 1e-12
+    ct = np.concatenate([p.c_true.reshape(-1) for p in probs])
+    assert rel(cs[True], ct) < 1e-10

@@ -1,0 +1,37 @@
+"""Host logic of the GEMM autotuner (no GPU): launch-log decoding and shape
+classes."""
+import numpy as np
+
+from paper_2607_00928_amd import tune_gemm as tg
+
+
+def test_clog2():
+    assert [tg.clog2(x) for x in (1, 2, 3, 4, 5, 16, 17, 1 << 20)] == [0, 1, 2, 2, 3, 4, 5, 20]
+
+
+def test_decode_variant_codes():
+    # regular launches: opA * 2 + opB + 10 * splits
+    assert tg.decode(10) == (0, 0, False)
+    assert tg.decode(11) == (0, 1, False)
+    assert tg.decode(12 + 10 * 7) == (1, 0, False)
+    assert tg.decode(13) == (1, 1, False)
+    # skinny launches: opA * 2 + 10 * splits + 1000 (op(B) = N)
+    assert tg.decode(1000 + 2 + 160) == (1, 0, True)
+    assert tg.decode(1010) == (0, 0, True)
+
+
+def test_classes_bucket_and_rank():
+    # cls ms flops nd m n k var
+    rows = np.array([
+        [1, 5.0, 1e9, 12, 5753, 5753, 5753, 10],
+        [1, 7.0, 1e9, 12, 5000, 6000, 5500, 10],    # same class as above
+        [2, 1.0, 1e9, 32, 16, 16, 1015804, 642],    # FP64, A^H B, 64 splits
+        [0, 9.0, 1e9, 1, 1, 1, 1, 0],               # apply: ignored
+        [3, 9.0, 0.0, 64, 512, 0, 0, 1],            # QR panel: ignored
+    ])
+    cl = tg.classes(rows, top=10)
+    assert len(cl) == 2
+    (k0, c0), (k1, c1) = cl
+    assert k0 == (1, 0, 0, 13, 13, 13, 4) and c0["ms"] == 12.0 and c0["count"] == 2
+    assert (c0["m"], c0["n"], c0["k"], c0["nd"]) == (5753, 6000, 5753, 12)
+    assert k1 == (0, 1, 0, 4, 4, 20, 5)
