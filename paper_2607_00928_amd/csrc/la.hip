@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 
 #include "device_util.h"
 #include "la.h"
@@ -68,14 +69,18 @@ constexpr int GT = 64;    // output tile
 constexpr int GK = 16;    // k per stage
 
 // splits > 1: blockIdx.z takes the k range [z kc, (z+1) kc) and the result is
-// added atomically (C must already hold beta C).
+// added atomically (C must already hold beta C).  The next k stage is loaded
+// into registers while the current one is multiplied out of LDS (double
+// buffered, one barrier per stage).  LDS rows are padded to an odd multiple
+// of 16 banks, so the 16-lane groups of an operand read hit distinct banks.
 template <typename T, int OPA, int OPB>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs,
                                                    int splits) {
   using C2 = cplx<T>;
   using A4 = typename acc4<T>::type;
-  __shared__ T Asr[GK][GT + 4], Asi[GK][GT + 4];
-  __shared__ T Bsr[GK][GT + 4], Bsi[GK][GT + 4];
+  constexpr int LDT = GT + 64 / (int)sizeof(T);
+  __shared__ T As[2][2][GK][LDT];   // [buffer][re, im][k][row]
+  __shared__ T Bs[2][2][GK][LDT];
   const GemmDesc<T> d = descs[blockIdx.y];
   const int tm = (d.m + GT - 1) / GT, tn = (d.n + GT - 1) / GT;
   if ((int)blockIdx.x >= tm * tn) return;
@@ -98,63 +103,73 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
       acc2[a][b] = A4{0, 0, 0, 0};
       acc3[a][b] = A4{0, 0, 0, 0};
     }
-
-  for (int l0 = kbeg; l0 < kend; l0 += GK) {
-    __syncthreads();
-    // A tile: rows i0..i0+63 of op(A), k l0..l0+15
-    if (OPA == OpN) {
-      int i = tid & 63, lq = tid >> 6;
+  // this thread's 4 elements of each stage: (row, k) of op(A), (k, column) of op(B)
+  auto a_at = [&](int u, int& i, int& l) {
+    if (OPA == OpN) { i = tid & 63; l = (tid >> 6) + 4 * u; }
+    else { l = tid & 15; i = (tid >> 4) + 16 * u; }
+  };
+  auto b_at = [&](int u, int& l, int& j) {
+    if (OPB == OpN) { l = tid & 15; j = (tid >> 4) + 16 * u; }
+    else { j = tid & 63; l = (tid >> 6) + 4 * u; }
+  };
+  C2 ra[4], rb[4];
+  auto gload = [&](int l0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int l = lq + 4 * u;
-        C2 v = mk<T>(0, 0);
-        if (i0 + i < d.m && l0 + l < kend) v = d.A[(int64_t)(i0 + i) + (int64_t)(l0 + l) * d.lda];
-        Asr[l][i] = v.x;
-        Asi[l][i] = v.y;
-      }
-    } else {
-      int l = tid & 15, iq = tid >> 4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int i = iq + 16 * u;
-        C2 v = mk<T>(0, 0);
-        if (i0 + i < d.m && l0 + l < kend) v = d.A[(int64_t)(l0 + l) + (int64_t)(i0 + i) * d.lda];
-        Asr[l][i] = v.x;
-        Asi[l][i] = -v.y;
-      }
+    for (int u = 0; u < 4; ++u) {
+      int i, l;
+      a_at(u, i, l);
+      C2 v = mk<T>(0, 0);
+      if (i0 + i < d.m && l0 + l < kend)
+        v = OPA == OpN ? d.A[(int64_t)(i0 + i) + (int64_t)(l0 + l) * d.lda]
+                       : d.A[(int64_t)(l0 + l) + (int64_t)(i0 + i) * d.lda];
+      ra[u] = v;
     }
-    if (OPB == OpN) {
-      int l = tid & 15, jq = tid >> 4;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int j = jq + 16 * u;
-        C2 v = mk<T>(0, 0);
-        if (j0 + j < d.n && l0 + l < kend) v = d.B[(int64_t)(l0 + l) + (int64_t)(j0 + j) * d.ldb];
-        Bsr[l][j] = v.x;
-        Bsi[l][j] = v.y;
-      }
-    } else {
-      int j = tid & 63, lq = tid >> 6;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int l = lq + 4 * u;
-        C2 v = mk<T>(0, 0);
-        if (j0 + j < d.n && l0 + l < kend) v = d.B[(int64_t)(j0 + j) + (int64_t)(l0 + l) * d.ldb];
-        Bsr[l][j] = v.x;
-        Bsi[l][j] = -v.y;
-      }
+    for (int u = 0; u < 4; ++u) {
+      int l, j;
+      b_at(u, l, j);
+      C2 v = mk<T>(0, 0);
+      if (j0 + j < d.n && l0 + l < kend)
+        v = OPB == OpN ? d.B[(int64_t)(l0 + l) + (int64_t)(j0 + j) * d.ldb]
+                       : d.B[(int64_t)(j0 + j) + (int64_t)(l0 + l) * d.ldb];
+      rb[u] = v;
     }
-    __syncthreads();
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int i, l;
+      a_at(u, i, l);
+      As[buf][0][l][i] = ra[u].x;
+      As[buf][1][l][i] = OPA == OpN ? ra[u].y : -ra[u].y;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int l, j;
+      b_at(u, l, j);
+      Bs[buf][0][l][j] = rb[u].x;
+      Bs[buf][1][l][j] = OPB == OpN ? rb[u].y : -rb[u].y;
+    }
+  };
+  const int nst = (kend - kbeg + GK - 1) / GK;
+  if (nst > 0) {
+    gload(kbeg);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) gload(kbeg + (st + 1) * GK);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int l = kk * 4 + (lane >> 4);
       T ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        ar[a] = Asr[l][wr + a * 16 + (lane & 15)];
-        ai[a] = Asi[l][wr + a * 16 + (lane & 15)];
-        br[a] = Bsr[l][wc + a * 16 + (lane & 15)];
-        bi[a] = Bsi[l][wc + a * 16 + (lane & 15)];
+        ar[a] = As[buf][0][l][wr + a * 16 + (lane & 15)];
+        ai[a] = As[buf][1][l][wr + a * 16 + (lane & 15)];
+        br[a] = Bs[buf][0][l][wc + a * 16 + (lane & 15)];
+        bi[a] = Bs[buf][1][l][wc + a * 16 + (lane & 15)];
       }
       T as[2], bs[2];
 #pragma unroll
@@ -171,6 +186,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict
           acc3[a][b] = mfma16(as[a], bs[b], acc3[a][b]);
         }
     }
+    if (st + 1 < nst) lstore(buf ^ 1);
+    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -225,7 +242,12 @@ __device__ inline void skinny_store(const GemmDesc<T>& d, int i, int j, cplx<T> 
   *p = out;
 }
 
-template <typename T>
+// op(A) = A: thread i accumulates row i of C over NC columns; the k loop
+// issues SK_U independent loads of A before using them (memory-level
+// parallelism on a bandwidth-bound stream).
+constexpr int SK_U = 8;
+
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void gemm_skinny_n_kernel(const GemmDesc<T>* __restrict__ descs,
                                                             int splits) {
   using C2 = cplx<T>;
@@ -235,36 +257,50 @@ __global__ __launch_bounds__(256) void gemm_skinny_n_kernel(const GemmDesc<T>* _
   const int kc = (d.k + splits - 1) / splits;
   const int kb = blockIdx.z * kc, ke = min(d.k, kb + kc);
   if (kb >= ke && splits > 1) return;
-  __shared__ C2 Bs[SK_L][SK_N];
+  __shared__ C2 Bs[SK_L][NC];
   const int tid = threadIdx.x, i = i0 + tid;
-  C2 acc[SK_N];
+  const bool row = i < d.m;
+  C2 acc[NC];
 #pragma unroll
-  for (int j = 0; j < SK_N; ++j) acc[j] = mk<T>(0, 0);
+  for (int j = 0; j < NC; ++j) acc[j] = mk<T>(0, 0);
   for (int l0 = kb; l0 < ke; l0 += SK_L) {
     __syncthreads();
-    for (int e = tid; e < SK_L * SK_N; e += 256) {
+    for (int e = tid; e < SK_L * NC; e += 256) {
       int l = e % SK_L, j = e / SK_L;
       Bs[l][j] = (l0 + l < ke && j < d.n) ? d.B[(int64_t)(l0 + l) + (int64_t)j * d.ldb] : mk<T>(0, 0);
     }
     __syncthreads();
-    if (i < d.m) {
-      const int lm = min(SK_L, ke - l0);
-      const C2* ap = d.A + i + (int64_t)l0 * d.lda;
-      for (int l = 0; l < lm; ++l) {
-        C2 a = ap[(int64_t)l * d.lda];
+    const int lm = min(SK_L, ke - l0);
+    const C2* ap = d.A + (row ? i : 0) + (int64_t)l0 * d.lda;
+    int l = 0;
+    for (; l + SK_U <= lm; l += SK_U) {
+      C2 a[SK_U];
 #pragma unroll
-        for (int j = 0; j < SK_N; ++j) acc[j] = cadd(acc[j], cmul(a, Bs[l][j]));
-      }
+      for (int u = 0; u < SK_U; ++u) a[u] = row ? ap[(int64_t)(l + u) * d.lda] : mk<T>(0, 0);
+#pragma unroll
+      for (int u = 0; u < SK_U; ++u)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[j] = cadd(acc[j], cmul(a[u], Bs[l + u][j]));
+    }
+    for (; l < lm; ++l) {
+      const C2 a = row ? ap[(int64_t)l * d.lda] : mk<T>(0, 0);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc[j] = cadd(acc[j], cmul(a, Bs[l][j]));
     }
   }
-  if (i < d.m)
-    for (int j = 0; j < d.n; ++j) skinny_store(d, i, j, acc[j], splits);
+  if (row)
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      if (j < d.n) skinny_store(d, i, j, acc[j], splits);
 }
 
-template <typename T>
+// op(A) = A^H: wave w computes row i of C (a dot product along column i of
+// A) over NC columns; each lane keeps SK_U / 2 independent loads in flight.
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(const GemmDesc<T>* __restrict__ descs,
                                                             int splits) {
   using C2 = cplx<T>;
+  constexpr int U = SK_U / 2;
   const GemmDesc<T> d = descs[blockIdx.y];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = blockIdx.x * 4 + wave;
@@ -272,18 +308,35 @@ __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(const GemmDesc<T>* _
   const int kc = (d.k + splits - 1) / splits;
   const int kb = blockIdx.z * kc, ke = min(d.k, kb + kc);
   if (kb >= ke && splits > 1) return;
-  C2 acc[SK_N];
+  C2 acc[NC];
 #pragma unroll
-  for (int j = 0; j < SK_N; ++j) acc[j] = mk<T>(0, 0);
+  for (int j = 0; j < NC; ++j) acc[j] = mk<T>(0, 0);
   const C2* ap = d.A + (int64_t)i * d.lda;
-  for (int l = kb + lane; l < ke; l += 64) {
-    C2 a = cconj(ap[l]);
+  int l = kb + lane;
+  for (; l + 64 * (U - 1) < ke; l += 64 * U) {
+    C2 a[U], b[U][NC];
 #pragma unroll
-    for (int j = 0; j < SK_N; ++j)
-      if (j < d.n) acc[j] = cadd(acc[j], cmul(a, d.B[(int64_t)l + (int64_t)j * d.ldb]));
+    for (int u = 0; u < U; ++u) {
+      a[u] = ap[l + 64 * u];
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        b[u][j] = j < d.n ? d.B[(int64_t)(l + 64 * u) + (int64_t)j * d.ldb] : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc[j] = cadd(acc[j], cmulc(a[u], b[u][j]));
   }
-  for (int j = 0; j < d.n; ++j) {
-    T re = warp_sum(acc[j].x), im = warp_sum(acc[j].y);
+  for (; l < ke; l += 64) {
+    const C2 a = ap[l];
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      if (j < d.n) acc[j] = cadd(acc[j], cmulc(a, d.B[(int64_t)l + (int64_t)j * d.ldb]));
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    if (j >= d.n) break;
+    const T re = warp_sum(acc[j].x), im = warp_sum(acc[j].y);
     if (lane == 0) skinny_store(d, i, j, mk<T>(re, im), splits);
   }
 }
@@ -879,10 +932,19 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
   ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn, maxk,
                (int)opA * 2 + 10 * splits + 1000);
   dim3 grid((unsigned)bx, (unsigned)n, (unsigned)splits);
-  if (opA == OpN)
-    hipLaunchKernelGGL((gemm_skinny_n_kernel<T>), grid, dim3(256), 0, pool.stream, dd, splits);
-  else
-    hipLaunchKernelGGL((gemm_skinny_c_kernel<T>), grid, dim3(256), 0, pool.stream, dd, splits);
+  auto launch = [&](auto nc) {
+    constexpr int NC = decltype(nc)::value;
+    if (opA == OpN)
+      hipLaunchKernelGGL((gemm_skinny_n_kernel<T, NC>), grid, dim3(256), 0, pool.stream, dd,
+                         splits);
+    else
+      hipLaunchKernelGGL((gemm_skinny_c_kernel<T, NC>), grid, dim3(256), 0, pool.stream, dd,
+                         splits);
+  };
+  if (maxn <= 1) launch(std::integral_constant<int, 1>{});
+  else if (maxn <= 2) launch(std::integral_constant<int, 2>{});
+  else if (maxn <= 4) launch(std::integral_constant<int, 4>{});
+  else launch(std::integral_constant<int, 8>{});
   ND_HIP(hipGetLastError());
 }
 
