@@ -14,6 +14,7 @@ baseline leg times the oracle's direct-sum apply on a bounded sample of rows.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -49,11 +50,17 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-factor comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nrhs16", action="store_true", help="also time 16 right-hand sides")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the timed steps (no sweep, apply, FP64 or CPU extras): the "
+                         "command the rocprofv3 summaries are taken on")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU runs are not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU (asked for --gpus {args.gpus}); the sharded "
+              "multi-GPU path is not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.profile_only:
+        args.no_fp64 = args.no_cpu_baseline = True
+        args.nrhs16 = False
 
     import torch
     from nudft_inputs import make_problem
@@ -125,7 +132,8 @@ def main():
     ach = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 and per_launch > 0 else None
     pk = peaks[dominant]
     roof = dict(bound="mfma", achieved=ach, peak=pk, unit="TFLOP/s",
-                frac=(ach / pk if ach is not None and pk else None), traffic=None,
+                frac=(ach / pk if ach is not None and pk else None),
+                traffic=gemm_traffic() if dominant == 1 else None,
                 kernel=names[dominant], avg_launch_ms=avg_ms, launches=kn[dominant],
                 flops_per_launch=per_launch)
     kernels = {names[i]: dict(ms=kms[i], launches=kn[i],
@@ -133,6 +141,12 @@ def main():
                for i in range(4)}
 
     extra = {}
+    if args.profile_only:
+        last_plan.close()
+        out = {"metric": "factor+solve/s (profile-only run)", "value": 1000.0 / ms_per_step,
+               "ms_per_step": ms_per_step, "roofline": roof, "kernels": kernels}
+        print(json.dumps(out))
+        return
     if args.nrhs16:
         F16 = f.unsqueeze(0).repeat(16, 1).contiguous()
         torch.cuda.synchronize()
@@ -216,6 +230,24 @@ def main():
     }
     out.update(extra)
     print(json.dumps(out))
+
+
+def gemm_traffic():
+    """HBM bytes per launch of the FP32 GEMM class, from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy of known
+    size); None when the kernel source changed since the counters were
+    taken."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "gemm_fp32_traffic_n512.md")
+    src = os.path.join(root, "paper_2607_00928_amd", "csrc", "la.hip")
+    try:
+        rec = json.loads(open(path).read().split("```json")[1].split("```")[0])
+        with open(src, "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != rec["la_hip_sha256"]:
+                return None
+        return rec["hbm_bytes_per_launch"]
+    except Exception:
+        return None
 
 
 def cpu_baseline(pr, nx, ny, log):

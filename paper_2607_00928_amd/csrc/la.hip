@@ -74,8 +74,8 @@ constexpr int GK = 16;    // k per stage
 // buffered, one barrier per stage).  LDS rows are padded to an odd multiple
 // of 16 banks, so the 16-lane groups of an operand read hit distinct banks.
 template <typename T, int OPA, int OPB>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc<T>* __restrict__ descs,
-                                                   int splits) {
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(
+    const GemmDesc<T>* __restrict__ descs, int splits) {
   using C2 = cplx<T>;
   using A4 = typename acc4<T>::type;
   constexpr int LDT = GT + 64 / (int)sizeof(T);
