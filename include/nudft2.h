@@ -67,9 +67,10 @@ typedef struct {
                             c += S S^* A^*(f - Ac) (exact least squares for any f) */
   void* stream;       /* hipStream_t; NULL = default stream                     */
   size_t mem_cap;     /* device bytes the plan may hold; 0 = no cap             */
-  int32_t graph;      /* 1: each solve call captures its refinement iteration
-                         (HSS solve sweep, update, exact apply, residual, norms)
-                         once into a HIP graph and replays it; 0: eager launches.
+  int32_t graph;      /* 1: each solve call runs its first refinement iteration
+                         eagerly, captures the next one (HSS solve sweep, update,
+                         exact apply, residual, norms) into a HIP graph and
+                         replays it for the rest; 0 (default): eager launches.
                          Kernel profiling (nudft2_set_profiling) runs eagerly. */
 } nudft2_opts;
 

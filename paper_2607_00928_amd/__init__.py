@@ -25,7 +25,7 @@ __all__ = ["Plan", "BatchPlan", "NudftError", "lsq_solve"]
 _PREC = {"fp64": 0, "fp32": 1, 0: 0, 1: 1}
 
 
-def _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph=True):
+def _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph=False):
     o = _lib.default_opts()
     o.graph = 1 if graph else 0
     o.precision = _PREC[precision]
@@ -188,7 +188,7 @@ class Plan(_PlanBase):
 
     def __init__(self, points, nx: int, ny: int, *, precision="fp32", eps=1e-4,
                  leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0, stream=None,
-                 mem_cap=0, device=None, graph=True):
+                 mem_cap=0, device=None, graph=False):
         pts = _host_points(points)
         self.M = pts.shape[0]
         self.nx, self.ny = int(nx), int(ny)
@@ -213,7 +213,7 @@ class BatchPlan(_PlanBase):
 
     def __init__(self, points_list, nx_list, ny_list, *, precision="fp32",
                  eps=1e-4, leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0,
-                 stream=None, mem_cap=0, device=None, graph=True):
+                 stream=None, mem_cap=0, device=None, graph=False):
         pts = [_host_points(p) for p in points_list]
         m_off = np.zeros(len(pts) + 1, dtype=np.int64)
         m_off[1:] = np.cumsum([p.shape[0] for p in pts])

@@ -181,7 +181,7 @@ void nudft2_default_opts(nudft2_opts* o) {
   o->refine = 0;
   o->stream = nullptr;
   o->mem_cap = 0;
-  o->graph = 1;
+  o->graph = 0;
 }
 
 const char* nudft2_strerror(nudft2_status s) {

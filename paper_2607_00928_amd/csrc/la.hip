@@ -1040,7 +1040,9 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const int* dact, int n
     ND_HIP(hipGetDevice(&dev));
     ND_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     ND_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, QP_NT, 0));
-    mres = std::max(1, cus * std::max(per, 1));
+    // one 1024-thread workgroup per CU at most: the group barriers assume that
+    // every workgroup of the grid is resident
+    mres = std::max(1, cus * std::min(std::max(per, 1), 1));
   }
   constexpr int rows = 128 * QPanel<T>::R;
   int gsize = std::max(1, (maxmr + rows - 1) / rows);

@@ -447,12 +447,15 @@ struct SolveCtx {
     for (auto& x : xs) norm_into(cx, i++, x.first, x.second);
     return read_norms(i);
   }
-  // Run the iteration body: eagerly, or (graph mode) captured once on the
-  // first call and replayed on cx.s.  The body must issue the same work with
+  // Run the iteration body: eagerly, or (graph mode) eagerly on the first
+  // call, then captured once and replayed on cx.s.  The eager first call
+  // leaves the body's temporaries in the arena's free list, so the capture
+  // allocates no new device memory.  The body must issue the same work with
   // the same pointers on every call, and launch only on k.s through k.pool.
+  int runs = 0;
   template <class F>
   void run(F&& body) {
-    if (!use_graph) {
+    if (!use_graph || runs++ == 0) {
       body(cx);
       return;
     }

@@ -183,7 +183,8 @@ def test_geqrf_ormqr(prec):
 
 def test_pchol_trace_rule():
     rng = np.random.default_rng(7)
-    sizes = [(40, 40), (300, 120), (473, 473), (17, 5)]
+    # up to 1100 rows: five cooperating workgroups per Gram, several panels
+    sizes = [(40, 40), (300, 120), (473, 473), (17, 5), (1100, 70)]
     keep, data = [], []
     w, rmax, ptr = [], [], []
     tol2 = 1e-8
