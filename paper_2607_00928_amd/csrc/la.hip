@@ -719,54 +719,119 @@ __global__ void pchol_init_kernel(const PcholDesc* __restrict__ descs, double* t
   }
 }
 
-// One panel of up to PC_NB pivots.  state[b]: 1 = still running.
-__global__ __launch_bounds__(256) void pchol_panel_kernel(const PcholDesc* __restrict__ descs,
-                                                          const double* __restrict__ trace,
-                                                          int* __restrict__ state, int k0) {
-  const int b = blockIdx.x;
+// Column-parallel pivoted Cholesky: one launch per pivot column, workgroup w
+// of Gram b owning rows [256 w, 256 w + 256) (one per thread).  The
+// workgroups exchange their partials of the Schur diagonal (largest entry,
+// its row, positive trace) through global slots, double-buffered by column
+// parity; the launch boundary orders a column's partials before their use,
+// so no workgroup waits on another inside a launch.  Ties go to the lower
+// row.  state[b]: 1 = still running.
+constexpr int PC_ROWS = 256;
+
+__device__ inline bool pc_better(double v, int i, double bv, int bi) {
+  return v > bv || (v == bv && i >= 0 && (bi < 0 || i < bi));
+}
+
+// (largest, row, sum) over the workgroup, valid in thread 0
+__device__ inline void pc_reduce(double& best, int& bi, double& sum) {
+  __shared__ double rv[4], rs[4];
+  __shared__ int ri[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  sum = warp_sum(sum);
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (pc_better(ob, oi, best, bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    rv[wave] = best;
+    ri[wave] = bi;
+    rs[wave] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 1; v < 4; ++v) {
+      rs[0] += rs[v];
+      if (pc_better(rv[v], ri[v], rv[0], ri[0])) {
+        rv[0] = rv[v];
+        ri[0] = ri[v];
+      }
+    }
+    best = rv[0];
+    bi = ri[0];
+    sum = rs[0];
+  }
+  __syncthreads();
+}
+
+// partial of this workgroup's rows of the diagonal workspace d
+__device__ inline void pc_partial(const PcholDesc& d, int i, double di, double* slot) {
+  double best = -1.0, sum = 0.0;
+  int bi = -1;
+  if (i < d.w && di > -1e300) {   // pivoted rows hold -inf
+    sum = di > 0 ? di : 0;
+    if (di > best) {
+      best = di;
+      bi = i;
+    }
+  }
+  pc_reduce(best, bi, sum);
+  if (threadIdx.x == 0) {
+    slot[0] = best;
+    slot[1] = (double)bi;
+    slot[2] = sum;
+  }
+}
+
+// partials of the current diagonal into slot parity `par`
+__global__ __launch_bounds__(256) void pchol_part_kernel(const PcholDesc* __restrict__ descs,
+                                                         int gsize, double* __restrict__ part,
+                                                         int par) {
+  const int b = blockIdx.x / gsize, w = blockIdx.x % gsize;
+  const PcholDesc d = descs[b];
+  if (w * PC_ROWS >= max(d.w, 1)) return;
+  const int i = w * PC_ROWS + threadIdx.x;
+  const double di = i < d.w ? d.d[i] : -1.0 / 0.0;
+  pc_partial(d, i, di, part + (((size_t)b * 2 + par) * gsize + w) * 3);
+}
+
+// column k = k0 + kk of every running Gram
+__global__ __launch_bounds__(256) void pchol_col_kernel(const PcholDesc* __restrict__ descs,
+                                                        const double* __restrict__ trace,
+                                                        int* __restrict__ state, int gsize,
+                                                        double* __restrict__ part, int k0,
+                                                        int kk) {
+  const int b = blockIdx.x / gsize, w = blockIdx.x % gsize;
   if (!state[b]) return;
   const PcholDesc d = descs[b];
-  __shared__ double rv[4];
-  __shared__ int ri[4];
-  __shared__ double rs[4];
-  __shared__ int piv_s;
-  __shared__ double dp_s;
-  __shared__ int stop_s;
+  const int gw = (max(d.w, 1) + PC_ROWS - 1) / PC_ROWS;   // workgroups holding rows
+  if (w >= gw) return;
+  const int tid = threadIdx.x;
+  const int k = k0 + kk;
   __shared__ double2 lp[PC_NB];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const double tol = d.tol2 * trace[b];
-  int k = k0;
-  for (int kk = 0; kk < PC_NB; ++kk, ++k) {
-    // remaining trace and argmax of the Schur diagonal
-    double best = -1.0, sum = 0.0;
-    int bi = -1;
-    for (int i = tid; i < d.w; i += 256) {
-      double v = d.d[i];
-      if (v > -1e300) {          // pivoted rows hold -inf
-        sum += v > 0 ? v : 0;
-        if (v > best) { best = v; bi = i; }
+  __shared__ int piv_s, stop_s;
+  __shared__ double dp_s;
+  if (tid == 0) {
+    // combine the workgroups' partials of this column (same order everywhere)
+    const double* sl = part + ((size_t)b * 2 + (k & 1)) * gsize * 3;
+    double bb = sl[0], ss = sl[2];
+    int ii = (int)sl[1];
+    for (int v = 1; v < gw; ++v) {
+      ss += sl[3 * v + 2];
+      if (pc_better(sl[3 * v], (int)sl[3 * v + 1], bb, ii)) {
+        bb = sl[3 * v];
+        ii = (int)sl[3 * v + 1];
       }
     }
-    sum = warp_sum(sum);
-    for (int o = 32; o > 0; o >>= 1) {
-      double ob = __shfl_xor(best, o, 64);
-      int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi >= 0 && (bi < 0 || oi < bi))) { best = ob; bi = oi; }
-    }
-    if (lane == 0) { rv[wave] = best; ri[wave] = bi; rs[wave] = sum; }
-    __syncthreads();
-    if (tid == 0) {
-      double bb = rv[0];
-      int ii = ri[0];
-      double ss = rs[0];
-      for (int w = 1; w < 4; ++w) {
-        ss += rs[w];
-        if (rv[w] > bb || (rv[w] == bb && ri[w] >= 0 && (ii < 0 || ri[w] < ii))) { bb = rv[w]; ii = ri[w]; }
-      }
-      int stop = (k >= d.rmax || k >= d.w || ss <= tol || ii < 0 || bb <= 0.0) ? 1 : 0;
-      stop_s = stop;
-      piv_s = ii;
-      dp_s = bb;
+    const double tol = d.tol2 * trace[b];
+    const int stop = (k >= d.rmax || k >= d.w || ss <= tol || ii < 0 || bb <= 0.0) ? 1 : 0;
+    stop_s = stop;
+    piv_s = ii;
+    dp_s = bb;
+    if (w == 0) {
       if (stop) {
         *d.rank = k;
         state[b] = 0;
@@ -774,32 +839,41 @@ __global__ __launch_bounds__(256) void pchol_panel_kernel(const PcholDesc* __res
         d.piv[k] = ii;
       }
     }
-    __syncthreads();
-    if (stop_s) return;
-    const int p = piv_s;
-    const double sdp = sqrt(dp_s);
-    // conj of the pivot row of the panel's previous columns
-    if (tid < kk) {
-      double2 v = d.L[p + (int64_t)(k0 + tid) * d.ldl];
-      lp[tid] = v;
-    }
-    __syncthreads();
-    for (int i = tid; i < d.w; i += 256) {
-      // K is Hermitian and held in its lower triangle
-      double2 v = i >= p ? d.K[i + (int64_t)p * d.ldk] : cconj(d.K[p + (int64_t)i * d.ldk]);
-      for (int q = 0; q < kk; ++q) v = csub(v, cmulc(lp[q], d.L[i + (int64_t)(k0 + q) * d.ldl]));
-      // L(i,k) = (K(i,p) - sum L(i,q) conj(L(p,q))) / sqrt(d_p)
-      double dd = d.d[i];
-      if (dd <= -1e300) v = mk<double>(0.0, 0.0);
-      v.x /= sdp;
-      v.y /= sdp;
-      if (i == p) v = mk<double>(sdp, 0.0);
-      d.L[i + (int64_t)k * d.ldl] = v;
-      if (i == p) d.d[i] = -1.0 / 0.0;
-      else if (dd > -1e300) d.d[i] = dd - (v.x * v.x + v.y * v.y);
-    }
-    __syncthreads();
   }
+  __syncthreads();
+  if (stop_s) return;
+  const int p = piv_s;
+  const double sdp = sqrt(dp_s);
+  // conj of the pivot row's earlier entries in this panel
+  if (tid < kk) lp[tid] = d.L[p + (int64_t)(k0 + tid) * d.ldl];
+  __syncthreads();
+  const int i = w * PC_ROWS + tid;
+  double di = -1.0 / 0.0;
+  if (i < d.w) {
+    di = d.d[i];
+    // L(i,k) = (K(i,p) - sum_q L(i,q) conj(L(p,q))) / sqrt(d_p); K holds its lower triangle
+    double2 v = i >= p ? d.K[i + (int64_t)p * d.ldk] : cconj(d.K[p + (int64_t)i * d.ldk]);
+    const double2* li = d.L + i + (int64_t)k0 * d.ldl;
+    int q = 0;
+    for (; q + 4 <= kk; q += 4) {
+      double2 l4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) l4[u] = li[(int64_t)(q + u) * d.ldl];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v = csub(v, cmulc(lp[q + u], l4[u]));
+    }
+    for (; q < kk; ++q) v = csub(v, cmulc(lp[q], li[(int64_t)q * d.ldl]));
+    if (di <= -1e300) v = mk<double>(0.0, 0.0);
+    v.x /= sdp;
+    v.y /= sdp;
+    if (i == p) v = mk<double>(sdp, 0.0);
+    d.L[i + (int64_t)k * d.ldl] = v;
+    if (i == p) di = -1.0 / 0.0;
+    else if (di > -1e300) di -= v.x * v.x + v.y * v.y;
+    d.d[i] = di;
+  }
+  // partials of the next column
+  pc_partial(d, i, di, part + (((size_t)b * 2 + ((k + 1) & 1)) * gsize + w) * 3);
 }
 
 __global__ void pchol_finish_kernel(const PcholDesc* __restrict__ descs, const int* state, int kend) {
@@ -1267,9 +1341,21 @@ void pchol_batched(DescPool& pool, const std::vector<PcholDesc>& d) {
   for (auto& q : d) rmax = std::max(rmax, std::min(q.rmax, q.w));
   std::vector<GemmDesc<double>> g;
   std::vector<int> hstate(nb);
+  int maxw = 1;
+  for (auto& q : d) maxw = std::max(maxw, q.w);
+  const int gsize = (maxw + PC_ROWS - 1) / PC_ROWS;
+  const int64_t grid = (int64_t)nb * gsize;
+  ND_CHECK(grid < (int64_t(1) << 31), NUDFT2_E_INTERNAL, "too many Gram rows for one launch");
+  std::vector<double> pz((size_t)nb * 2 * gsize * 3, 0.0);
+  double* part = (double*)pool.push(pz.data(), sizeof(double) * pz.size());
+  hipLaunchKernelGGL(pchol_part_kernel, dim3((unsigned)grid), dim3(PC_ROWS), 0, pool.stream, dd,
+                     gsize, part, 0);
+  ND_HIP(hipGetLastError());
   for (int k0 = 0; k0 < rmax; k0 += PC_NB) {
-    hipLaunchKernelGGL(pchol_panel_kernel, dim3(nb), dim3(256), 0, pool.stream, dd, trace,
-                       state, k0);
+    const int kb = std::min(PC_NB, rmax - k0);
+    for (int kk = 0; kk < kb; ++kk)
+      hipLaunchKernelGGL(pchol_col_kernel, dim3((unsigned)grid), dim3(PC_ROWS), 0, pool.stream, dd,
+                         trace, state, gsize, part, k0, kk);
     ND_HIP(hipGetLastError());
     // Schur update with this panel's columns for the problems still running
     ND_HIP(hipMemcpyAsync(hstate.data(), state, sizeof(int) * nb, hipMemcpyDeviceToHost,
