@@ -886,37 +886,82 @@ __global__ void pchol_finish_kernel(const PcholDesc* __restrict__ descs, const i
 
 // ------------------------------------------------------------ triangular solve
 // R X = B (CT = false, back substitution) or R^H X = B (CT = true, forward
-// substitution) with R upper triangular; one workgroup per (system, column).
+// substitution), R upper triangular of order k <= TRS_B; one workgroup per
+// (system, column of B).  The workgroup stages R's upper triangle in LDS,
+// packed by columns ((r, c), r <= c, at c (c + 1) / 2 + r), with the inverted
+// diagonal; one wave then substitutes with the right-hand side in registers
+// (lane l holds rows l and l + 64) and broadcasts each solved entry with a
+// lane read.
+constexpr int TRS_B = 128;
+
 template <typename T, bool CT>
-__global__ __launch_bounds__(256) void trsv_upper_kernel(const TrsDesc<T>* __restrict__ descs) {
+__global__ __launch_bounds__(256) void trsv_lds_kernel(const TrsDesc<T>* __restrict__ descs) {
   using C2 = cplx<T>;
+  __shared__ C2 Rp[TRS_B * (TRS_B + 1) / 2];
+  __shared__ C2 inv[TRS_B];
   const TrsDesc<T> d = descs[blockIdx.x];
   const int rhs = blockIdx.y;
-  if (rhs >= d.nrhs) return;
-  C2* b = d.B + (int64_t)rhs * d.ldb;
-  __shared__ C2 xs;
-  for (int s = 0; s < d.k; ++s) {
-    const int i = CT ? s : d.k - 1 - s;
-    if (threadIdx.x == 0) {
-      C2 r = d.R[i + (int64_t)i * d.ldr];
-      if (CT) r.y = -r.y;
-      C2 v = b[i];
-      T den = r.x * r.x + r.y * r.y;
-      C2 x = mk<T>((v.x * r.x + v.y * r.y) / den, (v.y * r.x - v.x * r.y) / den);
-      b[i] = x;
-      xs = x;
+  if (rhs >= d.nrhs || d.k <= 0) return;
+  const int k = min(d.k, TRS_B);
+  const int ne = k * (k + 1) / 2;
+  const int tid = threadIdx.x;
+  for (int e0 = 0; e0 < ne; e0 += 256 * 8) {
+    C2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256 + tid;
+      v[u] = mk<T>(0, 0);
+      if (e < ne) {
+        int c = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
+        while ((c + 1) * (c + 2) / 2 <= e) ++c;
+        while (c * (c + 1) / 2 > e) --c;
+        v[u] = d.R[(e - c * (c + 1) / 2) + (int64_t)c * d.ldr];
+      }
     }
-    __syncthreads();
-    C2 x = xs;
-    if (CT) {
-      // rows below: b_r -= conj(R(i, r)) x
-      for (int r = i + 1 + threadIdx.x; r < d.k; r += 256)
-        b[r] = csub(b[r], cmul(cconj(d.R[i + (int64_t)r * d.ldr]), x));
-    } else {
-      for (int r = threadIdx.x; r < i; r += 256) b[r] = csub(b[r], cmul(d.R[r + (int64_t)i * d.ldr], x));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256 + tid;
+      if (e < ne) Rp[e] = v[u];
     }
-    __syncthreads();
   }
+  __syncthreads();
+  if (tid < k) {
+    C2 r = Rp[tid * (tid + 1) / 2 + tid];
+    if (CT) r.y = -r.y;
+    const T den = r.x * r.x + r.y * r.y;
+    inv[tid] = mk<T>(r.x / den, -r.y / den);
+  }
+  __syncthreads();
+  if (tid >= 64) return;
+  const int lane = tid;
+  C2* b = d.B + (int64_t)rhs * d.ldb;
+  C2 x0 = lane < k ? b[lane] : mk<T>(0, 0);
+  C2 x1 = lane + 64 < k ? b[lane + 64] : mk<T>(0, 0);
+  for (int s = 0; s < k; ++s) {
+    const int i = CT ? s : k - 1 - s;
+    const int ow = i & 63;
+    const C2 bi = (i >> 6) ? x1 : x0;
+    C2 xi = cmul(bi, inv[i]);
+    xi.x = lane_bcast(xi.x, ow);
+    xi.y = lane_bcast(xi.y, ow);
+    if (lane == ow) {
+      if (i >> 6) x1 = xi;
+      else x0 = xi;
+    }
+    if (!CT) {
+      // rows above i: b_r -= R(r, i) x_i
+      const int off = i * (i + 1) / 2;
+      if (lane < i) x0 = csub(x0, cmul(Rp[off + lane], xi));
+      if (lane + 64 < i) x1 = csub(x1, cmul(Rp[off + lane + 64], xi));
+    } else {
+      // rows below i: b_r -= conj(R(i, r)) x_i
+      const int r0 = lane, r1 = lane + 64;
+      if (r0 > i && r0 < k) x0 = csub(x0, cmul(cconj(Rp[r0 * (r0 + 1) / 2 + i]), xi));
+      if (r1 > i && r1 < k) x1 = csub(x1, cmul(cconj(Rp[r1 * (r1 + 1) / 2 + i]), xi));
+    }
+  }
+  if (lane < k) b[lane] = x0;
+  if (lane + 64 < k) b[lane + 64] = x1;
 }
 
 // ------------------------------------------------------------ copy / fill
@@ -1387,21 +1432,21 @@ static void trsv_small(DescPool& pool, const std::vector<TrsDesc<T>>& d, bool ct
   for (auto& q : d) maxr = std::max(maxr, q.nrhs);
   auto* dd = (TrsDesc<T>*)pool.push(d.data(), sizeof(TrsDesc<T>) * d.size());
   if (ct)
-    hipLaunchKernelGGL((trsv_upper_kernel<T, true>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
+    hipLaunchKernelGGL((trsv_lds_kernel<T, true>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
                        pool.stream, dd);
   else
-    hipLaunchKernelGGL((trsv_upper_kernel<T, false>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
+    hipLaunchKernelGGL((trsv_lds_kernel<T, false>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
                        pool.stream, dd);
   ND_HIP(hipGetLastError());
 }
 
-// Upper-triangular solves R X = B, or R^H X = B when conj_trans.  Small
-// systems: one workgroup each.  Large ones: blocked substitution, 128 x 128
-// diagonal blocks solved by one workgroup, the remaining rows updated by a
-// matrix-core GEMM (rows above for R, rows below for R^H).
+// Upper-triangular solves R X = B, or R^H X = B when conj_trans.  Systems of
+// order <= TRS_B: one workgroup each.  Larger ones: blocked substitution,
+// TRS_B x TRS_B diagonal blocks solved by one workgroup each, the remaining
+// rows updated by a matrix-core GEMM (rows above for R, rows below for R^H).
 template <typename T>
 void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d, bool conj_trans) {
-  constexpr int BS = 128;
+  constexpr int BS = TRS_B;
   if (hazards_enabled()) {
     std::vector<Region> v;
     const int64_t es = sizeof(cplx<T>);
@@ -1416,7 +1461,7 @@ void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d, bool c
   std::vector<TrsDesc<T>> small, big;
   for (auto& q : d) {
     if (q.k <= 0 || q.nrhs <= 0) continue;
-    (q.k <= 2 * BS ? small : big).push_back(q);
+    (q.k <= BS ? small : big).push_back(q);
   }
   trsv_small<T>(pool, small, conj_trans);
   if (big.empty()) return;

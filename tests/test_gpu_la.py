@@ -237,7 +237,9 @@ def test_pchol_trace_rule():
 @pytest.mark.parametrize("ct", [0, 1])
 def test_trsv(prec, ct):
     rng = np.random.default_rng(11 + ct)
-    sizes = [(1, 1), (50, 3), (300, 2), (7, 1), (700, 2), (257, 1)]
+    # one block (<= 128) with the lane-slot boundaries 64 / 65 / 128, and blocked orders
+    sizes = [(1, 1), (50, 3), (300, 2), (7, 1), (700, 2), (257, 1), (64, 1), (65, 2), (128, 1),
+             (129, 3)]
     keep, data, dims, ld, ptr = [], [], [], [], []
     for (k, nr) in sizes:
         # well-conditioned triangle (a unit-scale random triangle is
