@@ -54,7 +54,8 @@ struct GemmDesc {
 // The k loop is split over workgroups (atomic accumulation into a pre-scaled
 // C) by the count the autotuned table gives for the launch's shape class
 // (gemm_tuning.inc, written by tune_gemm.py), else by a heuristic;
-// splits_force > 0 overrides both (used by the tuner).
+// splits_force > 0 overrides both (used by the tuner); splits_force = -1
+// runs the tile kernel unsplit, without the table (measurement).
 template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB,
                   int splits_force = 0);

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(
             continue;
           }
           if (d.beta != T(0)) {
-            C2 o = *p;
+            const C2 o = *p;
             out.x += d.beta * o.x;
             out.y += d.beta * o.y;
           }
@@ -1101,7 +1101,8 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     }
     if (maxt == 0) continue;
     const int force =
-        splits_force > 0 ? splits_force : tuned_splits<T>(opA, opB, maxm, maxn, maxk, (int)n);
+        splits_force > 0 ? splits_force
+                         : (splits_force < 0 ? 1 : tuned_splits<T>(opA, opB, maxm, maxn, maxk, (int)n));
     if (maxn <= SK_N && opB == OpN) {
       skinny_batched<T>(pool, sub, opA, maxm, maxn, maxk, force);
       continue;

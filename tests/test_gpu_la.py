@@ -298,3 +298,42 @@ def test_gemm_large_batch(prec, opa, opb):
         got = from_dev(tc, m, n)
         scale = max(1.0, np.abs(ref).max())
         assert np.abs(got - ref).max() < TOL[prec] * scale * max(1, k) ** 0.5 * 10, (m, n, k)
+
+
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_forced_unsplit(opa, opb):
+    """The tile kernel forced unsplit through the measurement hook: ragged m,
+    n, k around the tile and k-stage sizes, a one-row and an empty product in
+    the same batch, alpha complex, beta = 1."""
+    rng = np.random.default_rng(60 + 2 * opa + opb)
+    shapes = [(1100, 1030, 130), (129, 300, 17), (256, 128, 16), (1, 200, 33), (0, 5, 5),
+              (385, 511, 1)]
+    mats, keep = [], []
+    mnk, ld, ptr = [], [], []
+    alpha = 0.6 - 0.8j
+    for (m, n, k) in shapes:
+        A = crandn(rng, *((m, k) if opa == 0 else (k, m)))
+        B = crandn(rng, *((k, n) if opb == 0 else (n, k)))
+        Cm = crandn(rng, m, n)
+        ta, tb, tc = to_dev(A, 1), to_dev(B, 1), to_dev(Cm, 1)
+        keep += [ta, tb, tc]
+        mats.append((A, B, Cm, tc))
+        mnk += [m, n, k]
+        ld += [max(A.shape[0], 1), max(B.shape[0], 1), max(m, 1)]
+        ptr += [ta.data_ptr(), tb.data_ptr(), tc.data_ptr()]
+    a1, p1 = i32(mnk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    ms = C.c_float(0)
+    st = lib.nudft2_test_gemm_cfg(1, opa, opb, len(shapes), p1, p2, p3, alpha.real, alpha.imag,
+                                  1.0, -1, C.byref(ms))
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+        if m == 0:
+            continue
+        oA = A if opa == 0 else A.conj().T
+        oB = B if opb == 0 else B.conj().T
+        ref = alpha * (oA @ oB) + Cm
+        got = from_dev(tc, m, n)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(got - ref).max() < TOL[1] * scale * max(1, k) ** 0.5 * 10, (m, n, k)
