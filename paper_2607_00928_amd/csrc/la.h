@@ -30,6 +30,13 @@ struct DescPool {
   void check_flag();   // synchronises; E_INTERNAL if the flag is set
   // copies n bytes to the device, returns the device address
   void* push(const void* src, size_t n);
+  // push of read-only kernel arguments: when the pool slot already holds the
+  // same bytes from an upload completed before the last sync_reset(), the
+  // copy is skipped (repeated sweeps re-push identical descriptor lists).
+  // A plain push() may be kernel-modified scratch: it ends reuse for the pool.
+  void* push_ro(const void* src, size_t n);
+  size_t valid = 0;        // slots [0, valid) mirror the host staging on the device
+  bool tainted = false;    // a plain push happened: no reuse
   void flush();
   void sync_reset();
   ~DescPool() { destroy(); }

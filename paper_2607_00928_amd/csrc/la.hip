@@ -20,6 +20,8 @@ void DescPool::init(size_t bytes, hipStream_t s) {
   destroy();
   cap = bytes;
   stream = s;
+  valid = 0;
+  tainted = false;
   ND_HIP(hipHostMalloc((void**)&host, cap, hipHostMallocDefault));
   ND_HIP(hipMalloc((void**)&dev, cap + 256));
   flag = (int*)(dev + cap);
@@ -45,10 +47,24 @@ void DescPool::destroy() {
 void DescPool::sync_reset() {
   if (deferred) return;
   ND_HIP(hipStreamSynchronize(stream));
+  if (!tainted) valid = std::max(valid, used);
   used = 0;
 }
 
+void* DescPool::push_ro(const void* src, size_t n) {
+  if (!deferred && !tainted && used + n <= valid && std::memcmp(host + used, src, n) == 0) {
+    void* d = dev + used;
+    used += (n + 255) & ~size_t(255);
+    return d;
+  }
+  const bool t = tainted;
+  void* d = push(src, n);
+  tainted = t;
+  return d;
+}
+
 void* DescPool::push(const void* src, size_t n) {
+  tainted = true;
   size_t need = (n + 255) & ~size_t(255);
   ND_CHECK(used + need <= cap, NUDFT2_E_INTERNAL, "descriptor pool exhausted");
   std::memcpy(host + used, src, n);
@@ -1037,7 +1053,7 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
     splits = (int)std::min<int64_t>(maxk / kmin_split, (2048 + wgs - 1) / wgs);
     splits = std::max(1, std::min(splits, 256));
   }
-  auto* dd = (GemmDesc<T>*)pool.push(sub.data(), sizeof(GemmDesc<T>) * n);
+  auto* dd = (GemmDesc<T>*)pool.push_ro(sub.data(), sizeof(GemmDesc<T>) * n);
   if (splits > 1) {
     int64_t mx = 0;
     for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
@@ -1116,7 +1132,7 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
       splits = (int)std::min<int64_t>((maxk + 255) / 256, (2048 + wgs - 1) / wgs);
       splits = std::max(1, std::min(splits, 64));
     }
-    auto* dd = (GemmDesc<T>*)pool.push(sub.data(), sizeof(GemmDesc<T>) * n);
+    auto* dd = (GemmDesc<T>*)pool.push_ro(sub.data(), sizeof(GemmDesc<T>) * n);
     if (splits > 1) {
       int64_t mx = 0;
       for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
@@ -1431,7 +1447,7 @@ static void trsv_small(DescPool& pool, const std::vector<TrsDesc<T>>& d, bool ct
   if (d.empty()) return;
   int maxr = 0;
   for (auto& q : d) maxr = std::max(maxr, q.nrhs);
-  auto* dd = (TrsDesc<T>*)pool.push(d.data(), sizeof(TrsDesc<T>) * d.size());
+  auto* dd = (TrsDesc<T>*)pool.push_ro(d.data(), sizeof(TrsDesc<T>) * d.size());
   if (ct)
     hipLaunchKernelGGL((trsv_lds_kernel<T, true>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
                        pool.stream, dd);
@@ -1506,7 +1522,7 @@ void copy_batched(DescPool& pool, const std::vector<CopyDesc<TD, TS>>& d) {
     }
     check_hazards("copy", v);
   }
-  auto* dd = (CopyDesc<TD, TS>*)pool.push(d.data(), sizeof(CopyDesc<TD, TS>) * d.size());
+  auto* dd = (CopyDesc<TD, TS>*)pool.push_ro(d.data(), sizeof(CopyDesc<TD, TS>) * d.size());
   hipLaunchKernelGGL((copy_kernel<TD, TS>), dim3(64, (unsigned)d.size()), dim3(256), 0,
                      pool.stream, dd);
   ND_HIP(hipGetLastError());
@@ -1521,7 +1537,7 @@ void fill_batched(DescPool& pool, const std::vector<FillDesc<T>>& d) {
       v.push_back(region(d[i].D, sizeof(cplx<T>), d[i].m, d[i].n, d[i].ld, true, (int)i));
     check_hazards("fill", v);
   }
-  auto* dd = (FillDesc<T>*)pool.push(d.data(), sizeof(FillDesc<T>) * d.size());
+  auto* dd = (FillDesc<T>*)pool.push_ro(d.data(), sizeof(FillDesc<T>) * d.size());
   hipLaunchKernelGGL((fill_kernel<T>), dim3(64, (unsigned)d.size()), dim3(256), 0,
                      pool.stream, dd);
   ND_HIP(hipGetLastError());

@@ -273,7 +273,7 @@ void hss_inverse(Ctx& cx, HSS2<T>& H, const double2* r, double2* d, int nrhs, So
     pd.push_back({q.m0, q.M, q.nx, q.ny});
     mmax = std::max(mmax, q.M);
   }
-  auto* dpd = (PrepDesc*)cx.pool.push(pd.data(), sizeof(PrepDesc) * pd.size());
+  auto* dpd = (PrepDesc*)cx.pool.push_ro(pd.data(), sizeof(PrepDesc) * pd.size());
   hipLaunchKernelGGL((prep_rhs_kernel<T>), dim3(grid_for(mmax * nrhs), (unsigned)pd.size()),
                      dim3(256), 0, cx.s, dpd, P->pts_2d, P->perm2d, r, P->Mtot, inv_scale, w.fw,
                      P->Mtot, nrhs);
@@ -339,7 +339,7 @@ void hss_inverse_adj(Ctx& cx, HSS2<T>& H, const double2* v, double2* out, int nr
     pd.push_back({q.m0, q.M, q.nx, q.ny});
     mmax = std::max(mmax, q.M);
   }
-  auto* dpd = (PrepDesc*)cx.pool.push(pd.data(), sizeof(PrepDesc) * pd.size());
+  auto* dpd = (PrepDesc*)cx.pool.push_ro(pd.data(), sizeof(PrepDesc) * pd.size());
   hipLaunchKernelGGL((prep_adj_kernel<T>), dim3(grid_for(mmax * nrhs), (unsigned)pd.size()),
                      dim3(256), 0, cx.s, dpd, P->pts_2d, P->perm2d, w.fw, P->Mtot, scale, out,
                      P->Mtot, nrhs);
