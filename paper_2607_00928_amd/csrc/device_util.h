@@ -23,6 +23,39 @@ template <typename T> __device__ inline int mrow(int lane, int v);
 template <> __device__ inline int mrow<double>(int lane, int v) { return (lane >> 4) + 4 * v; }
 template <> __device__ inline int mrow<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
 
+// Loads and stores through the global address space.  Pointers read out of a
+// descriptor are generic, and generic (flat) accesses also count against the
+// LDS wait counter: a wait for an LDS read would then wait for every global
+// load in flight, serialising a register prefetch with the LDS work.
+template <typename T> __device__ __forceinline__ T ldg(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T> __device__ __forceinline__ void stg(T* p, const T& v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+// complex elements go through a builtin two-vector (a struct copy would take
+// its source by generic reference and turn the access back into a flat one)
+typedef float gf2 __attribute__((ext_vector_type(2)));
+typedef double gd2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ldc(const float2* p) {
+  const gf2 v = *(const __attribute__((address_space(1))) gf2*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ldc(const double2* p) {
+  const gd2 v = *(const __attribute__((address_space(1))) gd2*)p;
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void stc(float2* p, float2 c) {
+  *(__attribute__((address_space(1))) gf2*)p = gf2{c.x, c.y};
+}
+__device__ __forceinline__ void stc(double2* p, double2 c) {
+  *(__attribute__((address_space(1))) gd2*)p = gd2{c.x, c.y};
+}
+template <typename T> __device__ __forceinline__ void atomic_addg(T* p, T v) {
+  __hip_atomic_fetch_add((__attribute__((address_space(1))) T*)p, v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename T> struct acc4;
 template <> struct acc4<double> { using type = dbl4; };
 template <> struct acc4<float> { using type = flt4; };

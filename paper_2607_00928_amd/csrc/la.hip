@@ -136,8 +136,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(
       a_at(u, i, l);
       C2 v = mk<T>(0, 0);
       if (i0 + i < d.m && l0 + l < kend)
-        v = OPA == OpN ? d.A[(int64_t)(i0 + i) + (int64_t)(l0 + l) * d.lda]
-                       : d.A[(int64_t)(l0 + l) + (int64_t)(i0 + i) * d.lda];
+        v = OPA == OpN ? ldc(d.A + (int64_t)(i0 + i) + (int64_t)(l0 + l) * d.lda)
+                       : ldc(d.A + (int64_t)(l0 + l) + (int64_t)(i0 + i) * d.lda);
       ra[u] = v;
     }
 #pragma unroll
@@ -146,8 +146,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(
       b_at(u, l, j);
       C2 v = mk<T>(0, 0);
       if (j0 + j < d.n && l0 + l < kend)
-        v = OPB == OpN ? d.B[(int64_t)(l0 + l) + (int64_t)(j0 + j) * d.ldb]
-                       : d.B[(int64_t)(j0 + j) + (int64_t)(l0 + l) * d.ldb];
+        v = OPB == OpN ? ldc(d.B + (int64_t)(l0 + l) + (int64_t)(j0 + j) * d.ldb)
+                       : ldc(d.B + (int64_t)(j0 + j) + (int64_t)(l0 + l) * d.ldb);
       rb[u] = v;
     }
   };
@@ -205,6 +205,53 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(
     if (st + 1 < nst) lstore(buf ^ 1);
     __syncthreads();
   }
+  if constexpr (sizeof(T) == 4) {
+    // FP32 accumulators: a lane holds rows 4 (lane / 16) .. + 3 of one column,
+    // 32 contiguous bytes of column-major C, read and written as two 16-byte
+    // accesses (8-byte aligned: dword alignment is all the hardware needs)
+    if (splits == 1) {
+      typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int ib = i0 + wr + a * 16 + 4 * (lane >> 4);
+          const int j = j0 + wc + b * 16 + (lane & 15);
+          if (j >= d.n || ib >= d.m) continue;
+          C2 out[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T p1 = acc1[a][b][v], p2 = acc2[a][b][v];
+            const T cr = p1 - p2, ci = acc3[a][b][v] - p1 - p2;
+            out[v] = mk<T>(d.ar * cr - d.ai * ci, d.ar * ci + d.ai * cr);
+          }
+          C2* p = d.C + (int64_t)ib + (int64_t)j * d.ldc;
+          if (ib + 3 < d.m) {
+            f4u* q = (f4u*)p;
+            f4u w0 = {out[0].x, out[0].y, out[1].x, out[1].y};
+            f4u w1 = {out[2].x, out[2].y, out[3].x, out[3].y};
+            if (d.beta != T(0)) {
+              const f4u o0 = ldg(q), o1 = ldg(q + 1);
+              w0 += d.beta * o0;
+              w1 += d.beta * o1;
+            }
+            stg(q, w0);
+            stg(q + 1, w1);
+          } else {
+            for (int v = 0; v < 4 && ib + v < d.m; ++v) {
+              C2 o = out[v];
+              if (d.beta != T(0)) {
+                const C2 c = ldc(p + v);
+                o.x += d.beta * c.x;
+                o.y += d.beta * c.y;
+              }
+              stc(p + v, o);
+            }
+          }
+        }
+      return;
+    }
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -219,16 +266,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(
           C2 out = mk<T>(d.ar * cr - d.ai * ci, d.ar * ci + d.ai * cr);
           C2* p = d.C + (int64_t)i + (int64_t)j * d.ldc;
           if (splits > 1) {
-            atomicAdd(&p->x, out.x);
-            atomicAdd(&p->y, out.y);
+            atomic_addg(&p->x, out.x);
+            atomic_addg(&p->y, out.y);
             continue;
           }
           if (d.beta != T(0)) {
-            const C2 o = *p;
+            const C2 o = ldc(p);
             out.x += d.beta * o.x;
             out.y += d.beta * o.y;
           }
-          *p = out;
+          stc(p, out);
         }
       }
 }
@@ -246,16 +293,16 @@ __device__ inline void skinny_store(const GemmDesc<T>& d, int i, int j, cplx<T> 
   cplx<T> out = mk<T>(d.ar * v.x - d.ai * v.y, d.ar * v.y + d.ai * v.x);
   cplx<T>* p = d.C + (int64_t)i + (int64_t)j * d.ldc;
   if (splits > 1) {
-    atomicAdd(&p->x, out.x);
-    atomicAdd(&p->y, out.y);
+    atomic_addg(&p->x, out.x);
+    atomic_addg(&p->y, out.y);
     return;
   }
   if (d.beta != T(0)) {
-    cplx<T> o = *p;
+    cplx<T> o = ldc(p);
     out.x += d.beta * o.x;
     out.y += d.beta * o.y;
   }
-  *p = out;
+  stc(p, out);
 }
 
 // op(A) = A: thread i accumulates row i of C over NC columns; the k loop
@@ -283,7 +330,7 @@ __global__ __launch_bounds__(256) void gemm_skinny_n_kernel(const GemmDesc<T>* _
     __syncthreads();
     for (int e = tid; e < SK_L * NC; e += 256) {
       int l = e % SK_L, j = e / SK_L;
-      Bs[l][j] = (l0 + l < ke && j < d.n) ? d.B[(int64_t)(l0 + l) + (int64_t)j * d.ldb] : mk<T>(0, 0);
+      Bs[l][j] = (l0 + l < ke && j < d.n) ? ldc(d.B + (int64_t)(l0 + l) + (int64_t)j * d.ldb) : mk<T>(0, 0);
     }
     __syncthreads();
     const int lm = min(SK_L, ke - l0);
@@ -292,14 +339,14 @@ __global__ __launch_bounds__(256) void gemm_skinny_n_kernel(const GemmDesc<T>* _
     for (; l + SK_U <= lm; l += SK_U) {
       C2 a[SK_U];
 #pragma unroll
-      for (int u = 0; u < SK_U; ++u) a[u] = row ? ap[(int64_t)(l + u) * d.lda] : mk<T>(0, 0);
+      for (int u = 0; u < SK_U; ++u) a[u] = row ? ldc(ap + (int64_t)(l + u) * d.lda) : mk<T>(0, 0);
 #pragma unroll
       for (int u = 0; u < SK_U; ++u)
 #pragma unroll
         for (int j = 0; j < NC; ++j) acc[j] = cadd(acc[j], cmul(a[u], Bs[l + u][j]));
     }
     for (; l < lm; ++l) {
-      const C2 a = row ? ap[(int64_t)l * d.lda] : mk<T>(0, 0);
+      const C2 a = row ? ldc(ap + (int64_t)l * d.lda) : mk<T>(0, 0);
 #pragma unroll
       for (int j = 0; j < NC; ++j) acc[j] = cadd(acc[j], cmul(a, Bs[l][j]));
     }
@@ -333,10 +380,10 @@ __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(const GemmDesc<T>* _
     C2 a[U], b[U][NC];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      a[u] = ap[l + 64 * u];
+      a[u] = ldc(ap + l + 64 * u);
 #pragma unroll
       for (int j = 0; j < NC; ++j)
-        b[u][j] = j < d.n ? d.B[(int64_t)(l + 64 * u) + (int64_t)j * d.ldb] : mk<T>(0, 0);
+        b[u][j] = j < d.n ? ldc(d.B + (int64_t)(l + 64 * u) + (int64_t)j * d.ldb) : mk<T>(0, 0);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -344,16 +391,113 @@ __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(const GemmDesc<T>* _
       for (int j = 0; j < NC; ++j) acc[j] = cadd(acc[j], cmulc(a[u], b[u][j]));
   }
   for (; l < ke; l += 64) {
-    const C2 a = ap[l];
+    const C2 a = ldc(ap + l);
 #pragma unroll
     for (int j = 0; j < NC; ++j)
-      if (j < d.n) acc[j] = cadd(acc[j], cmulc(a, d.B[(int64_t)l + (int64_t)j * d.ldb]));
+      if (j < d.n) acc[j] = cadd(acc[j], cmulc(a, ldc(d.B + (int64_t)l + (int64_t)j * d.ldb)));
   }
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
     if (j >= d.n) break;
     const T re = warp_sum(acc[j].x), im = warp_sum(acc[j].y);
     if (lane == 0) skinny_store(d, i, j, mk<T>(re, im), splits);
+  }
+}
+
+// Small products with a long k: C (m x n, m, n <= 16 MB, 16 NB) += alpha
+// A^H B (the Grams of tall panels).  Memory-bound on A and B: workgroup x
+// takes SG_KC rows of k, each wave a contiguous 16 U row slice per step of
+// its loop, on 16x16x4 matrix-core steps (Gauss products, as in gemm_kernel).
+// When A and B are the same matrix, one load feeds both operands (lane l
+// supplies A(k, l % 16) for op(A) and B(k, l % 16) for B).  The four waves'
+// sums meet in LDS and are added atomically to a pre-scaled C.
+constexpr int SG_KC = 4096;
+constexpr int SG_U = 2;
+
+template <typename T, int MB, int NB>
+__global__ __launch_bounds__(256) void gemm_smallmn_kernel(const GemmDesc<T>* __restrict__ descs) {
+  using C2 = cplx<T>;
+  using A4 = typename acc4<T>::type;
+  __shared__ C2 red[16 * MB][16 * NB];
+  const GemmDesc<T> d = descs[blockIdx.y];
+  const int kb = (int)blockIdx.x * SG_KC;
+  if (d.m <= 0 || d.n <= 0 || kb >= d.k) return;
+  const int ke = min(d.k, kb + SG_KC);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const bool same = d.A == d.B && d.lda == d.ldb && d.m == d.n;
+  A4 acc[MB][NB][3];
+#pragma unroll
+  for (int a = 0; a < MB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[a][b][t] = A4{0, 0, 0, 0};
+  bool arow[MB], bcol[NB];
+#pragma unroll
+  for (int a = 0; a < MB; ++a) arow[a] = 16 * a + r < d.m;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) bcol[b] = 16 * b + r < d.n;
+  constexpr int S = 4 * SG_U;   // matrix-core steps per slice
+  for (int base = kb + wave * 16 * SG_U; base < ke; base += 64 * SG_U) {
+    C2 av[S][MB], bv[S][NB];
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      const int kk = base + 4 * st + q;
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+        av[st][a] = (kk < ke && arow[a]) ? ldc(d.A + kk + (int64_t)(16 * a + r) * d.lda)
+                                         : mk<T>(0, 0);
+      if (!same) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          bv[st][b] = (kk < ke && bcol[b]) ? ldc(d.B + kk + (int64_t)(16 * b + r) * d.ldb)
+                                           : mk<T>(0, 0);
+      }
+    }
+    if (same) {
+#pragma unroll
+      for (int st = 0; st < S; ++st)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bv[st][b] = b < MB ? av[st][b] : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int st = 0; st < S; ++st)
+#pragma unroll
+      for (int a = 0; a < MB; ++a) {
+        // op(A) = A^H: real part A.x, imaginary part -A.y
+        const T ar = av[st][a].x, ai = -av[st][a].y, as = ar + ai;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const T br = bv[st][b].x, bi = bv[st][b].y;
+          acc[a][b][0] = mfma16(ar, br, acc[a][b][0]);
+          acc[a][b][1] = mfma16(ai, bi, acc[a][b][1]);
+          acc[a][b][2] = mfma16(as, br + bi, acc[a][b][2]);
+        }
+      }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T p1 = acc[a][b][0][v], p2 = acc[a][b][1][v];
+            const C2 val = mk<T>(p1 - p2, acc[a][b][2][v] - p1 - p2);
+            C2& o = red[16 * a + mrow<T>(lane, v)][16 * b + r];
+            o = w == 0 ? val : cadd(o, val);
+          }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < d.m * d.n; e += 256) {
+    const int i = e % d.m, j = e / d.m;
+    const C2 v = red[i][j];
+    C2* p = d.C + i + (int64_t)j * d.ldc;
+    atomic_addg(&p->x, d.ar * v.x - d.ai * v.y);
+    atomic_addg(&p->y, d.ar * v.y + d.ai * v.x);
   }
 }
 
@@ -366,8 +510,8 @@ __global__ void gemm_prescale_kernel(const GemmDesc<T>* __restrict__ descs) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
     int i = (int)(e % d.m), j = (int)(e / d.m);
     cplx<T>* p = d.C + (int64_t)i + (int64_t)j * d.ldc;
-    if (d.beta == T(0)) *p = mk<T>(0, 0);
-    else { cplx<T> v = *p; *p = mk<T>(v.x * d.beta, v.y * d.beta); }
+    if (d.beta == T(0)) stc(p, mk<T>(0, 0));
+    else { cplx<T> v = ldc(p); stc(p, mk<T>(v.x * d.beta, v.y * d.beta)); }
   }
 }
 
@@ -466,7 +610,7 @@ __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(
       const int gi = r0 + lr + 64 * k;
 #pragma unroll
       for (int l = 0; l < QP_CG; ++l)
-        a[k][l] = (gi < mr && c0 + l < jb) ? Ap[gi + (int64_t)(c0 + l) * d.lda] : mk<T>(0, 0);
+        a[k][l] = (gi < mr && c0 + l < jb) ? ldc(Ap + gi + (int64_t)(c0 + l) * d.lda) : mk<T>(0, 0);
     }
     if (w == 0)
       for (int e = tid; e < QR_NB * QR_NB; e += QP_NT) Ts[e % QR_NB][e / QR_NB] = mk<T>(0, 0);
@@ -617,14 +761,14 @@ __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(
         if (gi < jb) {
           C2* pr = d.R + (j0 + gi) + (int64_t)(j0 + c) * d.ldr;
           if (gi <= c) {
-            *pr = a[k][l];
-            *pa = gi == c ? mk<T>(1, 0) : mk<T>(0, 0);
+            stc(pr, a[k][l]);
+            stc(pa, gi == c ? mk<T>(1, 0) : mk<T>(0, 0));
           } else {
-            *pr = mk<T>(0, 0);
-            *pa = a[k][l];
+            stc(pr, mk<T>(0, 0));
+            stc(pa, a[k][l]);
           }
         } else {
-          *pa = a[k][l];
+          stc(pa, a[k][l]);
         }
       }
     }
@@ -931,7 +1075,7 @@ __global__ __launch_bounds__(256) void trsv_lds_kernel(const TrsDesc<T>* __restr
         int c = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
         while ((c + 1) * (c + 2) / 2 <= e) ++c;
         while (c * (c + 1) / 2 > e) --c;
-        v[u] = d.R[(e - c * (c + 1) / 2) + (int64_t)c * d.ldr];
+        v[u] = ldc(d.R + (e - c * (c + 1) / 2) + (int64_t)c * d.ldr);
       }
     }
 #pragma unroll
@@ -1084,6 +1228,33 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
 }
 
 template <typename T>
+static void smallmn_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, int maxm, int maxn,
+                            int maxk) {
+  const size_t n = sub.size();
+  auto* dd = (GemmDesc<T>*)pool.push_ro(sub.data(), sizeof(GemmDesc<T>) * n);
+  bool scale = false;
+  for (auto& g : sub) scale = scale || (g.m > 0 && g.n > 0 && g.beta != T(1));
+  if (scale)
+    hipLaunchKernelGGL((gemm_prescale_kernel<T>), dim3(4, (unsigned)n), dim3(256), 0, pool.stream,
+                       dd);
+  double fl = 0;
+  for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
+  const int mb = (maxm + 15) / 16, nb = (maxn + 15) / 16;
+  ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn, maxk,
+               2000 + 10 * mb + nb);
+  dim3 grid((unsigned)((maxk + SG_KC - 1) / SG_KC), (unsigned)n);
+  if (mb == 1 && nb == 1)
+    hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 1>), grid, dim3(256), 0, pool.stream, dd);
+  else if (mb == 1)
+    hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 2>), grid, dim3(256), 0, pool.stream, dd);
+  else if (nb == 1)
+    hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 1>), grid, dim3(256), 0, pool.stream, dd);
+  else
+    hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 2>), grid, dim3(256), 0, pool.stream, dd);
+  ND_HIP(hipGetLastError());
+}
+
+template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB,
                   int splits_force) {
   if (d.empty()) return;
@@ -1119,6 +1290,11 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     const int force =
         splits_force > 0 ? splits_force
                          : (splits_force < 0 ? 1 : tuned_splits<T>(opA, opB, maxm, maxn, maxk, (int)n));
+    if (splits_force == 0 && opA == OpC && opB == OpN && maxn > SK_N && maxm <= 32 &&
+        maxn <= 32 && maxk >= 2 * SG_KC) {
+      smallmn_batched<T>(pool, sub, maxm, maxn, maxk);
+      continue;
+    }
     if (maxn <= SK_N && opB == OpN) {
       skinny_batched<T>(pool, sub, opA, maxm, maxn, maxk, force);
       continue;

@@ -337,3 +337,48 @@ def test_gemm_forced_unsplit(opa, opb):
         got = from_dev(tc, m, n)
         scale = max(1.0, np.abs(ref).max())
         assert np.abs(got - ref).max() < TOL[1] * scale * max(1, k) ** 0.5 * 10, (m, n, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("beta", [0.0, 1.0, -0.5])
+def test_gemm_small_output_long_k(prec, beta):
+    """A^H B with at most 32 x 32 outputs and a long k (the small-output
+    path): Grams whose two operands are one matrix (same pointer), cross
+    products, outputs that are not multiples of 16, k not a multiple of the
+    per-workgroup slice, and an empty k in the same batch.  Bound: a
+    forward error of 8 u sqrt(k) |a_i| |b_j| per entry."""
+    rng = np.random.default_rng(80 + 3 * prec + int(2 * beta))
+    npt, _ = CT[prec]
+    u = np.finfo(npt).eps / 2
+    # (m, n, k, same operand)
+    shapes = [(16, 16, 100003, True), (15, 15, 50000, True), (20, 31, 9000, False),
+              (32, 32, 8193, False), (5, 12, 20000, False), (30, 9, 12000, False),
+              (16, 16, 0, False), (27, 27, 16500, True)]
+    mats, keep = [], []
+    mnk, ld, ptr = [], [], []
+    alpha = 0.8 - 0.45j
+    for (m, n, k, same) in shapes:
+        A = crandn(rng, k, m)
+        B = A if same else crandn(rng, k, n)
+        Cm = crandn(rng, m, n)
+        ta, tc = to_dev(A, prec), to_dev(Cm, prec)
+        tb = ta if same else to_dev(B, prec)
+        keep += [ta, tb, tc]
+        mats.append((A, B, Cm, tc))
+        mnk += [m, n, k]
+        ld += [max(k, 1), max(k, 1), m]
+        ptr += [ta.data_ptr(), tb.data_ptr(), tc.data_ptr()]
+    a1, p1 = i32(mnk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_gemm(prec, 1, 0, len(shapes), p1, p2, p3, alpha.real, alpha.imag, beta)
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n, k, same), (A, B, Cm, tc) in zip(shapes, mats):
+        Ac, Bc = A.astype(npt).astype(np.complex128), B.astype(npt).astype(np.complex128)
+        Cc = Cm.astype(npt).astype(np.complex128)
+        ref = alpha * (Ac.conj().T @ Bc) + beta * Cc
+        got = from_dev(tc, m, n)
+        na = np.linalg.norm(Ac, axis=0)
+        nb_ = np.linalg.norm(Bc, axis=0)
+        bound = 8 * u * max(1, k) ** 0.5 * np.outer(na, nb_) + 8 * u * np.abs(beta * Cc) + 1e-300
+        assert np.all(np.abs(got - ref) <= bound + 4 * u * np.abs(ref)), (m, n, k, same)
