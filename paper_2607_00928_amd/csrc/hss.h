@@ -117,7 +117,7 @@ struct Node2 {
   Mat<T> R, W;               // l >= 2
   Mat<T> B[3];               // l >= 1: with the siblings in child order
   Mat<T> F, G;               // stage-1 factors
-  Mat<double> TU, TV;        // stage-2 weights (r x r)
+  Mat<T> TU, TV;             // stage-2 weights (r x r)
   // URV factorization (Section 2.4): the node is a leaf of the (reduced) HSS
   // matrix with mm rows, nn unknowns, row basis U (mm x wU), column basis V
   // (nn x wV) and diagonal block D (mm x nn).

@@ -503,10 +503,10 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
           }
           return o;
         };
-        // the parents' FP64 weights T in the Gram precision (one copy per parent)
+        // the parents' weights T in the Gram precision (one copy per parent)
         std::map<std::pair<int, int>, Mat<G>> tconv;
-        auto convT = [&](const Mat<double>& m, int p, int key) -> Mat<G> {
-          if constexpr (std::is_same<G, double>::value) {
+        auto convT = [&](const Mat<T>& m, int p, int key) -> Mat<G> {
+          if constexpr (std::is_same<G, T>::value) {
             (void)p;
             (void)key;
             return m;
@@ -518,8 +518,8 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
             o.c = m.c;
             o.ld = std::max(m.r, 1);
             o.p = (cplx<G>*)cx.tmp_alloc(sizeof(cplx<G>) * (size_t)o.ld * std::max(m.c, 1));
-            std::vector<CopyDesc<G, double>> cd{{m.r, m.c, m.ld, o.ld, m.p, o.p, 0}};
-            if (m.r > 0 && m.c > 0) copy_batched<G, double>(cx.pool, cd);
+            std::vector<CopyDesc<G, T>> cd{{m.r, m.c, m.ld, o.ld, m.p, o.p, 0}};
+            if (m.r > 0 && m.c > 0) copy_batched<G, T>(cx.pool, cd);
             tconv[{p, key}] = o;
             return o;
           }
@@ -625,18 +625,19 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
       }
       std::vector<PcholOut> po;
       pchol_run(cx, Ks, rmax, tol2, po);
-      // P = orth(L), T = triangular factor (FP64)
-      std::vector<Mat<double>> A, Q, R;
-      std::vector<Mat<double>> Pm(nodes.size() * 2);
-      std::vector<Mat<double>*> mp, mt;
+      // P = orth(L) and its triangular factor T, in the working precision (the
+      // rank decisions above are the FP64 part)
+      std::vector<Mat<T>> A, Q, R;
+      std::vector<Mat<T>> Pw(nodes.size() * 2);
+      std::vector<Mat<T>*> mp, mt;
       for (size_t i = 0; i < nodes.size(); ++i) {
         Node2<T>& nd = bd.node(nodes[i].p, l, nodes[i].z);
         for (int s = 0; s < 2; ++s) {
           int r = po[2 * i + s].rank;
-          Pm[2 * i + s].r = s == 0 ? nd.wU : nd.wV;
-          Pm[2 * i + s].c = r;
-          mp.push_back(&Pm[2 * i + s]);
-          Mat<double>& Tm = s == 0 ? nd.TU : nd.TV;
+          Pw[2 * i + s].r = s == 0 ? nd.wU : nd.wV;
+          Pw[2 * i + s].c = r;
+          mp.push_back(&Pw[2 * i + s]);
+          Mat<T>& Tm = s == 0 ? nd.TU : nd.TV;
           Tm.r = r;
           Tm.c = r;
           mt.push_back(&Tm);
@@ -645,34 +646,30 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
       carve(P->arena, mp, &cx.tmp);
       // the T matrices persist until the children are processed: one chunk per level
       bd.own(-1, l, Builder<T>::K_TU, carve(P->arena, mt), old);
+      std::vector<CopyDesc<T, double>> lcd;
       for (size_t i = 0; i < nodes.size(); ++i) {
         Node2<T>& nd = bd.node(nodes[i].p, l, nodes[i].z);
         for (int s = 0; s < 2; ++s) {
-          if (po[2 * i + s].rank == 0) continue;
-          Mat<double> a = po[2 * i + s].L;
-          a.c = po[2 * i + s].rank;
+          const PcholOut& pc = po[2 * i + s];
+          if (pc.rank == 0) continue;
+          Mat<T> a;
+          a.r = pc.L.r;
+          a.c = pc.rank;
+          if constexpr (std::is_same<T, double>::value) {
+            a.p = pc.L.p;
+            a.ld = pc.L.ld;
+          } else {
+            a.ld = std::max(a.r, 1);
+            a.p = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * (size_t)a.ld * a.c);
+            lcd.push_back({a.r, a.c, pc.L.ld, a.ld, pc.L.p, a.p, 0});
+          }
           A.push_back(a);
-          Q.push_back(Pm[2 * i + s]);
+          Q.push_back(Pw[2 * i + s]);
           R.push_back(s == 0 ? nd.TU : nd.TV);
         }
       }
-      orth<double>(cx, A, Q, &R);
-      // working-precision copies of P and Q
-      std::vector<Mat<T>> Pw(nodes.size() * 2);
-      std::vector<Mat<T>*> mpw;
-      for (size_t i = 0; i < Pm.size(); ++i) {
-        Pw[i].r = Pm[i].r;
-        Pw[i].c = Pm[i].c;
-        mpw.push_back(&Pw[i]);
-      }
-      carve(P->arena, mpw, &cx.tmp);
-      {
-        std::vector<CopyDesc<T, double>> cd;
-        for (size_t i = 0; i < Pm.size(); ++i)
-          if (Pm[i].r > 0 && Pm[i].c > 0)
-            cd.push_back({Pm[i].r, Pm[i].c, Pm[i].ld, Pw[i].ld, Pm[i].p, Pw[i].p, 0});
-        copy_batched<T, double>(cx.pool, cd);
-      }
+      copy_batched<T, double>(cx.pool, lcd);
+      orth<T>(cx, A, Q, &R);
       // ---- updates
       // B^_{alpha,s} = P_alpha^H B Q_s
       std::map<int, std::vector<Mat<T>*>> mnb;   // per problem
