@@ -535,10 +535,19 @@ __global__ void gemm_prescale_kernel(const GemmDesc<T>* __restrict__ descs) {
 // update u_c = A(jj, c) + conj(scal) s_c by itself.  Row jj (jj < QR_NB) is
 // lane jj of the first row half of workgroup 0.  Groups loop over problems.
 // Requires all workgroups to be resident (cooperative launch).
+//
+// Everything the workgroups of a group exchange goes through device-coherent
+// operations: atomic adds of the sums, agent-scope atomic stores and loads
+// of the pivot row and of the zeroed slot.  The barrier therefore needs no
+// L2 writeback or invalidate (an agent-scope release or acquire costs both on
+// this multi-die part); each thread waits for all its memory operations to
+// complete before the workgroup arrives, which orders the exchanged stores
+// before the arrival count.
 __device__ inline void group_barrier(unsigned* cnt, unsigned target, int* err) {
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned it = 0;
     while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (++it > (1u << 26)) {
@@ -547,9 +556,19 @@ __device__ inline void group_barrier(unsigned* cnt, unsigned target, int* err) {
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
+}
+
+template <typename T>
+__device__ inline void st_agent(cplx<T>* p, cplx<T> v) {
+  __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline cplx<T> ld_agent(const cplx<T>* p) {
+  return mk<T>(__hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+               __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
 constexpr int QS = QR_NB + 1;          // rotating sum slots per column
@@ -653,13 +672,13 @@ __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(
         }
         if (row_owner) {
 #pragma unroll
-          for (int l = 0; l < QP_CG; ++l) rbuf[c0 + l] = a[0][l];
+          for (int l = 0; l < QP_CG; ++l) st_agent<T>(rbuf + c0 + l, a[0][l]);
         }
-        if (w == 0 && tid < QS) sums[((step + 1) % 3) * QS + tid] = mk<T>(0, 0);
+        if (w == 0 && tid < QS) st_agent<T>(sums + ((step + 1) % 3) * QS + tid, mk<T>(0, 0));
         group_barrier(cnt, (++epoch) * (unsigned)gsize, err);
         if (tid < QR_NB) {
-          tot[tid] = buf[tid];
-          rowv[tid] = rbuf[tid];
+          tot[tid] = ld_agent<T>(buf + tid);
+          rowv[tid] = ld_agent<T>(rbuf + tid);
         }
         __syncthreads();
       }
@@ -809,38 +828,59 @@ struct WyDesc {
   cplx<T>* Tout;       // kb x kb, leading dimension kb
 };
 
+constexpr int WY_NT = 1024;   // threads of a merge workgroup (one per problem)
+
 template <typename T>
-__global__ __launch_bounds__(256) void wy_merge_kernel(const WyDesc<T>* __restrict__ descs) {
+__global__ __launch_bounds__(WY_NT) void wy_merge_kernel(const WyDesc<T>* __restrict__ descs) {
   using C2 = cplx<T>;
   const WyDesc<T> d = descs[blockIdx.x];
   const int kb = d.kb, tid = threadIdx.x;
   const int nbi = (kb + QR_NB - 1) / QR_NB;
   C2* To = d.Tout;
   __shared__ C2 X[QR_OB - QR_NB][QR_NB];
-  for (int e = tid; e < kb * kb; e += 256) {
+  for (int e = tid; e < kb * kb; e += WY_NT) {
     int r = e % kb, c = e / kb;
     int bi = r / QR_NB, bj = c / QR_NB;
-    To[r + (int64_t)c * kb] =
-        bi == bj ? d.Tw[(int64_t)bi * QR_NB * QR_NB + (r % QR_NB) + (c % QR_NB) * QR_NB]
-                 : mk<T>(0, 0);
+    stc(To + r + (int64_t)c * kb,
+        bi == bj ? ldc(d.Tw + (int64_t)bi * QR_NB * QR_NB + (r % QR_NB) + (c % QR_NB) * QR_NB)
+                 : mk<T>(0, 0));
   }
   __syncthreads();
   for (int j = 1; j < nbi; ++j) {
     const int c0 = j * QR_NB, jb = min(QR_NB, kb - c0);
-    for (int e = tid; e < c0 * jb; e += 256) {
+    // the dot products issue WY_U independent loads before using them (the
+    // operands sit in L2; a one-load-at-a-time loop is latency-bound)
+    constexpr int WY_U = 8;
+    for (int e = tid; e < c0 * jb; e += WY_NT) {
       int r = e % c0, c = e / c0;
       C2 sum = mk<T>(0, 0);
-      for (int q = 0; q <= c; ++q)   // T_j upper triangular
-        sum = cadd(sum, cmul(d.S[r + (int64_t)(c0 + q) * d.lds], To[(c0 + q) + (int64_t)(c0 + c) * kb]));
+      for (int q0 = 0; q0 <= c; q0 += WY_U) {   // T_j upper triangular
+        C2 sv[WY_U], tv[WY_U];
+#pragma unroll
+        for (int u = 0; u < WY_U; ++u) {
+          const int q = min(q0 + u, c);
+          sv[u] = ldc(d.S + r + (int64_t)(c0 + q) * d.lds);
+          tv[u] = ldc(To + (c0 + q) + (int64_t)(c0 + c) * kb);
+        }
+#pragma unroll
+        for (int u = 0; u < WY_U; ++u)
+          if (q0 + u <= c) sum = cadd(sum, cmul(sv[u], tv[u]));
+      }
       X[r][c] = sum;
     }
     __syncthreads();
-    for (int e = tid; e < c0 * jb; e += 256) {
+    for (int e = tid; e < c0 * jb; e += WY_NT) {
       int r = e % c0, c = e / c0;
       C2 sum = mk<T>(0, 0);
-      for (int q = r; q < c0; ++q)   // T(0:c0, 0:c0) upper triangular
-        sum = cadd(sum, cmul(To[r + (int64_t)q * kb], X[q][c]));
-      To[r + (int64_t)(c0 + c) * kb] = mk<T>(-sum.x, -sum.y);
+      for (int q0 = r; q0 < c0; q0 += WY_U) {   // T(0:c0, 0:c0) upper triangular
+        C2 tv[WY_U];
+#pragma unroll
+        for (int u = 0; u < WY_U; ++u) tv[u] = ldc(To + r + (int64_t)min(q0 + u, c0 - 1) * kb);
+#pragma unroll
+        for (int u = 0; u < WY_U; ++u)
+          if (q0 + u < c0) sum = cadd(sum, cmul(tv[u], X[q0 + u][c]));
+      }
+      stc(To + r + (int64_t)(c0 + c) * kb, mk<T>(-sum.x, -sum.y));
     }
     __syncthreads();
   }
@@ -1465,7 +1505,7 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& din, void* ws) 
     gemm_batched<T>(pool, g1, OpC, OpN);
     if (!wy.empty()) {
       auto* dw = (WyDesc<T>*)pool.push(wy.data(), sizeof(WyDesc<T>) * wy.size());
-      hipLaunchKernelGGL((wy_merge_kernel<T>), dim3((unsigned)wy.size()), dim3(256), 0,
+      hipLaunchKernelGGL((wy_merge_kernel<T>), dim3((unsigned)wy.size()), dim3(WY_NT), 0,
                          pool.stream, dw);
       ND_HIP(hipGetLastError());
     }

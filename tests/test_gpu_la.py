@@ -382,3 +382,57 @@ def test_gemm_small_output_long_k(prec, beta):
         nb_ = np.linalg.norm(Bc, axis=0)
         bound = 8 * u * max(1, k) ** 0.5 * np.outer(na, nb_) + 8 * u * np.abs(beta * Cc) + 1e-300
         assert np.all(np.abs(got - ref) <= bound + 4 * u * np.abs(ref)), (m, n, k, same)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_geqrf_tall_panels(prec):
+    """Householder QR of tall panels that need many cooperating workgroups per
+    panel (up to 40000 rows: 79 FP32 / 157 FP64 workgroups exchanging column
+    sums every column), batched with a short one.  Checks Q [R; 0] = A through
+    the Q application, R upper triangular, and |diag R| against LAPACK."""
+    rng = np.random.default_rng(90 + prec)
+    shapes = [(40000, 40), (20000, 70), (9000, 33), (600, 20)]
+    keep, data = [], []
+    mn, ld, ptr = [], [], []
+    for (m, n) in shapes:
+        A = crandn(rng, m, n)
+        k = min(m, n)
+        nob = (k + 127) // 128
+        tsize = 128 * 128 * (nob - 1) + (k - 128 * (nob - 1)) ** 2
+        tA = to_dev(A, prec)
+        tR = torch.full((n, k), 7.0 - 3.0j, dtype=CT[prec][1], device=DEV)
+        tT = torch.full((tsize,), 5.0 + 1.0j, dtype=CT[prec][1], device=DEV)
+        keep += [tA, tR, tT]
+        data.append((A, tA, tR, tT))
+        mn += [m, n]
+        ld += [m, k]
+        ptr += [tA.data_ptr(), tR.data_ptr(), tT.data_ptr()]
+    a1, p1 = i32(mn)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_geqrf(prec, len(shapes), p1, p2, p3)
+    assert st == 0, lib.nudft2_last_error()
+    # C = [R; 0], then C <- Q C must reproduce A
+    dims, ld2, ptr2, Cs = [], [], [], []
+    for (m, n), (A, tA, tR, tT) in zip(shapes, data):
+        k = min(m, n)
+        R = from_dev(tR, k, n)
+        assert np.abs(np.tril(R, -1)).max() == 0
+        Cm = np.zeros((m, n), dtype=np.complex128)
+        Cm[:k] = R
+        tC = to_dev(Cm, prec)
+        keep.append(tC)
+        Cs.append(tC)
+        dims += [m, k, n]
+        ld2 += [m, m]
+        ptr2 += [tA.data_ptr(), tT.data_ptr(), tC.data_ptr()]
+        Rl = np.linalg.qr(A, mode="r")
+        assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(Rl)), rtol=1e-3 if prec else 1e-9)
+    b1, q1 = i32(dims)
+    b2, q2 = i32(ld2)
+    b3, q3 = i64(ptr2)
+    assert lib.nudft2_test_ormqr(prec, 0, len(shapes), q1, q2, q3) == 0
+    for (m, n), (A, tA, tR, tT), tC in zip(shapes, data, Cs):
+        err = np.abs(from_dev(tC, m, n) - A).max() / np.abs(A).max()
+        print(f"tall qr {m}x{n} prec{prec}: recon {err:.1e}")
+        assert err < 50 * TOL[prec] * np.sqrt(m)
