@@ -46,7 +46,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n512", choices=sorted(WORKLOADS))
     ap.add_argument("--eps", type=float, default=1e-2)
-    ap.add_argument("--ir-tol", type=float, default=1e-12)
+    ap.add_argument("--ir-tol", type=float, default=1e-10)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-factor comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nrhs16", action="store_true", help="also time 16 right-hand sides")

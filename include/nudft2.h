@@ -67,10 +67,11 @@ typedef struct {
                             c += S S^* A^*(f - Ac) (exact least squares for any f) */
   void* stream;       /* hipStream_t; NULL = default stream                     */
   size_t mem_cap;     /* device bytes the plan may hold; 0 = no cap             */
-  int32_t graph;      /* 1: each solve call runs its first refinement iteration
-                         eagerly, captures the next one (HSS solve sweep, update,
-                         exact apply, residual, norms) into a HIP graph and
-                         replays it for the rest; 0 (default): eager launches.
+  int32_t graph;      /* 1: each solve call runs its first two refinement
+                         iterations eagerly, captures the next one (exact apply,
+                         residual, HSS solve sweep, update, norms) into a HIP
+                         graph and replays it for the rest; 0 (default): eager
+                         launches.
                          Kernel profiling (nudft2_set_profiling) runs eagerly. */
 } nudft2_opts;
 
@@ -78,7 +79,9 @@ typedef struct {
 typedef struct {
   int32_t iterations;     /* refinement iterations taken                     */
   double rel_update;      /* last ||dc|| / ||c||                              */
-  double rel_residual;    /* last ||f - A c|| / ||f|| (first right-hand side)  */
+  double rel_residual;    /* last ||f - A c|| / ||f|| formed (first right-hand
+                             side): that of the iterate before the last update,
+                             1 after a single iteration                       */
 } nudft2_solve_info;
 
 /* Plan-wide report (host memory). */

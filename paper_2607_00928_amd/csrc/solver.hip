@@ -528,11 +528,12 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
   sc.copy(f, rr, M);
   sc.zero(c, N);
   const double fn = std::sqrt(sc.norms2({{f, M}})[0]);
-  int it = 0;
+  int it = 1;
   double upd = 0, res = 1;
   bool conv = false;
-  // one iteration: d = S r (or S S^H A^H r), c += d, r = f - A c, norms
-  auto body = [&](Ctx& k) {
+  // correction of the current iterate from its residual r: d = S r (or
+  // S S^H A^H r), c += d, norms of d and c
+  auto correct = [&](Ctx& k) {
     if (ne) {
       apply_adj(P, rr, rN, nrhs, k.s);
       sc.SH(k, rN, tM);
@@ -541,24 +542,32 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
       sc.S(k, rr, dd);
     }
     sc.axpby(k, 1.0, dd, 1.0, c, N);
-    apply_fwd(P, c, rr, nrhs, k.s);
-    sc.axpby(k, 1.0, f, -1.0, rr, M);
     sc.norm_into(k, 0, dd, N);
     sc.norm_into(k, 1, c, N);
-    sc.norm_into(k, 2, rr, M);
   };
-  for (it = 1; it <= maxit; ++it) {
+  // iterations after the first: the residual r = f - A c of the current
+  // iterate, then its correction.  A converged solve thus forms no residual
+  // after its last update; the residual reported is that of the iterate
+  // before it (the returned c differs from it by rel_update).
+  auto body = [&](Ctx& k) {
+    apply_fwd(P, c, rr, nrhs, k.s);
+    sc.axpby(k, 1.0, f, -1.0, rr, M);
+    sc.norm_into(k, 2, rr, M);
+    correct(k);
+  };
+  // first iteration: c = 0, r = f
+  correct(sc.cx);
+  upd = sc.worst_ratio(sc.read_norms(2), 0, 1);
+  conv = upd <= P->opts.ir_tol;
+  while (!conv && upd == upd && it < maxit) {   // (upd != upd: NaN, stop)
+    ++it;
     sc.run(body);
     std::vector<double> h = sc.read_norms(3);
     upd = sc.worst_ratio(h, 0, 1);
     res = std::sqrt(h[2 * nrhs]) / std::max(fn, 1e-300);
-    if (!(upd == upd)) break;   // NaN: stop
-    if (upd <= P->opts.ir_tol) {
-      conv = true;
-      break;
-    }
+    conv = upd <= P->opts.ir_tol;
   }
-  report(info, std::min(it, maxit), upd, res);
+  report(info, it, upd, res);
   if (!conv) throw Error(NUDFT2_E_NOCONV, "refinement did not reach ir_tol");
 }
 
@@ -576,28 +585,32 @@ void normal_solve(SolveCtx<T>& sc, const double2* g, double2* z, int& its, doubl
   sc.copy(g, rz, N);
   sc.zero(z, N);
   bool conv = false;
-  // one iteration: d = S S^H r, z += d, r = g - A^H A z, norms
-  auto body = [&](Ctx& k) {
+  // correction from the residual r: d = S S^H r, z += d, norms of d and z
+  auto correct = [&](Ctx& k) {
     sc.SH(k, rz, tM);
     sc.S(k, tM, dd);
     sc.axpby(k, 1.0, dd, 1.0, z, N);
-    apply_fwd(P, z, u, sc.nrhs, k.s);
-    apply_adj(P, u, rz, sc.nrhs, k.s);
-    sc.axpby(k, 1.0, g, -1.0, rz, N);
     sc.norm_into(k, 0, dd, N);
     sc.norm_into(k, 1, z, N);
   };
-  for (its = 1; its <= maxit; ++its) {
+  // later iterations: r = g - A^H A z of the current iterate, then its
+  // correction (no residual is formed after the last update)
+  auto body = [&](Ctx& k) {
+    apply_fwd(P, z, u, sc.nrhs, k.s);
+    apply_adj(P, u, rz, sc.nrhs, k.s);
+    sc.axpby(k, 1.0, g, -1.0, rz, N);
+    correct(k);
+  };
+  its = 1;
+  correct(sc.cx);
+  upd = sc.worst_ratio(sc.read_norms(2), 0, 1);
+  conv = upd <= P->opts.ir_tol;
+  while (!conv && upd == upd && its < maxit) {   // (upd != upd: NaN, stop)
+    ++its;
     sc.run(body);
-    std::vector<double> h = sc.read_norms(2);
-    upd = sc.worst_ratio(h, 0, 1);
-    if (!(upd == upd)) break;
-    if (upd <= P->opts.ir_tol) {
-      conv = true;
-      break;
-    }
+    upd = sc.worst_ratio(sc.read_norms(2), 0, 1);
+    conv = upd <= P->opts.ir_tol;
   }
-  its = std::min(its, maxit);
   if (!conv) throw Error(NUDFT2_E_NOCONV, "refinement did not reach ir_tol");
 }
 
