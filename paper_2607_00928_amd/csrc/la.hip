@@ -238,7 +238,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(
             stg(q, w0);
             stg(q + 1, w1);
           } else {
-            for (int v = 0; v < 4 && ib + v < d.m; ++v) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              if (ib + v >= d.m) break;
               C2 o = out[v];
               if (d.beta != T(0)) {
                 const C2 c = ldc(p + v);

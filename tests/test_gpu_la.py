@@ -436,3 +436,38 @@ def test_geqrf_tall_panels(prec):
         err = np.abs(from_dev(tC, m, n) - A).max() / np.abs(A).max()
         print(f"tall qr {m}x{n} prec{prec}: recon {err:.1e}")
         assert err < 50 * TOL[prec] * np.sqrt(m)
+
+
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_gemm_split_k_few_tiles(opa, opb, beta):
+    """FP32 products with a long k and few output tiles (the k loop split
+    over workgroups, atomic accumulation into a pre-scaled C): ragged m, n,
+    k around the tile, k stage and split sizes, beta 0 and 1."""
+    rng = np.random.default_rng(100 + 4 * opa + 2 * opb + int(beta))
+    shapes = [(300, 200, 5000), (129, 77, 3001), (128, 64, 700), (255, 130, 1029)]
+    mats, keep = [], []
+    mnk, ld, ptr = [], [], []
+    alpha = -0.3 + 0.95j
+    for (m, n, k) in shapes:
+        A = crandn(rng, *((m, k) if opa == 0 else (k, m)))
+        B = crandn(rng, *((k, n) if opb == 0 else (n, k)))
+        Cm = crandn(rng, m, n)
+        ta, tb, tc = to_dev(A, 1), to_dev(B, 1), to_dev(Cm, 1)
+        keep += [ta, tb, tc]
+        mats.append((A, B, Cm, tc))
+        mnk += [m, n, k]
+        ld += [A.shape[0], B.shape[0], m]
+        ptr += [ta.data_ptr(), tb.data_ptr(), tc.data_ptr()]
+    a1, p1 = i32(mnk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_gemm(1, opa, opb, len(shapes), p1, p2, p3, alpha.real, alpha.imag, beta)
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+        oA = A if opa == 0 else A.conj().T
+        oB = B if opb == 0 else B.conj().T
+        ref = alpha * (oA @ oB) + beta * Cm
+        got = from_dev(tc, m, n)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(got - ref).max() < TOL[1] * scale * k ** 0.5 * 10, (m, n, k)
