@@ -62,7 +62,8 @@ struct GemmDesc {
 // C) by the count the autotuned table gives for the launch's shape class
 // (gemm_tuning.inc, written by tune_gemm.py), else by a heuristic;
 // splits_force > 0 overrides both (used by the tuner); splits_force = -1
-// runs the tile kernel unsplit, without the table (measurement).
+// runs the tile kernel unsplit, without the table; splits_force = -2 takes
+// the heuristic without the table (the tuner's baseline).
 template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB,
                   int splits_force = 0);

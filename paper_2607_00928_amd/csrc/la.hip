@@ -1330,9 +1330,12 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     }
     if (maxt == 0) continue;
     const int force =
-        splits_force > 0 ? splits_force
-                         : (splits_force < 0 ? 1 : tuned_splits<T>(opA, opB, maxm, maxn, maxk, (int)n));
-    if (splits_force == 0 && opA == OpC && opB == OpN && maxn > SK_N && maxm <= 32 &&
+        splits_force > 0    ? splits_force
+        : splits_force == -1 ? 1
+        : splits_force == -2 ? 0
+                             : tuned_splits<T>(opA, opB, maxm, maxn, maxk, (int)n);
+    if ((splits_force == 0 || splits_force == -2) && opA == OpC && opB == OpN && maxn > SK_N &&
+        maxm <= 32 &&
         maxn <= 32 && maxk >= 2 * SG_KC) {
       smallmn_batched<T>(pool, sub, maxm, maxn, maxk);
       continue;
