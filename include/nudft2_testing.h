@@ -54,7 +54,9 @@ nudft2_status nudft2_test_mfma_layout32(const float* a, const float* b, float* d
  *        kb x kb factor T_b (leading dimension kb) starts at element
  *        128^2 b of Tb (Tb holds 128^2 (nb - 1) + kb_last^2 elements).
  * ormqr: C <- Q C (trans = 0) or Q^H C (trans = 1) with dims = (m, k, nc),
- *        ld = (ldv, ldc), ptrs = (V, Tb, C).
+ *        ld = (ldv, ldc), ptrs = (V, Tb, C); trans = 2: C <- Q C for C
+ *        holding [I; 0] on entry (explicit Q formation, which skips the
+ *        columns each block leaves unchanged).
  * pchol: diagonally pivoted Cholesky of Hermitian PSD K_i (w_i x w_i,
  *        complex128, leading dimension w_i, overwritten) into L_i (w_i x
  *        rmax_i), stopping when the remaining Schur-complement trace is at

@@ -147,7 +147,7 @@ static void test_ormqr(int trans, int nb, const int32_t* dims, const int32_t* ld
   pool.init(16 << 20, nullptr);
   void* ws;
   ND_HIP(hipMalloc(&ws, orm_workspace<T>(d)));
-  ormqr_batched<T>(pool, d, trans != 0, ws);
+  ormqr_batched<T>(pool, d, trans == 1, ws, trans == 2);
   pool.sync_reset();
   ND_HIP(hipFree(ws));
 }
@@ -401,7 +401,8 @@ nudft2_status nudft2_test_geqrf(int32_t prec, int32_t nb, const int32_t* mn, con
 nudft2_status nudft2_test_ormqr(int32_t prec, int32_t trans, int32_t nb, const int32_t* dims,
                                 const int32_t* ld, const int64_t* ptrs) {
   return guard([&] {
-    ND_CHECK(dims && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
+    ND_CHECK(dims && ld && ptrs && nb > 0 && trans >= 0 && trans <= 2, NUDFT2_E_INVAL,
+             "bad arguments");
     need_device();
     if (prec == 0) test_ormqr<double>(trans, nb, dims, ld, ptrs);
     else test_ormqr<float>(trans, nb, dims, ld, ptrs);

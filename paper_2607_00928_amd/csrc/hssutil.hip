@@ -40,7 +40,7 @@ void orth(Ctx& cx, std::vector<Mat<T>>& A, std::vector<Mat<T>>& Q,
   }
   fill_batched<T>(cx.pool, fd);
   void* ws2 = cx.tmp_alloc(orm_workspace<T>(od));
-  ormqr_batched<T>(cx.pool, od, false, ws2);
+  ormqr_batched<T>(cx.pool, od, false, ws2, true);
   if (Rout) copy_batched<T, T>(cx.pool, cd);
 }
 template void orth<float>(Ctx&, std::vector<Mat<float>>&, std::vector<Mat<float>>&,

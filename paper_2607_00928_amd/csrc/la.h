@@ -116,8 +116,13 @@ struct OrmDesc {
 };
 template <typename T>
 size_t orm_workspace(const std::vector<OrmDesc<T>>& d);
+// C <- Q C (trans false) or Q^H C.  from_identity (with trans false): C holds
+// [I; 0] on entry (explicit Q formation); block b then updates only the
+// columns from its first reflector on, the earlier ones being unit vectors
+// its reflectors leave alone.
 template <typename T>
-void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans, void* ws);
+void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans, void* ws,
+                   bool from_identity = false);
 
 // Diagonally pivoted Cholesky of Hermitian PSD matrices K (w x w, FP64, only
 // the lower triangle is read; overwritten by the Schur complement's lower

@@ -1548,7 +1548,9 @@ size_t orm_workspace(const std::vector<OrmDesc<T>>& d) {
 
 // C <- Q C or Q^H C block by block (QR_OB reflectors and their T_b at a time)
 template <typename T>
-void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans, void* ws) {
+void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans, void* ws,
+                   bool from_identity) {
+  ND_CHECK(!(from_identity && trans), NUDFT2_E_INTERNAL, "Q^H applied to an identity");
   if (d.empty()) return;
   if (hazards_enabled()) {
     std::vector<Region> v;
@@ -1586,12 +1588,15 @@ void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans,
       int j0 = blk * QR_OB;
       int kb = std::min(QR_OB, q.k - j0);
       int mr = q.m - j0;
+      const int c0 = from_identity ? std::min(j0, q.nc) : 0;   // first column touched
+      const int nc = q.nc - c0;
+      if (nc <= 0) continue;
       const cplx<T>* V = q.V + j0 + (int64_t)j0 * q.ldv;
       const cplx<T>* Tb = q.Tb + (int64_t)QR_OB * QR_OB * blk;
-      cplx<T>* Cp = q.C + j0;
-      g1.push_back({kb, q.nc, mr, q.ldv, q.ldc, QR_OB, V, Cp, W[i], T(1), T(0), T(0)});
-      g2.push_back({kb, q.nc, kb, kb, QR_OB, QR_OB, Tb, W[i], W2[i], T(1), T(0), T(0)});
-      g3.push_back({mr, q.nc, kb, q.ldv, QR_OB, q.ldc, V, W2[i], Cp, T(-1), T(0), T(1)});
+      cplx<T>* Cp = q.C + j0 + (int64_t)c0 * q.ldc;
+      g1.push_back({kb, nc, mr, q.ldv, q.ldc, QR_OB, V, Cp, W[i], T(1), T(0), T(0)});
+      g2.push_back({kb, nc, kb, kb, QR_OB, QR_OB, Tb, W[i], W2[i], T(1), T(0), T(0)});
+      g3.push_back({mr, nc, kb, q.ldv, QR_OB, q.ldc, V, W2[i], Cp, T(-1), T(0), T(1)});
     }
     gemm_batched<T>(pool, g1, OpC, OpN);
     gemm_batched<T>(pool, g2, trans ? OpC : OpN, OpN);
@@ -1769,7 +1774,7 @@ void fill_batched(DescPool& pool, const std::vector<FillDesc<T>>& d) {
   template size_t qr_workspace<T>(const std::vector<QRDesc<T>>&);                        \
   template void geqrf_batched<T>(DescPool&, const std::vector<QRDesc<T>>&, void*);       \
   template size_t orm_workspace<T>(const std::vector<OrmDesc<T>>&);                      \
-  template void ormqr_batched<T>(DescPool&, const std::vector<OrmDesc<T>>&, bool, void*); \
+  template void ormqr_batched<T>(DescPool&, const std::vector<OrmDesc<T>>&, bool, void*, bool); \
   template void trsv_upper_batched<T>(DescPool&, const std::vector<TrsDesc<T>>&, bool);  \
   template void fill_batched<T>(DescPool&, const std::vector<FillDesc<T>>&);
 INST(float)

@@ -148,6 +148,19 @@ def test_geqrf_ormqr(prec):
     b3, q3 = i64(ptr2)
     st = lib.nudft2_test_ormqr(prec, 0, len(shapes), q1, q2, q3)
     assert st == 0, lib.nudft2_last_error()
+    # explicit Q formation from the identity (trans = 2 skips the columns each
+    # block leaves unchanged) must give the same Q
+    ptr2i, Qi = [], []
+    for (m, n), (A, tA, tR, tT) in zip(shapes, data):
+        tQi = to_dev(np.eye(m), prec)
+        keep.append(tQi)
+        Qi.append(tQi)
+        ptr2i += [tA.data_ptr(), tT.data_ptr(), tQi.data_ptr()]
+    b4, q4 = i64(ptr2i)
+    assert lib.nudft2_test_ormqr(prec, 2, len(shapes), q1, q2, q4) == 0, lib.nudft2_last_error()
+    for (m, n), tQ, tQi in zip(shapes, Qs, Qi):
+        d = np.abs(from_dev(tQi, m, m) - from_dev(tQ, m, m)).max()
+        assert d < 10 * TOL[prec] * np.sqrt(m), (m, n, d)
     for (m, n), (A, tA, tR, tT), tQ in zip(shapes, data, Qs):
         k = min(m, n)
         Q = from_dev(tQ, m, m)
