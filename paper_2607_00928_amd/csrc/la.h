@@ -35,6 +35,9 @@ struct DescPool {
   // copy is skipped (repeated sweeps re-push identical descriptor lists).
   // A plain push() may be kernel-modified scratch: it ends reuse for the pool.
   void* push_ro(const void* src, size_t n);
+  // n bytes of device scratch for a kernel, without an upload (the caller
+  // initialises them on the stream); ends reuse like push()
+  void* reserve(size_t n);
   size_t valid = 0;        // slots [0, valid) mirror the host staging on the device
   bool tainted = false;    // a plain push happened: no reuse
   void flush();

@@ -74,11 +74,49 @@ void* DescPool::push(const void* src, size_t n) {
   return d;
 }
 
+void* DescPool::reserve(size_t n) {
+  tainted = true;
+  size_t need = (n + 255) & ~size_t(255);
+  ND_CHECK(used + need <= cap, NUDFT2_E_INTERNAL, "descriptor pool exhausted");
+  void* d = dev + used;
+  used += need;
+  return d;
+}
+
 void DescPool::flush() {
   if (used > 0) ND_HIP(hipMemcpyAsync(dev, host, used, hipMemcpyHostToDevice, stream));
 }
 
 namespace {
+
+// ------------------------------------------------------ descriptor lists
+// A kernel reads its descriptor list through device memory (a copy into the
+// pool) or, for a short list, from its own kernel arguments: then no
+// host-to-device copy sits between two kernels of the stream, and the
+// dispatches follow each other without the copy's gap.
+constexpr size_t kArgDescBytes = 3072;
+template <typename D>
+struct DescMem {
+  const D* p;
+  __device__ const D& operator[](int i) const { return p[i]; }
+};
+template <typename D, int N>
+struct DescArg {
+  D d[N];
+  __device__ const D& operator[](int i) const { return d[i]; }
+};
+// launch(list) with the list as DescArg (short) or DescMem (pool copy)
+template <typename D, class F>
+void with_descs(DescPool& pool, const D* v, size_t n, F&& launch) {
+  constexpr int N = (int)(kArgDescBytes / sizeof(D));
+  if (n <= (size_t)N) {
+    DescArg<D, N> a{};
+    std::memcpy(a.d, v, sizeof(D) * n);
+    launch(a);
+  } else {
+    launch(DescMem<D>{(const D*)pool.push_ro(v, sizeof(D) * n)});
+  }
+}
 
 // ------------------------------------------------------------------- GEMM
 constexpr int GT = 64;    // output tile
@@ -89,9 +127,8 @@ constexpr int GK = 16;    // k per stage
 // into registers while the current one is multiplied out of LDS (double
 // buffered, one barrier per stage).  LDS rows are padded to an odd multiple
 // of 16 banks, so the 16-lane groups of an operand read hit distinct banks.
-template <typename T, int OPA, int OPB>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(
-    const GemmDesc<T>* __restrict__ descs, int splits) {
+template <typename T, int OPA, int OPB, class DS>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS descs, int splits) {
   using C2 = cplx<T>;
   using A4 = typename acc4<T>::type;
   constexpr int LDT = GT + 64 / (int)sizeof(T);
@@ -312,9 +349,8 @@ __device__ inline void skinny_store(const GemmDesc<T>& d, int i, int j, cplx<T> 
 // parallelism on a bandwidth-bound stream).
 constexpr int SK_U = 8;
 
-template <typename T, int NC>
-__global__ __launch_bounds__(256) void gemm_skinny_n_kernel(const GemmDesc<T>* __restrict__ descs,
-                                                            int splits) {
+template <typename T, int NC, class DS>
+__global__ __launch_bounds__(256) void gemm_skinny_n_kernel(DS descs, int splits) {
   using C2 = cplx<T>;
   const GemmDesc<T> d = descs[blockIdx.y];
   const int i0 = blockIdx.x * 256;
@@ -361,9 +397,8 @@ __global__ __launch_bounds__(256) void gemm_skinny_n_kernel(const GemmDesc<T>* _
 
 // op(A) = A^H: wave w computes row i of C (a dot product along column i of
 // A) over NC columns; each lane keeps SK_U / 2 independent loads in flight.
-template <typename T, int NC>
-__global__ __launch_bounds__(256) void gemm_skinny_c_kernel(const GemmDesc<T>* __restrict__ descs,
-                                                            int splits) {
+template <typename T, int NC, class DS>
+__global__ __launch_bounds__(256) void gemm_skinny_c_kernel(DS descs, int splits) {
   using C2 = cplx<T>;
   constexpr int U = SK_U / 2;
   const GemmDesc<T> d = descs[blockIdx.y];
@@ -416,8 +451,8 @@ __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(const GemmDesc<T>* _
 constexpr int SG_KC = 4096;
 constexpr int SG_U = 2;
 
-template <typename T, int MB, int NB>
-__global__ __launch_bounds__(256) void gemm_smallmn_kernel(const GemmDesc<T>* __restrict__ descs) {
+template <typename T, int MB, int NB, class DS>
+__global__ __launch_bounds__(256) void gemm_smallmn_kernel(DS descs) {
   using C2 = cplx<T>;
   using A4 = typename acc4<T>::type;
   __shared__ C2 red[16 * MB][16 * NB];
@@ -504,8 +539,8 @@ __global__ __launch_bounds__(256) void gemm_smallmn_kernel(const GemmDesc<T>* __
 }
 
 // C <- beta C for split-k launches (beta 0 writes zeros)
-template <typename T>
-__global__ void gemm_prescale_kernel(const GemmDesc<T>* __restrict__ descs) {
+template <typename T, class DS>
+__global__ void gemm_prescale_kernel(DS descs) {
   const GemmDesc<T> d = descs[blockIdx.y];
   if (d.beta == T(1)) return;
   int64_t cnt = (int64_t)d.m * d.n;
@@ -593,10 +628,10 @@ __device__ inline T wave_sum63(T v) {
   return v;
 }
 
-template <typename T>
+template <typename T, class AS>
 __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(
-    const QRDesc<T>* __restrict__ descs, const int* __restrict__ active, int nact, int j0,
-    int gsize, cplx<T>* __restrict__ scratch, unsigned* __restrict__ bar, int* __restrict__ err) {
+    const QRDesc<T>* __restrict__ descs, AS active, int nact, int j0, int gsize,
+    cplx<T>* __restrict__ scratch, unsigned* __restrict__ bar, int* __restrict__ err) {
   using C2 = cplx<T>;
   constexpr int R = QPanel<T>::R;
   constexpr int HALF = 64 * R;           // rows of one row half
@@ -832,8 +867,8 @@ struct WyDesc {
 
 constexpr int WY_NT = 1024;   // threads of a merge workgroup (one per problem)
 
-template <typename T>
-__global__ __launch_bounds__(WY_NT) void wy_merge_kernel(const WyDesc<T>* __restrict__ descs) {
+template <typename T, class DS>
+__global__ __launch_bounds__(WY_NT) void wy_merge_kernel(DS descs) {
   using C2 = cplx<T>;
   const WyDesc<T> d = descs[blockIdx.x];
   const int kb = d.kb, tid = threadIdx.x;
@@ -1096,8 +1131,8 @@ __global__ void pchol_finish_kernel(const PcholDesc* __restrict__ descs, const i
 // lane read.
 constexpr int TRS_B = 128;
 
-template <typename T, bool CT>
-__global__ __launch_bounds__(256) void trsv_lds_kernel(const TrsDesc<T>* __restrict__ descs) {
+template <typename T, bool CT, class DS>
+__global__ __launch_bounds__(256) void trsv_lds_kernel(DS descs) {
   using C2 = cplx<T>;
   __shared__ C2 Rp[TRS_B * (TRS_B + 1) / 2];
   __shared__ C2 inv[TRS_B];
@@ -1167,8 +1202,8 @@ __global__ __launch_bounds__(256) void trsv_lds_kernel(const TrsDesc<T>* __restr
 }
 
 // ------------------------------------------------------------ copy / fill
-template <typename TD, typename TS>
-__global__ void copy_kernel(const CopyDesc<TD, TS>* __restrict__ descs) {
+template <typename TD, typename TS, class DS>
+__global__ void copy_kernel(DS descs) {
   const CopyDesc<TD, TS> d = descs[blockIdx.y];
   int64_t cnt = (int64_t)d.m * d.n;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
@@ -1184,8 +1219,8 @@ __global__ void copy_kernel(const CopyDesc<TD, TS>* __restrict__ descs) {
   }
 }
 
-template <typename T>
-__global__ void fill_kernel(const FillDesc<T>* __restrict__ descs) {
+template <typename T, class DS>
+__global__ void fill_kernel(DS descs) {
   const FillDesc<T> d = descs[blockIdx.y];
   int64_t cnt = (int64_t)d.m * d.n;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
@@ -1239,33 +1274,35 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
     splits = (int)std::min<int64_t>(maxk / kmin_split, (2048 + wgs - 1) / wgs);
     splits = std::max(1, std::min(splits, 256));
   }
-  auto* dd = (GemmDesc<T>*)pool.push_ro(sub.data(), sizeof(GemmDesc<T>) * n);
-  if (splits > 1) {
-    int64_t mx = 0;
-    for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
-    hipLaunchKernelGGL((gemm_prescale_kernel<T>),
-                       dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
-                            (unsigned)n),
-                       dim3(256), 0, pool.stream, dd);
-  }
   double fl = 0;
   for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
-  ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn, maxk,
-               (int)opA * 2 + 10 * splits + 1000);
-  dim3 grid((unsigned)bx, (unsigned)n, (unsigned)splits);
-  auto launch = [&](auto nc) {
-    constexpr int NC = decltype(nc)::value;
-    if (opA == OpN)
-      hipLaunchKernelGGL((gemm_skinny_n_kernel<T, NC>), grid, dim3(256), 0, pool.stream, dd,
-                         splits);
-    else
-      hipLaunchKernelGGL((gemm_skinny_c_kernel<T, NC>), grid, dim3(256), 0, pool.stream, dd,
-                         splits);
-  };
-  if (maxn <= 1) launch(std::integral_constant<int, 1>{});
-  else if (maxn <= 2) launch(std::integral_constant<int, 2>{});
-  else if (maxn <= 4) launch(std::integral_constant<int, 4>{});
-  else launch(std::integral_constant<int, 8>{});
+  int64_t mx = 0;
+  for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
+  with_descs(pool, sub.data(), n, [&](auto dd) {
+    using DS = decltype(dd);
+    if (splits > 1)
+      hipLaunchKernelGGL(
+          (gemm_prescale_kernel<T, DS>),
+          dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
+               (unsigned)n),
+          dim3(256), 0, pool.stream, dd);
+    ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn,
+                 maxk, (int)opA * 2 + 10 * splits + 1000);
+    dim3 grid((unsigned)bx, (unsigned)n, (unsigned)splits);
+    auto launch = [&](auto nc) {
+      constexpr int NC = decltype(nc)::value;
+      if (opA == OpN)
+        hipLaunchKernelGGL((gemm_skinny_n_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
+                           dd, splits);
+      else
+        hipLaunchKernelGGL((gemm_skinny_c_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
+                           dd, splits);
+    };
+    if (maxn <= 1) launch(std::integral_constant<int, 1>{});
+    else if (maxn <= 2) launch(std::integral_constant<int, 2>{});
+    else if (maxn <= 4) launch(std::integral_constant<int, 4>{});
+    else launch(std::integral_constant<int, 8>{});
+  });
   ND_HIP(hipGetLastError());
 }
 
@@ -1273,26 +1310,28 @@ template <typename T>
 static void smallmn_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, int maxm, int maxn,
                             int maxk) {
   const size_t n = sub.size();
-  auto* dd = (GemmDesc<T>*)pool.push_ro(sub.data(), sizeof(GemmDesc<T>) * n);
   bool scale = false;
   for (auto& g : sub) scale = scale || (g.m > 0 && g.n > 0 && g.beta != T(1));
-  if (scale)
-    hipLaunchKernelGGL((gemm_prescale_kernel<T>), dim3(4, (unsigned)n), dim3(256), 0, pool.stream,
-                       dd);
   double fl = 0;
   for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
   const int mb = (maxm + 15) / 16, nb = (maxn + 15) / 16;
-  ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn, maxk,
-               2000 + 10 * mb + nb);
-  dim3 grid((unsigned)((maxk + SG_KC - 1) / SG_KC), (unsigned)n);
-  if (mb == 1 && nb == 1)
-    hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 1>), grid, dim3(256), 0, pool.stream, dd);
-  else if (mb == 1)
-    hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 2>), grid, dim3(256), 0, pool.stream, dd);
-  else if (nb == 1)
-    hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 1>), grid, dim3(256), 0, pool.stream, dd);
-  else
-    hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 2>), grid, dim3(256), 0, pool.stream, dd);
+  with_descs(pool, sub.data(), n, [&](auto dd) {
+    using DS = decltype(dd);
+    if (scale)
+      hipLaunchKernelGGL((gemm_prescale_kernel<T, DS>), dim3(4, (unsigned)n), dim3(256), 0,
+                         pool.stream, dd);
+    ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn,
+                 maxk, 2000 + 10 * mb + nb);
+    dim3 grid((unsigned)((maxk + SG_KC - 1) / SG_KC), (unsigned)n);
+    if (mb == 1 && nb == 1)
+      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 1, DS>), grid, dim3(256), 0, pool.stream, dd);
+    else if (mb == 1)
+      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 2, DS>), grid, dim3(256), 0, pool.stream, dd);
+    else if (nb == 1)
+      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 1, DS>), grid, dim3(256), 0, pool.stream, dd);
+    else
+      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 2, DS>), grid, dim3(256), 0, pool.stream, dd);
+  });
   ND_HIP(hipGetLastError());
 }
 
@@ -1353,15 +1392,8 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
       splits = (int)std::min<int64_t>((maxk + 255) / 256, (2048 + wgs - 1) / wgs);
       splits = std::max(1, std::min(splits, 64));
     }
-    auto* dd = (GemmDesc<T>*)pool.push_ro(sub.data(), sizeof(GemmDesc<T>) * n);
-    if (splits > 1) {
-      int64_t mx = 0;
-      for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
-      hipLaunchKernelGGL((gemm_prescale_kernel<T>),
-                         dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
-                              (unsigned)n),
-                         dim3(256), 0, pool.stream, dd);
-    }
+    int64_t mx = 0;
+    for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
     dim3 grid(maxt, (unsigned)n, splits);
     double fl = 0;
     int mm = 0, mn = 0;
@@ -1370,26 +1402,47 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
       mm = std::max(mm, g.m);
       mn = std::max(mn, g.n);
     }
-    ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, mm, mn, maxk,
-                 (int)opA * 2 + (int)opB + 10 * splits);
-    if (opA == OpN && opB == OpN)
-      hipLaunchKernelGGL((gemm_kernel<T, OpN, OpN>), grid, dim3(256), 0, pool.stream, dd, splits);
-    else if (opA == OpC && opB == OpN)
-      hipLaunchKernelGGL((gemm_kernel<T, OpC, OpN>), grid, dim3(256), 0, pool.stream, dd, splits);
-    else if (opA == OpN && opB == OpC)
-      hipLaunchKernelGGL((gemm_kernel<T, OpN, OpC>), grid, dim3(256), 0, pool.stream, dd, splits);
-    else
-      hipLaunchKernelGGL((gemm_kernel<T, OpC, OpC>), grid, dim3(256), 0, pool.stream, dd, splits);
+    with_descs(pool, sub.data(), n, [&](auto dd) {
+      using DS = decltype(dd);
+      if (splits > 1)
+        hipLaunchKernelGGL(
+            (gemm_prescale_kernel<T, DS>),
+            dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
+                 (unsigned)n),
+            dim3(256), 0, pool.stream, dd);
+      ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, mm, mn, maxk,
+                   (int)opA * 2 + (int)opB + 10 * splits);
+      if (opA == OpN && opB == OpN)
+        hipLaunchKernelGGL((gemm_kernel<T, OpN, OpN, DS>), grid, dim3(256), 0, pool.stream, dd,
+                           splits);
+      else if (opA == OpC && opB == OpN)
+        hipLaunchKernelGGL((gemm_kernel<T, OpC, OpN, DS>), grid, dim3(256), 0, pool.stream, dd,
+                           splits);
+      else if (opA == OpN && opB == OpC)
+        hipLaunchKernelGGL((gemm_kernel<T, OpN, OpC, DS>), grid, dim3(256), 0, pool.stream, dd,
+                           splits);
+      else
+        hipLaunchKernelGGL((gemm_kernel<T, OpC, OpC, DS>), grid, dim3(256), 0, pool.stream, dd,
+                           splits);
+    });
     ND_HIP(hipGetLastError());
   }
 }
 
+__global__ void zero_words_kernel(unsigned* p, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    p[e] = 0;
+}
+
 // Launch the cooperative panel kernel: groups of gsize workgroups, as many
 // groups as fit on the device at once (they loop over the active problems).
+// Their sums and barrier counters live in pool scratch zeroed by a kernel
+// just before (no host copy between the two launches).
 template <typename T>
-void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const int* dact, int nact, int j0,
+void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const std::vector<int>& act, int j0,
                      int maxmr) {
-  const void* kern = (const void*)qr_panel_kernel<T>;
+  const int nact = (int)act.size();
+  const void* kern = (const void*)qr_panel_kernel<T, DescMem<int>>;
   static int max_res[2] = {0, 0};
   int& mres = max_res[sizeof(T) == 4 ? 0 : 1];
   if (mres == 0) {
@@ -1405,16 +1458,21 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const int* dact, int n
   int gsize = std::max(1, (maxmr + rows - 1) / rows);
   ND_CHECK(gsize <= mres, NUDFT2_E_INTERNAL, "QR panel taller than the device can hold");
   int ngroups = std::max(1, std::min(nact, mres / gsize));
-  std::vector<char> zeros((size_t)ngroups * (QSCR * sizeof(cplx<T>) + sizeof(unsigned)) + 64, 0);
-  cplx<T>* scr = (cplx<T>*)pool.push(zeros.data(), (size_t)ngroups * QSCR * sizeof(cplx<T>));
-  unsigned* bar = (unsigned*)pool.push(zeros.data(), (size_t)ngroups * sizeof(unsigned));
+  const size_t scr_bytes = ((size_t)ngroups * QSCR * sizeof(cplx<T>) + 255) & ~size_t(255);
+  const size_t words = (scr_bytes + (size_t)ngroups * sizeof(unsigned)) / sizeof(unsigned);
+  char* z = (char*)pool.reserve(words * sizeof(unsigned));
+  cplx<T>* scr = (cplx<T>*)z;
+  unsigned* bar = (unsigned*)(z + scr_bytes);
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)std::min<size_t>((words + 255) / 256, 1024)),
+                     dim3(256), 0, pool.stream, (unsigned*)z, (int64_t)words);
   int* err = pool.flag;
-  void* args[] = {(void*)&dd, (void*)&dact, (void*)&nact, (void*)&j0, (void*)&gsize,
-                  (void*)&scr, (void*)&bar, (void*)&err};
-  {
+  with_descs(pool, act.data(), act.size(), [&](auto as) {
+    const void* k = (const void*)qr_panel_kernel<T, decltype(as)>;
+    void* args[] = {(void*)&dd, (void*)&as, (void*)&nact, (void*)&j0, (void*)&gsize,
+                    (void*)&scr, (void*)&bar, (void*)&err};
     ProfScope ps(pool.stream, KC_QRPANEL, 0.0, nact, maxmr, 0, 0, gsize);
-    ND_HIP(hipLaunchCooperativeKernel(kern, dim3(ngroups * gsize), dim3(QP_NT), args, 0, pool.stream));
-  }
+    ND_HIP(hipLaunchCooperativeKernel(k, dim3(ngroups * gsize), dim3(QP_NT), args, 0, pool.stream));
+  });
 }
 
 // per problem: W and W2 (QR_OB x n), S (QR_OB x QR_OB), the panels' factors
@@ -1486,10 +1544,9 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& din, void* ws) 
         g2.push_back({jb, nt, jb, QR_NB, QR_NB, QR_NB, Tj, W[i], W2[i], T(1), T(0), T(0)});
         g3.push_back({mr, nt, jb, q.lda, QR_NB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
       }
-      int* dact = (int*)pool.push(act.data(), sizeof(int) * act.size());
       int maxmr = 0;
       for (int i : act) maxmr = std::max(maxmr, d[i].m - j0);
-      qr_panel_launch<T>(pool, dd, dact, (int)act.size(), j0, maxmr);
+      qr_panel_launch<T>(pool, dd, act, j0, maxmr);
       gemm_batched<T>(pool, g1, OpC, OpN);
       gemm_batched<T>(pool, g2, OpC, OpN);
       gemm_batched<T>(pool, g3, OpN, OpN);
@@ -1509,9 +1566,10 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& din, void* ws) 
     }
     gemm_batched<T>(pool, g1, OpC, OpN);
     if (!wy.empty()) {
-      auto* dw = (WyDesc<T>*)pool.push(wy.data(), sizeof(WyDesc<T>) * wy.size());
-      hipLaunchKernelGGL((wy_merge_kernel<T>), dim3((unsigned)wy.size()), dim3(WY_NT), 0,
-                         pool.stream, dw);
+      with_descs(pool, wy.data(), wy.size(), [&](auto dw) {
+        hipLaunchKernelGGL((wy_merge_kernel<T, decltype(dw)>), dim3((unsigned)wy.size()),
+                           dim3(WY_NT), 0, pool.stream, dw);
+      });
       ND_HIP(hipGetLastError());
     }
     // trailing columns beyond the block: one update with the block's reflectors
@@ -1673,13 +1731,15 @@ static void trsv_small(DescPool& pool, const std::vector<TrsDesc<T>>& d, bool ct
   if (d.empty()) return;
   int maxr = 0;
   for (auto& q : d) maxr = std::max(maxr, q.nrhs);
-  auto* dd = (TrsDesc<T>*)pool.push_ro(d.data(), sizeof(TrsDesc<T>) * d.size());
-  if (ct)
-    hipLaunchKernelGGL((trsv_lds_kernel<T, true>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
-                       pool.stream, dd);
-  else
-    hipLaunchKernelGGL((trsv_lds_kernel<T, false>), dim3((unsigned)d.size(), maxr), dim3(256), 0,
-                       pool.stream, dd);
+  with_descs(pool, d.data(), d.size(), [&](auto dd) {
+    using DS = decltype(dd);
+    if (ct)
+      hipLaunchKernelGGL((trsv_lds_kernel<T, true, DS>), dim3((unsigned)d.size(), maxr), dim3(256),
+                         0, pool.stream, dd);
+    else
+      hipLaunchKernelGGL((trsv_lds_kernel<T, false, DS>), dim3((unsigned)d.size(), maxr),
+                         dim3(256), 0, pool.stream, dd);
+  });
   ND_HIP(hipGetLastError());
 }
 
@@ -1748,9 +1808,10 @@ void copy_batched(DescPool& pool, const std::vector<CopyDesc<TD, TS>>& d) {
     }
     check_hazards("copy", v);
   }
-  auto* dd = (CopyDesc<TD, TS>*)pool.push_ro(d.data(), sizeof(CopyDesc<TD, TS>) * d.size());
-  hipLaunchKernelGGL((copy_kernel<TD, TS>), dim3(64, (unsigned)d.size()), dim3(256), 0,
-                     pool.stream, dd);
+  with_descs(pool, d.data(), d.size(), [&](auto dd) {
+    hipLaunchKernelGGL((copy_kernel<TD, TS, decltype(dd)>), dim3(64, (unsigned)d.size()),
+                       dim3(256), 0, pool.stream, dd);
+  });
   ND_HIP(hipGetLastError());
 }
 
@@ -1763,9 +1824,10 @@ void fill_batched(DescPool& pool, const std::vector<FillDesc<T>>& d) {
       v.push_back(region(d[i].D, sizeof(cplx<T>), d[i].m, d[i].n, d[i].ld, true, (int)i));
     check_hazards("fill", v);
   }
-  auto* dd = (FillDesc<T>*)pool.push_ro(d.data(), sizeof(FillDesc<T>) * d.size());
-  hipLaunchKernelGGL((fill_kernel<T>), dim3(64, (unsigned)d.size()), dim3(256), 0,
-                     pool.stream, dd);
+  with_descs(pool, d.data(), d.size(), [&](auto dd) {
+    hipLaunchKernelGGL((fill_kernel<T, decltype(dd)>), dim3(64, (unsigned)d.size()), dim3(256),
+                       0, pool.stream, dd);
+  });
   ND_HIP(hipGetLastError());
 }
 
