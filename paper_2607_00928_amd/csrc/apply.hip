@@ -22,13 +22,13 @@ constexpr int TM = 64;    // rows (points) per workgroup
 constexpr int TN = 64;    // kx per chunk
 constexpr int TKY = 16;   // ky per shared-memory stage
 
-__global__ __launch_bounds__(256) void apply_fwd_kernel(
+__global__ __launch_bounds__(256, 2) void apply_fwd_kernel(
     const double* __restrict__ pts, const double2* __restrict__ c,
     double2* __restrict__ f, const ApplyProb* __restrict__ probs, int nprob,
     const int* __restrict__ tile_off, int64_t Mtot, int64_t Ntot) {
   __shared__ double2 E1y[TM][TKY + 1];
   __shared__ double2 E1x[TM][17];
-  __shared__ double Cr[TKY][TN + 1], Ci[TKY][TN + 1];
+  __shared__ double Cr[TKY][TN + 1], Ci[TKY][TN + 1], Cs[TKY][TN + 1];
   __shared__ double2 basey[TM];
   __shared__ double2 basex[TM][TN / 16];
   __shared__ double ptx[TM], pty[TM];
@@ -70,8 +70,14 @@ __global__ __launch_bounds__(256) void apply_fwd_kernel(
   const int kq = lane >> 4;                   // k index within a 4-step
 
   for (int kx0 = 0; kx0 < nx; kx0 += TN) {
-    dbl4 accr[4], acci[4];
-    for (int t = 0; t < 4; ++t) { accr[t] = dbl4{0, 0, 0, 0}; acci[t] = dbl4{0, 0, 0, 0}; }
+    // Gauss products: p1 = Ar Cr, p2 = Ai Ci, p3 = (Ar + Ai)(Cr + Ci);
+    // Re = p1 - p2, Im = p3 - p1 - p2 (three matrix-core products, not four)
+    dbl4 acc1[4], acc2[4], acc3[4];
+    for (int t = 0; t < 4; ++t) {
+      acc1[t] = dbl4{0, 0, 0, 0};
+      acc2[t] = dbl4{0, 0, 0, 0};
+      acc3[t] = dbl4{0, 0, 0, 0};
+    }
     for (int ky0 = 0; ky0 < ny; ky0 += TKY) {
       __syncthreads();
       {
@@ -85,6 +91,7 @@ __global__ __launch_bounds__(256) void apply_fwd_kernel(
           if (kx < nx && ky < ny) v = cp[(int64_t)kx * ny + ky];
           Cr[t][kxl] = v.x;
           Ci[t][kxl] = v.y;
+          Cs[t][kxl] = v.x + v.y;
         }
       }
       if (tid < TM) basey[tid] = expi_kx((double)(ky0 - ny / 2), pty[tid]);
@@ -94,14 +101,13 @@ __global__ __launch_bounds__(256) void apply_fwd_kernel(
         int t = kk * 4 + kq;
         double2 a = mk<double>(0.0, 0.0);
         if (ky0 + t < ny) a = cmul(basey[arow], E1y[arow][t]);
+        const double as = a.x + a.y;
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-          double br = Cr[t][tt * 16 + (lane & 15)];
-          double bi = Ci[t][tt * 16 + (lane & 15)];
-          accr[tt] = mfma16(a.x, br, accr[tt]);
-          accr[tt] = mfma16(-a.y, bi, accr[tt]);
-          acci[tt] = mfma16(a.x, bi, acci[tt]);
-          acci[tt] = mfma16(a.y, br, acci[tt]);
+          const int kxl = tt * 16 + (lane & 15);
+          acc1[tt] = mfma16(a.x, Cr[t][kxl], acc1[tt]);
+          acc2[tt] = mfma16(a.y, Ci[t][kxl], acc2[tt]);
+          acc3[tt] = mfma16(as, Cs[t][kxl], acc3[tt]);
         }
       }
     }
@@ -120,7 +126,8 @@ __global__ __launch_bounds__(256) void apply_fwd_kernel(
       for (int v = 0; v < 4; ++v) {
         int r = wave * 16 + mrow<double>(lane, v);
         double2 ax = cmul(basex[r][tt], E1x[r][lane & 15]);
-        double tr = accr[tt][v], ti = acci[tt][v];
+        const double p1 = acc1[tt][v], p2 = acc2[tt][v];
+        const double tr = p1 - p2, ti = acc3[tt][v] - p1 - p2;
         if (ok) {
           facc[v] += ax.x * tr - ax.y * ti;
           faci[v] += ax.x * ti + ax.y * tr;
