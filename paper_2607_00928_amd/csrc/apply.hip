@@ -157,7 +157,7 @@ constexpr int AK = 16;     // points per stage
 constexpr int ACHUNK = 2048;
 
 // C[kx][ky] += sum_{j in chunk} conj(Ax[j][kx]) f_j conj(Ay[j][ky])
-__global__ __launch_bounds__(256) void apply_adj_kernel(
+__global__ __launch_bounds__(256, 2) void apply_adj_kernel(
     const double* __restrict__ pts, const double2* __restrict__ f,
     double2* __restrict__ c, ApplyProb pr, int64_t Mtot, int64_t Ntot) {
   __shared__ double Ar[AK][AT + 1], Ai[AK][AT + 1];
@@ -177,9 +177,15 @@ __global__ __launch_bounds__(256) void apply_adj_kernel(
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;   // wave's 32x32 sub-tile
   const int nx = pr.nx, ny = pr.ny;
 
-  dbl4 accr[2][2], acci[2][2];
+  // Gauss products (three per complex multiply-add): p1 = Ar Br, p2 = Ai Bi,
+  // p3 = (Ar + Ai)(Br + Bi); Re = p1 - p2, Im = p3 - p1 - p2
+  dbl4 acc1[2][2], acc2[2][2], acc3[2][2];
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) { accr[a][b] = dbl4{0, 0, 0, 0}; acci[a][b] = dbl4{0, 0, 0, 0}; }
+    for (int b = 0; b < 2; ++b) {
+      acc1[a][b] = dbl4{0, 0, 0, 0};
+      acc2[a][b] = dbl4{0, 0, 0, 0};
+      acc3[a][b] = dbl4{0, 0, 0, 0};
+    }
 
   const int64_t jend = min((int64_t)pr.M, j0 + ACHUNK);
   for (int64_t js = j0; js < jend; js += AK) {
@@ -224,10 +230,9 @@ __global__ __launch_bounds__(256) void apply_adj_kernel(
       }
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
-          accr[a][b] = mfma16(ar[a], br[b], accr[a][b]);
-          accr[a][b] = mfma16(-ai[a], bi[b], accr[a][b]);
-          acci[a][b] = mfma16(ar[a], bi[b], acci[a][b]);
-          acci[a][b] = mfma16(ai[a], br[b], acci[a][b]);
+          acc1[a][b] = mfma16(ar[a], br[b], acc1[a][b]);
+          acc2[a][b] = mfma16(ai[a], bi[b], acc2[a][b]);
+          acc3[a][b] = mfma16(ar[a] + ai[a], br[b] + bi[b], acc3[a][b]);
         }
     }
   }
@@ -238,8 +243,9 @@ __global__ __launch_bounds__(256) void apply_adj_kernel(
         int ky = ky0 + wn + b * 16 + (lane & 15);
         if (kx < nx && ky < ny) {
           double* dst = reinterpret_cast<double*>(cp + (int64_t)kx * ny + ky);
-          atomicAdd(dst, accr[a][b][v]);
-          atomicAdd(dst + 1, acci[a][b][v]);
+          const double p1 = acc1[a][b][v], p2 = acc2[a][b][v];
+          atomicAdd(dst, p1 - p2);
+          atomicAdd(dst + 1, acc3[a][b][v] - p1 - p2);
         }
       }
 }
