@@ -49,10 +49,10 @@ nudft2_status nudft2_test_mfma_layout32(const float* a, const float* b, float* d
  * geqrf: Householder QR; mn = (m, n), ld = (lda, ldr), ptrs = (A, R, Tb).
  *        A returns the explicit unit lower-trapezoidal reflectors V, R the
  *        triangular factor, Tb the compact-WY factors of the column blocks
- *        of 128 reflectors (Q = prod_b (I - V_b T_b V_b^H)): with
- *        k = min(m, n), block b has kb = min(128, k - 128 b) columns and its
+ *        of 256 reflectors (Q = prod_b (I - V_b T_b V_b^H)): with
+ *        k = min(m, n), block b has kb = min(256, k - 256 b) columns and its
  *        kb x kb factor T_b (leading dimension kb) starts at element
- *        128^2 b of Tb (Tb holds 128^2 (nb - 1) + kb_last^2 elements).
+ *        256^2 b of Tb (Tb holds 256^2 (nb - 1) + kb_last^2 elements).
  * ormqr: C <- Q C (trans = 0) or Q^H C (trans = 1) with dims = (m, k, nc),
  *        ld = (ldv, ldc), ptrs = (V, Tb, C); trans = 2: C <- Q C for C
  *        holding [I; 0] on entry (explicit Q formation, which skips the

@@ -78,11 +78,14 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
 // = Q_0 Q_1 ..., Q_b = I - V_b T_b V_b^H).  Block b has kb = min(QR_OB, kmin -
 // QR_OB b) columns; its T_b (kb x kb, leading dimension kb) starts at
 // Tb + QR_OB^2 b; qr_tsize gives the element count.  The factorization runs in
-// QR_NB-column panels (one cooperative launch each) with their updates
-// confined to the block, then updates the trailing columns once per block.
+// QR_NB-column panels (one cooperative launch each) whose updates stay inside
+// their half of the block (QR_HB columns); the left half's reflectors then
+// update the right half, the block's T joins the two halves' factors, and the
+// trailing columns are updated once per block.
 // ws: workspace (see qr_workspace).
 constexpr int QR_NB = 32;
-constexpr int QR_OB = 128;
+constexpr int QR_OB = 256;
+constexpr int QR_HB = 128;   // the two halves of a block (see geqrf_batched)
 template <typename T>
 struct QRDesc {
   int m, n;

@@ -859,10 +859,10 @@ __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(
 // order (Q_A Q_B = I - [V_A V_B] [T_A, -T_A V_A^H V_B T_B; 0, T_B] [V_A V_B]^H).
 template <typename T>
 struct WyDesc {
-  int kb, lds;
+  int kb, lds, ldt;    // kb <= QR_HB
   const cplx<T>* Tw;   // the panels' QR_NB x QR_NB factors
   const cplx<T>* S;    // kb x kb, lds
-  cplx<T>* Tout;       // kb x kb, leading dimension kb
+  cplx<T>* Tout;       // kb x kb, leading dimension ldt
 };
 
 constexpr int WY_NT = 1024;   // threads of a merge workgroup (one per problem)
@@ -871,14 +871,14 @@ template <typename T, class DS>
 __global__ __launch_bounds__(WY_NT) void wy_merge_kernel(DS descs) {
   using C2 = cplx<T>;
   const WyDesc<T> d = descs[blockIdx.x];
-  const int kb = d.kb, tid = threadIdx.x;
+  const int kb = d.kb, ldt = d.ldt, tid = threadIdx.x;
   const int nbi = (kb + QR_NB - 1) / QR_NB;
   C2* To = d.Tout;
-  __shared__ C2 X[QR_OB - QR_NB][QR_NB];
+  __shared__ C2 X[QR_HB - QR_NB][QR_NB];
   for (int e = tid; e < kb * kb; e += WY_NT) {
     int r = e % kb, c = e / kb;
     int bi = r / QR_NB, bj = c / QR_NB;
-    stc(To + r + (int64_t)c * kb,
+    stc(To + r + (int64_t)c * ldt,
         bi == bj ? ldc(d.Tw + (int64_t)bi * QR_NB * QR_NB + (r % QR_NB) + (c % QR_NB) * QR_NB)
                  : mk<T>(0, 0));
   }
@@ -897,7 +897,7 @@ __global__ __launch_bounds__(WY_NT) void wy_merge_kernel(DS descs) {
         for (int u = 0; u < WY_U; ++u) {
           const int q = min(q0 + u, c);
           sv[u] = ldc(d.S + r + (int64_t)(c0 + q) * d.lds);
-          tv[u] = ldc(To + (c0 + q) + (int64_t)(c0 + c) * kb);
+          tv[u] = ldc(To + (c0 + q) + (int64_t)(c0 + c) * ldt);
         }
 #pragma unroll
         for (int u = 0; u < WY_U; ++u)
@@ -912,12 +912,12 @@ __global__ __launch_bounds__(WY_NT) void wy_merge_kernel(DS descs) {
       for (int q0 = r; q0 < c0; q0 += WY_U) {   // T(0:c0, 0:c0) upper triangular
         C2 tv[WY_U];
 #pragma unroll
-        for (int u = 0; u < WY_U; ++u) tv[u] = ldc(To + r + (int64_t)min(q0 + u, c0 - 1) * kb);
+        for (int u = 0; u < WY_U; ++u) tv[u] = ldc(To + r + (int64_t)min(q0 + u, c0 - 1) * ldt);
 #pragma unroll
         for (int u = 0; u < WY_U; ++u)
           if (q0 + u < c0) sum = cadd(sum, cmul(tv[u], X[q0 + u][c]));
       }
-      stc(To + r + (int64_t)(c0 + c) * kb, mk<T>(-sum.x, -sum.y));
+      stc(To + r + (int64_t)(c0 + c) * ldt, mk<T>(-sum.x, -sum.y));
     }
     __syncthreads();
   }
@@ -1389,7 +1389,11 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     if (force > 0) {
       splits = std::max(1, std::min({force, std::max(1, ceil_div(maxk, GK)), 4096}));
     } else if (wgs < 1024 && maxk >= 512) {
-      splits = (int)std::min<int64_t>((maxk + 255) / 256, (2048 + wgs - 1) / wgs);
+      // about 2048 workgroups, each with a k range of at least ~1024 (short
+      // ranges spend their time in the prologue, epilogue and atomics); up to
+      // four splits of 256 or more for shorter k
+      const int64_t by_k = std::max<int64_t>(maxk / 1024, std::min<int64_t>(maxk / 256, 4));
+      splits = (int)std::min<int64_t>(by_k, (2048 + wgs - 1) / wgs);
       splits = std::max(1, std::min(splits, 64));
     }
     int64_t mx = 0;
@@ -1523,55 +1527,110 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& din, void* ws) 
   std::vector<int> act;
   std::vector<GemmDesc<T>> g1, g2, g3;
   std::vector<WyDesc<T>> wy;
+  std::vector<FillDesc<T>> fz;
+  // Blocks of QR_OB columns, each made of two halves of QR_HB: the panels of a
+  // half update the half's later columns; the left half's reflectors then
+  // update the right half; the block's T joins the halves' factors; the
+  // columns beyond the block get one update with the block's reflectors.
   for (int J0 = 0; J0 < kmax; J0 += QR_OB) {
-    // panels of this block, each updating the block's later columns
-    for (int j0 = J0; j0 < std::min(J0 + QR_OB, kmax); j0 += QR_NB) {
-      act.clear();
+    const int bidx = J0 / QR_OB;
+    for (int H0 = J0; H0 < std::min(J0 + QR_OB, kmax); H0 += QR_HB) {
+      for (int j0 = H0; j0 < std::min(H0 + QR_HB, kmax); j0 += QR_NB) {
+        act.clear();
+        g1.clear(); g2.clear(); g3.clear();
+        for (int i = 0; i < nb; ++i) {
+          const QRDesc<T>& q = d[i];
+          int kmin = qr_kmin(q.m, q.n);
+          if (kmin <= j0) continue;
+          act.push_back(i);
+          int jb = std::min(QR_NB, kmin - j0);
+          int nt = std::min(q.n, H0 + QR_HB) - j0 - jb;
+          if (nt <= 0) continue;
+          int mr = q.m - j0;
+          cplx<T>* V = q.A + j0 + (int64_t)j0 * q.lda;
+          cplx<T>* At = q.A + j0 + (int64_t)(j0 + jb) * q.lda;
+          cplx<T>* Tj = q.Tw + (int64_t)((j0 % QR_OB) / QR_NB) * QR_NB * QR_NB;
+          g1.push_back({jb, nt, mr, q.lda, q.lda, QR_NB, V, At, W[i], T(1), T(0), T(0)});
+          g2.push_back({jb, nt, jb, QR_NB, QR_NB, QR_NB, Tj, W[i], W2[i], T(1), T(0), T(0)});
+          g3.push_back({mr, nt, jb, q.lda, QR_NB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
+        }
+        int maxmr = 0;
+        for (int i : act) maxmr = std::max(maxmr, d[i].m - j0);
+        qr_panel_launch<T>(pool, dd, act, j0, maxmr);
+        gemm_batched<T>(pool, g1, OpC, OpN);
+        gemm_batched<T>(pool, g2, OpC, OpN);
+        gemm_batched<T>(pool, g3, OpN, OpN);
+      }
+      // the half's factor T_h (in its place inside the block's T) from the
+      // panels' factors and S = V_h^H V_h
+      g1.clear();
+      wy.clear();
+      for (int i = 0; i < nb; ++i) {
+        const QRDesc<T>& q = d[i];
+        int kmin = qr_kmin(q.m, q.n);
+        if (kmin <= H0) continue;
+        const int kB = std::min(QR_OB, kmin - J0), kh = std::min(QR_HB, kmin - H0);
+        cplx<T>* V = q.A + H0 + (int64_t)H0 * q.lda;
+        cplx<T>* Tout =
+            q.Tb + (int64_t)QR_OB * QR_OB * bidx + (H0 - J0) + (int64_t)(H0 - J0) * kB;
+        if (kh > QR_NB)
+          g1.push_back({kh, kh, q.m - H0, q.lda, q.lda, QR_OB, V, V, S[i], T(1), T(0), T(0)});
+        wy.push_back({kh, QR_OB, kB, q.Tw + (int64_t)((H0 - J0) / QR_NB) * QR_NB * QR_NB, S[i],
+                      Tout});
+      }
+      gemm_batched<T>(pool, g1, OpC, OpN);
+      if (!wy.empty()) {
+        with_descs(pool, wy.data(), wy.size(), [&](auto dw) {
+          hipLaunchKernelGGL((wy_merge_kernel<T, decltype(dw)>), dim3((unsigned)wy.size()),
+                             dim3(WY_NT), 0, pool.stream, dw);
+        });
+        ND_HIP(hipGetLastError());
+      }
+      if (H0 != J0) continue;
+      // the left half's reflectors on the right half's columns
       g1.clear(); g2.clear(); g3.clear();
       for (int i = 0; i < nb; ++i) {
         const QRDesc<T>& q = d[i];
         int kmin = qr_kmin(q.m, q.n);
-        if (kmin <= j0) continue;
-        act.push_back(i);
-        int jb = std::min(QR_NB, kmin - j0);
-        int nt = std::min(q.n, J0 + QR_OB) - j0 - jb;
+        if (kmin <= H0) continue;
+        const int kB = std::min(QR_OB, kmin - J0), kh = std::min(QR_HB, kmin - H0);
+        const int nt = std::min(q.n, J0 + QR_OB) - (H0 + QR_HB);
         if (nt <= 0) continue;
-        int mr = q.m - j0;
-        cplx<T>* V = q.A + j0 + (int64_t)j0 * q.lda;
-        cplx<T>* At = q.A + j0 + (int64_t)(j0 + jb) * q.lda;
-        cplx<T>* Tj = q.Tw + (int64_t)((j0 % QR_OB) / QR_NB) * QR_NB * QR_NB;
-        g1.push_back({jb, nt, mr, q.lda, q.lda, QR_NB, V, At, W[i], T(1), T(0), T(0)});
-        g2.push_back({jb, nt, jb, QR_NB, QR_NB, QR_NB, Tj, W[i], W2[i], T(1), T(0), T(0)});
-        g3.push_back({mr, nt, jb, q.lda, QR_NB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
+        const int mr = q.m - H0;
+        cplx<T>* V = q.A + H0 + (int64_t)H0 * q.lda;
+        cplx<T>* At = q.A + H0 + (int64_t)(H0 + QR_HB) * q.lda;
+        const cplx<T>* Th = q.Tb + (int64_t)QR_OB * QR_OB * bidx;
+        g1.push_back({kh, nt, mr, q.lda, q.lda, QR_OB, V, At, W[i], T(1), T(0), T(0)});
+        g2.push_back({kh, nt, kh, kB, QR_OB, QR_OB, Th, W[i], W2[i], T(1), T(0), T(0)});
+        g3.push_back({mr, nt, kh, q.lda, QR_OB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
       }
-      int maxmr = 0;
-      for (int i : act) maxmr = std::max(maxmr, d[i].m - j0);
-      qr_panel_launch<T>(pool, dd, act, j0, maxmr);
       gemm_batched<T>(pool, g1, OpC, OpN);
       gemm_batched<T>(pool, g2, OpC, OpN);
       gemm_batched<T>(pool, g3, OpN, OpN);
     }
-    // block factor T_b from the panels' factors and S = V_b^H V_b
-    g1.clear();
-    wy.clear();
+    // blocks with two halves: T = [T_L, -T_L (V_L^H V_R) T_R; 0, T_R] (V_R is
+    // zero above its first row, so V_L^H V_R runs over the rows from there)
+    g1.clear(); g2.clear(); g3.clear();
+    fz.clear();
     for (int i = 0; i < nb; ++i) {
       const QRDesc<T>& q = d[i];
       int kmin = qr_kmin(q.m, q.n);
-      if (kmin <= J0) continue;
-      int kb = std::min(QR_OB, kmin - J0);
-      cplx<T>* V = q.A + J0 + (int64_t)J0 * q.lda;
-      if (kb > QR_NB)
-        g1.push_back({kb, kb, q.m - J0, q.lda, q.lda, QR_OB, V, V, S[i], T(1), T(0), T(0)});
-      wy.push_back({kb, QR_OB, q.Tw, S[i], q.Tb + (int64_t)QR_OB * QR_OB * (J0 / QR_OB)});
+      if (kmin <= J0 + QR_HB) continue;
+      const int kB = std::min(QR_OB, kmin - J0), kr = kB - QR_HB;
+      const int h1 = J0 + QR_HB;
+      cplx<T>* Tb = q.Tb + (int64_t)QR_OB * QR_OB * bidx;
+      g1.push_back({QR_HB, kr, q.m - h1, q.lda, q.lda, QR_OB, q.A + h1 + (int64_t)J0 * q.lda,
+                    q.A + h1 + (int64_t)h1 * q.lda, S[i], T(1), T(0), T(0)});
+      g2.push_back({QR_HB, kr, kr, QR_OB, kB, QR_OB, S[i], Tb + QR_HB + (int64_t)QR_HB * kB, W[i],
+                    T(1), T(0), T(0)});
+      g3.push_back({QR_HB, kr, QR_HB, kB, QR_OB, kB, Tb, W[i], Tb + (int64_t)QR_HB * kB, T(-1),
+                    T(0), T(0)});
+      fz.push_back({kr, QR_HB, kB, Tb + QR_HB, 0});
     }
     gemm_batched<T>(pool, g1, OpC, OpN);
-    if (!wy.empty()) {
-      with_descs(pool, wy.data(), wy.size(), [&](auto dw) {
-        hipLaunchKernelGGL((wy_merge_kernel<T, decltype(dw)>), dim3((unsigned)wy.size()),
-                           dim3(WY_NT), 0, pool.stream, dw);
-      });
-      ND_HIP(hipGetLastError());
-    }
+    gemm_batched<T>(pool, g2, OpN, OpN);
+    gemm_batched<T>(pool, g3, OpN, OpN);
+    fill_batched<T>(pool, fz);
     // trailing columns beyond the block: one update with the block's reflectors
     g1.clear(); g2.clear(); g3.clear();
     for (int i = 0; i < nb; ++i) {
@@ -1584,7 +1643,7 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& din, void* ws) 
       int mr = q.m - J0;
       cplx<T>* V = q.A + J0 + (int64_t)J0 * q.lda;
       cplx<T>* At = q.A + J0 + (int64_t)(J0 + QR_OB) * q.lda;
-      const cplx<T>* Tb = q.Tb + (int64_t)QR_OB * QR_OB * (J0 / QR_OB);
+      const cplx<T>* Tb = q.Tb + (int64_t)QR_OB * QR_OB * bidx;
       g1.push_back({kb, nt, mr, q.lda, q.lda, QR_OB, V, At, W[i], T(1), T(0), T(0)});
       g2.push_back({kb, nt, kb, kb, QR_OB, QR_OB, Tb, W[i], W2[i], T(1), T(0), T(0)});
       g3.push_back({mr, nt, kb, q.lda, QR_OB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});

@@ -15,6 +15,7 @@ lib = _lib.lib
 DEV = torch.device("cuda", 0)
 CT = {0: (np.complex128, torch.complex128), 1: (np.complex64, torch.complex64)}
 TOL = {0: 1e-12, 1: 2e-5}
+QB = 256   # reflectors per compact-WY block of the QR factors (T layout)
 
 
 def crandn(rng, *shape):
@@ -111,15 +112,19 @@ def test_gemm_skinny(prec, opa, beta):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_geqrf_ormqr(prec):
     rng = np.random.default_rng(3 + prec)
+    # around the 256-column blocks and their 128-column halves: a block with
+    # one reflector in its right half, exactly one block, a last block of one
+    # half, several blocks with partial halves, wide problems
     shapes = [(100, 37), (37, 100), (64, 64), (5, 3), (1030, 546), (33, 1), (300, 97),
-              (3000, 70), (257, 300), (700, 129), (400, 256), (130, 700)]
+              (3000, 70), (257, 300), (700, 129), (400, 256), (130, 700), (2000, 600),
+              (600, 384), (1000, 513)]
     keep = []
     mn, ld, ptr, data = [], [], [], []
     for (m, n) in shapes:
         A = crandn(rng, m, n)
         k = min(m, n)
-        nob = (k + 127) // 128
-        tsize = 128 * 128 * (nob - 1) + (k - 128 * (nob - 1)) ** 2
+        nob = (k + QB - 1) // QB
+        tsize = QB * QB * (nob - 1) + (k - QB * (nob - 1)) ** 2
         tA = to_dev(A, prec)
         # R starts as garbage: the factorization must write all of it
         tR = torch.full((n, k), 7.0 - 3.0j, dtype=CT[prec][1], device=DEV)   # k x n col-major
@@ -410,8 +415,8 @@ def test_geqrf_tall_panels(prec):
     for (m, n) in shapes:
         A = crandn(rng, m, n)
         k = min(m, n)
-        nob = (k + 127) // 128
-        tsize = 128 * 128 * (nob - 1) + (k - 128 * (nob - 1)) ** 2
+        nob = (k + QB - 1) // QB
+        tsize = QB * QB * (nob - 1) + (k - QB * (nob - 1)) ** 2
         tA = to_dev(A, prec)
         tR = torch.full((n, k), 7.0 - 3.0j, dtype=CT[prec][1], device=DEV)
         tT = torch.full((tsize,), 5.0 + 1.0j, dtype=CT[prec][1], device=DEV)
