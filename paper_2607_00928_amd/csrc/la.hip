@@ -443,23 +443,31 @@ __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(DS descs, int splits
 
 // Small products with a long k: C (m x n, m, n <= 16 MB, 16 NB) += alpha
 // A^H B (the Grams of tall panels).  Memory-bound on A and B: workgroup x
-// takes SG_KC rows of k, each wave a contiguous 16 U row slice per step of
-// its loop, on 16x16x4 matrix-core steps (Gauss products, as in gemm_kernel).
+// takes kc rows of k (chosen per launch for about 2048 workgroups), each wave
+// a contiguous 16 U row slice per step of its loop, on 16x16x4 matrix-core
+// steps (Gauss products, as in gemm_kernel).
 // When A and B are the same matrix, one load feeds both operands (lane l
 // supplies A(k, l % 16) for op(A) and B(k, l % 16) for B).  The four waves'
 // sums meet in LDS and are added atomically to a pre-scaled C.
-constexpr int SG_KC = 4096;
+constexpr int SG_KMIN = 4096;   // k from which these kernels are used
 constexpr int SG_U = 2;
+// rows of k per workgroup: about 2048 workgroups over the batch, at least 256 rows
+inline int small_out_kc(int maxk, size_t nd) {
+  const int64_t want = std::max<int64_t>(1, (2048 + (int64_t)nd - 1) / (int64_t)nd);
+  const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(want, maxk / 256));
+  const int64_t kc = (maxk + chunks - 1) / chunks;
+  return (int)((kc + 127) / 128 * 128);
+}
 
 template <typename T, int MB, int NB, class DS>
-__global__ __launch_bounds__(256) void gemm_smallmn_kernel(DS descs) {
+__global__ __launch_bounds__(256) void gemm_smallmn_kernel(DS descs, int kc) {
   using C2 = cplx<T>;
   using A4 = typename acc4<T>::type;
   __shared__ C2 red[16 * MB][16 * NB];
   const GemmDesc<T> d = descs[blockIdx.y];
-  const int kb = (int)blockIdx.x * SG_KC;
+  const int kb = (int)blockIdx.x * kc;
   if (d.m <= 0 || d.n <= 0 || kb >= d.k) return;
-  const int ke = min(d.k, kb + SG_KC);
+  const int ke = min(d.k, kb + kc);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, q = lane >> 4;
   const bool same = d.A == d.B && d.lda == d.ldb && d.m == d.n;
@@ -536,6 +544,75 @@ __global__ __launch_bounds__(256) void gemm_smallmn_kernel(DS descs) {
     atomic_addg(&p->x, d.ar * v.x - d.ai * v.y);
     atomic_addg(&p->y, d.ar * v.y + d.ai * v.x);
   }
+}
+
+// The same products with m <= 32 and 32 < n <= 128 (a panel's reflectors
+// against the columns they update): wave w owns output columns 32 w .. 32 w +
+// 31 and walks the workgroup's whole k range (kc rows), adding its part of
+// C atomically; the 32 x 128 output needs no cross-wave reduction.
+
+template <typename T, class DS>
+__global__ __launch_bounds__(256, 2) void gemm_smallm_wide_kernel(DS descs, int kc) {
+  using C2 = cplx<T>;
+  using A4 = typename acc4<T>::type;
+  const GemmDesc<T> d = descs[blockIdx.y];
+  const int kb = (int)blockIdx.x * kc;
+  if (d.m <= 0 || d.n <= 0 || kb >= d.k) return;
+  const int ke = min(d.k, kb + kc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int cb = 32 * wave;
+  if (cb >= d.n) return;   // no workgroup barrier below
+  A4 acc[2][2][3];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[a][b][t] = A4{0, 0, 0, 0};
+  const bool arow0 = r < d.m, arow1 = 16 + r < d.m;
+  const bool bcol0 = cb + r < d.n, bcol1 = cb + 16 + r < d.n;
+  constexpr int S = sizeof(T) == 8 ? 4 : 4 * SG_U;   // matrix-core steps per load batch
+  for (int base = kb; base < ke; base += 4 * S) {
+    C2 av[S][2], bv[S][2];
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      const int kk = base + 4 * st + q;
+      const bool ok = kk < ke;
+      av[st][0] = ok && arow0 ? ldc(d.A + kk + (int64_t)r * d.lda) : mk<T>(0, 0);
+      av[st][1] = ok && arow1 ? ldc(d.A + kk + (int64_t)(16 + r) * d.lda) : mk<T>(0, 0);
+      bv[st][0] = ok && bcol0 ? ldc(d.B + kk + (int64_t)(cb + r) * d.ldb) : mk<T>(0, 0);
+      bv[st][1] = ok && bcol1 ? ldc(d.B + kk + (int64_t)(cb + 16 + r) * d.ldb) : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int st = 0; st < S; ++st)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        // op(A) = A^H: real part A.x, imaginary part -A.y
+        const T ar = av[st][a].x, ai = -av[st][a].y, as = ar + ai;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const T br = bv[st][b].x, bi = bv[st][b].y;
+          acc[a][b][0] = mfma16(ar, br, acc[a][b][0]);
+          acc[a][b][1] = mfma16(ai, bi, acc[a][b][1]);
+          acc[a][b][2] = mfma16(as, br + bi, acc[a][b][2]);
+        }
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * a + mrow<T>(lane, v), j = cb + 16 * b + r;
+        if (i >= d.m || j >= d.n) continue;
+        const T p1 = acc[a][b][0][v], p2 = acc[a][b][1][v];
+        const T vr = p1 - p2, vi = acc[a][b][2][v] - p1 - p2;
+        C2* p = d.C + i + (int64_t)j * d.ldc;
+        atomic_addg(&p->x, d.ar * vr - d.ai * vi);
+        atomic_addg(&p->y, d.ar * vi + d.ai * vr);
+      }
 }
 
 // C <- beta C for split-k launches (beta 0 writes zeros)
@@ -1322,15 +1399,43 @@ static void smallmn_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub,
                          pool.stream, dd);
     ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn,
                  maxk, 2000 + 10 * mb + nb);
-    dim3 grid((unsigned)((maxk + SG_KC - 1) / SG_KC), (unsigned)n);
+    const int kc = small_out_kc(maxk, n);
+    dim3 grid((unsigned)((maxk + kc - 1) / kc), (unsigned)n);
     if (mb == 1 && nb == 1)
-      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 1, DS>), grid, dim3(256), 0, pool.stream, dd);
+      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 1, DS>), grid, dim3(256), 0, pool.stream, dd,
+                         kc);
     else if (mb == 1)
-      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 2, DS>), grid, dim3(256), 0, pool.stream, dd);
+      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 2, DS>), grid, dim3(256), 0, pool.stream, dd,
+                         kc);
     else if (nb == 1)
-      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 1, DS>), grid, dim3(256), 0, pool.stream, dd);
+      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 1, DS>), grid, dim3(256), 0, pool.stream, dd,
+                         kc);
     else
-      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 2, DS>), grid, dim3(256), 0, pool.stream, dd);
+      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 2, DS>), grid, dim3(256), 0, pool.stream, dd,
+                         kc);
+  });
+  ND_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void smallm_wide_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, int maxm,
+                                int maxn, int maxk) {
+  const size_t n = sub.size();
+  bool scale = false;
+  for (auto& g : sub) scale = scale || (g.m > 0 && g.n > 0 && g.beta != T(1));
+  double fl = 0;
+  for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
+  with_descs(pool, sub.data(), n, [&](auto dd) {
+    using DS = decltype(dd);
+    if (scale)
+      hipLaunchKernelGGL((gemm_prescale_kernel<T, DS>), dim3(4, (unsigned)n), dim3(256), 0,
+                         pool.stream, dd);
+    ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn,
+                 maxk, 3000);
+    const int kc = small_out_kc(maxk, n);
+    hipLaunchKernelGGL((gemm_smallm_wide_kernel<T, DS>),
+                       dim3((unsigned)((maxk + kc - 1) / kc), (unsigned)n), dim3(256), 0,
+                       pool.stream, dd, kc);
   });
   ND_HIP(hipGetLastError());
 }
@@ -1373,9 +1478,14 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
         : splits_force == -1 ? 1
         : splits_force == -2 ? 0
                              : tuned_splits<T>(opA, opB, maxm, maxn, maxk, (int)n);
+    if ((splits_force == 0 || splits_force == -2) && opA == OpC && opB == OpN && maxm <= 32 &&
+        maxn > 32 && maxn <= 128 && maxk >= SG_KMIN) {
+      smallm_wide_batched<T>(pool, sub, maxm, maxn, maxk);
+      continue;
+    }
     if ((splits_force == 0 || splits_force == -2) && opA == OpC && opB == OpN && maxn > SK_N &&
         maxm <= 32 &&
-        maxn <= 32 && maxk >= 2 * SG_KC) {
+        maxn <= 32 && maxk >= SG_KMIN) {
       smallmn_batched<T>(pool, sub, maxm, maxn, maxk);
       continue;
     }

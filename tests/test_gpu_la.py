@@ -489,3 +489,87 @@ def test_gemm_split_k_few_tiles(opa, opb, beta):
         got = from_dev(tc, m, n)
         scale = max(1.0, np.abs(ref).max())
         assert np.abs(got - ref).max() < TOL[1] * scale * k ** 0.5 * 10, (m, n, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0)])
+def test_gemm_long_descriptor_list(prec, opa, opb):
+    """100 ragged products in one launch: a descriptor list longer than fits in
+    the kernel arguments (read from device memory), with a skinny and a
+    small-output batch of the same length (beta = 1, alpha complex)."""
+    rng = np.random.default_rng(120 + 10 * prec + 2 * opa + opb)
+    batches = [[(int(rng.integers(1, 200)), int(rng.integers(9, 150)), int(rng.integers(0, 300)))
+                for _ in range(100)],
+               [(int(rng.integers(1, 400)), int(rng.integers(1, 9)), int(rng.integers(1, 500)))
+                for _ in range(100)]]
+    if opa == 1:
+        batches.append([(int(rng.integers(9, 33)), int(rng.integers(9, 33)),
+                         int(rng.integers(8200, 9000))) for _ in range(100)])
+    alpha = 0.25 + 0.7j
+    for shapes in batches:
+        mats, keep = [], []
+        mnk, ld, ptr = [], [], []
+        for (m, n, k) in shapes:
+            A = crandn(rng, *((m, k) if opa == 0 else (k, m)))
+            B = crandn(rng, *((k, n) if opb == 0 else (n, k)))
+            Cm = crandn(rng, m, n)
+            ta, tb, tc = to_dev(A, prec), to_dev(B, prec), to_dev(Cm, prec)
+            keep += [ta, tb, tc]
+            mats.append((A, B, Cm, tc))
+            mnk += [m, n, k]
+            ld += [max(A.shape[0], 1), max(B.shape[0], 1), m]
+            ptr += [ta.data_ptr(), tb.data_ptr(), tc.data_ptr()]
+        a1, p1 = i32(mnk)
+        a2, p2 = i32(ld)
+        a3, p3 = i64(ptr)
+        st = lib.nudft2_test_gemm(prec, opa, opb, len(shapes), p1, p2, p3, alpha.real, alpha.imag,
+                                  1.0)
+        assert st == 0, lib.nudft2_last_error()
+        for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+            oA = A if opa == 0 else A.conj().T
+            oB = B if opb == 0 else B.conj().T
+            ref = alpha * (oA @ oB) + Cm
+            got = from_dev(tc, m, n)
+            scale = max(1.0, np.abs(ref).max())
+            assert np.abs(got - ref).max() < TOL[prec] * scale * max(1, k) ** 0.5 * 10, (m, n, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_gemm_small_m_wide_long_k(prec, beta):
+    """A^H B with m <= 32, 32 < n <= 128 and a long k (a panel's reflectors
+    against the columns they update): each wave of the kernel owns 32 output
+    columns.  Ragged m, n (one wave partly or not at all used), k not a
+    multiple of the per-workgroup range, an empty k in the batch."""
+    rng = np.random.default_rng(140 + 3 * prec + int(2 * beta))
+    npt, _ = CT[prec]
+    u = np.finfo(npt).eps / 2
+    shapes = [(32, 96, 9000), (20, 128, 5000), (32, 33, 4100), (5, 100, 6000), (32, 64, 4096),
+              (17, 40, 0), (1, 127, 4500)]
+    mats, keep = [], []
+    mnk, ld, ptr = [], [], []
+    alpha = -0.6 + 0.55j
+    for (m, n, k) in shapes:
+        A = crandn(rng, k, m)
+        B = crandn(rng, k, n)
+        Cm = crandn(rng, m, n)
+        ta, tb, tc = to_dev(A, prec), to_dev(B, prec), to_dev(Cm, prec)
+        keep += [ta, tb, tc]
+        mats.append((A, B, Cm, tc))
+        mnk += [m, n, k]
+        ld += [max(k, 1), max(k, 1), m]
+        ptr += [ta.data_ptr(), tb.data_ptr(), tc.data_ptr()]
+    a1, p1 = i32(mnk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_gemm(prec, 1, 0, len(shapes), p1, p2, p3, alpha.real, alpha.imag, beta)
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+        Ac, Bc = A.astype(npt).astype(np.complex128), B.astype(npt).astype(np.complex128)
+        Cc = Cm.astype(npt).astype(np.complex128)
+        ref = alpha * (Ac.conj().T @ Bc) + beta * Cc
+        got = from_dev(tc, m, n)
+        na = np.linalg.norm(Ac, axis=0)
+        nb_ = np.linalg.norm(Bc, axis=0)
+        bound = 8 * u * max(1, k) ** 0.5 * np.outer(na, nb_) + 8 * u * np.abs(beta * Cc) + 1e-300
+        assert np.all(np.abs(got - ref) <= bound + 4 * u * np.abs(ref)), (m, n, k)
