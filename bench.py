@@ -104,24 +104,37 @@ def main():
         plan.close()
     torch.cuda.synchronize()
     recs = []
-    last_plan = None
     kms, kfl, kn = [0.0] * 4, [0.0] * 4, [0] * 4
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        if last_plan is not None:
-            last_plan.close()
-        plan, r = step("fp32", profile=True)
-        inf_k = plan.info()
+
+    def fold(pl):
+        # read back a plan's per-launch HIP events (recorded during its step)
+        inf_k = pl.info()
         for i in range(4):
             kms[i] += inf_k["kernel_ms"][i]
             kfl[i] += inf_k["kernel_flops"][i]
             kn[i] += inf_k["kernel_launches"][i]
+
+    # the steps' plans stay alive until the timed region ends, so reading back
+    # their events and freeing them happen outside it (at most two n512 plans,
+    # about 100 GB, are held; with more steps the oldest is folded and freed)
+    live = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        if len(live) == 2:
+            fold(live[0])
+            live.pop(0).close()
+        plan, r = step("fp32", profile=True)
         recs.append(r)
-        last_plan = plan
+        live.append(plan)
         log(f"step {k}: {r}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1e3 * elapsed / args.steps
+    for pl in live:
+        fold(pl)
+    for pl in live[:-1]:
+        pl.close()
+    last_plan = live[-1]
     info = last_plan.info()
     # kernel classes timed with HIP events on the plan's stream over the timed steps
     names = ["apply_fp64", "gemm_fp32_mfma", "gemm_fp64_mfma", "qr_panel"]
