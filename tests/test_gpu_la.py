@@ -573,3 +573,41 @@ def test_gemm_small_m_wide_long_k(prec, beta):
         nb_ = np.linalg.norm(Bc, axis=0)
         bound = 8 * u * max(1, k) ** 0.5 * np.outer(na, nb_) + 8 * u * np.abs(beta * Cc) + 1e-300
         assert np.all(np.abs(got - ref) <= bound + 4 * u * np.abs(ref)), (m, n, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1)])
+def test_gemm_few_row_tiles(prec, opa, opb):
+    """Products with at most 256 rows and many column tiles (the shape of the
+    V^H C products of the blocked QR): ragged m around the 64-row tiles, n not
+    a multiple of 64, one launch with the k loop split and one without,
+    beta = 1, alpha complex."""
+    rng = np.random.default_rng(160 + 10 * prec + 2 * opa + opb)
+    alpha = 0.45 - 0.85j
+    for shapes in ([(256, 2000, 700), (200, 1500, 300), (129, 2100, 64), (64, 4096, 33)],
+                   [(250, 3000, 150)] * 6):
+        mats, keep = [], []
+        mnk, ld, ptr = [], [], []
+        for (m, n, k) in shapes:
+            A = crandn(rng, *((m, k) if opa == 0 else (k, m)))
+            B = crandn(rng, *((k, n) if opb == 0 else (n, k)))
+            Cm = crandn(rng, m, n)
+            ta, tb, tc = to_dev(A, prec), to_dev(B, prec), to_dev(Cm, prec)
+            keep += [ta, tb, tc]
+            mats.append((A, B, Cm, tc))
+            mnk += [m, n, k]
+            ld += [A.shape[0], B.shape[0], m]
+            ptr += [ta.data_ptr(), tb.data_ptr(), tc.data_ptr()]
+        a1, p1 = i32(mnk)
+        a2, p2 = i32(ld)
+        a3, p3 = i64(ptr)
+        st = lib.nudft2_test_gemm(prec, opa, opb, len(shapes), p1, p2, p3, alpha.real, alpha.imag,
+                                  1.0)
+        assert st == 0, lib.nudft2_last_error()
+        for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+            oA = A if opa == 0 else A.conj().T
+            oB = B if opb == 0 else B.conj().T
+            ref = alpha * (oA @ oB) + Cm
+            got = from_dev(tc, m, n)
+            scale = max(1.0, np.abs(ref).max())
+            assert np.abs(got - ref).max() < TOL[prec] * scale * k ** 0.5 * 10, (m, n, k)
