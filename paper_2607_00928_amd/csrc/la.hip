@@ -685,6 +685,40 @@ __device__ inline cplx<T> ld_agent(const cplx<T>* p) {
                __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
+// FP32 exchange words: a float and the column step's tag in one 64-bit
+// agent-scope atomic word, so a reader that sees the tag sees the value (no
+// fence, no separate counter).
+__device__ inline void st_tagged(unsigned long long* p, float v, unsigned tag) {
+  const unsigned long long w = (unsigned long long)__float_as_uint(v) |
+                               ((unsigned long long)tag << 32);
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long ld_tagged(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// wait until the two words at p carry tag (bounded; sets err on timeout and
+// gives up at once when err is already set) and return their values
+__device__ inline float2 wait_tagged2(const unsigned long long* p, unsigned tag, int* err) {
+  unsigned long long a = ld_tagged(p), b = ld_tagged(p + 1);
+  unsigned it = 0;
+  while ((unsigned)(a >> 32) != tag || (unsigned)(b >> 32) != tag) {
+    if ((++it & 255) == 0 &&
+        (it > (1u << 20) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+      atomicExch(err, 1);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    a = ld_tagged(p);
+    b = ld_tagged(p + 1);
+  }
+  return make_float2(__uint_as_float((unsigned)a), __uint_as_float((unsigned)b));
+}
+// FP32 group scratch: two sets (by column-step parity) of gsize partial-sum
+// rows and one pivot row, each QR_NB complex values as tagged word pairs
+__host__ __device__ inline size_t qp_tag_words(int gsize) {
+  return (size_t)2 * (gsize + 1) * QR_NB * 2;
+}
+
 constexpr int QS = QR_NB + 1;          // rotating sum slots per column
 constexpr int QSCR = 3 * QS + 3 * QR_NB;   // rotating sums + rotating row copies
 constexpr int QP_NT = 1024;            // threads of a panel workgroup
@@ -719,6 +753,7 @@ __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(
   __shared__ C2 tot[QR_NB];              // (gsize > 1) group column sums
   __shared__ C2 rowv[QR_NB];             // row jj
   __shared__ C2 Ts[QR_NB][QR_NB + 1];
+  __shared__ C2 red[QP_NT / QR_NB][QR_NB];   // (FP32, gsize > 1) partial sums of the group
   const int ngroups = gridDim.x / gsize;
   const int g = blockIdx.x / gsize, w = blockIdx.x % gsize;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -776,7 +811,52 @@ __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(
         for (int l = 0; l < QP_CG; ++l) rowv[c0 + l] = a[0][l];
       }
       __syncthreads();
-      if (gsize > 1) {
+      if constexpr (sizeof(T) == 4) {
+        if (gsize > 1) {
+          // publish this workgroup's sums (and, from workgroup 0, row jj) as
+          // tagged words; every workgroup reads all of them: thread (j, c)
+          // adds the partials of workgroups j, j + 32, ... for column c, then
+          // the 32 partials per column are added in a fixed order
+          unsigned long long* tg = (unsigned long long*)scratch + (size_t)g * qp_tag_words(gsize);
+          unsigned long long* part = tg + (size_t)(step & 1) * (gsize + 1) * QR_NB * 2;
+          unsigned long long* rowp = part + (size_t)gsize * QR_NB * 2;
+          const unsigned tag = (unsigned)step + 1;
+          if (tid < QR_NB) {
+            unsigned long long* q = part + ((size_t)w * QR_NB + tid) * 2;
+            st_tagged(q, sp[0][tid].x + sp[1][tid].x, tag);
+            st_tagged(q + 1, sp[0][tid].y + sp[1][tid].y, tag);
+          }
+          if (row_owner) {
+#pragma unroll
+            for (int l = 0; l < QP_CG; ++l) {
+              st_tagged(rowp + (c0 + l) * 2, (float)a[0][l].x, tag);
+              st_tagged(rowp + (c0 + l) * 2 + 1, (float)a[0][l].y, tag);
+            }
+          }
+          const int cj = tid % QR_NB, jj2 = tid / QR_NB;
+          float vr = 0.f, vi = 0.f;
+          for (int w2 = jj2; w2 < gsize; w2 += QP_NT / QR_NB) {
+            const float2 v = wait_tagged2(part + ((size_t)w2 * QR_NB + cj) * 2, tag, err);
+            vr += v.x;
+            vi += v.y;
+          }
+          red[jj2][cj] = mk<T>(vr, vi);
+          if (jj2 == 0) {
+            const float2 v = wait_tagged2(rowp + cj * 2, tag, err);
+            rowv[cj] = mk<T>(v.x, v.y);
+          }
+          __syncthreads();
+          if (tid < QR_NB) {
+            T tr = 0, ti = 0;
+            for (int j2 = 0; j2 < QP_NT / QR_NB; ++j2) {
+              tr += red[j2][tid].x;
+              ti += red[j2][tid].y;
+            }
+            tot[tid] = mk<T>(tr, ti);
+          }
+          __syncthreads();
+        }
+      } else if (gsize > 1) {
         C2* buf = sums + (step % 3) * QS;
         C2* rbuf = rows + (step % 3) * QR_NB;
         if (tid < QR_NB) {
@@ -1572,7 +1652,9 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const std::vector<int>
   int gsize = std::max(1, (maxmr + rows - 1) / rows);
   ND_CHECK(gsize <= mres, NUDFT2_E_INTERNAL, "QR panel taller than the device can hold");
   int ngroups = std::max(1, std::min(nact, mres / gsize));
-  const size_t scr_bytes = ((size_t)ngroups * QSCR * sizeof(cplx<T>) + 255) & ~size_t(255);
+  const size_t per_group = sizeof(T) == 4 ? qp_tag_words(gsize) * sizeof(unsigned long long)
+                                           : QSCR * sizeof(cplx<T>);
+  const size_t scr_bytes = ((size_t)ngroups * per_group + 255) & ~size_t(255);
   const size_t words = (scr_bytes + (size_t)ngroups * sizeof(unsigned)) / sizeof(unsigned);
   char* z = (char*)pool.reserve(words * sizeof(unsigned));
   cplx<T>* scr = (cplx<T>*)z;
