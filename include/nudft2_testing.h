@@ -87,6 +87,16 @@ nudft2_status nudft2_test_pchol(int32_t nb, const int32_t* w, const int32_t* rma
                                 int32_t* piv_out);
 nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims,
                                const int32_t* ld, const int64_t* ptrs, int32_t conj_trans);
+/* copy with precision change: D_i = S_i (conj_trans[i] = 0, D_i m x n) or
+ * D_i = S_i^H (conj_trans[i] != 0, D_i n x m), S_i m x n; prec_d / prec_s
+ * select complex128 (0) or complex64 (1) for D and S; dims = (m, n),
+ * ld = (lds, ldd), ptrs = (S, D); conj_trans is a HOST array of nb ints.
+ * Sources and destinations must not overlap.  NUDFT2_E_INVAL on a
+ * precision other than 0 / 1, negative sizes or leading dimensions too
+ * small for the stated shapes. */
+nudft2_status nudft2_test_copy(int32_t prec_d, int32_t prec_s, int32_t nb, const int32_t* dims,
+                               const int32_t* ld, const int64_t* ptrs,
+                               const int32_t* conj_trans);
 
 /* 1D HSS compression of G^x (dim 0) or G^y (dim 1) of every problem of the
  * plan at tolerance tol (no factorization needed), then y = H x for problem

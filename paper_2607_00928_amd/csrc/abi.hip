@@ -164,6 +164,20 @@ static void test_trsv(int nb, const int32_t* dims, const int32_t* ld, const int6
   pool.sync_reset();
 }
 
+template <typename TD, typename TS>
+static void test_copy(int nb, const int32_t* dims, const int32_t* ld, const int64_t* ptrs,
+                      const int32_t* ct) {
+  std::vector<CopyDesc<TD, TS>> d(nb);
+  for (int i = 0; i < nb; ++i)
+    d[i] = CopyDesc<TD, TS>{dims[2 * i], dims[2 * i + 1], ld[2 * i], ld[2 * i + 1],
+                            (const cplx<TS>*)ptrs[2 * i], (cplx<TD>*)ptrs[2 * i + 1],
+                            ct[i] != 0};
+  DescPool pool;
+  pool.init(1 << 20, nullptr);
+  copy_batched<TD, TS>(pool, d);
+  pool.sync_reset();
+}
+
 }  // namespace nd
 
 using namespace nd;
@@ -451,6 +465,26 @@ nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims, co
     need_device();
     if (prec == 0) test_trsv<double>(nb, dims, ld, ptrs, conj_trans != 0);
     else test_trsv<float>(nb, dims, ld, ptrs, conj_trans != 0);
+  });
+}
+
+nudft2_status nudft2_test_copy(int32_t prec_d, int32_t prec_s, int32_t nb, const int32_t* dims,
+                               const int32_t* ld, const int64_t* ptrs, const int32_t* conj_trans) {
+  return guard([&] {
+    ND_CHECK(dims && ld && ptrs && conj_trans && nb > 0, NUDFT2_E_INVAL, "bad arguments");
+    ND_CHECK((prec_d == 0 || prec_d == 1) && (prec_s == 0 || prec_s == 1), NUDFT2_E_INVAL,
+             "precision must be 0 (complex128) or 1 (complex64)");
+    for (int i = 0; i < nb; ++i) {
+      const int m = dims[2 * i], n = dims[2 * i + 1];
+      ND_CHECK(m >= 0 && n >= 0 && ld[2 * i] >= std::max(1, m) &&
+                   ld[2 * i + 1] >= std::max(1, conj_trans[i] ? n : m),
+               NUDFT2_E_INVAL, "bad copy dimensions");
+    }
+    need_device();
+    if (prec_d == 0 && prec_s == 0) test_copy<double, double>(nb, dims, ld, ptrs, conj_trans);
+    else if (prec_d == 0) test_copy<double, float>(nb, dims, ld, ptrs, conj_trans);
+    else if (prec_s == 0) test_copy<float, double>(nb, dims, ld, ptrs, conj_trans);
+    else test_copy<float, float>(nb, dims, ld, ptrs, conj_trans);
   });
 }
 

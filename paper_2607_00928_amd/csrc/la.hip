@@ -1376,6 +1376,34 @@ __global__ void copy_kernel(DS descs) {
   }
 }
 
+// D = S^H through 32 x 32 tiles staged in LDS, so that both the reads of S
+// and the writes of D run along columns (coalesced)
+template <typename TD, typename TS, class DS>
+__global__ __launch_bounds__(256) void copy_ct_kernel(DS descs) {
+  const CopyDesc<TD, TS> d = descs[blockIdx.y];
+  __shared__ cplx<TS> t[32][33];   // t[j][i] = S(i0 + i, j0 + j)
+  const int tm = (d.m + 31) / 32, tn = (d.n + 31) / 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int tile = blockIdx.x; tile < tm * tn; tile += gridDim.x) {
+    const int i0 = (tile % tm) * 32, j0 = (tile / tm) * 32;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + tx, j = j0 + ty + 8 * r;
+      if (i < d.m && j < d.n) t[ty + 8 * r][tx] = ldc(d.S + i + (int64_t)j * d.lds);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int jd = j0 + tx, id = i0 + ty + 8 * r;   // D(jd, id) = conj(S(id, jd))
+      if (id < d.m && jd < d.n) {
+        const cplx<TS> v = t[tx][ty + 8 * r];
+        stc(d.D + jd + (int64_t)id * d.ldd, mk<TD>((TD)v.x, -(TD)v.y));
+      }
+    }
+  }
+}
+
 template <typename T, class DS>
 __global__ void fill_kernel(DS descs) {
   const FillDesc<T> d = descs[blockIdx.y];
@@ -2045,6 +2073,14 @@ void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d, bool c
   }
 }
 
+// workgroups per descriptor of a copy launch: enough for the largest copy's
+// work items, with the whole grid held to about 64K workgroups when the batch
+// is long (the kernels loop over their items, so any count is correct)
+static unsigned copy_grid_x(int64_t items, size_t ndesc) {
+  const int64_t cap = std::max<int64_t>(8, 65536 / (int64_t)ndesc);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>({items, cap, 4096}));
+}
+
 template <typename TD, typename TS>
 void copy_batched(DescPool& pool, const std::vector<CopyDesc<TD, TS>>& d) {
   if (d.empty()) return;
@@ -2059,10 +2095,32 @@ void copy_batched(DescPool& pool, const std::vector<CopyDesc<TD, TS>>& d) {
     }
     check_hazards("copy", v);
   }
-  with_descs(pool, d.data(), d.size(), [&](auto dd) {
-    hipLaunchKernelGGL((copy_kernel<TD, TS, decltype(dd)>), dim3(64, (unsigned)d.size()),
-                       dim3(256), 0, pool.stream, dd);
-  });
+  // plain copies: a grid-stride loop sized by the largest copy; conjugate
+  // transposes: LDS tiles
+  std::vector<CopyDesc<TD, TS>> pl, ct;
+  int64_t maxcnt = 0, maxtiles = 0;
+  for (auto& q : d) {
+    if (q.m <= 0 || q.n <= 0) continue;
+    if (q.conj_trans) {
+      ct.push_back(q);
+      maxtiles = std::max<int64_t>(maxtiles, (int64_t)((q.m + 31) / 32) * ((q.n + 31) / 32));
+    } else {
+      pl.push_back(q);
+      maxcnt = std::max<int64_t>(maxcnt, (int64_t)q.m * q.n);
+    }
+  }
+  if (!pl.empty())
+    with_descs(pool, pl.data(), pl.size(), [&](auto dd) {
+      const unsigned gx = copy_grid_x((maxcnt + 2047) / 2048, pl.size());
+      hipLaunchKernelGGL((copy_kernel<TD, TS, decltype(dd)>), dim3(gx, (unsigned)pl.size()),
+                         dim3(256), 0, pool.stream, dd);
+    });
+  if (!ct.empty())
+    with_descs(pool, ct.data(), ct.size(), [&](auto dd) {
+      const unsigned gx = copy_grid_x(maxtiles, ct.size());
+      hipLaunchKernelGGL((copy_ct_kernel<TD, TS, decltype(dd)>), dim3(gx, (unsigned)ct.size()),
+                         dim3(256), 0, pool.stream, dd);
+    });
   ND_HIP(hipGetLastError());
 }
 

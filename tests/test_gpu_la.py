@@ -611,3 +611,44 @@ def test_gemm_few_row_tiles(prec, opa, opb):
             got = from_dev(tc, m, n)
             scale = max(1.0, np.abs(ref).max())
             assert np.abs(got - ref).max() < TOL[prec] * scale * k ** 0.5 * 10, (m, n, k)
+
+
+@pytest.mark.parametrize("pd,ps", [(0, 0), (1, 1), (1, 0), (0, 1)])
+def test_copy_conj_transpose(pd, ps):
+    """Batched copies with precision change, plain and conjugate-transposed in
+    one batch: ragged shapes that span several 32 x 32 tiles, one-row and
+    one-column blocks, an empty one, padded leading dimensions on both sides.
+    Bit-exact (a copy, conjugation and round-to-nearest conversion); the
+    padding rows of every destination keep their sentinel."""
+    rng = np.random.default_rng(70 + 2 * pd + ps)
+    npd, _ = CT[pd]
+    nps, _ = CT[ps]
+    shapes = [(1000, 700, 1), (700, 1000, 0), (33, 31, 1), (1, 257, 1), (257, 1, 1), (0, 5, 1),
+              (64, 64, 0), (95, 130, 1), (5, 3, 0), (2048, 40, 1)]
+    keep, cases, dims, ld, ptr, ctl = [], [], [], [], [], []
+    for (m, n, ct) in shapes:
+        S = crandn(rng, m, n).astype(nps)
+        lds = m + 3
+        Sp = np.zeros((lds, max(n, 1)), dtype=nps)
+        Sp[:m, :n] = S
+        dm, dn = (n, m) if ct else (m, n)
+        ldd = dm + 5
+        Dp = np.full((ldd, max(dn, 1)), 7.0 - 3.0j, dtype=npd)
+        tS = torch.from_numpy(np.ascontiguousarray(Sp.T)).to(DEV)
+        tD = torch.from_numpy(np.ascontiguousarray(Dp.T)).to(DEV)
+        keep += [tS, tD]
+        ref = Dp.copy()
+        ref[:dm, :dn] = (S.conj().T if ct else S).astype(npd)
+        cases.append((tD, ref, ldd, max(dn, 1)))
+        dims += [m, n]
+        ld += [lds, ldd]
+        ptr += [tS.data_ptr(), tD.data_ptr()]
+        ctl.append(ct)
+    a1, p1 = i32(dims)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    a4, p4 = i32(ctl)
+    assert lib.nudft2_test_copy(pd, ps, len(shapes), p1, p2, p3, p4) == 0
+    for tD, ref, ldd, dn in cases:
+        got = tD.cpu().numpy().reshape(dn, ldd).T
+        assert np.array_equal(got, ref)
