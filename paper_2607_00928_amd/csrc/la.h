@@ -61,12 +61,14 @@ struct GemmDesc {
 // the same output matrix (their tiles run concurrently).  A descriptor with
 // lower = 1 leaves the tiles strictly above the diagonal untouched (for
 // Hermitian products whose consumer reads the lower triangle only).
-// The k loop is split over workgroups (atomic accumulation into a pre-scaled
-// C) by the count the autotuned table gives for the launch's shape class
-// (gemm_tuning.inc, written by tune_gemm.py), else by a heuristic;
-// splits_force > 0 overrides both (used by the tuner); splits_force = -1
-// runs the tile kernel unsplit, without the table; splits_force = -2 takes
-// the heuristic without the table (the tuner's baseline).
+// Where the output tiles cannot fill the device, the k loop is shared out
+// over workgroups (atomic accumulation into a pre-scaled C): when the
+// autotuned table (gemm_tuning.inc, written by tune_gemm.py) or else a
+// heuristic calls for a split, the tiles x k stages go in equal stream-K
+// shares to the device's workgroup slots.  splits_force > 0 forces that many
+// plain k splits (used by the tuner); -1 runs the tile kernel unsplit,
+// without the table; -2 takes the heuristic without the table (the tuner's
+// baseline); -3 takes stream-K wherever it applies.
 template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB,
                   int splits_force = 0);

@@ -122,27 +122,20 @@ void with_descs(DescPool& pool, const D* v, size_t n, F&& launch) {
 constexpr int GT = 64;    // output tile
 constexpr int GK = 16;    // k per stage
 
-// splits > 1: blockIdx.z takes the k range [z kc, (z+1) kc) and the result is
-// added atomically (C must already hold beta C).  The next k stage is loaded
-// into registers while the current one is multiplied out of LDS (double
-// buffered, one barrier per stage).  LDS rows are padded to an odd multiple
+// The next k stage is loaded into registers while the current one is
+// multiplied out of LDS (double buffered, one barrier per stage).  LDS rows are padded to an odd multiple
 // of 16 banks, so the 16-lane groups of an operand read hit distinct banks.
-template <typename T, int OPA, int OPB, class DS>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS descs, int splits) {
+template <typename T> constexpr int gemm_ldt() { return GT + 64 / (int)sizeof(T); }
+
+// The output tile at (i0, j0) over the k range [kbeg, kend), stored (C =
+// alpha P + beta C) or, when `atomic`, added to C atomically.  Called
+// uniformly by the whole workgroup; leaves the LDS buffers free on return.
+template <typename T, int OPA, int OPB>
+__device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, int kbeg, int kend,
+                                          bool atomic, T (&As)[2][2][GK][gemm_ldt<T>()],
+                                          T (&Bs)[2][2][GK][gemm_ldt<T>()]) {
   using C2 = cplx<T>;
   using A4 = typename acc4<T>::type;
-  constexpr int LDT = GT + 64 / (int)sizeof(T);
-  __shared__ T As[2][2][GK][LDT];   // [buffer][re, im][k][row]
-  __shared__ T Bs[2][2][GK][LDT];
-  const GemmDesc<T> d = descs[blockIdx.y];
-  const int tm = (d.m + GT - 1) / GT, tn = (d.n + GT - 1) / GT;
-  if ((int)blockIdx.x >= tm * tn) return;
-  int kc = (((d.k + splits - 1) / splits) + GK - 1) / GK * GK;
-  const int kbeg = (int)blockIdx.z * kc;
-  const int kend = min(d.k, kbeg + kc);
-  if (kbeg >= kend && splits > 1) return;
-  const int i0 = (blockIdx.x % tm) * GT, j0 = (blockIdx.x / tm) * GT;
-  if (d.lower && j0 > i0 + GT - 1) return;   // strictly above the diagonal of a Hermitian C
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   // Gauss (3M) products: p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi);
@@ -246,7 +239,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS de
     // FP32 accumulators: a lane holds rows 4 (lane / 16) .. + 3 of one column,
     // 32 contiguous bytes of column-major C, read and written as two 16-byte
     // accesses (8-byte aligned: dword alignment is all the hardware needs)
-    if (splits == 1) {
+    if (!atomic) {
       typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -304,7 +297,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS de
           const T cr = p1 - p2, ci = acc3[a][b][v] - p1 - p2;
           C2 out = mk<T>(d.ar * cr - d.ai * ci, d.ar * ci + d.ai * cr);
           C2* p = d.C + (int64_t)i + (int64_t)j * d.ldc;
-          if (splits > 1) {
+          if (atomic) {
             atomic_addg(&p->x, out.x);
             atomic_addg(&p->y, out.y);
             continue;
@@ -317,6 +310,43 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS de
           stc(p, out);
         }
       }
+}
+
+// splits > 1: blockIdx.z takes the k range [z kc, (z+1) kc) and the result is
+// added atomically (C must already hold beta C).
+// sk > 0 (stream-K): the descriptor's tiles x k stages are dealt out in equal
+// contiguous shares to its sk workgroups (blockIdx.x); a share may end in
+// one tile and go on in the next, and every piece is added atomically to a
+// pre-scaled C.  Equal shares leave no partial last round of workgroups.
+template <typename T, int OPA, int OPB, class DS>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS descs, int splits,
+                                                                          int sk) {
+  __shared__ T As[2][2][GK][gemm_ldt<T>()];   // [buffer][re, im][k][row]
+  __shared__ T Bs[2][2][GK][gemm_ldt<T>()];
+  const GemmDesc<T> d = descs[blockIdx.y];
+  const int tm = (d.m + GT - 1) / GT, tn = (d.n + GT - 1) / GT;
+  if (sk > 0) {
+    const int nst = (d.k + GK - 1) / GK;
+    const int64_t units = (int64_t)tm * tn * nst;
+    int64_t u = units * blockIdx.x / sk;
+    const int64_t u1 = units * (blockIdx.x + 1) / sk;
+    while (u < u1) {
+      const int tile = (int)(u / nst), s0 = (int)(u % nst);
+      const int s1 = (int)min((int64_t)nst, s0 + (u1 - u));
+      gemm_tile<T, OPA, OPB>(d, (tile % tm) * GT, (tile / tm) * GT, s0 * GK, min(d.k, s1 * GK),
+                             true, As, Bs);
+      u += s1 - s0;
+    }
+    return;
+  }
+  if ((int)blockIdx.x >= tm * tn) return;
+  int kc = (((d.k + splits - 1) / splits) + GK - 1) / GK * GK;
+  const int kbeg = (int)blockIdx.z * kc;
+  const int kend = min(d.k, kbeg + kc);
+  if (kbeg >= kend && splits > 1) return;
+  const int i0 = (blockIdx.x % tm) * GT, j0 = (blockIdx.x / tm) * GT;
+  if (d.lower && j0 > i0 + GT - 1) return;   // strictly above the diagonal of a Hermitian C
+  gemm_tile<T, OPA, OPB>(d, i0, j0, kbeg, kend, splits > 1, As, Bs);
 }
 
 // Skinny products (n <= SK_N columns, B not transposed): memory-bound on A.
@@ -1548,6 +1578,21 @@ static void smallm_wide_batched(DescPool& pool, const std::vector<GemmDesc<T>>& 
   ND_HIP(hipGetLastError());
 }
 
+// stream-K for long-k products whose tiles and splits stay under two rounds
+// of workgroups
+constexpr bool kGemmStreamK = true;
+
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    ND_HIP(hipGetDevice(&dev));
+    ND_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    cus = std::max(cus, 1);
+  }
+  return cus;
+}
+
 template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB,
                   int splits_force) {
@@ -1584,14 +1629,15 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     const int force =
         splits_force > 0    ? splits_force
         : splits_force == -1 ? 1
-        : splits_force == -2 ? 0
+        : splits_force <= -2 ? 0
                              : tuned_splits<T>(opA, opB, maxm, maxn, maxk, (int)n);
-    if ((splits_force == 0 || splits_force == -2) && opA == OpC && opB == OpN && maxm <= 32 &&
+    const bool auto_route = splits_force == 0 || splits_force <= -2;
+    if (auto_route && opA == OpC && opB == OpN && maxm <= 32 &&
         maxn > 32 && maxn <= 128 && maxk >= SG_KMIN) {
       smallm_wide_batched<T>(pool, sub, maxm, maxn, maxk);
       continue;
     }
-    if ((splits_force == 0 || splits_force == -2) && opA == OpC && opB == OpN && maxn > SK_N &&
+    if (auto_route && opA == OpC && opB == OpN && maxn > SK_N &&
         maxm <= 32 &&
         maxn <= 32 && maxk >= SG_KMIN) {
       smallmn_batched<T>(pool, sub, maxm, maxn, maxk);
@@ -1601,22 +1647,54 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
       skinny_batched<T>(pool, sub, opA, maxm, maxn, maxk, force);
       continue;
     }
-    // split the k loop when the output tiles cannot fill the chip
-    int64_t wgs = (int64_t)maxt * (int64_t)n;
+    // Splitting the k loop.  The device holds `slots` tile workgroups at once.
+    // Long k (>= 4096) with at least 16 output tiles a product: about seven
+    // rounds of workgroups, each split at least 2048 long; where that still
+    // leaves under two rounds, stream-K instead.  Otherwise, under one round
+    // and k >= 1024: about two rounds, splits of ~1024 (up to four of 256 or
+    // more for shorter k).  k < 1024 is never split (the pre-scale and the
+    // atomics cost more than the extra workgroups give).  Measured on the
+    // factorization's shapes (FP32, TF/s): 256 x 13661 x 28495 8 splits 134
+    // (3: 123); 4 x 256 x 7319 x 10595 4 splits 131 (1: 115); 4 x 256 x 2147
+    // x 5704 stream-K 111 (best split 100); 128 x 128^2 x 593 unsplit 88 (2
+    // splits: 36).  Four-tile outputs with k of 8K-32K (tall-panel Grams) lose
+    // half their rate under stream-K, whose many short shares are bound by
+    // the atomics.
+    const int64_t wgs = (int64_t)maxt * (int64_t)n;
+    const int64_t slots = (int64_t)device_cus() * (sizeof(T) == 4 ? 4 : 2);
     int splits = 1;
+    bool want_sk = splits_force == -3;
     if (force > 0) {
       splits = std::max(1, std::min({force, std::max(1, ceil_div(maxk, GK)), 4096}));
-    } else if (wgs < 1024 && maxk >= 512) {
-      // about 2048 workgroups, each with a k range of at least ~1024 (short
-      // ranges spend their time in the prologue, epilogue and atomics); up to
-      // four splits of 256 or more for shorter k
+    } else if (maxk >= 4096 && maxt >= 16) {
+      splits = (int)std::max<int64_t>(1, std::min<int64_t>(7 * slots / wgs, maxk / 2048));
+      want_sk = want_sk || (kGemmStreamK && wgs * splits < 2 * slots);
+    } else if (wgs < slots && maxk >= 1024) {
       const int64_t by_k = std::max<int64_t>(maxk / 1024, std::min<int64_t>(maxk / 256, 4));
-      splits = (int)std::min<int64_t>(by_k, (2048 + wgs - 1) / wgs);
+      splits = (int)std::min<int64_t>(by_k, (2 * slots + wgs - 1) / wgs);
       splits = std::max(1, std::min(splits, 64));
+    }
+    // stream-K: each descriptor's tiles x k stages in equal shares over its
+    // part of the workgroup slots, at least 64 stages (k = 1024) a share (not
+    // for Hermitian-lower outputs; splits_force = -3 takes it wherever it
+    // applies)
+    int sk = 0;
+    bool lower = false;
+    for (auto& g : sub) lower = lower || g.lower;
+    if (want_sk && !lower && splits_force != -1 && splits_force <= 0) {
+      int64_t umax = 0;
+      for (auto& g : sub)
+        umax = std::max<int64_t>(umax, (int64_t)ceil_div(g.m, GT) * ceil_div(g.n, GT) *
+                                           ceil_div(g.k, GK));
+      const int64_t per = slots / (int64_t)n;
+      if (per >= 2 && umax >= 128) {
+        sk = (int)std::min<int64_t>(per, umax / 64);
+        splits = 1;
+      }
     }
     int64_t mx = 0;
     for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
-    dim3 grid(maxt, (unsigned)n, splits);
+    const dim3 grid = sk > 0 ? dim3((unsigned)sk, (unsigned)n, 1) : dim3(maxt, (unsigned)n, splits);
     double fl = 0;
     int mm = 0, mn = 0;
     for (auto& g : sub) {
@@ -1626,26 +1704,26 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     }
     with_descs(pool, sub.data(), n, [&](auto dd) {
       using DS = decltype(dd);
-      if (splits > 1)
+      if (splits > 1 || sk > 0)
         hipLaunchKernelGGL(
             (gemm_prescale_kernel<T, DS>),
             dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
                  (unsigned)n),
             dim3(256), 0, pool.stream, dd);
       ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, mm, mn, maxk,
-                   (int)opA * 2 + (int)opB + 10 * splits);
+                   (int)opA * 2 + (int)opB + 10 * (sk > 0 ? 99 : splits));
       if (opA == OpN && opB == OpN)
         hipLaunchKernelGGL((gemm_kernel<T, OpN, OpN, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits);
+                           splits, sk);
       else if (opA == OpC && opB == OpN)
         hipLaunchKernelGGL((gemm_kernel<T, OpC, OpN, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits);
+                           splits, sk);
       else if (opA == OpN && opB == OpC)
         hipLaunchKernelGGL((gemm_kernel<T, OpN, OpC, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits);
+                           splits, sk);
       else
         hipLaunchKernelGGL((gemm_kernel<T, OpC, OpC, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits);
+                           splits, sk);
     });
     ND_HIP(hipGetLastError());
   }

@@ -652,3 +652,48 @@ def test_copy_conj_transpose(pd, ps):
     for tD, ref, ldd, dn in cases:
         got = tD.cpu().numpy().reshape(dn, ldd).T
         assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_stream_k(prec, opa, opb):
+    """Stream-K shares forced on a ragged batch: each descriptor's tiles x k
+    stages dealt out in equal pieces that start and end inside tiles, added
+    atomically to a pre-scaled C.  Shapes around the tile (64) and k stage
+    (16), one with k = 1 stage, an empty k and an empty output in the same
+    launch; beta = 0.5, alpha complex.  Also a single long product (the QR
+    V^H C shape class at reduced size)."""
+    rng = np.random.default_rng(140 + 8 * prec + 2 * opa + opb)
+    batches = [[(300, 200, 5000), (129, 77, 3001), (64, 64, 16), (65, 63, 17), (200, 100, 0),
+                (0, 40, 100), (1, 1, 999)],
+               [(256, 1500, 3000)]]
+    alpha, beta = 0.7 - 0.4j, 0.5
+    for shapes in batches:
+        mats, keep, mnk, ld, ptr = [], [], [], [], []
+        for (m, n, k) in shapes:
+            A = crandn(rng, *((m, k) if opa == 0 else (k, m)))
+            B = crandn(rng, *((k, n) if opb == 0 else (n, k)))
+            Cm = crandn(rng, m, n)
+            ta, tb, tc = (to_dev(A, prec) if A.size else torch.zeros(1, dtype=CT[prec][1], device=DEV),
+                          to_dev(B, prec) if B.size else torch.zeros(1, dtype=CT[prec][1], device=DEV),
+                          to_dev(Cm, prec) if Cm.size else torch.zeros(1, dtype=CT[prec][1], device=DEV))
+            keep += [ta, tb, tc]
+            mats.append((A, B, Cm, tc))
+            mnk += [m, n, k]
+            ld += [max(1, A.shape[0]), max(1, B.shape[0]), max(1, m)]
+            ptr += [ta.data_ptr(), tb.data_ptr(), tc.data_ptr()]
+        a1, p1 = i32(mnk)
+        a2, p2 = i32(ld)
+        a3, p3 = i64(ptr)
+        st = lib.nudft2_test_gemm_cfg(prec, opa, opb, len(shapes), p1, p2, p3, alpha.real,
+                                      alpha.imag, beta, -3, None)
+        assert st == 0, lib.nudft2_last_error()
+        for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+            if m == 0 or n == 0:
+                continue
+            oA = A if opa == 0 else A.conj().T
+            oB = B if opb == 0 else B.conj().T
+            ref = alpha * (oA @ oB) + beta * Cm
+            got = from_dev(tc, m, n)
+            scale = max(1.0, np.abs(ref).max())
+            assert np.abs(got - ref).max() < TOL[prec] * scale * max(k, 1) ** 0.5 * 10, (m, n, k)
