@@ -71,7 +71,8 @@ nudft2_status nudft2_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t n
 /* gemm with a forced k split (splits >= 1: that many plain k splits; 0 = the
  * library's choice; -1 = the tile kernel without splitting and without the
  * tuned table; -2 = the library's heuristic without the tuned table; -3 =
- * stream-K shares of the tiles' k stages wherever the batch allows) and the
+ * stream-K shares of the tiles' k stages wherever the batch allows; -4 = k
+ * splits into partial tiles summed in split order by a second kernel) and the
  * launch's duration in milliseconds (HIP events on the null stream) written to
  * *ms (HOST, may be NULL): the measurement hook of the GEMM autotuner. */
 nudft2_status nudft2_test_gemm_cfg(int32_t prec, int32_t opA, int32_t opB, int32_t nb,

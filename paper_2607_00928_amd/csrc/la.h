@@ -38,6 +38,15 @@ struct DescPool {
   // n bytes of device scratch for a kernel, without an upload (the caller
   // initialises them on the stream); ends reuse like push()
   void* reserve(size_t n);
+  // Device scratch used by one kernel pair at a time in stream order (the
+  // GEMM's partial tiles), apart from the descriptor slots: allocated on first
+  // use (a larger request synchronises the stream and replaces it), kept until
+  // destroy().  nullptr in deferred mode (nothing is allocated while a stream
+  // is captured) or when the allocation fails; the caller then takes a path
+  // without it.
+  void* stream_scratch(size_t n);
+  char* sscr = nullptr;
+  size_t sscr_cap = 0;
   size_t valid = 0;        // slots [0, valid) mirror the host staging on the device
   bool tainted = false;    // a plain push happened: no reuse
   void flush();
@@ -68,7 +77,12 @@ struct GemmDesc {
 // shares to the device's workgroup slots.  splits_force > 0 forces that many
 // plain k splits (used by the tuner); -1 runs the tile kernel unsplit,
 // without the table; -2 takes the heuristic without the table (the tuner's
-// baseline); -3 takes stream-K wherever it applies.
+// baseline); -3 takes stream-K wherever it applies; -4 takes the
+// partial-tile split wherever the pool has room for it.
+// Long-k products with few output tiles keep their k splits' partial tiles in
+// the pool's stream scratch, at most this many bytes a launch; without the
+// scratch they take the atomic split instead.
+constexpr size_t kGemmPartBytes = size_t(64) << 20;
 template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB,
                   int splits_force = 0);

@@ -39,7 +39,9 @@ void DescPool::check_flag() {
 void DescPool::destroy() {
   if (host) (void)hipHostFree(host);
   if (dev) (void)hipFree(dev);
-  host = dev = nullptr;
+  if (sscr) (void)hipFree(sscr);
+  host = dev = sscr = nullptr;
+  sscr_cap = 0;
   flag = nullptr;
   cap = used = 0;
 }
@@ -81,6 +83,25 @@ void* DescPool::reserve(size_t n) {
   void* d = dev + used;
   used += need;
   return d;
+}
+
+void* DescPool::stream_scratch(size_t n) {
+  if (deferred) return nullptr;
+  if (n > sscr_cap) {
+    if (sscr) {
+      ND_HIP(hipStreamSynchronize(stream));
+      ND_HIP(hipFree(sscr));
+      sscr = nullptr;
+      sscr_cap = 0;
+    }
+    if (hipMalloc((void**)&sscr, n) != hipSuccess) {
+      (void)hipGetLastError();   // out of memory: the caller falls back
+      sscr = nullptr;
+      return nullptr;
+    }
+    sscr_cap = n;
+  }
+  return sscr;
 }
 
 void DescPool::flush() {
@@ -127,12 +148,15 @@ constexpr int GK = 16;    // k per stage
 // of 16 banks, so the 16-lane groups of an operand read hit distinct banks.
 template <typename T> constexpr int gemm_ldt() { return GT + 64 / (int)sizeof(T); }
 
-// The output tile at (i0, j0) over the k range [kbeg, kend), stored (C =
-// alpha P + beta C) or, when `atomic`, added to C atomically.  Called
-// uniformly by the whole workgroup; leaves the LDS buffers free on return.
+// The output tile at (i0, j0) over the k range [kbeg, kend): alpha P is
+// stored (adding beta times the old value) or, when `atomic`, added
+// atomically, at cb + (i - i0) + (j - j0) cld for the tile's rows i < m and
+// columns j < n.  Called uniformly by the whole workgroup; leaves the LDS
+// buffers free on return.
 template <typename T, int OPA, int OPB>
 __device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, int kbeg, int kend,
-                                          bool atomic, T (&As)[2][2][GK][gemm_ldt<T>()],
+                                          bool atomic, cplx<T>* cb, int64_t cld, T beta,
+                                          T (&As)[2][2][GK][gemm_ldt<T>()],
                                           T (&Bs)[2][2][GK][gemm_ldt<T>()]) {
   using C2 = cplx<T>;
   using A4 = typename acc4<T>::type;
@@ -255,15 +279,15 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, 
             const T cr = p1 - p2, ci = acc3[a][b][v] - p1 - p2;
             out[v] = mk<T>(d.ar * cr - d.ai * ci, d.ar * ci + d.ai * cr);
           }
-          C2* p = d.C + (int64_t)ib + (int64_t)j * d.ldc;
+          C2* p = cb + (int64_t)(ib - i0) + (int64_t)(j - j0) * cld;
           if (ib + 3 < d.m) {
             f4u* q = (f4u*)p;
             f4u w0 = {out[0].x, out[0].y, out[1].x, out[1].y};
             f4u w1 = {out[2].x, out[2].y, out[3].x, out[3].y};
-            if (d.beta != T(0)) {
+            if (beta != T(0)) {
               const f4u o0 = ldg(q), o1 = ldg(q + 1);
-              w0 += d.beta * o0;
-              w1 += d.beta * o1;
+              w0 += beta * o0;
+              w1 += beta * o1;
             }
             stg(q, w0);
             stg(q + 1, w1);
@@ -272,10 +296,10 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, 
             for (int v = 0; v < 4; ++v) {
               if (ib + v >= d.m) break;
               C2 o = out[v];
-              if (d.beta != T(0)) {
+              if (beta != T(0)) {
                 const C2 c = ldc(p + v);
-                o.x += d.beta * c.x;
-                o.y += d.beta * c.y;
+                o.x += beta * c.x;
+                o.y += beta * c.y;
               }
               stc(p + v, o);
             }
@@ -296,16 +320,16 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, 
           const T p1 = acc1[a][b][v], p2 = acc2[a][b][v];
           const T cr = p1 - p2, ci = acc3[a][b][v] - p1 - p2;
           C2 out = mk<T>(d.ar * cr - d.ai * ci, d.ar * ci + d.ai * cr);
-          C2* p = d.C + (int64_t)i + (int64_t)j * d.ldc;
+          C2* p = cb + (int64_t)(i - i0) + (int64_t)(j - j0) * cld;
           if (atomic) {
             atomic_addg(&p->x, out.x);
             atomic_addg(&p->y, out.y);
             continue;
           }
-          if (d.beta != T(0)) {
+          if (beta != T(0)) {
             const C2 o = ldc(p);
-            out.x += d.beta * o.x;
-            out.y += d.beta * o.y;
+            out.x += beta * o.x;
+            out.y += beta * o.y;
           }
           stc(p, out);
         }
@@ -313,14 +337,17 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, 
 }
 
 // splits > 1: blockIdx.z takes the k range [z kc, (z+1) kc) and the result is
-// added atomically (C must already hold beta C).
+// added atomically (C must already hold beta C), or, with `part`, stored as
+// the 64 x 64 partial tile part[((y splits + z) gridDim.x + x) 4096] (column
+// major, leading dimension 64; ranges past k store nothing) for
+// gemm_reduce_kernel to sum.
 // sk > 0 (stream-K): the descriptor's tiles x k stages are dealt out in equal
 // contiguous shares to its sk workgroups (blockIdx.x); a share may end in
 // one tile and go on in the next, and every piece is added atomically to a
 // pre-scaled C.  Equal shares leave no partial last round of workgroups.
 template <typename T, int OPA, int OPB, class DS>
 __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS descs, int splits,
-                                                                          int sk) {
+                                                                          int sk, cplx<T>* part) {
   __shared__ T As[2][2][GK][gemm_ldt<T>()];   // [buffer][re, im][k][row]
   __shared__ T Bs[2][2][GK][gemm_ldt<T>()];
   const GemmDesc<T> d = descs[blockIdx.y];
@@ -333,8 +360,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS de
     while (u < u1) {
       const int tile = (int)(u / nst), s0 = (int)(u % nst);
       const int s1 = (int)min((int64_t)nst, s0 + (u1 - u));
-      gemm_tile<T, OPA, OPB>(d, (tile % tm) * GT, (tile / tm) * GT, s0 * GK, min(d.k, s1 * GK),
-                             true, As, Bs);
+      const int i0 = (tile % tm) * GT, j0 = (tile / tm) * GT;
+      gemm_tile<T, OPA, OPB>(d, i0, j0, s0 * GK, min(d.k, s1 * GK), true,
+                             d.C + i0 + (int64_t)j0 * d.ldc, d.ldc, T(0), As, Bs);
       u += s1 - s0;
     }
     return;
@@ -346,7 +374,46 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS de
   if (kbeg >= kend && splits > 1) return;
   const int i0 = (blockIdx.x % tm) * GT, j0 = (blockIdx.x / tm) * GT;
   if (d.lower && j0 > i0 + GT - 1) return;   // strictly above the diagonal of a Hermitian C
-  gemm_tile<T, OPA, OPB>(d, i0, j0, kbeg, kend, splits > 1, As, Bs);
+  if (part) {
+    cplx<T>* cb = part + (((size_t)blockIdx.y * splits + blockIdx.z) * gridDim.x + blockIdx.x) *
+                             (size_t)(GT * GT);
+    gemm_tile<T, OPA, OPB>(d, i0, j0, kbeg, kend, false, cb, GT, T(0), As, Bs);
+  } else {
+    gemm_tile<T, OPA, OPB>(d, i0, j0, kbeg, kend, splits > 1, d.C + i0 + (int64_t)j0 * d.ldc,
+                           d.ldc, d.beta, As, Bs);
+  }
+}
+
+// C = sum over z of the partial tiles (in order z = 0, 1, ...) + beta C:
+// the second pass of a k split through `part` (gemm_kernel).  Each
+// descriptor's ranges are those gemm_kernel gives it: kc rounded up to a
+// whole k stage, ranges starting at or past k hold nothing.
+template <typename T, class DS>
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(DS descs, int splits, int tiles,
+                                                          const cplx<T>* __restrict__ part) {
+  const GemmDesc<T> d = descs[blockIdx.y];
+  const int kc = (((d.k + splits - 1) / splits) + GK - 1) / GK * GK;
+  const int nz = kc > 0 ? min(splits, (d.k + kc - 1) / kc) : 0;
+  const int tm = (d.m + GT - 1) / GT;
+  const int64_t cnt = (int64_t)d.m * d.n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
+    const int i = (int)(e % d.m), j = (int)(e / d.m);
+    const size_t off = (size_t)((i / GT) + (j / GT) * tm) * (GT * GT) + (i % GT) + (j % GT) * GT;
+    const cplx<T>* pz = part + (size_t)blockIdx.y * splits * tiles * (GT * GT) + off;
+    T sr = 0, si = 0;
+    for (int z = 0; z < nz; ++z) {
+      const cplx<T> v = ldc(pz + (size_t)z * tiles * (GT * GT));
+      sr += v.x;
+      si += v.y;
+    }
+    cplx<T>* c = d.C + i + (int64_t)j * d.ldc;
+    if (d.beta != T(0)) {
+      const cplx<T> o = ldc(c);
+      sr += d.beta * o.x;
+      si += d.beta * o.y;
+    }
+    stc(c, mk<T>(sr, si));
+  }
 }
 
 // Skinny products (n <= SK_N columns, B not transposed): memory-bound on A.
@@ -1581,6 +1648,8 @@ static void smallm_wide_batched(DescPool& pool, const std::vector<GemmDesc<T>>& 
 // stream-K for long-k products whose tiles and splits stay under two rounds
 // of workgroups
 constexpr bool kGemmStreamK = true;
+// partial tiles plus an ordered reduction for long-k products with few tiles
+constexpr bool kGemmPartials = true;
 
 static int device_cus() {
   static int cus = 0;
@@ -1668,7 +1737,7 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
       splits = std::max(1, std::min({force, std::max(1, ceil_div(maxk, GK)), 4096}));
     } else if (maxk >= 4096 && maxt >= 16) {
       splits = (int)std::max<int64_t>(1, std::min<int64_t>(7 * slots / wgs, maxk / 2048));
-      want_sk = want_sk || (kGemmStreamK && wgs * splits < 2 * slots);
+      want_sk = want_sk || (kGemmStreamK && wgs * splits < 2 * slots && splits_force != -4);
     } else if (wgs < slots && maxk >= 1024) {
       const int64_t by_k = std::max<int64_t>(maxk / 1024, std::min<int64_t>(maxk / 256, 4));
       splits = (int)std::min<int64_t>(by_k, (2 * slots + wgs - 1) / wgs);
@@ -1692,6 +1761,28 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
         splits = 1;
       }
     }
+    // Fewer than 16 tiles a product and k >= 1024 (tall-panel Grams): about
+    // two rounds of k splits of 256 or more whose 64 x 64 partial tiles go
+    // to the pool's stream scratch (plain stores) and are summed in split order by
+    // gemm_reduce_kernel.  The atomics of a plain split made short splits
+    // pay more than they gained, and at the split counts that kept them
+    // affordable these products left one workgroup per CU (latency bound):
+    // 128 x 128 x 8163 x 4 ran at 30 TF/s with the best plain split, 64 this
+    // way.  splits_force = -4 takes this path wherever the scratch fits.
+    cplx<T>* part = nullptr;
+    if (!lower && sk == 0 &&
+        (splits_force == -4 ||
+         (kGemmPartials && (splits_force == 0 || splits_force == -2) && maxt < 16 &&
+          maxk >= 1024))) {
+      const size_t tile_b = (size_t)GT * GT * sizeof(cplx<T>);
+      int64_t sp = std::min<int64_t>(2 * slots / wgs, maxk / 256);
+      if (splits_force == -4) sp = std::max<int64_t>(sp, 2);
+      sp = std::min<int64_t>({sp, (int64_t)(kGemmPartBytes / (tile_b * (size_t)wgs)), 4096});
+      if (sp >= 2) {
+        part = (cplx<T>*)pool.stream_scratch(kGemmPartBytes);
+        if (part) splits = (int)sp;
+      }
+    }
     int64_t mx = 0;
     for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
     const dim3 grid = sk > 0 ? dim3((unsigned)sk, (unsigned)n, 1) : dim3(maxt, (unsigned)n, splits);
@@ -1704,26 +1795,32 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     }
     with_descs(pool, sub.data(), n, [&](auto dd) {
       using DS = decltype(dd);
-      if (splits > 1 || sk > 0)
+      if ((splits > 1 && !part) || sk > 0)
         hipLaunchKernelGGL(
             (gemm_prescale_kernel<T, DS>),
             dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
                  (unsigned)n),
             dim3(256), 0, pool.stream, dd);
       ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, mm, mn, maxk,
-                   (int)opA * 2 + (int)opB + 10 * (sk > 0 ? 99 : splits));
+                   (int)opA * 2 + (int)opB + 10 * (sk > 0 ? 99 : part ? 98 : splits));
       if (opA == OpN && opB == OpN)
         hipLaunchKernelGGL((gemm_kernel<T, OpN, OpN, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits, sk);
+                           splits, sk, part);
       else if (opA == OpC && opB == OpN)
         hipLaunchKernelGGL((gemm_kernel<T, OpC, OpN, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits, sk);
+                           splits, sk, part);
       else if (opA == OpN && opB == OpC)
         hipLaunchKernelGGL((gemm_kernel<T, OpN, OpC, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits, sk);
+                           splits, sk, part);
       else
         hipLaunchKernelGGL((gemm_kernel<T, OpC, OpC, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits, sk);
+                           splits, sk, part);
+      if (part)
+        hipLaunchKernelGGL(
+            (gemm_reduce_kernel<T, DS>),
+            dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
+                 (unsigned)n),
+            dim3(256), 0, pool.stream, dd, splits, maxt, (const cplx<T>*)part);
     });
     ND_HIP(hipGetLastError());
   }

@@ -697,3 +697,47 @@ def test_gemm_stream_k(prec, opa, opb):
             got = from_dev(tc, m, n)
             scale = max(1.0, np.abs(ref).max())
             assert np.abs(got - ref).max() < TOL[prec] * scale * max(k, 1) ** 0.5 * 10, (m, n, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_partial_tile_splits(prec, opa, opb):
+    """k splits kept as partial tiles in scratch and summed in split order by a
+    second kernel (forced, splits = -4): ragged outputs of one to a few tiles,
+    k long and short (splits past k hold nothing), k = 0 and an empty output
+    in the same launch, beta = 0.5 and 0, alpha complex.  Then the library's
+    own choice on a batch of tall-panel Gram shapes (128 x 128, k = 9000),
+    which takes this path."""
+    rng = np.random.default_rng(160 + 8 * prec + 2 * opa + opb)
+    alpha = -0.6 + 0.3j
+    runs = [([(128, 128, 5000), (65, 127, 4099), (1, 64, 700), (64, 1, 33), (100, 90, 0),
+              (0, 30, 200), (130, 70, 17)], -4, 0.5),
+            ([(128, 128, 9000)] * 4 + [(128, 96, 8191)], 0, 0.0)]
+    for shapes, sp, beta in runs:
+        mats, keep, mnk, ld, ptr = [], [], [], [], []
+        for (m, n, k) in shapes:
+            A = crandn(rng, *((m, k) if opa == 0 else (k, m)))
+            B = crandn(rng, *((k, n) if opb == 0 else (n, k)))
+            Cm = crandn(rng, m, n)
+            ts = [to_dev(X, prec) if X.size else torch.zeros(1, dtype=CT[prec][1], device=DEV)
+                  for X in (A, B, Cm)]
+            keep += ts
+            mats.append((A, B, Cm, ts[2]))
+            mnk += [m, n, k]
+            ld += [max(1, A.shape[0]), max(1, B.shape[0]), max(1, m)]
+            ptr += [t.data_ptr() for t in ts]
+        a1, p1 = i32(mnk)
+        a2, p2 = i32(ld)
+        a3, p3 = i64(ptr)
+        st = lib.nudft2_test_gemm_cfg(prec, opa, opb, len(shapes), p1, p2, p3, alpha.real,
+                                      alpha.imag, beta, sp, None)
+        assert st == 0, lib.nudft2_last_error()
+        for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+            if m == 0 or n == 0:
+                continue
+            oA = A if opa == 0 else A.conj().T
+            oB = B if opb == 0 else B.conj().T
+            ref = alpha * (oA @ oB) + beta * Cm
+            got = from_dev(tc, m, n)
+            scale = max(1.0, np.abs(ref).max())
+            assert np.abs(got - ref).max() < TOL[prec] * scale * max(k, 1) ** 0.5 * 10, (m, n, k)
