@@ -1124,54 +1124,72 @@ constexpr int WY_NT = 1024;   // threads of a merge workgroup (one per problem)
 template <typename T, class DS>
 __global__ __launch_bounds__(WY_NT) void wy_merge_kernel(DS descs) {
   using C2 = cplx<T>;
+  constexpr int NB = QR_NB, NR = QR_HB - QR_NB;   // panel width, most rows above a panel
   const WyDesc<T> d = descs[blockIdx.x];
   const int kb = d.kb, ldt = d.ldt, tid = threadIdx.x;
-  const int nbi = (kb + QR_NB - 1) / QR_NB;
+  const int nbi = (kb + NB - 1) / NB;
   C2* To = d.Tout;
-  __shared__ C2 X[QR_HB - QR_NB][QR_NB];
+  // X = S(0:c0, c0:c0+jb) T_j.  U holds S's block and T_j while X is formed,
+  // then 32-column chunks of T(0:c0, 0:c0); rows padded by one against bank
+  // conflicts.  Every operand is staged with one batch of coalesced loads.
+  __shared__ C2 X[NR][NB + 1];
+  __shared__ C2 U[(NR + NB) * (NB + 1)];
+  C2(*Sb)[NB + 1] = reinterpret_cast<C2(*)[NB + 1]>(U);
+  C2(*Tj)[NB + 1] = reinterpret_cast<C2(*)[NB + 1]>(U + NR * (NB + 1));
+  C2(*Tc)[NB + 1] = reinterpret_cast<C2(*)[NB + 1]>(U);
   for (int e = tid; e < kb * kb; e += WY_NT) {
     int r = e % kb, c = e / kb;
-    int bi = r / QR_NB, bj = c / QR_NB;
+    int bi = r / NB, bj = c / NB;
     stc(To + r + (int64_t)c * ldt,
-        bi == bj ? ldc(d.Tw + (int64_t)bi * QR_NB * QR_NB + (r % QR_NB) + (c % QR_NB) * QR_NB)
-                 : mk<T>(0, 0));
+        bi == bj ? ldc(d.Tw + (int64_t)bi * NB * NB + (r % NB) + (c % NB) * NB) : mk<T>(0, 0));
   }
   __syncthreads();
+  constexpr int EPT = (NR * NB + WY_NT - 1) / WY_NT;   // output entries per thread
   for (int j = 1; j < nbi; ++j) {
-    const int c0 = j * QR_NB, jb = min(QR_NB, kb - c0);
-    // the dot products issue WY_U independent loads before using them (the
-    // operands sit in L2; a one-load-at-a-time loop is latency-bound)
-    constexpr int WY_U = 8;
+    const int c0 = j * NB, jb = min(NB, kb - c0);
     for (int e = tid; e < c0 * jb; e += WY_NT) {
-      int r = e % c0, c = e / c0;
-      C2 sum = mk<T>(0, 0);
-      for (int q0 = 0; q0 <= c; q0 += WY_U) {   // T_j upper triangular
-        C2 sv[WY_U], tv[WY_U];
-#pragma unroll
-        for (int u = 0; u < WY_U; ++u) {
-          const int q = min(q0 + u, c);
-          sv[u] = ldc(d.S + r + (int64_t)(c0 + q) * d.lds);
-          tv[u] = ldc(To + (c0 + q) + (int64_t)(c0 + c) * ldt);
-        }
-#pragma unroll
-        for (int u = 0; u < WY_U; ++u)
-          if (q0 + u <= c) sum = cadd(sum, cmul(sv[u], tv[u]));
-      }
-      X[r][c] = sum;
+      const int r = e % c0, c = e / c0;
+      Sb[r][c] = ldc(d.S + r + (int64_t)(c0 + c) * d.lds);
+    }
+    for (int e = tid; e < jb * jb; e += WY_NT) {
+      const int q = e % jb, c = e / jb;
+      Tj[q][c] = ldc(d.Tw + (int64_t)j * NB * NB + q + c * NB);
     }
     __syncthreads();
     for (int e = tid; e < c0 * jb; e += WY_NT) {
-      int r = e % c0, c = e / c0;
+      const int r = e % c0, c = e / c0;
       C2 sum = mk<T>(0, 0);
-      for (int q0 = r; q0 < c0; q0 += WY_U) {   // T(0:c0, 0:c0) upper triangular
-        C2 tv[WY_U];
+      for (int q = 0; q <= c; ++q) sum = cadd(sum, cmul(Sb[r][q], Tj[q][c]));   // T_j upper
+      X[r][c] = sum;
+    }
+    __syncthreads();
+    // T(0:c0, c0:c0+jb) = -T(0:c0, 0:c0) X, T(0:c0, 0:c0) upper triangular
+    C2 acc[EPT];
 #pragma unroll
-        for (int u = 0; u < WY_U; ++u) tv[u] = ldc(To + r + (int64_t)min(q0 + u, c0 - 1) * ldt);
-#pragma unroll
-        for (int u = 0; u < WY_U; ++u)
-          if (q0 + u < c0) sum = cadd(sum, cmul(tv[u], X[q0 + u][c]));
+    for (int t = 0; t < EPT; ++t) acc[t] = mk<T>(0, 0);
+    for (int qb = 0; qb < c0; qb += NB) {
+      for (int e = tid; e < c0 * NB; e += WY_NT) {
+        const int r = e % c0, qq = e / c0;
+        Tc[r][qq] = ldc(To + r + (int64_t)(qb + qq) * ldt);
       }
-      stc(To + r + (int64_t)(c0 + c) * ldt, mk<T>(-sum.x, -sum.y));
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < EPT; ++t) {
+        const int e = tid + t * WY_NT;
+        if (e < c0 * jb) {
+          const int r = e % c0, c = e / c0;
+          for (int qq = max(r - qb, 0); qq < NB; ++qq) acc[t] = cadd(acc[t], cmul(Tc[r][qq], X[qb + qq][c]));
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
+      const int e = tid + t * WY_NT;
+      if (e < c0 * jb) {
+        const int r = e % c0, c = e / c0;
+        stc(To + r + (int64_t)(c0 + c) * ldt, mk<T>(-acc[t].x, -acc[t].y));
+      }
     }
     __syncthreads();
   }
@@ -1719,10 +1737,12 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     // Splitting the k loop.  The device holds `slots` tile workgroups at once.
     // Long k (>= 4096) with at least 16 output tiles a product: about seven
     // rounds of workgroups, each split at least 2048 long; where that still
-    // leaves under two rounds, stream-K instead.  Otherwise, under one round
-    // and k >= 1024: about two rounds, splits of ~1024 (up to four of 256 or
-    // more for shorter k).  k < 1024 is never split (the pre-scale and the
-    // atomics cost more than the extra workgroups give).  Measured on the
+    // leaves under two rounds, stream-K instead.  Fewer than 16 tiles and
+    // k >= 1024: partial-tile splits (below).  Otherwise, under one round and
+    // k >= 1024: about two rounds, splits of ~1024 (up to four of 256 or more
+    // for shorter k).  k < 1024 is never split (the pre-scale and the atomics
+    // cost more than the extra workgroups give).  A tuned table entry for the
+    // launch's class takes precedence over all of these.  Measured on the
     // factorization's shapes (FP32, TF/s): 256 x 13661 x 28495 8 splits 134
     // (3: 123); 4 x 256 x 7319 x 10595 4 splits 131 (1: 115); 4 x 256 x 2147
     // x 5704 stream-K 111 (best split 100); 128 x 128^2 x 593 unsplit 88 (2
@@ -1762,9 +1782,9 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
       }
     }
     // Fewer than 16 tiles a product and k >= 1024 (tall-panel Grams): about
-    // two rounds of k splits of 256 or more whose 64 x 64 partial tiles go
-    // to the pool's stream scratch (plain stores) and are summed in split order by
-    // gemm_reduce_kernel.  The atomics of a plain split made short splits
+    // two rounds of k splits of 256 or more whose 64 x 64 partial tiles go to
+    // the pool's stream scratch (plain stores) and are summed in split order
+    // by gemm_reduce_kernel.  The atomics of a plain split made short splits
     // pay more than they gained, and at the split counts that kept them
     // affordable these products left one workgroup per CU (latency bound):
     // 128 x 128 x 8163 x 4 ran at 30 TF/s with the best plain split, 64 this
@@ -1772,8 +1792,8 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     cplx<T>* part = nullptr;
     if (!lower && sk == 0 &&
         (splits_force == -4 ||
-         (kGemmPartials && (splits_force == 0 || splits_force == -2) && maxt < 16 &&
-          maxk >= 1024))) {
+         (kGemmPartials && (splits_force == 0 || splits_force == -2) && force <= 0 &&
+          maxt < 16 && maxk >= 1024))) {
       const size_t tile_b = (size_t)GT * GT * sizeof(cplx<T>);
       int64_t sp = std::min<int64_t>(2 * slots / wgs, maxk / 256);
       if (splits_force == -4) sp = std::max<int64_t>(sp, 2);
