@@ -1323,18 +1323,33 @@ __global__ __launch_bounds__(256) void pchol_col_kernel(const PcholDesc* __restr
   __shared__ double2 lp[PC_NB];
   __shared__ int piv_s, stop_s;
   __shared__ double dp_s;
-  if (tid == 0) {
-    // combine the workgroups' partials of this column (same order everywhere)
+  // combine the workgroups' partials of this column in wave 0: lane l takes
+  // partials l, l + 64, ... (all its loads in flight at once), then an xor
+  // butterfly leaves every lane the same sum and the same winner (ties to
+  // the lower row); the order is fixed, so every workgroup agrees
+  double bb = -1.0, ss = 0.0;
+  int ii = -1;
+  if (tid < 64) {
     const double* sl = part + ((size_t)b * 2 + (k & 1)) * gsize * 3;
-    double bb = sl[0], ss = sl[2];
-    int ii = (int)sl[1];
-    for (int v = 1; v < gw; ++v) {
-      ss += sl[3 * v + 2];
-      if (pc_better(sl[3 * v], (int)sl[3 * v + 1], bb, ii)) {
-        bb = sl[3 * v];
-        ii = (int)sl[3 * v + 1];
+    for (int v = tid; v < gw; v += 64) {
+      const double pv = sl[3 * v], pi = sl[3 * v + 1], ps = sl[3 * v + 2];
+      ss += ps;
+      if (pc_better(pv, (int)pi, bb, ii)) {
+        bb = pv;
+        ii = (int)pi;
       }
     }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(bb, o, 64), os = __shfl_xor(ss, o, 64);
+      const int oi = __shfl_xor(ii, o, 64);
+      ss += os;
+      if (pc_better(ob, oi, bb, ii)) {
+        bb = ob;
+        ii = oi;
+      }
+    }
+  }
+  if (tid == 0) {
     const double tol = d.tol2 * trace[b];
     const int stop = (k >= d.rmax || k >= d.w || ss <= tol || ii < 0 || bb <= 0.0) ? 1 : 0;
     stop_s = stop;
@@ -1363,7 +1378,15 @@ __global__ __launch_bounds__(256) void pchol_col_kernel(const PcholDesc* __restr
     // L(i,k) = (K(i,p) - sum_q L(i,q) conj(L(p,q))) / sqrt(d_p); K holds its lower triangle
     double2 v = i >= p ? d.K[i + (int64_t)p * d.ldk] : cconj(d.K[p + (int64_t)i * d.ldk]);
     const double2* li = d.L + i + (int64_t)k0 * d.ldl;
+    // the row's panel entries in batches of 16 loads in flight
     int q = 0;
+    for (; q + 16 <= kk; q += 16) {
+      double2 l16[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) l16[u] = li[(int64_t)(q + u) * d.ldl];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v = csub(v, cmulc(lp[q + u], l16[u]));
+    }
     for (; q + 4 <= kk; q += 4) {
       double2 l4[4];
 #pragma unroll
