@@ -1600,10 +1600,14 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
   double fl = 0;
   for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
   int64_t mx = 0;
-  for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
+  bool scale = false;   // some C needs beta applied before the atomic adds
+  for (auto& g : sub) {
+    mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
+    scale = scale || (g.m > 0 && g.n > 0 && g.beta != T(1));
+  }
   with_descs(pool, sub.data(), n, [&](auto dd) {
     using DS = decltype(dd);
-    if (splits > 1)
+    if (splits > 1 && scale)
       hipLaunchKernelGGL(
           (gemm_prescale_kernel<T, DS>),
           dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
@@ -1827,7 +1831,11 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
       }
     }
     int64_t mx = 0;
-    for (auto& g : sub) mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
+    bool scale = false;   // some C needs beta applied before the atomic adds
+    for (auto& g : sub) {
+      mx = std::max<int64_t>(mx, (int64_t)g.m * g.n);
+      scale = scale || (g.m > 0 && g.n > 0 && g.beta != T(1));
+    }
     const dim3 grid = sk > 0 ? dim3((unsigned)sk, (unsigned)n, 1) : dim3(maxt, (unsigned)n, splits);
     double fl = 0;
     int mm = 0, mn = 0;
@@ -1838,7 +1846,7 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     }
     with_descs(pool, sub.data(), n, [&](auto dd) {
       using DS = decltype(dd);
-      if ((splits > 1 && !part) || sk > 0)
+      if (((splits > 1 && !part) || sk > 0) && scale)
         hipLaunchKernelGGL(
             (gemm_prescale_kernel<T, DS>),
             dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
