@@ -1,5 +1,6 @@
 // C-ABI entry points: argument checks, error mapping, dispatch.
 #include <cstring>
+#include <mutex>
 
 #include "../../include/nudft2_testing.h"
 #include "device_util.h"
@@ -12,6 +13,32 @@ namespace nd {
 
 static thread_local std::string g_last_error;
 thread_local Profiler* g_prof = nullptr;
+
+namespace {
+std::mutex g_ev_mu;
+std::vector<std::vector<hipEvent_t>> g_ev_cache;   // per device; kept until the process ends
+}  // namespace
+
+hipEvent_t event_cache_get(int dev) {
+  {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    if (dev >= 0 && (size_t)dev < g_ev_cache.size() && !g_ev_cache[dev].empty()) {
+      hipEvent_t e = g_ev_cache[dev].back();
+      g_ev_cache[dev].pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e;
+  ND_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void event_cache_put(int dev, hipEvent_t e) {
+  if (!e || dev < 0) return;
+  std::lock_guard<std::mutex> lk(g_ev_mu);
+  if ((size_t)dev >= g_ev_cache.size()) g_ev_cache.resize(dev + 1);
+  g_ev_cache[dev].push_back(e);
+}
 
 // Routes kernel timing of the calling thread to the plan's profiler while an
 // entry point runs.

@@ -9,6 +9,8 @@
 #include <type_traits>
 
 #include "device_util.h"
+#include <hip/hip_ext.h>
+
 #include "la.h"
 #include "hazard.h"
 #include "prof.h"
@@ -1614,16 +1616,16 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
                (unsigned)n),
           dim3(256), 0, pool.stream, dd);
     ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn,
-                 maxk, (int)opA * 2 + 10 * splits + 1000);
+                 maxk, (int)opA * 2 + 10 * splits + 1000, true);
     dim3 grid((unsigned)bx, (unsigned)n, (unsigned)splits);
     auto launch = [&](auto nc) {
       constexpr int NC = decltype(nc)::value;
       if (opA == OpN)
-        hipLaunchKernelGGL((gemm_skinny_n_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
-                           dd, splits);
+        hipExtLaunchKernelGGL((gemm_skinny_n_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
+                              ps.start(), ps.stop(), 0, dd, splits);
       else
-        hipLaunchKernelGGL((gemm_skinny_c_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
-                           dd, splits);
+        hipExtLaunchKernelGGL((gemm_skinny_c_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
+                              ps.start(), ps.stop(), 0, dd, splits);
     };
     if (maxn <= 1) launch(std::integral_constant<int, 1>{});
     else if (maxn <= 2) launch(std::integral_constant<int, 2>{});
@@ -1648,21 +1650,21 @@ static void smallmn_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub,
       hipLaunchKernelGGL((gemm_prescale_kernel<T, DS>), dim3(4, (unsigned)n), dim3(256), 0,
                          pool.stream, dd);
     ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn,
-                 maxk, 2000 + 10 * mb + nb);
+                 maxk, 2000 + 10 * mb + nb, true);
     const int kc = small_out_kc(maxk, n);
     dim3 grid((unsigned)((maxk + kc - 1) / kc), (unsigned)n);
     if (mb == 1 && nb == 1)
-      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 1, DS>), grid, dim3(256), 0, pool.stream, dd,
-                         kc);
+      hipExtLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 1, DS>), grid, dim3(256), 0, pool.stream,
+                            ps.start(), ps.stop(), 0, dd, kc);
     else if (mb == 1)
-      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 2, DS>), grid, dim3(256), 0, pool.stream, dd,
-                         kc);
+      hipExtLaunchKernelGGL((gemm_smallmn_kernel<T, 1, 2, DS>), grid, dim3(256), 0, pool.stream,
+                            ps.start(), ps.stop(), 0, dd, kc);
     else if (nb == 1)
-      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 1, DS>), grid, dim3(256), 0, pool.stream, dd,
-                         kc);
+      hipExtLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 1, DS>), grid, dim3(256), 0, pool.stream,
+                            ps.start(), ps.stop(), 0, dd, kc);
     else
-      hipLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 2, DS>), grid, dim3(256), 0, pool.stream, dd,
-                         kc);
+      hipExtLaunchKernelGGL((gemm_smallmn_kernel<T, 2, 2, DS>), grid, dim3(256), 0, pool.stream,
+                            ps.start(), ps.stop(), 0, dd, kc);
   });
   ND_HIP(hipGetLastError());
 }
@@ -1681,11 +1683,11 @@ static void smallm_wide_batched(DescPool& pool, const std::vector<GemmDesc<T>>& 
       hipLaunchKernelGGL((gemm_prescale_kernel<T, DS>), dim3(4, (unsigned)n), dim3(256), 0,
                          pool.stream, dd);
     ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn,
-                 maxk, 3000);
+                 maxk, 3000, true);
     const int kc = small_out_kc(maxk, n);
-    hipLaunchKernelGGL((gemm_smallm_wide_kernel<T, DS>),
-                       dim3((unsigned)((maxk + kc - 1) / kc), (unsigned)n), dim3(256), 0,
-                       pool.stream, dd, kc);
+    hipExtLaunchKernelGGL((gemm_smallm_wide_kernel<T, DS>),
+                          dim3((unsigned)((maxk + kc - 1) / kc), (unsigned)n), dim3(256), 0,
+                          pool.stream, ps.start(), ps.stop(), 0, dd, kc);
   });
   ND_HIP(hipGetLastError());
 }
@@ -1853,25 +1855,28 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
                  (unsigned)n),
             dim3(256), 0, pool.stream, dd);
       ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, mm, mn, maxk,
-                   (int)opA * 2 + (int)opB + 10 * (sk > 0 ? 99 : part ? 98 : splits));
+                   (int)opA * 2 + (int)opB + 10 * (sk > 0 ? 99 : part ? 98 : splits), true);
+      // the reduction pass, when there is one, ends the timed span
+      hipEvent_t e1 = part ? nullptr : ps.stop();
       if (opA == OpN && opB == OpN)
-        hipLaunchKernelGGL((gemm_kernel<T, OpN, OpN, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits, sk, part);
+        hipExtLaunchKernelGGL((gemm_kernel<T, OpN, OpN, DS>), grid, dim3(256), 0, pool.stream,
+                              ps.start(), e1, 0, dd, splits, sk, part);
       else if (opA == OpC && opB == OpN)
-        hipLaunchKernelGGL((gemm_kernel<T, OpC, OpN, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits, sk, part);
+        hipExtLaunchKernelGGL((gemm_kernel<T, OpC, OpN, DS>), grid, dim3(256), 0, pool.stream,
+                              ps.start(), e1, 0, dd, splits, sk, part);
       else if (opA == OpN && opB == OpC)
-        hipLaunchKernelGGL((gemm_kernel<T, OpN, OpC, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits, sk, part);
+        hipExtLaunchKernelGGL((gemm_kernel<T, OpN, OpC, DS>), grid, dim3(256), 0, pool.stream,
+                              ps.start(), e1, 0, dd, splits, sk, part);
       else
-        hipLaunchKernelGGL((gemm_kernel<T, OpC, OpC, DS>), grid, dim3(256), 0, pool.stream, dd,
-                           splits, sk, part);
+        hipExtLaunchKernelGGL((gemm_kernel<T, OpC, OpC, DS>), grid, dim3(256), 0, pool.stream,
+                              ps.start(), e1, 0, dd, splits, sk, part);
       if (part)
-        hipLaunchKernelGGL(
+        hipExtLaunchKernelGGL(
             (gemm_reduce_kernel<T, DS>),
             dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
                  (unsigned)n),
-            dim3(256), 0, pool.stream, dd, splits, maxt, (const cplx<T>*)part);
+            dim3(256), 0, pool.stream, nullptr, ps.stop(), 0, dd, splits, maxt,
+            (const cplx<T>*)part);
     });
     ND_HIP(hipGetLastError());
   }

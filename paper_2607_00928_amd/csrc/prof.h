@@ -12,6 +12,14 @@ namespace nd {
 
 enum KClass { KC_APPLY = 0, KC_GEMM32 = 1, KC_GEMM64 = 2, KC_QRPANEL = 3, KC_COUNT = 4 };
 
+// Timing events are reused across plans through a process-wide cache with one
+// list per device (an event belongs to the device current at its creation):
+// a profiler takes its events from the cache and returns them once read, so
+// profiled runs after the first create no events (creating one per launch had
+// cost about 2% of an n512 factor + solve).
+hipEvent_t event_cache_get(int dev);
+void event_cache_put(int dev, hipEvent_t e);
+
 struct Profiler {
   struct Rec {
     hipEvent_t a, b;
@@ -20,25 +28,25 @@ struct Profiler {
     int info[5];   // launch shape for the optional log: descriptors, max m, n, k, variant
   };
   std::vector<Rec> recs;
-  std::vector<hipEvent_t> pool;
+  int dev = -1;   // the plan's device, taken at the first event
   double ms[KC_COUNT] = {0, 0, 0, 0};
   double flops[KC_COUNT] = {0, 0, 0, 0};
   int64_t launches[KC_COUNT] = {0, 0, 0, 0};
   hipEvent_t get() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
-    }
-    hipEvent_t e;
-    ND_HIP(hipEventCreate(&e));
-    return e;
+    if (dev < 0) ND_HIP(hipGetDevice(&dev));
+    return event_cache_get(dev);
   }
   void begin(hipStream_t s, int cls, double fl, hipEvent_t& a) {
     a = get();
     ND_HIP(hipEventRecord(a, s));
     (void)cls;
     (void)fl;
+  }
+  // a pair whose timestamps the dispatches record themselves
+  void push(hipEvent_t a, hipEvent_t b, int cls, double fl, const int* info) {
+    Rec r{a, b, cls, fl, {0, 0, 0, 0, 0}};
+    for (int i = 0; i < 5; ++i) r.info[i] = info[i];
+    recs.push_back(r);
   }
   void end(hipStream_t s, int cls, double fl, hipEvent_t a, const int* info) {
     hipEvent_t b = get();
@@ -62,8 +70,8 @@ struct Profiler {
       ms[r.cls] += t;
       flops[r.cls] += r.flops;
       launches[r.cls] += 1;
-      pool.push_back(r.a);
-      pool.push_back(r.b);
+      event_cache_put(dev, r.a);
+      event_cache_put(dev, r.b);
     }
     if (log) std::fclose(log);
     recs.clear();
@@ -77,29 +85,45 @@ struct Profiler {
   }
   ~Profiler() {
     for (auto& r : recs) {
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
+      event_cache_put(dev, r.a);
+      event_cache_put(dev, r.b);
     }
-    for (auto e : pool) (void)hipEventDestroy(e);
   }
 };
 
 // Profiler of the plan whose entry point is running on this thread (or null).
 extern thread_local Profiler* g_prof;
 
+// Timing of the launches inside a scope.  ext = false: an event pair is
+// recorded on the stream around them.  ext = true: nothing is queued for the
+// timing; the scope's first kernel takes start() and its last kernel takes
+// stop() at dispatch (hipExtLaunchKernelGGL), so the timestamps come with the
+// dispatches themselves and the stream carries no extra packets.  Every ext
+// scope must launch at least one kernel with each event.
 struct ProfScope {
   hipStream_t s;
   int cls;
   double fl;
-  hipEvent_t a = nullptr;
+  bool ext;
+  hipEvent_t a = nullptr, b = nullptr;
   int info[5] = {0, 0, 0, 0, 0};
   ProfScope(hipStream_t st, int c, double f, int nd = 0, int m = 0, int n = 0, int k = 0,
-            int var = 0)
-      : s(st), cls(c), fl(f), info{nd, m, n, k, var} {
-    if (g_prof) g_prof->begin(s, cls, fl, a);
+            int var = 0, bool ext_ = false)
+      : s(st), cls(c), fl(f), ext(ext_), info{nd, m, n, k, var} {
+    if (!g_prof) return;
+    if (ext) {
+      a = g_prof->get();
+      b = g_prof->get();
+    } else {
+      g_prof->begin(s, cls, fl, a);
+    }
   }
+  hipEvent_t start() const { return a; }
+  hipEvent_t stop() const { return b; }
   ~ProfScope() {
-    if (g_prof && a) g_prof->end(s, cls, fl, a, info);
+    if (!g_prof || !a) return;
+    if (ext) g_prof->push(a, b, cls, fl, info);
+    else g_prof->end(s, cls, fl, a, info);
   }
 };
 
