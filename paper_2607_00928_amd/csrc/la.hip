@@ -1698,14 +1698,15 @@ constexpr bool kGemmStreamK = true;
 // partial tiles plus an ordered reduction for long-k products with few tiles
 constexpr bool kGemmPartials = true;
 
+// compute units of the first device used, taken once per process
+// (thread-safe initialisation; the devices of a node are alike)
 static int device_cus() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
+  static const int cus = [] {
+    int dev = 0, n = 0;
     ND_HIP(hipGetDevice(&dev));
-    ND_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    cus = std::max(cus, 1);
-  }
+    ND_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+    return std::max(n, 1);
+  }();
   return cus;
 }
 
@@ -1896,17 +1897,15 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const std::vector<int>
                      int maxmr) {
   const int nact = (int)act.size();
   const void* kern = (const void*)qr_panel_kernel<T, DescMem<int>>;
-  static int max_res[2] = {0, 0};
-  int& mres = max_res[sizeof(T) == 4 ? 0 : 1];
-  if (mres == 0) {
-    int dev = 0, cus = 0, per = 0;
-    ND_HIP(hipGetDevice(&dev));
-    ND_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  // workgroups the device holds at once, taken once per process (per
+  // precision; thread-safe initialisation) on the first device used
+  static const int mres = [&] {
+    int per = 0;
     ND_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, QP_NT, 0));
     // one 1024-thread workgroup per CU at most: the group barriers assume that
     // every workgroup of the grid is resident
-    mres = std::max(1, cus * std::min(std::max(per, 1), 1));
-  }
+    return std::max(1, device_cus() * std::min(std::max(per, 1), 1));
+  }();
   constexpr int rows = 128 * QPanel<T>::R;
   int gsize = std::max(1, (maxmr + rows - 1) / rows);
   ND_CHECK(gsize <= mres, NUDFT2_E_INTERNAL, "QR panel taller than the device can hold");
