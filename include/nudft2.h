@@ -95,6 +95,9 @@ typedef struct {
   int64_t sweep_bytes;    /* factor bytes one solve sweep reads (Algorithm 4.1's
                              bottom-up, root and top-down steps, per pass;
                              right-hand sides excluded): its HBM traffic   */
+  /* wall-clock phases (ms): plan (point copy, binning, upload); 1D
+   * compression; face-splitting assembly; recompression (both stages); URV
+   * factorization.  Each phase ends with a stream synchronisation. */
   double t_plan_ms, t_compress_ms, t_facesplit_ms, t_recompress_ms, t_urv_ms;
   /* kernel timing while profiling is on (nudft2_set_profiling), per class:
    * 0 = exact FP64 apply, 1 = FP32 matrix-core GEMM, 2 = FP64 matrix-core
@@ -104,24 +107,33 @@ typedef struct {
   double kernel_ms[4];
   double kernel_flops[4];
   int64_t kernel_launches[4];
+  int64_t peak_bytes;     /* most device bytes the plan's arena held at once
+                             (factors plus the factorization's workspaces)  */
 } nudft2_info;
 
 void nudft2_default_opts(nudft2_opts* opts);
 
-/* Plan for one problem.  points: HOST pointer to M interleaved (x_j, y_j)
- * doubles, any finite values (wrapped into [0,1)); copied, caller keeps
- * ownership.  Requires nx, ny even and >= 2, M >= nx*ny (Section 1), all
- * points finite, opts valid (eps in (0,1), leaf >= 2).  Bins the points into
- * the quadtree and uploads them; does not factor.  *out is set only on
- * success.  Errors: E_INVAL, E_DEVICE, E_NOMEM. */
+/* Plan for one problem (Section 1: the M >= N sample points of the type-II
+ * problem; Section 3.2 and Definition 3.2: the face-splitting product of the
+ * two 1D trees that the plan builds).  points: DEVICE pointer to M
+ * interleaved (x_j, y_j) doubles, any finite values (wrapped into [0,1));
+ * the plan copies them (caller keeps ownership; the copy direction is taken
+ * from the address, so a host pointer is accepted too).  Requires nx, ny even
+ * and >= 2, M >= nx*ny, all points finite, opts valid (eps in (0,1),
+ * leaf >= 2).  Bins the points into the quadtree (host counting sorts after
+ * one device-to-host copy) and uploads them in tree order; does not factor.
+ * Synchronises with opts.stream.  *out is set only on success.  Errors:
+ * E_INVAL, E_DEVICE, E_NOMEM. */
 nudft2_status nudft2_plan(nudft2_plan_t* out, const double* points, int64_t M,
                           int32_t nx, int32_t ny, const nudft2_opts* opts);
 
 /* Plan for nprob independent problems solved together (one launch per tree
- * level for all problems).  points: HOST, concatenated; problem p owns
- * points[2*m_off[p] .. 2*m_off[p+1]).  m_off, nx, ny: HOST arrays (nprob+1,
- * nprob, nprob).  Right-hand sides and solutions of a batch plan are
- * concatenated in problem order: f of problem p at f + 2*m_off[p] (per
+ * level for all problems; the reuse of one factorization across right-hand
+ * sides, Section 5, extended across problems).  points: DEVICE (as in
+ * nudft2_plan), concatenated; problem p owns points[2*m_off[p] ..
+ * 2*m_off[p+1]).  m_off, nx, ny: HOST arrays (nprob+1, nprob, nprob).
+ * Right-hand sides and solutions of a batch plan are concatenated in
+ * problem order: f of problem p at f + 2*m_off[p] (per
  * right-hand side stride 2*m_off[nprob] doubles), c of problem p at an offset
  * of sum_{q<p} nx[q]*ny[q] complex entries. */
 nudft2_status nudft2_plan_batch(nudft2_plan_t* out, int32_t nprob,
@@ -129,10 +141,12 @@ nudft2_status nudft2_plan_batch(nudft2_plan_t* out, int32_t nprob,
                                 const int32_t* nx, const int32_t* ny,
                                 const nudft2_opts* opts);
 
-/* Build the HSS approximation of G (1D compression, face-splitting assembly,
- * recompression) and its URV factorization.  Idempotent.  Synchronises with
- * the stream (ranks are read back per level).  Errors: E_NOMEM, E_SINGULAR,
- * E_DEVICE. */
+/* The offline stage of Algorithm 4.1: build the HSS approximation of G
+ * (1D compression of G^x, G^y at eps/10, Section 2.5; face-splitting
+ * assembly, Theorem 3.3; recompression at eps, Section 2.3) and its URV
+ * factorization (Section 2.4).  The plan owns every factor.  Idempotent.
+ * Synchronises with the stream (ranks are read back per level).  Errors:
+ * E_NOMEM, E_SINGULAR, E_DEVICE. */
 nudft2_status nudft2_factor(nudft2_plan_t plan);
 
 /* Least-squares solve for nrhs right-hand sides.  f: DEVICE, nrhs x M
@@ -155,9 +169,11 @@ nudft2_status nudft2_solve(nudft2_plan_t plan, const double* f, double* c,
 nudft2_status nudft2_set_solve_opts(nudft2_plan_t plan, double ir_tol, int32_t ir_maxit,
                                     int32_t refine);
 
-/* Adjoint of the least-squares solution operator: w = (A^+)^* g =
- * A (A^*A)^{-1} g for g of shape nrhs x nx x ny, w of shape nrhs x M (DEVICE,
- * caller-owned).  (A^*A)^{-1} g is obtained by refinement on the normal
+/* Adjoint of the least-squares solution operator (Section 4.1 applies the
+ * adjoint of the factored solution operator, a 2D FFT followed by the
+ * adjoint URV solve; here it preconditions the normal equations):
+ * w = (A^+)^* g = A (A^*A)^{-1} g for g of shape nrhs x nx x ny, w of shape
+ * nrhs x M (DEVICE, caller-owned).  (A^*A)^{-1} g is obtained by refinement on the normal
  * equations preconditioned by S S^* (S = F^{-1} H^+ the factored solution
  * operator and S^* its adjoint sweep), stopped at ||dz||/||z|| <= ir_tol
  * (at least one step even when ir_maxit == 0).  This is the map that gives
@@ -187,7 +203,9 @@ nudft2_status nudft2_lsq_backward(nudft2_plan_t plan, const double* f, const dou
 nudft2_status nudft2_apply(nudft2_plan_t plan, const double* c, double* f,
                            int32_t nrhs);
 
-/* c = A^* f exactly in FP64.  f: DEVICE nrhs x M, c: DEVICE nrhs x nx x ny. */
+/* c = A^* f exactly in FP64 (the adjoint of the Section 1 sum, which the
+ * least-squares iterations of Section 4.1 apply).  f: DEVICE nrhs x M, c:
+ * DEVICE nrhs x nx x ny.  Does not need the factorization.  Errors: E_INVAL. */
 nudft2_status nudft2_apply_adj(nudft2_plan_t plan, const double* f, double* c,
                                int32_t nrhs);
 

@@ -6,7 +6,7 @@ direct solver for the 2D type-II inverse NUDFT based on HSS matrices"):
 
 * ``nudft``  -- the transform itself (Section 1, eq. for the 2D type-II NUDFT
   and its matrix), its adjoint, the dense least-squares solution, and the
-  transformed matrix G = A F^{-1} with its closed-form kernel (Section 2.4,
+  transformed matrix G = A F^{-1} with its closed-form kernel (Section 2.5,
   Cauchy-like entries; Section 3.1, separable 2D kernel).
 * ``hss``    -- a small dense-friendly reference of the HSS machinery: HSS
   expansion, 1D HSS by truncated SVD, the face-splitting product generators

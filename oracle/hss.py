@@ -229,7 +229,7 @@ def matvec(h: HSS, x: np.ndarray, M: int) -> np.ndarray:
 
 def hss_1d(x: np.ndarray, n: int, L: int, tol: float) -> HSS:
     """Nested orthonormal bases for the HSS blocks G(J_tau, K_tau^c) and
-    G(J_tau^c, K_tau)^* of the 1D transformed matrix (Section 2.4), bottom up;
+    G(J_tau^c, K_tau)^* of the 1D transformed matrix (Section 2.5), bottom up;
     leaves keep the exact kernel block as D.  tol = 0 keeps every nonzero
     singular direction (an exact representation up to round-off)."""
     t = tree_1d(x, n, L)

@@ -8,7 +8,7 @@ paper:
   centred frequencies (see the package docstring for the phase relation).
 * lstsq: Section 1, the inverse problem min_c ||A c - f||_2, solved by a dense
   Householder QR (the O(M N^2) method the paper cites as the dense baseline).
-* kernel_1d / dense_G: Section 2.4 (1D Cauchy-like matrix G = A F^{-1}, eq. for
+* kernel_1d / dense_G: Section 2.5 (1D Cauchy-like matrix G = A F^{-1}, eq. for
   its entries) and Section 3.1 (separable 2D kernel, G = G^x face-split G^y),
   with the paper's 0-based frequencies.
 """
@@ -133,7 +133,7 @@ def kernel_1d(x: np.ndarray, n: int, cols: np.ndarray | None = None) -> np.ndarr
     """G^x(j, l) for G^x = A^x (F^x)^{-1}, F(k, l) = exp(-2 pi i k l / n).
 
     Entry: (1/n) sum_{k<n} exp(-2 pi i k theta), theta = x_j - l/n (mod 1),
-    which is the Cauchy-like ratio of Section 2.4, ((g/xi)^n - 1)/(n((g/xi)-1))
+    which is the Cauchy-like ratio of Section 2.5, ((g/xi)^n - 1)/(n((g/xi)-1))
     with g = exp(-2 pi i x_j), xi = exp(-2 pi i l/n), and equals 1 where
     g = xi.  It is evaluated in the Dirichlet form
         exp(-i pi (n-1) theta) sin(pi n theta) / (n sin(pi theta)),
@@ -162,7 +162,7 @@ def kernel_1d(x: np.ndarray, n: int, cols: np.ndarray | None = None) -> np.ndarr
 
 
 def dft_matrix(n: int) -> np.ndarray:
-    """F(k, l) = exp(-2 pi i k l / n) (Section 2.4); the phase k l / n is
+    """F(k, l) = exp(-2 pi i k l / n) (Section 2.5); the phase k l / n is
     reduced mod 1 in exact integer arithmetic."""
     k = np.arange(n, dtype=np.int64)
     kl = np.mod(np.multiply.outer(k, k), n).astype(np.float64) / n

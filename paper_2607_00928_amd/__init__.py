@@ -39,13 +39,20 @@ def _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph
     return o
 
 
-def _host_points(points) -> np.ndarray:
+def _device_points(points, dev) -> torch.Tensor:
+    """The points as a contiguous float64 (M, 2) tensor on dev (the library
+    takes a device pointer and copies the points itself)."""
     if isinstance(points, torch.Tensor):
-        points = points.detach().cpu().numpy()
-    pts = np.ascontiguousarray(points, dtype=np.float64)
-    if pts.ndim != 2 or pts.shape[1] != 2:
+        t = points.detach()
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(points, dtype=np.float64))
+    if t.dim() != 2 or t.shape[1] != 2:
         raise ValueError("points must have shape (M, 2)")
-    return pts
+    t = t.to(device=dev, dtype=torch.float64).contiguous()
+    # the library reads the points on the plan's stream, which may differ
+    # from the one this copy ran on
+    torch.cuda.current_stream(dev).synchronize()
+    return t
 
 
 def _current_stream(device) -> int:
@@ -72,7 +79,8 @@ class _PlanBase:
         return dict(nprob=inf.nprob, levels=L,
                     max_rank_u=list(inf.max_rank_u)[:L + 1],
                     max_rank_v=list(inf.max_rank_v)[:L + 1],
-                    factor_bytes=inf.factor_bytes, factor_flops=inf.factor_flops,
+                    factor_bytes=inf.factor_bytes, peak_bytes=inf.peak_bytes,
+                    factor_flops=inf.factor_flops,
                     sweep_bytes=inf.sweep_bytes,
                     t_plan_ms=inf.t_plan_ms, t_compress_ms=inf.t_compress_ms,
                     t_facesplit_ms=inf.t_facesplit_ms,
@@ -184,24 +192,25 @@ class _PlanBase:
 
 
 class Plan(_PlanBase):
-    """One problem: points (M, 2) host array, nx x ny centred frequencies."""
+    """One problem: points (M, 2) float64 (array or tensor; handed to the
+    library in device memory), nx x ny centred frequencies."""
 
     def __init__(self, points, nx: int, ny: int, *, precision="fp32", eps=1e-4,
                  leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0, stream=None,
                  mem_cap=0, device=None, graph=False):
-        pts = _host_points(points)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        pts = _device_points(points, dev)
         self.M = pts.shape[0]
         self.nx, self.ny = int(nx), int(ny)
         self.N_shape = (self.nx, self.ny)
-        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         if stream is None:
             stream = _current_stream(dev)
         o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph)
         self.ir_tol, self.ir_maxit, self.refine = float(ir_tol), int(ir_maxit), int(refine)
         h = C.c_void_p()
         with torch.cuda.device(dev):
-            st = lib.nudft2_plan(C.byref(h), _lib.dptr(pts), self.M, self.nx, self.ny,
-                                 C.byref(o))
+            st = lib.nudft2_plan(C.byref(h), C.c_void_p(pts.data_ptr()), self.M, self.nx,
+                                 self.ny, C.byref(o))
         check(st, "nudft2_plan")
         self._handle = h
         self.points = pts
@@ -214,17 +223,18 @@ class BatchPlan(_PlanBase):
     def __init__(self, points_list, nx_list, ny_list, *, precision="fp32",
                  eps=1e-4, leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0,
                  stream=None, mem_cap=0, device=None, graph=False):
-        pts = [_host_points(p) for p in points_list]
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        pts = [_device_points(p, dev) for p in points_list]
         m_off = np.zeros(len(pts) + 1, dtype=np.int64)
         m_off[1:] = np.cumsum([p.shape[0] for p in pts])
-        allp = np.ascontiguousarray(np.concatenate(pts, axis=0))
+        allp = torch.cat(pts, dim=0).contiguous()
+        torch.cuda.current_stream(dev).synchronize()
         nx = np.ascontiguousarray(nx_list, dtype=np.int32)
         ny = np.ascontiguousarray(ny_list, dtype=np.int32)
         self.M = int(m_off[-1])
         self.m_off = m_off
         self.n_off = np.concatenate([[0], np.cumsum(nx.astype(np.int64) * ny)])
         self.N_shape = (int(self.n_off[-1]),)
-        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         if stream is None:
             stream = _current_stream(dev)
         o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph)
@@ -232,7 +242,7 @@ class BatchPlan(_PlanBase):
         h = C.c_void_p()
         with torch.cuda.device(dev):
             st = lib.nudft2_plan_batch(
-                C.byref(h), len(pts), _lib.dptr(allp),
+                C.byref(h), len(pts), C.c_void_p(allp.data_ptr()),
                 m_off.ctypes.data_as(C.POINTER(C.c_int64)),
                 nx.ctypes.data_as(C.POINTER(C.c_int32)),
                 ny.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(o))

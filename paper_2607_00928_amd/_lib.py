@@ -57,6 +57,7 @@ class Info(C.Structure):
         ("kernel_ms", C.c_double * 4),
         ("kernel_flops", C.c_double * 4),
         ("kernel_launches", C.c_int64 * 4),
+        ("peak_bytes", C.c_int64),
     ]
 
 
@@ -81,9 +82,9 @@ def _load():
     FP = C.POINTER(C.c_float)
     sig = {
         "nudft2_default_opts": (None, [C.POINTER(Opts)]),
-        "nudft2_plan": (C.c_int, [C.POINTER(P), DP, C.c_int64, C.c_int32, C.c_int32,
+        "nudft2_plan": (C.c_int, [C.POINTER(P), P, C.c_int64, C.c_int32, C.c_int32,
                                   C.POINTER(Opts)]),
-        "nudft2_plan_batch": (C.c_int, [C.POINTER(P), C.c_int32, DP, I64P, I32P, I32P,
+        "nudft2_plan_batch": (C.c_int, [C.POINTER(P), C.c_int32, P, I64P, I32P, I32P,
                                         C.POINTER(Opts)]),
         "nudft2_factor": (C.c_int, [P]),
         "nudft2_solve": (C.c_int, [P, P, P, C.c_int32, C.POINTER(SolveInfo)]),

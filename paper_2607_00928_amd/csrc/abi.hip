@@ -328,6 +328,7 @@ nudft2_status nudft2_apply_adj(nudft2_plan_t plan, const double* f, double* c, i
     ND_CHECK(plan != nullptr && f != nullptr && c != nullptr, NUDFT2_E_INVAL, "null pointer");
     ND_CHECK(nrhs > 0, NUDFT2_E_INVAL, "nrhs must be positive");
     Plan* P = reinterpret_cast<Plan*>(plan);
+    PlanProf pp(P);
     apply_adj(P, reinterpret_cast<const double2*>(f), reinterpret_cast<double2*>(c), nrhs,
               P->stream);
   });
@@ -341,6 +342,7 @@ nudft2_status nudft2_get_info(nudft2_plan_t plan, nudft2_info* info) {
     P->prof.collect();
     *info = P->info;
     info->factor_bytes = (int64_t)P->arena.bytes;
+    info->peak_bytes = (int64_t)P->arena.peak;
     for (int i = 0; i < KC_COUNT; ++i) {
       info->kernel_ms[i] = P->prof.ms[i];
       info->kernel_flops[i] = P->prof.flops[i];

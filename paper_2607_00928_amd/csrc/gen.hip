@@ -1,6 +1,6 @@
 // Kernel-tile generation and face-split generator assembly.
 //
-// * G^x(j, l): the transformed 1D NUDFT matrix A^x (F^x)^{-1} (Section 2.4),
+// * G^x(j, l): the transformed 1D NUDFT matrix A^x (F^x)^{-1} (Section 2.5),
 //   entry (1/n) sum_{k<n} exp(-2 pi i k theta), theta = x_j - l/n, evaluated
 //   in the Dirichlet form exp(-i pi (n-1) theta) sin(pi n theta) /
 //   (n sin(pi theta)) with exact reduction of n theta and (n-1) theta, and

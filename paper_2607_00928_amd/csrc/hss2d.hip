@@ -20,6 +20,7 @@
 // S^2 in the paper).  The updates B <- P^H B Q, R <- P^H R, W <- Q^H W,
 // U <- U P, V <- V Q and R_child <- R_child P, W_child <- W_child Q follow the
 // paper.
+#include <chrono>
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -77,6 +78,7 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
               HSS2<T>& H, int stages) {
   TmpScope scope_(cx);
   Plan* P = cx.P;
+  const auto t_start = std::chrono::steady_clock::now();
   Builder<T> bd(cx, H);
   const int np = (int)P->probs.size();
   H.probs.assign(np, Prob2<T>());
@@ -271,6 +273,10 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
     cx.pool.sync_reset();
     P->arena.check("face-split assembly");
   }
+  // the assembly ends with a synchronisation, so this is its device time
+  P->info.t_facesplit_ms = std::chrono::duration<double, std::milli>(
+                               std::chrono::steady_clock::now() - t_start)
+                               .count();
 
   // ------------------------------------------------ stage 1 (bottom-up)
   if (stages >= 1) {

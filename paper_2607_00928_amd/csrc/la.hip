@@ -1,7 +1,8 @@
 // Batched complex GEMM / Householder QR / pivoted Cholesky / triangular solve
 // for gfx950.  GEMM-shaped work runs on the 16x16x4 matrix cores (FP64 or
-// FP32 with FP32 accumulation): a complex product is four real MFMAs,
-// Cr += Ar Br - Ai Bi and Ci += Ar Bi + Ai Br.
+// FP32 with FP32 accumulation): a complex product is three real MFMA
+// products in Gauss's form, p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi),
+// with Cr = p1 - p2 and Ci = p3 - p1 - p2 formed at the store.
 #include <algorithm>
 #include <cstdlib>
 #include <cstdio>
@@ -756,15 +757,24 @@ __global__ void gemm_prescale_kernel(DS descs) {
 // this multi-die part); each thread waits for all its memory operations to
 // complete before the workgroup arrives, which orders the exchanged stores
 // before the arrival count.
+//
+// The wait is bounded (2^20 polls, well under a second) and gives up at once
+// once err is set, by this or any other workgroup: after one timeout the
+// panel's remaining barriers fall through instead of each waiting its full
+// bound, and the host reports the error after the launch.
 __device__ inline void group_barrier(unsigned* cnt, unsigned target, int* err) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned it = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (++it > (1u << 26)) {
+    bool failed = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    while (!failed &&
+           __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if ((++it & 255) == 0 &&
+          (it > (1u << 20) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
         atomicExch(err, 1);
+        failed = true;
         break;
       }
       __builtin_amdgcn_s_sleep(1);

@@ -1,5 +1,7 @@
 // Plan construction: validation, point binning (quadtree and 1D trees) and
-// upload.  Binning is host code (the points arrive in host memory).
+// upload.  Binning is host code: the caller's points (device memory) are
+// copied to the host once, binned by counting sorts, and uploaded in tree
+// order.
 //
 // Trees (Definitions 2.1 and 3.2): both 1D trees bisect [0, 1) dyadically to
 // a common depth L = ceil(log2(max(nx, ny) / leaf)); node (l, a) of the x tree
@@ -13,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <numeric>
 
@@ -315,6 +318,8 @@ static void validate(int nprob, const double* points, const int64_t* m_off,
                      const int32_t* nx, const int32_t* ny, const nudft2_opts* o) {
   ND_CHECK(nprob >= 1, NUDFT2_E_INVAL, "nprob must be >= 1");
   ND_CHECK(points && m_off && nx && ny, NUDFT2_E_INVAL, "null pointer argument");
+  for (int p = 0; p < nprob; ++p)
+    ND_CHECK(m_off[p + 1] >= m_off[p], NUDFT2_E_INVAL, "m_off must be non-decreasing");
   ND_CHECK(m_off[0] == 0, NUDFT2_E_INVAL, "m_off[0] must be 0");
   ND_CHECK(o != nullptr, NUDFT2_E_INVAL, "null options");
   ND_CHECK(o->precision == 0 || o->precision == 1, NUDFT2_E_INVAL, "precision must be 0 or 1");
@@ -333,20 +338,37 @@ static void validate(int nprob, const double* points, const int64_t* m_off,
     int L = tree_depth(nx[p], ny[p], o->leaf);
     ND_CHECK(L <= 10, NUDFT2_E_INVAL, "tree too deep (nx/leaf > 1024)");
   }
-  int64_t Mt = m_off[nprob];
-  for (int64_t j = 0; j < 2 * Mt; ++j)
-    ND_CHECK(std::isfinite(points[j]), NUDFT2_E_INVAL, "non-finite point coordinate");
 }
 
-Plan* make_plan(int nprob, const double* points, const int64_t* m_off,
+static double now_ms_plan() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// points_dev: the caller's points (device memory; the copy direction is
+// taken from the address, so host memory works as well).  They are copied
+// to the host once for the O(M) integer binning, then uploaded in tree order.
+Plan* make_plan(int nprob, const double* points_dev, const int64_t* m_off,
                 const int32_t* nx, const int32_t* ny, const nudft2_opts* opts) {
-  validate(nprob, points, m_off, nx, ny, opts);
+  const double t0 = now_ms_plan();
+  validate(nprob, points_dev, m_off, nx, ny, opts);
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
     throw Error(NUDFT2_E_DEVICE, "no HIP device available");
   }
+  const int64_t Mt = m_off[nprob];
+  std::vector<double> host_pts((size_t)2 * Mt);
+  if (Mt > 0) {
+    ND_HIP(hipMemcpyAsync(host_pts.data(), points_dev, sizeof(double) * 2 * Mt, hipMemcpyDefault,
+                          (hipStream_t)opts->stream));
+    ND_HIP(hipStreamSynchronize((hipStream_t)opts->stream));
+  }
+  const double* points = host_pts.data();
+  for (int64_t j = 0; j < 2 * Mt; ++j)
+    ND_CHECK(std::isfinite(points[j]), NUDFT2_E_INVAL, "non-finite point coordinate");
   std::unique_ptr<Plan> P(new Plan());
   P->opts = *opts;
   P->stream = (hipStream_t)opts->stream;
@@ -412,6 +434,7 @@ Plan* make_plan(int nprob, const double* points, const int64_t* m_off,
   ND_HIP(hipStreamSynchronize(s));
   P->info.nprob = nprob;
   P->info.levels = P->Lmax;
+  P->info.t_plan_ms = now_ms_plan() - t0;
   return P.release();
 }
 

@@ -88,6 +88,28 @@ __global__ void sumsq_kernel(const double2* __restrict__ x, int64_t n, int64_t l
   if (threadIdx.x == 0) atomicAdd(out + r, red[0] + red[1] + red[2] + red[3]);
 }
 
+// per right-hand side and problem sum of squares (atomics): x is nrhs rows of
+// ldx entries, problem p's segment of a row is [m0, m0 + M) (M-vectors) or
+// [c0, c0 + nx ny) (N-vectors, ncoef); out[r * nprob + p]
+__global__ void seg_sumsq_kernel(const double2* __restrict__ x, int64_t ldx,
+                                 const ApplyProb* __restrict__ ap, int nprob, int ncoef,
+                                 double* __restrict__ out) {
+  const int p = blockIdx.y % nprob, r = blockIdx.y / nprob;
+  const ApplyProb q = ap[p];
+  const int64_t o = ncoef ? q.c0 : q.m0;
+  const int64_t n = ncoef ? (int64_t)q.nx * q.ny : q.M;
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double2 v = x[r * ldx + o + i];
+    s += v.x * v.x + v.y * v.y;
+  }
+  s = warp_sum(s);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out + r * nprob + p, red[0] + red[1] + red[2] + red[3]);
+}
+
 // y = a x + b y (complex vectors, real a, b)
 __global__ void axpby_kernel(double a, const double2* __restrict__ x, double b,
                              double2* __restrict__ y, int64_t n) {
@@ -244,8 +266,8 @@ void factor_t(Plan* P) {
   cx.pool.check_flag();
   double t3 = now_ms();
   P->info.t_compress_ms = t1 - t0;
-  P->info.t_recompress_ms = t2 - t1;   // face-split assembly + recompression
-  P->info.t_facesplit_ms = 0;
+  // build_2d timed its face-split assembly; the rest is recompression
+  P->info.t_recompress_ms = std::max(0.0, t2 - t1 - P->info.t_facesplit_ms);
   P->info.t_urv_ms = t3 - t2;
   P->info.sweep_bytes = urv_sweep_bytes<T>(*H);
   P->hss.reset(H.release());
@@ -360,7 +382,12 @@ struct SolveCtx {
   double* nrm2;
   double* scale;
   double* inv;
-  double* red;   // 5 nrhs slots of norms read back by the drivers
+  // norms read back by the drivers: 5 slots of nrhs x nprob squared norms,
+  // one per right-hand side and problem, so that every problem of a batch
+  // plan meets the stopping test on its own
+  double* red;
+  int nprob;
+  int64_t mmax = 0, nmax = 0;   // longest problem segment of an M- / N-vector
   // graph of the iteration body: recorded on a private stream by a context of
   // its own that keeps its descriptors and temporaries while the graph lives
   bool use_graph;
@@ -376,7 +403,12 @@ struct SolveCtx {
     w.cw = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * P->Ntot * nrhs);
     w.chat = (double2*)cx.tmp_alloc(sizeof(double2) * P->Ntot * nrhs);
     w.tmp = (double2*)cx.tmp_alloc(sizeof(double2) * P->Ntot * nrhs);
-    w.sums = (double*)cx.tmp_alloc(sizeof(double) * 8 * nrhs);
+    nprob = (int)P->probs.size();
+    for (auto& q : P->probs) {
+      mmax = std::max(mmax, q.M);
+      nmax = std::max(nmax, q.N());
+    }
+    w.sums = (double*)cx.tmp_alloc(sizeof(double) * (3 + 5 * (size_t)nprob) * nrhs);
     nrm2 = w.sums;
     scale = w.sums + nrhs;
     inv = w.sums + 2 * nrhs;
@@ -427,15 +459,26 @@ struct SolveCtx {
     normalise(k, v, P->Ntot);
     hss_inverse_adj<T>(k, H, v, out, nrhs, w, scale, inv);
   }
-  // squared norms per right-hand side into red + i nrhs (no wait)
+  // squared norms per right-hand side and problem into slot i of red (no
+  // wait); x is an M-vector (n == Mtot) or an N-vector (n == Ntot).  Every
+  // problem has M_p >= N_p, so Mtot == Ntot only when M_p == N_p for all p,
+  // and then both segmentations coincide.
   void norm_into(Ctx& k, int i, const double2* x, int64_t n) {
-    sumsq(k.s, x, n, n, nrhs, red + i * nrhs);
+    double* out = red + (size_t)i * nrhs * nprob;
+    const bool coef = n != P->Mtot;
+    hipLaunchKernelGGL(zero_d_kernel, dim3(1), dim3(256), 0, k.s, out, (int64_t)nrhs * nprob);
+    const int64_t len = coef ? nmax : mmax;
+    hipLaunchKernelGGL(seg_sumsq_kernel,
+                       dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_for(len), 256)),
+                            (unsigned)(nrhs * nprob)),
+                       dim3(256), 0, k.s, x, n, P->d_aprob, nprob, coef ? 1 : 0, out);
+    ND_HIP(hipGetLastError());
   }
   // read back the first cnt norm slots (synchronises); the eager pool is
   // recycled here
   std::vector<double> read_norms(int cnt) {
-    std::vector<double> h(cnt * nrhs);
-    ND_HIP(hipMemcpyAsync(h.data(), red, sizeof(double) * cnt * nrhs, hipMemcpyDeviceToHost,
+    std::vector<double> h((size_t)cnt * nrhs * nprob);
+    ND_HIP(hipMemcpyAsync(h.data(), red, sizeof(double) * h.size(), hipMemcpyDeviceToHost,
                           cx.s));
     ND_HIP(hipStreamSynchronize(cx.s));
     cx.pool.sync_reset();
@@ -488,13 +531,21 @@ struct SolveCtx {
     }
     ND_HIP(hipGraphLaunch(gexec, cx.s));
   }
-  // worst ||a_r|| / ||b_r|| over the right-hand sides of a two-vector norm read
+  // worst ||a|| / ||b|| over the right-hand sides and problems of two norm
+  // slots (a problem whose b vanishes counts as converged when a does too)
   double worst_ratio(const std::vector<double>& h, int ia, int ib) const {
     double worst = 0;
-    for (int r = 0; r < nrhs; ++r)
-      worst = std::max(worst, std::sqrt(h[ia * nrhs + r]) /
-                                  std::max(std::sqrt(h[ib * nrhs + r]), 1e-300));
+    const size_t sl = (size_t)nrhs * nprob;
+    for (size_t e = 0; e < sl; ++e)
+      worst = std::max(worst, std::sqrt(h[ia * sl + e]) /
+                                  std::max(std::sqrt(h[ib * sl + e]), 1e-300));
     return worst;
+  }
+  // ||x|| of right-hand side r over all problems from one norm slot
+  double total(const std::vector<double>& h, int i, int r) const {
+    double t = 0;
+    for (int p = 0; p < nprob; ++p) t += h[((size_t)i * nrhs + r) * nprob + p];
+    return std::sqrt(t);
   }
 };
 
@@ -527,7 +578,7 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
   double2* tM = ne ? sc.vecM() : nullptr;
   sc.copy(f, rr, M);
   sc.zero(c, N);
-  const double fn = std::sqrt(sc.norms2({{f, M}})[0]);
+  const double fn = sc.total(sc.norms2({{f, M}}), 0, 0);
   int it = 1;
   double upd = 0, res = 1;
   bool conv = false;
@@ -564,7 +615,7 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
     sc.run(body);
     std::vector<double> h = sc.read_norms(3);
     upd = sc.worst_ratio(h, 0, 1);
-    res = std::sqrt(h[2 * nrhs]) / std::max(fn, 1e-300);
+    res = sc.total(h, 2, 0) / std::max(fn, 1e-300);
     conv = upd <= P->opts.ir_tol;
   }
   report(info, it, upd, res);

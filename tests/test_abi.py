@@ -50,11 +50,8 @@ def test_invalid_arguments_rejected_before_device_work():
     assert _plan(pts, 63, 8, 8)[0] == 1            # M < N
     assert _plan(pts, pr.M, 7, 8)[0] == 1          # odd
     assert _plan(pts, pr.M, 0, 8)[0] == 1
-    bad = pts.copy()
-    bad[5, 1] = np.nan
-    assert _plan(bad, pr.M, 8, 8)[0] == 1
-    bad[5, 1] = np.inf
-    assert _plan(bad, pr.M, 8, 8)[0] == 1
+    # (non-finite coordinates are found after the points are copied from the
+    # device; tests/test_gpu_status.py checks that case)
     o = _lib.default_opts()
     o.eps = 0.0
     assert _plan(pts, pr.M, 8, 8, o)[0] == 1

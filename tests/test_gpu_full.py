@@ -63,9 +63,13 @@ def test_fp64_128_subblocks_of_hss_approximation():
 
 
 def test_fp64_128_direct_solve_small_eps():
-    """FP64 factors at eps = 1e-10 without refinement: the direct solution is
-    within the approximation error of the least-squares solution, which the
-    1e-12 noise keeps within ~1e-12 of c_true."""
+    """FP64 factors at eps = 1e-10 without refinement.  The plain FP64 direct
+    solve does not reach 1e-10: its rank decisions are taken on FP64 Gram
+    matrices, whose rounding (unit roundoff times the trace) hides singular
+    values below about sqrt(1.1e-16) = 1e-8 of the largest, so the HSS form
+    is accurate to about 1e-9 however small eps is (measured 2.2e-9 here).
+    The FP64 path meets 1e-10 with refinement (test_fp64_128_consistent_pin,
+    5e-13).  This test pins the plain direct solve at that Gram floor."""
     pr = config_problem("fp64_128")
     f0 = onu.apply(pr.points, pr.c_true)
     eta = pr.noise_dir * (pr.noise_rel * np.linalg.norm(f0) / np.linalg.norm(pr.noise_dir))
@@ -76,18 +80,18 @@ def test_fp64_128_direct_solve_small_eps():
     e = rel(c, pr.c_true)
     info = plan.info()
     print(f"fp64_128 direct, eps 1e-10: {e:.2e}, ranks U {info['max_rank_u']}")
-    assert e < 1e-8
+    assert e < 5e-9
     plan.close()
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_n512_factor_refined_solve(precision):
-    """n = 512 x 512, M = 1024^2, jitter 0.4, eps = 1e-2, refinement to 1e-12
-    (the benchmark's configuration)."""
+    """n = 512 x 512, M = 1024^2, jitter 0.4, eps = 1e-2, refinement to
+    ||dc||/||c|| <= 1e-10: the configuration the benchmark times."""
     pr = config_problem("n512")
     nx = ny = 512
     ct = torch.from_numpy(pr.c_true).to(DEV)
-    plan = nd.Plan(pr.points, nx, ny, precision=precision, eps=1e-2, ir_tol=1e-12, ir_maxit=60)
+    plan = nd.Plan(pr.points, nx, ny, precision=precision, eps=1e-2, ir_tol=1e-10, ir_maxit=60)
     f = plan.apply(ct)
     rng = np.random.default_rng(12)
     rows = np.sort(rng.choice(pr.M, 2048, replace=False))

@@ -18,6 +18,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def direct_bound(eps, prec):
+    """Bound on the relative error of the direct (unrefined) solve: eps plus a
+    rounding floor of the working precision (2e-6 for FP32: about 30 unit
+    roundoffs through the sweep's triangular solves; 1e-13 for FP64)."""
+    return eps + (2e-6 if prec == "fp32" else 1e-13)
+
+
 @pytest.mark.parametrize("nx,ny,mx,my,delta,seed", [
     (32, 32, 64, 64, 0.25, 1),      # the small workload
     (48, 32, 96, 64, 0.4, 5),       # ragged leaves, non-square
@@ -45,9 +52,11 @@ def test_direct_and_refined(nx, ny, mx, my, delta, seed, prec, eps):
     plan.close()
     print(f"{nx}x{ny} {prec} eps={eps:.0e}: direct {e0:.2e}, refined {e1:.2e} "
           f"({si['iterations']} its), ranks U {info['max_rank_u']} V {info['max_rank_v']}")
-    # FP32 factors: the direct error can exceed eps by the amplification of
-    # single-precision rounding in the triangular solves; refinement removes it.
-    assert e0 < (30 * eps if prec == "fp64" else max(30 * eps, 0.2))
+    # The direct error tracks eps (measured 0.14-0.31 eps on these cases, the
+    # same in both precisions); the floor is the working precision's rounding
+    # through the URV sweep (measured 3e-7 FP32, 7e-16 FP64 on the single-node
+    # tree, where the HSS form is exact).
+    assert e0 < direct_bound(eps, prec)
     assert e1 < 1e-10
 
 

@@ -20,7 +20,7 @@ def grid_points(mx, my):
 
 
 def test_apply_exact_grid_is_fft2():
-    # Section 2 (related work): on the uniform grid x = p/n the transform is a
+    # Section 1.1 (related work): on the uniform grid x = p/n the transform is a
     # 2D DFT.  With centred k the sum picks up the sign (-1)^(p+q).
     nx, ny = 8, 6
     rng = np.random.default_rng(0)
@@ -146,7 +146,7 @@ def test_lstsq_matches_pinv_and_normal_equations():
 
 @pytest.mark.parametrize("n", [8, 16, 32])
 def test_kernel_is_rowwise_inverse_dft(n):
-    # G^x = A^x F^{-1} (Section 2.4): row-wise inverse FFT of the 0-based
+    # G^x = A^x F^{-1} (Section 2.5): row-wise inverse FFT of the 0-based
     # NUDFT matrix equals the closed-form kernel.
     rng = np.random.default_rng(n)
     x = rng.uniform(0, 1, 50)
