@@ -9,7 +9,10 @@
 // base phase (one sincospi per 16 frequencies) and a per-row step table, each
 // evaluated with exact phase reduction, so entries are accurate to ~2 ulp for
 // any frequency.  The adjoint is the GEMM  C = (A^x)^H diag(f) conj(A^y),
-// split over chunks of points with FP64 atomics into C.
+// split over chunks of points: every (chunk, coefficient tile) workgroup
+// stores its partial tile with plain stores, and a second kernel adds the
+// chunks' partials in chunk order, so the result does not depend on the
+// order in which workgroups run.
 #include "device_util.h"
 #include "plan.h"
 #include "prof.h"
@@ -154,12 +157,15 @@ __global__ __launch_bounds__(256, 2) void apply_fwd_kernel(
 
 constexpr int AT = 64;     // output tile (kx, ky)
 constexpr int AK = 16;     // points per stage
-constexpr int ACHUNK = 2048;
 
-// C[kx][ky] += sum_{j in chunk} conj(Ax[j][kx]) f_j conj(Ay[j][ky])
+// part[(chunk nrhs + rhs) Ntot + c0 + kx ny + ky] =
+//     sum_{j in chunk} conj(Ax[j][kx]) f_j conj(Ay[j][ky])
+// for the chunk of rows [blockIdx.y rows, (blockIdx.y + 1) rows); every entry
+// of the problem's partial vector is stored by exactly one workgroup.
 __global__ __launch_bounds__(256, 2) void apply_adj_kernel(
     const double* __restrict__ pts, const double2* __restrict__ f,
-    double2* __restrict__ c, ApplyProb pr, int64_t Mtot, int64_t Ntot) {
+    double2* __restrict__ part, ApplyProb pr, int64_t Mtot, int64_t Ntot, int64_t rows,
+    int nrhs) {
   __shared__ double Ar[AK][AT + 1], Ai[AK][AT + 1];
   __shared__ double Br[AK][AT + 1], Bi[AK][AT + 1];
   __shared__ double2 bx[AK][AT / 16], by[AK][AT / 16];
@@ -169,10 +175,10 @@ __global__ __launch_bounds__(256, 2) void apply_adj_kernel(
   const int ntx = (pr.nx + AT - 1) / AT;
   const int kx0 = (blockIdx.x % ntx) * AT;
   const int ky0 = (blockIdx.x / ntx) * AT;
-  const int64_t j0 = (int64_t)blockIdx.y * ACHUNK;
+  const int64_t j0 = (int64_t)blockIdx.y * rows;
   const int rhs = blockIdx.z;
   const double2* fp = f + rhs * Mtot + pr.m0;
-  double2* cp = c + rhs * Ntot + pr.c0;
+  double2* cp = part + ((int64_t)blockIdx.y * nrhs + rhs) * Ntot + pr.c0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;   // wave's 32x32 sub-tile
   const int nx = pr.nx, ny = pr.ny;
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(256, 2) void apply_adj_kernel(
       acc3[a][b] = dbl4{0, 0, 0, 0};
     }
 
-  const int64_t jend = min((int64_t)pr.M, j0 + ACHUNK);
+  const int64_t jend = min((int64_t)pr.M, j0 + rows);
   for (int64_t js = j0; js < jend; js += AK) {
     __syncthreads();
     // per-point tables: conj phases (exp(+2 pi i k x)) as conj of expi
@@ -242,18 +248,67 @@ __global__ __launch_bounds__(256, 2) void apply_adj_kernel(
         int kx = kx0 + wm + a * 16 + mrow<double>(lane, v);
         int ky = ky0 + wn + b * 16 + (lane & 15);
         if (kx < nx && ky < ny) {
-          double* dst = reinterpret_cast<double*>(cp + (int64_t)kx * ny + ky);
           const double p1 = acc1[a][b][v], p2 = acc2[a][b][v];
-          atomicAdd(dst, p1 - p2);
-          atomicAdd(dst + 1, acc3[a][b][v] - p1 - p2);
+          cp[(int64_t)kx * ny + ky] = mk<double>(p1 - p2, acc3[a][b][v] - p1 - p2);
         }
       }
 }
 
-__global__ void zero_kernel(double2* p, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = mk<double>(0.0, 0.0);
+// c[rhs][c0 + i] = sum over chunks, in chunk order, of the partials
+__global__ void adj_reduce_kernel(const double2* __restrict__ part, double2* __restrict__ c,
+                                  ApplyProb pr, int nch, int64_t Ntot, int nrhs) {
+  const int64_t n = (int64_t)pr.nx * pr.ny;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / n);
+    const int64_t i = pr.c0 + e % n;
+    double sr = 0.0, si = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+      const double2 v = part[((int64_t)ch * nrhs + r) * Ntot + i];
+      sr += v.x;
+      si += v.y;
+    }
+    c[(int64_t)r * Ntot + i] = mk<double>(sr, si);
+  }
+}
+
+constexpr int64_t ADJ_MIN_ROWS = 2048;   // rows per chunk, at least
+constexpr int64_t ADJ_WG_TARGET = 2048;  // workgroups per problem launch wanted
+
+// Row chunks of the adjoint apply for a plan: as many as fill the device
+// (about ADJ_WG_TARGET workgroups per problem) but no more than the partial
+// buffer of cap bytes holds; 0 when not even one chunk fits.
+int adj_chunks(const Plan* P, int nrhs, size_t cap) {
+  int64_t want = 1;
+  for (const Problem& q : P->probs) {
+    const int64_t tiles = (int64_t)ceil_div(q.nx, AT) * ceil_div(q.ny, AT);
+    const int64_t by_rows = std::max<int64_t>(1, (q.M + ADJ_MIN_ROWS - 1) / ADJ_MIN_ROWS);
+    want = std::max(want, std::min(by_rows, (ADJ_WG_TARGET + tiles - 1) / tiles));
+  }
+  const size_t per_chunk = sizeof(double2) * (size_t)P->Ntot * (size_t)nrhs;
+  const int64_t fit = per_chunk ? (int64_t)(cap / per_chunk) : want;
+  return (int)std::min<int64_t>(want, fit);
+}
+
+// the adjoint apply with its partials in part (nch chunks, see adj_chunks)
+void apply_adj_into(Plan* P, const double2* f, double2* c, int nrhs, double2* part, int nch,
+                    hipStream_t s) {
+  for (const Problem& q : P->probs) {
+    ApplyProb pr{q.m0, q.M, q.c0, q.nx, q.ny};
+    const int tiles = ceil_div(q.nx, AT) * ceil_div(q.ny, AT);
+    // rows per chunk: a multiple of the stage height, nch chunks cover M
+    int64_t rows = std::max<int64_t>(AK, (q.M + nch - 1) / nch);
+    rows = (rows + AK - 1) / AK * AK;
+    const int nchp = std::max(1, ceil_div(q.M, rows));
+    dim3 grid(tiles, nchp, nrhs);
+    hipLaunchKernelGGL(apply_adj_kernel, grid, dim3(256), 0, s, P->pts_user, f, part, pr,
+                       P->Mtot, P->Ntot, rows, nrhs);
+    const int64_t n = q.N() * nrhs;
+    hipLaunchKernelGGL(adj_reduce_kernel,
+                       dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256))),
+                       dim3(256), 0, s, part, c, pr, nchp, P->Ntot, nrhs);
+  }
+  ND_HIP(hipGetLastError());
 }
 
 }  // namespace
@@ -269,18 +324,24 @@ void apply_fwd(Plan* P, const double2* c, double2* f, int nrhs, hipStream_t s) {
   ND_HIP(hipGetLastError());
 }
 
+// Partial buffer of the library path: at most 256 MiB (n = 512: 32 chunks of
+// 4 MiB per right-hand side), held by the plan and grown on demand.
+constexpr size_t ADJ_PART_CAP = size_t(256) << 20;
+
 void apply_adj(Plan* P, const double2* f, double2* c, int nrhs, hipStream_t s) {
-  int64_t n = P->Ntot * nrhs;
-  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)),
-                     dim3(256), 0, s, c, n);
-  for (const Problem& q : P->probs) {
-    ApplyProb pr{q.m0, q.M, q.c0, q.nx, q.ny};
-    int tiles = ceil_div(q.nx, AT) * ceil_div(q.ny, AT);
-    dim3 grid(tiles, ceil_div(q.M, ACHUNK), nrhs);
-    hipLaunchKernelGGL(apply_adj_kernel, grid, dim3(256), 0, s, P->pts_user, f, c,
-                       pr, P->Mtot, P->Ntot);
+  const int nch = std::max(1, adj_chunks(P, nrhs, ADJ_PART_CAP));
+  const size_t need = sizeof(double2) * (size_t)P->Ntot * (size_t)nrhs * (size_t)nch;
+  if (need > P->adj_part_bytes) {
+    if (P->adj_part) {
+      ND_HIP(hipStreamSynchronize(s));   // earlier launches may still read it
+      P->arena.release(P->adj_part);
+    }
+    P->adj_part = nullptr;
+    P->adj_part_bytes = 0;
+    P->adj_part = (double2*)P->arena.alloc(need);
+    P->adj_part_bytes = need;
   }
-  ND_HIP(hipGetLastError());
+  apply_adj_into(P, f, c, nrhs, P->adj_part, nch, s);
 }
 
 }  // namespace nd

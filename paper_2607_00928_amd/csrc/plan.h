@@ -69,6 +69,10 @@ struct Plan {
   int64_t* posy = nullptr;         // 2D-sorted index -> y-sorted index
   int64_t* colperm = nullptr;      // quadtree column index (global) -> natural index (global)
   ApplyProb* d_aprob = nullptr;
+  // partial sums of the adjoint apply (one coefficient vector per row chunk
+  // and right-hand side), grown on demand from the arena
+  double2* adj_part = nullptr;
+  size_t adj_part_bytes = 0;
   int* d_tile_off = nullptr;       // apply row-tile prefix (nprob + 1)
   int apply_tiles = 0;
 
