@@ -209,6 +209,21 @@ nudft2_status nudft2_apply(nudft2_plan_t plan, const double* c, double* f,
 nudft2_status nudft2_apply_adj(nudft2_plan_t plan, const double* f, double* c,
                                int32_t nrhs);
 
+/* nudft2_apply_adj without device allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, result and kernels as
+ * nudft2_apply_adj (the same summation order whenever both split the rows
+ * into the same number of chunks); its partial sums live in a static 64 MiB
+ * device array per GPU instead of plan memory, so it needs
+ * nrhs * nx * ny * 16 bytes <= 64 MiB (summed over the problems of a batch
+ * plan), else E_INVAL; larger inputs run with fewer, longer row chunks.  Each
+ * GPU's array is shared by every call on that GPU and held until the process
+ * ends: calls that overlap on one GPU race (serialise them, e.g. on one
+ * stream).  Runs on the plan's stream with the plan's device current.
+ * Errors: E_INVAL, E_DEVICE. */
+nudft2_status nudft2_apply_adj_noalloc(nudft2_plan_t plan, const double* f, double* c,
+                                       int32_t nrhs);
+
 /* Fill *info (HOST).  Synchronises with the plan's stream. */
 nudft2_status nudft2_get_info(nudft2_plan_t plan, nudft2_info* info);
 

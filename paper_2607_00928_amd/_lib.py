@@ -92,6 +92,7 @@ def _load():
         "nudft2_lsq_backward": (C.c_int, [P, P, P, P, P, P, C.c_int32, C.POINTER(SolveInfo)]),
         "nudft2_apply": (C.c_int, [P, P, P, C.c_int32]),
         "nudft2_apply_adj": (C.c_int, [P, P, P, C.c_int32]),
+        "nudft2_apply_adj_noalloc": (C.c_int, [P, P, P, C.c_int32]),
         "nudft2_get_info": (C.c_int, [P, C.POINTER(Info)]),
         "nudft2_destroy": (C.c_int, [P]),
         "nudft2_set_profiling": (C.c_int, [P, C.c_int32]),

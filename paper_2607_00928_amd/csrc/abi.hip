@@ -334,6 +334,17 @@ nudft2_status nudft2_apply_adj(nudft2_plan_t plan, const double* f, double* c, i
   });
 }
 
+nudft2_status nudft2_apply_adj_noalloc(nudft2_plan_t plan, const double* f, double* c,
+                                       int32_t nrhs) {
+  return guard([&] {
+    ND_CHECK(plan != nullptr && f != nullptr && c != nullptr, NUDFT2_E_INVAL, "null pointer");
+    ND_CHECK(nrhs > 0, NUDFT2_E_INVAL, "nrhs must be positive");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    apply_adj_noalloc(P, reinterpret_cast<const double2*>(f), reinterpret_cast<double2*>(c),
+                      nrhs);
+  });
+}
+
 nudft2_status nudft2_get_info(nudft2_plan_t plan, nudft2_info* info) {
   return guard([&] {
     ND_CHECK(plan != nullptr && info != nullptr, NUDFT2_E_INVAL, "null pointer");

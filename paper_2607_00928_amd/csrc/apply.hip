@@ -13,6 +13,9 @@
 // stores its partial tile with plain stores, and a second kernel adds the
 // chunks' partials in chunk order, so the result does not depend on the
 // order in which workgroups run.
+#include <mutex>
+#include <string>
+
 #include "device_util.h"
 #include "plan.h"
 #include "prof.h"
@@ -322,6 +325,57 @@ void apply_fwd(Plan* P, const double2* c, double2* f, int nrhs, hipStream_t s) {
                      P->d_aprob, (int)P->probs.size(), P->d_tile_off, P->Mtot,
                      P->Ntot);
   ND_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------ no-allocation variant
+// The adjoint apply for callers that cannot allocate device memory keeps its
+// partial sums in this file-scope array.  Its name is only a host-side stand
+// -in: the device address comes from hipGetSymbolAddress, looked up once per
+// device with that device current and kept in scratch_addr.  Every call on a
+// device shares that device's array, so calls that overlap on one device
+// race; nothing in it needs to start at zero (every partial is stored before
+// it is read).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) double2 scratch[NOALLOC_SCRATCH_BYTES / sizeof(double2)];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[MAX_DEVICES] = {};
+
+// device address of this device's scratch (the current device must be dev)
+double2* scratch_addr(int dev) {
+  ND_CHECK(dev >= 0 && dev < MAX_DEVICES, NUDFT2_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      throw Error(NUDFT2_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                       hipGetErrorString(e));
+    }
+    g_scratch_addr[dev] = ptr;
+  }
+  return (double2*)g_scratch_addr[dev];
+}
+}  // namespace
+
+void apply_adj_noalloc(Plan* P, const double2* f, double2* c, int nrhs) {
+  const int nch = adj_chunks(P, nrhs, NOALLOC_SCRATCH_BYTES);
+  ND_CHECK(nch >= 1, NUDFT2_E_INVAL,
+           "nrhs * N * 16 bytes exceeds the 64 MiB scratch of the no-allocation adjoint");
+  int cur = -1;
+  ND_HIP(hipGetDevice(&cur));
+  const bool switch_dev = cur != P->device;
+  if (switch_dev) ND_HIP(hipSetDevice(P->device));
+  try {
+    apply_adj_into(P, f, c, nrhs, scratch_addr(P->device), nch, P->stream);
+  } catch (...) {
+    if (switch_dev) (void)hipSetDevice(cur);
+    throw;
+  }
+  if (switch_dev) ND_HIP(hipSetDevice(cur));
 }
 
 // Partial buffer of the library path: at most 256 MiB (n = 512: 32 chunks of

@@ -90,5 +90,8 @@ Plan* make_plan(int nprob, const double* points, const int64_t* m_off,
 
 void apply_fwd(Plan* P, const double2* c, double2* f, int nrhs, hipStream_t s);
 void apply_adj(Plan* P, const double2* f, double2* c, int nrhs, hipStream_t s);
+// apply_adj on the plan's stream with its partial sums in a static device
+// array (no device allocation); E_INVAL when they do not fit
+void apply_adj_noalloc(Plan* P, const double2* f, double2* c, int nrhs);
 
 }  // namespace nd
