@@ -62,9 +62,17 @@ typedef struct {
   int32_t leaf;       /* columns per dimension of a leaf (paper: 16)           */
   double ir_tol;      /* refinement stop: ||dc||_2 / ||c||_2 <= ir_tol          */
   int32_t ir_maxit;   /* refinement iterations; 0 = plain direct solve          */
-  int32_t refine;     /* 0: refinement c += S(f - Ac) (exact for consistent f);
-                         1: refinement on the normal equations
-                            c += S S^* A^*(f - Ac) (exact least squares for any f) */
+  int32_t refine;     /* with S = F^{-1} H^+ the factored solution operator:
+                         0: iterative refinement c += S(f - Ac) (exact for
+                            consistent f);
+                         1: preconditioned conjugate gradients on the normal
+                            equations A^*A c = A^*f, preconditioner S S^*,
+                            from the direct solution (exact least squares
+                            for any f);
+                         2: plsqr (Section 4.1): LSQR on the left-
+                            preconditioned system S A c = S f, restarted from
+                            the exact residual with FP32 factors (exact for
+                            consistent f) */
   void* stream;       /* hipStream_t; NULL = default stream                     */
   size_t mem_cap;     /* device bytes the plan may hold; 0 = no cap             */
   int32_t graph;      /* 1: each solve call runs its first two refinement
@@ -154,10 +162,12 @@ nudft2_status nudft2_factor(nudft2_plan_t plan);
  * point order.  c: DEVICE, nrhs x nx x ny complex128 output.  With
  * opts.ir_maxit == 0 returns the direct solution c = S f with S = F^{-1} H^+
  * (Algorithm 4.1); otherwise refines in FP64 against the exact A until
- * ||dc||/||c|| <= ir_tol: opts.refine = 0 iterates c += S(f - A c), whose fixed
- * point is the least-squares solution when f is in the range of A; refine = 1
- * iterates c += S S^* A^*(f - A c), whose fixed point is the least-squares
- * solution for any f (E_NOCONV leaves the last iterate in c).  Errors: E_INVAL
+ * ||dc||/||c|| <= ir_tol (per problem and right-hand side): opts.refine = 0
+ * iterates c += S(f - A c), whose fixed point is the least-squares solution
+ * when f is in the range of A; refine = 1 runs conjugate gradients on the
+ * normal equations preconditioned by S S^* (the least-squares solution for
+ * any f); refine = 2 runs the paper's plsqr, LSQR on S A c = S f (Section
+ * 4.1; exact for consistent f).  E_NOCONV leaves the last iterate in c.  Errors: E_INVAL
  * (null pointer, nrhs <= 0), E_STATE (not factored), E_NOCONV, E_DEVICE. */
 nudft2_status nudft2_solve(nudft2_plan_t plan, const double* f, double* c,
                            int32_t nrhs, nudft2_solve_info* info);
@@ -173,10 +183,11 @@ nudft2_status nudft2_set_solve_opts(nudft2_plan_t plan, double ir_tol, int32_t i
  * adjoint of the factored solution operator, a 2D FFT followed by the
  * adjoint URV solve; here it preconditions the normal equations):
  * w = (A^+)^* g = A (A^*A)^{-1} g for g of shape nrhs x nx x ny, w of shape
- * nrhs x M (DEVICE, caller-owned).  (A^*A)^{-1} g is obtained by refinement on the normal
- * equations preconditioned by S S^* (S = F^{-1} H^+ the factored solution
- * operator and S^* its adjoint sweep), stopped at ||dz||/||z|| <= ir_tol
- * (at least one step even when ir_maxit == 0).  This is the map that gives
+ * nrhs x M (DEVICE, caller-owned).  (A^*A)^{-1} g is obtained by conjugate
+ * gradients on the normal equations preconditioned by S S^* (S = F^{-1} H^+
+ * the factored solution operator and S^* its adjoint sweep) from
+ * z = S S^* g, stopped at ||dz||/||z|| <= ir_tol (at least one step even
+ * when ir_maxit < 2).  This is the map that gives
  * dL/df = w for an upstream gradient g = dL/dc of the solution.  Errors:
  * E_INVAL, E_STATE (not factored), E_NOCONV, E_DEVICE. */
 nudft2_status nudft2_solve_adj(nudft2_plan_t plan, const double* g, double* w,

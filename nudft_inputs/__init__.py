@@ -12,6 +12,13 @@ Workloads (frequencies are centred: k in [-n/2, n/2) per axis; points lie in
   dx, dy iid U[-delta, delta] per point and per coordinate, wrapped mod 1.
   Point j = p * m^y + q.  With m = 2n this gives M = 4N.
 * ``uniform``: the same grid without jitter (the DFT special case).
+* ``random``: M points drawn iid uniform on [0, 1)^2 (the random grid of
+  Section 5, with M = 1.5 N there).
+* ``polar``: the modified polar grid of Section 5: the centre (1/2, 1/2) and
+  the points 1/2 + r_p (cos 2 pi t_q, sin 2 pi t_q) with r_p = (sqrt 2 / 2)
+  p / n_r (p = 1..n_r - 1), t_q = q / n_t (q = 0..n_t - 1), n_r = n,
+  n_t = ceil(beta n log2 n), keeping only the points inside [0, 1)^2.  It has
+  no random draws.
 * random coefficients: complex standard normal, Re and Im iid N(0, 1/2).
 
 Draw order for a seeded problem: dx (M), dy (M), Re c, Im c, then the extra
@@ -26,6 +33,9 @@ import numpy as np
 __all__ = [
     "Problem",
     "jittered_points",
+    "random_points",
+    "polar_points",
+    "make_grid_problem",
     "complex_normal",
     "make_problem",
     "CONFIGS",
@@ -71,6 +81,54 @@ def jittered_points(rng: np.random.Generator, mx: int, my: int,
     # np.mod can return exactly 1.0 for tiny negative inputs; fold it back.
     pts[pts >= 1.0] -= 1.0
     return pts
+
+
+def random_points(rng: np.random.Generator, M: int) -> np.ndarray:
+    """(M, 2) points iid uniform on [0, 1)^2 (x drawn first, then y)."""
+    pts = np.empty((M, 2), dtype=np.float64)
+    pts[:, 0] = rng.random(M)
+    pts[:, 1] = rng.random(M)
+    return pts
+
+
+def polar_points(n: int, beta: float = 0.6) -> np.ndarray:
+    """The modified polar grid for n frequencies per axis: the centre first,
+    then ring p = 1..n-1 (outer loop) and angle q = 0..n_t-1 (inner loop),
+    points outside [0, 1)^2 dropped."""
+    nr = n
+    nt = int(np.ceil(beta * n * np.log2(n)))
+    p = np.arange(1, nr, dtype=np.float64)
+    q = np.arange(nt, dtype=np.float64)
+    r = (np.sqrt(2.0) / 2.0) * p / nr
+    t = q / nt
+    x = 0.5 + np.outer(r, np.cos(2.0 * np.pi * t))
+    y = 0.5 + np.outer(r, np.sin(2.0 * np.pi * t))
+    x, y = x.reshape(-1), y.reshape(-1)
+    keep = (x >= 0.0) & (x < 1.0) & (y >= 0.0) & (y < 1.0)
+    pts = np.empty((1 + int(keep.sum()), 2), dtype=np.float64)
+    pts[0] = (0.5, 0.5)
+    pts[1:, 0] = x[keep]
+    pts[1:, 1] = y[keep]
+    return pts
+
+
+def make_grid_problem(kind: str, n: int, seed, ratio: float = 1.5, beta: float = 0.6,
+                      noise_rel: float = 0.0) -> "Problem":
+    """An n x n problem on the random grid (M = round(ratio N) uniform
+    points) or the polar grid (parameter beta), with complex Gaussian
+    coefficients.  Draw order: the random grid's x then y, then Re c, Im c,
+    then the noise direction when noise_rel > 0."""
+    rng = np.random.default_rng(seed)
+    if kind == "random":
+        pts = random_points(rng, int(round(ratio * n * n)))
+    elif kind == "polar":
+        pts = polar_points(n, beta)
+    else:
+        raise ValueError(f"unknown grid kind {kind!r}")
+    c = complex_normal(rng, (n, n))
+    noise = complex_normal(rng, (pts.shape[0],)) if noise_rel > 0.0 else None
+    return Problem(nx=n, ny=n, points=pts, c_true=c, noise_dir=noise, noise_rel=noise_rel,
+                   seed=seed if isinstance(seed, int) else 0)
 
 
 def complex_normal(rng: np.random.Generator, shape) -> np.ndarray:

@@ -366,7 +366,7 @@ nudft2_status nudft2_set_solve_opts(nudft2_plan_t plan, double ir_tol, int32_t i
                                     int32_t refine) {
   return guard([&] {
     ND_CHECK(plan != nullptr, NUDFT2_E_INVAL, "null plan");
-    ND_CHECK(ir_tol >= 0 && ir_maxit >= 0 && (refine == 0 || refine == 1), NUDFT2_E_INVAL,
+    ND_CHECK(ir_tol >= 0 && ir_maxit >= 0 && refine >= 0 && refine <= 2, NUDFT2_E_INVAL,
              "bad refinement options");
     Plan* P = reinterpret_cast<Plan*>(plan);
     P->opts.ir_tol = ir_tol;

@@ -327,7 +327,7 @@ static void validate(int nprob, const double* points, const int64_t* m_off,
   ND_CHECK(o->leaf >= 2 && o->leaf <= 64, NUDFT2_E_INVAL, "leaf must lie in [2, 64]");
   ND_CHECK(o->ir_maxit >= 0, NUDFT2_E_INVAL, "ir_maxit must be >= 0");
   ND_CHECK(o->ir_tol >= 0.0, NUDFT2_E_INVAL, "ir_tol must be >= 0");
-  ND_CHECK(o->refine == 0 || o->refine == 1, NUDFT2_E_INVAL, "refine must be 0 or 1");
+  ND_CHECK(o->refine >= 0 && o->refine <= 2, NUDFT2_E_INVAL, "refine must be 0, 1 or 2");
   ND_CHECK(o->graph == 0 || o->graph == 1, NUDFT2_E_INVAL, "graph must be 0 or 1");
   for (int p = 0; p < nprob; ++p) {
     ND_CHECK(nx[p] >= 2 && ny[p] >= 2 && nx[p] % 2 == 0 && ny[p] % 2 == 0,

@@ -110,6 +110,132 @@ __global__ void seg_sumsq_kernel(const double2* __restrict__ x, int64_t ldx,
   if (threadIdx.x == 0) atomicAdd(out + r * nprob + p, red[0] + red[1] + red[2] + red[3]);
 }
 
+// ---- per-segment FP64 vector kernels of the Krylov refinements.  A
+// segment is one problem's part of one right-hand side (blockIdx.y =
+// rhs * nprob + problem); coefficient arrays hold one scalar per segment.
+struct SegArgs {
+  const ApplyProb* ap;
+  int nprob;
+  int ncoef;     // 1: N-vector segments [c0, c0 + nx ny); 0: M-vector [m0, m0 + M)
+  int64_t ld;    // entries per right-hand side (Ntot or Mtot)
+};
+
+__device__ inline void seg_range(const SegArgs& a, int64_t& o, int64_t& n) {
+  const int p = blockIdx.y % a.nprob, r = blockIdx.y / a.nprob;
+  const ApplyProb q = a.ap[p];
+  o = r * a.ld + (a.ncoef ? q.c0 : q.m0);
+  n = a.ncoef ? (int64_t)q.nx * q.ny : q.M;
+}
+
+// out[seg] += Re(x^H y) over the segment (out zeroed beforehand)
+__global__ void seg_dot_kernel(SegArgs a, const double2* __restrict__ x,
+                               const double2* __restrict__ y, double* __restrict__ out) {
+  int64_t o, n;
+  seg_range(a, o, n);
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double2 u = x[o + i], v = y[o + i];
+    s += u.x * v.x + u.y * v.y;
+  }
+  s = warp_sum(s);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out + blockIdx.y, red[0] + red[1] + red[2] + red[3]);
+}
+
+// y += sgn coef[seg] x
+__global__ void seg_axpy_kernel(SegArgs a, const double* __restrict__ coef, double sgn,
+                                const double2* __restrict__ x, double2* __restrict__ y) {
+  int64_t o, n;
+  seg_range(a, o, n);
+  const double c = sgn * coef[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double2 u = x[o + i];
+    double2 v = y[o + i];
+    v.x += c * u.x;
+    v.y += c * u.y;
+    y[o + i] = v;
+  }
+}
+
+// y = x + sgn coef[seg] y
+__global__ void seg_xpay_kernel(SegArgs a, const double2* __restrict__ x,
+                                const double* __restrict__ coef, double sgn,
+                                double2* __restrict__ y) {
+  int64_t o, n;
+  seg_range(a, o, n);
+  const double c = sgn * coef[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double2 u = x[o + i], v = y[o + i];
+    y[o + i] = mk<double>(u.x + c * v.x, u.y + c * v.y);
+  }
+}
+
+// y *= coef[seg]
+__global__ void seg_scale_kernel(SegArgs a, const double* __restrict__ coef,
+                                 double2* __restrict__ y) {
+  int64_t o, n;
+  seg_range(a, o, n);
+  const double c = coef[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double2 v = y[o + i];
+    y[o + i] = mk<double>(c * v.x, c * v.y);
+  }
+}
+
+__global__ void copy_d2_kernel(const double2* __restrict__ x, double2* __restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    y[i] = x[i];
+}
+
+// conjugate gradients: alpha = rho / gamma (gamma = ||A p||^2)
+__global__ void pcg_alpha_kernel(const double* rho, const double* gamma, double* alpha, int nseg) {
+  for (int e = threadIdx.x; e < nseg; e += blockDim.x)
+    alpha[e] = gamma[e] > 0.0 ? rho[e] / gamma[e] : 0.0;
+}
+
+// flexible (Polak-Ribiere) beta = (rho_new - r^H z_old) / rho, then rho = rho_new
+__global__ void pcg_beta_kernel(double* rho, const double* rho_new, const double* mix,
+                                double* beta, int nseg) {
+  for (int e = threadIdx.x; e < nseg; e += blockDim.x) {
+    beta[e] = rho[e] > 0.0 ? (rho_new[e] - mix[e]) / rho[e] : 0.0;
+    rho[e] = rho_new[e];
+  }
+}
+
+// nrm = sqrt(s2), inv = 1 / nrm (0 for a zero vector)
+__global__ void norm_inv_kernel(const double* s2, double* nrm, double* inv, int nseg) {
+  for (int e = threadIdx.x; e < nseg; e += blockDim.x) {
+    const double v = sqrt(s2[e]);
+    nrm[e] = v;
+    inv[e] = v > 0.0 ? 1.0 / v : 0.0;
+  }
+}
+
+// LSQR's plane rotation (Paige and Saunders): from rhobar, phibar and the new
+// beta, alpha: rho = |(rhobar, beta)|, c = rhobar / rho, s = beta / rho,
+// theta = s alpha, rhobar' = -c alpha, phi = c phibar, phibar' = s phibar;
+// the solution moves by (phi / rho) w, then w = v - (theta / rho) w
+__global__ void lsqr_rot_kernel(const double* alpha, const double* beta, double* rhobar,
+                                double* phibar, double* ax, double* aw, int nseg) {
+  for (int e = threadIdx.x; e < nseg; e += blockDim.x) {
+    const double rho = hypot(rhobar[e], beta[e]);
+    if (rho > 0.0) {
+      const double c = rhobar[e] / rho, s = beta[e] / rho;
+      const double theta = s * alpha[e];
+      rhobar[e] = -c * alpha[e];
+      const double phi = c * phibar[e];
+      phibar[e] = s * phibar[e];
+      ax[e] = phi / rho;
+      aw[e] = -theta / rho;
+    } else {
+      ax[e] = 0.0;
+      aw[e] = 0.0;
+    }
+  }
+}
+
 // y = a x + b y (complex vectors, real a, b)
 __global__ void axpby_kernel(double a, const double2* __restrict__ x, double b,
                              double2* __restrict__ y, int64_t n) {
@@ -531,6 +657,53 @@ struct SolveCtx {
     }
     ND_HIP(hipGraphLaunch(gexec, cx.s));
   }
+  // ---- segmented vector operations (one scalar per right-hand side and
+  // problem), launched on k.s; n is Mtot (M-vectors) or Ntot (N-vectors)
+  int nseg() const { return nrhs * nprob; }
+  SegArgs seg(int64_t n) const {
+    return SegArgs{P->d_aprob, nprob, n != P->Mtot ? 1 : 0, n};
+  }
+  dim3 seg_grid(int64_t n) const {
+    const int64_t len = n != P->Mtot ? nmax : mmax;
+    return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_for(len), 256)),
+                (unsigned)nseg());
+  }
+  void seg_zero(Ctx& k, double* out) {
+    hipLaunchKernelGGL(zero_d_kernel, dim3(1), dim3(256), 0, k.s, out, (int64_t)nseg());
+  }
+  void seg_dot(Ctx& k, double* out, const double2* x, const double2* y, int64_t n) {
+    seg_zero(k, out);
+    hipLaunchKernelGGL(seg_dot_kernel, seg_grid(n), dim3(256), 0, k.s, seg(n), x, y, out);
+  }
+  void seg_axpy(Ctx& k, const double* coef, double sgn, const double2* x, double2* y, int64_t n) {
+    hipLaunchKernelGGL(seg_axpy_kernel, seg_grid(n), dim3(256), 0, k.s, seg(n), coef, sgn, x, y);
+  }
+  void seg_xpay(Ctx& k, const double2* x, const double* coef, double sgn, double2* y, int64_t n) {
+    hipLaunchKernelGGL(seg_xpay_kernel, seg_grid(n), dim3(256), 0, k.s, seg(n), x, coef, sgn, y);
+  }
+  void seg_scale(Ctx& k, const double* coef, double2* y, int64_t n) {
+    hipLaunchKernelGGL(seg_scale_kernel, seg_grid(n), dim3(256), 0, k.s, seg(n), coef, y);
+  }
+  void copyk(Ctx& k, const double2* x, double2* y, int64_t n) {
+    hipLaunchKernelGGL(copy_d2_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, k.s, x, y,
+                       n * nrhs);
+  }
+  // device scalars of the Krylov drivers: slot i holds one value per segment
+  double* ks = nullptr;
+  double* kslot(int i) {
+    if (!ks) ks = (double*)cx.tmp_alloc(sizeof(double) * 32 * (size_t)nseg());
+    return ks + (size_t)i * nseg();
+  }
+  // read back cnt consecutive scalar slots from slot i (synchronises)
+  std::vector<double> read_slots(int i, int cnt) {
+    std::vector<double> h((size_t)cnt * nseg());
+    ND_HIP(hipMemcpyAsync(h.data(), kslot(i), sizeof(double) * h.size(), hipMemcpyDeviceToHost,
+                          cx.s));
+    ND_HIP(hipStreamSynchronize(cx.s));
+    cx.pool.sync_reset();
+    return h;
+  }
+
   // worst ||a|| / ||b|| over the right-hand sides and problems of two norm
   // slots (a problem whose b vanishes counts as converged when a does too)
   double worst_ratio(const std::vector<double>& h, int ia, int ib) const {
@@ -556,10 +729,175 @@ void report(nudft2_solve_info* info, int its, double upd, double res) {
   info->rel_residual = res;
 }
 
+// Slots of SolveCtx::kslot used by the Krylov drivers.
+enum KSlot {
+  K_PN2 = 0, K_CN2, K_ALPHA,            // read back together (PCG)
+  K_RHO, K_GAMMA, K_BETA, K_RHON, K_MIX,
+  K_WN2 = 8, K_LCN2, K_AX, K_PHIBAR, K_BETA1,   // read back together (LSQR)
+  K_LA, K_LB, K_RHOBAR, K_AW, K_S2, K_INV
+};
+
+// Preconditioned conjugate gradients on the normal equations A^H A c = b
+// with the preconditioner S S^H (S the factored solution operator, S^H its
+// adjoint sweep), in the flexible Polak-Ribiere form: A^H A is applied
+// exactly in FP64 each iteration, while the preconditioner may be the FP32
+// sweep, whose rounding makes it vary slightly between applications.  Every
+// scalar is per right-hand side and problem (the problems of a batch plan are
+// independent).  On entry c holds the first iterate and r = b - A^H A c; on
+// exit c is the solution.  Stops when every problem's ||alpha p|| / ||c|| <=
+// tol; its counts the iterations taken here.
+template <typename T>
+bool pcg_normal(SolveCtx<T>& sc, double2* c, double2* r, int maxit, double tol, int& its,
+                double& upd) {
+  Plan* P = sc.P;
+  const int64_t M = P->Mtot, N = P->Ntot;
+  const int ns = sc.nseg();
+  double2* z = sc.vecN();
+  double2* zo = sc.vecN();
+  double2* p = sc.vecN();
+  double2* q = sc.vecN();
+  double2* t = sc.vecM();
+  double* pn2 = sc.kslot(K_PN2);
+  double* cn2 = sc.kslot(K_CN2);
+  double* alpha = sc.kslot(K_ALPHA);
+  double* rho = sc.kslot(K_RHO);
+  double* gamma = sc.kslot(K_GAMMA);
+  double* beta = sc.kslot(K_BETA);
+  double* rhon = sc.kslot(K_RHON);
+  double* mix = sc.kslot(K_MIX);
+  // z = S S^H r, p = z, rho = Re(r^H z)
+  sc.SH(sc.cx, r, t);
+  sc.S(sc.cx, t, z);
+  sc.copyk(sc.cx, z, p, N);
+  sc.seg_dot(sc.cx, rho, r, z, N);
+  auto body = [&](Ctx& k) {
+    apply_fwd(P, p, t, sc.nrhs, k.s);                 // t = A p
+    sc.seg_dot(k, gamma, t, t, M);                    // gamma = ||A p||^2
+    apply_adj(P, t, q, sc.nrhs, k.s);                 // q = A^H A p
+    hipLaunchKernelGGL(pcg_alpha_kernel, dim3(1), dim3(256), 0, k.s, rho, gamma, alpha, ns);
+    sc.seg_dot(k, pn2, p, p, N);
+    sc.seg_axpy(k, alpha, 1.0, p, c, N);              // c += alpha p
+    sc.seg_axpy(k, alpha, -1.0, q, r, N);             // r -= alpha q
+    sc.seg_dot(k, cn2, c, c, N);
+    sc.copyk(k, z, zo, N);
+    sc.SH(k, r, t);                                   // z = S S^H r
+    sc.S(k, t, z);
+    sc.seg_dot(k, rhon, r, z, N);
+    sc.seg_dot(k, mix, r, zo, N);
+    hipLaunchKernelGGL(pcg_beta_kernel, dim3(1), dim3(256), 0, k.s, rho, rhon, mix, beta, ns);
+    sc.seg_xpay(k, z, beta, 1.0, p, N);               // p = z + beta p
+    ND_HIP(hipGetLastError());
+  };
+  its = 0;
+  upd = 1.0;
+  bool conv = false;
+  while (!conv && upd == upd && its < maxit) {   // (upd != upd: NaN, stop)
+    ++its;
+    sc.run(body);
+    const std::vector<double> h = sc.read_slots(K_PN2, 3);
+    upd = 0;
+    for (int e = 0; e < ns; ++e)
+      upd = std::max(upd, std::fabs(h[2 * ns + e]) * std::sqrt(h[e]) /
+                              std::max(std::sqrt(h[ns + e]), 1e-300));
+    conv = upd <= tol;
+  }
+  return conv;
+}
+
+// The paper's plsqr (Section 4.1): LSQR (Paige and Saunders) on the left-
+// preconditioned system S A c = S f, with B = S A applied as the exact FP64
+// apply followed by the factored sweep and B^H = A^H S^H as the adjoint sweep
+// followed by the exact adjoint apply.  Its fixed point is the least-squares
+// solution for consistent f (S A is nonsingular), as for plain refinement.
+// With FP32 factors the sweep's rounding bounds what one LSQR run can reach
+// (about 1e-6 relative), so the run restarts from the exact FP64 residual
+// r = f - A c whenever its own residual estimate phibar has fallen by
+// cycle_tol; with FP64 factors it is one run.  Scalars per right-hand side
+// and problem.  Stops when every problem's ||dc|| / ||c|| <= tol.
+template <typename T>
+bool plsqr(SolveCtx<T>& sc, const double2* f, double2* c, int maxit, double tol,
+           double cycle_tol, int& its, double& upd) {
+  Plan* P = sc.P;
+  const int64_t M = P->Mtot, N = P->Ntot;
+  const int ns = sc.nseg();
+  double2* u = sc.vecN();
+  double2* v = sc.vecN();
+  double2* w = sc.vecN();
+  double2* tN = sc.vecN();
+  double2* tM = sc.vecM();
+  double* wn2 = sc.kslot(K_WN2);
+  double* cn2 = sc.kslot(K_LCN2);
+  double* ax = sc.kslot(K_AX);
+  double* phibar = sc.kslot(K_PHIBAR);
+  double* beta1 = sc.kslot(K_BETA1);
+  double* la = sc.kslot(K_LA);
+  double* lb = sc.kslot(K_LB);
+  double* rhobar = sc.kslot(K_RHOBAR);
+  double* aw = sc.kslot(K_AW);
+  double* s2 = sc.kslot(K_S2);
+  double* inv = sc.kslot(K_INV);
+  auto normalise_seg = [&](Ctx& k, double2* x, double* nrm) {
+    sc.seg_dot(k, s2, x, x, N);
+    hipLaunchKernelGGL(norm_inv_kernel, dim3(1), dim3(256), 0, k.s, s2, nrm, inv, ns);
+    sc.seg_scale(k, inv, x, N);
+  };
+  auto body = [&](Ctx& k) {
+    apply_fwd(P, v, tM, sc.nrhs, k.s);                // tN = B v
+    sc.S(k, tM, tN);
+    sc.seg_xpay(k, tN, la, -1.0, u, N);               // u = B v - alpha u
+    normalise_seg(k, u, lb);                          // beta, u /= beta
+    sc.SH(k, u, tM);                                  // tN = B^H u
+    apply_adj(P, tM, tN, sc.nrhs, k.s);
+    sc.seg_xpay(k, tN, lb, -1.0, v, N);               // v = B^H u - beta v
+    normalise_seg(k, v, la);                          // alpha, v /= alpha
+    hipLaunchKernelGGL(lsqr_rot_kernel, dim3(1), dim3(256), 0, k.s, la, lb, rhobar, phibar,
+                       ax, aw, ns);
+    sc.seg_dot(k, wn2, w, w, N);
+    sc.seg_axpy(k, ax, 1.0, w, c, N);                 // c += (phi / rho) w
+    sc.seg_xpay(k, v, aw, 1.0, w, N);                 // w = v - (theta / rho) w
+    sc.seg_dot(k, cn2, c, c, N);
+    ND_HIP(hipGetLastError());
+  };
+  sc.zero(c, N);
+  its = 0;
+  upd = 1.0;
+  bool conv = false;
+  while (!conv && upd == upd && its < maxit) {
+    // a run starts from the exact residual of the current iterate
+    Ctx& k = sc.cx;
+    apply_fwd(P, c, tM, sc.nrhs, k.s);
+    sc.axpby(k, 1.0, f, -1.0, tM, M);                 // tM = f - A c
+    sc.S(k, tM, u);                                   // beta_1 u = S r
+    normalise_seg(k, u, beta1);
+    sc.SH(k, u, tM);                                  // alpha_1 v = B^H u
+    apply_adj(P, tM, v, sc.nrhs, k.s);
+    normalise_seg(k, v, la);
+    sc.copyk(k, v, w, N);
+    ND_HIP(hipMemcpyAsync(phibar, beta1, sizeof(double) * ns, hipMemcpyDeviceToDevice, k.s));
+    ND_HIP(hipMemcpyAsync(rhobar, la, sizeof(double) * ns, hipMemcpyDeviceToDevice, k.s));
+    while (!conv && upd == upd && its < maxit) {
+      ++its;
+      sc.run(body);
+      const std::vector<double> h = sc.read_slots(K_WN2, 5);
+      upd = 0;
+      double rres = 0;
+      for (int e = 0; e < ns; ++e) {
+        upd = std::max(upd, std::fabs(h[2 * ns + e]) * std::sqrt(h[e]) /
+                                std::max(std::sqrt(h[ns + e]), 1e-300));
+        if (h[4 * ns + e] > 0) rres = std::max(rres, h[3 * ns + e] / h[4 * ns + e]);
+      }
+      conv = upd <= tol;
+      if (rres <= cycle_tol) break;   // restart from the exact residual
+    }
+  }
+  return conv;
+}
+
 // Least-squares solve.  refine == 0: iterative refinement c += S (f - A c)
-// (exact for consistent f); refine == 1: refinement on the normal equations,
-// c += S S^H A^H (f - A c), whose fixed point is the least-squares solution
-// for any f.  ir_maxit == 0: the direct solution S f.
+// (exact for consistent f); refine == 1: preconditioned conjugate gradients
+// on the normal equations from the direct solution (exact least squares for
+// any f); refine == 2: the paper's plsqr (exact for consistent f).
+// ir_maxit == 0: the direct solution S f.
 template <typename T>
 void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info* info) {
   SolveCtx<T> sc(P, nrhs);
@@ -571,27 +909,46 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
     report(info, 0, 0, -1);
     return;
   }
-  const bool ne = P->opts.refine == 1;
+  const int mode = P->opts.refine;
+  if (mode == 1 || mode == 2) {
+    const double fn = sc.total(sc.norms2({{f, M}}), 0, 0);
+    int its = 0;
+    double upd = 0;
+    bool conv;
+    double2* rM = sc.vecM();
+    if (mode == 1) {
+      // first iterate: the direct solution; then CG on the normal equations
+      double2* r = sc.vecN();
+      sc.S(f, c);
+      apply_fwd(P, c, rM, nrhs, sc.cx.s);
+      sc.axpby(1.0, f, -1.0, rM, M);
+      apply_adj(P, rM, r, nrhs, sc.cx.s);
+      conv = pcg_normal<T>(sc, c, r, maxit - 1, P->opts.ir_tol, its, upd);
+      ++its;
+    } else {
+      const double cycle_tol = P->hss->precision == 1 ? 1e-5 : 0.0;
+      conv = plsqr<T>(sc, f, c, maxit, P->opts.ir_tol, cycle_tol, its, upd);
+    }
+    // the residual of the returned solution (first right-hand side)
+    apply_fwd(P, c, rM, nrhs, sc.cx.s);
+    sc.axpby(1.0, f, -1.0, rM, M);
+    const double res = sc.total(sc.norms2({{rM, M}}), 0, 0) / std::max(fn, 1e-300);
+    report(info, its, upd, res);
+    if (!conv) throw Error(NUDFT2_E_NOCONV, "refinement did not reach ir_tol");
+    return;
+  }
   double2* rr = sc.vecM();
   double2* dd = sc.vecN();
-  double2* rN = ne ? sc.vecN() : nullptr;
-  double2* tM = ne ? sc.vecM() : nullptr;
   sc.copy(f, rr, M);
   sc.zero(c, N);
   const double fn = sc.total(sc.norms2({{f, M}}), 0, 0);
   int it = 1;
   double upd = 0, res = 1;
   bool conv = false;
-  // correction of the current iterate from its residual r: d = S r (or
-  // S S^H A^H r), c += d, norms of d and c
+  // correction of the current iterate from its residual r: d = S r, c += d,
+  // norms of d and c
   auto correct = [&](Ctx& k) {
-    if (ne) {
-      apply_adj(P, rr, rN, nrhs, k.s);
-      sc.SH(k, rN, tM);
-      sc.S(k, tM, dd);
-    } else {
-      sc.S(k, rr, dd);
-    }
+    sc.S(k, rr, dd);
     sc.axpby(k, 1.0, dd, 1.0, c, N);
     sc.norm_into(k, 0, dd, N);
     sc.norm_into(k, 1, c, N);
@@ -622,46 +979,22 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
   if (!conv) throw Error(NUDFT2_E_NOCONV, "refinement did not reach ir_tol");
 }
 
-// z = (A^H A)^{-1} g by refinement on the normal equations preconditioned by
-// S S^H: z += S S^H (g - A^H A z).  Returns iterations and the last update.
+// z = (A^H A)^{-1} g by preconditioned conjugate gradients on the normal
+// equations, from z = S S^H g.  Returns iterations and the last update.
 template <typename T>
 void normal_solve(SolveCtx<T>& sc, const double2* g, double2* z, int& its, double& upd) {
   Plan* P = sc.P;
-  const int64_t M = P->Mtot, N = P->Ntot;
-  const int maxit = std::max(P->opts.ir_maxit, 1);
-  double2* rz = sc.vecN();
-  double2* dd = sc.vecN();
+  const int64_t N = P->Ntot;
+  const int maxit = std::max(P->opts.ir_maxit, 2);   // at least one CG step
+  double2* r = sc.vecN();
   double2* u = sc.vecM();
-  double2* tM = sc.vecM();
-  sc.copy(g, rz, N);
-  sc.zero(z, N);
-  bool conv = false;
-  // correction from the residual r: d = S S^H r, z += d, norms of d and z
-  auto correct = [&](Ctx& k) {
-    sc.SH(k, rz, tM);
-    sc.S(k, tM, dd);
-    sc.axpby(k, 1.0, dd, 1.0, z, N);
-    sc.norm_into(k, 0, dd, N);
-    sc.norm_into(k, 1, z, N);
-  };
-  // later iterations: r = g - A^H A z of the current iterate, then its
-  // correction (no residual is formed after the last update)
-  auto body = [&](Ctx& k) {
-    apply_fwd(P, z, u, sc.nrhs, k.s);
-    apply_adj(P, u, rz, sc.nrhs, k.s);
-    sc.axpby(k, 1.0, g, -1.0, rz, N);
-    correct(k);
-  };
-  its = 1;
-  correct(sc.cx);
-  upd = sc.worst_ratio(sc.read_norms(2), 0, 1);
-  conv = upd <= P->opts.ir_tol;
-  while (!conv && upd == upd && its < maxit) {   // (upd != upd: NaN, stop)
-    ++its;
-    sc.run(body);
-    upd = sc.worst_ratio(sc.read_norms(2), 0, 1);
-    conv = upd <= P->opts.ir_tol;
-  }
+  sc.SH(sc.cx, g, u);                 // z = S S^H g
+  sc.S(sc.cx, u, z);
+  apply_fwd(P, z, u, sc.nrhs, sc.cx.s);
+  apply_adj(P, u, r, sc.nrhs, sc.cx.s);
+  sc.axpby(1.0, g, -1.0, r, N);       // r = g - A^H A z
+  const bool conv = pcg_normal<T>(sc, z, r, maxit - 1, P->opts.ir_tol, its, upd);
+  ++its;
   if (!conv) throw Error(NUDFT2_E_NOCONV, "refinement did not reach ir_tol");
 }
 

@@ -109,7 +109,7 @@ def test_set_solve_opts_direct_and_refined():
     assert rel(plan.solve(ft).cpu().numpy(), pr.c_true) < 1e-10
     assert plan.info()["sweep_bytes"] > 0
     with pytest.raises(nd.NudftError):
-        plan.set_solve_opts(refine=2)
+        plan.set_solve_opts(refine=3)
     plan.close()
 
 
