@@ -27,11 +27,18 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 WORKLOADS = {
-    # name: (nx, ny, mx, my, delta, seed)
+    # name: (nx, ny, mx, my, delta, seed) -- jittered grids (M = 4N)
     "n512": (512, 512, 1024, 1024, 0.4, 3),
     "n256": (256, 256, 512, 512, 0.4, 3),
     "fp64_128": (128, 128, 256, 256, 0.3, 2),
     "small": (32, 32, 64, 64, 0.25, 1),
+}
+# the paper's grid families (Section 5): name -> (kind, n, seed)
+GRID_WORKLOADS = {
+    "random512": ("random", 512, 3),   # M = 1.5 N uniform points
+    "polar512": ("polar", 512, 3),     # beta = 0.6, M = 1122019
+    "random256": ("random", 256, 3),
+    "polar256": ("polar", 256, 3),
 }
 
 FP64_PEAK_TFLOPS = 78.6
@@ -44,7 +51,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n512", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="n512", choices=sorted(WORKLOADS) + sorted(GRID_WORKLOADS))
+    ap.add_argument("--refine", type=int, default=0, choices=[0, 1, 2],
+                    help="0 iterative refinement, 1 PCG on the normal equations, 2 plsqr")
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--ir-tol", type=float, default=1e-10)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-factor comparison")
@@ -63,13 +72,20 @@ def main():
         args.nrhs16 = False
 
     import torch
-    from nudft_inputs import make_problem
+    from nudft_inputs import make_problem, make_grid_problem
     import paper_2607_00928_amd as nd
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    nx, ny, mx, my, delta, seed = WORKLOADS[args.workload]
-    pr = make_problem(nx, ny, mx, my, delta, seed)
+    if args.workload in GRID_WORKLOADS:
+        kind, nx, seed = GRID_WORKLOADS[args.workload]
+        ny = nx
+        pr = make_grid_problem(kind, nx, seed)
+        wl_desc = (f"{args.workload}: {kind} grid, nx=ny={nx}, M={pr.M}, eps={args.eps}")
+    else:
+        nx, ny, mx, my, delta, seed = WORKLOADS[args.workload]
+        pr = make_problem(nx, ny, mx, my, delta, seed)
+        wl_desc = f"{args.workload}: nx=ny={nx}, M={pr.M}, jitter {delta}, eps={args.eps}"
     M, N = pr.M, nx * ny
     c_true = torch.from_numpy(pr.c_true).to(dev)
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
@@ -82,8 +98,8 @@ def main():
 
     def step(precision, profile=False):
         t0 = time.perf_counter()
-        plan = nd.Plan(pr.points, nx, ny, precision=precision, eps=args.eps, ir_maxit=60,
-                       ir_tol=args.ir_tol)
+        plan = nd.Plan(pr.points, nx, ny, precision=precision, eps=args.eps, ir_maxit=200,
+                       ir_tol=args.ir_tol, refine=args.refine)
         if profile:
             plan.set_profiling(True)
         t1 = time.perf_counter()
@@ -182,7 +198,7 @@ def main():
     sb = info["sweep_bytes"]
     sweep = {"ms": 1e3 * sweep_s, "bytes": sb, "gbps": sb / sweep_s / 1e9,
              "frac_hbm": sb / sweep_s / (HBM_PEAK_GBPS * 1e9)}
-    last_plan.set_solve_opts(ir_maxit=60)
+    last_plan.set_solve_opts(ir_maxit=200)
     # exact FP64 apply alone (its own kernel-class timing)
     last_plan.set_profiling(True)
     for _ in range(5):
@@ -221,9 +237,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64 factors + f64 refinement",
-        "data": "synthetic (seeded jittered grid, complex Gaussian coefficients)",
-        "config": {"workload": f"{args.workload}: nx=ny={nx}, M={M}, jitter {delta}, eps={args.eps}",
-                   "precision": "fp32+ir", "ir_tol": args.ir_tol},
+        "data": ("synthetic (seeded %s grid, complex Gaussian coefficients)"
+                 % ("jittered" if args.workload in WORKLOADS else GRID_WORKLOADS[args.workload][0])),
+        "config": {"workload": wl_desc, "precision": "fp32+ir", "ir_tol": args.ir_tol,
+                   "refine": ["iterative refinement", "pcg-ne", "plsqr"][args.refine]},
         "factor_s": float(np.median([r["factor_s"] for r in recs])),
         "solve_s": float(np.median([r["solve_s"] for r in recs])),
         "plan_s": float(np.median([r["plan_s"] for r in recs])),
@@ -234,6 +251,7 @@ def main():
         "phases_ms": {k: info[k] for k in ("t_compress_ms", "t_facesplit_ms", "t_recompress_ms", "t_urv_ms")},
         "ranks_u": info["max_rank_u"], "ranks_v": info["max_rank_v"],
         "factor_bytes": info["factor_bytes"],
+        "peak_bytes": info["peak_bytes"],
         "kernels": kernels,
         "sweep": sweep,
         "apply": {"ms": apply_ms, "tflops": apply_tf, "frac_fp64_peak": apply_tf / FP64_PEAK_TFLOPS},

@@ -848,12 +848,14 @@ __device__ inline T wave_sum63(T v) {
   return v;
 }
 
-template <typename T, class AS>
+// RM = 2 doubles the rows each lane holds, for panels taller than the
+// device holds at RM = 1 (one workgroup per CU)
+template <typename T, class AS, int RM = 1>
 __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(
     const QRDesc<T>* __restrict__ descs, AS active, int nact, int j0, int gsize,
     cplx<T>* __restrict__ scratch, unsigned* __restrict__ bar, int* __restrict__ err) {
   using C2 = cplx<T>;
-  constexpr int R = QPanel<T>::R;
+  constexpr int R = QPanel<T>::R * RM;
   constexpr int HALF = 64 * R;           // rows of one row half
   constexpr int ROWS = 2 * HALF;         // rows of a workgroup
   static_assert(QP_NT / 64 == 2 * (QR_NB / QP_CG), "16 waves: 8 column groups x 2 row halves");
@@ -1918,6 +1920,9 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const std::vector<int>
   }();
   constexpr int rows = 128 * QPanel<T>::R;
   int gsize = std::max(1, (maxmr + rows - 1) / rows);
+  // taller panels: twice the rows per workgroup (RM = 2)
+  const bool tall = gsize > mres;
+  if (tall) gsize = std::max(1, (maxmr + 2 * rows - 1) / (2 * rows));
   ND_CHECK(gsize <= mres, NUDFT2_E_INTERNAL, "QR panel taller than the device can hold");
   int ngroups = std::max(1, std::min(nact, mres / gsize));
   const size_t per_group = sizeof(T) == 4 ? qp_tag_words(gsize) * sizeof(unsigned long long)
@@ -1931,7 +1936,8 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const std::vector<int>
                      dim3(256), 0, pool.stream, (unsigned*)z, (int64_t)words);
   int* err = pool.flag;
   with_descs(pool, act.data(), act.size(), [&](auto as) {
-    const void* k = (const void*)qr_panel_kernel<T, decltype(as)>;
+    const void* k = tall ? (const void*)qr_panel_kernel<T, decltype(as), 2>
+                         : (const void*)qr_panel_kernel<T, decltype(as), 1>;
     void* args[] = {(void*)&dd, (void*)&as, (void*)&nact, (void*)&j0, (void*)&gsize,
                     (void*)&scr, (void*)&bar, (void*)&err};
     ProfScope ps(pool.stream, KC_QRPANEL, 0.0, nact, maxmr, 0, 0, gsize);

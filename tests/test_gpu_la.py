@@ -402,14 +402,21 @@ def test_gemm_small_output_long_k(prec, beta):
         assert np.all(np.abs(got - ref) <= bound + 4 * u * np.abs(ref)), (m, n, k, same)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_geqrf_tall_panels(prec):
+@pytest.mark.parametrize("prec,shapes", [
+    (0, [(40000, 40), (20000, 70), (9000, 33), (600, 20)]),
+    (1, [(40000, 40), (20000, 70), (9000, 33), (600, 20)]),
+    # taller than one row slab per CU holds (65536 FP64 / 131072 FP32 rows):
+    # twice the rows per workgroup
+    (0, [(90000, 36), (3000, 40)]),
+    (1, [(140000, 36), (3000, 40)]),
+])
+def test_geqrf_tall_panels(prec, shapes):
     """Householder QR of tall panels that need many cooperating workgroups per
-    panel (up to 40000 rows: 79 FP32 / 157 FP64 workgroups exchanging column
-    sums every column), batched with a short one.  Checks Q [R; 0] = A through
-    the Q application, R upper triangular, and |diag R| against LAPACK."""
+    panel (40000 rows: 79 FP32 / 157 FP64 workgroups exchanging column sums
+    every column; up to 140000 rows with twice the rows per workgroup),
+    batched with shorter ones.  Checks Q [R; 0] = A through the Q application,
+    R upper triangular, and |diag R| against LAPACK."""
     rng = np.random.default_rng(90 + prec)
-    shapes = [(40000, 40), (20000, 70), (9000, 33), (600, 20)]
     keep, data = [], []
     mn, ld, ptr = [], [], []
     for (m, n) in shapes:
