@@ -145,16 +145,13 @@ def test_batch_mixed_direct_and_refined(prec):
     bp.close()
 
 
-@pytest.mark.skip(reason="held off the GPU for now: this case stopped responding (no output "
-                  "for 180 s) twice, after a cooperative multi-workgroup pivoted-Cholesky "
-                  "panel and graph-captured refinement were introduced; the cause is not "
-                  "shown, the cooperative panel is taken out and graphs are opt-in")
 def test_batch_64_uneven_problems():
     """64 problems, n^x, n^y uniform over {32, 48, 64, 96, 128}, M = 4N each,
     FP32 factors + FP64 refinement.  Consistent right-hand sides: every
     solution must match its c_true; the smallest problems are also checked
     against the oracle's dense least-squares solution."""
     probs = batch_problems()
+    print("64-problem batch: shapes", [p.c_true.shape for p in probs], flush=True)
     f, ft = _pack(probs)
     nxs = [p.c_true.shape[0] for p in probs]
     nys = [p.c_true.shape[1] for p in probs]
@@ -202,3 +199,31 @@ def test_batch_per_problem_stopping_test():
         e = rel(ci, p.c_true)
         print(f"problem {i} {shapes[i]}: err vs c_true {e:.2e}")
         assert e < 1e-10, (i, e)
+
+
+def test_batch_64_graph_captured_solve():
+    """The 64-problem batch with the refinement iteration captured into a HIP
+    graph and replayed (opts.graph): the same iterations and solutions as the
+    eager launches, every problem within 1e-10 of c_true."""
+    probs = batch_problems()
+    f, ft = _pack(probs)
+    nxs = [p.c_true.shape[0] for p in probs]
+    nys = [p.c_true.shape[1] for p in probs]
+    out = {}
+    for graph in (False, True):
+        bp = nd.BatchPlan([p.points for p in probs], nxs, nys, precision="fp32", eps=1e-2,
+                          ir_maxit=60, ir_tol=1e-12, graph=graph)
+        bp.factor()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c, si = bp.solve(ft, return_info=True)
+        torch.cuda.synchronize()
+        out[graph] = (c.cpu().numpy(), si["iterations"], time.perf_counter() - t0)
+        bp.close()
+    print(f"64-problem batch solve: eager {out[False][2]:.3f} s ({out[False][1]} its), "
+          f"graph {out[True][2]:.3f} s ({out[True][1]} its)")
+    assert out[True][1] == out[False][1]
+    assert rel(out[True][0], out[False][0]) < 1e-12
+    cs = _split_c(bp, torch.from_numpy(out[True][0]), probs)
+    worst = max(rel(ci, p.c_true) for ci, p in zip(cs, probs))
+    assert worst < 1e-10
