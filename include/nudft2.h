@@ -81,6 +81,11 @@ typedef struct {
                          graph and replays it for the rest; 0 (default): eager
                          launches.
                          Kernel profiling (nudft2_set_profiling) runs eagerly. */
+  double nufft_tol;   /* operator of the refinement iterations: 0 (default) the
+                         exact FP64 direct sums of A and A^*; > 0 their
+                         approximation by spreading and FFT (Section 4.1's
+                         NUFFT) to about this relative accuracy, in (0, 0.1);
+                         nx, ny <= 1024 */
 } nudft2_opts;
 
 /* Per-solve report (host memory, may be NULL). */
@@ -234,6 +239,19 @@ nudft2_status nudft2_apply_adj(nudft2_plan_t plan, const double* f, double* c,
  * Errors: E_INVAL, E_DEVICE. */
 nudft2_status nudft2_apply_adj_noalloc(nudft2_plan_t plan, const double* f, double* c,
                                        int32_t nrhs);
+
+/* f ~= A c (type-2 NUFFT) and c ~= A^* f (type-1 NUFFT) by spreading with an
+ * exponential-of-semicircle kernel and FFTs on a twice-oversampled grid (the
+ * NUFFT with which Section 4.1 applies A and its adjoint inside the Krylov
+ * iterations), in FP64, to relative accuracy about tol (0 < tol < 0.1; the
+ * kernel spans ceil(log10(1/tol)) + 2 cells, at most 16).  Shapes and
+ * pointers as nudft2_apply / nudft2_apply_adj.  Needs nx, ny <= 1024 and no
+ * factorization.  The plan keeps the NUFFT state of the last tol.  Errors:
+ * E_INVAL, E_NOMEM, E_DEVICE. */
+nudft2_status nudft2_nufft(nudft2_plan_t plan, const double* c, double* f, int32_t nrhs,
+                           double tol);
+nudft2_status nudft2_nufft_adj(nudft2_plan_t plan, const double* f, double* c, int32_t nrhs,
+                               double tol);
 
 /* Fill *info (HOST).  Synchronises with the plan's stream. */
 nudft2_status nudft2_get_info(nudft2_plan_t plan, nudft2_info* info);

@@ -25,9 +25,11 @@ __all__ = ["Plan", "BatchPlan", "NudftError", "lsq_solve"]
 _PREC = {"fp64": 0, "fp32": 1, 0: 0, 1: 1}
 
 
-def _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph=False):
+def _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph=False,
+          nufft_tol=0.0):
     o = _lib.default_opts()
     o.graph = 1 if graph else 0
+    o.nufft_tol = float(nufft_tol)
     o.precision = _PREC[precision]
     o.eps = float(eps)
     o.leaf = int(leaf)
@@ -172,6 +174,25 @@ class _PlanBase:
                                C.c_void_p(f.data_ptr()), nrhs), "nudft2_apply")
         return f
 
+    def nufft(self, c: torch.Tensor, tol: float = 1e-12) -> torch.Tensor:
+        """f ~= A c by spreading and FFT (nudft2_nufft)."""
+        self._check_dev(c, "c")
+        nrhs = 1 if c.dim() == len(self.N_shape) else c.shape[0]
+        shape = (self.M,) if c.dim() == len(self.N_shape) else (nrhs, self.M)
+        f = torch.empty(shape, dtype=torch.complex128, device=c.device)
+        check(lib.nudft2_nufft(self._handle, C.c_void_p(c.data_ptr()), C.c_void_p(f.data_ptr()),
+                               nrhs, float(tol)), "nudft2_nufft")
+        return f
+
+    def nufft_adj(self, f: torch.Tensor, tol: float = 1e-12) -> torch.Tensor:
+        """c ~= A^* f by spreading and FFT (nudft2_nufft_adj)."""
+        nrhs, shape = self._rhs(f)
+        c = torch.empty(shape, dtype=torch.complex128, device=f.device)
+        check(lib.nudft2_nufft_adj(self._handle, C.c_void_p(f.data_ptr()),
+                                   C.c_void_p(c.data_ptr()), nrhs, float(tol)),
+              "nudft2_nufft_adj")
+        return c
+
     def apply_adj(self, f: torch.Tensor) -> torch.Tensor:
         nrhs, shape = self._rhs(f)
         c = torch.empty(shape, dtype=torch.complex128, device=f.device)
@@ -197,7 +218,7 @@ class Plan(_PlanBase):
 
     def __init__(self, points, nx: int, ny: int, *, precision="fp32", eps=1e-4,
                  leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0, stream=None,
-                 mem_cap=0, device=None, graph=False):
+                 mem_cap=0, device=None, graph=False, nufft_tol=0.0):
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         pts = _device_points(points, dev)
         self.M = pts.shape[0]
@@ -205,7 +226,8 @@ class Plan(_PlanBase):
         self.N_shape = (self.nx, self.ny)
         if stream is None:
             stream = _current_stream(dev)
-        o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph)
+        o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph,
+                  nufft_tol)
         self.ir_tol, self.ir_maxit, self.refine = float(ir_tol), int(ir_maxit), int(refine)
         h = C.c_void_p()
         with torch.cuda.device(dev):
@@ -222,7 +244,7 @@ class BatchPlan(_PlanBase):
 
     def __init__(self, points_list, nx_list, ny_list, *, precision="fp32",
                  eps=1e-4, leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0,
-                 stream=None, mem_cap=0, device=None, graph=False):
+                 stream=None, mem_cap=0, device=None, graph=False, nufft_tol=0.0):
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         pts = [_device_points(p, dev) for p in points_list]
         m_off = np.zeros(len(pts) + 1, dtype=np.int64)
@@ -237,7 +259,8 @@ class BatchPlan(_PlanBase):
         self.N_shape = (int(self.n_off[-1]),)
         if stream is None:
             stream = _current_stream(dev)
-        o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph)
+        o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph,
+                  nufft_tol)
         self.ir_tol, self.ir_maxit, self.refine = float(ir_tol), int(ir_maxit), int(refine)
         h = C.c_void_p()
         with torch.cuda.device(dev):

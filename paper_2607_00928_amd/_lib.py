@@ -29,6 +29,7 @@ class Opts(C.Structure):
         ("stream", C.c_void_p),
         ("mem_cap", C.c_size_t),
         ("graph", C.c_int32),
+        ("nufft_tol", C.c_double),
     ]
 
 
@@ -93,6 +94,8 @@ def _load():
         "nudft2_apply": (C.c_int, [P, P, P, C.c_int32]),
         "nudft2_apply_adj": (C.c_int, [P, P, P, C.c_int32]),
         "nudft2_apply_adj_noalloc": (C.c_int, [P, P, P, C.c_int32]),
+        "nudft2_nufft": (C.c_int, [P, P, P, C.c_int32, C.c_double]),
+        "nudft2_nufft_adj": (C.c_int, [P, P, P, C.c_int32, C.c_double]),
         "nudft2_get_info": (C.c_int, [P, C.POINTER(Info)]),
         "nudft2_destroy": (C.c_int, [P]),
         "nudft2_set_profiling": (C.c_int, [P, C.c_int32]),

@@ -223,6 +223,7 @@ void nudft2_default_opts(nudft2_opts* o) {
   o->stream = nullptr;
   o->mem_cap = 0;
   o->graph = 0;
+  o->nufft_tol = 0.0;
 }
 
 const char* nudft2_strerror(nudft2_status s) {
@@ -330,6 +331,28 @@ nudft2_status nudft2_apply_adj(nudft2_plan_t plan, const double* f, double* c, i
     Plan* P = reinterpret_cast<Plan*>(plan);
     PlanProf pp(P);
     apply_adj(P, reinterpret_cast<const double2*>(f), reinterpret_cast<double2*>(c), nrhs,
+              P->stream);
+  });
+}
+
+nudft2_status nudft2_nufft(nudft2_plan_t plan, const double* c, double* f, int32_t nrhs,
+                           double tol) {
+  return guard([&] {
+    ND_CHECK(plan != nullptr && f != nullptr && c != nullptr, NUDFT2_E_INVAL, "null pointer");
+    ND_CHECK(nrhs > 0, NUDFT2_E_INVAL, "nrhs must be positive");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    nufft_fwd(P, reinterpret_cast<const double2*>(c), reinterpret_cast<double2*>(f), nrhs, tol,
+              P->stream);
+  });
+}
+
+nudft2_status nudft2_nufft_adj(nudft2_plan_t plan, const double* f, double* c, int32_t nrhs,
+                               double tol) {
+  return guard([&] {
+    ND_CHECK(plan != nullptr && f != nullptr && c != nullptr, NUDFT2_E_INVAL, "null pointer");
+    ND_CHECK(nrhs > 0, NUDFT2_E_INVAL, "nrhs must be positive");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    nufft_adj(P, reinterpret_cast<const double2*>(f), reinterpret_cast<double2*>(c), nrhs, tol,
               P->stream);
   });
 }

@@ -50,6 +50,27 @@ struct ApplyProb {
   int nx, ny;
 };
 
+// State of the NUDFT approximation by spreading and FFT (type 2 for A c,
+// type 1 for A^* f), built on first use for a tolerance: the kernel width w
+// and shape beta, per problem the fine grid nfx x nfy and the deconvolution
+// factors 1 / phihat(k / nf) per axis, FFT twiddles per length, and the two
+// fine-grid buffers (grown on demand).
+struct NufftProb {
+  int nfx = 0, nfy = 0;
+  double* invx = nullptr;   // nx entries, centred k
+  double* invy = nullptr;   // ny entries
+};
+struct NufftState {
+  double tol = 0.0;
+  int w = 0;
+  double beta = 0.0;
+  std::vector<NufftProb> probs;
+  std::map<int, double2*> tw;   // FFT length n -> exp(-2 pi i j / n), j < n / 2
+  double2* g1 = nullptr;
+  double2* g2 = nullptr;
+  size_t gbytes = 0;            // bytes of each of g1, g2
+};
+
 struct Plan {
   nudft2_opts opts{};
   hipStream_t stream = nullptr;
@@ -73,6 +94,7 @@ struct Plan {
   // and right-hand side), grown on demand from the arena
   double2* adj_part = nullptr;
   size_t adj_part_bytes = 0;
+  NufftState nufft;
   int* d_tile_off = nullptr;       // apply row-tile prefix (nprob + 1)
   int apply_tiles = 0;
 
@@ -93,5 +115,14 @@ void apply_adj(Plan* P, const double2* f, double2* c, int nrhs, hipStream_t s);
 // apply_adj on the plan's stream with its partial sums in a static device
 // array (no device allocation); E_INVAL when they do not fit
 void apply_adj_noalloc(Plan* P, const double2* f, double2* c, int nrhs);
+
+// A c and A^* f by spreading and FFT to relative accuracy about tol
+// (nufft.hip); the state is built on the first call for a tolerance
+void nufft_fwd(Plan* P, const double2* c, double2* f, int nrhs, double tol, hipStream_t s);
+void nufft_adj(Plan* P, const double2* f, double2* c, int nrhs, double tol, hipStream_t s);
+// the refinement's operators: the NUFFT when opts.nufft_tol > 0, else the
+// exact direct sums
+void op_fwd(Plan* P, const double2* c, double2* f, int nrhs, hipStream_t s);
+void op_adj(Plan* P, const double2* f, double2* c, int nrhs, hipStream_t s);
 
 }  // namespace nd

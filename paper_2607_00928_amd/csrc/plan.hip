@@ -329,6 +329,12 @@ static void validate(int nprob, const double* points, const int64_t* m_off,
   ND_CHECK(o->ir_tol >= 0.0, NUDFT2_E_INVAL, "ir_tol must be >= 0");
   ND_CHECK(o->refine >= 0 && o->refine <= 2, NUDFT2_E_INVAL, "refine must be 0, 1 or 2");
   ND_CHECK(o->graph == 0 || o->graph == 1, NUDFT2_E_INVAL, "graph must be 0 or 1");
+  ND_CHECK(o->nufft_tol == 0.0 || (o->nufft_tol > 0.0 && o->nufft_tol < 0.1), NUDFT2_E_INVAL,
+           "nufft_tol must be 0 or lie in (0, 0.1)");
+  if (o->nufft_tol > 0.0)
+    for (int p = 0; p < nprob; ++p)
+      ND_CHECK(nx[p] <= 1024 && ny[p] <= 1024, NUDFT2_E_INVAL,
+               "the NUFFT operator needs nx, ny <= 1024");
   for (int p = 0; p < nprob; ++p) {
     ND_CHECK(nx[p] >= 2 && ny[p] >= 2 && nx[p] % 2 == 0 && ny[p] % 2 == 0,
              NUDFT2_E_INVAL, "nx, ny must be even and >= 2");

@@ -771,9 +771,9 @@ bool pcg_normal(SolveCtx<T>& sc, double2* c, double2* r, int maxit, double tol, 
   sc.copyk(sc.cx, z, p, N);
   sc.seg_dot(sc.cx, rho, r, z, N);
   auto body = [&](Ctx& k) {
-    apply_fwd(P, p, t, sc.nrhs, k.s);                 // t = A p
+    op_fwd(P, p, t, sc.nrhs, k.s);                 // t = A p
     sc.seg_dot(k, gamma, t, t, M);                    // gamma = ||A p||^2
-    apply_adj(P, t, q, sc.nrhs, k.s);                 // q = A^H A p
+    op_adj(P, t, q, sc.nrhs, k.s);                 // q = A^H A p
     hipLaunchKernelGGL(pcg_alpha_kernel, dim3(1), dim3(256), 0, k.s, rho, gamma, alpha, ns);
     sc.seg_dot(k, pn2, p, p, N);
     sc.seg_axpy(k, alpha, 1.0, p, c, N);              // c += alpha p
@@ -842,12 +842,12 @@ bool plsqr(SolveCtx<T>& sc, const double2* f, double2* c, int maxit, double tol,
     sc.seg_scale(k, inv, x, N);
   };
   auto body = [&](Ctx& k) {
-    apply_fwd(P, v, tM, sc.nrhs, k.s);                // tN = B v
+    op_fwd(P, v, tM, sc.nrhs, k.s);                // tN = B v
     sc.S(k, tM, tN);
     sc.seg_xpay(k, tN, la, -1.0, u, N);               // u = B v - alpha u
     normalise_seg(k, u, lb);                          // beta, u /= beta
     sc.SH(k, u, tM);                                  // tN = B^H u
-    apply_adj(P, tM, tN, sc.nrhs, k.s);
+    op_adj(P, tM, tN, sc.nrhs, k.s);
     sc.seg_xpay(k, tN, lb, -1.0, v, N);               // v = B^H u - beta v
     normalise_seg(k, v, la);                          // alpha, v /= alpha
     hipLaunchKernelGGL(lsqr_rot_kernel, dim3(1), dim3(256), 0, k.s, la, lb, rhobar, phibar,
@@ -865,12 +865,12 @@ bool plsqr(SolveCtx<T>& sc, const double2* f, double2* c, int maxit, double tol,
   while (!conv && upd == upd && its < maxit) {
     // a run starts from the exact residual of the current iterate
     Ctx& k = sc.cx;
-    apply_fwd(P, c, tM, sc.nrhs, k.s);
+    op_fwd(P, c, tM, sc.nrhs, k.s);
     sc.axpby(k, 1.0, f, -1.0, tM, M);                 // tM = f - A c
     sc.S(k, tM, u);                                   // beta_1 u = S r
     normalise_seg(k, u, beta1);
     sc.SH(k, u, tM);                                  // alpha_1 v = B^H u
-    apply_adj(P, tM, v, sc.nrhs, k.s);
+    op_adj(P, tM, v, sc.nrhs, k.s);
     normalise_seg(k, v, la);
     sc.copyk(k, v, w, N);
     ND_HIP(hipMemcpyAsync(phibar, beta1, sizeof(double) * ns, hipMemcpyDeviceToDevice, k.s));
@@ -920,9 +920,9 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
       // first iterate: the direct solution; then CG on the normal equations
       double2* r = sc.vecN();
       sc.S(f, c);
-      apply_fwd(P, c, rM, nrhs, sc.cx.s);
+      op_fwd(P, c, rM, nrhs, sc.cx.s);
       sc.axpby(1.0, f, -1.0, rM, M);
-      apply_adj(P, rM, r, nrhs, sc.cx.s);
+      op_adj(P, rM, r, nrhs, sc.cx.s);
       conv = pcg_normal<T>(sc, c, r, maxit - 1, P->opts.ir_tol, its, upd);
       ++its;
     } else {
@@ -930,7 +930,7 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
       conv = plsqr<T>(sc, f, c, maxit, P->opts.ir_tol, cycle_tol, its, upd);
     }
     // the residual of the returned solution (first right-hand side)
-    apply_fwd(P, c, rM, nrhs, sc.cx.s);
+    op_fwd(P, c, rM, nrhs, sc.cx.s);
     sc.axpby(1.0, f, -1.0, rM, M);
     const double res = sc.total(sc.norms2({{rM, M}}), 0, 0) / std::max(fn, 1e-300);
     report(info, its, upd, res);
@@ -958,7 +958,7 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
   // after its last update; the residual reported is that of the iterate
   // before it (the returned c differs from it by rel_update).
   auto body = [&](Ctx& k) {
-    apply_fwd(P, c, rr, nrhs, k.s);
+    op_fwd(P, c, rr, nrhs, k.s);
     sc.axpby(k, 1.0, f, -1.0, rr, M);
     sc.norm_into(k, 2, rr, M);
     correct(k);
@@ -990,8 +990,8 @@ void normal_solve(SolveCtx<T>& sc, const double2* g, double2* z, int& its, doubl
   double2* u = sc.vecM();
   sc.SH(sc.cx, g, u);                 // z = S S^H g
   sc.S(sc.cx, u, z);
-  apply_fwd(P, z, u, sc.nrhs, sc.cx.s);
-  apply_adj(P, u, r, sc.nrhs, sc.cx.s);
+  op_fwd(P, z, u, sc.nrhs, sc.cx.s);
+  op_adj(P, u, r, sc.nrhs, sc.cx.s);
   sc.axpby(1.0, g, -1.0, r, N);       // r = g - A^H A z
   const bool conv = pcg_normal<T>(sc, z, r, maxit - 1, P->opts.ir_tol, its, upd);
   ++its;
@@ -1006,7 +1006,7 @@ void solve_adj_t(Plan* P, const double2* g, double2* w, int nrhs, nudft2_solve_i
   int its = 0;
   double upd = 0;
   normal_solve<T>(sc, g, z, its, upd);
-  apply_fwd(P, z, w, nrhs, sc.cx.s);
+  op_fwd(P, z, w, nrhs, sc.cx.s);
   ND_HIP(hipStreamSynchronize(sc.cx.s));
   report(info, its, upd, -1);
 }
@@ -1023,10 +1023,10 @@ void lsq_backward_t(Plan* P, const double2* f, const double2* c, const double2* 
   double upd = 0;
   normal_solve<T>(sc, g, z, its, upd);
   double2* w = grad_f ? grad_f : sc.vecM();
-  apply_fwd(P, z, w, nrhs, sc.cx.s);
+  op_fwd(P, z, w, nrhs, sc.cx.s);
   if (grad_pts) {
     double2* r = sc.vecM();
-    apply_fwd(P, c, r, nrhs, sc.cx.s);
+    op_fwd(P, c, r, nrhs, sc.cx.s);
     sc.axpby(1.0, f, -1.0, r, M);
     double2* Y = (double2*)sc.cx.tmp_alloc(sizeof(double2) * 4 * N * nrhs);
     double2* S4 = (double2*)sc.cx.tmp_alloc(sizeof(double2) * 4 * M * nrhs);
@@ -1040,7 +1040,7 @@ void lsq_backward_t(Plan* P, const double2* f, const double2* c, const double2* 
     hipLaunchKernelGGL(kscale_kernel, dim3(grid_for(nmax * nrhs), (unsigned)kd.size()), dim3(256),
                        0, sc.cx.s, dkd, c, z, Y, N, nrhs);
     ND_HIP(hipGetLastError());
-    apply_fwd(P, Y, S4, 4 * nrhs, sc.cx.s);
+    op_fwd(P, Y, S4, 4 * nrhs, sc.cx.s);
     hipLaunchKernelGGL(grad_points_kernel, dim3(grid_for(M)), dim3(256), 0, sc.cx.s, r, w, S4,
                        grad_pts, M, nrhs);
     ND_HIP(hipGetLastError());
