@@ -89,6 +89,10 @@ nudft2_status nudft2_test_pchol(int32_t nb, const int32_t* w, const int32_t* rma
                                 int32_t* piv_out);
 nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims,
                                const int32_t* ld, const int64_t* ptrs, int32_t conj_trans);
+/* in-place inversion of nb upper-triangular matrices (zeros below the
+ * diagonal): k[i], ld[i], ptrs[i] (DEVICE); R_i <- R_i^{-1} */
+nudft2_status nudft2_test_trtri(int32_t prec, int32_t nb, const int32_t* k, const int32_t* ld,
+                                const int64_t* ptrs);
 /* copy with precision change: D_i = S_i (conj_trans[i] = 0, D_i m x n) or
  * D_i = S_i^H (conj_trans[i] != 0, D_i n x m), S_i m x n; prec_d / prec_s
  * select complex128 (0) or complex64 (1) for D and S; dims = (m, n),

@@ -115,6 +115,7 @@ def _load():
         "nudft2_test_ormqr": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, I32P, I32P, I64P]),
         "nudft2_test_pchol": (C.c_int, [C.c_int32, I32P, I32P, I64P, C.c_double, I32P, I32P]),
         "nudft2_test_trsv": (C.c_int, [C.c_int32, C.c_int32, I32P, I32P, I64P, C.c_int32]),
+        "nudft2_test_trtri": (C.c_int, [C.c_int32, C.c_int32, I32P, I32P, I64P]),
         "nudft2_test_copy": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, I32P, I32P, I64P, I32P]),
         "nudft2_test_hss1d_matvec": (C.c_int, [P, C.c_int32, C.c_double, P, P, I32P, C.c_int32]),
         "nudft2_test_hss_matvec": (C.c_int, [P, P, P, C.c_int32, C.c_int32, C.c_int32]),

@@ -531,6 +531,31 @@ nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims, co
   });
 }
 
+nudft2_status nudft2_test_trtri(int32_t prec, int32_t nb, const int32_t* k, const int32_t* ld,
+                                const int64_t* ptrs) {
+  return guard([&] {
+    ND_CHECK(k && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
+    need_device();
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      std::vector<TriDesc<T>> d(nb);
+      for (int i = 0; i < nb; ++i) {
+        ND_CHECK(k[i] >= 0 && ld[i] >= std::max(1, k[i]), NUDFT2_E_INVAL, "bad sizes");
+        d[i] = TriDesc<T>{k[i], ld[i], (cplx<T>*)ptrs[i]};
+      }
+      DescPool pool;
+      pool.init(16 << 20, nullptr);
+      void* ws;
+      ND_HIP(hipMalloc(&ws, trtri_workspace<T>(d)));
+      trtri_upper_batched<T>(pool, d, ws);
+      pool.sync_reset();
+      ND_HIP(hipFree(ws));
+    };
+    if (prec == 0) run(double());
+    else run(float());
+  });
+}
+
 nudft2_status nudft2_test_copy(int32_t prec_d, int32_t prec_s, int32_t nb, const int32_t* dims,
                                const int32_t* ld, const int64_t* ptrs, const int32_t* conj_trans) {
   return guard([&] {

@@ -174,6 +174,19 @@ template <typename T>
 void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d,
                         bool conj_trans = false);
 
+// Batched in-place inversion of upper-triangular matrices: R (k x k, ldr) is
+// overwritten by R^{-1}.  The strictly lower triangle must hold zeros (it
+// stays zero).  ws: trtri_workspace bytes.
+template <typename T>
+struct TriDesc {
+  int k, ldr;
+  cplx<T>* R;
+};
+template <typename T>
+size_t trtri_workspace(const std::vector<TriDesc<T>>& d);
+template <typename T>
+void trtri_upper_batched(DescPool& pool, const std::vector<TriDesc<T>>& d, void* ws);
+
 // Elementwise helpers (batched over descriptors).
 template <typename TD, typename TS>
 struct CopyDesc {

@@ -2319,6 +2319,78 @@ void trsv_upper_batched(DescPool& pool, const std::vector<TrsDesc<T>>& d, bool c
   }
 }
 
+// Triangular inversion.  The TRS_B x TRS_B diagonal blocks are inverted by
+// the triangular-solve kernel against identity columns (the block is copied
+// to the workspace and replaced by I, then solved in place).  Then inverted
+// diagonal groups of g blocks are joined pairwise for g = 1, 2, 4, ...:
+//   inv([R11 R12; 0 R22]) = [X11, -X11 (R12 X22); 0, X22],  Xii = inv(Rii),
+// two batched GEMMs per doubling (T = R12 X22 into the workspace, then
+// R12 <- -X11 T), every pair of every matrix in the same launch.
+template <typename T>
+size_t trtri_workspace(const std::vector<TriDesc<T>>& d) {
+  constexpr int BS = TRS_B;
+  size_t s0 = 0, s1 = 0;
+  for (auto& q : d) {
+    if (q.k <= 0) continue;
+    const size_t nblk = (q.k + BS - 1) / BS;
+    s0 += nblk * BS * BS;
+    s1 += (size_t)q.k * q.k / 2 + (size_t)BS * BS;
+  }
+  return std::max(s0, s1) * sizeof(cplx<T>) + 256;
+}
+
+template <typename T>
+void trtri_upper_batched(DescPool& pool, const std::vector<TriDesc<T>>& d, void* ws) {
+  constexpr int BS = TRS_B;
+  if (d.empty()) return;
+  cplx<T>* w0 = (cplx<T>*)ws;
+  {
+    std::vector<CopyDesc<T, T>> cp;
+    std::vector<FillDesc<T>> fl;
+    std::vector<TrsDesc<T>> ts;
+    cplx<T>* w = w0;
+    for (auto& q : d) {
+      for (int i0 = 0; i0 < q.k; i0 += BS) {
+        const int bs = std::min(BS, q.k - i0);
+        cplx<T>* Rbb = q.R + i0 + (int64_t)i0 * q.ldr;
+        cp.push_back({bs, bs, q.ldr, bs, Rbb, w, 0});
+        fl.push_back({bs, bs, q.ldr, Rbb, 1});
+        ts.push_back({bs, bs, bs, q.ldr, w, Rbb});
+        w += (size_t)BS * BS;
+      }
+    }
+    copy_batched<T, T>(pool, cp);
+    fill_batched<T>(pool, fl);
+    trsv_upper_batched<T>(pool, ts, false);
+  }
+  for (int g = 1;; g *= 2) {
+    std::vector<GemmDesc<T>> g1, g2;
+    cplx<T>* w = w0;
+    for (auto& q : d) {
+      const int nblk = (q.k + BS - 1) / BS;
+      for (int a = 0; a + g < nblk; a += 2 * g) {
+        const int r0 = a * BS, r1 = std::min((a + g) * BS, q.k);
+        const int r2 = std::min((a + 2 * g) * BS, q.k);
+        const int m = r1 - r0, n = r2 - r1;
+        cplx<T>* R12 = q.R + r0 + (int64_t)r1 * q.ldr;
+        const cplx<T>* X22 = q.R + r1 + (int64_t)r1 * q.ldr;
+        const cplx<T>* X11 = q.R + r0 + (int64_t)r0 * q.ldr;
+        g1.push_back({m, n, n, q.ldr, q.ldr, m, R12, X22, w, T(1), T(0), T(0)});
+        g2.push_back({m, n, m, q.ldr, m, q.ldr, X11, w, R12, T(-1), T(0), T(0)});
+        w += (size_t)m * n;
+      }
+    }
+    if (g1.empty()) break;
+    gemm_batched<T>(pool, g1, OpN, OpN);
+    gemm_batched<T>(pool, g2, OpN, OpN);
+  }
+}
+
+template size_t trtri_workspace<float>(const std::vector<TriDesc<float>>&);
+template size_t trtri_workspace<double>(const std::vector<TriDesc<double>>&);
+template void trtri_upper_batched<float>(DescPool&, const std::vector<TriDesc<float>>&, void*);
+template void trtri_upper_batched<double>(DescPool&, const std::vector<TriDesc<double>>&, void*);
+
 // workgroups per descriptor of a copy launch: enough for the largest copy's
 // work items, with the whole grid held to about 64K workgroups when the batch
 // is long (the kernels loop over their items, so any count is correct)

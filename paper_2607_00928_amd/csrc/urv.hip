@@ -17,7 +17,10 @@
 //
 // Storage per node: W = [D~(:,0:k) | U' | D~(:,k:)] so that one QR of its
 // first k columns and one application of P^H to the remaining columns give
-// [U1 D12; U2 D22] in place.
+// [U1 D12; U2 D22] in place.  Once the factorization is complete, D11 and the
+// root's triangle are replaced by their inverses (blocked triangular
+// inversion), which is all the solves use: every triangular solve of a sweep
+// becomes one batched matrix-vector product.
 #include <algorithm>
 
 #include "gen.h"
@@ -373,6 +376,19 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
         qd.push_back({pb.root_m, pb.root_n, pb.rootA.ld, pb.rootR.ld, pb.rootA.p, pb.rootR.p,
                       pb.rootT.p});
     if (!qd.empty()) geqrf_batched<T>(cx.pool, qd, cx.tmp_alloc(qr_workspace<T>(qd)));
+  }
+  // The solves need D11^{-1} and R^{-1} only: invert every node's triangle
+  // and the root's in place, so that each triangular solve of a sweep is one
+  // batched matrix-vector product instead of a chain of blocked substitutions.
+  {
+    std::vector<TriDesc<T>> td;
+    for (auto& pb : H.probs) {
+      for (int l = 1; l <= pb.L; ++l)
+        for (auto& nd : pb.lv[l])
+          if (nd.k > 0) td.push_back({nd.k, nd.D11.ld, nd.D11.p});
+      if (pb.root_n > 0) td.push_back({pb.root_n, pb.rootR.ld, pb.rootR.p});
+    }
+    if (!td.empty()) trtri_upper_batched<T>(cx.pool, td, cx.tmp_alloc(trtri_workspace<T>(td)));
     cx.release_tmp();
     cx.pool.sync_reset();
   }
@@ -402,6 +418,12 @@ void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t
     }
   }
   std::vector<Mat<T>*> mtmp;
+  std::vector<Mat<T>> Rt(np);   // the root's R^{-1} Q^H f
+  for (int p = 0; p < np; ++p) {
+    Rt[p].r = std::max(H.probs[p].root_n, 1);
+    Rt[p].c = nrhs;
+    mtmp.push_back(&Rt[p]);
+  }
   for (int p = 0; p < np; ++p) {
     Prob2<T>& pb = H.probs[p];
     const Problem& q = P->probs[p];
@@ -484,19 +506,25 @@ void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t
     if (!o2.empty()) ormqr_batched<T>(cx.pool, o2, true, cx.tmp_alloc(orm_workspace<T>(o2)));
     copy_batched<T, T>(cx.pool, cd);
   }
-  // ---- root least squares
+  // ---- root least squares: Q^H f, then R^{-1} (stored inverted) through a
+  // temporary and back into the root's buffer
   {
     std::vector<OrmDesc<T>> od;
-    std::vector<TrsDesc<T>> td;
+    std::vector<GemmDesc<T>> gr;
+    std::vector<CopyDesc<T, T>> cr;
     for (int p = 0; p < np; ++p) {
       Prob2<T>& pb = H.probs[p];
       Mat<T>& fr = F[p][0][0];
       if (pb.root_n == 0) continue;
       od.push_back({pb.root_m, pb.root_n, nrhs, pb.rootA.ld, fr.ld, pb.rootA.p, pb.rootT.p, fr.p});
-      td.push_back({pb.root_n, nrhs, pb.rootR.ld, fr.ld, pb.rootR.p, fr.p});
+      Mat<T>& t = Rt[p];
+      gr.push_back({pb.root_n, nrhs, pb.root_n, pb.rootR.ld, fr.ld, t.ld, pb.rootR.p, fr.p, t.p,
+                    T(1), T(0), T(0)});
+      cr.push_back({pb.root_n, nrhs, t.ld, fr.ld, t.p, fr.p, 0});
     }
     ormqr_batched<T>(cx.pool, od, true, cx.tmp_alloc(orm_workspace<T>(od)));
-    trsv_upper_batched<T>(cx.pool, td);
+    gemm_batched<T>(cx.pool, gr, OpN, OpN);
+    copy_batched<T, T>(cx.pool, cr);
     // L == 0: the root solution is the leaf solution
     std::vector<CopyDesc<T, T>> cd;
     for (int p = 0; p < np; ++p) {
@@ -509,9 +537,8 @@ void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t
   }
   // ---- top-down substitution
   for (int l = 1; l <= Lmax; ++l) {
-    std::vector<GemmDesc<T>> gz, gbs[3], gbr, g12, gu1;
-    std::vector<TrsDesc<T>> td;
-    std::vector<CopyDesc<T, T>> cc2, cc1;
+    std::vector<GemmDesc<T>> gz, gbs[3], gbr, g12, gu1, gd1;
+    std::vector<CopyDesc<T, T>> cc2;
     std::vector<OrmDesc<T>> oq;
     for (int p = 0; p < np; ++p) {
       Prob2<T>& pb = H.probs[p];
@@ -575,15 +602,15 @@ void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t
         if (nd.wU > 0)
           gu1.push_back({nd.k, nrhs, nd.wU, U1.ld, Bh[p][l][nd.z].ld, fm.ld, U1.p,
                          Bh[p][l][nd.z].p, fm.p, T(-1), T(0), T(1)});
-        td.push_back({nd.k, nrhs, nd.D11.ld, fm.ld, nd.D11.p, fm.p});
-        cc1.push_back({nd.k, nrhs, fm.ld, cp.ld, fm.p, cp.at(nd.nu, 0), 0});
+        // c1 = D11^{-1} (f1 - D12 c2 - U1 b), straight into the c+ buffer
+        gd1.push_back({nd.k, nrhs, nd.k, nd.D11.ld, fm.ld, cp.ld, nd.D11.p, fm.p,
+                       cp.at(nd.nu, 0), T(1), T(0), T(0)});
         oq.push_back({nd.nn, nd.wV, nrhs, nd.Vm.ld, cp.ld, nd.Vm.p, nd.Tq.p, cp.p});
       }
     }
     gemm_batched<T>(cx.pool, g12, OpN, OpN);
     gemm_batched<T>(cx.pool, gu1, OpN, OpN);
-    trsv_upper_batched<T>(cx.pool, td);
-    copy_batched<T, T>(cx.pool, cc1);
+    gemm_batched<T>(cx.pool, gd1, OpN, OpN);
     if (!oq.empty()) ormqr_batched<T>(cx.pool, oq, false, cx.tmp_alloc(orm_workspace<T>(oq)));
   }
   cx.release_tmp();
@@ -607,6 +634,12 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
   for (auto& pb : H.probs) Lmax = std::max(Lmax, pb.L);
   std::vector<std::vector<std::vector<Mat<T>>>> Fb(np), Cb(np), Bb(np), Zb(np);
   std::vector<Mat<T>*> mtmp;
+  std::vector<Mat<T>> Rt(np);   // the root's R^{-H} c
+  for (int p = 0; p < np; ++p) {
+    Rt[p].r = std::max(H.probs[p].root_n, 1);
+    Rt[p].c = nrhs;
+    mtmp.push_back(&Rt[p]);
+  }
   for (int p = 0; p < np; ++p) {
     Prob2<T>& pb = H.probs[p];
     const Problem& q = P->probs[p];
@@ -682,9 +715,8 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
   // ---- adjoint of the top-down substitution
   for (int l = Lmax; l >= 1; --l) {
     std::vector<OrmDesc<T>> oq;
-    std::vector<CopyDesc<T, T>> cy, cpar;
-    std::vector<TrsDesc<T>> td;
-    std::vector<GemmDesc<T>> g12, gu1, gz[3], gv, gr[4];
+    std::vector<CopyDesc<T, T>> cpar;
+    std::vector<GemmDesc<T>> gd1, g12, gu1, gz[3], gv, gr[4];
     for (int p = 0; p < np; ++p) {
       Prob2<T>& pb = H.probs[p];
       if (l > pb.L) continue;
@@ -693,8 +725,9 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
         Mat<T>& cb = Cb[p][l][nd.z];
         Mat<T>& fb = Fb[p][l][nd.z];
         oq.push_back({nd.nn, nd.wV, nrhs, nd.Vm.ld, cb.ld, nd.Vm.p, nd.Tq.p, cb.p});
-        cy.push_back({nd.k, nrhs, cb.ld, fb.ld, cb.at(nd.nu, 0), fb.p, 0});
-        td.push_back({nd.k, nrhs, nd.D11.ld, fb.ld, nd.D11.p, fb.p});
+        // f1-bar = D11^{-H} c1-bar (D11 stored inverted)
+        gd1.push_back({nd.k, nrhs, nd.k, nd.D11.ld, cb.ld, fb.ld, nd.D11.p, cb.at(nd.nu, 0), fb.p,
+                       T(1), T(0), T(0)});
         Mat<T> U1 = nd.Wm.sub(0, nd.k, nd.k, nd.wU);
         Mat<T> D12 = nd.Wm.sub(0, nd.k + nd.wU, nd.k, nd.nu);
         if (nd.nu > 0)
@@ -706,8 +739,7 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
       }
     }
     if (!oq.empty()) ormqr_batched<T>(cx.pool, oq, true, cx.tmp_alloc(orm_workspace<T>(oq)));
-    copy_batched<T, T>(cx.pool, cy);
-    trsv_upper_batched<T>(cx.pool, td, true);
+    gemm_batched<T>(cx.pool, gd1, OpC, OpN);
     gemm_batched<T>(cx.pool, g12, OpC, OpN);
     gemm_batched<T>(cx.pool, gu1, OpC, OpN);
     // Z-bar of a node: its siblings' b-bar through their interaction blocks
@@ -757,9 +789,9 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
   }
   // ---- adjoint of the root least-squares step: f_root = Q [R^{-H} c_root; 0]
   {
-    std::vector<CopyDesc<T, T>> cd;
+    std::vector<CopyDesc<T, T>> cd, cr;
     std::vector<FillDesc<T>> fz;
-    std::vector<TrsDesc<T>> td;
+    std::vector<GemmDesc<T>> gr;
     std::vector<OrmDesc<T>> od;
     for (int p = 0; p < np; ++p) {
       Prob2<T>& pb = H.probs[p];
@@ -769,12 +801,17 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
       if (pb.root_m > pb.root_n)
         fz.push_back({pb.root_m - pb.root_n, nrhs, fr.ld, fr.at(pb.root_n, 0), 0});
       if (pb.root_n == 0) continue;
-      td.push_back({pb.root_n, nrhs, pb.rootR.ld, fr.ld, pb.rootR.p, fr.p});
+      // R^{-H} (R stored inverted) through a temporary and back
+      Mat<T>& t = Rt[p];
+      gr.push_back({pb.root_n, nrhs, pb.root_n, pb.rootR.ld, fr.ld, t.ld, pb.rootR.p, fr.p, t.p,
+                    T(1), T(0), T(0)});
+      cr.push_back({pb.root_n, nrhs, t.ld, fr.ld, t.p, fr.p, 0});
       od.push_back({pb.root_m, pb.root_n, nrhs, pb.rootA.ld, fr.ld, pb.rootA.p, pb.rootT.p, fr.p});
     }
     copy_batched<T, T>(cx.pool, cd);
     fill_batched<T>(cx.pool, fz);
-    trsv_upper_batched<T>(cx.pool, td, true);
+    gemm_batched<T>(cx.pool, gr, OpC, OpN);
+    copy_batched<T, T>(cx.pool, cr);
     if (!od.empty()) ormqr_batched<T>(cx.pool, od, false, cx.tmp_alloc(orm_workspace<T>(od)));
   }
   // ---- adjoint of the bottom-up sweep: unstack, P, Omega
@@ -817,7 +854,8 @@ template void urv_factor<double>(Ctx&, HSS2<double>&);
 // Stored entries each step of urv_solve reads: the reflector blocks of
 // Omega, P and Q0 with their compact-WY factors, V^_2 (z = V^_2^H c2), the
 // sibling couplings B and the parent transfer R (b^), D12 and U1, the
-// triangle D11, and the root's reflectors, factor and triangle.
+// inverted triangle D11 (read as a full square by its matrix-vector product),
+// and the root's reflectors, factor and inverted triangle (likewise).
 template <typename T>
 int64_t urv_sweep_bytes(const HSS2<T>& H) {
   double e = 0;
@@ -827,7 +865,7 @@ int64_t urv_sweep_bytes(const HSS2<T>& H) {
         if (nd.sizered) e += (double)nd.mm * nd.mchk + qr_tsize(nd.mm, nd.mchk);
         if (nd.k > 0) {
           e += (double)nd.mchk * nd.k + qr_tsize(nd.mchk, nd.k);
-          e += (double)nd.k * (nd.k + 1) / 2 + (double)nd.k * nd.nu + (double)nd.k * nd.wU;
+          e += (double)nd.k * nd.k + (double)nd.k * nd.nu + (double)nd.k * nd.wU;
         }
         e += (double)nd.nu * nd.wV;
         if (nd.wV > 0) e += (double)nd.nn * nd.wV + qr_tsize(nd.nn, nd.wV);
@@ -836,7 +874,7 @@ int64_t urv_sweep_bytes(const HSS2<T>& H) {
       }
     if (pb.root_n > 0)
       e += (double)pb.root_m * pb.root_n + qr_tsize(pb.root_m, pb.root_n) +
-           (double)pb.root_n * (pb.root_n + 1) / 2;
+           (double)pb.root_n * pb.root_n;
   }
   return (int64_t)(e * sizeof(cplx<T>));
 }

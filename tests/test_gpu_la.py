@@ -748,3 +748,32 @@ def test_gemm_partial_tile_splits(prec, opa, opb):
             got = from_dev(tc, m, n)
             scale = max(1.0, np.abs(ref).max())
             assert np.abs(got - ref).max() < TOL[prec] * scale * max(k, 1) ** 0.5 * 10, (m, n, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_trtri_inverts_upper_triangles(prec):
+    """Batched in-place inversion of upper-triangular matrices (the solves'
+    stored D11^{-1} and root R^{-1}) against LAPACK's inverse, for orders
+    around the 128-row diagonal blocks and the doubling joins."""
+    rng = np.random.default_rng(77 + prec)
+    ks = [1, 5, 128, 129, 300, 1000, 1537]
+    keep, ref, kk, ld, ptr = [], [], [], [], []
+    for k in ks:
+        R = np.triu(crandn(rng, k, k)) / np.sqrt(k)
+        R[np.diag_indices(k)] = 1.0 + 0.5 * rng.random(k) * np.exp(2j * np.pi * rng.random(k))
+        t = to_dev(R, prec)
+        keep.append(t)
+        ref.append(np.linalg.inv(R))
+        kk.append(k)
+        ld.append(k)
+        ptr.append(t.data_ptr())
+    a1, p1 = i32(kk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    assert lib.nudft2_test_trtri(prec, len(ks), p1, p2, p3) == 0, lib.nudft2_last_error()
+    for k, t, X in zip(ks, keep, ref):
+        got = from_dev(t, k, k)
+        err = np.linalg.norm(got - X) / np.linalg.norm(X)
+        print(f"trtri k={k} prec{prec}: {err:.1e}")
+        assert np.abs(np.tril(got, -1)).max() == 0
+        assert err < (1e-13 if prec == 0 else 2e-5) * max(1.0, np.log2(k))
