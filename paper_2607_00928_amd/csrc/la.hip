@@ -495,6 +495,61 @@ __global__ __launch_bounds__(256) void gemm_skinny_n_kernel(DS descs, int splits
       if (j < d.n) skinny_store(d, i, j, acc[j], splits);
 }
 
+// op(A) = A for short, tall batches: a workgroup takes 64 rows of C and its
+// four waves split the k range into quarters (lane = row, SK_U loads of A in
+// flight per lane, B read by uniform loads), then the waves' partial sums
+// meet in LDS.  Four times the workgroups of gemm_skinny_n_kernel for the
+// same rows: the sweep's reflector updates C -= V W on a few tall nodes
+// otherwise leave most CUs idle.
+template <typename T, int NC, class DS>
+__global__ __launch_bounds__(256) void gemm_skinny_n4_kernel(DS descs, int splits) {
+  using C2 = cplx<T>;
+  __shared__ C2 red[3][64][NC];
+  const GemmDesc<T> d = descs[blockIdx.y];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * 64;
+  if (i0 >= d.m || d.n <= 0) return;
+  const int kc = (d.k + splits - 1) / splits;
+  const int kb0 = blockIdx.z * kc, ke0 = min(d.k, kb0 + kc);
+  if (kb0 >= ke0 && splits > 1) return;
+  const int kq = (max(ke0 - kb0, 0) + 3) / 4;
+  const int kb = kb0 + wave * kq, ke = min(ke0, kb + kq);
+  const int i = i0 + lane;
+  const bool row = i < d.m;
+  C2 acc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) acc[j] = mk<T>(0, 0);
+  const C2* ap = d.A + (row ? i : 0);
+  int l = kb;
+  for (; l + SK_U <= ke; l += SK_U) {
+    C2 a[SK_U];
+#pragma unroll
+    for (int u = 0; u < SK_U; ++u) a[u] = row ? ldc(ap + (int64_t)(l + u) * d.lda) : mk<T>(0, 0);
+#pragma unroll
+    for (int u = 0; u < SK_U; ++u)
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        if (j < d.n) acc[j] = cadd(acc[j], cmul(a[u], ldc(d.B + (int64_t)(l + u) + (int64_t)j * d.ldb)));
+  }
+  for (; l < ke; ++l) {
+    const C2 a = row ? ldc(ap + (int64_t)l * d.lda) : mk<T>(0, 0);
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      if (j < d.n) acc[j] = cadd(acc[j], cmul(a, ldc(d.B + (int64_t)l + (int64_t)j * d.ldb)));
+  }
+  if (wave > 0)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) red[wave - 1][lane][j] = acc[j];
+  __syncthreads();
+  if (wave == 0 && row)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      if (j >= d.n) break;
+      const C2 v = cadd(acc[j], cadd(red[0][lane][j], cadd(red[1][lane][j], red[2][lane][j])));
+      skinny_store(d, i, j, v, splits);
+    }
+}
+
 // op(A) = A^H: wave w computes row i of C (a dot product along column i of
 // A) over NC columns; each lane keeps SK_U / 2 independent loads in flight.
 template <typename T, int NC, class DS>
@@ -1600,7 +1655,11 @@ template <typename T>
 static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, Op opA, int maxm,
                            int maxn, int maxk, int force) {
   const size_t n = sub.size();
-  const int rows_per_wg = opA == OpN ? 256 : 4;
+  // op N: 256 rows per workgroup, or 64 rows with the k range split over the
+  // four waves (gemm_skinny_n4_kernel) when 256-row workgroups would not
+  // fill the device
+  const bool n4 = opA == OpN && (int64_t)((maxm + 255) / 256) * (int64_t)n < 1024;
+  const int rows_per_wg = opA == OpN ? (n4 ? 64 : 256) : 4;
   const int64_t bx = (maxm + rows_per_wg - 1) / rows_per_wg;
   int64_t wgs = bx * (int64_t)n;
   int splits = 1;
@@ -1632,7 +1691,10 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
     dim3 grid((unsigned)bx, (unsigned)n, (unsigned)splits);
     auto launch = [&](auto nc) {
       constexpr int NC = decltype(nc)::value;
-      if (opA == OpN)
+      if (opA == OpN && n4)
+        hipExtLaunchKernelGGL((gemm_skinny_n4_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
+                              ps.start(), ps.stop(), 0, dd, splits);
+      else if (opA == OpN)
         hipExtLaunchKernelGGL((gemm_skinny_n_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
                               ps.start(), ps.stop(), 0, dd, splits);
       else
