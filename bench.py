@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="only the timed steps (no sweep, apply, FP64 or CPU extras): the "
                          "command the rocprofv3 summaries are taken on")
+    ap.add_argument("--profile-sweep", action="store_true",
+                    help="factor once (untimed), then --steps direct solves (no refinement): "
+                         "the command the sweep's rocprofv3 summaries are taken on")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU (asked for --gpus {args.gpus}); the sharded "
@@ -95,6 +98,23 @@ def main():
     f = p0.apply(c_true)
     torch.cuda.synchronize()
     p0.close()
+
+    if args.profile_sweep:
+        plan = nd.Plan(pr.points, nx, ny, precision="fp32", eps=args.eps, ir_maxit=0)
+        plan.factor()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            plan.solve(f)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        sb = plan.info()["sweep_bytes"]
+        plan.close()
+        med = float(np.median(ts))
+        print(json.dumps({"metric": "direct solve (profile run)", "ms": 1e3 * med,
+                          "sweep_bytes": sb, "gbps": sb / med / 1e9}))
+        return
 
     def step(precision, profile=False):
         t0 = time.perf_counter()
@@ -160,11 +180,20 @@ def main():
     per_launch = kfl[dominant] / max(kn[dominant], 1)
     ach = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 and per_launch > 0 else None
     pk = peaks[dominant]
+    rec = gemm_record() if dominant == 1 else None
     roof = dict(bound="mfma", achieved=ach, peak=pk, unit="TFLOP/s",
                 frac=(ach / pk if ach is not None and pk else None),
-                traffic=gemm_traffic() if dominant == 1 else None,
+                traffic=rec["hbm_bytes_per_launch"] if rec else None,
                 kernel=names[dominant], avg_launch_ms=avg_ms, launches=kn[dominant],
                 flops_per_launch=per_launch)
+    if rec and ach is not None:
+        # achieved counts 8 algorithmic flops per complex multiply-add; the
+        # matrix cores execute fewer (Gauss's three real products), as the
+        # committed PMC record measures: executed rate / peak, and the busy
+        # counter's fraction of the class's time
+        ex = rec["executed_mfma_flops_per_launch"] / rec["flops_per_launch"]
+        roof.update(executed_frac=ach * ex / pk, mfma_busy_frac=rec["mfma_busy_frac"],
+                    algorithmic_flop_per_hbm_byte=rec["flops_per_launch"] / rec["hbm_bytes_per_launch"])
     kernels = {names[i]: dict(ms=kms[i], launches=kn[i],
                               tflops=(kfl[i] / (kms[i] * 1e-3) / 1e12 if kms[i] > 0 and kfl[i] > 0 else None))
                for i in range(4)}
@@ -290,11 +319,11 @@ def main():
     print(json.dumps(out))
 
 
-def gemm_traffic():
-    """HBM bytes per launch of the FP32 GEMM class, from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy of known
-    size); None when the kernel source changed since the counters were
-    taken."""
+def gemm_record():
+    """The FP32 GEMM class's committed rocprofv3 PMC record (HBM bytes per
+    launch from FETCH_SIZE / WRITE_SIZE scaled by a plain copy of known size;
+    executed matrix-core flops and busy fraction); None when the kernel source
+    changed since the counters were taken."""
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "gemm_fp32_traffic_n512.md")
     src = os.path.join(root, "paper_2607_00928_amd", "csrc", "la.hip")
@@ -303,7 +332,7 @@ def gemm_traffic():
         with open(src, "rb") as fh:
             if hashlib.sha256(fh.read()).hexdigest() != rec["la_hip_sha256"]:
                 return None
-        return rec["hbm_bytes_per_launch"]
+        return rec
     except Exception:
         return None
 
