@@ -184,6 +184,12 @@ nudft2_status nudft2_solve(nudft2_plan_t plan, const double* f, double* c,
 nudft2_status nudft2_set_solve_opts(nudft2_plan_t plan, double ir_tol, int32_t ir_maxit,
                                     int32_t refine);
 
+/* Change the refinement's operator of a plan (opts.nufft_tol: 0 the exact
+ * direct sums, in (0, 0.1) the NUFFT at that accuracy), factored or not.
+ * Errors: E_INVAL (null plan, tolerance out of range, nx or ny > 1024 for a
+ * positive tolerance). */
+nudft2_status nudft2_set_nufft_tol(nudft2_plan_t plan, double nufft_tol);
+
 /* Adjoint of the least-squares solution operator (Section 4.1 applies the
  * adjoint of the factored solution operator, a 2D FFT followed by the
  * adjoint URV solve; here it preconditions the normal equations):

@@ -100,6 +100,11 @@ class _PlanBase:
         self.ir_tol, self.ir_maxit, self.refine = tol, maxit, ref
         return self
 
+    def set_nufft_tol(self, tol: float):
+        """Refinement operator: 0 the exact direct sums, > 0 the NUFFT."""
+        check(lib.nudft2_set_nufft_tol(self._handle, float(tol)), "nudft2_set_nufft_tol")
+        return self
+
     def set_profiling(self, on: bool = True):
         check(lib.nudft2_set_profiling(self._handle, 1 if on else 0), "nudft2_set_profiling")
 

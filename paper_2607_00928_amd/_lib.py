@@ -99,6 +99,7 @@ def _load():
         "nudft2_get_info": (C.c_int, [P, C.POINTER(Info)]),
         "nudft2_destroy": (C.c_int, [P]),
         "nudft2_set_profiling": (C.c_int, [P, C.c_int32]),
+        "nudft2_set_nufft_tol": (C.c_int, [P, C.c_double]),
         "nudft2_set_solve_opts": (C.c_int, [P, C.c_double, C.c_int32, C.c_int32]),
         "nudft2_strerror": (C.c_char_p, [C.c_int]),
         "nudft2_last_error": (C.c_char_p, []),

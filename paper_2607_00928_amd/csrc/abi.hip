@@ -398,6 +398,20 @@ nudft2_status nudft2_set_solve_opts(nudft2_plan_t plan, double ir_tol, int32_t i
   });
 }
 
+nudft2_status nudft2_set_nufft_tol(nudft2_plan_t plan, double nufft_tol) {
+  return guard([&] {
+    ND_CHECK(plan != nullptr, NUDFT2_E_INVAL, "null plan");
+    ND_CHECK(nufft_tol == 0.0 || (nufft_tol > 0.0 && nufft_tol < 0.1), NUDFT2_E_INVAL,
+             "nufft_tol must be 0 or lie in (0, 0.1)");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    if (nufft_tol > 0.0)
+      for (auto& q : P->probs)
+        ND_CHECK(q.nx <= 1024 && q.ny <= 1024, NUDFT2_E_INVAL,
+                 "the NUFFT operator needs nx, ny <= 1024");
+    P->opts.nufft_tol = nufft_tol;
+  });
+}
+
 nudft2_status nudft2_set_profiling(nudft2_plan_t plan, int32_t on) {
   return guard([&] {
     ND_CHECK(plan != nullptr, NUDFT2_E_INVAL, "null plan");

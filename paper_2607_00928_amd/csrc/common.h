@@ -82,6 +82,9 @@ struct Arena {
   void release(void* p);
   void release_all();
   size_t block_size(const void* p) const;
+  // hand slabs that hold no live block back to the device (synchronises the
+  // device first); returns the bytes freed
+  size_t trim();
   void check(const char* where);
   ~Arena() { release_all(); }
 

@@ -109,6 +109,12 @@ void* Arena::alloc(size_t n) {
       want = span;
       e = hipMalloc(&p, want);
     }
+    if (e != hipSuccess && trim() > 0) {
+      // slabs left entirely free (fragmentation of earlier phases) went back
+      // to the device: try once more
+      (void)hipGetLastError();
+      e = hipMalloc(&p, want);
+    }
     if (e != hipSuccess) {
       (void)hipGetLastError();
       throw Error(NUDFT2_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -126,6 +132,32 @@ void* Arena::alloc(size_t n) {
   bytes += n;
   peak = std::max(peak, bytes);
   return p;
+}
+
+size_t Arena::trim() {
+  // Blocks are released once their last use is ordered on the plan's stream;
+  // wait for the device before handing slabs back.
+  if (hipDeviceSynchronize() != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  size_t freed = 0;
+  for (size_t i = 0; i < slabs.size();) {
+    const uintptr_t a = (uintptr_t)slabs[i].first;
+    const size_t n = slabs[i].second;
+    auto it = free_by_addr.find(a);
+    if (it != free_by_addr.end() && it->second == n) {
+      take_free(it);
+      slab_start.erase(a);
+      (void)hipFree(slabs[i].first);
+      reserved -= n;
+      freed += n;
+      slabs.erase(slabs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+  return freed;
 }
 
 size_t Arena::block_size(const void* p) const {
@@ -152,6 +184,11 @@ void Arena::release(void* p) {
 }
 
 void Arena::check(const char* where) {
+  // NUDFT2_MEM_LOG=1: the arena's live, peak and reserved bytes at each check
+  static const bool mem_log = env_on("NUDFT2_MEM_LOG");
+  if (mem_log)
+    std::fprintf(stderr, "[nudft2 mem] %-28s live %8.2f GB  peak %8.2f GB  reserved %8.2f GB\n",
+                 where, bytes / 1e9, peak / 1e9, reserved / 1e9);
   if (quarantine_on()) {
     ND_HIP(hipDeviceSynchronize());
     for (auto& q : g_quarantine) {

@@ -369,13 +369,16 @@ void factor_t(Plan* P) {
   build_1d(cx, 0, P->opts.eps / 10, tx);
   build_1d(cx, 1, P->opts.eps / 10, ty);
   ND_HIP(hipStreamSynchronize(cx.s));
+  P->arena.check("1D compression");
   double t1 = now_ms();
   build_2d<T>(cx, tx, ty, P->opts.eps, *H, 2);
   free_1d(P, tx);
   free_1d(P, ty);
   ND_HIP(hipStreamSynchronize(cx.s));
+  P->arena.check("recompression");
   double t2 = now_ms();
   urv_factor<T>(cx, *H);
+  P->arena.check("URV factorization");
   // inverse DFT matrices
   for (size_t p = 0; p < P->probs.size(); ++p) {
     Prob2<T>& pb = H->probs[p];

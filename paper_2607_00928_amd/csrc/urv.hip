@@ -228,6 +228,7 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
       if (!qd.empty()) geqrf_batched<T>(cx.pool, qd, cx.tmp_alloc(qr_workspace<T>(qd)));
       if (!od.empty()) ormqr_batched<T>(cx.pool, od, true, cx.tmp_alloc(orm_workspace<T>(od)));
     }
+    P->arena.check("URV level");
     // ---- merge into the parents
     {
       struct PRef { int p, l, z; };
