@@ -1982,9 +1982,16 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const std::vector<int>
   }();
   constexpr int rows = 128 * QPanel<T>::R;
   int gsize = std::max(1, (maxmr + rows - 1) / rows);
-  // taller panels: twice the rows per workgroup (RM = 2)
-  const bool tall = gsize > mres;
-  if (tall) gsize = std::max(1, (maxmr + 2 * rows - 1) / (2 * rows));
+  // Twice the rows per workgroup (RM = 2): for panels taller than the device
+  // holds otherwise, and for multi-workgroup panels when the halved groups
+  // still fill every CU (many problems): fewer workgroups exchange column
+  // sums, which outweighs the spilled registers (1024 leaf panels of
+  // 1024 x 430: 42.5 -> 32.1 ms FP32; 1024 x 500 x 300 FP64: 32.6 -> 23.7 ms);
+  // with few tall problems the halved group count leaves CUs idle (16 x 5000:
+  // 7.4 -> 7.9 ms), so those keep RM = 1.
+  const int gsize2 = std::max(1, (maxmr + 2 * rows - 1) / (2 * rows));
+  const bool tall = gsize > mres || (gsize > 1 && (int64_t)nact * gsize2 >= mres);
+  if (tall) gsize = gsize2;
   ND_CHECK(gsize <= mres, NUDFT2_E_INTERNAL, "QR panel taller than the device can hold");
   int ngroups = std::max(1, std::min(nact, mres / gsize));
   const size_t per_group = sizeof(T) == 4 ? qp_tag_words(gsize) * sizeof(unsigned long long)
