@@ -13,6 +13,7 @@ namespace nd {
 
 static thread_local std::string g_last_error;
 thread_local Profiler* g_prof = nullptr;
+thread_local int g_prof_site = PS_NONE;
 
 namespace {
 std::mutex g_ev_mu;

@@ -120,6 +120,7 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
 
   // ------------------------------------------------ face-split assembly
   {
+    ProfSite fs_site_(PS_FACESPLIT);
     // leaves
     std::vector<LeafDesc<T>> ud;
     std::vector<LeafVDesc<T>> vd;
@@ -280,6 +281,7 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
 
   // ------------------------------------------------ stage 1 (bottom-up)
   if (stages >= 1) {
+    ProfSite site_(PS_S1_PROJ);
     // leaves: U = U~ F, V = V~ G
     std::vector<Mat<T>> A, Q, R;
     std::vector<std::tuple<int, int, int>> who;   // (p, z, 0=U / 1=V)
@@ -317,7 +319,10 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
           R.push_back(nd.G);
         }
       }
-      orth<T>(cx, A, Q, &R);
+      {
+        ProfSite orth_site_(PS_S1_QR);
+        orth<T>(cx, A, Q, &R);
+      }
       A.clear(); Q.clear(); R.clear();
       ND_HIP(hipStreamSynchronize(cx.s));
       cx.release_tmp();
@@ -432,7 +437,10 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
               R.push_back(nd.G);
             }
           }
-          orth<T>(cx, A, Q, &R);
+          {
+            ProfSite orth_site_(PS_S1_QR);
+            orth<T>(cx, A, Q, &R);
+          }
           bd.own(p, l, Builder<T>::K_F, cf, old);
           bd.own(p, lc, Builder<T>::K_R, cq, old);
           bd.own(p, lc, Builder<T>::K_W, nullptr, old);
@@ -478,6 +486,7 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
 
   // ------------------------------------------------ stage 2 (top-down)
   if (stages >= 2) {
+    ProfSite s2_site_(PS_S2_UPDATE);
     const double tol2 = eps * eps;
     for (int l = 1; l <= Lmax; ++l) {
       struct Ref { int p, z; };
@@ -618,8 +627,11 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
           copy_batched<double, G>(cx.pool, cd);
         }
       };
-      if (std::is_same<T, float>::value && eps >= 5e-3) form_grams(float{});
-      else form_grams(double{});
+      {
+        ProfSite gram_site_(PS_S2_GRAM);
+        if (std::is_same<T, float>::value && eps >= 5e-3) form_grams(float{});
+        else form_grams(double{});
+      }
       // rank decisions
       std::vector<Mat<double>> Ks;
       std::vector<int> rmax;
@@ -630,7 +642,10 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
         rmax.push_back(KV[i].r);
       }
       std::vector<PcholOut> po;
-      pchol_run(cx, Ks, rmax, tol2, po);
+      {
+        ProfSite pchol_site_(PS_S2_PCHOL);
+        pchol_run(cx, Ks, rmax, tol2, po);
+      }
       // P = orth(L) and its triangular factor T, in the working precision (the
       // rank decisions above are the FP64 part)
       std::vector<Mat<T>> A, Q, R;
@@ -675,7 +690,11 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
         }
       }
       copy_batched<T, double>(cx.pool, lcd);
-      orth<T>(cx, A, Q, &R);
+      {
+        ProfSite orth_site_(PS_S2_ORTH);
+        orth<T>(cx, A, Q, &R);
+      }
+      ProfSite upd_site_(PS_S2_UPDATE);
       // ---- updates
       // B^_{alpha,s} = P_alpha^H B Q_s
       std::map<int, std::vector<Mat<T>*>> mnb;   // per problem

@@ -1152,18 +1152,17 @@ __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(
       }
     }
     if (w == 0) {
-      // rows above the panel move from A to R; R below the panel's diagonal
-      // block is zero (nothing else writes it)
-      for (int e = tid; e < jb * j0; e += QP_NT) {
-        const int r = e % j0, c = e / j0;
+      // the rows above the panel inside its block of QR_OB columns move from
+      // A to R (the block's reflectors are read from row J0 on, so these
+      // must be zero before the block's later steps); the rows above the
+      // block and R below the panel's diagonal block are left to
+      // qr_finish_kernel, which runs with the whole device
+      const int J0 = j0 - j0 % QR_OB, na = j0 - J0;
+      for (int e = tid; e < jb * na; e += QP_NT) {
+        const int r = J0 + e % na, c = e / na;
         C2* pa = d.A + r + (int64_t)(j0 + c) * d.lda;
         d.R[r + (int64_t)(j0 + c) * d.ldr] = *pa;
         *pa = mk<T>(0, 0);
-      }
-      const int nz = kmin - j0 - jb;
-      for (int e = tid; e < jb * nz; e += QP_NT) {
-        const int r = j0 + jb + e % nz, c = e / nz;
-        d.R[r + (int64_t)(j0 + c) * d.ldr] = mk<T>(0, 0);
       }
       const int blk = (j0 % QR_OB) / QR_NB;
       C2* Tb = d.Tw + (int64_t)blk * QR_NB * QR_NB;
@@ -1264,15 +1263,32 @@ __global__ __launch_bounds__(WY_NT) void wy_merge_kernel(DS descs) {
   }
 }
 
-// copy of the trailing columns of wide problems (n > m) into R at the end
+// The end of a factorization, over all of R (kmin x n): for column c < kmin
+// of the block starting at J0, the rows above J0 move from A to R (A keeps
+// zeros there) and R below the diagonal block of c's panel is zero (the
+// panels wrote the rows from J0 to the end of their diagonal blocks); the
+// trailing columns of wide problems (n > m) are copied into R.
 template <typename T>
-__global__ void qr_wide_tail_kernel(const QRDesc<T>* __restrict__ descs) {
+__global__ void qr_finish_kernel(const QRDesc<T>* __restrict__ descs) {
   const QRDesc<T> d = descs[blockIdx.y];
-  if (d.n <= d.m) return;
-  int64_t cnt = (int64_t)d.m * (d.n - d.m);
+  const int kmin = min(d.m, d.n);
+  if (kmin <= 0) return;
+  const int64_t cnt = (int64_t)kmin * d.n;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
-    int r = (int)(e % d.m), c = d.m + (int)(e / d.m);
-    d.R[r + (int64_t)c * d.ldr] = d.A[r + (int64_t)c * d.lda];
+    const int r = (int)(e % kmin), c = (int)(e / kmin);
+    cplx<T>* pr = d.R + r + (int64_t)c * d.ldr;
+    cplx<T>* pa = d.A + r + (int64_t)c * d.lda;
+    if (c >= kmin) {
+      *pr = *pa;
+      continue;
+    }
+    const int J0 = c - c % QR_OB, pe = min(c - c % QR_NB + QR_NB, kmin);
+    if (r < J0) {
+      *pr = *pa;
+      *pa = mk<T>(0, 0);
+    } else if (r >= pe) {
+      *pr = mk<T>(0, 0);
+    }
   }
 }
 
@@ -2010,7 +2026,14 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const std::vector<int>
     void* args[] = {(void*)&dd, (void*)&as, (void*)&nact, (void*)&j0, (void*)&gsize,
                     (void*)&scr, (void*)&bar, (void*)&err};
     ProfScope ps(pool.stream, KC_QRPANEL, 0.0, nact, maxmr, 0, 0, gsize);
-    ND_HIP(hipLaunchCooperativeKernel(k, dim3(ngroups * gsize), dim3(QP_NT), args, 0, pool.stream));
+    static const bool plain = [] {
+      const char* e = std::getenv("NUDFT2_PANEL_LAUNCH");
+      return e && std::strcmp(e, "plain") == 0;
+    }();
+    if (plain)
+      ND_HIP(hipLaunchKernel(k, dim3(ngroups * gsize), dim3(QP_NT), args, 0, pool.stream));
+    else
+      ND_HIP(hipLaunchCooperativeKernel(k, dim3(ngroups * gsize), dim3(QP_NT), args, 0, pool.stream));
   });
 }
 
@@ -2187,7 +2210,11 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& din, void* ws) 
     gemm_batched<T>(pool, g2, OpC, OpN);
     gemm_batched<T>(pool, g3, OpN, OpN);
   }
-  hipLaunchKernelGGL((qr_wide_tail_kernel<T>), dim3(64, nb), dim3(256), 0, pool.stream, dd);
+  int64_t rmax = 0;
+  for (auto& q : d) rmax = std::max<int64_t>(rmax, (int64_t)qr_kmin(q.m, q.n) * std::max(q.n, 0));
+  const int64_t fx = std::max<int64_t>(1, std::min<int64_t>((rmax + 2047) / 2048,
+                                                          std::max(16, 16384 / nb)));
+  hipLaunchKernelGGL((qr_finish_kernel<T>), dim3((unsigned)fx, nb), dim3(256), 0, pool.stream, dd);
   ND_HIP(hipGetLastError());
 }
 

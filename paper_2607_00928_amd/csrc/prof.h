@@ -20,12 +20,28 @@ enum KClass { KC_APPLY = 0, KC_GEMM32 = 1, KC_GEMM64 = 2, KC_QRPANEL = 3, KC_COU
 hipEvent_t event_cache_get(int dev);
 void event_cache_put(int dev, hipEvent_t e);
 
+// Step of the factorization or solve that issues the current launches
+// (ProfSite below); written as the last column of the optional launch log.
+enum PSite {
+  PS_NONE = 0, PS_1D = 1, PS_FACESPLIT = 2, PS_S1_QR = 3, PS_S1_PROJ = 4, PS_S2_GRAM = 5,
+  PS_S2_PCHOL = 6, PS_S2_ORTH = 7, PS_S2_UPDATE = 8, PS_URV_SIZERED = 9, PS_URV_VQR = 10,
+  PS_URV_DQ = 11, PS_URV_PARTIAL = 12, PS_URV_MERGE = 13, PS_URV_ROOT = 14, PS_URV_INV = 15,
+  PS_SOLVE = 16, PS_APPLY = 17
+};
+extern thread_local int g_prof_site;
+struct ProfSite {
+  int old;
+  explicit ProfSite(int s) : old(g_prof_site) { g_prof_site = s; }
+  ~ProfSite() { g_prof_site = old; }
+};
+
 struct Profiler {
   struct Rec {
     hipEvent_t a, b;
     int cls;
     double flops;
     int info[5];   // launch shape for the optional log: descriptors, max m, n, k, variant
+    int site;      // PSite of the launch
   };
   std::vector<Rec> recs;
   int dev = -1;   // the plan's device, taken at the first event
@@ -44,20 +60,21 @@ struct Profiler {
   }
   // a pair whose timestamps the dispatches record themselves
   void push(hipEvent_t a, hipEvent_t b, int cls, double fl, const int* info) {
-    Rec r{a, b, cls, fl, {0, 0, 0, 0, 0}};
+    Rec r{a, b, cls, fl, {0, 0, 0, 0, 0}, g_prof_site};
     for (int i = 0; i < 5; ++i) r.info[i] = info[i];
     recs.push_back(r);
   }
   void end(hipStream_t s, int cls, double fl, hipEvent_t a, const int* info) {
     hipEvent_t b = get();
     ND_HIP(hipEventRecord(b, s));
-    Rec r{a, b, cls, fl, {0, 0, 0, 0, 0}};
+    Rec r{a, b, cls, fl, {0, 0, 0, 0, 0}, g_prof_site};
     for (int i = 0; i < 5; ++i) r.info[i] = info[i];
     recs.push_back(r);
   }
   // fold recorded pairs into the totals (synchronises on the last event)
   void collect() {
-    // NUDFT2_PROF_LOG=<file>: one line per timed launch (class, ms, flops, shape)
+    // NUDFT2_PROF_LOG=<file>: one line per timed launch (class, ms, flops,
+    // shape, step)
     static const char* logname = std::getenv("NUDFT2_PROF_LOG");
     FILE* log = logname ? std::fopen(logname, "a") : nullptr;
     for (auto& r : recs) {
@@ -65,8 +82,8 @@ struct Profiler {
       float t = 0;
       ND_HIP(hipEventElapsedTime(&t, r.a, r.b));
       if (log)
-        std::fprintf(log, "%d %.6f %.6e %d %d %d %d %d\n", r.cls, t, r.flops, r.info[0], r.info[1],
-                     r.info[2], r.info[3], r.info[4]);
+        std::fprintf(log, "%d %.6f %.6e %d %d %d %d %d %d\n", r.cls, t, r.flops, r.info[0],
+                     r.info[1], r.info[2], r.info[3], r.info[4], r.site);
       ms[r.cls] += t;
       flops[r.cls] += r.flops;
       launches[r.cls] += 1;

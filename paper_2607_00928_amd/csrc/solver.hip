@@ -366,8 +366,11 @@ void factor_t(Plan* P) {
   ND_HIP(hipStreamSynchronize(cx.s));
   double t0 = now_ms();
   std::vector<Tree1> tx, ty;
-  build_1d(cx, 0, P->opts.eps / 10, tx);
-  build_1d(cx, 1, P->opts.eps / 10, ty);
+  {
+    ProfSite site_(PS_1D);
+    build_1d(cx, 0, P->opts.eps / 10, tx);
+    build_1d(cx, 1, P->opts.eps / 10, ty);
+  }
   ND_HIP(hipStreamSynchronize(cx.s));
   P->arena.check("1D compression");
   double t1 = now_ms();
@@ -429,7 +432,10 @@ void hss_inverse(Ctx& cx, HSS2<T>& H, const double2* r, double2* d, int nrhs, So
                      dim3(256), 0, cx.s, dpd, P->pts_2d, P->perm2d, r, P->Mtot, inv_scale, w.fw,
                      P->Mtot, nrhs);
   ND_HIP(hipGetLastError());
-  urv_solve<T>(cx, H, w.fw, P->Mtot, w.cw, P->Ntot, nrhs);
+  {
+    ProfSite site_(PS_SOLVE);
+    urv_solve<T>(cx, H, w.fw, P->Mtot, w.cw, P->Ntot, nrhs);
+  }
   hipLaunchKernelGGL((post_sol_kernel<T>), dim3(grid_for(P->Ntot * nrhs)), dim3(256), 0, cx.s,
                      w.cw, P->Ntot, P->colperm, scale, w.chat, P->Ntot, P->Ntot, nrhs);
   ND_HIP(hipGetLastError());

@@ -154,6 +154,7 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
     }
     // ---- size reduction
     {
+      ProfSite site_(PS_URV_SIZERED);
       std::vector<QRDesc<T>> qd;
       for (size_t i = 0; i < nodes.size(); ++i) {
         Node2<T>& nd = N(nodes[i]);
@@ -172,6 +173,7 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
     }
     // ---- basis elimination: QR of V
     {
+      ProfSite site_(PS_URV_VQR);
       std::vector<QRDesc<T>> qd;
       for (size_t i = 0; i < nodes.size(); ++i) {
         Node2<T>& nd = N(nodes[i]);
@@ -182,6 +184,7 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
     }
     // ---- W = [D~(:,0:k) | U' | D~(:,k:)] with D~ = D' Q
     {
+      ProfSite site_(PS_URV_DQ);
       std::vector<Mat<T>> X(nodes.size());
       std::vector<Mat<T>*> mx;
       for (size_t i = 0; i < nodes.size(); ++i) {
@@ -215,6 +218,7 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
     }
     // ---- partial decomposition
     {
+      ProfSite site_(PS_URV_PARTIAL);
       std::vector<QRDesc<T>> qd;
       std::vector<OrmDesc<T>> od;
       for (size_t i = 0; i < nodes.size(); ++i) {
@@ -231,6 +235,7 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
     P->arena.check("URV level");
     // ---- merge into the parents
     {
+      ProfSite site_(PS_URV_MERGE);
       struct PRef { int p, l, z; };
       std::vector<PRef> par;
       for (int p = 0; p < np; ++p) {
@@ -376,12 +381,14 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
       if (pb.root_n > 0)
         qd.push_back({pb.root_m, pb.root_n, pb.rootA.ld, pb.rootR.ld, pb.rootA.p, pb.rootR.p,
                       pb.rootT.p});
+    ProfSite site_(PS_URV_ROOT);
     if (!qd.empty()) geqrf_batched<T>(cx.pool, qd, cx.tmp_alloc(qr_workspace<T>(qd)));
   }
   // The solves need D11^{-1} and R^{-1} only: invert every node's triangle
   // and the root's in place, so that each triangular solve of a sweep is one
   // batched matrix-vector product instead of a chain of blocked substitutions.
   {
+    ProfSite site_(PS_URV_INV);
     std::vector<TriDesc<T>> td;
     for (auto& pb : H.probs) {
       for (int l = 1; l <= pb.L; ++l)

@@ -171,6 +171,9 @@ def test_geqrf_ormqr(prec):
         Q = from_dev(tQ, m, m)
         R = from_dev(tR, k, n)
         assert np.abs(np.tril(R, -1)).max() == 0
+        # A returns the explicit unit lower-trapezoidal reflectors
+        V = from_dev(tA, m, n)[:, :k]
+        assert np.abs(np.triu(V, 1)).max() == 0 and np.all(np.diag(V) == 1), (m, n)
         err = np.abs(Q[:, :k] @ R - A).max() / np.abs(A).max()
         orth = np.abs(Q.conj().T @ Q - np.eye(m)).max()
         print(f"qr {m}x{n} prec{prec}: recon {err:.1e} orth {orth:.1e}")
