@@ -2026,14 +2026,7 @@ void qr_panel_launch(DescPool& pool, const QRDesc<T>* dd, const std::vector<int>
     void* args[] = {(void*)&dd, (void*)&as, (void*)&nact, (void*)&j0, (void*)&gsize,
                     (void*)&scr, (void*)&bar, (void*)&err};
     ProfScope ps(pool.stream, KC_QRPANEL, 0.0, nact, maxmr, 0, 0, gsize);
-    static const bool plain = [] {
-      const char* e = std::getenv("NUDFT2_PANEL_LAUNCH");
-      return e && std::strcmp(e, "plain") == 0;
-    }();
-    if (plain)
-      ND_HIP(hipLaunchKernel(k, dim3(ngroups * gsize), dim3(QP_NT), args, 0, pool.stream));
-    else
-      ND_HIP(hipLaunchCooperativeKernel(k, dim3(ngroups * gsize), dim3(QP_NT), args, 0, pool.stream));
+    ND_HIP(hipLaunchCooperativeKernel(k, dim3(ngroups * gsize), dim3(QP_NT), args, 0, pool.stream));
   });
 }
 

@@ -77,7 +77,9 @@ def collect(workload: str, log_path: str):
 
 def classes(rows, top: int):
     out = {}
-    for cls, ms, _fl, ndesc, m, n, k, var in rows:
+    for row in rows:
+        # class, ms, flops, descriptors, m, n, k, variant (then the algorithm step)
+        cls, ms, _fl, ndesc, m, n, k, var = row[:8]
         if int(cls) not in (1, 2) or m <= 0 or n <= 0 or k <= 0:
             continue
         prec = 1 if int(cls) == 1 else 0

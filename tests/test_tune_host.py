@@ -35,3 +35,11 @@ def test_classes_bucket_and_rank():
     assert k0 == (1, 0, 0, 13, 13, 13, 4) and c0["ms"] == 12.0 and c0["count"] == 2
     assert (c0["m"], c0["n"], c0["k"], c0["nd"]) == (5753, 6000, 5753, 12)
     assert k1 == (0, 1, 0, 4, 4, 20, 5)
+
+
+def test_classes_accept_step_column():
+    # launch logs carry the algorithm step as a ninth column
+    rows = np.array([[1, 5.0, 1e9, 12, 5753, 5753, 5753, 10, 9],
+                     [1, 2.0, 1e9, 12, 5000, 6000, 5500, 10, 3]])
+    cl = tg.classes(rows, top=10)
+    assert len(cl) == 1 and cl[0][1]["ms"] == 7.0 and cl[0][1]["count"] == 2
