@@ -116,6 +116,15 @@ struct Node2 {
   Mat<T> U, V;               // leaves
   Mat<T> R, W;               // l >= 2
   Mat<T> B[3];               // l >= 1: with the siblings in child order
+  // Structure of the face-split B[s] (Theorem 3.3) until stage 1 replaces
+  // it: one nonzero block, rows [r0, r0 + h) x columns [c0, c0 + w), equal to
+  // I (x) F1 (bcase 0, cnt = dx diagonal copies of the kr x kc factor F1),
+  // F1 (x) I (bcase 1, index u dy + v, cnt = dy) or F1 (x) F2 (bcase 2, used
+  // as the materialised block).  f: the 1D factor F1 (FP64, leading dim ldf).
+  struct KronB {
+    int bcase = 2, r0 = 0, h = 0, c0 = 0, w = 0, cnt = 0, kr = 0, kc = 0, ldf = 0;
+    const double2* f = nullptr;
+  } kb[3];
   Mat<T> F, G;               // stage-1 factors
   Mat<T> TU, TV;             // stage-2 weights (r x r)
   // URV factorization (Section 2.4): the node is a leaf of the (reduced) HSS

@@ -252,16 +252,22 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
             b.out = nd.B[s].p;
             b.dx = nd.dx; b.dy = nd.dy; b.rx = ax.rU; b.ry = by.rU;
             b.cdx = sb.dx; b.cdy = sb.dy; b.crx = axs.rV; b.cry = bys.rV;
+            auto& kb = nd.kb[s];
             if (sb.a == nd.a) {
               b.bcase = 0;
               b.Y = by.B.p; b.ldY = by.B.ld;
+              kb = {0, 0, b.dx * b.ry, 0, b.cdx * b.cry, b.dx, b.ry, b.cry, by.B.ld, by.B.p};
             } else if (sb.b == nd.b) {
               b.bcase = 1;
               b.X = ax.B.p; b.ldX = ax.B.ld;
+              kb = {1, b.dx * b.ry, b.rx * b.dy, b.cdx * b.cry, b.crx * b.cdy, b.dy, b.rx, b.crx,
+                    ax.B.ld, ax.B.p};
             } else {
               b.bcase = 2;
               b.X = ax.B.p; b.ldX = ax.B.ld;
               b.Y = by.B.p; b.ldY = by.B.ld;
+              kb = {2, b.dx * b.ry + b.rx * b.dy, b.rx * b.ry, b.cdx * b.cry + b.crx * b.cdy,
+                    b.crx * b.cry, 1, 0, 0, 0, nullptr};
             }
             ad.push_back(b);
           }
@@ -343,38 +349,74 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
         int l = pb.L - h;
         if (l < 0) continue;
         int lc = l + 1;
-        // B~_{ci,cj} = F_ci B_{ci,cj} G_cj^H for the children (level lc)
-        std::vector<Mat<T>*> mb, mx;
-        std::vector<Mat<T>> X(pb.lv[lc].size() * 3), NB(pb.lv[lc].size() * 3);
+        // B~_{ci,cj} = F_ci B_{ci,cj} G_cj^H for the children (level lc).  The
+        // face-split B has a single nonzero block Bblk (rows R, columns C),
+        // so B~ = F(:, R) Z with Z^H = G(:, C) Bblk^H; for Bblk = I (x) F1 or
+        // F1 (x) I, Z^H is a batch of products with the small factor F1.
+        std::vector<Mat<T>*> mb, mx, mk;
+        const size_t n3 = pb.lv[lc].size() * 3;
+        std::vector<Mat<T>> X(n3), NB(n3), Kf(n3);
         for (auto& nd : pb.lv[lc]) {
           int c = nd.z & 3;
           for (int s = 0; s < 3; ++s) {
             const Node2<T>& sb = pb.lv[lc][(nd.z & ~3) | Builder<T>::sib_child(c, s)];
-            X[nd.z * 3 + s].r = nd.B[s].r;
-            X[nd.z * 3 + s].c = sb.G.r;
-            NB[nd.z * 3 + s].r = nd.F.r;
-            NB[nd.z * 3 + s].c = sb.G.r;
-            mx.push_back(&X[nd.z * 3 + s]);
-            mb.push_back(&NB[nd.z * 3 + s]);
+            const size_t i = (size_t)nd.z * 3 + s;
+            const auto& kb = nd.kb[s];
+            X[i].r = sb.G.r;
+            X[i].c = kb.h;
+            NB[i].r = nd.F.r;
+            NB[i].c = sb.G.r;
+            mx.push_back(&X[i]);
+            mb.push_back(&NB[i]);
+            if (kb.bcase < 2) {
+              Kf[i].r = kb.kr;
+              Kf[i].c = kb.kc;
+              mk.push_back(&Kf[i]);
+            }
           }
         }
         carve(P->arena, mx, &cx.tmp);
+        carve(P->arena, mk, &cx.tmp);
         void* cb = carve(P->arena, mb);
+        std::vector<CopyDesc<T, double>> kcd;
         std::vector<GemmDesc<T>> g1, g2;
         for (auto& nd : pb.lv[lc]) {
           int c = nd.z & 3;
           for (int s = 0; s < 3; ++s) {
             const Node2<T>& sb = pb.lv[lc][(nd.z & ~3) | Builder<T>::sib_child(c, s)];
-            Mat<T>& x = X[nd.z * 3 + s];
-            Mat<T>& nb = NB[nd.z * 3 + s];
-            g1.push_back({x.r, x.c, sb.G.c, nd.B[s].ld, sb.G.ld, x.ld, nd.B[s].p, sb.G.p, x.p,
-                          T(1), T(0), T(0)});
-            g2.push_back({nb.r, nb.c, nd.F.c, nd.F.ld, x.ld, nb.ld, nd.F.p, x.p, nb.p, T(1), T(0),
-                          T(0)});
+            const size_t i = (size_t)nd.z * 3 + s;
+            const auto& kb = nd.kb[s];
+            Mat<T>& x = X[i];
+            Mat<T>& nb = NB[i];
+            if (nb.r <= 0 || nb.c <= 0) continue;
+            if (x.c > 0) {
+              if (kb.bcase == 2) {
+                g1.push_back({x.r, x.c, kb.w, sb.G.ld, nd.B[s].ld, x.ld,
+                              sb.G.p + (int64_t)kb.c0 * sb.G.ld, nd.B[s].p + kb.r0 +
+                              (int64_t)kb.c0 * nd.B[s].ld, x.p, T(1), T(0), T(0)});
+              } else {
+                Mat<T>& kf = Kf[i];
+                if (kb.kr > 0 && kb.kc > 0) kcd.push_back({kb.kr, kb.kc, kb.ldf, kf.ld, kb.f, kf.p, 0});
+                for (int u = 0; u < kb.cnt; ++u) {
+                  if (kb.bcase == 0)   // columns u kr .. of Z^H from columns c0 + u kc .. of G
+                    g1.push_back({x.r, kb.kr, kb.kc, sb.G.ld, kf.ld, x.ld,
+                                  sb.G.p + (int64_t)(kb.c0 + u * kb.kc) * sb.G.ld, kf.p,
+                                  x.p + (int64_t)u * kb.kr * x.ld, T(1), T(0), T(0)});
+                  else                 // columns u cnt + v of Z^H from columns c0 + u' cnt + v of G
+                    g1.push_back({x.r, kb.kr, kb.kc, (int)((int64_t)kb.cnt * sb.G.ld), kf.ld,
+                                  (int)((int64_t)kb.cnt * x.ld),
+                                  sb.G.p + (int64_t)(kb.c0 + u) * sb.G.ld, kf.p,
+                                  x.p + (int64_t)u * x.ld, T(1), T(0), T(0)});
+                }
+              }
+            }
+            g2.push_back({nb.r, nb.c, x.c, nd.F.ld, x.ld, nb.ld, nd.F.p + (int64_t)kb.r0 * nd.F.ld,
+                          x.p, nb.p, T(1), T(0), T(0)});
           }
         }
+        copy_batched<T, double>(cx.pool, kcd);
         gemm_batched<T>(cx.pool, g1, OpN, OpC);
-        gemm_batched<T>(cx.pool, g2, OpN, OpN);
+        gemm_batched<T>(cx.pool, g2, OpN, OpC);
         std::vector<Mat<T>> SR, SW, QR_, QW_, FR, FW;
         std::vector<Mat<T>*> ms, mnew, mf;
         std::vector<Mat<T>> sr(pb.lv[l].size()), sw(pb.lv[l].size()), qr(pb.lv[l].size()),
