@@ -125,6 +125,18 @@ struct Node2 {
     int bcase = 2, r0 = 0, h = 0, c0 = 0, w = 0, cnt = 0, kr = 0, kc = 0, ldf = 0;
     const double2* f = nullptr;
   } kb[3];
+  // Structure of the face-split R (kind 0) and W (kind 1) of a node at level
+  // >= 2 until stage 1 consumes them: row blocks [dx ry | rx dy | rx ry] of
+  // the node, column blocks [cdx cry | crx cdy | crx cry] of the parent, the
+  // node's x / y columns at own_x / own_y of the parent's, its sibling's
+  // (dsx / dsy of them) at sib_x / sib_y; X, Y the 1D transfer factors and
+  // BX, BY the 1D sibling terms (R only), all FP64.
+  struct KronRW {
+    int dx = 0, dy = 0, rx = 0, ry = 0, cdx = 0, cdy = 0, crx = 0, cry = 0;
+    int own_x = 0, own_y = 0, sib_x = 0, sib_y = 0, dsx = 0, dsy = 0;
+    const double2 *X = nullptr, *Y = nullptr, *BX = nullptr, *BY = nullptr;
+    int ldX = 0, ldY = 0, ldBX = 0, ldBY = 0;
+  } kr, kw;
   Mat<T> F, G;               // stage-1 factors
   Mat<T> TU, TV;             // stage-2 weights (r x r)
   // URV factorization (Section 2.4): the node is a leaf of the (reduced) HSS

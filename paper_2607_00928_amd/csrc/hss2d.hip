@@ -73,6 +73,115 @@ struct Builder {
 
 }  // namespace
 
+// P = F Z for a face-split transfer matrix Z (kind 0: R, kind 1: W; Theorem
+// 3.3) described by k: F is the node's stage-1 factor (ku x the node's basis
+// width), P a row slab of the parent's stacked matrix (ku x the parent's
+// width).  With the node's row groups g0 | g1 | g2 and the parent's column
+// groups G0 | G1 | G2 (see Node2::KronRW), Z has the blocks
+//   Z00 = S_own (x) Y,  Z11 = X (x) S_own,  Z22 = X (x) Y   (R and W),
+//   Z20 = BX_sib (x) Y, Z21 = X (x) BY_sib                 (R only),
+// where S_own places the node's x (y) columns at their offset in the
+// parent's and BX_sib (BY_sib) places the sibling term at the sibling's
+// columns.  Own and sibling columns partition G0 and G1, so each column of P
+// comes from one term; every term is a batch of products with the small 1D
+// factors (FP64 factors converted to the working precision first), through
+// T1 = F(:, g2) (I (x) Y) and T2 = F(:, g2) (I (x) BY) for the two-factor
+// terms.  P is cleared first (W has no sibling terms).
+template <typename T>
+struct KronJob {
+  int kind;
+  const typename Node2<T>::KronRW* k;
+  Mat<T> F;   // ku x (dx ry + rx dy + rx ry)
+  Mat<T> P;   // ku x (cdx cry + crx cdy + crx cry)
+};
+
+template <typename T>
+static void kron_transfer_products(Ctx& cx, const std::vector<KronJob<T>>& jobs) {
+  Plan* P = cx.P;
+  const size_t nj = jobs.size();
+  std::vector<Mat<T>> Xc(nj), Yc(nj), BXc(nj), BYc(nj), T1(nj), T2(nj);
+  std::vector<Mat<T>*> mk;
+  for (size_t i = 0; i < nj; ++i) {
+    const auto& k = *jobs[i].k;
+    const int ku = jobs[i].F.r;
+    Xc[i].r = k.rx; Xc[i].c = k.crx;
+    Yc[i].r = k.ry; Yc[i].c = k.cry;
+    T1[i].r = ku; T1[i].c = k.rx * k.cry;
+    mk.push_back(&Xc[i]);
+    mk.push_back(&Yc[i]);
+    mk.push_back(&T1[i]);
+    if (jobs[i].kind == 0) {
+      BXc[i].r = k.rx; BXc[i].c = k.dsx;
+      BYc[i].r = k.ry; BYc[i].c = k.dsy;
+      T2[i].r = ku; T2[i].c = k.rx * k.dsy;
+      mk.push_back(&BXc[i]);
+      mk.push_back(&BYc[i]);
+      mk.push_back(&T2[i]);
+    }
+  }
+  carve(P->arena, mk, &cx.tmp);
+  std::vector<FillDesc<T>> fz;
+  std::vector<CopyDesc<T, double>> cd;
+  std::vector<GemmDesc<T>> g1, g2;
+  auto conv = [&](const double2* src, int ld, Mat<T>& dst) {
+    if (dst.r > 0 && dst.c > 0) cd.push_back({dst.r, dst.c, ld, dst.ld, src, dst.p, 0});
+  };
+  // C (m x n, ldc) = A (m x kk, lda) B (kk x n, ldb); skipped when empty
+  auto mm = [](std::vector<GemmDesc<T>>& g, int m, int n, int kk, const cplx<T>* A, int64_t lda,
+               const cplx<T>* B, int ldb, cplx<T>* C, int64_t ldc) {
+    if (m > 0 && n > 0 && kk > 0)
+      g.push_back({m, n, kk, (int)lda, ldb, (int)ldc, A, B, C, T(1), T(0), T(0)});
+  };
+  for (size_t i = 0; i < nj; ++i) {
+    const auto& k = *jobs[i].k;
+    const Mat<T>& F = jobs[i].F;
+    const Mat<T>& Pm = jobs[i].P;
+    const int ku = F.r;
+    if (ku <= 0 || Pm.c <= 0) continue;
+    fz.push_back({Pm.r, Pm.c, Pm.ld, Pm.p, 0});
+    conv(k.X, k.ldX, Xc[i]);
+    conv(k.Y, k.ldY, Yc[i]);
+    const int64_t lf = F.ld, lp = Pm.ld;
+    const int g1o = k.dx * k.ry, g2o = k.dx * k.ry + k.rx * k.dy;
+    const int G1o = k.cdx * k.cry, G2o = k.cdx * k.cry + k.crx * k.cdy;
+    // Z00: P(:, (own_x + u) cry + .) = F(:, u ry + .) Y
+    for (int u = 0; u < k.dx; ++u)
+      mm(g1, ku, k.cry, k.ry, F.p + (int64_t)u * k.ry * lf, lf, Yc[i].p, Yc[i].ld,
+         Pm.p + (int64_t)(k.own_x + u) * k.cry * lp, lp);
+    // Z11: P(:, G1 + u' cdy + own_y + v) = sum_u F(:, g1 + u dy + v) X(u, u')
+    for (int v = 0; v < k.dy; ++v)
+      mm(g1, ku, k.crx, k.rx, F.p + (int64_t)(g1o + v) * lf, (int64_t)k.dy * lf, Xc[i].p,
+         Xc[i].ld, Pm.p + (int64_t)(G1o + k.own_y + v) * lp, (int64_t)k.cdy * lp);
+    // T1(:, u cry + .) = F(:, g2 + u ry + .) Y
+    for (int u = 0; u < k.rx; ++u)
+      mm(g1, ku, k.cry, k.ry, F.p + (int64_t)(g2o + u * k.ry) * lf, lf, Yc[i].p, Yc[i].ld,
+         T1[i].p + (int64_t)u * k.cry * T1[i].ld, T1[i].ld);
+    // Z22: P(:, G2 + u' cry + w) = sum_u T1(:, u cry + w) X(u, u')
+    for (int w = 0; w < k.cry; ++w)
+      mm(g2, ku, k.crx, k.rx, T1[i].p + (int64_t)w * T1[i].ld, (int64_t)k.cry * T1[i].ld,
+         Xc[i].p, Xc[i].ld, Pm.p + (int64_t)(G2o + w) * lp, (int64_t)k.cry * lp);
+    if (jobs[i].kind != 0) continue;
+    conv(k.BX, k.ldBX, BXc[i]);
+    conv(k.BY, k.ldBY, BYc[i]);
+    // T2(:, u dsy + .) = F(:, g2 + u ry + .) BY
+    for (int u = 0; u < k.rx; ++u)
+      mm(g1, ku, k.dsy, k.ry, F.p + (int64_t)(g2o + u * k.ry) * lf, lf, BYc[i].p, BYc[i].ld,
+         T2[i].p + (int64_t)u * k.dsy * T2[i].ld, T2[i].ld);
+    // Z20: P(:, (sib_x + q) cry + w) = sum_u T1(:, u cry + w) BX(u, q)
+    for (int w = 0; w < k.cry; ++w)
+      mm(g2, ku, k.dsx, k.rx, T1[i].p + (int64_t)w * T1[i].ld, (int64_t)k.cry * T1[i].ld,
+         BXc[i].p, BXc[i].ld, Pm.p + (int64_t)(k.sib_x * k.cry + w) * lp, (int64_t)k.cry * lp);
+    // Z21: P(:, G1 + u' cdy + sib_y + q) = sum_u T2(:, u dsy + q) X(u, u')
+    for (int q = 0; q < k.dsy; ++q)
+      mm(g2, ku, k.crx, k.rx, T2[i].p + (int64_t)q * T2[i].ld, (int64_t)k.dsy * T2[i].ld,
+         Xc[i].p, Xc[i].ld, Pm.p + (int64_t)(G1o + k.sib_y + q) * lp, (int64_t)k.cdy * lp);
+  }
+  fill_batched<T>(cx.pool, fz);
+  copy_batched<T, double>(cx.pool, cd);
+  gemm_batched<T>(cx.pool, g1, OpN, OpN);
+  gemm_batched<T>(cx.pool, g2, OpN, OpN);
+}
+
 template <typename T>
 void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& ty, double eps,
               HSS2<T>& H, int stages) {
@@ -238,6 +347,17 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
             w.X = ax.W.p; w.ldX = ax.W.ld;
             w.Y = by.W.p; w.ldY = by.W.ld;
             ad.push_back(w);
+            for (int kind = 0; kind < 2; ++kind) {
+              const AsmDesc<T>& a = kind == 0 ? r : w;
+              auto& k = kind == 0 ? nd.kr : nd.kw;
+              k.dx = a.dx; k.dy = a.dy; k.rx = a.rx; k.ry = a.ry;
+              k.cdx = a.cdx; k.cdy = a.cdy; k.crx = a.crx; k.cry = a.cry;
+              k.own_x = a.own_x; k.own_y = a.own_y; k.sib_x = a.sib_x; k.sib_y = a.sib_y;
+              k.dsx = a.dsx; k.dsy = a.dsy;
+              k.X = a.X; k.ldX = a.ldX; k.Y = a.Y; k.ldY = a.ldY;
+              k.BX = kind == 0 ? a.BX : nullptr; k.ldBX = a.ldBX;
+              k.BY = kind == 0 ? a.BY : nullptr; k.ldBY = a.ldBY;
+            }
           }
           int c = nd.z & 3;
           for (int s = 0; s < 3; ++s) {
@@ -450,20 +570,20 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
             mf.push_back(&nd.G);
           }
           carve(P->arena, ms, &cx.tmp);
-          std::vector<GemmDesc<T>> gs;
-          for (auto& nd : pb.lv[l]) {
-            int ou = 0, ov = 0;
-            for (int c = 0; c < 4; ++c) {
-              Node2<T>& ch = pb.lv[lc][4 * nd.z + c];
-              gs.push_back({ch.F.r, nd.wU, ch.F.c, ch.F.ld, ch.R.ld, sr[nd.z].ld, ch.F.p, ch.R.p,
-                            sr[nd.z].at(ou, 0), T(1), T(0), T(0)});
-              gs.push_back({ch.G.r, nd.wV, ch.G.c, ch.G.ld, ch.W.ld, sw[nd.z].ld, ch.G.p, ch.W.p,
-                            sw[nd.z].at(ov, 0), T(1), T(0), T(0)});
-              ou += ch.F.r;
-              ov += ch.G.r;
+          {
+            std::vector<KronJob<T>> jobs;
+            for (auto& nd : pb.lv[l]) {
+              int ou = 0, ov = 0;
+              for (int c = 0; c < 4; ++c) {
+                Node2<T>& ch = pb.lv[lc][4 * nd.z + c];
+                jobs.push_back({0, &ch.kr, ch.F, sr[nd.z].sub(ou, 0, ch.F.r, nd.wU)});
+                jobs.push_back({1, &ch.kw, ch.G, sw[nd.z].sub(ov, 0, ch.G.r, nd.wV)});
+                ou += ch.F.r;
+                ov += ch.G.r;
+              }
             }
+            kron_transfer_products<T>(cx, jobs);
           }
-          gemm_batched<T>(cx.pool, gs, OpN, OpN);
           void* cq = carve(P->arena, mnew);
           void* cf = carve(P->arena, mf);
           std::vector<Mat<T>> A, Q, R;
