@@ -43,6 +43,9 @@ GRID_WORKLOADS = {
 
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+# kernel classes of the library's per-launch timing (nudft2_info.kernel_ms)
+NCLASS = 6
+TIMED_CLASSES = (0, 1, 2, 3)
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -122,7 +125,10 @@ def main():
         plan = nd.Plan(pr.points, nx, ny, precision=precision, eps=args.eps, ir_maxit=200,
                        ir_tol=args.ir_tol, refine=args.refine)
         if profile:
-            plan.set_profiling(True)
+            # per-launch events for the apply, the matrix-core GEMMs and the
+            # Householder panels; the memory-bound skinny products (thousands
+            # of short launches, covered by the sweep figure) record none
+            plan.set_profiling(True, classes=TIMED_CLASSES)
         t1 = time.perf_counter()
         plan.factor()
         torch.cuda.synchronize()
@@ -141,12 +147,12 @@ def main():
         plan.close()
     torch.cuda.synchronize()
     recs = []
-    kms, kfl, kn = [0.0] * 4, [0.0] * 4, [0] * 4
+    kms, kfl, kn = [0.0] * NCLASS, [0.0] * NCLASS, [0] * NCLASS
 
     def fold(pl):
         # read back a plan's per-launch HIP events (recorded during its step)
         inf_k = pl.info()
-        for i in range(4):
+        for i in range(NCLASS):
             kms[i] += inf_k["kernel_ms"][i]
             kfl[i] += inf_k["kernel_flops"][i]
             kn[i] += inf_k["kernel_launches"][i]
@@ -177,9 +183,10 @@ def main():
     last_plan = live[-1]
     info = last_plan.info()
     # kernel classes timed with HIP events on the plan's stream over the timed steps
-    names = ["apply_fp64", "gemm_fp32_mfma", "gemm_fp64_mfma", "qr_panel"]
-    dominant = max(range(4), key=lambda i: kms[i])
-    peaks = [FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS, FP64_PEAK_TFLOPS, None]
+    names = ["apply_fp64", "gemm_fp32_mfma", "gemm_fp64_mfma", "qr_panel", "gemv_fp32",
+             "gemv_fp64"]
+    dominant = max(range(NCLASS), key=lambda i: kms[i])
+    peaks = [FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS, FP64_PEAK_TFLOPS, None, None, None]
     avg_ms = kms[dominant] / max(kn[dominant], 1)
     per_launch = kfl[dominant] / max(kn[dominant], 1)
     ach = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 and per_launch > 0 else None
@@ -200,7 +207,7 @@ def main():
                     algorithmic_flop_per_hbm_byte=rec["flops_per_launch"] / rec["hbm_bytes_per_launch"])
     kernels = {names[i]: dict(ms=kms[i], launches=kn[i],
                               tflops=(kfl[i] / (kms[i] * 1e-3) / 1e12 if kms[i] > 0 and kfl[i] > 0 else None))
-               for i in range(4)}
+               for i in range(NCLASS) if i in TIMED_CLASSES}
 
     extra = {}
     if args.profile_only:

@@ -114,12 +114,13 @@ typedef struct {
   double t_plan_ms, t_compress_ms, t_facesplit_ms, t_recompress_ms, t_urv_ms;
   /* kernel timing while profiling is on (nudft2_set_profiling), per class:
    * 0 = exact FP64 apply, 1 = FP32 matrix-core GEMM, 2 = FP64 matrix-core
-   * GEMM, 3 = Householder panel.  Milliseconds from HIP events recorded on
+   * GEMM, 3 = Householder panel, 4 / 5 = FP32 / FP64 skinny products (at
+   * most 8 columns, memory bound).  Milliseconds from HIP events recorded on
    * the plan's stream around each launch; algorithmic flops (8 per complex
    * multiply-add of the launch's problems); launch counts. */
-  double kernel_ms[4];
-  double kernel_flops[4];
-  int64_t kernel_launches[4];
+  double kernel_ms[6];
+  double kernel_flops[6];
+  int64_t kernel_launches[6];
   int64_t peak_bytes;     /* most device bytes the plan's arena held at once
                              (factors plus the factorization's workspaces)  */
 } nudft2_info;
@@ -262,9 +263,14 @@ nudft2_status nudft2_nufft_adj(nudft2_plan_t plan, const double* f, double* c, i
 /* Fill *info (HOST).  Synchronises with the plan's stream. */
 nudft2_status nudft2_get_info(nudft2_plan_t plan, nudft2_info* info);
 
-/* Turn per-kernel-class event timing on (1) or off (0); resets the totals.
- * Synchronises with the plan's stream. */
+/* Turn per-kernel-class event timing on (1: every class) or off (0); resets
+ * the totals.  Synchronises with the plan's stream. */
 nudft2_status nudft2_set_profiling(nudft2_plan_t plan, int32_t on);
+/* Event timing for the classes whose bits are set in `classes` (bit c =
+ * class c of nudft2_info.kernel_ms; 0 turns timing off): launches of the
+ * other classes record no events.  Resets the totals; synchronises with the
+ * plan's stream.  E_INVAL for bits beyond the last class. */
+nudft2_status nudft2_set_profiling_classes(nudft2_plan_t plan, uint32_t classes);
 
 /* Release every device buffer of the plan.  NULL is accepted. */
 nudft2_status nudft2_destroy(nudft2_plan_t plan);

@@ -105,8 +105,17 @@ class _PlanBase:
         check(lib.nudft2_set_nufft_tol(self._handle, float(tol)), "nudft2_set_nufft_tol")
         return self
 
-    def set_profiling(self, on: bool = True):
-        check(lib.nudft2_set_profiling(self._handle, 1 if on else 0), "nudft2_set_profiling")
+    def set_profiling(self, on: bool = True, classes=None):
+        """Per-launch event timing of the kernel classes (info()["kernel_ms"]):
+        every class when on, or only the class indices listed in classes."""
+        if classes is None:
+            check(lib.nudft2_set_profiling(self._handle, 1 if on else 0), "nudft2_set_profiling")
+        else:
+            mask = 0
+            for c in classes:
+                mask |= 1 << int(c)
+            check(lib.nudft2_set_profiling_classes(self._handle, mask if on else 0),
+                  "nudft2_set_profiling_classes")
 
     def _rhs(self, f: torch.Tensor):
         self._check_dev(f, "f")

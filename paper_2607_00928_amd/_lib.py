@@ -55,9 +55,9 @@ class Info(C.Structure):
         ("t_facesplit_ms", C.c_double),
         ("t_recompress_ms", C.c_double),
         ("t_urv_ms", C.c_double),
-        ("kernel_ms", C.c_double * 4),
-        ("kernel_flops", C.c_double * 4),
-        ("kernel_launches", C.c_int64 * 4),
+        ("kernel_ms", C.c_double * 6),
+        ("kernel_flops", C.c_double * 6),
+        ("kernel_launches", C.c_int64 * 6),
         ("peak_bytes", C.c_int64),
     ]
 
@@ -99,6 +99,7 @@ def _load():
         "nudft2_get_info": (C.c_int, [P, C.POINTER(Info)]),
         "nudft2_destroy": (C.c_int, [P]),
         "nudft2_set_profiling": (C.c_int, [P, C.c_int32]),
+        "nudft2_set_profiling_classes": (C.c_int, [P, C.c_uint32]),
         "nudft2_set_nufft_tol": (C.c_int, [P, C.c_double]),
         "nudft2_set_solve_opts": (C.c_int, [P, C.c_double, C.c_int32, C.c_int32]),
         "nudft2_strerror": (C.c_char_p, [C.c_int]),

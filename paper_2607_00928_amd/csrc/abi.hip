@@ -414,12 +414,18 @@ nudft2_status nudft2_set_nufft_tol(nudft2_plan_t plan, double nufft_tol) {
 }
 
 nudft2_status nudft2_set_profiling(nudft2_plan_t plan, int32_t on) {
+  return nudft2_set_profiling_classes(plan, on ? (1u << KC_COUNT) - 1 : 0u);
+}
+
+nudft2_status nudft2_set_profiling_classes(nudft2_plan_t plan, uint32_t classes) {
   return guard([&] {
     ND_CHECK(plan != nullptr, NUDFT2_E_INVAL, "null plan");
+    ND_CHECK(classes < (1u << KC_COUNT), NUDFT2_E_INVAL, "unknown kernel class in the mask");
     Plan* P = reinterpret_cast<Plan*>(plan);
     ND_HIP(hipStreamSynchronize(P->stream));
     P->prof.reset();
-    P->profiling = on != 0;
+    P->prof.mask = classes;
+    P->profiling = classes != 0;
   });
 }
 

@@ -33,7 +33,8 @@ struct DescPool {
   // push of read-only kernel arguments: when the pool slot already holds the
   // same bytes from an upload completed before the last sync_reset(), the
   // copy is skipped (repeated sweeps re-push identical descriptor lists).
-  // A plain push() may be kernel-modified scratch: it ends reuse for the pool.
+  // A plain push() may be kernel-modified scratch: it ends reuse until the
+  // cycle after the next sync_reset() has uploaded its lists again.
   void* push_ro(const void* src, size_t n);
   // n bytes of device scratch for a kernel, without an upload (the caller
   // initialises them on the stream); ends reuse like push()
@@ -51,6 +52,9 @@ struct DescPool {
   bool tainted = false;    // a plain push happened: no reuse
   void flush();
   void sync_reset();
+  // take over o's buffers and state (o is left empty); the current ones are
+  // released first
+  void adopt(DescPool& o);
   ~DescPool() { destroy(); }
 };
 
@@ -64,6 +68,11 @@ struct GemmDesc {
   T ar, ai;     // alpha
   T beta;       // real beta
   int lower;    // 1: C (square) is Hermitian, only tiles reaching its lower triangle are computed
+  // structure of the stored A (zeros are stored; the skinny-product kernels
+  // skip the zero part, the others read it): 1 = unit lower trapezoidal
+  // (explicit Householder reflectors, A(i, j) = 0 for i < j), 2 = upper
+  // triangular (A(i, j) = 0 for i > j)
+  int tri;
 };
 
 // One launch for the whole list.  Two descriptors of one list must not write

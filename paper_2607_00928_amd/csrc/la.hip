@@ -49,10 +49,34 @@ void DescPool::destroy() {
   cap = used = 0;
 }
 
+void DescPool::adopt(DescPool& o) {
+  if (&o == this) return;
+  destroy();
+  host = o.host;
+  dev = o.dev;
+  flag = o.flag;
+  cap = o.cap;
+  used = o.used;
+  stream = o.stream;
+  deferred = o.deferred;
+  sscr = o.sscr;
+  sscr_cap = o.sscr_cap;
+  valid = o.valid;
+  tainted = o.tainted;
+  o.host = o.dev = o.sscr = nullptr;
+  o.flag = nullptr;
+  o.cap = o.used = o.sscr_cap = o.valid = 0;
+  o.tainted = false;
+}
+
 void DescPool::sync_reset() {
   if (deferred) return;
   ND_HIP(hipStreamSynchronize(stream));
+  // after a plain push the device copy may differ from the staging (kernel
+  // scratch): nothing is reusable until the next cycle has uploaded again
   if (!tainted) valid = std::max(valid, used);
+  else valid = 0;
+  tainted = false;
   used = 0;
 }
 
@@ -456,8 +480,11 @@ __global__ __launch_bounds__(256) void gemm_skinny_n_kernel(DS descs, int splits
   const int i0 = blockIdx.x * 256;
   if (i0 >= d.m || d.n <= 0) return;
   const int kc = (d.k + splits - 1) / splits;
-  const int kb = blockIdx.z * kc, ke = min(d.k, kb + kc);
+  int kb = blockIdx.z * kc, ke = min(d.k, kb + kc);
   if (kb >= ke && splits > 1) return;
+  // rows i0 .. i0 + 255 have no nonzeros of A outside [lo, hi)
+  if (d.tri == 1) ke = min(ke, i0 + 256);
+  else if (d.tri == 2) kb = max(kb, i0);
   __shared__ C2 Bs[SK_L][NC];
   const int tid = threadIdx.x, i = i0 + tid;
   const bool row = i < d.m;
@@ -510,8 +537,12 @@ __global__ __launch_bounds__(256) void gemm_skinny_n4_kernel(DS descs, int split
   const int i0 = blockIdx.x * 64;
   if (i0 >= d.m || d.n <= 0) return;
   const int kc = (d.k + splits - 1) / splits;
-  const int kb0 = blockIdx.z * kc, ke0 = min(d.k, kb0 + kc);
+  int kb0 = blockIdx.z * kc, ke0 = min(d.k, kb0 + kc);
   if (kb0 >= ke0 && splits > 1) return;
+  // rows i0 .. i0 + 63 have no nonzeros of A outside [lo, hi); the waves
+  // still meet in LDS when that leaves nothing
+  if (d.tri == 1) ke0 = min(ke0, i0 + 64);
+  else if (d.tri == 2) kb0 = max(kb0, i0);
   const int kq = (max(ke0 - kb0, 0) + 3) / 4;
   const int kb = kb0 + wave * kq, ke = min(ke0, kb + kq);
   const int i = i0 + lane;
@@ -561,8 +592,12 @@ __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(DS descs, int splits
   const int i = blockIdx.x * 4 + wave;
   if (i >= d.m || d.n <= 0) return;
   const int kc = (d.k + splits - 1) / splits;
-  const int kb = blockIdx.z * kc, ke = min(d.k, kb + kc);
+  int kb = blockIdx.z * kc, ke = min(d.k, kb + kc);
   if (kb >= ke && splits > 1) return;
+  // column i of A has no nonzeros outside [lo, hi) (the result row i
+  // still gets its store, zero or not)
+  if (d.tri == 1) kb = max(kb, i);
+  else if (d.tri == 2) ke = min(ke, i + 1);
   C2 acc[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) acc[j] = mk<T>(0, 0);
@@ -593,6 +628,66 @@ __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(DS descs, int splits
     if (j >= d.n) break;
     const T re = warp_sum(acc[j].x), im = warp_sum(acc[j].y);
     if (lane == 0) skinny_store(d, i, j, mk<T>(re, im), splits);
+  }
+}
+
+// op(A) = A^H with a short k (at most 512): four rows of C per wave, 16 lanes
+// per row (a wave per row would leave most lanes without work); the row's
+// partial sums meet through row shifts within its 16 lanes.
+template <typename T, int NC, class DS>
+__global__ __launch_bounds__(256) void gemm_skinny_c16_kernel(DS descs, int splits) {
+  using C2 = cplx<T>;
+  constexpr int U = SK_U / 2;
+  const GemmDesc<T> d = descs[blockIdx.y];
+  if ((int)blockIdx.x * 16 >= d.m || d.n <= 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, sub = lane & 15;
+  const int i = blockIdx.x * 16 + wave * 4 + (lane >> 4);
+  const bool row = i < d.m;
+  const int kc = (d.k + splits - 1) / splits;
+  int kb = blockIdx.z * kc, ke = min(d.k, kb + kc);
+  if (kb >= ke && splits > 1) return;
+  if (d.tri == 1) kb = max(kb, i);
+  else if (d.tri == 2) ke = min(ke, i + 1);
+  C2 acc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) acc[j] = mk<T>(0, 0);
+  if (row) {
+    const C2* ap = d.A + (int64_t)i * d.lda;
+    int l = kb + sub;
+    for (; l + 16 * (U - 1) < ke; l += 16 * U) {
+      C2 a[U], b[U][NC];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        a[u] = ldc(ap + l + 16 * u);
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+          b[u][j] = j < d.n ? ldc(d.B + (int64_t)(l + 16 * u) + (int64_t)j * d.ldb) : mk<T>(0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[j] = cadd(acc[j], cmulc(a[u], b[u][j]));
+    }
+    for (; l < ke; l += 16) {
+      const C2 a = ldc(ap + l);
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        if (j < d.n) acc[j] = cadd(acc[j], cmulc(a, ldc(d.B + (int64_t)l + (int64_t)j * d.ldb)));
+    }
+  }
+  // inclusive shifts within each row of 16 lanes: lane 15 of the row holds its sum
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    T re = acc[j].x, im = acc[j].y;
+    re += dpp_get<0x121, 0xF>(re);
+    im += dpp_get<0x121, 0xF>(im);
+    re += dpp_get<0x122, 0xF>(re);
+    im += dpp_get<0x122, 0xF>(im);
+    re += dpp_get<0x124, 0xF>(re);
+    im += dpp_get<0x124, 0xF>(im);
+    re += dpp_get<0x128, 0xF>(re);
+    im += dpp_get<0x128, 0xF>(im);
+    if (row && sub == 15 && j < d.n) skinny_store(d, i, j, mk<T>(re, im), splits);
   }
 }
 
@@ -1675,7 +1770,9 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
   // four waves (gemm_skinny_n4_kernel) when 256-row workgroups would not
   // fill the device
   const bool n4 = opA == OpN && (int64_t)((maxm + 255) / 256) * (int64_t)n < 1024;
-  const int rows_per_wg = opA == OpN ? (n4 ? 64 : 256) : 4;
+  // op C with a short k: 16 lanes per row of C
+  const bool c16 = opA == OpC && maxk <= 512;
+  const int rows_per_wg = opA == OpN ? (n4 ? 64 : 256) : (c16 ? 16 : 4);
   const int64_t bx = (maxm + rows_per_wg - 1) / rows_per_wg;
   int64_t wgs = bx * (int64_t)n;
   int splits = 1;
@@ -1702,7 +1799,7 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
           dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((mx + 255) / 256, 1024)),
                (unsigned)n),
           dim3(256), 0, pool.stream, dd);
-    ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMM32 : KC_GEMM64, fl, (int)n, maxm, maxn,
+    ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMV32 : KC_GEMV64, fl, (int)n, maxm, maxn,
                  maxk, (int)opA * 2 + 10 * splits + 1000, true);
     dim3 grid((unsigned)bx, (unsigned)n, (unsigned)splits);
     auto launch = [&](auto nc) {
@@ -1712,6 +1809,9 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
                               ps.start(), ps.stop(), 0, dd, splits);
       else if (opA == OpN)
         hipExtLaunchKernelGGL((gemm_skinny_n_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
+                              ps.start(), ps.stop(), 0, dd, splits);
+      else if (c16)
+        hipExtLaunchKernelGGL((gemm_skinny_c16_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
                               ps.start(), ps.stop(), 0, dd, splits);
       else
         hipExtLaunchKernelGGL((gemm_skinny_c_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
@@ -2266,9 +2366,10 @@ void ormqr_batched(DescPool& pool, const std::vector<OrmDesc<T>>& d, bool trans,
       const cplx<T>* V = q.V + j0 + (int64_t)j0 * q.ldv;
       const cplx<T>* Tb = q.Tb + (int64_t)QR_OB * QR_OB * blk;
       cplx<T>* Cp = q.C + j0 + (int64_t)c0 * q.ldc;
-      g1.push_back({kb, nc, mr, q.ldv, q.ldc, QR_OB, V, Cp, W[i], T(1), T(0), T(0)});
-      g2.push_back({kb, nc, kb, kb, QR_OB, QR_OB, Tb, W[i], W2[i], T(1), T(0), T(0)});
-      g3.push_back({mr, nc, kb, q.ldv, QR_OB, q.ldc, V, W2[i], Cp, T(-1), T(0), T(1)});
+      // V unit lower trapezoidal, T upper triangular
+      g1.push_back({kb, nc, mr, q.ldv, q.ldc, QR_OB, V, Cp, W[i], T(1), T(0), T(0), 0, 1});
+      g2.push_back({kb, nc, kb, kb, QR_OB, QR_OB, Tb, W[i], W2[i], T(1), T(0), T(0), 0, 2});
+      g3.push_back({mr, nc, kb, q.ldv, QR_OB, q.ldc, V, W2[i], Cp, T(-1), T(0), T(1), 0, 1});
     }
     gemm_batched<T>(pool, g1, OpC, OpN);
     gemm_batched<T>(pool, g2, trans ? OpC : OpN, OpN);

@@ -4,6 +4,7 @@
 #include <memory>
 
 #include "common.h"
+#include "la.h"
 #include "prof.h"
 
 namespace nd {
@@ -103,6 +104,9 @@ struct Plan {
   bool profiling = false;
   Profiler prof;
   nudft2_info info{};
+  // descriptor pool of the solves, kept between solve calls so that repeated
+  // solves find their descriptor lists already on the device
+  DescPool spool;
 
   ~Plan();
 };

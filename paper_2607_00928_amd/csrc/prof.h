@@ -10,7 +10,13 @@
 
 namespace nd {
 
-enum KClass { KC_APPLY = 0, KC_GEMM32 = 1, KC_GEMM64 = 2, KC_QRPANEL = 3, KC_COUNT = 4 };
+// Timed kernel classes: the exact FP64 apply, the matrix-core GEMMs (tile,
+// small-output and reduction kernels) in FP32 / FP64, the Householder panels,
+// and the memory-bound skinny products (at most 8 columns) in FP32 / FP64.
+enum KClass {
+  KC_APPLY = 0, KC_GEMM32 = 1, KC_GEMM64 = 2, KC_QRPANEL = 3, KC_GEMV32 = 4, KC_GEMV64 = 5,
+  KC_COUNT = 6
+};
 
 // Timing events are reused across plans through a process-wide cache with one
 // list per device (an event belongs to the device current at its creation):
@@ -45,9 +51,10 @@ struct Profiler {
   };
   std::vector<Rec> recs;
   int dev = -1;   // the plan's device, taken at the first event
-  double ms[KC_COUNT] = {0, 0, 0, 0};
-  double flops[KC_COUNT] = {0, 0, 0, 0};
-  int64_t launches[KC_COUNT] = {0, 0, 0, 0};
+  double ms[KC_COUNT] = {};
+  double flops[KC_COUNT] = {};
+  int64_t launches[KC_COUNT] = {};
+  unsigned mask = (1u << KC_COUNT) - 1;   // classes that record events
   hipEvent_t get() {
     if (dev < 0) ND_HIP(hipGetDevice(&dev));
     return event_cache_get(dev);
@@ -127,7 +134,7 @@ struct ProfScope {
   ProfScope(hipStream_t st, int c, double f, int nd = 0, int m = 0, int n = 0, int k = 0,
             int var = 0, bool ext_ = false)
       : s(st), cls(c), fl(f), ext(ext_), info{nd, m, n, k, var} {
-    if (!g_prof) return;
+    if (!g_prof || !(g_prof->mask >> cls & 1u)) return;
     if (ext) {
       a = g_prof->get();
       b = g_prof->get();

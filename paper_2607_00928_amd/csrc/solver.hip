@@ -533,7 +533,9 @@ struct SolveCtx {
   SolveCtx(Plan* p, int nr) : P(p), H(*static_cast<HSS2<T>*>(p->hss.get())), nrhs(nr) {
     cx.P = P;
     cx.s = P->stream;
-    cx.pool.init(64 << 20, cx.s);
+    if (!P->spool.host) P->spool.init(64 << 20, cx.s);
+    cx.pool.adopt(P->spool);
+    cx.pool.sync_reset();
     w.fw = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * P->Mtot * nrhs);
     w.cw = (cplx<T>*)cx.tmp_alloc(sizeof(cplx<T>) * P->Ntot * nrhs);
     w.chat = (double2*)cx.tmp_alloc(sizeof(double2) * P->Ntot * nrhs);
@@ -552,6 +554,15 @@ struct SolveCtx {
   }
   ~SolveCtx() {
     (void)hipStreamSynchronize(cx.s);
+    // the descriptor pool goes back to the plan for the next solve
+    try {
+      cx.pool.sync_reset();
+    } catch (...) {
+      // a failed solve may have left uploads unexecuted: nothing is reusable
+      cx.pool.valid = cx.pool.used = 0;
+      cx.pool.tainted = false;
+    }
+    P->spool.adopt(cx.pool);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) {

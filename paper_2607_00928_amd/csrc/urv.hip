@@ -527,7 +527,7 @@ void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t
       od.push_back({pb.root_m, pb.root_n, nrhs, pb.rootA.ld, fr.ld, pb.rootA.p, pb.rootT.p, fr.p});
       Mat<T>& t = Rt[p];
       gr.push_back({pb.root_n, nrhs, pb.root_n, pb.rootR.ld, fr.ld, t.ld, pb.rootR.p, fr.p, t.p,
-                    T(1), T(0), T(0)});
+                    T(1), T(0), T(0), 0, 2});
       cr.push_back({pb.root_n, nrhs, t.ld, fr.ld, t.p, fr.p, 0});
     }
     ormqr_batched<T>(cx.pool, od, true, cx.tmp_alloc(orm_workspace<T>(od)));
@@ -612,7 +612,7 @@ void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t
                          Bh[p][l][nd.z].p, fm.p, T(-1), T(0), T(1)});
         // c1 = D11^{-1} (f1 - D12 c2 - U1 b), straight into the c+ buffer
         gd1.push_back({nd.k, nrhs, nd.k, nd.D11.ld, fm.ld, cp.ld, nd.D11.p, fm.p,
-                       cp.at(nd.nu, 0), T(1), T(0), T(0)});
+                       cp.at(nd.nu, 0), T(1), T(0), T(0), 0, 2});
         oq.push_back({nd.nn, nd.wV, nrhs, nd.Vm.ld, cp.ld, nd.Vm.p, nd.Tq.p, cp.p});
       }
     }
@@ -735,7 +735,7 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
         oq.push_back({nd.nn, nd.wV, nrhs, nd.Vm.ld, cb.ld, nd.Vm.p, nd.Tq.p, cb.p});
         // f1-bar = D11^{-H} c1-bar (D11 stored inverted)
         gd1.push_back({nd.k, nrhs, nd.k, nd.D11.ld, cb.ld, fb.ld, nd.D11.p, cb.at(nd.nu, 0), fb.p,
-                       T(1), T(0), T(0)});
+                       T(1), T(0), T(0), 0, 2});
         Mat<T> U1 = nd.Wm.sub(0, nd.k, nd.k, nd.wU);
         Mat<T> D12 = nd.Wm.sub(0, nd.k + nd.wU, nd.k, nd.nu);
         if (nd.nu > 0)
@@ -812,7 +812,7 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
       // R^{-H} (R stored inverted) through a temporary and back
       Mat<T>& t = Rt[p];
       gr.push_back({pb.root_n, nrhs, pb.root_n, pb.rootR.ld, fr.ld, t.ld, pb.rootR.p, fr.p, t.p,
-                    T(1), T(0), T(0)});
+                    T(1), T(0), T(0), 0, 2});
       cr.push_back({pb.root_n, nrhs, t.ld, fr.ld, t.p, fr.p, 0});
       od.push_back({pb.root_m, pb.root_n, nrhs, pb.rootA.ld, fr.ld, pb.rootA.p, pb.rootT.p, fr.p});
     }
@@ -859,30 +859,41 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
 
 template void urv_factor<float>(Ctx&, HSS2<float>&);
 template void urv_factor<double>(Ctx&, HSS2<double>&);
-// Stored entries each step of urv_solve reads: the reflector blocks of
-// Omega, P and Q0 with their compact-WY factors, V^_2 (z = V^_2^H c2), the
-// sibling couplings B and the parent transfer R (b^), D12 and U1, the
-// inverted triangle D11 (read as a full square by its matrix-vector product),
-// and the root's reflectors, factor and inverted triangle (likewise).
+// Stored entries each step of urv_solve reads, without the zeros the
+// products skip: the reflector blocks of Omega, P and Q0 (unit lower
+// trapezoidal) with their compact-WY factors (upper triangular), V^_2
+// (z = V^_2^H c2), the sibling couplings B and the parent transfer R (b^),
+// D12 and U1, the inverted triangle D11, and the root's reflectors, factors
+// and inverted triangle.
 template <typename T>
 int64_t urv_sweep_bytes(const HSS2<T>& H) {
+  // m x min(m, n) reflectors (lower trapezoid with the unit diagonal) and the
+  // upper triangles of their QR_OB-column compact-WY blocks
+  auto refl = [](int m, int n) -> double {
+    const double k = std::min(m, n);
+    double e = (double)m * k - k * (k - 1) / 2;
+    for (int j0 = 0; j0 < (int)k; j0 += QR_OB) {
+      const double kb = std::min(QR_OB, (int)k - j0);
+      e += kb * (kb + 1) / 2;
+    }
+    return e;
+  };
+  auto tri = [](int k) -> double { return (double)k * (k + 1) / 2; };
   double e = 0;
   for (const auto& pb : H.probs) {
     for (int l = 1; l <= pb.L; ++l)
       for (const auto& nd : pb.lv[l]) {
-        if (nd.sizered) e += (double)nd.mm * nd.mchk + qr_tsize(nd.mm, nd.mchk);
+        if (nd.sizered) e += refl(nd.mm, nd.mchk);
         if (nd.k > 0) {
-          e += (double)nd.mchk * nd.k + qr_tsize(nd.mchk, nd.k);
-          e += (double)nd.k * nd.k + (double)nd.k * nd.nu + (double)nd.k * nd.wU;
+          e += refl(nd.mchk, nd.k);
+          e += tri(nd.k) + (double)nd.k * nd.nu + (double)nd.k * nd.wU;
         }
         e += (double)nd.nu * nd.wV;
-        if (nd.wV > 0) e += (double)nd.nn * nd.wV + qr_tsize(nd.nn, nd.wV);
+        if (nd.wV > 0) e += refl(nd.nn, nd.wV);
         for (int s = 0; s < 3; ++s) e += (double)nd.B[s].r * nd.B[s].c;
         if (l >= 2) e += (double)nd.R.r * nd.R.c;
       }
-    if (pb.root_n > 0)
-      e += (double)pb.root_m * pb.root_n + qr_tsize(pb.root_m, pb.root_n) +
-           (double)pb.root_n * pb.root_n;
+    if (pb.root_n > 0) e += refl(pb.root_m, pb.root_n) + tri(pb.root_n);
   }
   return (int64_t)(e * sizeof(cplx<T>));
 }

@@ -80,9 +80,10 @@ def classes(rows, top: int):
     for row in rows:
         # class, ms, flops, descriptors, m, n, k, variant (then the algorithm step)
         cls, ms, _fl, ndesc, m, n, k, var = row[:8]
-        if int(cls) not in (1, 2) or m <= 0 or n <= 0 or k <= 0:
+        # matrix-core GEMMs (classes 1, 2) and skinny products (4, 5)
+        if int(cls) not in (1, 2, 4, 5) or m <= 0 or n <= 0 or k <= 0:
             continue
-        prec = 1 if int(cls) == 1 else 0
+        prec = 1 if int(cls) in (1, 4) else 0
         opa, opb, _sk = decode(int(var))
         key = (prec, opa, opb, clog2(int(m)), clog2(int(n)), clog2(int(k)), clog2(int(ndesc)))
         c = out.setdefault(key, dict(ms=0.0, count=0, m=0, n=0, k=0, nd=0))

@@ -43,3 +43,11 @@ def test_classes_accept_step_column():
                      [1, 2.0, 1e9, 12, 5000, 6000, 5500, 10, 3]])
     cl = tg.classes(rows, top=10)
     assert len(cl) == 1 and cl[0][1]["ms"] == 7.0 and cl[0][1]["count"] == 2
+
+
+def test_classes_skinny_products():
+    # skinny products log as classes 4 (FP32) and 5 (FP64)
+    rows = np.array([[4, 3.0, 1e9, 1024, 1042, 1, 256, 1010, 16],
+                     [5, 1.0, 1e9, 4, 300, 2, 5000, 1032, 16]])
+    cl = dict(tg.classes(rows, top=10))
+    assert (1, 0, 0, 11, 0, 8, 10) in cl and (0, 1, 0, 9, 1, 13, 2) in cl
