@@ -749,15 +749,16 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
             Mat<G> r = conv(nd.R), w = conv(nd.W);
             if (nd.wU > 0 && par.TU.c > 0) {
               Mat<G> tu = convT(par.TU, p, 2 * (z >> 2));
+              // T^U_parent is upper triangular
               gx.push_back({nd.wU, par.TU.c, r.c, r.ld, tu.ld, XU[i].ld, r.p, tu.p, XU[i].p, G(1),
-                            G(0), G(0)});
+                            G(0), G(0), 0, 0, 2});
               gnc[3].push_back({nd.wU, nd.wU, XU[i].c, XU[i].ld, XU[i].ld, GU[i].ld, XU[i].p,
                                 XU[i].p, GU[i].p, G(1), G(0), G(1), 1});
             }
             if (nd.wV > 0 && par.TV.c > 0) {
               Mat<G> tv = convT(par.TV, p, 2 * (z >> 2) + 1);
               gx.push_back({nd.wV, par.TV.c, w.c, w.ld, tv.ld, XV[i].ld, w.p, tv.p, XV[i].p, G(1),
-                            G(0), G(0)});
+                            G(0), G(0), 0, 0, 2});
               gnc[3].push_back({nd.wV, nd.wV, XV[i].c, XV[i].ld, XV[i].ld, GV[i].ld, XV[i].p,
                                 XV[i].p, GV[i].p, G(1), G(0), G(1), 1});
             }

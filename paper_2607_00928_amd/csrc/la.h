@@ -68,11 +68,11 @@ struct GemmDesc {
   T ar, ai;     // alpha
   T beta;       // real beta
   int lower;    // 1: C (square) is Hermitian, only tiles reaching its lower triangle are computed
-  // structure of the stored A (zeros are stored; the skinny-product kernels
-  // skip the zero part, the others read it): 1 = unit lower trapezoidal
-  // (explicit Householder reflectors, A(i, j) = 0 for i < j), 2 = upper
-  // triangular (A(i, j) = 0 for i > j)
+  // structure of the stored A and B (zeros are stored; kernels may skip
+  // them): 1 = unit lower trapezoidal (explicit Householder reflectors,
+  // X(i, j) = 0 for i < j), 2 = upper triangular (X(i, j) = 0 for i > j)
   int tri;
+  int trib;
 };
 
 // One launch for the whole list.  Two descriptors of one list must not write

@@ -189,6 +189,19 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, 
   using A4 = typename acc4<T>::type;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  // k beyond which op(A)'s rows i0.. or op(B)'s columns j0.. hold only
+  // stored zeros (an empty range leaves the accumulators at zero)
+  {
+    const int ta = d.tri, tb = d.trib;
+    // op(A)(i, l) = 0 for l > i: A unit lower (op N) or upper (op C)
+    if ((OPA == OpN && ta == 1) || (OPA == OpC && ta == 2)) kend = min(kend, i0 + GT);
+    // op(A)(i, l) = 0 for l < i
+    if ((OPA == OpN && ta == 2) || (OPA == OpC && ta == 1)) kbeg = max(kbeg, i0);
+    // op(B)(l, j) = 0 for l > j: B upper (op N) or unit lower (op C)
+    if ((OPB == OpN && tb == 2) || (OPB == OpC && tb == 1)) kend = min(kend, j0 + GT);
+    // op(B)(l, j) = 0 for l < j
+    if ((OPB == OpN && tb == 1) || (OPB == OpC && tb == 2)) kbeg = max(kbeg, j0);
+  }
   // Gauss (3M) products: p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi);
   // Re = p1 - p2, Im = p3 - p1 - p2
   A4 acc1[2][2], acc2[2][2], acc3[2][2];
@@ -2201,9 +2214,10 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& din, void* ws) 
           cplx<T>* V = q.A + j0 + (int64_t)j0 * q.lda;
           cplx<T>* At = q.A + j0 + (int64_t)(j0 + jb) * q.lda;
           cplx<T>* Tj = q.Tw + (int64_t)((j0 % QR_OB) / QR_NB) * QR_NB * QR_NB;
-          g1.push_back({jb, nt, mr, q.lda, q.lda, QR_NB, V, At, W[i], T(1), T(0), T(0)});
-          g2.push_back({jb, nt, jb, QR_NB, QR_NB, QR_NB, Tj, W[i], W2[i], T(1), T(0), T(0)});
-          g3.push_back({mr, nt, jb, q.lda, QR_NB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
+          // V unit lower trapezoidal, T upper triangular
+          g1.push_back({jb, nt, mr, q.lda, q.lda, QR_NB, V, At, W[i], T(1), T(0), T(0), 0, 1});
+          g2.push_back({jb, nt, jb, QR_NB, QR_NB, QR_NB, Tj, W[i], W2[i], T(1), T(0), T(0), 0, 2});
+          g3.push_back({mr, nt, jb, q.lda, QR_NB, q.lda, V, W2[i], At, T(-1), T(0), T(1), 0, 1});
         }
         int maxmr = 0;
         for (int i : act) maxmr = std::max(maxmr, d[i].m - j0);
@@ -2251,9 +2265,9 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& din, void* ws) 
         cplx<T>* V = q.A + H0 + (int64_t)H0 * q.lda;
         cplx<T>* At = q.A + H0 + (int64_t)(H0 + QR_HB) * q.lda;
         const cplx<T>* Th = q.Tb + (int64_t)QR_OB * QR_OB * bidx;
-        g1.push_back({kh, nt, mr, q.lda, q.lda, QR_OB, V, At, W[i], T(1), T(0), T(0)});
-        g2.push_back({kh, nt, kh, kB, QR_OB, QR_OB, Th, W[i], W2[i], T(1), T(0), T(0)});
-        g3.push_back({mr, nt, kh, q.lda, QR_OB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
+        g1.push_back({kh, nt, mr, q.lda, q.lda, QR_OB, V, At, W[i], T(1), T(0), T(0), 0, 1});
+        g2.push_back({kh, nt, kh, kB, QR_OB, QR_OB, Th, W[i], W2[i], T(1), T(0), T(0), 0, 2});
+        g3.push_back({mr, nt, kh, q.lda, QR_OB, q.lda, V, W2[i], At, T(-1), T(0), T(1), 0, 1});
       }
       gemm_batched<T>(pool, g1, OpC, OpN);
       gemm_batched<T>(pool, g2, OpC, OpN);
@@ -2295,9 +2309,9 @@ void geqrf_batched(DescPool& pool, const std::vector<QRDesc<T>>& din, void* ws) 
       cplx<T>* V = q.A + J0 + (int64_t)J0 * q.lda;
       cplx<T>* At = q.A + J0 + (int64_t)(J0 + QR_OB) * q.lda;
       const cplx<T>* Tb = q.Tb + (int64_t)QR_OB * QR_OB * bidx;
-      g1.push_back({kb, nt, mr, q.lda, q.lda, QR_OB, V, At, W[i], T(1), T(0), T(0)});
-      g2.push_back({kb, nt, kb, kb, QR_OB, QR_OB, Tb, W[i], W2[i], T(1), T(0), T(0)});
-      g3.push_back({mr, nt, kb, q.lda, QR_OB, q.lda, V, W2[i], At, T(-1), T(0), T(1)});
+      g1.push_back({kb, nt, mr, q.lda, q.lda, QR_OB, V, At, W[i], T(1), T(0), T(0), 0, 1});
+      g2.push_back({kb, nt, kb, kb, QR_OB, QR_OB, Tb, W[i], W2[i], T(1), T(0), T(0), 0, 2});
+      g3.push_back({mr, nt, kb, q.lda, QR_OB, q.lda, V, W2[i], At, T(-1), T(0), T(1), 0, 1});
     }
     gemm_batched<T>(pool, g1, OpC, OpN);
     gemm_batched<T>(pool, g2, OpC, OpN);

@@ -299,8 +299,10 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
         const Node2<T>& ci = pb.lv[par[pi].l + 1][4 * par[pi].z + i];
         const Node2<T>& cj = pb.lv[par[pi].l + 1][4 * par[pi].z + j];
         if (ci.wU > 0 && cj.nu > 0)
+          // V2 is the upper-triangular factor of the basis elimination when
+          // the node eliminated unknowns (k > 0), else the basis itself
           gx.push_back({ci.wU, cj.nu, cj.wV, ci.B[s].ld, cj.V2.ld, Xs[t].ld, ci.B[s].p, cj.V2.p,
-                        Xs[t].p, T(1), T(0), T(0)});
+                        Xs[t].p, T(1), T(0), T(0), 0, 0, cj.k > 0 ? 2 : 0});
       }
       gemm_batched<T>(cx.pool, gx, OpN, OpC);
       for (size_t pi = 0; pi < par.size(); ++pi) {
@@ -327,7 +329,7 @@ void urv_factor(Ctx& cx, HSS2<T>& H) {
                             dst.at(roff[i], 0), T(1), T(0), T(0)});
             if (ci.nu > 0 && nd.wV > 0)
               gv.push_back({ci.nu, nd.wV, ci.wV, ci.V2.ld, ci.W.ld, nd.Vm.ld, ci.V2.p, ci.W.p,
-                            nd.Vm.at(coff[i], 0), T(1), T(0), T(0)});
+                            nd.Vm.at(coff[i], 0), T(1), T(0), T(0), 0, ci.k > 0 ? 2 : 0});
           }
         }
       }
@@ -560,7 +562,7 @@ void urv_solve(Ctx& cx, HSS2<T>& H, cplx<T>* f, int64_t ldf, cplx<T>* c, int64_t
         // z = V2^H c2
         if (nd.wV > 0 && nd.nu > 0)
           gz.push_back({nd.wV, nrhs, nd.nu, nd.V2.ld, c2.ld, Z[p][l][nd.z].ld, nd.V2.p, c2.p,
-                        Z[p][l][nd.z].p, T(1), T(0), T(0)});
+                        Z[p][l][nd.z].p, T(1), T(0), T(0), 0, nd.k > 0 ? 2 : 0});
         else if (nd.wV > 0) {
           std::vector<FillDesc<T>> fz{{nd.wV, nrhs, Z[p][l][nd.z].ld, Z[p][l][nd.z].p, 0}};
           fill_batched<T>(cx.pool, fz);
@@ -766,7 +768,8 @@ void urv_solve_adj(Ctx& cx, HSS2<T>& H, cplx<T>* c, int64_t ldc, cplx<T>* f, int
         }
         if (nd.nu > 0)
           gv.push_back({nd.nu, nrhs, nd.wV, nd.V2.ld, Zb[p][l][nd.z].ld, Cb[p][l][nd.z].ld,
-                        nd.V2.p, Zb[p][l][nd.z].p, Cb[p][l][nd.z].p, T(1), T(0), T(1)});
+                        nd.V2.p, Zb[p][l][nd.z].p, Cb[p][l][nd.z].p, T(1), T(0), T(1), 0,
+                        nd.k > 0 ? 2 : 0});
       }
     }
     for (int s = 0; s < 3; ++s) gemm_batched<T>(cx.pool, gz[s], OpC, OpN);
@@ -888,7 +891,7 @@ int64_t urv_sweep_bytes(const HSS2<T>& H) {
           e += refl(nd.mchk, nd.k);
           e += tri(nd.k) + (double)nd.k * nd.nu + (double)nd.k * nd.wU;
         }
-        e += (double)nd.nu * nd.wV;
+        e += nd.k > 0 ? tri(nd.wV) : (double)nd.nu * nd.wV;   // V^_2 triangular when k > 0
         if (nd.wV > 0) e += refl(nd.nn, nd.wV);
         for (int s = 0; s < 3; ++s) e += (double)nd.B[s].r * nd.B[s].c;
         if (l >= 2) e += (double)nd.R.r * nd.R.c;
