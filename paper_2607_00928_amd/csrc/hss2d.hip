@@ -499,6 +499,7 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
         carve(P->arena, mk, &cx.tmp);
         void* cb = carve(P->arena, mb);
         std::vector<CopyDesc<T, double>> kcd;
+        std::vector<FillDesc<T>> fzb;
         std::vector<GemmDesc<T>> g1, g2;
         for (auto& nd : pb.lv[lc]) {
           int c = nd.z & 3;
@@ -530,11 +531,16 @@ void build_2d(Ctx& cx, const std::vector<Tree1>& tx, const std::vector<Tree1>& t
                 }
               }
             }
-            g2.push_back({nb.r, nb.c, x.c, nd.F.ld, x.ld, nb.ld, nd.F.p + (int64_t)kb.r0 * nd.F.ld,
+            // F is upper trapezoidal: its columns r0 .. r0 + h - 1 vanish below
+            // row r0 + h, and so do the rows of B~ there
+            const int mr = std::min(nb.r, kb.r0 + x.c);
+            if (mr < nb.r) fzb.push_back({nb.r - mr, nb.c, nb.ld, nb.p + mr, 0});
+            g2.push_back({mr, nb.c, x.c, nd.F.ld, x.ld, nb.ld, nd.F.p + (int64_t)kb.r0 * nd.F.ld,
                           x.p, nb.p, T(1), T(0), T(0)});
           }
         }
         copy_batched<T, double>(cx.pool, kcd);
+        fill_batched<T>(cx.pool, fzb);
         gemm_batched<T>(cx.pool, g1, OpN, OpC);
         gemm_batched<T>(cx.pool, g2, OpN, OpC);
         std::vector<Mat<T>> SR, SW, QR_, QW_, FR, FW;
