@@ -1775,6 +1775,34 @@ static int tuned_splits(Op opA, Op opB, int maxm, int maxn, int maxk, int nd) {
   return 0;
 }
 
+// Algorithmic flops of one product: 8 per complex multiply-add with a
+// nonzero operand entry (entries a triangular operand stores as zeros are
+// not counted), halved for a Hermitian output computed in its lower half.
+template <typename T>
+static double gemm_flops(const GemmDesc<T>& g, Op opA, Op opB) {
+  const double m = g.m, n = g.n, k = g.k;
+  if (g.m <= 0 || g.n <= 0 || g.k <= 0) return 0.0;
+  // nonzeros of op(X) per row (column) index i < r over a k range: below or
+  // above the diagonal
+  auto lower = [](double r, double kk) {   // sum_i min(i + 1, kk)
+    const double t = std::min(r, kk);
+    return t * (t + 1) / 2 + (r - t) * kk;
+  };
+  auto upper = [](double r, double kk) {   // sum_i max(kk - i, 0)
+    const double t = std::min(r, kk);
+    return t * kk - t * (t - 1) / 2;
+  };
+  double macs = m * n * k;
+  // op(A)(i, l) = 0 for l > i (A unit lower, op N; A upper, op C)
+  if ((opA == OpN && g.tri == 1) || (opA == OpC && g.tri == 2)) macs = n * lower(m, k);
+  else if ((opA == OpN && g.tri == 2) || (opA == OpC && g.tri == 1)) macs = n * upper(m, k);
+  // op(B)(l, j) = 0 for l > j (B upper, op N; B unit lower, op C)
+  else if ((opB == OpN && g.trib == 2) || (opB == OpC && g.trib == 1)) macs = m * lower(n, k);
+  else if ((opB == OpN && g.trib == 1) || (opB == OpC && g.trib == 2)) macs = m * upper(n, k);
+  if (g.lower) macs *= (n + 1) / (2 * n);
+  return 8.0 * macs;
+}
+
 template <typename T>
 static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, Op opA, int maxm,
                            int maxn, int maxk, int force) {
@@ -1797,7 +1825,7 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
     splits = std::max(1, std::min(splits, 256));
   }
   double fl = 0;
-  for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
+  for (auto& g : sub) fl += gemm_flops(g, opA, OpN);
   int64_t mx = 0;
   bool scale = false;   // some C needs beta applied before the atomic adds
   for (auto& g : sub) {
@@ -1845,7 +1873,7 @@ static void smallmn_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub,
   bool scale = false;
   for (auto& g : sub) scale = scale || (g.m > 0 && g.n > 0 && g.beta != T(1));
   double fl = 0;
-  for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
+  for (auto& g : sub) fl += gemm_flops(g, OpC, OpN);
   const int mb = (maxm + 15) / 16, nb = (maxn + 15) / 16;
   with_descs(pool, sub.data(), n, [&](auto dd) {
     using DS = decltype(dd);
@@ -1879,7 +1907,7 @@ static void smallm_wide_batched(DescPool& pool, const std::vector<GemmDesc<T>>& 
   bool scale = false;
   for (auto& g : sub) scale = scale || (g.m > 0 && g.n > 0 && g.beta != T(1));
   double fl = 0;
-  for (auto& g : sub) fl += 8.0 * g.m * (double)g.n * g.k;
+  for (auto& g : sub) fl += gemm_flops(g, OpC, OpN);
   with_descs(pool, sub.data(), n, [&](auto dd) {
     using DS = decltype(dd);
     if (scale)
@@ -2046,7 +2074,7 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     double fl = 0;
     int mm = 0, mn = 0;
     for (auto& g : sub) {
-      fl += (g.lower ? 4.0 * (double)g.m * (g.n + 1) : 8.0 * g.m * (double)g.n) * g.k;
+      fl += gemm_flops(g, opA, opB);
       mm = std::max(mm, g.m);
       mn = std::max(mn, g.n);
     }
