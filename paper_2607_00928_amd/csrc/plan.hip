@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <numeric>
+#include <thread>
 
 #include "hss.h"
 #include "plan.h"
@@ -239,6 +240,59 @@ static inline double wrap01(double v) {
   return w;
 }
 
+// f(begin, end, t) over contiguous chunks [begin, end) of [0, n) on up to
+// 16 host threads (chunk t before chunk t + 1), serially for small n
+template <class F>
+static void par_chunks(int64_t n, int nt, F&& f) {
+  if (nt <= 1) {
+    f((int64_t)0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(nt);
+  for (int t = 0; t < nt; ++t) th.emplace_back(f, n * t / nt, n * (t + 1) / nt, t);
+  for (auto& x : th) x.join();
+}
+
+static int host_threads(int64_t n) {
+  if (n < (int64_t)1 << 16) return 1;
+  const unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::max<unsigned>(1, std::min<unsigned>(hc ? hc : 1, 16));
+}
+
+// Stable counting sort of 0 .. n-1 by key(j) in [0, nbins): ord receives the
+// indices in key order (ties in index order), cnt (nbins + 1) the prefix
+// counts.  Per-thread histograms of contiguous index chunks, then each chunk
+// scatters from its own offsets, so the result equals the serial sort.
+template <class K>
+static void counting_sort(int64_t n, int nbins, K key, std::vector<int64_t>& ord,
+                          std::vector<int64_t>& cnt) {
+  const int nt = host_threads(n);
+  std::vector<std::vector<int64_t>> h(nt, std::vector<int64_t>(nbins, 0));
+  par_chunks(n, nt, [&](int64_t a, int64_t b, int t) {
+    for (int64_t j = a; j < b; ++j) h[t][key(j)]++;
+  });
+  cnt.assign(nbins + 1, 0);
+  for (int k = 0; k < nbins; ++k) {
+    int64_t s = 0;
+    for (int t = 0; t < nt; ++t) s += h[t][k];
+    cnt[k + 1] = cnt[k] + s;
+  }
+  // chunk t's first slot in bin k: the bin start plus the earlier chunks'
+  for (int k = 0; k < nbins; ++k) {
+    int64_t o = cnt[k];
+    for (int t = 0; t < nt; ++t) {
+      const int64_t c = h[t][k];
+      h[t][k] = o;
+      o += c;
+    }
+  }
+  ord.resize(n);
+  par_chunks(n, nt, [&](int64_t a, int64_t b, int t) {
+    for (int64_t j = a; j < b; ++j) ord[h[t][key(j)]++] = j;
+  });
+}
+
 static inline int bin_of(double v, int level) {
   int b = (int)std::floor(v * (double)(1 << level));
   return std::min(std::max(b, 0), (1 << level) - 1);
@@ -257,14 +311,17 @@ static void bin_problem(Problem& q, const double* pts, int leaf, HostOrder& H) {
   const int nleaf2 = 1 << (2 * L);
   std::vector<int> bx(M), by(M);
   std::vector<uint32_t> z(M);
-  for (int64_t j = 0; j < M; ++j) {
-    double x = wrap01(pts[2 * (m0 + j)]), y = wrap01(pts[2 * (m0 + j) + 1]);
-    H.pts_user[2 * (m0 + j)] = x;
-    H.pts_user[2 * (m0 + j) + 1] = y;
-    bx[j] = bin_of(x, L);
-    by[j] = bin_of(y, L);
-    z[j] = interleave(bx[j], by[j], L);
-  }
+  const int nt = host_threads(M);
+  par_chunks(M, nt, [&](int64_t a, int64_t b, int) {
+    for (int64_t j = a; j < b; ++j) {
+      double x = wrap01(pts[2 * (m0 + j)]), y = wrap01(pts[2 * (m0 + j) + 1]);
+      H.pts_user[2 * (m0 + j)] = x;
+      H.pts_user[2 * (m0 + j) + 1] = y;
+      bx[j] = bin_of(x, L);
+      by[j] = bin_of(y, L);
+      z[j] = interleave(bx[j], by[j], L);
+    }
+  });
   // columns of the 1D trees
   q.colx.assign(L + 1, {});
   q.coly.assign(L + 1, {});
@@ -278,14 +335,8 @@ static void bin_problem(Problem& q, const double* pts, int leaf, HostOrder& H) {
     }
   }
   // 2D order: stable counting sort by leaf Morton code
-  std::vector<int64_t> cnt2(nleaf2 + 1, 0);
-  for (int64_t j = 0; j < M; ++j) cnt2[z[j] + 1]++;
-  for (int i = 0; i < nleaf2; ++i) cnt2[i + 1] += cnt2[i];
-  std::vector<int64_t> ord2(M);
-  {
-    std::vector<int64_t> pos(cnt2.begin(), cnt2.end() - 1);
-    for (int64_t j = 0; j < M; ++j) ord2[pos[z[j]]++] = j;
-  }
+  std::vector<int64_t> cnt2, ord2;
+  counting_sort(M, nleaf2, [&](int64_t j) { return (int)z[j]; }, ord2, cnt2);
   q.row2.assign(L + 1, {});
   for (int l = 0; l <= L; ++l) {
     int nn = 1 << (2 * l);
@@ -296,12 +347,8 @@ static void bin_problem(Problem& q, const double* pts, int leaf, HostOrder& H) {
   // 1D orders
   auto sort1d = [&](const std::vector<int>& b, std::vector<int64_t>& ord,
                     std::vector<std::vector<int64_t>>& rows) {
-    std::vector<int64_t> cnt(nleaf1 + 1, 0);
-    for (int64_t j = 0; j < M; ++j) cnt[b[j] + 1]++;
-    for (int i = 0; i < nleaf1; ++i) cnt[i + 1] += cnt[i];
-    ord.resize(M);
-    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
-    for (int64_t j = 0; j < M; ++j) ord[pos[b[j]]++] = j;
+    std::vector<int64_t> cnt;
+    counting_sort(M, nleaf1, [&](int64_t j) { return b[j]; }, ord, cnt);
     rows.assign(L + 1, {});
     for (int l = 0; l <= L; ++l) {
       int na = 1 << l;
@@ -313,20 +360,24 @@ static void bin_problem(Problem& q, const double* pts, int leaf, HostOrder& H) {
   sort1d(bx, ordx, q.rowx);
   sort1d(by, ordy, q.rowy);
   std::vector<int64_t> invx(M), invy(M);
-  for (int64_t i = 0; i < M; ++i) {
-    invx[ordx[i]] = i;
-    invy[ordy[i]] = i;
-  }
-  for (int64_t i = 0; i < M; ++i) {
-    int64_t j = ord2[i];
-    H.perm2d[m0 + i] = m0 + j;
-    H.pts_2d[2 * (m0 + i)] = H.pts_user[2 * (m0 + j)];
-    H.pts_2d[2 * (m0 + i) + 1] = H.pts_user[2 * (m0 + j) + 1];
-    H.posx[m0 + i] = m0 + invx[j];
-    H.posy[m0 + i] = m0 + invy[j];
-    H.xs[m0 + i] = H.pts_user[2 * (m0 + ordx[i])];
-    H.ys[m0 + i] = H.pts_user[2 * (m0 + ordy[i]) + 1];
-  }
+  par_chunks(M, nt, [&](int64_t a, int64_t b, int) {
+    for (int64_t i = a; i < b; ++i) {
+      invx[ordx[i]] = i;
+      invy[ordy[i]] = i;
+    }
+  });
+  par_chunks(M, nt, [&](int64_t a, int64_t b, int) {
+    for (int64_t i = a; i < b; ++i) {
+      int64_t j = ord2[i];
+      H.perm2d[m0 + i] = m0 + j;
+      H.pts_2d[2 * (m0 + i)] = H.pts_user[2 * (m0 + j)];
+      H.pts_2d[2 * (m0 + i) + 1] = H.pts_user[2 * (m0 + j) + 1];
+      H.posx[m0 + i] = m0 + invx[j];
+      H.posy[m0 + i] = m0 + invy[j];
+      H.xs[m0 + i] = H.pts_user[2 * (m0 + ordx[i])];
+      H.ys[m0 + i] = H.pts_user[2 * (m0 + ordy[i]) + 1];
+    }
+  });
   // quadtree column order
   q.col2.assign(L + 1, {});
   for (int l = 0; l <= L; ++l) {
