@@ -86,6 +86,13 @@ typedef struct {
                          approximation by spreading and FFT (Section 4.1's
                          NUFFT) to about this relative accuracy, in (0, 0.1);
                          nx, ny <= 1024 */
+  int32_t fp32_products; /* matrix-core products of the FP32 factorization:
+                         0 (default) bf16 instructions on a split of every
+                         FP32 entry x into three bf16 parts (x = x0 + x1 + x2
+                         exactly), six bf16 products per real product
+                         (FP32-level accuracy: the three left out are below
+                         2^-23 |a||b|); 1 FP32 instructions.  The FP64
+                         factorization ignores it. */
 } nudft2_opts;
 
 /* Per-solve report (host memory, may be NULL). */

@@ -39,7 +39,10 @@ nudft2_status nudft2_test_mfma_layout(const double* a, const double* b, double* 
 nudft2_status nudft2_test_mfma_layout32(const float* a, const float* b, float* d);
 
 /* Batched dense building blocks on DEVICE data (complex128 when prec == 0,
- * complex64 when prec == 1; column-major with leading dimensions).  Per
+ * complex64 when prec == 1 or 2; column-major with leading dimensions).
+ * complex64 tile products run on the FP32 matrix instructions with prec 1
+ * and on the bf16 ones through the three-way split (nudft2_opts
+ * fp32_products = 0) with prec 2.  Per
  * problem sizes, leading dimensions and device addresses are HOST arrays;
  * all work runs on the default stream and is finished on return.
  *

@@ -30,6 +30,7 @@ class Opts(C.Structure):
         ("mem_cap", C.c_size_t),
         ("graph", C.c_int32),
         ("nufft_tol", C.c_double),
+        ("fp32_products", C.c_int32),
     ]
 
 

@@ -41,12 +41,26 @@ void event_cache_put(int dev, hipEvent_t e) {
   g_ev_cache[dev].push_back(e);
 }
 
-// Routes kernel timing of the calling thread to the plan's profiler while an
-// entry point runs.
+// Routes kernel timing of the calling thread to the plan's profiler, and
+// its FP32 products to the plan's kind, while an entry point runs.
 struct PlanProf {
   Profiler* saved;
-  explicit PlanProf(Plan* P) : saved(g_prof) { g_prof = P->profiling ? &P->prof : nullptr; }
-  ~PlanProf() { g_prof = saved; }
+  bool split;
+  explicit PlanProf(Plan* P) : saved(g_prof), split(g_fp32_split) {
+    g_prof = P->profiling ? &P->prof : nullptr;
+    g_fp32_split = P->opts.fp32_products == 0;
+  }
+  ~PlanProf() {
+    g_prof = saved;
+    g_fp32_split = split;
+  }
+};
+// FP32 products of a testing entry point: prec 1 the FP32 instructions,
+// prec 2 the bf16 split (prec 0: FP64, unaffected)
+struct TestPrec {
+  bool split;
+  explicit TestPrec(int prec) : split(g_fp32_split) { g_fp32_split = prec == 2; }
+  ~TestPrec() { g_fp32_split = split; }
 };
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
@@ -225,6 +239,7 @@ void nudft2_default_opts(nudft2_opts* o) {
   o->mem_cap = 0;
   o->graph = 0;
   o->nufft_tol = 0.0;
+  o->fp32_products = 0;
 }
 
 const char* nudft2_strerror(nudft2_status s) {
@@ -469,6 +484,7 @@ nudft2_status nudft2_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t n
   return guard([&] {
     ND_CHECK(mnk && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
     need_device();
+    TestPrec tp(prec);
     if (prec == 0) test_gemm<double>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta);
     else test_gemm<float>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta);
   });
@@ -481,6 +497,7 @@ nudft2_status nudft2_test_gemm_cfg(int32_t prec, int32_t opA, int32_t opB, int32
   return guard([&] {
     ND_CHECK(mnk && ld && ptrs && nb > 0 && splits >= -4, NUDFT2_E_INVAL, "bad arguments");
     need_device();
+    TestPrec tp(prec);
     if (prec == 0) test_gemm<double>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta, splits, ms);
     else test_gemm<float>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta, splits, ms);
   });
@@ -491,6 +508,7 @@ nudft2_status nudft2_test_geqrf(int32_t prec, int32_t nb, const int32_t* mn, con
   return guard([&] {
     ND_CHECK(mn && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
     need_device();
+    TestPrec tp(prec);
     if (prec == 0) test_geqrf<double>(nb, mn, ld, ptrs);
     else test_geqrf<float>(nb, mn, ld, ptrs);
   });
@@ -502,6 +520,7 @@ nudft2_status nudft2_test_ormqr(int32_t prec, int32_t trans, int32_t nb, const i
     ND_CHECK(dims && ld && ptrs && nb > 0 && trans >= 0 && trans <= 2, NUDFT2_E_INVAL,
              "bad arguments");
     need_device();
+    TestPrec tp(prec);
     if (prec == 0) test_ormqr<double>(trans, nb, dims, ld, ptrs);
     else test_ormqr<float>(trans, nb, dims, ld, ptrs);
   });
@@ -547,6 +566,7 @@ nudft2_status nudft2_test_trsv(int32_t prec, int32_t nb, const int32_t* dims, co
   return guard([&] {
     ND_CHECK(dims && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
     need_device();
+    TestPrec tp(prec);
     if (prec == 0) test_trsv<double>(nb, dims, ld, ptrs, conj_trans != 0);
     else test_trsv<float>(nb, dims, ld, ptrs, conj_trans != 0);
   });
@@ -557,6 +577,7 @@ nudft2_status nudft2_test_trtri(int32_t prec, int32_t nb, const int32_t* k, cons
   return guard([&] {
     ND_CHECK(k && ld && ptrs && nb > 0, NUDFT2_E_INVAL, "bad arguments");
     need_device();
+    TestPrec tp(prec);
     auto run = [&](auto tag) {
       using T = decltype(tag);
       std::vector<TriDesc<T>> d(nb);

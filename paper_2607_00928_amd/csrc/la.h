@@ -92,6 +92,11 @@ struct GemmDesc {
 // the pool's stream scratch, at most this many bytes a launch; without the
 // scratch they take the atomic split instead.
 constexpr size_t kGemmPartBytes = size_t(64) << 20;
+// FP32 tile products of the calling thread's launches: true (the default) on
+// the bf16 matrix cores through a three-way split of each operand entry (six
+// bf16 products per real product, FP32-level accuracy, see gemm_tile_bf),
+// false on the FP32 matrix instructions.  Set per entry point from the plan.
+extern thread_local bool g_fp32_split;
 template <typename T>
 void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op opB,
                   int splits_force = 0);

@@ -18,6 +18,8 @@
 
 namespace nd {
 
+thread_local bool g_fp32_split = true;
+
 // ------------------------------------------------------------ descriptor pool
 void DescPool::init(size_t bytes, hipStream_t s) {
   destroy();
@@ -175,6 +177,113 @@ constexpr int GK = 16;    // k per stage
 // of 16 banks, so the 16-lane groups of an operand read hit distinct banks.
 template <typename T> constexpr int gemm_ldt() { return GT + 64 / (int)sizeof(T); }
 
+// Store of a workgroup's 64 x 64 output tile, held by its four waves as 2 x 2
+// blocks of 16 x 16 matrix-core accumulators: the wave at (wr, wc) =
+// (32 (wave / 2), 32 (wave % 2)) holds Re and Im of element (wr + 16 a +
+// mrow(lane, v), wc + 16 b + lane % 16) in cr[a][b][v] and ci[a][b][v].
+// alpha P is stored (adding beta times the old value) or, when `atomic`,
+// added atomically, at cb + (i - i0) + (j - j0) cld for the tile's rows i < m
+// and columns j < n.
+template <typename T>
+__device__ __forceinline__ void gemm_store_tile(const GemmDesc<T>& d, int i0, int j0, bool atomic,
+                                                cplx<T>* cb, int64_t cld, T beta,
+                                                const typename acc4<T>::type (&cr)[2][2],
+                                                const typename acc4<T>::type (&ci)[2][2]) {
+  using C2 = cplx<T>;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  if constexpr (sizeof(T) == 4) {
+    // FP32 accumulators: a lane holds rows 4 (lane / 16) .. + 3 of one column,
+    // 32 contiguous bytes of column-major C, read and written as two 16-byte
+    // accesses (8-byte aligned: dword alignment is all the hardware needs)
+    if (!atomic) {
+      typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int ib = i0 + wr + a * 16 + 4 * (lane >> 4);
+          const int j = j0 + wc + b * 16 + (lane & 15);
+          if (j >= d.n || ib >= d.m) continue;
+          C2 out[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T re = cr[a][b][v], im = ci[a][b][v];
+            out[v] = mk<T>(d.ar * re - d.ai * im, d.ar * im + d.ai * re);
+          }
+          C2* p = cb + (int64_t)(ib - i0) + (int64_t)(j - j0) * cld;
+          if (ib + 3 < d.m) {
+            f4u* q = (f4u*)p;
+            f4u w0 = {out[0].x, out[0].y, out[1].x, out[1].y};
+            f4u w1 = {out[2].x, out[2].y, out[3].x, out[3].y};
+            if (beta != T(0)) {
+              const f4u o0 = ldg(q), o1 = ldg(q + 1);
+              w0 += beta * o0;
+              w1 += beta * o1;
+            }
+            stg(q, w0);
+            stg(q + 1, w1);
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              if (ib + v >= d.m) break;
+              C2 o = out[v];
+              if (beta != T(0)) {
+                const C2 c = ldc(p + v);
+                o.x += beta * c.x;
+                o.y += beta * c.y;
+              }
+              stc(p + v, o);
+            }
+          }
+        }
+      return;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int i = i0 + wr + a * 16 + mrow<T>(lane, v);
+        int j = j0 + wc + b * 16 + (lane & 15);
+        if (i < d.m && j < d.n) {
+          const T re = cr[a][b][v], im = ci[a][b][v];
+          C2 out = mk<T>(d.ar * re - d.ai * im, d.ar * im + d.ai * re);
+          C2* p = cb + (int64_t)(i - i0) + (int64_t)(j - j0) * cld;
+          if (atomic) {
+            atomic_addg(&p->x, out.x);
+            atomic_addg(&p->y, out.y);
+            continue;
+          }
+          if (beta != T(0)) {
+            const C2 o = ldc(p);
+            out.x += beta * o.x;
+            out.y += beta * o.y;
+          }
+          stc(p, out);
+        }
+      }
+}
+
+// Narrows [kbeg, kend) to the k beyond which op(A)'s rows i0.. or op(B)'s
+// columns j0.. of a 64 x 64 output tile hold only stored zeros (an empty
+// range leaves the accumulators at zero).
+template <typename T, int OPA, int OPB>
+__device__ __forceinline__ void tri_krange(const GemmDesc<T>& d, int i0, int j0, int& kbeg,
+                                           int& kend) {
+  const int ta = d.tri, tb = d.trib;
+  // op(A)(i, l) = 0 for l > i: A unit lower (op N) or upper (op C)
+  if ((OPA == OpN && ta == 1) || (OPA == OpC && ta == 2)) kend = min(kend, i0 + GT);
+  // op(A)(i, l) = 0 for l < i
+  if ((OPA == OpN && ta == 2) || (OPA == OpC && ta == 1)) kbeg = max(kbeg, i0);
+  // op(B)(l, j) = 0 for l > j: B upper (op N) or unit lower (op C)
+  if ((OPB == OpN && tb == 2) || (OPB == OpC && tb == 1)) kend = min(kend, j0 + GT);
+  // op(B)(l, j) = 0 for l < j
+  if ((OPB == OpN && tb == 1) || (OPB == OpC && tb == 2)) kbeg = max(kbeg, j0);
+}
+
 // The output tile at (i0, j0) over the k range [kbeg, kend): alpha P is
 // stored (adding beta times the old value) or, when `atomic`, added
 // atomically, at cb + (i - i0) + (j - j0) cld for the tile's rows i < m and
@@ -189,19 +298,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, 
   using A4 = typename acc4<T>::type;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  // k beyond which op(A)'s rows i0.. or op(B)'s columns j0.. hold only
-  // stored zeros (an empty range leaves the accumulators at zero)
-  {
-    const int ta = d.tri, tb = d.trib;
-    // op(A)(i, l) = 0 for l > i: A unit lower (op N) or upper (op C)
-    if ((OPA == OpN && ta == 1) || (OPA == OpC && ta == 2)) kend = min(kend, i0 + GT);
-    // op(A)(i, l) = 0 for l < i
-    if ((OPA == OpN && ta == 2) || (OPA == OpC && ta == 1)) kbeg = max(kbeg, i0);
-    // op(B)(l, j) = 0 for l > j: B upper (op N) or unit lower (op C)
-    if ((OPB == OpN && tb == 2) || (OPB == OpC && tb == 1)) kend = min(kend, j0 + GT);
-    // op(B)(l, j) = 0 for l < j
-    if ((OPB == OpN && tb == 1) || (OPB == OpC && tb == 2)) kbeg = max(kbeg, j0);
-  }
+  tri_krange<T, OPA, OPB>(d, i0, j0, kbeg, kend);
   // Gauss (3M) products: p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi);
   // Re = p1 - p2, Im = p3 - p1 - p2
   A4 acc1[2][2], acc2[2][2], acc3[2][2];
@@ -299,83 +396,221 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, 
     if (st + 1 < nst) lstore(buf ^ 1);
     __syncthreads();
   }
-  if constexpr (sizeof(T) == 4) {
-    // FP32 accumulators: a lane holds rows 4 (lane / 16) .. + 3 of one column,
-    // 32 contiguous bytes of column-major C, read and written as two 16-byte
-    // accesses (8-byte aligned: dword alignment is all the hardware needs)
-    if (!atomic) {
-      typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int ib = i0 + wr + a * 16 + 4 * (lane >> 4);
-          const int j = j0 + wc + b * 16 + (lane & 15);
-          if (j >= d.n || ib >= d.m) continue;
-          C2 out[4];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const T p1 = acc1[a][b][v], p2 = acc2[a][b][v];
-            const T cr = p1 - p2, ci = acc3[a][b][v] - p1 - p2;
-            out[v] = mk<T>(d.ar * cr - d.ai * ci, d.ar * ci + d.ai * cr);
-          }
-          C2* p = cb + (int64_t)(ib - i0) + (int64_t)(j - j0) * cld;
-          if (ib + 3 < d.m) {
-            f4u* q = (f4u*)p;
-            f4u w0 = {out[0].x, out[0].y, out[1].x, out[1].y};
-            f4u w1 = {out[2].x, out[2].y, out[3].x, out[3].y};
-            if (beta != T(0)) {
-              const f4u o0 = ldg(q), o1 = ldg(q + 1);
-              w0 += beta * o0;
-              w1 += beta * o1;
-            }
-            stg(q, w0);
-            stg(q + 1, w1);
-          } else {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              if (ib + v >= d.m) break;
-              C2 o = out[v];
-              if (beta != T(0)) {
-                const C2 c = ldc(p + v);
-                o.x += beta * c.x;
-                o.y += beta * c.y;
-              }
-              stc(p + v, o);
-            }
-          }
-        }
-      return;
-    }
-  }
+  A4 cr[2][2], ci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        int i = i0 + wr + a * 16 + mrow<T>(lane, v);
-        int j = j0 + wc + b * 16 + (lane & 15);
-        if (i < d.m && j < d.n) {
-          const T p1 = acc1[a][b][v], p2 = acc2[a][b][v];
-          const T cr = p1 - p2, ci = acc3[a][b][v] - p1 - p2;
-          C2 out = mk<T>(d.ar * cr - d.ai * ci, d.ar * ci + d.ai * cr);
-          C2* p = cb + (int64_t)(i - i0) + (int64_t)(j - j0) * cld;
-          if (atomic) {
-            atomic_addg(&p->x, out.x);
-            atomic_addg(&p->y, out.y);
-            continue;
-          }
-          if (beta != T(0)) {
-            const C2 o = ldc(p);
-            out.x += beta * o.x;
-            out.y += beta * o.y;
-          }
-          stc(p, out);
-        }
-      }
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = acc1[a][b] - acc2[a][b];
+      ci[a][b] = acc3[a][b] - acc1[a][b] - acc2[a][b];
+    }
+  gemm_store_tile<T>(d, i0, j0, atomic, cb, cld, beta, cr, ci);
 }
 
+// ------------------------------------- FP32 products on the bf16 matrix cores
+// Every FP32 entry x of op(A) and op(B) is split into three bf16 values:
+// x0 = bf16(x) rounded to nearest, x1 = bf16(x - x0), x2 = x - x0 - x1.  Both
+// differences are exact in FP32 and x2 keeps at most 8 significant bits, so
+// x = x0 + x1 + x2 exactly.  A real product a b is summed from the six bf16
+// products a_p b_q with p + q <= 2, each exact in the FP32 accumulator; the
+// three left out (a1 b2, a2 b1, a2 b2) are below (2^-23 + 2^-32) |a| |b|, so
+// the result carries the error of an FP32 dot product (one more unit of
+// 2^-24 |a| |b| a term) and keeps FP32's exponent range.  A complex product
+// takes four real ones in three accumulators per block (Ar Br, Ai Bi, and
+// Ar Bi + Ai Br).  The 16x16x32 bf16 instruction does 16 times the FP32
+// instruction's multiply-adds per cycle, so the 24 of a complex block cost
+// 3/8 of the FP32 path's Gauss products.  Each operand entry is split once,
+// as its stage is written to LDS.
+constexpr int BK = 32;        // k per stage: one 16x16x32 instruction
+constexpr int BLD = BK + 8;   // bf16 per LDS row (80 bytes: the 16 rows of a
+                              // 16-byte read start on distinct banks)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+// one stage: [op(A), op(B)][plane: Re x0, x1, x2, Im x0, x1, x2][row i of
+// op(A) / column j of op(B)][k]
+struct BfStage {
+  unsigned short p[2][6][GT][BLD];
+};
+
+__device__ __forceinline__ unsigned bf16_pair(float lo, float hi) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f2{lo, hi}, b2));
+}
+// the three bf16 parts of a and b, packed in pairs (a in the low half)
+__device__ __forceinline__ void bf16_split3(float a, float b, unsigned& h, unsigned& m,
+                                            unsigned& l) {
+  h = bf16_pair(a, b);
+  const float ra = a - __uint_as_float(h << 16), rb = b - __uint_as_float(h & 0xffff0000u);
+  m = bf16_pair(ra, rb);
+  l = bf16_pair(ra - __uint_as_float(m << 16), rb - __uint_as_float(m & 0xffff0000u));
+}
+
+// 8 consecutive k (k0 .. k0 + 7) of row r of an operand tile whose element
+// (r, k) sits at p[k + r ld] (KC: k contiguous) or p[r + k ld], as loaded:
+// indices are clamped into the stored matrix (kq: its k extent from p; KC:
+// >= 2, pairs of entries are read) and nothing is selected, so no
+// instruction waits for the loads until bf_split8 masks them.
+template <bool KC>
+__device__ __forceinline__ void bf_load8(const float2* p, int64_t ld, int r, int k0, int kq,
+                                         float2 (&v)[8]) {
+  if constexpr (KC) {
+    typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
+    const float2* q = p + (int64_t)r * ld;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const f4u w = ldg((const f4u*)(q + min(k0 + 2 * u, kq - 2)));
+      v[2 * u] = make_float2(w.x, w.y);
+      v[2 * u + 1] = make_float2(w.z, w.w);
+    }
+  } else {
+    const float2* q = p + r;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ldc(q + (int64_t)min(k0 + u, kq - 1) * ld);
+  }
+}
+
+// The entries bf_load8 loaded with the same k0, kq, masked (zero where `rv`
+// is false or k >= kn) and conjugated when `cj`, split into the three bf16
+// planes: w[plane][pair], planes Re x0, x1, x2, Im x0, x1, x2.
+template <bool KC>
+__device__ __forceinline__ void bf_split8(const float2 (&v)[8], bool rv, int k0, int kn, int kq,
+                                          bool cj, unsigned (&w)[6][4]) {
+  float2 x[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = k0 + u;
+    float2 y = v[u];
+    // KC: a pair read from kq - 2 because e = kq - 1 holds e in its upper half
+    if (KC && (u & 1) == 0 && e == kq - 1) y = v[u + 1];
+    x[u] = rv && e < kn ? y : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    bf16_split3(x[2 * q].x, x[2 * q + 1].x, w[0][q], w[1][q], w[2][q]);
+    const float i0 = cj ? -x[2 * q].y : x[2 * q].y, i1 = cj ? -x[2 * q + 1].y : x[2 * q + 1].y;
+    bf16_split3(i0, i1, w[3][q], w[4][q], w[5][q]);
+  }
+}
+
+__device__ __forceinline__ void bf_store8(unsigned short (&pl)[6][GT][BLD], int r, int k0,
+                                          const unsigned (&w)[6][4]) {
+#pragma unroll
+  for (int p = 0; p < 6; ++p) *(u32x4*)&pl[p][r][k0] = u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
+}
+
+__device__ __forceinline__ flt4 mfma_bf16(u32x4 a, u32x4 b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// gemm_tile for FP32 operands through the bf16 split (same contract).  One
+// LDS stage, software pipelined over registers: while stage s is multiplied
+// out of LDS, the entries of stage s + 1 (loaded during stage s - 1) are
+// split, and the loads of stage s + 2 are issued; the split stage is written
+// to LDS between two barriers.
+template <int OPA, int OPB>
+__device__ __forceinline__ void gemm_tile_bf(const GemmDesc<float>& d, int i0, int j0, int kbeg,
+                                             int kend, bool atomic, float2* cb, int64_t cld,
+                                             float beta, BfStage& S) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  tri_krange<float, OPA, OPB>(d, i0, j0, kbeg, kend);
+  flt4 arr[2][2], aii[2][2], ax[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) arr[a][b] = aii[a][b] = ax[a][b] = flt4{0, 0, 0, 0};
+  // op(A)(i, l): A[i + l lda] (op N: rows contiguous) or conj A[l + i lda];
+  // op(B)(l, j): B[l + j ldb] (op N: k contiguous) or conj B[j + l ldb]
+  constexpr bool AKC = OPA != OpN, BKC = OPB == OpN;
+  const int ra = AKC ? tid >> 2 : tid & 63, ka = AKC ? 8 * (tid & 3) : 8 * (tid >> 6);
+  const int rb = BKC ? tid >> 2 : tid & 63, kb = BKC ? 8 * (tid & 3) : 8 * (tid >> 6);
+  const bool rva = ra < d.m - i0, rvb = rb < d.n - j0;
+  const int rac = min(ra, d.m - i0 - 1), rbc = min(rb, d.n - j0 - 1);
+  const int nst = (kend - kbeg + BK - 1) / BK;
+  const int llast = kbeg + max(nst - 1, 0) * BK;   // stages past the end reload the last
+  float2 va[8], vb[8];
+  unsigned wa[6][4], wb[6][4];
+  auto gload = [&](int l0) __attribute__((always_inline)) {
+    l0 = min(l0, llast);
+    const float2* pa = AKC ? d.A + l0 + (int64_t)i0 * d.lda : d.A + i0 + (int64_t)l0 * d.lda;
+    const float2* pb = BKC ? d.B + l0 + (int64_t)j0 * d.ldb : d.B + j0 + (int64_t)l0 * d.ldb;
+    bf_load8<AKC>(pa, d.lda, rac, ka, d.k - l0, va);
+    bf_load8<BKC>(pb, d.ldb, rbc, kb, d.k - l0, vb);
+  };
+  auto split = [&](int l0) __attribute__((always_inline)) {
+    l0 = min(l0, llast);
+    bf_split8<AKC>(va, rva, ka, kend - l0, d.k - l0, OPA != OpN, wa);
+    bf_split8<BKC>(vb, rvb, kb, kend - l0, d.k - l0, OPB != OpN, wb);
+  };
+  if (nst > 0) {
+    gload(kbeg);
+    split(kbeg);
+    gload(kbeg + BK);
+  }
+  const int g8 = 8 * (lane >> 4), rl = lane & 15;
+  for (int st = 0; st < nst; ++st) {
+    bf_store8(S.p[0], ra, ka, wa);
+    bf_store8(S.p[1], rb, kb, wb);
+    __syncthreads();
+    u32x4 fb[2][6], fa[3][2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) fb[b][q] = *(const u32x4*)&S.p[1][q][wc + 16 * b + rl][g8];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        fa[p][a][0] = *(const u32x4*)&S.p[0][p][wr + 16 * a + rl][g8];
+        fa[p][a][1] = *(const u32x4*)&S.p[0][3 + p][wr + 16 * a + rl][g8];
+      }
+    // the next stage's split, then the loads of the one after it
+    split(kbeg + (st + 1) * BK);
+    gload(kbeg + (st + 2) * BK);
+    // terms (p, q), p + q <= 2, smallest first
+#pragma unroll
+    for (int p = 2; p >= 0; --p)
+#pragma unroll
+      for (int q = 2 - p; q >= 0; --q)
+#pragma unroll
+        for (int kind = 0; kind < 4; ++kind)
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              if (kind == 0) arr[a][b] = mfma_bf16(fa[p][a][0], fb[b][q], arr[a][b]);
+              if (kind == 1) aii[a][b] = mfma_bf16(fa[p][a][1], fb[b][3 + q], aii[a][b]);
+              if (kind == 2) ax[a][b] = mfma_bf16(fa[p][a][0], fb[b][3 + q], ax[a][b]);
+              if (kind == 3) ax[a][b] = mfma_bf16(fa[p][a][1], fb[b][q], ax[a][b]);
+            }
+    // issue order: the LDS reads, then the products with the split's
+    // arithmetic and the loads spread among them
+    __builtin_amdgcn_sched_group_barrier(0x100, 24, 0);
+#pragma unroll
+    for (int i = 0; i < 56; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 24, 0);
+    __syncthreads();
+  }
+  flt4 cr[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) cr[a][b] = arr[a][b] - aii[a][b];
+  gemm_store_tile<float>(d, i0, j0, atomic, cb, cld, beta, cr, ax);
+}
+
+// The workgroup's share of a launch: tile(i0, j0, kbeg, kend, atomic, cb,
+// cld, beta) for each output tile (and k range) it takes.
 // splits > 1: blockIdx.z takes the k range [z kc, (z+1) kc) and the result is
 // added atomically (C must already hold beta C), or, with `part`, stored as
 // the 64 x 64 partial tile part[((y splits + z) gridDim.x + x) 4096] (column
@@ -385,12 +620,9 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, 
 // contiguous shares to its sk workgroups (blockIdx.x); a share may end in
 // one tile and go on in the next, and every piece is added atomically to a
 // pre-scaled C.  Equal shares leave no partial last round of workgroups.
-template <typename T, int OPA, int OPB, class DS>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS descs, int splits,
-                                                                          int sk, cplx<T>* part) {
-  __shared__ T As[2][2][GK][gemm_ldt<T>()];   // [buffer][re, im][k][row]
-  __shared__ T Bs[2][2][GK][gemm_ldt<T>()];
-  const GemmDesc<T> d = descs[blockIdx.y];
+template <typename T, class F>
+__device__ __forceinline__ void gemm_share(const GemmDesc<T>& d, int splits, int sk, cplx<T>* part,
+                                           F&& tile) {
   const int tm = (d.m + GT - 1) / GT, tn = (d.n + GT - 1) / GT;
   if (sk > 0) {
     const int nst = (d.k + GK - 1) / GK;
@@ -398,11 +630,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS de
     int64_t u = units * blockIdx.x / sk;
     const int64_t u1 = units * (blockIdx.x + 1) / sk;
     while (u < u1) {
-      const int tile = (int)(u / nst), s0 = (int)(u % nst);
+      const int tl = (int)(u / nst), s0 = (int)(u % nst);
       const int s1 = (int)min((int64_t)nst, s0 + (u1 - u));
-      const int i0 = (tile % tm) * GT, j0 = (tile / tm) * GT;
-      gemm_tile<T, OPA, OPB>(d, i0, j0, s0 * GK, min(d.k, s1 * GK), true,
-                             d.C + i0 + (int64_t)j0 * d.ldc, d.ldc, T(0), As, Bs);
+      const int i0 = (tl % tm) * GT, j0 = (tl / tm) * GT;
+      tile(i0, j0, s0 * GK, min(d.k, s1 * GK), true, d.C + i0 + (int64_t)j0 * d.ldc, d.ldc, T(0));
       u += s1 - s0;
     }
     return;
@@ -417,11 +648,36 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS de
   if (part) {
     cplx<T>* cb = part + (((size_t)blockIdx.y * splits + blockIdx.z) * gridDim.x + blockIdx.x) *
                              (size_t)(GT * GT);
-    gemm_tile<T, OPA, OPB>(d, i0, j0, kbeg, kend, false, cb, GT, T(0), As, Bs);
+    tile(i0, j0, kbeg, kend, false, cb, (int64_t)GT, T(0));
   } else {
-    gemm_tile<T, OPA, OPB>(d, i0, j0, kbeg, kend, splits > 1, d.C + i0 + (int64_t)j0 * d.ldc,
-                           d.ldc, d.beta, As, Bs);
+    tile(i0, j0, kbeg, kend, splits > 1, d.C + i0 + (int64_t)j0 * d.ldc, (int64_t)d.ldc, d.beta);
   }
+}
+
+template <typename T, int OPA, int OPB, class DS>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS descs, int splits,
+                                                                          int sk, cplx<T>* part) {
+  __shared__ T As[2][2][GK][gemm_ldt<T>()];   // [buffer][re, im][k][row]
+  __shared__ T Bs[2][2][GK][gemm_ldt<T>()];
+  const GemmDesc<T> d = descs[blockIdx.y];
+  gemm_share<T>(d, splits, sk, part,
+                [&](int i0, int j0, int kb, int ke, bool atomic, cplx<T>* cb, int64_t cld,
+                    T beta) __attribute__((always_inline)) {
+                  gemm_tile<T, OPA, OPB>(d, i0, j0, kb, ke, atomic, cb, cld, beta, As, Bs);
+                });
+}
+
+// gemm_kernel for FP32 operands on the bf16 matrix cores (the split above)
+template <int OPA, int OPB, class DS>
+__global__ __launch_bounds__(256, 2) void gemm_bf_kernel(DS descs, int splits, int sk,
+                                                         float2* part) {
+  __shared__ BfStage S;
+  const GemmDesc<float> d = descs[blockIdx.y];
+  gemm_share<float>(d, splits, sk, part,
+                    [&](int i0, int j0, int kb, int ke, bool atomic, float2* cb, int64_t cld,
+                        float beta) __attribute__((always_inline)) {
+                      gemm_tile_bf<OPA, OPB>(d, i0, j0, kb, ke, atomic, cb, cld, beta, S);
+                    });
 }
 
 // C = sum over z of the partial tiles (in order z = 0, 1, ...) + beta C:
@@ -2011,7 +2267,11 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
     // half their rate under stream-K, whose many short shares are bound by
     // the atomics.
     const int64_t wgs = (int64_t)maxt * (int64_t)n;
-    const int64_t slots = (int64_t)device_cus() * (sizeof(T) == 4 ? 4 : 2);
+    // the split kernel reads k in pairs from a stored matrix: k = 1 stays on
+    // the FP32 instructions
+    bool bf = std::is_same<T, float>::value && g_fp32_split;
+    for (auto& g : sub) bf = bf && g.k != 1;
+    const int64_t slots = (int64_t)device_cus() * (sizeof(T) == 4 && !bf ? 4 : 2);
     int splits = 1;
     bool want_sk = splits_force == -3;
     if (force > 0) {
@@ -2090,7 +2350,24 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
                    (int)opA * 2 + (int)opB + 10 * (sk > 0 ? 99 : part ? 98 : splits), true);
       // the reduction pass, when there is one, ends the timed span
       hipEvent_t e1 = part ? nullptr : ps.stop();
-      if (opA == OpN && opB == OpN)
+      if constexpr (std::is_same<T, float>::value) {
+        if (bf) {
+          if (opA == OpN && opB == OpN)
+            hipExtLaunchKernelGGL((gemm_bf_kernel<OpN, OpN, DS>), grid, dim3(256), 0, pool.stream,
+                                  ps.start(), e1, 0, dd, splits, sk, part);
+          else if (opA == OpC && opB == OpN)
+            hipExtLaunchKernelGGL((gemm_bf_kernel<OpC, OpN, DS>), grid, dim3(256), 0, pool.stream,
+                                  ps.start(), e1, 0, dd, splits, sk, part);
+          else if (opA == OpN && opB == OpC)
+            hipExtLaunchKernelGGL((gemm_bf_kernel<OpN, OpC, DS>), grid, dim3(256), 0, pool.stream,
+                                  ps.start(), e1, 0, dd, splits, sk, part);
+          else
+            hipExtLaunchKernelGGL((gemm_bf_kernel<OpC, OpC, DS>), grid, dim3(256), 0, pool.stream,
+                                  ps.start(), e1, 0, dd, splits, sk, part);
+        }
+      }
+      if (bf) {
+      } else if (opA == OpN && opB == OpN)
         hipExtLaunchKernelGGL((gemm_kernel<T, OpN, OpN, DS>), grid, dim3(256), 0, pool.stream,
                               ps.start(), e1, 0, dd, splits, sk, part);
       else if (opA == OpC && opB == OpN)

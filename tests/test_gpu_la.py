@@ -14,7 +14,8 @@ from paper_2607_00928_amd import _lib  # noqa: E402
 lib = _lib.lib
 DEV = torch.device("cuda", 0)
 CT = {0: (np.complex128, torch.complex128), 1: (np.complex64, torch.complex64)}
-TOL = {0: 1e-12, 1: 2e-5}
+CT[2] = CT[1]   # complex64 with the products on the bf16 split
+TOL = {0: 1e-12, 1: 2e-5, 2: 2e-5}
 QB = 256   # reflectors per compact-WY block of the QR factors (T layout)
 
 
@@ -42,11 +43,13 @@ def i64(a):
     return a, a.ctypes.data_as(C.POINTER(C.c_int64))
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_gemm_batched_ragged(prec, opa, opb):
     rng = np.random.default_rng(10 * prec + 2 * opa + opb)
     shapes = [(1, 1, 1), (70, 33, 19), (64, 64, 64), (130, 5, 200), (3, 150, 17), (65, 129, 0)]
+    if prec == 2:   # a k = 1 product keeps its launch on the FP32 instructions
+        shapes[0] = (1, 1, 2)
     mats, keep = [], []
     mnk, ld, ptr = [], [], []
     alpha = 0.7 - 0.3j
@@ -72,6 +75,46 @@ def test_gemm_batched_ragged(prec, opa, opb):
         got = from_dev(tc, m, n)
         scale = max(1.0, np.abs(ref).max())
         assert np.abs(got - ref).max() < TOL[prec] * scale * max(1, k) ** 0.5 * 10, (m, n, k)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_fp32_entrywise_error(prec, opa, opb):
+    """Each entry of a complex64 product against the FP64 product of the same
+    (rounded) operands, relative to (|op(A)| |op(B)|)_ij: FP32 rounding of k
+    products and sums stays within a few times 2^-24 sqrt(k) of it.  The bf16
+    split (prec 2) must meet the same bound as the FP32 instructions: a
+    dropped split product (a0 b1, a1 b0: 2^-8; a0 b2, a1 b1, a2 b0: 2^-16)
+    or a lost plane would exceed it by orders of magnitude.  Odd k (the split
+    kernel reads k in pairs), k = 2, tiles past the matrix edge, long k with
+    the library's split choice, alpha complex, beta = 0.5."""
+    rng = np.random.default_rng(300 + 4 * prec + 2 * opa + opb)
+    shapes = [(70, 33, 19), (2, 3, 2), (129, 65, 33), (64, 64, 64), (200, 150, 999),
+              (17, 300, 3001), (1, 130, 77)]
+    alpha, beta = 0.8 - 0.5j, 0.5
+    mats, keep, mnk, ld, ptr = [], [], [], [], []
+    for (m, n, k) in shapes:
+        A = crandn(rng, *((m, k) if opa == 0 else (k, m))).astype(np.complex64)
+        B = crandn(rng, *((k, n) if opb == 0 else (n, k))).astype(np.complex64)
+        Cm = crandn(rng, m, n).astype(np.complex64)
+        ts = [to_dev(X, prec) for X in (A, B, Cm)]
+        keep += ts
+        mats.append((A, B, Cm, ts[2]))
+        mnk += [m, n, k]
+        ld += [A.shape[0], B.shape[0], m]
+        ptr += [t.data_ptr() for t in ts]
+    a1, p1 = i32(mnk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_gemm(prec, opa, opb, len(shapes), p1, p2, p3, alpha.real, alpha.imag, beta)
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+        oA = (A if opa == 0 else A.conj().T).astype(np.complex128)
+        oB = (B if opb == 0 else B.conj().T).astype(np.complex128)
+        ref = alpha * (oA @ oB) + beta * Cm.astype(np.complex128)
+        scale = abs(alpha) * (np.abs(oA) @ np.abs(oB)) + beta * np.abs(Cm)
+        err = (np.abs(from_dev(tc, m, n) - ref) / scale).max()
+        assert err < 8 * 2.0 ** -24 * np.sqrt(k), (m, n, k, err)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -109,7 +152,7 @@ def test_gemm_skinny(prec, opa, beta):
         assert np.abs(got - ref).max() < TOL[prec] * scale * max(1, k) ** 0.5 * 10, (m, n, k)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_geqrf_ormqr(prec):
     rng = np.random.default_rng(3 + prec)
     # around the 256-column blocks and their 128-column halves: a block with
@@ -283,7 +326,7 @@ def test_trsv(prec, ct):
         assert np.abs(X - ref).max() < 100 * TOL[prec] * max(1, np.abs(ref).max())
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_gemm_large_batch(prec, opa, opb):
     """A batch of 24 products of a few hundred rows and columns (many tiles,
@@ -291,7 +334,7 @@ def test_gemm_large_batch(prec, opa, opb):
     tiny product and an empty one in the same batch, beta = 1."""
     rng = np.random.default_rng(40 + 10 * prec + 2 * opa + opb)
     shapes = [(600 - 7 * i, 520 + 5 * i, 200 + 13 * i) for i in range(24)]
-    shapes += [(3, 2, 5), (0, 4, 4), (130, 129, 1)]
+    shapes += [(3, 2, 5), (0, 4, 4), (130, 129, 1 if prec != 2 else 3)]
     mats, keep = [], []
     mnk, ld, ptr = [], [], []
     alpha = 0.9 + 0.2j
@@ -408,6 +451,7 @@ def test_gemm_small_output_long_k(prec, beta):
 @pytest.mark.parametrize("prec,shapes", [
     (0, [(40000, 40), (20000, 70), (9000, 33), (600, 20)]),
     (1, [(40000, 40), (20000, 70), (9000, 33), (600, 20)]),
+    (2, [(40000, 40), (20000, 70), (9000, 33), (600, 20)]),
     # taller than one row slab per CU holds (65536 FP64 / 131072 FP32 rows):
     # twice the rows per workgroup
     (0, [(90000, 36), (3000, 40)]),
@@ -501,7 +545,7 @@ def test_gemm_split_k_few_tiles(opa, opb, beta):
         assert np.abs(got - ref).max() < TOL[1] * scale * k ** 0.5 * 10, (m, n, k)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0)])
 def test_gemm_long_descriptor_list(prec, opa, opb):
     """100 ragged products in one launch: a descriptor list longer than fits in
@@ -585,7 +629,7 @@ def test_gemm_small_m_wide_long_k(prec, beta):
         assert np.all(np.abs(got - ref) <= bound + 4 * u * np.abs(ref)), (m, n, k)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1)])
 def test_gemm_few_row_tiles(prec, opa, opb):
     """Products with at most 256 rows and many column tiles (the shape of the
@@ -664,7 +708,7 @@ def test_copy_conj_transpose(pd, ps):
         assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_gemm_stream_k(prec, opa, opb):
     """Stream-K shares forced on a ragged batch: each descriptor's tiles x k
@@ -709,7 +753,7 @@ def test_gemm_stream_k(prec, opa, opb):
             assert np.abs(got - ref).max() < TOL[prec] * scale * max(k, 1) ** 0.5 * 10, (m, n, k)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("opa,opb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_gemm_partial_tile_splits(prec, opa, opb):
     """k splits kept as partial tiles in scratch and summed in split order by a
