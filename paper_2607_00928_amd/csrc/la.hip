@@ -499,9 +499,68 @@ __device__ __forceinline__ void bf_store8(unsigned short (&pl)[6][GT][BLD], int 
   for (int p = 0; p < 6; ++p) *(u32x4*)&pl[p][r][k0] = u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
 }
 
-__device__ __forceinline__ flt4 mfma_bf16(u32x4 a, u32x4 b, flt4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+typedef float flt16 __attribute__((ext_vector_type(16)));
+// 32x32x16 bf16 step: lane l supplies A[l % 32][8 (l / 32) .. + 7] and
+// B[8 (l / 32) .. + 7][l % 32]; accumulator register v of lane l holds
+// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]
+__device__ __forceinline__ flt16 mfma_bf16(u32x4 a, u32x4 b, flt16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// Store of the 64 x 64 tile as gemm_store_tile, held by the four waves as one
+// 32 x 32 block each (wave at (32 (wave / 2), 32 (wave % 2))) in the layout
+// of mfma_bf16.
+__device__ __forceinline__ void gemm_store_tile32(const GemmDesc<float>& d, int i0, int j0,
+                                                  bool atomic, float2* cb, int64_t cld, float beta,
+                                                  const flt16& cr, const flt16& ci) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = j0 + (wave & 1) * 32 + (lane & 31);
+  if (j >= d.n) return;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int ib = i0 + (wave >> 1) * 32 + 8 * g + 4 * (lane >> 5);
+    if (ib >= d.m) continue;
+    float2 out[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float re = cr[4 * g + v], im = ci[4 * g + v];
+      out[v] = make_float2(d.ar * re - d.ai * im, d.ar * im + d.ai * re);
+    }
+    float2* p = cb + (int64_t)(ib - i0) + (int64_t)(j - j0) * cld;
+    if (atomic) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (ib + v >= d.m) break;
+        atomic_addg(&p[v].x, out[v].x);
+        atomic_addg(&p[v].y, out[v].y);
+      }
+    } else if (ib + 3 < d.m) {
+      typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
+      f4u* q = (f4u*)p;
+      f4u w0 = {out[0].x, out[0].y, out[1].x, out[1].y};
+      f4u w1 = {out[2].x, out[2].y, out[3].x, out[3].y};
+      if (beta != 0.f) {
+        const f4u o0 = ldg(q), o1 = ldg(q + 1);
+        w0 += beta * o0;
+        w1 += beta * o1;
+      }
+      stg(q, w0);
+      stg(q + 1, w1);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (ib + v >= d.m) break;
+        float2 o = out[v];
+        if (beta != 0.f) {
+          const float2 c = ldc(p + v);
+          o.x += beta * c.x;
+          o.y += beta * c.y;
+        }
+        stc(p + v, o);
+      }
+    }
+  }
 }
 
 // gemm_tile for FP32 operands through the bf16 split (same contract).  One
@@ -516,11 +575,9 @@ __device__ __forceinline__ void gemm_tile_bf(const GemmDesc<float>& d, int i0, i
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   tri_krange<float, OPA, OPB>(d, i0, j0, kbeg, kend);
-  flt4 arr[2][2], aii[2][2], ax[2][2];
+  flt16 arr, aii, ax;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) arr[a][b] = aii[a][b] = ax[a][b] = flt4{0, 0, 0, 0};
+  for (int v = 0; v < 16; ++v) arr[v] = aii[v] = ax[v] = 0.f;
   // op(A)(i, l): A[i + l lda] (op N: rows contiguous) or conj A[l + i lda];
   // op(B)(l, j): B[l + j ldb] (op N: k contiguous) or conj B[j + l ldb]
   constexpr bool AKC = OPA != OpN, BKC = OPB == OpN;
@@ -549,22 +606,19 @@ __device__ __forceinline__ void gemm_tile_bf(const GemmDesc<float>& d, int i0, i
     split(kbeg);
     gload(kbeg + BK);
   }
-  const int g8 = 8 * (lane >> 4), rl = lane & 15;
+  const int g8 = 8 * (lane >> 5), rl = lane & 31;
   for (int st = 0; st < nst; ++st) {
     bf_store8(S.p[0], ra, ka, wa);
     bf_store8(S.p[1], rb, kb, wb);
     __syncthreads();
-    u32x4 fb[2][6], fa[3][2][2];
+    // [k half][plane]
+    u32x4 fa[2][6], fb[2][6];
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int q = 0; q < 6; ++q) fb[b][q] = *(const u32x4*)&S.p[1][q][wc + 16 * b + rl][g8];
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        fa[p][a][0] = *(const u32x4*)&S.p[0][p][wr + 16 * a + rl][g8];
-        fa[p][a][1] = *(const u32x4*)&S.p[0][3 + p][wr + 16 * a + rl][g8];
+      for (int q = 0; q < 6; ++q) {
+        fa[h][q] = *(const u32x4*)&S.p[0][q][wr + rl][16 * h + g8];
+        fb[h][q] = *(const u32x4*)&S.p[1][q][wc + rl][16 * h + g8];
       }
     // the next stage's split, then the loads of the one after it
     split(kbeg + (st + 1) * BK);
@@ -575,38 +629,29 @@ __device__ __forceinline__ void gemm_tile_bf(const GemmDesc<float>& d, int i0, i
 #pragma unroll
       for (int q = 2 - p; q >= 0; --q)
 #pragma unroll
-        for (int kind = 0; kind < 4; ++kind)
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-              if (kind == 0) arr[a][b] = mfma_bf16(fa[p][a][0], fb[b][q], arr[a][b]);
-              if (kind == 1) aii[a][b] = mfma_bf16(fa[p][a][1], fb[b][3 + q], aii[a][b]);
-              if (kind == 2) ax[a][b] = mfma_bf16(fa[p][a][0], fb[b][3 + q], ax[a][b]);
-              if (kind == 3) ax[a][b] = mfma_bf16(fa[p][a][1], fb[b][q], ax[a][b]);
-            }
+        for (int h = 0; h < 2; ++h) {
+          arr = mfma_bf16(fa[h][p], fb[h][q], arr);
+          aii = mfma_bf16(fa[h][3 + p], fb[h][3 + q], aii);
+          ax = mfma_bf16(fa[h][p], fb[h][3 + q], ax);
+          ax = mfma_bf16(fa[h][3 + p], fb[h][q], ax);
+        }
     // issue order: the LDS reads, then the products with the split's
     // arithmetic and the loads spread among them
     __builtin_amdgcn_sched_group_barrier(0x100, 24, 0);
 #pragma unroll
-    for (int i = 0; i < 56; ++i) {
+    for (int i = 0; i < 28; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, 24, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
     __syncthreads();
   }
-  flt4 cr[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) cr[a][b] = arr[a][b] - aii[a][b];
-  gemm_store_tile<float>(d, i0, j0, atomic, cb, cld, beta, cr, ax);
+  gemm_store_tile32(d, i0, j0, atomic, cb, cld, beta, arr - aii, ax);
 }
 
 // The workgroup's share of a launch: tile(i0, j0, kbeg, kend, atomic, cb,
