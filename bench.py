@@ -43,6 +43,11 @@ GRID_WORKLOADS = {
 
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
+# FP32 products on the bf16 matrix cores (fp32_products "bf16x3"): six bf16
+# products per real FP32 product, so the class's algorithmic FP32 flops run
+# against a sixth of the bf16 peak
+SPLIT_PEAK_TFLOPS = BF16_PEAK_TFLOPS / 6
 # kernel classes of the library's per-launch timing (nudft2_info.kernel_ms)
 NCLASS = 6
 TIMED_CLASSES = (1,)
@@ -58,6 +63,8 @@ def main():
     ap.add_argument("--refine", type=int, default=0, choices=[0, 1, 2],
                     help="0 iterative refinement, 1 PCG on the normal equations, 2 plsqr")
     ap.add_argument("--eps", type=float, default=1e-2)
+    ap.add_argument("--fp32-products", default="bf16x3", choices=["bf16x3", "fp32"],
+                    help="matrix instructions of the FP32 factorization's products")
     ap.add_argument("--ir-tol", type=float, default=1e-10)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-factor comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -104,7 +111,8 @@ def main():
     p0.close()
 
     if args.profile_sweep:
-        plan = nd.Plan(pr.points, nx, ny, precision="fp32", eps=args.eps, ir_maxit=0)
+        plan = nd.Plan(pr.points, nx, ny, precision="fp32", eps=args.eps, ir_maxit=0,
+                       fp32_products=args.fp32_products)
         plan.factor()
         torch.cuda.synchronize()
         ts = []
@@ -123,7 +131,7 @@ def main():
     def step(precision, profile=False):
         t0 = time.perf_counter()
         plan = nd.Plan(pr.points, nx, ny, precision=precision, eps=args.eps, ir_maxit=200,
-                       ir_tol=args.ir_tol, refine=args.refine)
+                       ir_tol=args.ir_tol, refine=args.refine, fp32_products=args.fp32_products)
         if profile:
             # per-launch events for the dominant class only (the FP32
             # matrix-core GEMMs: about three quarters of the step's kernel
@@ -186,24 +194,35 @@ def main():
     names = ["apply_fp64", "gemm_fp32_mfma", "gemm_fp64_mfma", "qr_panel", "gemv_fp32",
              "gemv_fp64"]
     dominant = max(range(NCLASS), key=lambda i: kms[i])
-    peaks = [FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS, FP64_PEAK_TFLOPS, None, None, None]
+    split = args.fp32_products == "bf16x3"
+    peaks = [FP64_PEAK_TFLOPS, SPLIT_PEAK_TFLOPS if split else FP32_PEAK_TFLOPS,
+             FP64_PEAK_TFLOPS, None, None, None]
     avg_ms = kms[dominant] / max(kn[dominant], 1)
     per_launch = kfl[dominant] / max(kn[dominant], 1)
     ach = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 and per_launch > 0 else None
     pk = peaks[dominant]
-    rec = gemm_record() if dominant == 1 else None
+    rec = gemm_record(args.fp32_products) if dominant == 1 else None
     roof = dict(bound="mfma", achieved=ach, peak=pk, unit="TFLOP/s",
                 frac=(ach / pk if ach is not None and pk else None),
                 traffic=rec["hbm_bytes_per_launch"] if rec else None,
                 kernel=names[dominant], avg_launch_ms=avg_ms, launches=kn[dominant],
                 flops_per_launch=per_launch)
+    if dominant == 1:
+        roof.update(mfma_dtype="bf16" if split else "fp32",
+                    peak_basis=("bf16 dense matrix peak 2500 TFLOP/s / 6 (six bf16 products "
+                                "of split FP32 operands per real FP32 product)" if split
+                                else "fp32 dense matrix peak"))
     if rec and ach is not None:
         # achieved counts 8 algorithmic flops per complex multiply-add; the
-        # matrix cores execute fewer (Gauss's three real products), as the
-        # committed PMC record measures: executed rate / peak, and the busy
-        # counter's fraction of the class's time
-        ex = rec["executed_mfma_flops_per_launch"] / rec["flops_per_launch"]
-        roof.update(executed_frac=ach * ex / pk, mfma_busy_frac=rec["mfma_busy_frac"],
+        # matrix cores execute a different count (six bf16 products per real
+        # product on the split, Gauss's three real products on the FP32
+        # instructions), as the committed PMC record measures: executed rate
+        # over each instruction kind's peak, and the busy counter's fraction
+        # of the class's time
+        t = rec["flops_per_launch"] / (ach * 1e12)   # seconds per launch at this rate
+        ex = (rec.get("executed_bf16_flops_per_launch", 0.0) / t / 1e12 / BF16_PEAK_TFLOPS +
+              rec.get("executed_f32_flops_per_launch", 0.0) / t / 1e12 / FP32_PEAK_TFLOPS)
+        roof.update(executed_frac=ex, mfma_busy_frac=rec["mfma_busy_frac"],
                     algorithmic_flop_per_hbm_byte=rec["flops_per_launch"] / rec["hbm_bytes_per_launch"])
     kernels = {names[i]: dict(ms=kms[i], launches=kn[i],
                               tflops=(kfl[i] / (kms[i] * 1e-3) / 1e12 if kms[i] > 0 and kfl[i] > 0 else None))
@@ -322,6 +341,7 @@ def main():
         "data": ("synthetic (seeded %s grid, complex Gaussian coefficients)"
                  % ("jittered" if args.workload in WORKLOADS else GRID_WORKLOADS[args.workload][0])),
         "config": {"workload": wl_desc, "precision": "fp32+ir", "ir_tol": args.ir_tol,
+                   "fp32_products": args.fp32_products,
                    "refine": ["iterative refinement", "pcg-ne", "plsqr"][args.refine]},
         "factor_s": float(np.median([r["factor_s"] for r in recs])),
         "solve_s": float(np.median([r["solve_s"] for r in recs])),
@@ -346,11 +366,12 @@ def main():
     print(json.dumps(out))
 
 
-def gemm_record():
+def gemm_record(products):
     """The FP32 GEMM class's committed rocprofv3 PMC record (HBM bytes per
     launch from FETCH_SIZE / WRITE_SIZE scaled by a plain copy of known size;
     executed matrix-core flops and busy fraction); None when the kernel source
-    changed since the counters were taken."""
+    changed since the counters were taken or they were taken on the other
+    kind of FP32 product."""
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "gemm_fp32_traffic_n512.md")
     src = os.path.join(root, "paper_2607_00928_amd", "csrc", "la.hip")
@@ -359,6 +380,8 @@ def gemm_record():
         with open(src, "rb") as fh:
             if hashlib.sha256(fh.read()).hexdigest() != rec["la_hip_sha256"]:
                 return None
+        if rec.get("fp32_products", "fp32") != products:
+            return None
         return rec
     except Exception:
         return None
