@@ -1,8 +1,10 @@
 // Batched complex GEMM / Householder QR / pivoted Cholesky / triangular solve
-// for gfx950.  GEMM-shaped work runs on the 16x16x4 matrix cores (FP64 or
-// FP32 with FP32 accumulation): a complex product is three real MFMA
-// products in Gauss's form, p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi),
-// with Cr = p1 - p2 and Ci = p3 - p1 - p2 formed at the store.
+// for gfx950.  GEMM-shaped work runs on the matrix cores.  On the 16x16x4
+// FP64 / FP32 instructions a complex product is three real products in
+// Gauss's form, p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi), with
+// Cr = p1 - p2 and Ci = p3 - p1 - p2 formed at the store.  FP32 tile
+// products run by default on the bf16 instructions through an exact
+// three-way split of every operand entry (gemm_tile_bf).
 #include <algorithm>
 #include <cstdlib>
 #include <cstdio>
@@ -417,20 +419,22 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc<T>& d, int i0, int j0, 
 // the result carries the error of an FP32 dot product (one more unit of
 // 2^-24 |a| |b| a term) and keeps FP32's exponent range.  A complex product
 // takes four real ones in three accumulators per block (Ar Br, Ai Bi, and
-// Ar Bi + Ai Br).  The 16x16x32 bf16 instruction does 16 times the FP32
-// instruction's multiply-adds per cycle, so the 24 of a complex block cost
-// 3/8 of the FP32 path's Gauss products.  Each operand entry is split once,
-// as its stage is written to LDS.
-constexpr int BK = 32;        // k per stage: one 16x16x32 instruction
-constexpr int BLD = BK + 8;   // bf16 per LDS row (80 bytes: the 16 rows of a
-                              // 16-byte read start on distinct banks)
+// Ar Bi + Ai Br).  The bf16 matrix instructions do 16 times the FP32 ones'
+// multiply-adds per cycle, so the 24 bf16 products of a complex
+// multiply-add cost 3/8 of the FP32 path's three Gauss products.  Each
+// operand entry is split once, as its stage is written to LDS.
+constexpr int BK = 32;   // k per stage: two 32x32x16 instructions
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-// one stage: [op(A), op(B)][plane: Re x0, x1, x2, Im x0, x1, x2][row i of
-// op(A) / column j of op(B)][k]
+// One stage: [op(A), op(B)][plane: Re x0, x1, x2, Im x0, x1, x2][row i of
+// op(A) / column j of op(B)][k] (48 KB: three workgroups a CU).  A row's
+// 32 k are four 16-byte chunks; chunk c of row r sits at position
+// c ^ ((r / 4) % 4), so the 8 rows of a 16-byte access phase start on
+// distinct banks.
 struct BfStage {
-  unsigned short p[2][6][GT][BLD];
+  unsigned short p[2][6][GT][BK];
 };
+__device__ __forceinline__ int bf_chunk(int r, int c) { return (c ^ (r >> 2)) & 3; }
 
 __device__ __forceinline__ unsigned bf16_pair(float lo, float hi) {
   typedef float f2 __attribute__((ext_vector_type(2)));
@@ -493,10 +497,11 @@ __device__ __forceinline__ void bf_split8(const float2 (&v)[8], bool rv, int k0,
   }
 }
 
-__device__ __forceinline__ void bf_store8(unsigned short (&pl)[6][GT][BLD], int r, int k0,
+__device__ __forceinline__ void bf_store8(unsigned short (&pl)[6][GT][BK], int r, int k0,
                                           const unsigned (&w)[6][4]) {
+  const int c = 8 * bf_chunk(r, k0 >> 3);
 #pragma unroll
-  for (int p = 0; p < 6; ++p) *(u32x4*)&pl[p][r][k0] = u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
+  for (int p = 0; p < 6; ++p) *(u32x4*)&pl[p][r][c] = u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
 }
 
 typedef float flt16 __attribute__((ext_vector_type(16)));
@@ -564,10 +569,10 @@ __device__ __forceinline__ void gemm_store_tile32(const GemmDesc<float>& d, int 
 }
 
 // gemm_tile for FP32 operands through the bf16 split (same contract).  One
-// LDS stage, software pipelined over registers: while stage s is multiplied
-// out of LDS, the entries of stage s + 1 (loaded during stage s - 1) are
-// split, and the loads of stage s + 2 are issued; the split stage is written
-// to LDS between two barriers.
+// LDS stage: its entries, loaded during the previous stage, are masked, split
+// and written between two barriers, then the next stage's loads are issued
+// and the stage is multiplied out one k half at a time.  Register use is
+// held to three workgroups a CU, whose phases overlap.
 template <int OPA, int OPB>
 __device__ __forceinline__ void gemm_tile_bf(const GemmDesc<float>& d, int i0, int j0, int kbeg,
                                              int kend, bool atomic, float2* cb, int64_t cld,
@@ -588,7 +593,6 @@ __device__ __forceinline__ void gemm_tile_bf(const GemmDesc<float>& d, int i0, i
   const int nst = (kend - kbeg + BK - 1) / BK;
   const int llast = kbeg + max(nst - 1, 0) * BK;   // stages past the end reload the last
   float2 va[8], vb[8];
-  unsigned wa[6][4], wb[6][4];
   auto gload = [&](int l0) __attribute__((always_inline)) {
     l0 = min(l0, llast);
     const float2* pa = AKC ? d.A + l0 + (int64_t)i0 * d.lda : d.A + i0 + (int64_t)l0 * d.lda;
@@ -596,59 +600,39 @@ __device__ __forceinline__ void gemm_tile_bf(const GemmDesc<float>& d, int i0, i
     bf_load8<AKC>(pa, d.lda, rac, ka, d.k - l0, va);
     bf_load8<BKC>(pb, d.ldb, rbc, kb, d.k - l0, vb);
   };
-  auto split = [&](int l0) __attribute__((always_inline)) {
-    l0 = min(l0, llast);
-    bf_split8<AKC>(va, rva, ka, kend - l0, d.k - l0, OPA != OpN, wa);
-    bf_split8<BKC>(vb, rvb, kb, kend - l0, d.k - l0, OPB != OpN, wb);
-  };
-  if (nst > 0) {
-    gload(kbeg);
-    split(kbeg);
-    gload(kbeg + BK);
-  }
-  const int g8 = 8 * (lane >> 5), rl = lane & 31;
+  if (nst > 0) gload(kbeg);
+  const int gc = lane >> 5, rl = lane & 31;
+  const int rA = wr + rl, rB = wc + rl;
   for (int st = 0; st < nst; ++st) {
-    bf_store8(S.p[0], ra, ka, wa);
-    bf_store8(S.p[1], rb, kb, wb);
+    const int l0 = kbeg + st * BK;
+    {
+      unsigned w[6][4];
+      bf_split8<AKC>(va, rva, ka, kend - l0, d.k - l0, OPA != OpN, w);
+      bf_store8(S.p[0], ra, ka, w);
+      bf_split8<BKC>(vb, rvb, kb, kend - l0, d.k - l0, OPB != OpN, w);
+      bf_store8(S.p[1], rb, kb, w);
+    }
     __syncthreads();
-    // [k half][plane]
-    u32x4 fa[2][6], fb[2][6];
+    gload(l0 + BK);
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < 2; ++h) {
+      u32x4 fa[6], fb[6];
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        fa[h][q] = *(const u32x4*)&S.p[0][q][wr + rl][16 * h + g8];
-        fb[h][q] = *(const u32x4*)&S.p[1][q][wc + rl][16 * h + g8];
+        fa[q] = *(const u32x4*)&S.p[0][q][rA][8 * bf_chunk(rA, 2 * h + gc)];
+        fb[q] = *(const u32x4*)&S.p[1][q][rB][8 * bf_chunk(rB, 2 * h + gc)];
       }
-    // the next stage's split, then the loads of the one after it
-    split(kbeg + (st + 1) * BK);
-    gload(kbeg + (st + 2) * BK);
-    // terms (p, q), p + q <= 2, smallest first
+      // terms (p, q), p + q <= 2, smallest first
 #pragma unroll
-    for (int p = 2; p >= 0; --p)
+      for (int p = 2; p >= 0; --p)
 #pragma unroll
-      for (int q = 2 - p; q >= 0; --q)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          arr = mfma_bf16(fa[h][p], fb[h][q], arr);
-          aii = mfma_bf16(fa[h][3 + p], fb[h][3 + q], aii);
-          ax = mfma_bf16(fa[h][p], fb[h][3 + q], ax);
-          ax = mfma_bf16(fa[h][3 + p], fb[h][q], ax);
+        for (int q = 2 - p; q >= 0; --q) {
+          arr = mfma_bf16(fa[p], fb[q], arr);
+          aii = mfma_bf16(fa[3 + p], fb[3 + q], aii);
+          ax = mfma_bf16(fa[p], fb[3 + q], ax);
+          ax = mfma_bf16(fa[3 + p], fb[q], ax);
         }
-    // issue order: the LDS reads, then the products with the split's
-    // arithmetic and the loads spread among them
-    __builtin_amdgcn_sched_group_barrier(0x100, 24, 0);
-#pragma unroll
-    for (int i = 0; i < 28; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
     }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
     __syncthreads();
   }
   gemm_store_tile32(d, i0, j0, atomic, cb, cld, beta, arr - aii, ax);
@@ -714,7 +698,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 4) void gemm_kernel(DS de
 
 // gemm_kernel for FP32 operands on the bf16 matrix cores (the split above)
 template <int OPA, int OPB, class DS>
-__global__ __launch_bounds__(256, 2) void gemm_bf_kernel(DS descs, int splits, int sk,
+__global__ __launch_bounds__(256, 3) void gemm_bf_kernel(DS descs, int splits, int sk,
                                                          float2* part) {
   __shared__ BfStage S;
   const GemmDesc<float> d = descs[blockIdx.y];
