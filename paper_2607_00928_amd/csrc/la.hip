@@ -1686,7 +1686,7 @@ __global__ void qr_finish_kernel(const QRDesc<T>* __restrict__ descs) {
 }
 
 // ------------------------------------------------------------ pivoted Cholesky
-constexpr int PC_NB = 64;   // pivots per panel (one Schur update of the Gram per panel)
+constexpr int PC_NB = 128;   // pivots per panel (one Schur update of the Gram per panel)
 
 __global__ void pchol_init_kernel(const PcholDesc* __restrict__ descs, double* trace_out) {
   const PcholDesc d = descs[blockIdx.x];
