@@ -1,7 +1,10 @@
 """Benchmark: factor + refined solve of the 2D type-II inverse NUDFT at
 n = 512 x 512 (N = 262144), M = 1024^2 jittered points, FP32 HSS factors with
 FP64 iterative refinement to ||dc||/||c|| <= 1e-10 (relative error vs the true
-coefficients reported), on one MI355X.
+coefficients reported), on one MI355X.  The refinement applies A and A^* by
+the NUFFT at tolerance 1e-13 (Section 4.1's operator; --nufft-tol 0 takes
+the exact FP64 direct sums), and both operators' refined solves are
+reported.
 
 A step = plan (binning + upload of the points) + factorization (1D HSS
 compression, face-splitting assembly, recompression, URV) + refined solve of
@@ -65,6 +68,10 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--fp32-products", default="bf16x3", choices=["bf16x3", "fp32"],
                     help="matrix instructions of the FP32 factorization's products")
+    ap.add_argument("--nufft-tol", type=float, default=1e-13,
+                    help="operator of the refinement: A and A^* by the NUFFT to this "
+                         "relative accuracy (Section 4.1; default 1e-13), 0 = the exact FP64 "
+                         "direct sums")
     ap.add_argument("--ir-tol", type=float, default=1e-10)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-factor comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -131,7 +138,8 @@ def main():
     def step(precision, profile=False):
         t0 = time.perf_counter()
         plan = nd.Plan(pr.points, nx, ny, precision=precision, eps=args.eps, ir_maxit=200,
-                       ir_tol=args.ir_tol, refine=args.refine, fp32_products=args.fp32_products)
+                       ir_tol=args.ir_tol, refine=args.refine, fp32_products=args.fp32_products,
+                       nufft_tol=args.nufft_tol)
         if profile:
             # per-launch events for the dominant class only (the FP32
             # matrix-core GEMMs: about three quarters of the step's kernel
@@ -253,7 +261,7 @@ def main():
             e16 = ((c16[15] / 16 - c_true).norm() / c_true.norm()).item()
             extra.setdefault("nrhs16", {})[key] = {"s": dt, "solves_per_s": 16 / dt,
                                                    "its": s16["iterations"], "rel_err_rhs16": e16}
-        last_plan.set_nufft_tol(0.0)
+        last_plan.set_nufft_tol(args.nufft_tol)
         log(f"nrhs16: {extra['nrhs16']}")
     # direct solve (no refinement): the sweep reads every URV factor once, so
     # its rate against the factor bytes it reads is its HBM roofline (timed
@@ -273,18 +281,27 @@ def main():
     sweep = {"ms": 1e3 * sweep_s, "bytes": sb, "gbps": sb / sweep_s / 1e9,
              "frac_hbm": sb / sweep_s / (HBM_PEAK_GBPS * 1e9)}
     last_plan.set_solve_opts(ir_maxit=200)
-    # the refined solve with the NUFFT operator (spreading + FFT, tol 1e-13)
-    # in place of the exact apply, on the same factors, and the NUFFT alone
-    nufft = None
+    # the refined solve with each operator (the exact FP64 direct sums, and
+    # the NUFFT's spreading + FFT at tol 1e-13) on the same factors, and the
+    # NUFFT alone
+    operators = {}
+    for tol, key in ((0.0, "exact_apply"), (1e-13, "nufft")):
+        try:
+            last_plan.set_nufft_tol(tol)
+            last_plan.solve(f)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cn, sn = last_plan.solve(f, return_info=True)
+            torch.cuda.synchronize()
+            t_sn = time.perf_counter() - t0
+            en = ((cn - c_true).norm() / c_true.norm()).item()
+            operators[key] = {"tol": tol, "refined_solve_s": t_sn, "its": sn["iterations"],
+                              "rel_err": en, "solves_per_s": 1.0 / t_sn}
+        except Exception as e:   # report, do not hide
+            operators[key] = dict(error=str(e))
+        log(f"operator {key}: {operators[key]}")
+    last_plan.set_nufft_tol(args.nufft_tol)
     try:
-        last_plan.set_nufft_tol(1e-13)
-        last_plan.solve(f)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        cn, sn = last_plan.solve(f, return_info=True)
-        torch.cuda.synchronize()
-        t_sn = time.perf_counter() - t0
-        en = ((cn - c_true).norm() / c_true.norm()).item()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         last_plan.nufft(c_true, 1e-13)
         ev0.record()
@@ -292,14 +309,9 @@ def main():
             last_plan.nufft(c_true, 1e-13)
         ev1.record()
         torch.cuda.synchronize()
-        t_nu = ev0.elapsed_time(ev1) / 5
-        last_plan.set_nufft_tol(0.0)
-        nufft = {"tol": 1e-13, "refined_solve_s": t_sn, "its": sn["iterations"], "rel_err": en,
-                 "solves_per_s": 1.0 / t_sn, "type2_ms": t_nu}
-        log(f"nufft operator: {nufft}")
+        operators["nufft"]["type2_ms"] = ev0.elapsed_time(ev1) / 5
     except Exception as e:   # report, do not hide
-        nufft = dict(error=str(e))
-        log(f"nufft operator failed: {e}")
+        operators["nufft_type2_error"] = str(e)
     # exact FP64 apply alone (its own kernel-class timing)
     last_plan.set_profiling(True)
     for _ in range(5):
@@ -342,6 +354,8 @@ def main():
                  % ("jittered" if args.workload in WORKLOADS else GRID_WORKLOADS[args.workload][0])),
         "config": {"workload": wl_desc, "precision": "fp32+ir", "ir_tol": args.ir_tol,
                    "fp32_products": args.fp32_products,
+                   "operator": (f"nufft tol {args.nufft_tol:g}" if args.nufft_tol > 0
+                                else "exact FP64 direct sums"),
                    "refine": ["iterative refinement", "pcg-ne", "plsqr"][args.refine]},
         "factor_s": float(np.median([r["factor_s"] for r in recs])),
         "solve_s": float(np.median([r["solve_s"] for r in recs])),
@@ -357,7 +371,7 @@ def main():
         "kernels": kernels,
         "sweep": sweep,
         "apply": {"ms": apply_ms, "tflops": apply_tf, "frac_fp64_peak": apply_tf / FP64_PEAK_TFLOPS},
-        "nufft_refinement": nufft,
+        "refinement_operators": operators,
         "fp64_path": fp64,
         "roofline": roof,
         "cpu_baseline": cpu,
