@@ -59,6 +59,11 @@ def test_invalid_arguments_rejected_before_device_work():
     o.precision = 3
     assert _plan(pts, pr.M, 8, 8, o)[0] == 1
     assert lib.nudft2_last_error() != b""
+    o = _lib.default_opts()
+    assert o.fp32_products == 0          # the bf16 split is the default
+    o.fp32_products = 2
+    assert _plan(pts, pr.M, 8, 8, o)[0] == 1
+    assert b"fp32_products" in lib.nudft2_last_error()
 
 
 def test_null_plan_calls():

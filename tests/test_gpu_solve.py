@@ -30,22 +30,26 @@ def direct_bound(eps, prec):
     (48, 32, 96, 64, 0.4, 5),       # ragged leaves, non-square
     (8, 8, 16, 16, 0.3, 7),         # single-node tree (dense root)
 ])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_ins"])
 @pytest.mark.parametrize("eps", [1e-2, 1e-4])
 def test_direct_and_refined(nx, ny, mx, my, delta, seed, prec, eps):
+    """prec "fp32": FP32 factors with their products on the bf16 split (the
+    default); "fp32_ins": the same on the FP32 matrix instructions."""
     pr = make_problem(nx, ny, mx, my, delta, seed)
     f = onu.apply(pr.points, pr.c_true)
     c_ref = onu.lstsq(pr.points, f, nx, ny)
     ft = torch.from_numpy(f).to(DEV)
+    kw = dict(fp32_products="fp32") if prec == "fp32_ins" else {}
+    prec = "fp32" if prec == "fp32_ins" else prec
     # direct solve
-    plan = nd.Plan(pr.points, nx, ny, precision=prec, eps=eps, ir_maxit=0)
+    plan = nd.Plan(pr.points, nx, ny, precision=prec, eps=eps, ir_maxit=0, **kw)
     plan.factor()
     c0 = plan.solve(ft).cpu().numpy()
     e0 = rel(c0, c_ref)
     info = plan.info()
     plan.close()
     # refined solve
-    plan = nd.Plan(pr.points, nx, ny, precision=prec, eps=eps, ir_maxit=40, ir_tol=1e-13)
+    plan = nd.Plan(pr.points, nx, ny, precision=prec, eps=eps, ir_maxit=40, ir_tol=1e-13, **kw)
     plan.factor()
     c1, si = plan.solve(ft, return_info=True)
     e1 = rel(c1.cpu().numpy(), c_ref)
