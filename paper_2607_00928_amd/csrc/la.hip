@@ -929,6 +929,68 @@ __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(DS descs, int splits
   }
 }
 
+// op(A) = A^H with a long k and too few rows of C to fill the device a wave
+// per row: a workgroup per row, its four waves sharing the row's k range and
+// their sums meeting in LDS in a fixed order (no k split: no atomics and no
+// pre-scaling of C).
+template <typename T, int NC, class DS>
+__global__ __launch_bounds__(256) void gemm_skinny_cw_kernel(DS descs) {
+  using C2 = cplx<T>;
+  constexpr int U = SK_U / 2;
+  __shared__ T red[4][NC][2];
+  const GemmDesc<T> d = descs[blockIdx.y];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = blockIdx.x;
+  if (i >= d.m || d.n <= 0) return;   // uniform over the workgroup
+  int kb = 0, ke = d.k;
+  // column i of A has no nonzeros outside [kb, ke)
+  if (d.tri == 1) kb = min(i, ke);
+  else if (d.tri == 2) ke = min(ke, i + 1);
+  C2 acc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) acc[j] = mk<T>(0, 0);
+  const C2* ap = d.A + (int64_t)i * d.lda;
+  int l = kb + tid;
+  for (; l + 256 * (U - 1) < ke; l += 256 * U) {
+    C2 a[U], b[U][NC];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] = ldc(ap + l + 256 * u);
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        b[u][j] = j < d.n ? ldc(d.B + (int64_t)(l + 256 * u) + (int64_t)j * d.ldb) : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc[j] = cadd(acc[j], cmulc(a[u], b[u][j]));
+  }
+  for (; l < ke; l += 256) {
+    const C2 a = ldc(ap + l);
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      if (j < d.n) acc[j] = cadd(acc[j], cmulc(a, ldc(d.B + (int64_t)l + (int64_t)j * d.ldb)));
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const T re = warp_sum(acc[j].x), im = warp_sum(acc[j].y);
+    if (lane == 0) {
+      red[wave][j][0] = re;
+      red[wave][j][1] = im;
+    }
+  }
+  __syncthreads();
+  if (tid < NC && tid < d.n) {
+    T re = 0, im = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      re += red[w][tid][0];
+      im += red[w][tid][1];
+    }
+    skinny_store(d, i, tid, mk<T>(re, im), 1);
+  }
+}
+
 // op(A) = A^H with a short k (at most 512): four rows of C per wave, 16 lanes
 // per row (a wave per row would leave most lanes without work); the row's
 // partial sums meet through row shifts within its 16 lanes.
@@ -2103,7 +2165,12 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
   int64_t wgs = bx * (int64_t)n;
   int splits = 1;
   const int kmin_split = opA == OpN ? 4 * SK_L : 1024;
-  if (force > 0) {
+  // op C with a long k where a wave per row leaves the device short of work:
+  // a workgroup per row instead of a k split
+  const bool cw = opA == OpC && !c16 && force <= 0 && wgs < 1024 && maxk >= 2 * kmin_split;
+  if (cw) {
+    wgs = (int64_t)maxm * (int64_t)n;
+  } else if (force > 0) {
     splits = std::max(1, std::min({force, std::max(1, maxk / SK_L), 4096}));
   } else if (wgs < 1024 && maxk >= 2 * kmin_split) {
     splits = (int)std::min<int64_t>(maxk / kmin_split, (2048 + wgs - 1) / wgs);
@@ -2127,10 +2194,13 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
           dim3(256), 0, pool.stream, dd);
     ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMV32 : KC_GEMV64, fl, (int)n, maxm, maxn,
                  maxk, (int)opA * 2 + 10 * splits + 1000, true);
-    dim3 grid((unsigned)bx, (unsigned)n, (unsigned)splits);
+    dim3 grid((unsigned)(cw ? maxm : bx), (unsigned)n, (unsigned)splits);
     auto launch = [&](auto nc) {
       constexpr int NC = decltype(nc)::value;
-      if (opA == OpN && n4)
+      if (cw)
+        hipExtLaunchKernelGGL((gemm_skinny_cw_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
+                              ps.start(), ps.stop(), 0, dd);
+      else if (opA == OpN && n4)
         hipExtLaunchKernelGGL((gemm_skinny_n4_kernel<T, NC, DS>), grid, dim3(256), 0, pool.stream,
                               ps.start(), ps.stop(), 0, dd, splits);
       else if (opA == OpN)

@@ -152,6 +152,39 @@ def test_gemm_skinny(prec, opa, beta):
         assert np.abs(got - ref).max() < TOL[prec] * scale * max(1, k) ** 0.5 * 10, (m, n, k)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("beta", [0.0, 0.5])
+def test_gemm_skinny_ch_long_k_few_rows(prec, beta):
+    """A^H B with at most 8 columns, a long k and few rows of C (the sweep's
+    V^H c against a block of reflectors): a workgroup per row of C, no k
+    split.  Ragged k (not a multiple of the 256-thread stride), one and eight
+    columns, a row count that is not a multiple of anything."""
+    rng = np.random.default_rng(400 + 2 * prec + int(beta > 0))
+    shapes = [(256, 1, 11000), (200, 3, 9001), (5, 8, 4097), (77, 1, 2049)]
+    alpha = 0.3 + 0.9j
+    mats, keep, mnk, ld, ptr = [], [], [], [], []
+    for (m, n, k) in shapes:
+        A = crandn(rng, k, m)
+        B = crandn(rng, k, n)
+        Cm = crandn(rng, m, n)
+        ts = [to_dev(X, prec) for X in (A, B, Cm)]
+        keep += ts
+        mats.append((A, B, Cm, ts[2]))
+        mnk += [m, n, k]
+        ld += [k, k, m]
+        ptr += [t.data_ptr() for t in ts]
+    a1, p1 = i32(mnk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_gemm(prec, 1, 0, len(shapes), p1, p2, p3, alpha.real, alpha.imag, beta)
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+        ref = alpha * (A.conj().T @ B) + beta * Cm
+        got = from_dev(tc, m, n)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(got - ref).max() < TOL[prec] * scale * k ** 0.5 * 10, (m, n, k)
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_geqrf_ormqr(prec):
     rng = np.random.default_rng(3 + prec)
