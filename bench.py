@@ -1,10 +1,10 @@
 """Benchmark: factor + refined solve of the 2D type-II inverse NUDFT at
 n = 512 x 512 (N = 262144), M = 1024^2 jittered points, FP32 HSS factors with
 FP64 iterative refinement to ||dc||/||c|| <= 1e-10 (relative error vs the true
-coefficients reported), on one MI355X.  The refinement applies A and A^* by
-the NUFFT at tolerance 1e-13 (Section 4.1's operator; --nufft-tol 0 takes
-the exact FP64 direct sums), and both operators' refined solves are
-reported.
+coefficients reported), on one MI355X.  The refinement's FP64 residual
+comes from the exact face-split apply (the FP64 direct sums; --nufft-tol
+1e-13 takes Section 4.1's NUFFT operator instead), and both operators'
+refined solves are reported.
 
 A step = plan (binning + upload of the points) + factorization (1D HSS
 compression, face-splitting assembly, recompression, URV) + refined solve of
@@ -68,10 +68,10 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--fp32-products", default="bf16x3", choices=["bf16x3", "fp32"],
                     help="matrix instructions of the FP32 factorization's products")
-    ap.add_argument("--nufft-tol", type=float, default=1e-13,
-                    help="operator of the refinement: A and A^* by the NUFFT to this "
-                         "relative accuracy (Section 4.1; default 1e-13), 0 = the exact FP64 "
-                         "direct sums")
+    ap.add_argument("--nufft-tol", type=float, default=0.0,
+                    help="operator of the refinement: 0 (default) the exact FP64 face-split "
+                         "direct sums; > 0 A and A^* by the NUFFT to this relative accuracy "
+                         "(Section 4.1)")
     ap.add_argument("--ir-tol", type=float, default=1e-10)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-factor comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
