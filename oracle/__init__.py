@@ -12,6 +12,9 @@ direct solver for the 2D type-II inverse NUDFT based on HSS matrices"):
   expansion, 1D HSS by truncated SVD, the face-splitting product generators
   (Theorem 3.3), recompression (Section 2.3) and the URV least-squares solver
   (Section 2.4 / URV section).  Used for tiny problems only.
+* ``fadi``   -- factored ADI (fADI) low-rank factors of the 1D HSS row blocks
+  from the displacement equation of Section 2.5, with Zolotarev shifts on the
+  two arcs of the unit circle, and a 1D HSS whose leaf row bases use them.
 * ``grad``   -- derivatives of the least-squares solution with respect to the
   right-hand side and the sample points (chain rule on the normal equations).
 

@@ -227,11 +227,13 @@ def matvec(h: HSS, x: np.ndarray, M: int) -> np.ndarray:
 # 1D HSS approximation of G^x by truncated SVD
 # --------------------------------------------------------------------------
 
-def hss_1d(x: np.ndarray, n: int, L: int, tol: float) -> HSS:
+def hss_1d(x: np.ndarray, n: int, L: int, tol: float, leaf_row_bases=None) -> HSS:
     """Nested orthonormal bases for the HSS blocks G(J_tau, K_tau^c) and
     G(J_tau^c, K_tau)^* of the 1D transformed matrix (Section 2.5), bottom up;
     leaves keep the exact kernel block as D.  tol = 0 keeps every nonzero
-    singular direction (an exact representation up to round-off)."""
+    singular direction (an exact representation up to round-off).
+    leaf_row_bases: optional {leaf key: orthonormal U} used in place of the
+    truncated SVD of the leaf row blocks."""
     t = tree_1d(x, n, L)
     G = nudft.kernel_1d(x, n)
     M = x.size
@@ -246,7 +248,10 @@ def hss_1d(x: np.ndarray, n: int, L: int, tol: float) -> HSS:
             cc = np.setdiff1d(allcols, nd.cols)
             if not nd.children:
                 D[k] = G[np.ix_(nd.rows, nd.cols)]
-                Uk, _ = trunc_left(G[np.ix_(nd.rows, cc)], tol)
+                if leaf_row_bases is not None:
+                    Uk = leaf_row_bases[k]
+                else:
+                    Uk, _ = trunc_left(G[np.ix_(nd.rows, cc)], tol)
                 Vk, _ = trunc_left(G[np.ix_(rc, nd.cols)].conj().T, tol)
                 U[k], V[k] = Uk, Vk
                 Uf[k], Vf[k] = Uk, Vk
