@@ -152,12 +152,14 @@ def adi_rational(z, p, q):
 
 def displacement_terms(x, n: int):
     """g, u of the rows and xi, v of the columns (Section 2.5), u_j =
-    g_j^n - 1 with n x_j reduced mod 1 in extended precision first."""
+    g_j^n - 1 with n x_j reduced mod 1 in extended precision first (f), then
+    written as exp(-2 pi i f) - 1 = -2i sin(pi f) exp(-i pi f), which keeps
+    its relative accuracy when f is near 0."""
     xl = np.asarray(x, dtype=np.longdouble)
     t = xl * n
     frac = (t - np.rint(t)).astype(np.float64)
     g = arc_point(x)
-    u = np.exp(-2j * np.pi * frac) - 1.0
+    u = -2j * np.sin(np.pi * frac) * np.exp(-1j * np.pi * frac)
     xi = arc_point(np.arange(n) / n)
     v = xi / n
     return g, u, xi, v
@@ -191,8 +193,12 @@ def block_plan(n: int, level: int, a: int, tau: float):
     return best[1], best[2], best[3], best[4], lo, hi
 
 
-def row_block_factor(x_rows, n: int, level: int, a: int, tau: float) -> BlockFactor:
-    """fADI factor of G(J_a, K_a^c) for the rows x_rows of node (level, a)."""
+def row_block_factor(x_rows, n: int, level: int, a: int, tau: float,
+                     shifts=None) -> BlockFactor:
+    """fADI factor of G(J_a, K_a^c) for the rows x_rows of node (level, a).
+    shifts: optional (p, q) used in place of the computed Zolotarev shifts
+    (the same count), so that the recurrences can be compared on given
+    inputs."""
     b, s, g, arcs, lo, hi = block_plan(n, level, a, tau)
     x_rows = np.asarray(x_rows, dtype=np.float64)
     cols = hss.col_range(n, level, a)
@@ -205,7 +211,8 @@ def row_block_factor(x_rows, n: int, level: int, a: int, tau: float) -> BlockFac
     near = np.array([(hi + i) % n for i in range(b)] + [(lo - b + i) % n for i in range(b)],
                     dtype=np.int64)
     far = np.array([l % n for l in range(hi + b, lo - b + n)], dtype=np.int64)
-    p, q = zolotarev_shifts(*arcs, s)
+    p, q = zolotarev_shifts(*arcs, s) if shifts is None else shifts
+    assert len(p) == s and len(q) == s
     gr, u, xi, v = displacement_terms(x_rows, n)
     Zf, Yf, w = fadi(gr, xi[far], u, v[far], p, q)
     Z = np.hstack([nudft.kernel_1d(x_rows, n, near), Zf])
