@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--fp32-products", default="bf16x3", choices=["bf16x3", "fp32"],
                     help="matrix instructions of the FP32 factorization's products")
+    ap.add_argument("--construct-1d", default="fadi", choices=["fadi", "gram"],
+                    help="1D HSS stage: leaf row bases from fADI factors (default) or from "
+                         "explicit Gram matrices")
     ap.add_argument("--nufft-tol", type=float, default=0.0,
                     help="operator of the refinement: 0 (default) the exact FP64 face-split "
                          "direct sums; > 0 A and A^* by the NUFFT to this relative accuracy "
@@ -119,7 +122,7 @@ def main():
 
     if args.profile_sweep:
         plan = nd.Plan(pr.points, nx, ny, precision="fp32", eps=args.eps, ir_maxit=0,
-                       fp32_products=args.fp32_products)
+                       fp32_products=args.fp32_products, fadi_1d=args.construct_1d == "fadi")
         plan.factor()
         torch.cuda.synchronize()
         ts = []
@@ -139,7 +142,7 @@ def main():
         t0 = time.perf_counter()
         plan = nd.Plan(pr.points, nx, ny, precision=precision, eps=args.eps, ir_maxit=200,
                        ir_tol=args.ir_tol, refine=args.refine, fp32_products=args.fp32_products,
-                       nufft_tol=args.nufft_tol)
+                       nufft_tol=args.nufft_tol, fadi_1d=args.construct_1d == "fadi")
         if profile:
             # per-launch events for the dominant class only (the FP32
             # matrix-core GEMMs: about three quarters of the step's kernel
@@ -354,6 +357,7 @@ def main():
                  % ("jittered" if args.workload in WORKLOADS else GRID_WORKLOADS[args.workload][0])),
         "config": {"workload": wl_desc, "precision": "fp32+ir", "ir_tol": args.ir_tol,
                    "fp32_products": args.fp32_products,
+                   "construct_1d": args.construct_1d,
                    "operator": (f"nufft tol {args.nufft_tol:g}" if args.nufft_tol > 0
                                 else "exact FP64 direct sums"),
                    "refine": ["iterative refinement", "pcg-ne", "plsqr"][args.refine]},

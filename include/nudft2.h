@@ -93,6 +93,13 @@ typedef struct {
                          (FP32-level accuracy: the three left out are below
                          2^-23 |a||b|); 1 FP32 instructions.  The FP64
                          factorization ignores it. */
+  int32_t fadi_1d;    /* 1D HSS construction of G^x and G^y (Section 2.5):
+                         1 (default) the leaf row bases from fADI factors of
+                         the displacement equation (Zolotarev shifts on the
+                         two arcs of the unit circle, the kernel columns next
+                         to each node's interval kept exactly), accurate to a
+                         tenth of the 1D tolerance eps/10; 0 from the explicit
+                         Gram matrices of the blocks. */
 } nudft2_opts;
 
 /* Per-solve report (host memory, may be NULL). */

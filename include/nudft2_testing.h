@@ -113,6 +113,24 @@ nudft2_status nudft2_test_copy(int32_t prec_d, int32_t prec_s, int32_t nb, const
  * frequency l), y: DEVICE M_prob complex128, the problem's points in the
  * caller's order.  ranks (HOST, 2*(L+1) ints, may be
  * NULL) receives the largest row / column rank per level. */
+/* fADI factor of the HSS row block G(J_a, K_a^c) of node (level, a) of a 1D
+ * tree with n columns (K_a = the columns l with l/n in [a/2^level,
+ * (a+1)/2^level)), relative accuracy tau (the library uses a tenth of the 1D
+ * tolerance).  Writes (b, s) to HOST plan_out[2] (b near columns a side,
+ * s shifts; b = 0: the library keeps all of K_a^c exactly), the gamma of the
+ * arcs' symmetric image to *gamma, and the shifts to HOST pq (complex128
+ * pairs): p_j at pq[2j], q_j at pq[2(smax + j)], j < s.  When Z and W are
+ * not NULL and b > 0, also fills DEVICE Z (m x (2b+s), leading dimension
+ * max(m, 1)) and W (n x (2b+s), leading dimension n), complex128, from the
+ * DEVICE row coordinates xs[m]: G(J_a, l) ~= sum_j Z(., j) conj(W(l, j)) for
+ * l outside K_a; Z's first 2b columns are the kernel columns (hi + c) mod n,
+ * then (lo - b + c) mod n, c < b, with unit W entries; the next s are the fADI
+ * vectors and W carries the conjugated weighted column vectors.
+ * NUDFT2_E_INVAL if s > smax (plan_out and gamma are still written). */
+nudft2_status nudft2_test_fadi_block(const double* xs, int64_t m, int32_t n, int32_t level,
+                                     int32_t a, double tau, int32_t* plan_out, double* gamma,
+                                     double* pq, int32_t smax, double* Z, double* W);
+
 nudft2_status nudft2_test_hss1d_matvec(nudft2_plan_t plan, int32_t dim, double tol,
                                        const double* x, double* y, int32_t* ranks,
                                        int32_t prob);

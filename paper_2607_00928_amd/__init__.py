@@ -29,9 +29,10 @@ _FP32_PRODUCTS = {"bf16x3": 0, "fp32": 1}
 
 
 def _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph=False,
-          nufft_tol=0.0, fp32_products="bf16x3"):
+          nufft_tol=0.0, fp32_products="bf16x3", fadi_1d=True):
     o = _lib.default_opts()
     o.fp32_products = _FP32_PRODUCTS[fp32_products]
+    o.fadi_1d = 1 if fadi_1d else 0
     o.graph = 1 if graph else 0
     o.nufft_tol = float(nufft_tol)
     o.precision = _PREC[precision]
@@ -234,12 +235,14 @@ class Plan(_PlanBase):
     """One problem: points (M, 2) float64 (array or tensor; handed to the
     library in device memory), nx x ny centred frequencies.
     fp32_products ("bf16x3" or "fp32"): matrix instructions of the FP32
-    factorization's products (nudft2_opts.fp32_products)."""
+    factorization's products (nudft2_opts.fp32_products).
+    fadi_1d: 1D construction from fADI factors (True) or explicit Gram
+    matrices (nudft2_opts.fadi_1d)."""
 
     def __init__(self, points, nx: int, ny: int, *, precision="fp32", eps=1e-4,
                  leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0, stream=None,
                  mem_cap=0, device=None, graph=False, nufft_tol=0.0,
-                 fp32_products="bf16x3"):
+                 fp32_products="bf16x3", fadi_1d=True):
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         pts = _device_points(points, dev)
         self.M = pts.shape[0]
@@ -248,7 +251,7 @@ class Plan(_PlanBase):
         if stream is None:
             stream = _current_stream(dev)
         o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph,
-                  nufft_tol, fp32_products)
+                  nufft_tol, fp32_products, fadi_1d)
         self.ir_tol, self.ir_maxit, self.refine = float(ir_tol), int(ir_maxit), int(refine)
         h = C.c_void_p()
         with torch.cuda.device(dev):
@@ -266,7 +269,7 @@ class BatchPlan(_PlanBase):
     def __init__(self, points_list, nx_list, ny_list, *, precision="fp32",
                  eps=1e-4, leaf=16, ir_tol=1e-12, ir_maxit=30, refine=0,
                  stream=None, mem_cap=0, device=None, graph=False, nufft_tol=0.0,
-                 fp32_products="bf16x3"):
+                 fp32_products="bf16x3", fadi_1d=True):
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         pts = [_device_points(p, dev) for p in points_list]
         m_off = np.zeros(len(pts) + 1, dtype=np.int64)
@@ -282,7 +285,7 @@ class BatchPlan(_PlanBase):
         if stream is None:
             stream = _current_stream(dev)
         o = _opts(precision, eps, leaf, ir_tol, ir_maxit, refine, stream, mem_cap, graph,
-                  nufft_tol, fp32_products)
+                  nufft_tol, fp32_products, fadi_1d)
         self.ir_tol, self.ir_maxit, self.refine = float(ir_tol), int(ir_maxit), int(refine)
         h = C.c_void_p()
         with torch.cuda.device(dev):

@@ -31,6 +31,7 @@ class Opts(C.Structure):
         ("graph", C.c_int32),
         ("nufft_tol", C.c_double),
         ("fp32_products", C.c_int32),
+        ("fadi_1d", C.c_int32),
     ]
 
 
@@ -120,6 +121,8 @@ def _load():
         "nudft2_test_trsv": (C.c_int, [C.c_int32, C.c_int32, I32P, I32P, I64P, C.c_int32]),
         "nudft2_test_trtri": (C.c_int, [C.c_int32, C.c_int32, I32P, I32P, I64P]),
         "nudft2_test_copy": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, I32P, I32P, I64P, I32P]),
+        "nudft2_test_fadi_block": (C.c_int, [P, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                             C.c_double, I32P, DP, DP, C.c_int32, P, P]),
         "nudft2_test_hss1d_matvec": (C.c_int, [P, C.c_int32, C.c_double, P, P, I32P, C.c_int32]),
         "nudft2_test_hss_matvec": (C.c_int, [P, P, P, C.c_int32, C.c_int32, C.c_int32]),
     }

@@ -4,6 +4,7 @@
 
 #include "../../include/nudft2_testing.h"
 #include "device_util.h"
+#include "gen.h"
 #include "hss.h"
 #include "la.h"
 #include "plan.h"
@@ -240,6 +241,7 @@ void nudft2_default_opts(nudft2_opts* o) {
   o->graph = 0;
   o->nufft_tol = 0.0;
   o->fp32_products = 0;
+  o->fadi_1d = 1;
 }
 
 const char* nudft2_strerror(nudft2_status s) {
@@ -615,6 +617,40 @@ nudft2_status nudft2_test_copy(int32_t prec_d, int32_t prec_s, int32_t nb, const
     else if (prec_d == 0) test_copy<double, float>(nb, dims, ld, ptrs, conj_trans);
     else if (prec_s == 0) test_copy<float, double>(nb, dims, ld, ptrs, conj_trans);
     else test_copy<float, float>(nb, dims, ld, ptrs, conj_trans);
+  });
+}
+
+nudft2_status nudft2_test_fadi_block(const double* xs, int64_t m, int32_t n, int32_t level,
+                                     int32_t a, double tau, int32_t* plan_out, double* gamma,
+                                     double* pq, int32_t smax, double* Z, double* W) {
+  return guard([&] {
+    ND_CHECK(plan_out && gamma && pq && smax >= 0, NUDFT2_E_INVAL, "bad arguments");
+    ND_CHECK(n >= 1 && level >= 1 && level < 31 && a >= 0 && a < (1 << level) && tau > 0.0 &&
+                 tau < 1.0 && m >= 0 && m <= INT32_MAX,
+             NUDFT2_E_INVAL, "bad block");
+    const FadiPlan pl = fadi_plan(n, level, a, tau);
+    plan_out[0] = pl.b;
+    plan_out[1] = pl.s;
+    *gamma = pl.gamma;
+    ND_CHECK(pl.s <= smax, NUDFT2_E_INVAL, "more shifts than smax");
+    for (int j = 0; j < pl.s; ++j) {
+      pq[2 * j] = pl.p[j].x;
+      pq[2 * j + 1] = pl.p[j].y;
+      pq[2 * (smax + j)] = pl.q[j].x;
+      pq[2 * (smax + j) + 1] = pl.q[j].y;
+    }
+    if (!Z || !W || pl.b == 0) return;
+    ND_CHECK(xs || m == 0, NUDFT2_E_INVAL, "xs is NULL");
+    need_device();
+    std::vector<double2> sh(pl.p);
+    sh.insert(sh.end(), pl.q.begin(), pl.q.end());
+    DescPool pool;
+    pool.init(1 << 20, nullptr);
+    const double2* dsh = (const double2*)pool.push_ro(sh.data(), sizeof(double2) * sh.size());
+    std::vector<FadiDesc> d{{xs, dsh, (double2*)Z, (double2*)W, (int)m, n, pl.b, pl.s, pl.lo,
+                             pl.hi, (int)std::max<int64_t>(m, 1), n}};
+    fadi_factors(pool, d);
+    pool.sync_reset();
   });
 }
 

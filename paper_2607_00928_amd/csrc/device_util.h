@@ -62,8 +62,10 @@ template <> struct acc4<float> { using type = flt4; };
 
 // exp(-2 pi i k x) for integer k (|k| < 2^20) and x in [0, 1): the product
 // k x is split into its rounded value and exact error (fma), reduced mod 1,
-// so the phase carries no error proportional to |k|.
+// so the phase carries no error proportional to |k|.  Contraction is off:
+// fusing k x - rint(p) into one fma would add the error e twice.
 __device__ inline double2 expi_kx(double k, double x) {
+#pragma clang fp contract(off)
   double p = k * x;
   double e = fma(k, x, -p);
   double t = (p - rint(p)) + e;

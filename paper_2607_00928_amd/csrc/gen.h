@@ -64,7 +64,24 @@ struct Diag1Desc {
   double2* y;
 };
 
+// fADI factor of one HSS row block G(J_a, K_a^c) of the 1D matrix (Section
+// 2.5's displacement equation diag(g) G - G diag(xi) = u v^T):
+// G(J_a, l) ~= sum_j Z(., j) conj(W(l, j)) for l in K_a^c, W(l, .) = 0 on
+// K_a = [lo, hi).  Columns 0 .. 2b-1 of Z are the exact kernel columns
+// (hi + c) mod n and (lo - b + c) mod n (c < b), with W = 1 there; columns
+// 2b .. 2b+s-1 are the fADI vectors z_j = u / (g - q_1) prod_{i<j} (g - p_i) /
+// (g - q_{i+1}) and W(l, 2b+j) = conj((q_j - p_j) y_j(l)), y_j = v / (xi - p_1)
+// prod_{i<j} (xi - q_i) / (xi - p_{i+1}), on the far columns.
+struct FadiDesc {
+  const double* xs;      // the block's m row coordinates (device)
+  const double2* pq;     // shifts p_1..p_s then q_1..q_s (device)
+  double2* Z;            // m x (2b + s), leading dimension ldz
+  double2* W;            // n x (2b + s), leading dimension ldw
+  int m, n, b, s, lo, hi, ldz, ldw;
+};
+
 void gen_G1(hipStream_t s, const double* xs, int64_t M, int n, double2* G, int64_t ld);
+void fadi_factors(DescPool& pool, const std::vector<FadiDesc>& d);
 template <typename T>
 void gen_leafD(DescPool& pool, const std::vector<LeafDesc<T>>& d, const double* pts2d);
 template <typename T>

@@ -16,6 +16,7 @@
 namespace nd {
 
 __device__ inline double2 dirichlet(double x, int l, int n) {
+#pragma clang fp contract(off)   // the two-sum reductions below must stay as written
   double t = x - (double)l / (double)n;
   t -= rint(t);
   if (t == 0.0) return mk<double>(1.0, 0.0);
@@ -327,6 +328,109 @@ void gen_asm(DescPool& pool, const std::vector<AsmDesc<T>>& d) {
   auto* dd = (AsmDesc<T>*)pool.push(d.data(), sizeof(AsmDesc<T>) * d.size());
   hipLaunchKernelGGL((gen_asm_kernel<T>), dim3(grid_for(mx), (unsigned)d.size()), dim3(256), 0,
                      pool.stream, dd);
+  ND_HIP(hipGetLastError());
+}
+
+namespace {
+
+__device__ inline double2 cdiv(double2 a, double2 b) {
+  const double r = 1.0 / (b.x * b.x + b.y * b.y);
+  return mk<double>((a.x * b.x + a.y * b.y) * r, (a.y * b.x - a.x * b.y) * r);
+}
+
+// one thread per row of the block: its near kernel entries and its fADI
+// vector entries (a running product over the shifts)
+__global__ void fadi_rows_kernel(const FadiDesc* __restrict__ descs) {
+#pragma clang fp contract(off)
+  const FadiDesc d = descs[blockIdx.y];
+  const double2* p = d.pq;
+  const double2* q = d.pq + d.s;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < d.m; i += gridDim.x * 256) {
+    const double x = d.xs[i];
+    for (int c = 0; c < d.b; ++c) {
+      d.Z[i + (int64_t)c * d.ldz] = dirichlet(x, (d.hi + c) % d.n, d.n);
+      d.Z[i + (int64_t)(d.b + c) * d.ldz] = dirichlet(x, (d.lo - d.b + c + d.n) % d.n, d.n);
+    }
+    double sx, cx;
+    sincospi(2.0 * x, &sx, &cx);
+    const double2 g = mk<double>(cx, -sx);
+    // u = g^n - 1 = exp(-2 pi i f) - 1, f = n x mod 1: pn + e = n x exactly
+    // and pn - rint(pn) is exact (contraction is off in this kernel: fusing
+    // n x - rint(pn) into one fma would count e twice)
+    const double dn = (double)d.n;
+    const double pn = dn * x, e = fma(dn, x, -pn);
+    const double f = (pn - rint(pn)) + e;
+    double sf, cf;
+    sincospi(f, &sf, &cf);
+    double2 z = cdiv(mk<double>(-2.0 * sf * sf, -2.0 * sf * cf), csub(g, q[0]));
+    double2* out = d.Z + i + (int64_t)(2 * d.b) * d.ldz;
+    out[0] = z;
+    for (int j = 1; j < d.s; ++j) {
+      z = cmul(z, cdiv(csub(g, p[j - 1]), csub(g, q[j])));
+      out[(int64_t)j * d.ldz] = z;
+    }
+  }
+}
+
+// one thread per column: W(l, .) = 0 on K_a, a unit entry on a near column,
+// the conjugated weighted fADI vector entries on a far one
+__global__ void fadi_cols_kernel(const FadiDesc* __restrict__ descs) {
+  const FadiDesc d = descs[blockIdx.y];
+  const double2* p = d.pq;
+  const double2* q = d.pq + d.s;
+  const int w = 2 * d.b + d.s;
+  for (int l = blockIdx.x * 256 + threadIdx.x; l < d.n; l += gridDim.x * 256) {
+    double2* row = d.W + l;
+    const int dh = (l - d.hi + d.n) % d.n;
+    const int dl = (d.lo - 1 - l + d.n) % d.n;
+    const bool own = l >= d.lo && l < d.hi;
+    int near = -1;
+    if (!own && dh < d.b) near = dh;
+    else if (!own && dl < d.b) near = 2 * d.b - 1 - dl;
+    for (int c = 0; c < 2 * d.b; ++c)
+      row[(int64_t)c * d.ldw] = mk<double>(c == near ? 1.0 : 0.0, 0.0);
+    if (own || near >= 0) {
+      for (int c = 2 * d.b; c < w; ++c) row[(int64_t)c * d.ldw] = mk<double>(0.0, 0.0);
+      continue;
+    }
+    double sw, cw;
+    sincospi(2.0 * (double)l / (double)d.n, &sw, &cw);
+    const double2 xi = mk<double>(cw, -sw);
+    double2 y = cdiv(mk<double>(cw / d.n, -sw / d.n), csub(xi, p[0]));
+    for (int j = 0; j < d.s; ++j) {
+      if (j > 0) y = cmul(y, cdiv(csub(xi, q[j - 1]), csub(xi, p[j])));
+      row[(int64_t)(2 * d.b + j) * d.ldw] = cconj(cmul(csub(q[j], p[j]), y));
+    }
+  }
+}
+
+}  // namespace
+
+void fadi_factors(DescPool& pool, const std::vector<FadiDesc>& d) {
+  if (d.empty()) return;
+  if (hazards_enabled()) {
+    std::vector<Region> v;
+    for (size_t i = 0; i < d.size(); ++i) {
+      const int w = 2 * d[i].b + d[i].s;
+      v.push_back(region(d[i].Z, 16, d[i].m, w, d[i].ldz, true, (int)i));
+      v.push_back(region(d[i].W, 16, d[i].n, w, d[i].ldw, true, (int)i));
+    }
+    check_hazards("fadi_factors", v);
+  }
+  int mm = 1, mn = 1;
+  for (auto& q : d) {
+    ND_CHECK(q.s >= 1 && q.b >= 1 && q.m >= 0 && q.n > 2 * q.b && q.lo >= 0 && q.lo < q.hi &&
+                 q.hi <= q.n && q.ldz >= std::max(q.m, 1) && q.ldw >= q.n,
+             NUDFT2_E_INTERNAL, "fadi_factors: bad descriptor");
+    mm = std::max(mm, q.m);
+    mn = std::max(mn, q.n);
+  }
+  auto* dd = (FadiDesc*)pool.push(d.data(), sizeof(FadiDesc) * d.size());
+  hipLaunchKernelGGL(fadi_rows_kernel, dim3(std::min(ceil_div(mm, 256), 256), (unsigned)d.size()),
+                     dim3(256), 0, pool.stream, dd);
+  ND_HIP(hipGetLastError());
+  hipLaunchKernelGGL(fadi_cols_kernel, dim3(std::min(ceil_div(mn, 256), 64), (unsigned)d.size()),
+                     dim3(256), 0, pool.stream, dd);
   ND_HIP(hipGetLastError());
 }
 

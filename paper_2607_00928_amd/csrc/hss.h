@@ -200,6 +200,20 @@ void host_binning(const double* points, int64_t M, int nx, int ny, int leaf,
                   int64_t* perm2d, int64_t* leaf_rows, int64_t* colperm);
 
 // 1D compression of G^x (dim 0) or G^y (dim 1) for every problem.
+// fADI plan of the HSS row block G(J_a, K_a^c) of node (level, a) of a 1D
+// tree with n columns (K_a = [lo, hi)), for relative accuracy tau: b near
+// columns on each side of K_a kept exactly and s Zolotarev shifts p (on the
+// arc of the node's interval) and q (on the arc of the far columns) for the
+// rest; b = 0 when keeping all of K_a^c exactly is no more expensive.
+struct FadiPlan {
+  int b = 0, s = 0, lo = 0, hi = 0;
+  double gamma = 0.0;
+  std::vector<double2> p, q;
+};
+FadiPlan fadi_plan(int n, int level, int a, double tau);
+
+// build_1d compresses the leaf row blocks from their fADI factors when the
+// plan's fadi_1d option is set, else from their explicit Gram matrices.
 void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out);
 void free_1d(Plan* P, std::vector<Tree1>& t);
 // y = H x for a 1D HSS (test hook): x (n, natural columns), y (M, caller order).

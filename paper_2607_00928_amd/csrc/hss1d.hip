@@ -1,15 +1,23 @@
 // 1D HSS compression of the transformed NUDFT matrices G^x and G^y.
 //
 // The paper builds these 1D HSS approximations (tolerance eps/10, Algorithm
-// 4.1, first construction step) with an fADI + interpolative-decomposition
-// method delegated to another work.  Here every HSS block is compressed
-// explicitly with nested orthonormal bases (Definition 2.2), bottom up:
+// 4.1, first construction step) from the displacement equation of Section
+// 2.5, diag(g) G - G diag(xi) = u v^T, with factored ADI (fADI) and an
+// interpolative decomposition.  Here every HSS block is compressed with
+// nested orthonormal bases (Definition 2.2), bottom up:
 //
 //  * leaf a, row basis: the columns I selected by a diagonally pivoted
 //    Cholesky factorization of the Gram matrix of G(J_a, K_a^c) (a column
 //    interpolative decomposition, stopped when the discarded Schur
 //    complement has trace <= tol^2 ||G(J_a, K_a^c)||_F^2), orthonormalised:
-//    U_a = orth(G(J_a, I)).
+//    U_a = orth(G(J_a, I)).  With fADI (the default) the Gram matrix is that
+//    of the low-rank factor G(J_a, K_a^c) ~= Z W^H, W C W^H with C = Z^H Z:
+//    Z holds the exact kernel columns next to the ends of the node's
+//    interval and the fADI vectors of the remaining (far) columns, whose
+//    Zolotarev shifts on the two arcs of the unit circle reach tol/10
+//    entrywise.  This replaces an O(m n^2) product per leaf by O(m w^2 + n^2 w)
+//    with w = 2b + s columns (b near columns a side, s shifts).  Without
+//    fADI the Gram matrix is formed from the explicit block.
 //  * leaf a, column basis: V_a = orth(L) for the pivoted Cholesky factor L of
 //    the Gram matrix of G(J_a^c, K_a).
 //  * parent t of c1, c2: the stacked projected row blocks [U_c^H G(J_c,
@@ -18,8 +26,13 @@
 //    transfer matrices, so U_t = diag(U_c) Z and V_t = diag(V_c) Y.
 //  * B_{a,a'} = U_a^H G(J_a, K_a') V_a' for the two siblings of each parent.
 //
-// Everything in this stage is FP64; it costs O(M n r) per level.
+// Everything in this stage is FP64.  The shifts come from the Moebius map of
+// the two arcs onto [-gamma, -1] u [1, gamma] and the elliptic-function
+// shifts of that symmetric pair, with the shift count from the bound
+// Z_s <= 4 exp(-pi^2 s / log(16 gamma)) on the Zolotarev number.
 #include <algorithm>
+#include <cmath>
+#include <complex>
 
 #include "gen.h"
 #include "hss.h"
@@ -29,8 +42,122 @@ namespace nd {
 namespace {
 
 constexpr int RMAX1D = 128;
+constexpr double FADI_TOL_FRACTION = 0.1;   // fADI accuracy / truncation tolerance
+constexpr int FADI_MAX_COLS = 64;           // wider factors fall back to the explicit Gram
+constexpr int NEAR_COUNTS[] = {1, 2, 3, 4, 6, 8};
+
+typedef std::complex<double> zc;
+
+zc arc_point(double t) { return zc(std::cos(2.0 * M_PI * t), -std::sin(2.0 * M_PI * t)); }
+
+zc cross_ratio(zc z1, zc z2, zc z3, zc z4) {
+  return ((z1 - z3) * (z2 - z4)) / ((z1 - z4) * (z2 - z3));
+}
+
+// gamma of the image [-gamma, -1] u [1, gamma] of the arcs c([e0, e1]) and
+// c([f0, f1]): (-gamma, -1, 1, gamma) has cross-ratio (1 + gamma)^2 / (4 gamma)
+double gamma_of(double e0, double e1, double f0, double f1) {
+  const double rho = cross_ratio(arc_point(e0), arc_point(e1), arc_point(f0), arc_point(f1)).real();
+  return 2.0 * rho - 1.0 + 2.0 * std::sqrt(rho * rho - rho);
+}
+
+int shift_count(double gamma, double tau) {
+  return std::max(1, (int)std::ceil(std::log(4.0 / tau) * std::log(16.0 * gamma) / (M_PI * M_PI)));
+}
+
+// complete elliptic integral K and Jacobi dn for the complementary modulus
+// kp = sqrt(1 - k^2), by the arithmetic-geometric mean (Abramowitz and
+// Stegun 17.6 and 16.4: descending AGM sequence, then the phase recursion
+// phi_{i-1} = (phi_i + asin(c_i sin(phi_i) / a_i)) / 2, dn = cos(phi_0) /
+// cos(phi_1 - phi_0))
+double ellip_K(double kp) {
+  double a = 1.0, b = kp;
+  for (int i = 0; i < 64 && std::fabs(a - b) > 1e-16 * a; ++i) {
+    const double an = 0.5 * (a + b);
+    b = std::sqrt(a * b);
+    a = an;
+  }
+  return M_PI / (2.0 * a);
+}
+
+double jacobi_dn(double u, double kp) {
+  double a[66], c[66];
+  a[0] = 1.0;
+  c[0] = std::sqrt((1.0 - kp) * (1.0 + kp));
+  double b = kp;
+  int N = 0;
+  while (N < 64 && std::fabs(c[N]) > 1e-17) {
+    a[N + 1] = 0.5 * (a[N] + b);
+    c[N + 1] = 0.5 * (a[N] - b);
+    b = std::sqrt(a[N] * b);
+    ++N;
+  }
+  double phi = std::ldexp(1.0, N) * a[N] * u, phi1 = phi;
+  for (int i = N; i >= 1; --i) {
+    phi1 = phi;
+    phi = 0.5 * (phi + std::asin(c[i] * std::sin(phi) / a[i]));
+  }
+  return std::cos(phi) / std::cos(phi1 - phi);
+}
+
+// the optimal shifts of [-gamma, -1] x [1, gamma]: -w_j and w_j, w_j = gamma
+// dn((2j - 1) K / (2s)), k' = 1 / gamma; the upper half from the lower one
+// through w_j w_{s+1-j} = gamma (dn(u) dn(K - u) = k')
+std::vector<double> symmetric_shifts(double gamma, int s) {
+  const double kp = 1.0 / gamma, K = ellip_K(kp);
+  std::vector<double> w(s);
+  for (int j = 1; 2 * j <= s + 1; ++j) {
+    w[j - 1] = gamma * jacobi_dn((2 * j - 1) * K / (2.0 * s), kp);
+    w[s - j] = gamma / w[j - 1];
+  }
+  if (s % 2) w[s / 2] = std::sqrt(gamma);
+  return w;
+}
+
+// z -> 0, 1, infinity for z = z1, z2, z3, and its inverse
+zc mob(zc z, zc z1, zc z2, zc z3) { return ((z - z1) * (z2 - z3)) / ((z - z3) * (z2 - z1)); }
+zc mob_inv(zc s, zc z1, zc z2, zc z3) {
+  const zc k = s * (z2 - z1) / (z2 - z3);
+  return (z1 - k * z3) / (1.0 - k);
+}
 
 }  // namespace
+
+FadiPlan fadi_plan(int n, int level, int a, double tau) {
+  FadiPlan pl;
+  const int64_t nl = (int64_t)1 << level;
+  pl.lo = (int)((a * (int64_t)n + nl - 1) / nl);
+  pl.hi = (int)(((a + 1) * (int64_t)n + nl - 1) / nl);
+  const int nc = n - (pl.hi - pl.lo);
+  const double e0 = (double)a / (double)nl, e1 = (double)(a + 1) / (double)nl;
+  int best = nc;
+  double f0b = 0, f1b = 0;
+  for (int b : NEAR_COUNTS) {
+    if (nc - 2 * b <= 0) break;
+    const double f0 = (double)(pl.hi + b) / n, f1 = (double)(pl.lo - b - 1 + n) / n;
+    const double g = gamma_of(e0, e1, f0, f1);
+    const int s = shift_count(g, tau);
+    if (2 * b + s < best) {
+      best = 2 * b + s;
+      pl.b = b;
+      pl.s = s;
+      pl.gamma = g;
+      f0b = f0;
+      f1b = f1;
+    }
+  }
+  if (pl.b == 0) return pl;
+  const std::vector<double> w = symmetric_shifts(pl.gamma, pl.s);
+  const zc z1 = arc_point(e0), z2 = arc_point(e1), z3 = arc_point(f0b);
+  (void)f1b;
+  for (int j = 0; j < pl.s; ++j) {
+    const zc pj = mob_inv(mob(zc(-w[j], 0.0), -pl.gamma, -1.0, 1.0), z1, z2, z3);
+    const zc qj = mob_inv(mob(zc(w[j], 0.0), -pl.gamma, -1.0, 1.0), z1, z2, z3);
+    pl.p.push_back(mk<double>(pj.real(), pj.imag()));
+    pl.q.push_back(mk<double>(qj.real(), qj.imag()));
+  }
+  return pl;
+}
 
 void free_1d(Plan* P, std::vector<Tree1>& t) {
   for (auto& tr : t)
@@ -122,10 +249,24 @@ void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out) {
     std::vector<ZeroRCDesc> zr;
     std::vector<Mat<double>> Stmp(nodes.size());
     if (leaf) {
+      // fADI factors Z (m x w), W (n x w) where the plan finds one narrower
+      // than FADI_MAX_COLS, else the explicit Gram G(J_a, :)^H G(J_a, :) with
+      // the rows and columns of K_a zeroed
+      std::vector<FadiPlan> fp(nodes.size());
+      std::vector<size_t> fi;
       for (size_t i = 0; i < nodes.size(); ++i) {
         const Ref& r = nodes[i];
         Tree1& t = out[r.p];
         Node1& nd = t.lv[r.l][r.a];
+        if (P->opts.fadi_1d && nd.m > 0) {
+          fp[i] = fadi_plan(t.n, r.l, r.a, FADI_TOL_FRACTION * tol);
+          ND_CHECK(fp[i].b == 0 || (fp[i].lo == nd.col0 && fp[i].hi == nd.col0 + nd.d),
+                   NUDFT2_E_INTERNAL, "fADI plan: column range differs from the tree's");
+          if (fp[i].b > 0 && 2 * fp[i].b + fp[i].s <= FADI_MAX_COLS) {
+            fi.push_back(i);
+            continue;
+          }
+        }
         const double2* Ga = Gf[r.p] + (nd.row0 - t.m0);
         g1.push_back({t.n, t.n, (int)nd.m, (int)t.M, (int)t.M, KU[i].ld, Ga, Ga,
                       (double2*)KU[i].p, 1.0, 0.0, 0.0, 1});
@@ -133,6 +274,60 @@ void build_1d(Ctx& cx, int dim, double tol, std::vector<Tree1>& out) {
       }
       gemm_batched<double>(cx.pool, g1, OpC, OpN);
       zero_rc(cx.pool, zr, true);
+      if (!fi.empty()) {
+        std::vector<Mat<double>> Zm(fi.size()), Wm(fi.size()), Cm(fi.size()), Tm(fi.size());
+        std::vector<Mat<double>*> ms;
+        std::vector<double2> shifts;
+        for (size_t u = 0; u < fi.size(); ++u) {
+          const size_t i = fi[u];
+          const Ref& r = nodes[i];
+          Tree1& t = out[r.p];
+          Node1& nd = t.lv[r.l][r.a];
+          const int w = 2 * fp[i].b + fp[i].s;
+          Zm[u].r = (int)nd.m;
+          Zm[u].c = w;
+          Wm[u].r = t.n;
+          Wm[u].c = w;
+          Cm[u].r = w;
+          Cm[u].c = w;
+          Tm[u].r = t.n;
+          Tm[u].c = w;
+          ms.push_back(&Zm[u]);
+          ms.push_back(&Wm[u]);
+          ms.push_back(&Cm[u]);
+          ms.push_back(&Tm[u]);
+          shifts.insert(shifts.end(), fp[i].p.begin(), fp[i].p.end());
+          shifts.insert(shifts.end(), fp[i].q.begin(), fp[i].q.end());
+        }
+        carve(P->arena, ms, &cx.tmp);
+        const double2* dsh = (const double2*)cx.pool.push_ro(shifts.data(),
+                                                             sizeof(double2) * shifts.size());
+        std::vector<FadiDesc> fd;
+        std::vector<GemmDesc<double>> gc, gt, gk;
+        size_t off = 0;
+        for (size_t u = 0; u < fi.size(); ++u) {
+          const size_t i = fi[u];
+          const Ref& r = nodes[i];
+          Tree1& t = out[r.p];
+          Node1& nd = t.lv[r.l][r.a];
+          const FadiPlan& pl = fp[i];
+          const int w = 2 * pl.b + pl.s;
+          fd.push_back({axis + nd.row0, dsh + off, (double2*)Zm[u].p, (double2*)Wm[u].p, (int)nd.m,
+                        t.n, pl.b, pl.s, pl.lo, pl.hi, Zm[u].ld, Wm[u].ld});
+          off += 2 * pl.s;
+          // C = Z^H Z, T = W C, KU = T W^H (Hermitian: lower triangle)
+          gc.push_back({w, w, (int)nd.m, Zm[u].ld, Zm[u].ld, Cm[u].ld, (double2*)Zm[u].p,
+                        (double2*)Zm[u].p, (double2*)Cm[u].p, 1.0, 0.0, 0.0});
+          gt.push_back({t.n, w, w, Wm[u].ld, Cm[u].ld, Tm[u].ld, (double2*)Wm[u].p,
+                        (double2*)Cm[u].p, (double2*)Tm[u].p, 1.0, 0.0, 0.0});
+          gk.push_back({t.n, t.n, w, Tm[u].ld, Wm[u].ld, KU[i].ld, (double2*)Tm[u].p,
+                        (double2*)Wm[u].p, (double2*)KU[i].p, 1.0, 0.0, 0.0, 1});
+        }
+        fadi_factors(cx.pool, fd);
+        gemm_batched<double>(cx.pool, gc, OpC, OpN);
+        gemm_batched<double>(cx.pool, gt, OpN, OpN);
+        gemm_batched<double>(cx.pool, gk, OpN, OpC);
+      }
     } else {
       // S = [T_c1; T_c2] with the columns of K_t zeroed
       std::vector<Mat<double>*> ms;

@@ -419,6 +419,7 @@ static void validate(int nprob, const double* points, const int64_t* m_off,
   ND_CHECK(o->graph == 0 || o->graph == 1, NUDFT2_E_INVAL, "graph must be 0 or 1");
   ND_CHECK(o->fp32_products == 0 || o->fp32_products == 1, NUDFT2_E_INVAL,
            "fp32_products must be 0 or 1");
+  ND_CHECK(o->fadi_1d == 0 || o->fadi_1d == 1, NUDFT2_E_INVAL, "fadi_1d must be 0 or 1");
   ND_CHECK(o->nufft_tol == 0.0 || (o->nufft_tol > 0.0 && o->nufft_tol < 0.1), NUDFT2_E_INVAL,
            "nufft_tol must be 0 or lie in (0, 0.1)");
   if (o->nufft_tol > 0.0)

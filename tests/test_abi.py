@@ -64,6 +64,11 @@ def test_invalid_arguments_rejected_before_device_work():
     o.fp32_products = 2
     assert _plan(pts, pr.M, 8, 8, o)[0] == 1
     assert b"fp32_products" in lib.nudft2_last_error()
+    o = _lib.default_opts()
+    assert o.fadi_1d == 1                # fADI 1D construction is the default
+    o.fadi_1d = 2
+    assert _plan(pts, pr.M, 8, 8, o)[0] == 1
+    assert b"fadi_1d" in lib.nudft2_last_error()
 
 
 def test_null_plan_calls():

@@ -23,9 +23,10 @@ DEV = torch.device("cuda", 0)
     (48, 96, 96, 192, 0.4, 3),
 ])
 @pytest.mark.parametrize("tol", [1e-5, 1e-9])
-def test_hss1d_matvec(nx, ny, mx, my, delta, seed, tol):
+@pytest.mark.parametrize("fadi_1d", [True, False])
+def test_hss1d_matvec(nx, ny, mx, my, delta, seed, tol, fadi_1d):
     pr = make_problem(nx, ny, mx, my, delta, seed)
-    plan = nd.Plan(pr.points, nx, ny)
+    plan = nd.Plan(pr.points, nx, ny, fadi_1d=fadi_1d)
     rng = np.random.default_rng(seed)
     for dim, n in ((0, nx), (1, ny)):
         x = complex_normal(rng, (n,))
@@ -39,7 +40,8 @@ def test_hss1d_matvec(nx, ny, mx, my, delta, seed, tol):
         G = onu.kernel_1d(pr.points[:, dim], n)
         ref = G @ x
         err = np.linalg.norm(yt.cpu().numpy() - ref) / np.linalg.norm(ref)
-        print(f"1D dim{dim} n={n} tol={tol:.0e}: rel err {err:.2e} ranks {ranks.tolist()}")
+        print(f"1D dim{dim} n={n} tol={tol:.0e} fadi={fadi_1d}: rel err {err:.2e} "
+              f"ranks {ranks.tolist()}")
         assert err < 5 * tol
     plan.close()
 

@@ -30,17 +30,21 @@ def direct_bound(eps, prec):
     (48, 32, 96, 64, 0.4, 5),       # ragged leaves, non-square
     (8, 8, 16, 16, 0.3, 7),         # single-node tree (dense root)
 ])
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_ins"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_ins", "fp64_gram1d"])
 @pytest.mark.parametrize("eps", [1e-2, 1e-4])
 def test_direct_and_refined(nx, ny, mx, my, delta, seed, prec, eps):
     """prec "fp32": FP32 factors with their products on the bf16 split (the
-    default); "fp32_ins": the same on the FP32 matrix instructions."""
+    default); "fp32_ins": the same on the FP32 matrix instructions;
+    "fp64_gram1d": FP64 with the 1D stage's leaf row bases from explicit Gram
+    matrices instead of fADI factors."""
     pr = make_problem(nx, ny, mx, my, delta, seed)
     f = onu.apply(pr.points, pr.c_true)
     c_ref = onu.lstsq(pr.points, f, nx, ny)
     ft = torch.from_numpy(f).to(DEV)
     kw = dict(fp32_products="fp32") if prec == "fp32_ins" else {}
-    prec = "fp32" if prec == "fp32_ins" else prec
+    if prec == "fp64_gram1d":
+        kw = dict(fadi_1d=False)
+    prec = {"fp32_ins": "fp32", "fp64_gram1d": "fp64"}.get(prec, prec)
     # direct solve
     plan = nd.Plan(pr.points, nx, ny, precision=prec, eps=eps, ir_maxit=0, **kw)
     plan.factor()
