@@ -20,7 +20,8 @@
  * (Theorem 3.3), recompresses it (Section 2.3, tolerance eps), factors it by
  * URV (Section 2.4), and solves with one URV sweep plus a 2D inverse DFT.
  * Optionally the solution is refined in FP64 against the exact operator A
- * (r = f - A c; c += F^{-1} H^+ r) until ||dc||/||c|| <= ir_tol.
+ * (r = f - A c; c += F^{-1} H^+ r) until ||dc||/||c|| <= ir_tol, or until
+ * the contraction bound on the error (see nudft2_solve) is below ir_tol.
  *
  * Complex data are interleaved (re, im) double pairs, the storage of
  * torch.complex128 / numpy complex128.  Unless stated otherwise pointers to
@@ -60,7 +61,8 @@ typedef struct {
   int32_t precision;  /* 0: FP64 HSS factors; 1: FP32 factors, FP64 refinement */
   double eps;         /* HSS tolerance of the recompression (1D stage: eps/10) */
   int32_t leaf;       /* columns per dimension of a leaf (paper: 16)           */
-  double ir_tol;      /* refinement stop: ||dc||_2 / ||c||_2 <= ir_tol          */
+  double ir_tol;      /* refinement stop: ||dc||_2 / ||c||_2 <= ir_tol, or for
+                         refine = 0 the error bound of nudft2_solve      */
   int32_t ir_maxit;   /* refinement iterations; 0 = plain direct solve          */
   int32_t refine;     /* with S = F^{-1} H^+ the factored solution operator:
                          0: iterative refinement c += S(f - Ac) (exact for
@@ -184,7 +186,10 @@ nudft2_status nudft2_factor(nudft2_plan_t plan);
  * (Algorithm 4.1); otherwise refines in FP64 against the exact A until
  * ||dc||/||c|| <= ir_tol (per problem and right-hand side): opts.refine = 0
  * iterates c += S(f - A c), whose fixed point is the least-squares solution
- * when f is in the range of A; refine = 1 runs conjugate gradients on the
+ * when f is in the range of A, and also stops, from its third iteration,
+ * where q / (1 - q) ||dc_k|| / ||c_k|| <= ir_tol with q = 10 ||dc_k|| /
+ * ||dc_{k-1}|| (relative) below 1/2: the error bound of a contraction with
+ * ten times the observed rate; refine = 1 runs conjugate gradients on the
  * normal equations preconditioned by S S^* (the least-squares solution for
  * any f); refine = 2 runs the paper's plsqr, LSQR on S A c = S f (Section
  * 4.1; exact for consistent f).  E_NOCONV leaves the last iterate in c.  Errors: E_INVAL

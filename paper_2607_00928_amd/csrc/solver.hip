@@ -734,6 +734,14 @@ struct SolveCtx {
                                   std::max(std::sqrt(h[ib * sl + e]), 1e-300));
     return worst;
   }
+  // ||a|| / ||b|| per right-hand side and problem of two norm slots
+  std::vector<double> ratios(const std::vector<double>& h, int ia, int ib) const {
+    const size_t sl = (size_t)nrhs * nprob;
+    std::vector<double> r(sl);
+    for (size_t e = 0; e < sl; ++e)
+      r[e] = std::sqrt(h[ia * sl + e]) / std::max(std::sqrt(h[ib * sl + e]), 1e-300);
+    return r;
+  }
   // ||x|| of right-hand side r over all problems from one norm slot
   double total(const std::vector<double>& h, int i, int r) const {
     double t = 0;
@@ -983,17 +991,50 @@ void solve_t(Plan* P, const double2* f, double2* c, int nrhs, nudft2_solve_info*
     sc.norm_into(k, 2, rr, M);
     correct(k);
   };
+  // Stop test, per right-hand side and problem: the relative update u_k =
+  // ||dc_k|| / ||c_k|| is at most ir_tol, or (from the third iteration, whose
+  // update and the one before it are both corrections of the direct solution)
+  // the error bound of a contraction, q / (1 - q) u_k <= ir_tol, holds with
+  // q = 10 u_k / u_{k-1} < 1/2 (ten times the observed contraction).  For
+  // e_{k+1} = (I - S A) e_k with ||I - S A|| <= q, ||c_k - c*|| <= q / (1 - q)
+  // ||dc_k||; the factor 10 covers an observed ratio below the true one.
+  const double tol = P->opts.ir_tol;
+  std::vector<double> uprev;
+  // the worst relative update (NaN if any is NaN)
+  auto worst = [](const std::vector<double>& u) {
+    double w = 0;
+    for (double x : u) {
+      if (!(x == x)) return x;
+      w = std::max(w, x);
+    }
+    return w;
+  };
+  auto converged = [&](const std::vector<double>& u, bool bound) {
+    for (size_t e = 0; e < u.size(); ++e) {
+      if (u[e] <= tol) continue;
+      if (!bound || !(u[e] == u[e])) return false;
+      const double q = 10.0 * u[e] / std::max(uprev[e], 1e-300);
+      if (!(q < 0.5) || q / (1.0 - q) * u[e] > tol) return false;
+    }
+    return true;
+  };
   // first iteration: c = 0, r = f
   correct(sc.cx);
-  upd = sc.worst_ratio(sc.read_norms(2), 0, 1);
-  conv = upd <= P->opts.ir_tol;
+  {
+    std::vector<double> u = sc.ratios(sc.read_norms(2), 0, 1);
+    upd = worst(u);
+    conv = converged(u, false);
+    uprev = u;
+  }
   while (!conv && upd == upd && it < maxit) {   // (upd != upd: NaN, stop)
     ++it;
     sc.run(body);
     std::vector<double> h = sc.read_norms(3);
-    upd = sc.worst_ratio(h, 0, 1);
+    std::vector<double> u = sc.ratios(h, 0, 1);
+    upd = worst(u);
     res = sc.total(h, 2, 0) / std::max(fn, 1e-300);
-    conv = upd <= P->opts.ir_tol;
+    conv = converged(u, it >= 3);
+    uprev = u;
   }
   report(info, it, upd, res);
   if (!conv) throw Error(NUDFT2_E_NOCONV, "refinement did not reach ir_tol");
