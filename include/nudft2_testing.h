@@ -71,11 +71,14 @@ nudft2_status nudft2_test_mfma_layout32(const float* a, const float* b, float* d
 nudft2_status nudft2_test_gemm(int32_t prec, int32_t opA, int32_t opB, int32_t nb,
                                const int32_t* mnk, const int32_t* ld, const int64_t* ptrs,
                                double alpha_re, double alpha_im, double beta);
-/* gemm with a forced k split (splits >= 1: that many plain k splits; 0 = the
- * library's choice; -1 = the tile kernel without splitting and without the
- * tuned table; -2 = the library's heuristic without the tuned table; -3 =
- * stream-K shares of the tiles' k stages wherever the batch allows; -4 = k
- * splits into partial tiles summed in split order by a second kernel) and the
+/* gemm with a forced k split or tile shape (splits >= 1: that many plain k
+ * splits of the 64 x 64 output tiles; 0 = the library's choice; -1 = the tile
+ * kernel without splitting and without the tuned table; -2 = the library's
+ * heuristic without the tuned table; -3 = stream-K shares of the tiles' k
+ * stages wherever the batch allows; -4 = k splits into partial tiles summed
+ * in split order by a second kernel; -5 = 32 x 128 output tiles, -6 = 16- or
+ * 32-square output tiles, both for opA = 1, opB = 0, m <= 32 and 8 < n <=
+ * 128 (-5) or <= 32 (-6), else NUDFT2_E_INVAL) and the
  * launch's duration in milliseconds (HIP events on the null stream) written to
  * *ms (HOST, may be NULL): the measurement hook of the GEMM autotuner. */
 nudft2_status nudft2_test_gemm_cfg(int32_t prec, int32_t opA, int32_t opB, int32_t nb,

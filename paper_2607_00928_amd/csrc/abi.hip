@@ -497,7 +497,7 @@ nudft2_status nudft2_test_gemm_cfg(int32_t prec, int32_t opA, int32_t opB, int32
                                    double ar, double ai, double beta, int32_t splits,
                                    float* ms) {
   return guard([&] {
-    ND_CHECK(mnk && ld && ptrs && nb > 0 && splits >= -4, NUDFT2_E_INVAL, "bad arguments");
+    ND_CHECK(mnk && ld && ptrs && nb > 0 && splits >= -6, NUDFT2_E_INVAL, "bad arguments");
     need_device();
     TestPrec tp(prec);
     if (prec == 0) test_gemm<double>(opA, opB, nb, mnk, ld, ptrs, ar, ai, beta, splits, ms);

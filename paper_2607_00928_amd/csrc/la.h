@@ -83,11 +83,15 @@ struct GemmDesc {
 // over workgroups (atomic accumulation into a pre-scaled C): when the
 // autotuned table (gemm_tuning.inc, written by tune_gemm.py) or else a
 // heuristic calls for a split, the tiles x k stages go in equal stream-K
-// shares to the device's workgroup slots.  splits_force > 0 forces that many
-// plain k splits (used by the tuner); -1 runs the tile kernel unsplit,
-// without the table; -2 takes the heuristic without the table (the tuner's
-// baseline); -3 takes stream-K wherever it applies; -4 takes the
-// partial-tile split wherever the pool has room for it.
+// shares to the device's workgroup slots.  The table also picks the output
+// tile shape of its shape classes: the 64 x 64 tiles, or for A^H B with
+// m <= 32 the 32 x 128 or 16/32-square tiles of the small-output kernels.
+// splits_force > 0 forces that many plain k splits on the 64 x 64 tiles
+// (used by the tuner); -1 runs the tile kernel unsplit, without the table;
+// -2 takes the heuristic without the table (the tuner's baseline); -3 takes
+// stream-K wherever it applies; -4 takes the partial-tile split wherever the
+// pool has room for it; -5 / -6 force the 32 x 128 / square small-output
+// tiles (E_INVAL where the shapes do not allow them).
 // Long-k products with few output tiles keep their k splits' partial tiles in
 // the pool's stream scratch, at most this many bytes a launch; without the
 // scratch they take the atomic split instead.

@@ -2095,10 +2095,13 @@ __global__ void fill_kernel(DS descs) {
 }  // namespace
 
 // ------------------------------------------------------------------ host API
-// Autotuned k splits per launch shape class: precision (0 FP64, 1 FP32),
-// op(A), op(B), ceil(log2) of the largest m, n, k and of the descriptor count.
+// Autotuned tile shape and k split per launch shape class: precision (0
+// FP64, 1 FP32), op(A), op(B), ceil(log2) of the largest m, n, k and of the
+// descriptor count; tile 0: the 64 x 64 output tiles with `splits`; 1: the
+// 32 x 128 tiles of gemm_smallm_wide_kernel; 2: the 16- or 32-square tiles of
+// gemm_smallmn_kernel (both for op(A) = C, op(B) = N, m <= 32).
 struct GemmTune {
-  int prec, opa, opb, lm, ln, lk, lnd, splits;
+  int prec, opa, opb, lm, ln, lk, lnd, splits, tile;
 };
 static const GemmTune kGemmTune[] = {
     {-1, 0, 0, 0, 0, 0, 0, 0},   // sentinel
@@ -2112,14 +2115,14 @@ static int clog2(int64_t x) {
 }
 
 template <typename T>
-static int tuned_splits(Op opA, Op opB, int maxm, int maxn, int maxk, int nd) {
+static const GemmTune* tuned_entry(Op opA, Op opB, int maxm, int maxn, int maxk, int nd) {
   const int prec = sizeof(T) == 4 ? 1 : 0;
   const int lm = clog2(maxm), ln = clog2(maxn), lk = clog2(maxk), lnd = clog2(nd);
   for (const GemmTune& t : kGemmTune)
     if (t.prec == prec && t.opa == (int)opA && t.opb == (int)opB && t.lm == lm && t.ln == ln &&
         t.lk == lk && t.lnd == lnd)
-      return t.splits;
-  return 0;
+      return &t;
+  return nullptr;
 }
 
 // Algorithmic flops of one product: 8 per complex multiply-add with a
@@ -2329,11 +2332,37 @@ void gemm_batched(DescPool& pool, const std::vector<GemmDesc<T>>& d, Op opA, Op 
       maxm = std::max(maxm, g.m);
     }
     if (maxt == 0) continue;
+    const GemmTune* tt =
+        splits_force == 0 ? tuned_entry<T>(opA, opB, maxm, maxn, maxk, (int)n) : nullptr;
     const int force =
         splits_force > 0    ? splits_force
         : splits_force == -1 ? 1
         : splits_force <= -2 ? 0
-                             : tuned_splits<T>(opA, opB, maxm, maxn, maxk, (int)n);
+                             : (tt && tt->tile == 0 ? tt->splits : 0);
+    // the small-m tiles: a tuned choice, or forced (-5: 32 x 128, -6: 16/32
+    // square); a forced tile the shapes do not allow is an error
+    bool lower_any = false;
+    for (auto& g : sub) lower_any = lower_any || g.lower;
+    const bool cn = opA == OpC && opB == OpN && maxm <= 32 && maxn > SK_N && !lower_any;
+    const bool wide_ok = cn && maxn <= 128, sq_ok = cn && maxn <= 32;
+    if (splits_force == -5 || splits_force == -6) {
+      ND_CHECK(splits_force == -5 ? wide_ok : sq_ok, NUDFT2_E_INVAL,
+               "forced small tile: needs op(A) = C, op(B) = N, m <= 32, 8 < n <= 128 (32 x "
+               "128) or <= 32 (square), no Hermitian-lower output");
+    }
+    const int tile = splits_force == -5 ? 1
+                     : splits_force == -6 ? 2
+                     : tt && tt->tile == 1 && wide_ok ? 1
+                     : tt && tt->tile == 2 && sq_ok ? 2
+                                                    : 0;
+    if (tile == 1) {
+      smallm_wide_batched<T>(pool, sub, maxm, maxn, maxk);
+      continue;
+    }
+    if (tile == 2) {
+      smallmn_batched<T>(pool, sub, maxm, maxn, maxk);
+      continue;
+    }
     const bool auto_route = splits_force == 0 || splits_force <= -2;
     if (auto_route && opA == OpC && opB == OpN && maxm <= 32 &&
         maxn > 32 && maxn <= 128 && maxk >= SG_KMIN) {

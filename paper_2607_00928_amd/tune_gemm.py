@@ -1,18 +1,25 @@
-"""Autotuner of the batched complex GEMM: picks the k split per launch shape
-class by measurement and writes csrc/gemm_tuning.inc (rebuild afterwards).
+"""Autotuner of the batched complex GEMM: picks the output tile shape and the
+k split per launch shape class by measurement and writes
+csrc/gemm_tuning.inc (rebuild afterwards).
 
-    python -m paper_2607_00928_amd.tune_gemm [--workload n512] [--top 48]
+    python -m paper_2607_00928_amd.tune_gemm [--workload n512,batch64] [--top 48]
 
-1. Runs factor + refined solve of a workload with per-launch kernel logging
-   (NUDFT2_PROF_LOG) to collect the shapes of the GEMM launches.
+1. Runs each workload (factor + refined solve of one problem; the batch of 64
+   uneven problems: factor) with per-launch kernel logging (NUDFT2_PROF_LOG)
+   to collect the shapes of the GEMM launches.
 2. Buckets the launches into classes (precision, op(A), op(B), ceil(log2) of
-   the largest m, n, k and of the descriptor count) and keeps the classes that
-   took the most time.
+   the largest m, n, k and of the descriptor count) and keeps, per workload,
+   the classes that took the most time.
 3. Times, for each class, a synthetic batch at the class's largest shape with
-   every candidate split and with the library's heuristic without the table
+   every candidate: the 64 x 64 output tiles with each k split, and for A^H B
+   with m <= 32 the 32 x 128 and the 16/32-square output tiles of the
+   small-output kernels; and the library's heuristic without the table
    (nudft2_test_gemm_cfg: HIP events around the launch).
-4. Writes the classes where a forced split beats the heuristic by more than
-   5% (so a rerun keeps the entries that still hold).
+4. Writes the classes where a candidate beats the heuristic by more than 5%,
+   as {..., splits, tile} with tile 0 (64 x 64, splits), 1 (32 x 128) or 2
+   (square).  Entries of the existing table are kept for classes this run
+   did not measure, and for measured classes whose best candidate is still
+   the entry's and still beats the heuristic (merge_entries).
 """
 from __future__ import annotations
 
@@ -39,8 +46,50 @@ def clog2(x: int) -> int:
     return l
 
 
+TILE_CODES = {1: -5, 2: -6}   # tile -> nudft2_test_gemm_cfg's forcing code
+
+
+def small_tiles(opa: int, opb: int, m: int, n: int):
+    """Small-output tile shapes the library accepts for this shape."""
+    if opa != 1 or opb != 0 or m > 32 or n <= 8:
+        return []
+    return [t for t, nmax in ((1, 128), (2, 32)) if n <= nmax]
+
+
+def read_table(path: str) -> dict:
+    """{class key: (splits, tile)} of a gemm_tuning.inc (8-field entries of
+    older tables have tile 0)."""
+    out = {}
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        line = line.strip()
+        if not (line.startswith("{") and line[1:2].isdigit()):
+            continue
+        v = [int(x) for x in line.strip("{},").split(",")]
+        out[tuple(v[:7])] = (v[7], v[8] if len(v) > 8 else 0)
+    return out
+
+
+def merge_entries(old: dict, measured: dict, threshold: float = 1.05) -> dict:
+    """measured: {key: ((splits, tile) of the best candidate, heuristic time /
+    best time)}.  A measured class gets its best candidate when it wins by
+    more than `threshold`, keeps its old entry when that is still the best
+    and still wins, and has no entry otherwise; classes not measured keep
+    theirs."""
+    out = {k: v for k, v in old.items() if k not in measured}
+    for k, (best, gain) in measured.items():
+        if gain > threshold:
+            out[k] = best
+        elif k in old and old[k] == best and gain > 1.0:
+            out[k] = old[k]
+    return out
+
+
 def decode(var: int):
     """(opA, opB, skinny) from the launch log's variant code."""
+    if var in (2011, 2012, 2021, 2022, 3000):   # small-output tiles: A^H B
+        return 1, 0, False
     if var >= 1000:
         v = var - 1000
         return (v % 10) // 2, 0, True
@@ -53,8 +102,17 @@ def collect(workload: str, log_path: str):
     import torch
     sys.path.insert(0, ROOT)
     import paper_2607_00928_amd as nd
-    from nudft_inputs import config_problem, make_problem
+    from nudft_inputs import batch_problems, config_problem, make_problem
 
+    if workload == "batch64":
+        probs = batch_problems()
+        bp = nd.BatchPlan([p.points for p in probs], [p.c_true.shape[0] for p in probs],
+                          [p.c_true.shape[1] for p in probs], precision="fp32", eps=1e-2)
+        bp.set_profiling(True)
+        bp.factor()
+        bp.info()          # folds the recorded launches into the log
+        bp.close()
+        return np.loadtxt(log_path, ndmin=2)
     if workload == "n512":
         pr = config_problem("n512")
         nx = ny = 512
@@ -141,7 +199,9 @@ def time_class(lib, key, c, reps=3):
     for s in SPLITS:
         if k // s < kmin and s > 1:
             break
-        res[s] = run(s)
+        res[(s, 0)] = run(s)
+    for t in small_tiles(opa, opb, m, n):
+        res[(0, t)] = run(TILE_CODES[t])
     # the first configuration of a class can run before the clocks settle:
     # time the baseline again once the candidates have run
     auto = min(auto, run(-2))
@@ -152,37 +212,65 @@ def time_class(lib, key, c, reps=3):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--workload", default="n512", choices=["n512", "n128"])
+    ap.add_argument("--workload", default="n512,batch64",
+                    help="comma-separated: n512, n128, batch64")
     ap.add_argument("--top", type=int, default=48)
     ap.add_argument("--out", default=INC)
+    ap.add_argument("--no-merge", action="store_true",
+                    help="write only this run's entries (default: merge with --out's table)")
     args = ap.parse_args()
+    workloads = args.workload.split(",")
+    for w in workloads:
+        if w not in ("n512", "n128", "batch64"):
+            raise SystemExit(f"unknown workload {w}")
+    picked = {}
+    # the library takes the log's path once per process: one file, each
+    # workload's rows are the ones it appended
     log_path = os.path.join(tempfile.mkdtemp(prefix="nudft2_tune_"), "launches.txt")
-    t0 = time.time()
-    rows = collect(args.workload, log_path)
-    print(f"[tune] {len(rows)} launches logged in {time.time() - t0:.1f} s", flush=True)
+    seen = 0
+    for w in workloads:
+        t0 = time.time()
+        allrows = collect(w, log_path)
+        rows = allrows[seen:]
+        seen = len(allrows)
+        print(f"[tune] {w}: {len(rows)} launches logged in {time.time() - t0:.1f} s", flush=True)
+        for key, c in classes(rows, args.top):
+            if key in picked:
+                o = picked[key]
+                o["ms"] += c["ms"]
+                o["count"] += c["count"]
+                for f in ("m", "n", "k", "nd"):
+                    o[f] = max(o[f], c[f])
+            else:
+                picked[key] = dict(c)
     sys.path.insert(0, ROOT)
     from paper_2607_00928_amd import _lib
     lib = _lib.lib
-    lines = []
-    for key, c in classes(rows, args.top):
+    measured = {}
+    for key, c in sorted(picked.items(), key=lambda kv: -kv[1]["ms"]):
         r = time_class(lib, key, c)
         if r is None:
             print(f"[tune] {key} skipped (operands above the memory cap)", flush=True)
             continue
         auto, res = r
-        best_s = min(res, key=res.get)
-        gain = auto / res[best_s] if res[best_s] > 0 else 1.0
+        best = min(res, key=res.get)
+        gain = auto / res[best] if res[best] > 0 else 1.0
+        what = f"split {best[0]}" if best[1] == 0 else ("32x128 tiles", "square tiles")[best[1] - 1]
         print(f"[tune] {key} m={c['m']} n={c['n']} k={c['k']} nd={c['nd']} "
-              f"({c['ms']:.1f} ms in the run): heuristic {auto:.3f} ms, best split {best_s} "
-              f"{res[best_s]:.3f} ms (x{gain:.2f})", flush=True)
-        if gain > 1.05:
-            lines.append("{%d, %d, %d, %d, %d, %d, %d, %d}," % (*key, best_s))
+              f"({c['ms']:.1f} ms in the run): heuristic {auto:.3f} ms, best {what} "
+              f"{res[best]:.3f} ms (x{gain:.2f})", flush=True)
+        measured[key] = (best, gain)
+    old = {} if args.no_merge else read_table(args.out)
+    table = merge_entries(old, measured)
+    lines = sorted("{%d, %d, %d, %d, %d, %d, %d, %d, %d}," % (*k, *v) for k, v in table.items())
     with open(args.out, "w") as fh:
-        fh.write("// Autotuned k splits (written by tune_gemm.py from a %s run):\n" % args.workload)
-        fh.write("// {prec, opA, opB, log2 m, log2 n, log2 k, log2 descriptors, splits},\n")
-        for l in sorted(lines):
+        fh.write("// Autotuned tile shapes and k splits (written by tune_gemm.py from %s runs):\n"
+                 % args.workload)
+        fh.write("// {prec, opA, opB, log2 m, log2 n, log2 k, log2 descriptors, splits, tile},\n")
+        for l in lines:
             fh.write(l + "\n")
-    print(f"[tune] wrote {len(lines)} entries to {args.out}", flush=True)
+    print(f"[tune] wrote {len(lines)} entries to {args.out} ({len(measured)} classes measured, "
+          f"{len(old)} entries before)", flush=True)
 
 
 if __name__ == "__main__":

@@ -830,6 +830,59 @@ def test_gemm_partial_tile_splits(prec, opa, opb):
             assert np.abs(got - ref).max() < TOL[prec] * scale * max(k, 1) ** 0.5 * 10, (m, n, k)
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("code", [-5, -6])
+def test_gemm_forced_small_tiles(prec, code):
+    """The small-output tile shapes the autotuner can pick for A^H B with
+    m <= 32 (-5: 32 x 128 tiles, -6: 16- or 32-square tiles), forced on ragged
+    batches with short and long k, k = 0 and an empty output in the same
+    launch, beta = 0.5, alpha complex; shapes the tiles do not cover are
+    rejected with E_INVAL and leave C untouched."""
+    rng = np.random.default_rng(180 + 4 * prec - code)
+    nmax = 128 if code == -5 else 32
+    shapes = [(32, nmax, 5000), (17, nmax - 3, 333), (1, 9, 70), (32, 12, 1), (20, 20, 0),
+              (0, 16, 100)]
+    alpha, beta = 0.4 + 0.9j, 0.5
+    mats, keep, mnk, ld, ptr = [], [], [], [], []
+    for (m, n, k) in shapes:
+        A = crandn(rng, k, m)
+        B = crandn(rng, k, n)
+        Cm = crandn(rng, m, n)
+        ts = [to_dev(X, prec) if X.size else torch.zeros(1, dtype=CT[prec][1], device=DEV)
+              for X in (A, B, Cm)]
+        keep += ts
+        mats.append((A, B, Cm, ts[2]))
+        mnk += [m, n, k]
+        ld += [max(1, k), max(1, k), max(1, m)]
+        ptr += [t.data_ptr() for t in ts]
+    a1, p1 = i32(mnk)
+    a2, p2 = i32(ld)
+    a3, p3 = i64(ptr)
+    st = lib.nudft2_test_gemm_cfg(prec, 1, 0, len(shapes), p1, p2, p3, alpha.real, alpha.imag,
+                                  beta, code, None)
+    assert st == 0, lib.nudft2_last_error()
+    for (m, n, k), (A, B, Cm, tc) in zip(shapes, mats):
+        if m == 0 or n == 0:
+            continue
+        ref = alpha * (A.conj().T @ B) + beta * Cm
+        got = from_dev(tc, m, n)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(got - ref).max() < TOL[prec] * scale * max(k, 1) ** 0.5 * 10, (m, n, k)
+    # out of range: m > 32, n above the tile, op(A) = N
+    for (m, n, k, opa) in [(33, 16, 100, 1), (16, nmax + 1, 100, 1), (16, 16, 100, 0)]:
+        A = crandn(rng, *((k, m) if opa else (m, k)))
+        B = crandn(rng, k, n)
+        Cm = crandn(rng, m, n)
+        ta, tb, tc = to_dev(A, prec), to_dev(B, prec), to_dev(Cm, prec)
+        b1, q1 = i32([m, n, k])
+        b2, q2 = i32([A.shape[0], k, m])
+        b3, q3 = i64([ta.data_ptr(), tb.data_ptr(), tc.data_ptr()])
+        st = lib.nudft2_test_gemm_cfg(prec, opa, 0, 1, q1, q2, q3, 1.0, 0.0, 0.0, code, None)
+        assert st == 1 and b"forced small tile" in lib.nudft2_last_error()
+        torch.cuda.synchronize()
+        assert np.array_equal(from_dev(tc, m, n), Cm.astype(CT[prec][0]))
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_trtri_inverts_upper_triangles(prec):
     """Batched in-place inversion of upper-triangular matrices (the solves'

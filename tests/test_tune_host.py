@@ -18,6 +18,19 @@ def test_decode_variant_codes():
     # skinny launches: opA * 2 + 10 * splits + 1000 (op(B) = N)
     assert tg.decode(1000 + 2 + 160) == (1, 0, True)
     assert tg.decode(1010) == (0, 0, True)
+    # small-output tiles (always A^H B): 2000 + 10 mb + nb, and 3000
+    for v in (2011, 2012, 2021, 2022, 3000):
+        assert tg.decode(v) == (1, 0, False)
+
+
+def test_small_tile_candidates():
+    assert tg.small_tiles(1, 0, 32, 128) == [1]
+    assert tg.small_tiles(1, 0, 16, 20) == [1, 2]
+    assert tg.small_tiles(1, 0, 33, 64) == []
+    assert tg.small_tiles(0, 0, 16, 64) == []
+    assert tg.small_tiles(1, 0, 16, 8) == []
+    assert tg.small_tiles(1, 0, 16, 129) == []
+    assert tg.TILE_CODES == {1: -5, 2: -6}
 
 
 def test_classes_bucket_and_rank():
@@ -51,3 +64,25 @@ def test_classes_skinny_products():
                      [5, 1.0, 1e9, 4, 300, 2, 5000, 1032, 16]])
     cl = dict(tg.classes(rows, top=10))
     assert (1, 0, 0, 11, 0, 8, 10) in cl and (0, 1, 0, 9, 1, 13, 2) in cl
+
+
+def test_merge_entries():
+    a, b, c, d, e = [(1, 0, 0, i, 0, 0, 0) for i in range(5)]
+    old = {a: (1, 0), b: (4, 0), c: (0, 2), d: (8, 0)}
+    measured = {b: ((4, 0), 1.02),      # same winner, small gain: kept
+                c: ((2, 0), 1.03),      # another winner below the threshold: dropped
+                d: ((16, 0), 1.30),     # a clear new winner: replaced
+                e: ((0, 1), 1.10)}      # new class: added
+    out = tg.merge_entries(old, measured)
+    assert out == {a: (1, 0), b: (4, 0), d: (16, 0), e: (0, 1)}
+    # the heuristic now wins: the old entry goes
+    assert tg.merge_entries({a: (1, 0)}, {a: ((1, 0), 0.97)}) == {}
+
+
+def test_read_table(tmp_path):
+    p = tmp_path / "t.inc"
+    p.write_text("// header\n// {prec, ...},\n{1, 0, 0, 12, 11, 8, 5, 1},\n"
+                 "{1, 1, 0, 5, 5, 10, 5, 0, 2},\n")
+    assert tg.read_table(str(p)) == {(1, 0, 0, 12, 11, 8, 5): (1, 0),
+                                     (1, 1, 0, 5, 5, 10, 5): (0, 2)}
+    assert tg.read_table(str(tmp_path / "missing.inc")) == {}
