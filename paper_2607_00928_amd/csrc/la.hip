@@ -770,6 +770,8 @@ __device__ inline void skinny_store(const GemmDesc<T>& d, int i, int j, cplx<T> 
 // issues SK_U independent loads of A before using them (memory-level
 // parallelism on a bandwidth-bound stream).
 constexpr int SK_U = 8;
+// rows of C per wave in gemm_skinny_c_kernel (op C, long k)
+constexpr int SKC_ROWS = 2;
 
 template <typename T, int NC, class DS>
 __global__ __launch_bounds__(256) void gemm_skinny_n_kernel(DS descs, int splits) {
@@ -885,27 +887,36 @@ template <typename T, int NC, class DS>
 __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(DS descs, int splits) {
   using C2 = cplx<T>;
   constexpr int U = SK_U / 2;
+  constexpr int R = SKC_ROWS;
   const GemmDesc<T> d = descs[blockIdx.y];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = blockIdx.x * 4 + wave;
+  // R rows of C a wave: each load of B feeds all R rows' products
+  const int i = R * (blockIdx.x * 4 + wave);
   if (i >= d.m || d.n <= 0) return;
+  const int nr = min(R, d.m - i);
   const int kc = (d.k + splits - 1) / splits;
   int kb = blockIdx.z * kc, ke = min(d.k, kb + kc);
   if (kb >= ke && splits > 1) return;
-  // column i of A has no nonzeros outside [lo, hi) (the result row i
-  // still gets its store, zero or not)
+  // columns i .. i + nr - 1 of A have no nonzeros outside the union of their
+  // ranges (the entries outside a column's own range are stored zeros; the
+  // result rows still get their stores, zero or not)
   if (d.tri == 1) kb = max(kb, i);
-  else if (d.tri == 2) ke = min(ke, i + 1);
-  C2 acc[NC];
+  else if (d.tri == 2) ke = min(ke, i + nr);
+  C2 acc[R][NC];
+  const C2* ap[R];
 #pragma unroll
-  for (int j = 0; j < NC; ++j) acc[j] = mk<T>(0, 0);
-  const C2* ap = d.A + (int64_t)i * d.lda;
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[r][j] = mk<T>(0, 0);
+    ap[r] = d.A + (int64_t)(i + min(r, nr - 1)) * d.lda;   // rows past m reread the last
+  }
   int l = kb + lane;
   for (; l + 64 * (U - 1) < ke; l += 64 * U) {
-    C2 a[U], b[U][NC];
+    C2 a[R][U], b[U][NC];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      a[u] = ldc(ap + l + 64 * u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r][u] = ldc(ap[r] + l + 64 * u);
 #pragma unroll
       for (int j = 0; j < NC; ++j)
         b[u][j] = j < d.n ? ldc(d.B + (int64_t)(l + 64 * u) + (int64_t)j * d.ldb) : mk<T>(0, 0);
@@ -913,20 +924,30 @@ __global__ __launch_bounds__(256) void gemm_skinny_c_kernel(DS descs, int splits
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int j = 0; j < NC; ++j) acc[j] = cadd(acc[j], cmulc(a[u], b[u][j]));
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[r][j] = cadd(acc[r][j], cmulc(a[r][u], b[u][j]));
   }
   for (; l < ke; l += 64) {
-    const C2 a = ldc(ap + l);
+    C2 a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = ldc(ap[r] + l);
 #pragma unroll
     for (int j = 0; j < NC; ++j)
-      if (j < d.n) acc[j] = cadd(acc[j], cmulc(a, ldc(d.B + (int64_t)l + (int64_t)j * d.ldb)));
+      if (j < d.n) {
+        const C2 bb = ldc(d.B + (int64_t)l + (int64_t)j * d.ldb);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r][j] = cadd(acc[r][j], cmulc(a[r], bb));
+      }
   }
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    if (j >= d.n) break;
-    const T re = warp_sum(acc[j].x), im = warp_sum(acc[j].y);
-    if (lane == 0) skinny_store(d, i, j, mk<T>(re, im), splits);
-  }
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      if (j >= d.n) break;
+      const T re = warp_sum(acc[r][j].x), im = warp_sum(acc[r][j].y);
+      if (lane == 0 && r < nr) skinny_store(d, i + r, j, mk<T>(re, im), splits);
+    }
 }
 
 // op(A) = A^H with a long k and too few rows of C to fill the device a wave
@@ -2197,7 +2218,10 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
           dim3(256), 0, pool.stream, dd);
     ProfScope ps(pool.stream, sizeof(T) == 4 ? KC_GEMV32 : KC_GEMV64, fl, (int)n, maxm, maxn,
                  maxk, (int)opA * 2 + 10 * splits + 1000, true);
-    dim3 grid((unsigned)(cw ? maxm : bx), (unsigned)n, (unsigned)splits);
+    // the op C kernel takes SKC_ROWS rows a wave
+    const int64_t gx =
+        cw ? maxm : (opA == OpC && !c16 ? (maxm + 4 * SKC_ROWS - 1) / (4 * SKC_ROWS) : bx);
+    dim3 grid((unsigned)gx, (unsigned)n, (unsigned)splits);
     auto launch = [&](auto nc) {
       constexpr int NC = decltype(nc)::value;
       if (cw)
