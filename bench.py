@@ -1,13 +1,15 @@
 """Benchmark: factor + refined solve of the 2D type-II inverse NUDFT at
 n = 512 x 512 (N = 262144), M = 1024^2 jittered points, FP32 HSS factors with
-FP64 iterative refinement to ||dc||/||c|| <= 1e-10 (relative error vs the true
-coefficients reported), on one MI355X.  The refinement's FP64 residual
+FP64 iterative refinement, ir_tol = 1e-10 (an update, or the contraction bound
+on the error, below it; relative error vs the true coefficients reported), on
+one MI355X.  The refinement's FP64 residual
 comes from the exact face-split apply (the FP64 direct sums; --nufft-tol
 1e-13 takes Section 4.1's NUFFT operator instead), and both operators'
 refined solves are reported.
 
 A step = plan (binning + upload of the points) + factorization (1D HSS
-compression, face-splitting assembly, recompression, URV) + refined solve of
+compression with fADI factors, face-splitting assembly, recompression, URV) +
+refined solve of
 one right-hand side, inputs resident in device memory before timing.  The
 FP64-factor path is timed beside it (same refinement target).  The CPU
 baseline leg times the oracle's direct-sum apply on a bounded sample of rows.
