@@ -9,8 +9,8 @@ refined solves are reported.
 
 A step = plan (binning + upload of the points) + factorization (1D HSS
 compression with fADI factors, face-splitting assembly, recompression, URV) +
-refined solve of
-one right-hand side, inputs resident in device memory before timing.  The
+refined solve of one right-hand side, inputs resident in device memory before
+timing.  The
 FP64-factor path is timed beside it (same refinement target).  The CPU
 baseline leg times the oracle's direct-sum apply on a bounded sample of rows.
 
