@@ -770,8 +770,10 @@ __device__ inline void skinny_store(const GemmDesc<T>& d, int i, int j, cplx<T> 
 // issues SK_U independent loads of A before using them (memory-level
 // parallelism on a bandwidth-bound stream).
 constexpr int SK_U = 8;
-// rows of C per wave in gemm_skinny_c_kernel (op C, long k)
+// rows of C per wave in gemm_skinny_c_kernel (op C, long k) and per
+// workgroup in gemm_skinny_cw_kernel
 constexpr int SKC_ROWS = 2;
+constexpr int SKCW_ROWS = 2;
 
 template <typename T, int NC, class DS>
 __global__ __launch_bounds__(256) void gemm_skinny_n_kernel(DS descs, int splits) {
@@ -958,25 +960,33 @@ template <typename T, int NC, class DS>
 __global__ __launch_bounds__(256) void gemm_skinny_cw_kernel(DS descs) {
   using C2 = cplx<T>;
   constexpr int U = SK_U / 2;
-  __shared__ T red[4][NC][2];
+  constexpr int R = SKCW_ROWS;
+  __shared__ T red[4][R][NC][2];
   const GemmDesc<T> d = descs[blockIdx.y];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int i = blockIdx.x;
+  const int i = R * blockIdx.x;
   if (i >= d.m || d.n <= 0) return;   // uniform over the workgroup
+  const int nr = min(R, d.m - i);
   int kb = 0, ke = d.k;
-  // column i of A has no nonzeros outside [kb, ke)
+  // columns i .. i + nr - 1 of A have no nonzeros outside the union of their
+  // ranges (entries outside a column's own range are stored zeros)
   if (d.tri == 1) kb = min(i, ke);
-  else if (d.tri == 2) ke = min(ke, i + 1);
-  C2 acc[NC];
+  else if (d.tri == 2) ke = min(ke, i + nr);
+  C2 acc[R][NC];
+  const C2* ap[R];
 #pragma unroll
-  for (int j = 0; j < NC; ++j) acc[j] = mk<T>(0, 0);
-  const C2* ap = d.A + (int64_t)i * d.lda;
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[r][j] = mk<T>(0, 0);
+    ap[r] = d.A + (int64_t)(i + min(r, nr - 1)) * d.lda;   // rows past m reread the last
+  }
   int l = kb + tid;
   for (; l + 256 * (U - 1) < ke; l += 256 * U) {
-    C2 a[U], b[U][NC];
+    C2 a[R][U], b[U][NC];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      a[u] = ldc(ap + l + 256 * u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r][u] = ldc(ap[r] + l + 256 * u);
 #pragma unroll
       for (int j = 0; j < NC; ++j)
         b[u][j] = j < d.n ? ldc(d.B + (int64_t)(l + 256 * u) + (int64_t)j * d.ldb) : mk<T>(0, 0);
@@ -984,31 +994,44 @@ __global__ __launch_bounds__(256) void gemm_skinny_cw_kernel(DS descs) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int j = 0; j < NC; ++j) acc[j] = cadd(acc[j], cmulc(a[u], b[u][j]));
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[r][j] = cadd(acc[r][j], cmulc(a[r][u], b[u][j]));
   }
   for (; l < ke; l += 256) {
-    const C2 a = ldc(ap + l);
+    C2 a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = ldc(ap[r] + l);
 #pragma unroll
     for (int j = 0; j < NC; ++j)
-      if (j < d.n) acc[j] = cadd(acc[j], cmulc(a, ldc(d.B + (int64_t)l + (int64_t)j * d.ldb)));
+      if (j < d.n) {
+        const C2 bb = ldc(d.B + (int64_t)l + (int64_t)j * d.ldb);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r][j] = cadd(acc[r][j], cmulc(a[r], bb));
+      }
   }
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    const T re = warp_sum(acc[j].x), im = warp_sum(acc[j].y);
-    if (lane == 0) {
-      red[wave][j][0] = re;
-      red[wave][j][1] = im;
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const T re = warp_sum(acc[r][j].x), im = warp_sum(acc[r][j].y);
+      if (lane == 0) {
+        red[wave][r][j][0] = re;
+        red[wave][r][j][1] = im;
+      }
     }
-  }
   __syncthreads();
-  if (tid < NC && tid < d.n) {
-    T re = 0, im = 0;
+  if (tid < R * NC) {
+    const int r = tid / NC, j = tid % NC;
+    if (r < nr && j < d.n) {
+      T re = 0, im = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      re += red[w][tid][0];
-      im += red[w][tid][1];
+      for (int w = 0; w < 4; ++w) {
+        re += red[w][r][j][0];
+        im += red[w][r][j][1];
+      }
+      skinny_store(d, i + r, j, mk<T>(re, im), 1);
     }
-    skinny_store(d, i, tid, mk<T>(re, im), 1);
   }
 }
 
@@ -2220,7 +2243,8 @@ static void skinny_batched(DescPool& pool, const std::vector<GemmDesc<T>>& sub, 
                  maxk, (int)opA * 2 + 10 * splits + 1000, true);
     // the op C kernel takes SKC_ROWS rows a wave
     const int64_t gx =
-        cw ? maxm : (opA == OpC && !c16 ? (maxm + 4 * SKC_ROWS - 1) / (4 * SKC_ROWS) : bx);
+        cw ? (maxm + SKCW_ROWS - 1) / SKCW_ROWS
+           : (opA == OpC && !c16 ? (maxm + 4 * SKC_ROWS - 1) / (4 * SKC_ROWS) : bx);
     dim3 grid((unsigned)gx, (unsigned)n, (unsigned)splits);
     auto launch = [&](auto nc) {
       constexpr int NC = decltype(nc)::value;
